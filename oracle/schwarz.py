@@ -1,0 +1,367 @@
+"""Sequential optimized Schwarz iteration on x-strips (Sections 2-4).
+
+Oracle code (test infrastructure).  Follows the paper's discrete algorithm:
+
+* Decomposition (Section 2.1, Fig. figsub3): strip j owns cells
+  [s_j, s_j + cells_j) in x; its node-lines s_j .. s_j + cells_j include both
+  edge lines, so an interface line is duplicated (non-overlapping FEM).
+* Local problem (eqs. algolocal, NproblemRobinNL): with the transmission data
+  (l_j, r_j) on its two edges the strip solves
+      K_j(W + beta|v|^2) v = 2i/dt M_j u_{j,n-1} - c M^Gamma Q^T (l_j; r_j)
+  by the fixed point of step.py (forms A/B), started from zeta^0 = u_{j,n-1}.
+  K_j carries the Robin term i c p on interface edges and i c p_bc on the
+  physical edges of the two extreme strips, where l_1 = r_N = 0.
+* Flux update (eqs. fluxlr, AlgoGraph with S = -ip):
+      new l_{j+1} = -r_j     - 2ip Q_r v_j,
+      new r_j     = -l_{j+1} - 2ip Q_l v_{j+1}.
+* Interface vector (eq. algo_d) g = (r_1, l_2, r_2, ..., r_{N-1}, l_N); here
+  stored as an array of shape (2(N-1), ny) with g[2i] = r_i and
+  g[2i+1] = l_{i+1} for the interface i between strips i and i+1 (0-based).
+* Classical algorithm: g^{k+1} = R(g^k), stop when ||g^{k+1} - g^k|| < tol
+  (Section 5, stopping rule).
+* Preconditioned algorithm (eq. algo_pd, read as
+  g^{k+1} = g^k - P^{-1}(g^k - R(g^k))) with P = I - L_h, where L_h is the
+  linear part of the Schwarz map of the free problem V = 0, f = 0
+  (Section 3, eq. Lmpi).  L_h is built numerically, column by column, as the
+  free map applied to unit vectors (Section 4.2 does the same with the
+  formulas of Proposition 3.1); P x = y is solved by GMRES or directly.
+* The output v_{j,n} comes from the last evaluation of R; the global u_n
+  takes 2 v - u_{n-1} on every line, the mean of the two copies on interface
+  lines.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .fem import StripMatrices, weighted_mass_2d
+from .step import NoConvergence
+
+
+def gmres(matvec, b, rtol=1e-12, restart=50, maxiter=2000):
+    """Restarted GMRES with modified Gram-Schmidt and Givens rotations
+    (textbook form), x0 = 0.  Returns (x, total inner iterations)."""
+    n = b.shape[0]
+    x = np.zeros(n, dtype=complex)
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return x, 0
+    total = 0
+    while total < maxiter:
+        r = b - matvec(x)
+        beta = np.linalg.norm(r)
+        if beta <= rtol * bnorm:
+            return x, total
+        V = np.zeros((restart + 1, n), dtype=complex)
+        H = np.zeros((restart + 1, restart), dtype=complex)
+        cs = np.zeros(restart, dtype=complex)
+        sn = np.zeros(restart, dtype=complex)
+        e = np.zeros(restart + 1, dtype=complex)
+        e[0] = beta
+        V[0] = r / beta
+        j_done = 0
+        for j in range(restart):
+            w = matvec(V[j])
+            for i in range(j + 1):
+                H[i, j] = np.vdot(V[i], w)
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] != 0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + np.conj(cs[i]) * H[i + 1, j]
+                H[i, j] = t
+            a, bb = H[j, j], H[j + 1, j]
+            den = np.sqrt(abs(a) ** 2 + abs(bb) ** 2)
+            cs[j] = a / den if den else 1.0
+            sn[j] = bb / den if den else 0.0
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            e[j + 1] = -np.conj(sn[j]) * e[j]
+            e[j] = np.conj(cs[j]) * e[j]
+            total += 1
+            j_done = j + 1
+            if abs(e[j + 1]) <= rtol * bnorm or total >= maxiter:
+                break
+        y = np.linalg.solve(np.triu(H[:j_done, :j_done]), e[:j_done])
+        x = x + V[:j_done].T @ y
+        if abs(e[j_done]) <= rtol * bnorm:
+            r = b - matvec(x)
+            if np.linalg.norm(r) <= 10 * rtol * bnorm:
+                return x, total
+    return x, total
+
+
+class SchwarzOracle:
+    def __init__(self, pb, W: np.ndarray, form: str = "B", tol_q: float = 1e-13,
+                 max_q: int = 200):
+        self.pb = pb
+        self.form = form
+        self.tol_q = tol_q
+        self.max_q = max_q
+        self.N = pb.nsub
+        self.ny = pb.ncy + 1
+        cells = list(pb.strip_cells)
+        assert len(cells) == self.N and sum(cells) == pb.ncx
+        self.cells = cells
+        self.starts = np.concatenate([[0], np.cumsum(cells)[:-1]]).astype(int)
+        self.mats = [StripMatrices(c, pb.ncy, pb.hx, pb.hy) for c in cells]
+        self.pl = [pb.p_bc if j == 0 else pb.p for j in range(self.N)]
+        self.pr = [pb.p_bc if j == self.N - 1 else pb.p for j in range(self.N)]
+        self._free_lu = None
+        self.Lh_blocks = None
+        self.set_potential(W)
+
+    # ---- data movement between the global mesh and strips -------------
+    def restrict(self, u: np.ndarray, j: int) -> np.ndarray:
+        s, c = self.starts[j], self.cells[j]
+        return np.array(u[s:s + c + 1, :])
+
+    def assemble_global(self, vs, u_old: np.ndarray) -> np.ndarray:
+        acc = np.zeros(u_old.shape, dtype=complex)
+        cnt = np.zeros(u_old.shape[0])
+        for j, v in enumerate(vs):
+            s, c = self.starts[j], self.cells[j]
+            acc[s:s + c + 1] += v
+            cnt[s:s + c + 1] += 1
+        vbar = acc / cnt[:, None]
+        return 2.0 * vbar - u_old
+
+    # ---- local problems ------------------------------------------------
+    def set_potential(self, W: np.ndarray):
+        pb = self.pb
+        self.W = np.asarray(W, dtype=float)
+        self.Wj = [self.restrict(self.W, j) for j in range(self.N)]
+        self._lu = [None] * self.N
+        if self.form == "B":
+            for j in range(self.N):
+                K = self.mats[j].operator(self.Wj[j], pb.dt, pb.lap_coef,
+                                          self.pl[j], self.pr[j])
+                self._lu[j] = spla.splu(K)
+
+    def traces(self, g: np.ndarray, j: int):
+        """(l_j, r_j) read from the interface vector; zero on physical edges."""
+        ny = self.ny
+        l = g[2 * (j - 1) + 1] if j >= 1 else np.zeros(ny, complex)
+        r = g[2 * j] if j <= self.N - 2 else np.zeros(ny, complex)
+        return l, r
+
+    def strip_rhs(self, j: int, u_old_j: np.ndarray, l, r) -> np.ndarray:
+        """2i/dt M_j u_{j,n-1} - c M^Gamma Q^T (l; r)."""
+        pb = self.pb
+        m = self.mats[j]
+        F = (2j / pb.dt) * (m.M @ u_old_j.ravel())
+        F = F.reshape(m.nx, m.ny)
+        F[0] -= pb.lap_coef * (m.My @ l)
+        F[-1] -= pb.lap_coef * (m.My @ r)
+        return F.ravel()
+
+    def solve_strip(self, j, u_old_j, l, r, zeta0=None, fixed_q=None):
+        pb = self.pb
+        m = self.mats[j]
+        shape = (m.nx, m.ny)
+        F = self.strip_rhs(j, u_old_j, l, r)
+        zeta = (u_old_j if zeta0 is None else zeta0).ravel().astype(complex)
+        nq = fixed_q if fixed_q is not None else self.max_q
+        for q in range(1, nq + 1):
+            rho = pb.beta * np.abs(zeta) ** 2
+            if self.form == "A":
+                K = m.operator(self.Wj[j] + rho.reshape(shape), pb.dt, pb.lap_coef,
+                               self.pl[j], self.pr[j])
+                znew = spla.spsolve(K, F)
+            else:
+                Mrho = weighted_mass_2d(rho.reshape(shape), pb.hx, pb.hy)
+                znew = self._lu[j].solve(F - Mrho @ zeta)
+            inc = np.linalg.norm(znew - zeta)
+            zeta = znew
+            if not np.isfinite(inc):
+                raise NoConvergence("fixed point diverged")
+            if fixed_q is None and inc <= self.tol_q * np.linalg.norm(zeta):
+                return zeta.reshape(shape), q
+        if fixed_q is None:
+            raise NoConvergence("strip fixed point did not converge")
+        return zeta.reshape(shape), nq
+
+    # ---- the Schwarz map R ---------------------------------------------
+    def flux(self, g: np.ndarray, vs) -> np.ndarray:
+        """Eq. fluxlr with S = -ip: every trace is updated from the k-th
+        iterate of the neighbouring strip (Jacobi)."""
+        p = self.pb.p
+        gn = np.empty_like(g)
+        for i in range(self.N - 1):
+            l_next = g[2 * i + 1]
+            r_i = g[2 * i]
+            gn[2 * i] = -l_next - 2j * p * vs[i + 1][0]       # new r_i
+            gn[2 * i + 1] = -r_i - 2j * p * vs[i][-1]          # new l_{i+1}
+        return gn
+
+    def R(self, g, u_old, zetas=None, fixed_q=None):
+        vs, qs = [], []
+        for j in range(self.N):
+            l, r = self.traces(g, j)
+            z0 = None if zetas is None else zetas[j]
+            v, q = self.solve_strip(j, self.restrict(u_old, j), l, r, z0, fixed_q)
+            vs.append(v)
+            qs.append(q)
+        return self.flux(g, vs), vs, qs
+
+    # ---- classical and preconditioned iterations -----------------------
+    @staticmethod
+    def _converged(inc, ref, tol, relative):
+        return inc < (tol * max(ref, 1e-300) if relative else tol)
+
+    def classical(self, u_old, g0, tol=1e-10, relative=False, max_k=10000,
+                  fixed_k=None, fixed_q=None, warm=False):
+        g = np.array(g0, dtype=complex)
+        q_total = 0
+        zetas = None
+        nk = fixed_k if fixed_k is not None else max_k
+        for k in range(1, nk + 1):
+            gn, vs, qs = self.R(g, u_old, zetas, fixed_q)
+            q_total += sum(qs)
+            if warm:
+                zetas = vs
+            inc = np.linalg.norm(gn - g)
+            g = gn
+            if fixed_k is None and self._converged(inc, np.linalg.norm(g), tol, relative):
+                return dict(g=g, vs=vs, k=k, q_total=q_total, inc=inc)
+        if fixed_k is None:
+            raise NoConvergence(f"classical Schwarz did not converge in {max_k}")
+        return dict(g=g, vs=vs, k=nk, q_total=q_total, inc=inc)
+
+    # ---- free interface operator L_h (Section 3, eq. Lmpi) -------------
+    def free_solver(self, j):
+        """LU of the free strip operator K_j(0) (V = 0, f = 0)."""
+        if self._free_lu is None:
+            self._free_lu = [None] * self.N
+        if self._free_lu[j] is None:
+            pb = self.pb
+            m = self.mats[j]
+            K = m.operator(np.zeros((m.nx, m.ny)), pb.dt, pb.lap_coef,
+                           self.pl[j], self.pr[j])
+            self._free_lu[j] = spla.splu(K)
+        return self._free_lu[j]
+
+    def build_Lh(self):
+        """Blocks of L_h as a dict {(row, col): (ny, ny) array} over the
+        trace index t of g (t = 0 .. 2(N-1)-1).  Column t is the free Schwarz
+        map (u_{n-1} = 0, V = 0, beta = 0) applied to unit vectors in trace
+        t; only the strip that reads trace t responds."""
+        pb = self.pb
+        ny, N, p, c = self.ny, self.N, pb.p, pb.lap_coef
+        blocks = {}
+        for j in range(N):
+            m = self.mats[j]
+            lu = self.free_solver(j)
+            inputs = []
+            if j >= 1:
+                inputs.append(("l", 2 * (j - 1) + 1))
+            if j <= N - 2:
+                inputs.append(("r", 2 * j))
+            for side, col in inputs:
+                # right-hand sides -c M^Gamma Q^T e_s for s = 0..ny-1
+                B = np.zeros((m.nx, ny, ny), dtype=complex)
+                line = 0 if side == "l" else m.nx - 1
+                B[line] = -c * m.My.toarray()
+                Vsol = lu.solve(B.reshape(m.nx * ny, ny)).reshape(m.nx, ny, ny)
+                eye = np.eye(ny)
+                if j >= 1:      # out_left of strip j -> new r_{j-1}
+                    blk = -2j * p * Vsol[0]
+                    if side == "l":
+                        blk = blk - eye
+                    blocks[(2 * (j - 1), col)] = blk
+                if j <= N - 2:  # out_right of strip j -> new l_{j+1}
+                    blk = -2j * p * Vsol[-1]
+                    if side == "r":
+                        blk = blk - eye
+                    blocks[(2 * j + 1, col)] = blk
+        self.Lh_blocks = blocks
+        return blocks
+
+    def Lh_matvec(self, x: np.ndarray) -> np.ndarray:
+        ny = self.ny
+        X = x.reshape(-1, ny)
+        Y = np.zeros_like(X)
+        for (r, c), blk in self.Lh_blocks.items():
+            Y[r] += blk @ X[c]
+        return Y.ravel()
+
+    def Lh_dense(self) -> np.ndarray:
+        ny = self.ny
+        nt = 2 * (self.N - 1)
+        L = np.zeros((nt * ny, nt * ny), dtype=complex)
+        for (r, c), blk in self.Lh_blocks.items():
+            L[r * ny:(r + 1) * ny, c * ny:(c + 1) * ny] = blk
+        return L
+
+    def Lh_sparse(self) -> sp.csc_matrix:
+        ny = self.ny
+        nt = 2 * (self.N - 1)
+        rows, cols, vals = [], [], []
+        for (r, c), blk in self.Lh_blocks.items():
+            rr, cc = np.meshgrid(np.arange(ny), np.arange(ny), indexing="ij")
+            rows.append((r * ny + rr).ravel())
+            cols.append((c * ny + cc).ravel())
+            vals.append(blk.ravel())
+        n = nt * ny
+        return sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows),
+                                                     np.concatenate(cols))), shape=(n, n))
+
+    def precond(self, u_old, g0, tol=1e-10, relative=False, max_k=1000,
+                pinv="gmres", gmres_rtol=1e-12, gmres_restart=50, fixed_k=None,
+                fixed_q=None, warm=False):
+        if self.Lh_blocks is None:
+            self.build_Lh()
+        shape = g0.shape
+        if pinv == "direct":
+            P = sp.identity(self.Lh_sparse().shape[0], dtype=complex, format="csc") - self.Lh_sparse()
+            Plu = spla.splu(P.tocsc())
+        g = np.array(g0, dtype=complex)
+        q_total = 0
+        gm_total = 0
+        zetas = None
+        nk = fixed_k if fixed_k is not None else max_k
+        for k in range(1, nk + 1):
+            Rg, vs, qs = self.R(g, u_old, zetas, fixed_q)
+            q_total += sum(qs)
+            if warm:
+                zetas = vs
+            y = (g - Rg).ravel()
+            if pinv == "direct":
+                x = Plu.solve(y)
+            else:
+                x, it = gmres(lambda z: z - self.Lh_matvec(z), y, rtol=gmres_rtol,
+                              restart=gmres_restart)
+                gm_total += it
+            inc = np.linalg.norm(x)
+            g = g - x.reshape(shape)
+            if fixed_k is None and self._converged(inc, np.linalg.norm(g), tol, relative):
+                return dict(g=g, vs=vs, k=k, q_total=q_total, gmres_total=gm_total, inc=inc)
+        if fixed_k is None:
+            raise NoConvergence(f"preconditioned Schwarz did not converge in {max_k}")
+        return dict(g=g, vs=vs, k=nk, q_total=q_total, gmres_total=gm_total, inc=inc)
+
+
+def run_schwarz(pb, u0, W, steps, algo="classical", g0=None, tol=1e-10,
+                relative=False, form="B", tol_q=1e-13, warm=False, **kw):
+    """Time loop: g_1^0 = g0 (zero by default), g_n^0 = g_{n-1}^infinity
+    (Section 5, initial vectors).  W: nodal array or callable n -> W_n."""
+    static = not callable(W)
+    orc = SchwarzOracle(pb, W if static else W(1), form=form, tol_q=tol_q)
+    ny = pb.ncy + 1
+    g = np.zeros((2 * (pb.nsub - 1), ny), complex) if g0 is None else np.array(g0, complex)
+    u = np.array(u0, dtype=complex)
+    stats = []
+    for n in range(1, steps + 1):
+        if not static and n > 1:
+            orc.set_potential(W(n))
+        if algo == "classical":
+            res = orc.classical(u, g, tol=tol, relative=relative, warm=warm, **kw)
+        else:
+            res = orc.precond(u, g, tol=tol, relative=relative, warm=warm, **kw)
+        u = orc.assemble_global(res["vs"], u)
+        g = res["g"]
+        stats.append({k: v for k, v in res.items() if k not in ("g", "vs")})
+    return u, g, stats, orc
