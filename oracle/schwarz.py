@@ -69,9 +69,11 @@ def gmres(matvec, b, rtol=1e-12, restart=50, maxiter=2000):
             H[j + 1, j] = np.linalg.norm(w)
             if H[j + 1, j] != 0:
                 V[j + 1] = w / H[j + 1, j]
+            # complex Givens rotation [[conj(c), conj(s)], [-s, c]] with
+            # c = a/rho, s = b/rho maps (a, b) to (rho, 0)
             for i in range(j):
-                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
-                H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + np.conj(cs[i]) * H[i + 1, j]
+                t = np.conj(cs[i]) * H[i, j] + np.conj(sn[i]) * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
                 H[i, j] = t
             a, bb = H[j, j], H[j + 1, j]
             den = np.sqrt(abs(a) ** 2 + abs(bb) ** 2)
@@ -79,7 +81,7 @@ def gmres(matvec, b, rtol=1e-12, restart=50, maxiter=2000):
             sn[j] = bb / den if den else 0.0
             H[j, j] = den
             H[j + 1, j] = 0.0
-            e[j + 1] = -np.conj(sn[j]) * e[j]
+            e[j + 1] = -sn[j] * e[j]
             e[j] = np.conj(cs[j]) * e[j]
             total += 1
             j_done = j + 1

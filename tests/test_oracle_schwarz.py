@@ -95,6 +95,23 @@ def test_gmres_matches_direct_solve():
     x, it = gmres(lambda z: z - orc.Lh_matvec(z), y, rtol=1e-13)
     assert np.linalg.norm(x - np.linalg.solve(P, y)) < 1e-11 * np.linalg.norm(x)
     assert it > 0
+    # one restart cycle that reaches the tolerance returns without a second
+    # cycle: the residual estimate of the rotated Hessenberg system is exact
+    x1, it1 = gmres(lambda z: z - orc.Lh_matvec(z), y, rtol=1e-10, restart=44)
+    assert it1 <= 44
+    assert np.linalg.norm(y - (x1 - orc.Lh_matvec(x1))) < 1e-9 * np.linalg.norm(y)
+
+
+def test_gmres_on_a_complex_nonnormal_matrix():
+    """Dense complex test matrix with known solution: the least-squares
+    residual tracked by the rotations equals the true residual."""
+    rng = np.random.default_rng(11)
+    n = 60
+    A = np.eye(n) + 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    xs = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, it = gmres(lambda z: A @ z, A @ xs, rtol=1e-12, restart=n)
+    assert it < n
+    assert np.linalg.norm(x - xs) < 1e-10 * np.linalg.norm(xs)
 
 
 def test_warm_start_and_forms_do_not_change_the_answer():
