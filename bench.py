@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the optimized Schwarz time loop on one MI355X.
+
+Workload: the GPE with harmonic trap V = -(x^2+y^2)/2, f(u) = -50|u|^2,
+c = 1/2 on (-8,8)^2 with 512 x 512 cells (263,169 nodes), 16 equal x-strips,
+Robin p = 5 (transmission and physical), dt = 1e-3, preconditioned algorithm
+with GMRES on P = I - L_h; u0 = normalised Gaussian + 1e-3 seeded complex
+noise.  Synthetic, seeded inputs.
+
+A "step" is one time step: the stationary nonlinear problem of the step is
+solved by preconditioned Schwarz iterations, each of which runs the strip
+fixed point (residual stencil + block-tridiagonal substitution per
+iteration) and GMRES on the interface.  The timed region covers the
+factorisation of the strip operators for W_n plus K steps with the inputs
+resident in HBM; L_h is built once at setup (outside the timed region, its
+time is reported).
+
+Printed: one JSON line with dof-steps/s, iterations, a roofline entry for
+the strip-solve kernel (live HIP-event timing of every launch in the timed
+region), the plain FP64 GPU path for comparison, the parity of the first
+steps against the FP64 CPU oracle, and the oracle's own throughput.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dof-steps/s at 1e-10 rel L2 vs FP64 oracle; Schwarz/GMRES iters per step"
+HBM_PEAK_GBS = 8000.0
+
+
+def solver_opts(prec):
+    return dict(algo="precond", prec=prec, tol_k=1e-12, tol_k_relative=True, max_k=500,
+                tol_q=1e-13, max_q=200, warm_start=True, tol_gmres=1e-4,
+                gmres_restart=50, max_gmres=2000, eta_q=1e-2)
+
+
+def solve_bytes(pb, prec):
+    """Algorithmic bytes of one strip-solve launch: the stored inverse of
+    every line is read once in the forward sweep and once in the backward
+    sweep (the last line of a strip only once), plus the right-hand side,
+    the solution and the coupling coefficients once."""
+    n = pb.ncy + 1
+    lt = pb.ncx + pb.nsub
+    es = 8 if prec == "c32" else 16
+    return (2 * lt - pb.nsub) * n * n * es + lt * n * (16 + 16 + 48)
+
+
+def run_gpu(pb, u0, V, prec, steps, warmup, dev, measure=True):
+    import torch
+    from paper_1603_05110_amd import osm
+    t = time.perf_counter()
+    s = osm.OsmSolver(pb, dev, **solver_opts(prec))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t
+    W = torch.from_numpy(V).to(dev)
+    u = torch.from_numpy(u0).to(dev)
+    if warmup > 0:
+        s.factor(W)
+        for _ in range(warmup):
+            s.step(u)
+    torch.cuda.synchronize()
+    if measure:
+        s.kernel_timing(True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.factor(W)
+    t_fac = time.perf_counter() - t0
+    for _ in range(steps):
+        stats.append(s.step(u))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = s.kernel_timing(False) if measure else (0.0, 0)
+    s.close()
+    return dict(seconds=t1 - t0, factor_s=t_fac, setup_s=t_setup, stats=stats, u=u,
+                solve_ms=kern[0], solve_launches=kern[1])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="c32", choices=["fp64", "c32"])
+    ap.add_argument("--fp64-steps", type=int, default=50,
+                    help="steps of the plain FP64 GPU path timed for comparison (0 = skip)")
+    ap.add_argument("--parity-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the strips of one instance are spread over the workgroups of one MI355X.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from workloads import c2
+
+    dev = "cuda:0"
+    wl = c2()
+    pb, u0, V = wl.problems[0], wl.u0[0], wl.V[0]
+    dof = (pb.ncx + 1) * (pb.ncy + 1)
+    print(f"bench: {pb.name} dof={dof} prec={args.prec} steps={args.steps}", file=sys.stderr,
+          flush=True)
+
+    main_run = run_gpu(pb, u0, V, args.prec, args.steps, args.warmup, dev)
+    T = main_run["seconds"]
+    st = main_run["stats"]
+    value = dof * args.steps / T
+    ks = [x["k"] for x in st]
+    qs = [x["q_total"] for x in st]
+    gm = [x["gmres_total"] for x in st]
+    print(f"bench: {args.prec} {T:.3f}s for factor+{args.steps} steps, {value:.4g} dof-steps/s",
+          file=sys.stderr, flush=True)
+
+    avg_ms = main_run["solve_ms"] / max(main_run["solve_launches"], 1)
+    nbytes = solve_bytes(pb, args.prec)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+
+    fp64 = None
+    if args.prec != "fp64" and args.fp64_steps > 0:
+        r = run_gpu(pb, u0, V, "fp64", args.fp64_steps, args.warmup, dev)
+        fp64 = {"value": dof * args.fp64_steps / r["seconds"], "steps": args.fp64_steps,
+                "ms_per_step": 1e3 * r["seconds"] / args.fp64_steps,
+                "solve_kernel_ms": r["solve_ms"] / max(r["solve_launches"], 1)}
+        print(f"bench: fp64 {fp64['value']:.4g} dof-steps/s", file=sys.stderr, flush=True)
+
+    # parity of the first steps against the FP64 CPU oracle, and its throughput
+    parity = None
+    cpu = None
+    if args.parity_steps > 0 and not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle.step import MonolithicStepper
+        r = run_gpu(pb, u0, V, args.prec, args.parity_steps, 0, dev, measure=False)
+        ugpu = r["u"].cpu().numpy()
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            ost = MonolithicStepper(pb, V, form="B", tol_q=1e-14)
+            t_fac = time.perf_counter() - t0
+            u = np.array(u0, dtype=complex)
+            t1 = time.perf_counter()
+            for _ in range(args.parity_steps):
+                u, _, _ = ost.step(u)
+            t_step = (time.perf_counter() - t1) / args.parity_steps
+        err = float(np.linalg.norm(ugpu - u) / np.linalg.norm(u))
+        parity = {"steps": args.parity_steps, "rel_l2_vs_oracle": err}
+        cpu = {"value": dof * args.steps / (t_fac + args.steps * t_step),
+               "unit": "dof-steps/s", "cores": 1, "kind": "oracle",
+               "sample": (f"FP64 monolithic oracle (SciPy splu, fixed point form B) on the same "
+                          f"workload: factor {t_fac:.2f}s + {args.parity_steps} steps at "
+                          f"{t_step:.2f}s/step, extrapolated to the {args.steps}-step job")}
+        print(f"bench: parity rel L2 {err:.3e}; oracle {cpu['value']:.4g} dof-steps/s",
+              file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "dof-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64-refine" if args.prec == "c32" else "c128",
+        "data": "synthetic",
+        "config": {"workload": "GPE trap V=-(x^2+y^2)/2, f=-50|u|^2, (-8,8)^2, 512x512 cells, "
+                               "16 equal strips, Robin p=5, dt=1e-3, preconditioned GMRES",
+                   "dof": dof, "strips": pb.nsub, "algo": "precond", "prec": args.prec,
+                   "timed": "factor(W) + steps"},
+        "iters": {"k_mean": float(np.mean(ks)), "k_max": int(np.max(ks)),
+                  "q_total": int(np.sum(qs)), "gmres_total": int(np.sum(gm)),
+                  "gmres_per_step": float(np.mean(gm))},
+        "roofline": {"kernel": "strip_solve", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
+                     "launches": main_run["solve_launches"]},
+        "setup_s": main_run["setup_s"],
+        "factor_s": main_run["factor_s"],
+        "fp64_gpu": fp64,
+        "parity": parity,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * osm.h -- C ABI of the MI355X optimized-Schwarz solver for the 2-D nonlinear
+ * Schroedinger / Gross-Pitaevskii equation (Besse & Xing, arXiv:1603.05110).
+ *
+ * One call of osm_step advances the Duran-Sanz-Serna midpoint scheme by one
+ * time step (Section 2.1, eq. CNS): the stationary nonlinear problem of the
+ * step is split into non-overlapping x-strips (Section 2.1, eq. algolocal)
+ * coupled by Robin transmission conditions S = -ip (eq. TCSRobin), each strip
+ * problem is resolved by the fixed point of Section 2.2 (eq. localpbrobin) on
+ * the Q1 finite-element system of eq. NproblemRobinNL, and the interface
+ * vector g = (r_1, l_2, r_2, ..., l_N) (eq. algo_d) is iterated either by the
+ * classical algorithm g <- R(g) (eqs. fluxlr, AlgoGraph) or by the
+ * preconditioned algorithm g <- g - P^{-1}(g - R(g)) with P = I - L_h
+ * (Section 3, eqs. algo_pd, Lmpi), P^{-1} applied by GMRES (Section 4.2).
+ *
+ * Conventions shared by every entry point
+ *   - Mesh: ncx x ncy cells on (xl,xr) x (yb,yu); nodal arrays are x-major,
+ *     y-fast, (ncx+1)*(ncy+1) entries, node (i,k) at (xl+i*hx, yb+k*hy).
+ *   - Strip j owns cells [s_j, s_j + strip_cells[j]) in x and the node-lines
+ *     s_j .. s_j+strip_cells[j]; interface lines are duplicated.  "Packed
+ *     strip layout" = the strips' node-lines concatenated in strip order,
+ *     (ncx + nsub) lines of ny = ncy+1 complex values.
+ *   - Interface vectors have shape (2*(nsub-1), ny): row 2i is r_i, row 2i+1
+ *     is l_{i+1}, for the interface between strips i and i+1 (0-based).
+ *   - Complex values are osm_c64 = {re, im} (the layout of torch.complex128).
+ *   - Pointers named *_dev are device pointers on the handle's device, valid
+ *     and 16-byte aligned for the duration of the call; the caller owns them.
+ *     Host structs are read during the call and copied where needed.
+ *   - All work is enqueued on the HIP stream given to osm_setup; entry points
+ *     that report scalars (stats, norms) synchronise that stream.
+ *   - Every call returns an osm_status; nothing throws or aborts across the
+ *     ABI.  On error the message is available from osm_last_error.
+ *     OSM_EINVAL leaves outputs untouched; OSM_ENOCONV leaves u_dev holding
+ *     u_{n-1} unchanged and fills the stats.
+ */
+#ifndef OSM_H
+#define OSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct osm_handle osm_handle;
+typedef struct { double re, im; } osm_c64;
+
+typedef enum {
+    OSM_OK = 0,
+    OSM_EINVAL = -1,        /* bad argument (sizes, strips, parameters)         */
+    OSM_ENOMEM = -2,        /* footprint exceeds free device memory or the cap  */
+    OSM_EHIP = -3,          /* a HIP runtime call or kernel launch failed       */
+    OSM_ENOCONV = -4,       /* fixed point, Schwarz or GMRES hit its cap        */
+    OSM_ENONFINITE = -5,    /* NaN/Inf met in the iterates                      */
+    OSM_ESTATE = -6,        /* call out of order (e.g. step before factor)      */
+    OSM_EUNSUPPORTED = -7   /* option not built (e.g. the Pade condition)       */
+} osm_status;
+
+typedef enum { OSM_TC_ROBIN = 0, OSM_TC_PADE = 1 } osm_tc;
+typedef enum { OSM_CLASSICAL = 0, OSM_PRECOND = 1 } osm_algo;
+typedef enum { OSM_FP64 = 0, OSM_C32_REFINE = 1 } osm_prec;
+typedef enum {
+    OSM_IFACE_R = 0,          /* g_out = R(g_in): the nonlinear Schwarz map      */
+    OSM_IFACE_I_MINUS_R = 1,  /* g_out = g_in - R(g_in)                          */
+    OSM_IFACE_LH = 2,         /* g_out = L_h g_in (free linear part, eq. Lmpi)  */
+    OSM_IFACE_PINV = 3        /* g_out = (I - L_h)^{-1} g_in by GMRES            */
+} osm_iface_op;
+
+/* The problem statement (Section 2: eqs. Sch, BC, BCRobin; Section 2.1). */
+typedef struct {
+    double xl, xr, yb, yu;        /* Omega = (xl,xr) x (yb,yu)                    */
+    int32_t ncx, ncy;             /* cells per direction                          */
+    int32_t nsub;                 /* N x-strips (>= 2)                            */
+    const int32_t *strip_cells;   /* host, nsub entries >= 2 summing to ncx;
+                                     NULL = equal strips (ncx % nsub == 0)        */
+    double lap_coef;              /* c in i u_t + c Lap u + V u + f(u) u = 0:
+                                     1 (NLS) or 1/2 (GPE, Section 5.2)            */
+    double beta;                  /* f(u) = beta |u|^2, sign as in eq. Sch        */
+    int32_t tc;                   /* osm_tc; only OSM_TC_ROBIN is built            */
+    double p;                     /* Robin transmission parameter, S = -ip, p > 0  */
+    double p_bc;                  /* Robin parameter on the physical x-edges
+                                     (the paper uses p_bc = p; 0 = Neumann)        */
+    double dt;                    /* time step                                     */
+    double omega, vxx, vyy;       /* rotating-frame potential (Section 5.2.1):
+                                     V(x,y) = vxx x^2 + vyy y^2 seen at A(t) x~;
+                                     used only by osm_factor_rotating              */
+} osm_problem;
+
+typedef struct {
+    int32_t algo;                 /* osm_algo                                      */
+    int32_t prec;                 /* osm_prec: FP64, or complex-FP32 factor and
+                                     substitution with FP64 residual correction    */
+    double tol_k;                 /* Schwarz stop: ||g^{k+1}-g^k||_2 < tol_k
+                                     (paper: 1e-10 absolute, Section 5)            */
+    int32_t tol_k_relative;       /* 1: tol_k * ||g^{k+1}||_2 instead             */
+    int32_t max_k;
+    double tol_q;                 /* fixed point: ||dzeta|| <= tol_q ||zeta||      */
+    int32_t max_q;
+    int32_t fixed_k, fixed_q;     /* > 0: run exactly that many iterations         */
+    int32_t warm_start;           /* 1: each fixed point starts from the previous
+                                     Schwarz iterate; 0: from u_{n-1} (paper)      */
+    double tol_gmres;             /* relative residual of P x = y                  */
+    int32_t gmres_restart, max_gmres;
+    int32_t guess;                /* 0: g_n^0 = g_{n-1} converged (paper);
+                                     1: the vector of osm_set_interface_guess     */
+    int32_t team;                 /* workgroups per strip in the solve; 0 = auto   */
+    uint64_t mem_cap;             /* 0 = free device memory; else a byte cap       */
+    double eta_q;                 /* > 0: inexact inner solves; Schwarz iteration k
+                                     stops its fixed points at
+                                     max(tol_q, eta_q * (relative increment of
+                                     iteration k-1)), iteration 1 at
+                                     max(tol_q, eta_q); the converged answer is
+                                     unchanged.  0 = always tol_q                 */
+} osm_options;
+
+typedef struct {
+    int32_t k;                    /* Schwarz (outer) iterations                    */
+    int32_t q_total;              /* fixed-point iterations summed over k          */
+    int32_t gmres_total;          /* GMRES iterations summed over k                */
+    int32_t refine_total;         /* FP32 solves corrected by an FP64 residual     */
+    int32_t fallback_used;        /* guess rejected, previous g used instead       */
+    double last_increment;        /* last ||g^{k+1} - g^k||_2                      */
+    double mass_before, mass_after; /* u* M u before and after the step           */
+} osm_step_stats;
+
+typedef struct { uint64_t device_bytes, host_bytes; } osm_footprint;
+
+/* Device and host bytes osm_setup would allocate.  Pure host computation. */
+osm_status osm_query(const osm_problem *prob, const osm_options *opt,
+                     osm_footprint *out);
+
+/* Validate the problem, allocate every device buffer (the only allocation
+ * point), build the free interface operator L_h when opt->algo is
+ * OSM_PRECOND (Section 4.2: 2 ny single-strip solves per distinct strip),
+ * and return a handle bound to hip_stream (NULL = default stream) and to the
+ * current device.  Returns OSM_ENOMEM before allocating when the footprint
+ * exceeds the free device memory or opt->mem_cap. */
+osm_status osm_setup(const osm_problem *prob, const osm_options *opt,
+                     void *hip_stream, osm_handle **out);
+
+/* Set the step potential W_n = (V_n + V_{n-1})/2 (Section 2.1) from a device
+ * array of (ncx+1)*(ncy+1) doubles and factor every strip operator
+ * K_j(W_n) = 2i/dt M - c S + M_W + i c (p_l M^Gamma_l + p_r M^Gamma_r)
+ * (eq. NproblemRobinNL without the nonlinear term) by block Thomas with dense
+ * ny x ny Schur complements, inverted on the matrix cores. */
+osm_status osm_factor(osm_handle *h, const double *W_dev);
+
+/* Same, with W_n computed on the device from the rotating-frame potential of
+ * Section 5.2.1 at t_n = n dt and t_{n-1}. */
+osm_status osm_factor_rotating(osm_handle *h, int32_t n);
+
+/* One time step: u_dev holds u_{n-1} (global nodes) on entry and u_n on
+ * successful exit.  stats may be NULL. */
+osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats);
+
+/* Interface operators at the state u_dev = u_{n-1} (read only; ignored for
+ * OSM_IFACE_LH and OSM_IFACE_PINV).  g_in_dev and g_out_dev have the
+ * interface layout and must not overlap. */
+osm_status osm_interface_apply(osm_handle *h, osm_iface_op op,
+                               const osm_c64 *u_dev, const osm_c64 *g_in_dev,
+                               osm_c64 *g_out_dev);
+
+/* Interface guess g^0 for the next osm_step when opt->guess == 1. */
+osm_status osm_set_interface_guess(osm_handle *h, const osm_c64 *g0_dev);
+
+/* Copy the last converged interface vector. */
+osm_status osm_get_interface(osm_handle *h, osm_c64 *g_dev);
+
+/* x = K_j(W_n)^{-1} b on every strip at once (packed strip layout), with the
+ * factor of the last osm_factor in the handle's precision (FP32 factors are
+ * applied without correction).  b_dev and x_dev must not overlap. */
+osm_status osm_strip_solve(osm_handle *h, const osm_c64 *b_dev, osm_c64 *x_dev);
+
+/* Copy the strip solutions v_j of the last step or interface apply (packed
+ * strip layout). */
+osm_status osm_get_strip_solution(osm_handle *h, osm_c64 *v_dev);
+
+/* Copy the dense blocks X^{j,1..4} of L_h (Proposition 3.1) of every strip:
+ * nsub x 4 x ny x ny complex, row-major blocks; blocks a strip does not have
+ * (X^{1,1..3}, X^{N,2..4}) are zero. */
+osm_status osm_get_lh_blocks(osm_handle *h, osm_c64 *blocks_dev);
+
+/* Copy the stored block-Thomas factor: for every line of the packed strip
+ * layout the dense inverse S_i^{-1} of its Schur complement (ny x ny,
+ * row-major), complex128 in OSM_FP64 and complex64 in OSM_C32_REFINE;
+ * (ncx + nsub) * ny * ny elements. */
+osm_status osm_get_factor(osm_handle *h, void *dst_dev);
+
+/* Kernel timing for measurement: enable = 1 resets the counters and brackets
+ * every later launch of the strip-solve kernel with HIP events on the
+ * handle's stream; enable = 0 stops.  Both return, in *solve_ms and
+ * *solve_launches (either may be NULL), the summed kernel time and the
+ * launch count accumulated since the last reset. */
+osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
+                             int64_t *solve_launches);
+
+void osm_destroy(osm_handle *h);
+const char *osm_last_error(const osm_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OSM_H */

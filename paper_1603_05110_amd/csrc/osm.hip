@@ -1,0 +1,926 @@
+// Host side of libosm: the C ABI of include/osm.h.  Owns every device
+// buffer (allocated in osm_setup only), drives the factorisation, the fixed
+// point, the Schwarz iterations and GMRES on the handle's stream.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <complex>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/osm.h"
+#include "osm_internal.h"
+
+#define GJ_BK 32
+
+typedef std::complex<double> zc;
+
+struct osm_handle {
+    osm_problem prob;
+    osm_options opt;
+    std::vector<int> cells;
+    hipStream_t st = nullptr;
+    int device = 0;
+    Phys P;
+    int n = 0, N = 0, Lt = 0, nglob = 0, ng = 0, maxnx = 0;
+    int fp32 = 0;
+    std::vector<StripMeta> strips_h;
+    StripMeta *strips_d = nullptr;
+    int *line_strip_d = nullptr;
+    int2 *gmap_d = nullptr;
+    // factor
+    void *F = nullptr;
+    double2 *Dc = nullptr, *Uc = nullptr;
+    double *W_d = nullptr;
+    std::vector<int> step_batch, step_off;
+    int *step_lines_d = nullptr, *step_first_d = nullptr;
+    int *ff_lines_d = nullptr, *ff_first_d = nullptr;
+    void *Rbuf = nullptr, *Cbuf = nullptr;
+    // strip vectors
+    double2 *zeta = nullptr, *res = nullptr, *delta = nullptr;
+    // interface vectors
+    double2 *g = nullptr, *gn = nullptr, *gtmp = nullptr, *gguess = nullptr, *gx = nullptr;
+    double *line_part = nullptr, *strip_norms = nullptr, *trace_part = nullptr;
+    double *mass_part = nullptr, *scal = nullptr;
+    int *flag_d = nullptr;
+    // solve
+    unsigned *counters = nullptr;
+    int *err_d = nullptr;
+    int team = 0;
+    // L_h
+    int ncls = 0;
+    double2 *LH = nullptr;
+    // GMRES
+    int m = 0, nblk = 0;
+    double2 *Vb = nullptr, *dots_part = nullptr, *dots = nullptr;
+    double *norm_part = nullptr;
+    // kernel timing (HIP events around every solve launch when enabled)
+    bool prof = false, prof_pending = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double solve_ms = 0.0;
+    long long solve_launches = 0;
+    // state
+    bool factored = false, has_guess = false;
+    std::string err;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+osm_status fail(osm_handle *h, osm_status s, const std::string &msg) {
+    if (h) h->err = msg;
+    else g_setup_error = msg;
+    return s;
+}
+
+#define HIPCHK(h, call)                                                                     \
+    do {                                                                                    \
+        hipError_t _e = (call);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return fail(h, OSM_EHIP, std::string(#call) + ": " + hipGetErrorString(_e));    \
+    } while (0)
+
+std::vector<int> strip_cells_of(const osm_problem *p) {
+    std::vector<int> c;
+    if (p->strip_cells) {
+        for (int j = 0; j < p->nsub; ++j) c.push_back(p->strip_cells[j]);
+    } else if (p->nsub > 0 && p->ncx % p->nsub == 0) {
+        c.assign(p->nsub, p->ncx / p->nsub);
+    }
+    return c;
+}
+
+std::string validate(const osm_problem *p, const osm_options *o) {
+    if (!p || !o) return "null problem or options";
+    if (!(p->xr > p->xl) || !(p->yu > p->yb)) return "empty domain";
+    if (p->ncx < 4 || p->ncy < 2) return "mesh too small (ncx >= 4, ncy >= 2)";
+    if (p->ncy + 1 > 4096) return "ncy + 1 > 4096 not supported";
+    if (p->nsub < 2) return "nsub must be >= 2";
+    if (p->tc != OSM_TC_ROBIN) return "only the Robin transmission condition is built";
+    if (!(p->p > 0)) return "Robin parameter p must be > 0";
+    if (!(p->p_bc >= 0)) return "p_bc must be >= 0";
+    if (!(p->dt > 0) || !(p->lap_coef > 0)) return "dt and lap_coef must be > 0";
+    if (!isfinite(p->beta)) return "beta not finite";
+    std::vector<int> c = strip_cells_of(p);
+    if ((int)c.size() != p->nsub) return "strip_cells NULL but ncx not divisible by nsub";
+    long sum = 0;
+    for (int v : c) {
+        if (v < 2) return "every strip needs >= 2 cells";
+        sum += v;
+    }
+    if (sum != p->ncx) return "strip_cells do not sum to ncx";
+    if (o->algo != OSM_CLASSICAL && o->algo != OSM_PRECOND) return "bad algo";
+    if (o->prec != OSM_FP64 && o->prec != OSM_C32_REFINE) return "bad prec";
+    if (o->max_k < 1 && o->fixed_k < 1) return "max_k must be >= 1";
+    if (o->max_q < 1 && o->fixed_q < 1) return "max_q must be >= 1";
+    if (o->algo == OSM_PRECOND && (o->gmres_restart < 1 || o->gmres_restart > 200))
+        return "gmres_restart must be in [1, 200]";
+    return "";
+}
+
+struct Sizes {
+    long n, N, Lt, nglob, ng, maxnx, ncls, m;
+    int fp32;
+};
+
+Sizes sizes_of(const osm_problem *p, const osm_options *o) {
+    Sizes s;
+    std::vector<int> c = strip_cells_of(p);
+    s.n = p->ncy + 1;
+    s.N = p->nsub;
+    s.Lt = p->ncx + p->nsub;
+    s.nglob = p->ncx + 1;
+    s.ng = 2 * (s.N - 1) * s.n;
+    s.maxnx = 0;
+    std::map<std::tuple<int, double, double>, int> cls;
+    for (int j = 0; j < (int)c.size(); ++j) {
+        s.maxnx = std::max<long>(s.maxnx, c[j] + 1);
+        double pl = j == 0 ? p->p_bc : p->p, pr = j == (int)c.size() - 1 ? p->p_bc : p->p;
+        cls.emplace(std::make_tuple(c[j] + 1, pl, pr), 0);
+    }
+    s.ncls = (long)cls.size();
+    s.m = o->algo == OSM_PRECOND ? o->gmres_restart : 0;
+    s.fp32 = o->prec == OSM_C32_REFINE;
+    return s;
+}
+
+uint64_t device_bytes(const Sizes &s) {
+    uint64_t fe = s.fp32 ? 8 : 16;
+    uint64_t b = 0;
+    b += (uint64_t)s.Lt * s.n * s.n * fe;               // factor
+    b += 2ull * s.Lt * s.n * 3 * 16;                    // Dc, Uc
+    b += (uint64_t)s.nglob * s.n * 8;                   // W
+    b += 3ull * s.Lt * s.n * 16;                        // zeta, res, delta
+    b += 5ull * s.ng * 16;                              // interface vectors
+    b += 2ull * s.N * GJ_BK * s.n * fe;                 // GJ panels
+    b += (uint64_t)(3 * s.Lt + 3 * s.N + 2 * 2 * s.N + s.nglob + 64) * 8;
+    if (s.m > 0) {
+        b += 4ull * s.ncls * s.n * s.n * 16;            // L_h blocks
+        b += (uint64_t)(s.m + 2) * s.ng * 16;           // Krylov basis
+        b += 2ull * s.maxnx * s.n * s.n * 16 + (uint64_t)s.n * s.n * 16;  // L_h build temporaries
+        b += 2ull * s.maxnx * s.n * 3 * 16;
+    }
+    return b;
+}
+
+template <typename T>
+void *dalloc(osm_handle *h, size_t bytes, hipError_t *e) {
+    void *p = nullptr;
+    *e = hipMalloc(&p, bytes ? bytes : 16);
+    if (*e == hipSuccess) h->allocs.push_back(p);
+    return p;
+}
+
+#define ALLOC(h, ptr, type, count)                                                          \
+    do {                                                                                    \
+        hipError_t _e;                                                                      \
+        ptr = (type *)dalloc<type>(h, sizeof(type) * (size_t)(count), &_e);                 \
+        if (_e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for " #ptr);     \
+    } while (0)
+
+// ---------------------------------------------------------------- factor
+template <typename T>
+osm_status factor_chain(osm_handle *h, typename cplx_of<T>::type *F, const double2 *Dc,
+                        const double2 *Uc, int nsteps, const std::vector<int> &batch,
+                        const std::vector<int> &off, const int *lines_d, const int *first_d) {
+    typedef typename cplx_of<T>::type T2;
+    int n = h->n;
+    int nblk = (n + GJ_BK - 1) / GJ_BK;
+    T2 *R = (T2 *)h->Rbuf, *C = (T2 *)h->Cbuf;
+    for (int i = 0; i < nsteps; ++i) {
+        int bt = batch[i];
+        if (bt == 0) continue;
+        const int *lines = lines_d + off[i];
+        const int *first = first_d + off[i];
+        HIPCHK(h, launch_schur<T>(h->st, n, F, lines, first, bt, Dc, Uc));
+        for (int kb = 0; kb < nblk; ++kb) {
+            int k0 = kb * GJ_BK, b = std::min(GJ_BK, n - k0);
+            HIPCHK(h, launch_gj_panel<T>(h->st, n, kb, F, lines, bt, R, C));
+            GemmArgs<T> g;
+            g.M = n; g.N = n; g.K = b;
+            g.A = C; g.lda = GJ_BK; g.strideA = (long)n * GJ_BK;
+            g.B = R; g.ldb = n; g.strideB = (long)GJ_BK * n;
+            g.C = F; g.ldc = n; g.D = F; g.ldd = n;
+            g.strideCD = (long)n * n; g.idxCD = lines;
+            g.sign = -1; g.mask_lo = k0; g.mask_hi = k0 + b;
+            HIPCHK(h, launch_zgemm<T>(h->st, g, bt));
+        }
+    }
+    return OSM_OK;
+}
+
+osm_status do_factor(osm_handle *h) {
+    HIPCHK(h, launch_coef(h->st, h->P, h->strips_d, h->line_strip_d, h->W_d, 0, h->Dc, h->Uc, 0,
+                          h->Lt));
+    osm_status s;
+    if (h->fp32)
+        s = factor_chain<float>(h, (float2 *)h->F, h->Dc, h->Uc, h->maxnx, h->step_batch,
+                                h->step_off, h->step_lines_d, h->step_first_d);
+    else
+        s = factor_chain<double>(h, (double2 *)h->F, h->Dc, h->Uc, h->maxnx, h->step_batch,
+                                 h->step_off, h->step_lines_d, h->step_first_d);
+    if (s != OSM_OK) return s;
+    h->factored = true;
+    return OSM_OK;
+}
+
+// x = K^{-1} b on every strip (packed layout)
+osm_status do_solve(osm_handle *h, const double2 *b, double2 *x) {
+    SolveArgs a;
+    a.n = h->n;
+    a.team = h->team;
+    a.nstrips = h->N;
+    a.strips = h->strips_d;
+    a.F = h->F;
+    a.Uc = h->Uc;
+    a.b = b;
+    a.x = x;
+    a.counters = h->counters;
+    a.error = h->err_d;
+    HIPCHK(h, launch_strip_solve(h->st, a, h->fp32, h->prof ? h->ev0 : nullptr,
+                                 h->prof ? h->ev1 : nullptr));
+    h->prof_pending = h->prof;
+    return OSM_OK;
+}
+
+osm_status check_solve_error(osm_handle *h) {
+    int e = 0;
+    HIPCHK(h, hipMemcpyAsync(&e, h->err_d, sizeof(int), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    if (e) return fail(h, OSM_EHIP, "strip solve: barrier wait timed out");
+    if (h->prof_pending) {
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        h->solve_ms += ms;
+        h->solve_launches += 1;
+        h->prof_pending = false;
+    }
+    return OSM_OK;
+}
+
+// ---------------------------------------------------------------- Schwarz map
+// g_out = R(g_in) at state u; the strip solutions are left in h->zeta.
+// zeta holds the fixed-point start on entry (u_{j,n-1} or a warm start).
+osm_status apply_R(osm_handle *h, const double2 *u, const double2 *g_in, double2 *g_out,
+                   int *q_out, double *inc2, double *gn2, double tol_q) {
+    const osm_options &o = h->opt;
+    int nq = o.fixed_q > 0 ? o.fixed_q : o.max_q;
+    int q = 0;
+    bool conv = false;
+    std::vector<double> sn(3 * h->N);
+    for (q = 1; q <= nq; ++q) {
+        HIPCHK(h, launch_residual(h->st, h->P, h->strips_d, h->line_strip_d, h->W_d, u, h->zeta,
+                                  g_in, h->res));
+        osm_status s = do_solve(h, h->res, h->delta);
+        if (s != OSM_OK) return s;
+        HIPCHK(h, launch_update_norms(h->st, h->P, h->zeta, h->delta, h->line_part));
+        HIPCHK(h, launch_strip_sums(h->st, h->P, h->strips_d, h->line_part, h->strip_norms));
+        HIPCHK(h, hipMemcpyAsync(sn.data(), h->strip_norms, sizeof(double) * 3 * h->N,
+                                 hipMemcpyDeviceToHost, h->st));
+        s = check_solve_error(h);   // synchronises the stream
+        if (s != OSM_OK) return s;
+        bool all = true;
+        for (int j = 0; j < h->N; ++j) {
+            if (sn[3 * j + 2] > 0 || !isfinite(sn[3 * j]) || !isfinite(sn[3 * j + 1]))
+                return fail(h, OSM_ENONFINITE, "non-finite fixed-point iterate");
+            if (!(sqrt(sn[3 * j]) <= tol_q * sqrt(sn[3 * j + 1]))) all = false;
+        }
+        if (o.fixed_q <= 0 && all) { conv = true; break; }
+    }
+    if (o.fixed_q > 0) { q = nq; conv = true; }
+    if (!conv) return fail(h, OSM_ENOCONV, "fixed point did not converge within max_q");
+    *q_out = q;
+    int nt = 2 * (h->N - 1);
+    HIPCHK(h, launch_flux(h->st, h->P, h->strips_d, g_in, h->zeta, g_out, h->trace_part));
+    HIPCHK(h, launch_sum(h->st, h->trace_part, nt, 2, h->scal));
+    double sc[2];
+    HIPCHK(h, hipMemcpyAsync(sc, h->scal, sizeof(sc), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    *inc2 = sc[0];
+    *gn2 = sc[1];
+    return OSM_OK;
+}
+
+double dev_norm(osm_handle *h, const double2 *x, long n, osm_status *st) {
+    *st = OSM_OK;
+    hipError_t e = launch_norm_partials(h->st, n, x, h->norm_part, h->nblk);
+    if (e == hipSuccess) e = launch_sum(h->st, h->norm_part, h->nblk, 1, h->scal);
+    double v = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&v, h->scal, sizeof(double), hipMemcpyDeviceToHost, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) { *st = fail(h, OSM_EHIP, hipGetErrorString(e)); return 0; }
+    return sqrt(v);
+}
+
+// ---------------------------------------------------------------- GMRES
+// x = (I - L_h)^{-1} y by restarted GMRES, x0 = 0, classical Gram-Schmidt
+// applied twice (FP64), Givens rotations on the host.
+osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
+    const osm_options &o = h->opt;
+    long n = h->ng;
+    int m = h->m;
+    osm_status s;
+    *iters = 0;
+    HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double2) * n, h->st));
+    double bnorm = dev_norm(h, y, n, &s);
+    if (s != OSM_OK) return s;
+    if (bnorm == 0.0) return OSM_OK;
+    double2 *V = h->Vb;
+    double2 *w = h->Vb + (long)(m + 1) * n;   // scratch vector
+    std::vector<zc> H((m + 1) * m), cs(m), sn(m), e(m + 1);
+    std::vector<double2> hb(2 * (m + 1));
+    int total = 0;
+    bool first = true;
+    bool inner_conv = false;
+    while (total < o.max_gmres) {
+        // r = y - P x
+        if (first) {
+            HIPCHK(h, hipMemcpyAsync(w, y, sizeof(double2) * n, hipMemcpyDeviceToDevice, h->st));
+        } else {
+            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->LH, x, w, 1));
+            HIPCHK(h, launch_axpby(h->st, n, cd(1, 0), y, cd(-1, 0), w, w));
+        }
+        double beta = dev_norm(h, w, n, &s);
+        if (s != OSM_OK) return s;
+        if (!isfinite(beta)) return fail(h, OSM_ENONFINITE, "GMRES residual not finite");
+        // the true residual decides; after a cycle whose rotated residual
+        // met the tolerance, allow a rounding margin of 10x
+        if (beta <= o.tol_gmres * bnorm || (inner_conv && beta <= 10.0 * o.tol_gmres * bnorm))
+            break;
+        HIPCHK(h, launch_scale_copy(h->st, n, w, cd(1.0 / beta, 0), V));
+        std::fill(H.begin(), H.end(), zc(0));
+        std::fill(e.begin(), e.end(), zc(0));
+        e[0] = beta;
+        int jdone = 0;
+        bool conv = false;
+        for (int j = 0; j < m && total < o.max_gmres; ++j) {
+            double2 *vj1 = V + (long)(j + 1) * n;
+            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->LH, V + (long)j * n, vj1, 1));
+            // CGS, twice
+            for (int pass = 0; pass < 2; ++pass) {
+                HIPCHK(h, launch_multidot(h->st, n, V, j + 1, vj1, h->dots_part, h->nblk));
+                HIPCHK(h, launch_multidot_finalize(h->st, h->dots_part, j + 1, h->nblk,
+                                                   h->dots + pass * (m + 1)));
+                HIPCHK(h, launch_multiaxpy(h->st, n, V, j + 1, h->dots + pass * (m + 1), vj1, 1));
+            }
+            HIPCHK(h, launch_norm_partials(h->st, n, vj1, h->norm_part, h->nblk));
+            HIPCHK(h, launch_sum(h->st, h->norm_part, h->nblk, 1, h->scal));
+            HIPCHK(h, hipMemcpyAsync(hb.data(), h->dots, sizeof(double2) * 2 * (m + 1),
+                                     hipMemcpyDeviceToHost, h->st));
+            double hn2 = 0;
+            HIPCHK(h, hipMemcpyAsync(&hn2, h->scal, sizeof(double), hipMemcpyDeviceToHost, h->st));
+            HIPCHK(h, hipStreamSynchronize(h->st));
+            double hn = sqrt(hn2);
+            for (int i = 0; i <= j; ++i)
+                H[i * m + j] = zc(hb[i].x + hb[m + 1 + i].x, hb[i].y + hb[m + 1 + i].y);
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0) HIPCHK(h, launch_scale_copy(h->st, n, vj1, cd(1.0 / hn, 0), vj1));
+            // complex Givens rotation [[conj(c), conj(s)], [-s, c]],
+            // c = a/rho, s = b/rho, maps (a, b) to (rho, 0)
+            for (int i = 0; i < j; ++i) {
+                zc t = std::conj(cs[i]) * H[i * m + j] + std::conj(sn[i]) * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t;
+            }
+            zc a = H[j * m + j], bb = H[(j + 1) * m + j];
+            double den = sqrt(std::norm(a) + std::norm(bb));
+            cs[j] = den > 0 ? a / den : zc(1);
+            sn[j] = den > 0 ? bb / den : zc(0);
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0;
+            e[j + 1] = -sn[j] * e[j];
+            e[j] = std::conj(cs[j]) * e[j];
+            ++total;
+            jdone = j + 1;
+            if (std::abs(e[j + 1]) <= o.tol_gmres * bnorm) { conv = true; break; }
+            if (hn == 0) { conv = true; break; }
+        }
+        // back substitution and x += V y
+        std::vector<zc> yv(jdone);
+        for (int i = jdone - 1; i >= 0; --i) {
+            zc t = e[i];
+            for (int k = i + 1; k < jdone; ++k) t -= H[i * m + k] * yv[k];
+            yv[i] = t / H[i * m + i];
+        }
+        std::vector<double2> yd(jdone);
+        for (int i = 0; i < jdone; ++i) yd[i] = cd(yv[i].real(), yv[i].imag());
+        HIPCHK(h, hipMemcpyAsync(h->dots, yd.data(), sizeof(double2) * jdone, hipMemcpyHostToDevice,
+                                 h->st));
+        HIPCHK(h, launch_multiaxpy(h->st, n, V, jdone, h->dots, x, 0));
+        first = false;
+        inner_conv = conv;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    *iters = total;
+    if (total >= o.max_gmres && !inner_conv)
+        return fail(h, OSM_ENOCONV, "GMRES did not converge within max_gmres");
+    return OSM_OK;
+}
+
+// ---------------------------------------------------------------- L_h build
+osm_status build_lh(osm_handle *h) {
+    int n = h->n;
+    long nn = (long)n * n;
+    // class table: strips with equal (nx, pl, pr) share their blocks
+    std::map<std::tuple<int, double, double>, int> cls;
+    std::vector<int> rep;
+    for (int j = 0; j < h->N; ++j) {
+        StripMeta &s = h->strips_h[j];
+        auto key = std::make_tuple(s.nx, s.pl, s.pr);
+        auto it = cls.find(key);
+        if (it == cls.end()) {
+            int c = (int)rep.size();
+            cls.emplace(key, c);
+            rep.push_back(j);
+            s.cls = c;
+        } else {
+            s.cls = it->second;
+        }
+    }
+    h->ncls = (int)rep.size();
+    HIPCHK(h, hipMemcpy(h->strips_d, h->strips_h.data(), sizeof(StripMeta) * h->N,
+                        hipMemcpyHostToDevice));
+    ALLOC(h, h->LH, double2, 4 * h->ncls * nn);
+    double2 *FF, *Y, *Tb, *fD, *fU;
+    size_t keep = h->allocs.size();
+    ALLOC(h, FF, double2, (long)h->maxnx * nn);
+    ALLOC(h, Y, double2, (long)h->maxnx * nn);
+    ALLOC(h, Tb, double2, nn);
+    ALLOC(h, fD, double2, (long)h->maxnx * n * 3);
+    ALLOC(h, fU, double2, (long)h->maxnx * n * 3);
+    std::vector<int> one(h->maxnx, 1), offs(h->maxnx);
+    for (int i = 0; i < h->maxnx; ++i) offs[i] = i;
+    double p = h->prob.p, c = h->prob.lap_coef;
+    osm_status s = OSM_OK;
+    for (int cl = 0; cl < h->ncls && s == OSM_OK; ++cl) {
+        const StripMeta &sm = h->strips_h[rep[cl]];
+        int nx = sm.nx;
+        HIPCHK(h, launch_coef(h->st, h->P, h->strips_d, h->line_strip_d, nullptr, 1, fD, fU, sm.off, nx));
+        s = factor_chain<double>(h, FF, fD, fU, nx, one, offs, h->ff_lines_d, h->ff_first_d);
+        if (s != OSM_OK) break;
+        double2 *X1 = h->LH + (long)(4 * cl + 0) * nn, *X2 = h->LH + (long)(4 * cl + 1) * nn;
+        double2 *X3 = h->LH + (long)(4 * cl + 2) * nn, *X4 = h->LH + (long)(4 * cl + 3) * nn;
+        GemmArgs<double> g;
+        g.M = n; g.N = n; g.K = n;
+        g.lda = n; g.ldb = n; g.ldc = n; g.ldd = n;
+        g.strideA = 0; g.strideB = 0; g.strideCD = 0; g.idxCD = nullptr;
+        g.mask_lo = 0; g.mask_hi = 0;
+        // right-hand sides -c M^Gamma Q_l^T e_s: forward then backward sweep
+        HIPCHK(h, launch_set_tridiag_mass(h->st, n, h->P.hy, -c, Tb));
+        for (int i = 0; i < nx; ++i) {
+            if (i > 0)
+                HIPCHK(h, launch_tridiag_apply(h->st, n, fU + (long)(i - 1) * n * 3, 1, -1.0,
+                                               Y + (long)(i - 1) * nn, Tb));
+            g.A = FF + (long)i * nn; g.B = Tb; g.C = nullptr; g.D = Y + (long)i * nn; g.sign = 1;
+            HIPCHK(h, launch_zgemm<double>(h->st, g, 1));
+        }
+        HIPCHK(h, launch_lh_form(h->st, n, Y + (long)(nx - 1) * nn, -2.0 * p, 0, X3));
+        for (int i = nx - 2; i >= 0; --i) {
+            HIPCHK(h, launch_tridiag_apply(h->st, n, fU + (long)i * n * 3, 0, 1.0,
+                                           Y + (long)(i + 1) * nn, Tb));
+            g.A = FF + (long)i * nn; g.B = Tb; g.C = Y + (long)i * nn; g.D = Y + (long)i * nn;
+            g.sign = -1;
+            HIPCHK(h, launch_zgemm<double>(h->st, g, 1));
+        }
+        HIPCHK(h, launch_lh_form(h->st, n, Y, -2.0 * p, 1, X1));
+        // right-hand sides -c M^Gamma Q_r^T e_s: only the last line is nonzero
+        HIPCHK(h, launch_set_tridiag_mass(h->st, n, h->P.hy, -c, Tb));
+        g.A = FF + (long)(nx - 1) * nn; g.B = Tb; g.C = nullptr; g.D = Y + (long)(nx - 1) * nn;
+        g.sign = 1;
+        HIPCHK(h, launch_zgemm<double>(h->st, g, 1));
+        HIPCHK(h, launch_lh_form(h->st, n, Y + (long)(nx - 1) * nn, -2.0 * p, 1, X4));
+        for (int i = nx - 2; i >= 0; --i) {
+            HIPCHK(h, launch_tridiag_apply(h->st, n, fU + (long)i * n * 3, 0, 1.0,
+                                           Y + (long)(i + 1) * nn, Tb));
+            g.A = FF + (long)i * nn; g.B = Tb; g.C = nullptr; g.D = Y + (long)i * nn; g.sign = -1;
+            HIPCHK(h, launch_zgemm<double>(h->st, g, 1));
+        }
+        HIPCHK(h, launch_lh_form(h->st, n, Y, -2.0 * p, 0, X2));
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    // release the build temporaries
+    for (size_t i = keep; i < h->allocs.size(); ++i) hipFree(h->allocs[i]);
+    h->allocs.resize(keep);
+    return s;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+osm_status osm_query(const osm_problem *prob, const osm_options *opt, osm_footprint *out) {
+    if (!out) return fail(nullptr, OSM_EINVAL, "out is NULL");
+    std::string v = validate(prob, opt);
+    if (!v.empty()) return fail(nullptr, OSM_EINVAL, v);
+    Sizes s = sizes_of(prob, opt);
+    out->device_bytes = device_bytes(s);
+    out->host_bytes = (uint64_t)(s.N * 64 + s.maxnx * 16 + (s.m + 1) * (s.m + 8) * 16 + 4096);
+    return OSM_OK;
+}
+
+osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_stream,
+                     osm_handle **out) {
+    if (!out) return OSM_EINVAL;
+    *out = nullptr;
+    std::string v = validate(prob, opt);
+    if (!v.empty()) return fail(nullptr, OSM_EINVAL, v);
+    Sizes sz = sizes_of(prob, opt);
+    uint64_t need = device_bytes(sz);
+    size_t freeb = 0, totalb = 0;
+    if (opt->mem_cap == 0 || opt->mem_cap > (uint64_t)1 << 62) {
+        if (hipMemGetInfo(&freeb, &totalb) != hipSuccess)
+            return fail(nullptr, OSM_EHIP, "hipMemGetInfo failed");
+    } else {
+        freeb = (size_t)opt->mem_cap;
+    }
+    uint64_t cap = opt->mem_cap ? std::min<uint64_t>(opt->mem_cap, freeb) : freeb;
+    if (need > cap)
+        return fail(nullptr, OSM_ENOMEM, "footprint " + std::to_string(need) +
+                                             " B exceeds available " + std::to_string(cap) + " B");
+
+    osm_handle *h = new osm_handle();
+    h->prob = *prob;
+    h->prob.strip_cells = nullptr;
+    h->opt = *opt;
+    h->cells = strip_cells_of(prob);
+    h->st = (hipStream_t)hip_stream;
+    hipGetDevice(&h->device);
+    h->n = (int)sz.n; h->N = (int)sz.N; h->Lt = (int)sz.Lt; h->nglob = (int)sz.nglob;
+    h->ng = (int)sz.ng; h->maxnx = (int)sz.maxnx; h->fp32 = sz.fp32; h->m = (int)sz.m;
+    Phys &P = h->P;
+    P.hx = (prob->xr - prob->xl) / prob->ncx;
+    P.hy = (prob->yu - prob->yb) / prob->ncy;
+    P.dt = prob->dt; P.c = prob->lap_coef; P.beta = prob->beta; P.p = prob->p;
+    P.ny = h->n; P.nsub = h->N; P.nglob = h->nglob; P.lt = h->Lt;
+    // strips
+    int line = 0, off = 0;
+    std::vector<int> line_strip(h->Lt);
+    std::vector<int2> gmap(h->nglob);
+    for (int j = 0; j < h->N; ++j) {
+        StripMeta s;
+        s.line0 = line; s.nx = h->cells[j] + 1; s.off = off; s.cls = 0;
+        s.pl = j == 0 ? prob->p_bc : prob->p;
+        s.pr = j == h->N - 1 ? prob->p_bc : prob->p;
+        h->strips_h.push_back(s);
+        for (int i = 0; i < s.nx; ++i) {
+            line_strip[off + i] = j;
+            int gl = line + i;
+            if (i == 0 && j > 0) gmap[gl].y = off + i;
+            else { gmap[gl].x = off + i; gmap[gl].y = -1; }
+        }
+        line += h->cells[j];
+        off += s.nx;
+    }
+    // chain steps of the factor: step i factors local line i of every strip with nx > i
+    std::vector<int> lines_all, first_all;
+    for (int i = 0; i < h->maxnx; ++i) {
+        h->step_off.push_back((int)lines_all.size());
+        int bt = 0;
+        for (int j = 0; j < h->N; ++j)
+            if (h->strips_h[j].nx > i) {
+                lines_all.push_back(h->strips_h[j].off + i);
+                first_all.push_back(i == 0);
+                ++bt;
+            }
+        h->step_batch.push_back(bt);
+    }
+    std::vector<int> ffl(h->maxnx), fff(h->maxnx);
+    for (int i = 0; i < h->maxnx; ++i) { ffl[i] = i; fff[i] = i == 0; }
+
+    long nn = (long)h->n * h->n;
+    size_t fe = h->fp32 ? sizeof(float2) : sizeof(double2);
+#define SALLOC(ptr, type, count) ALLOC(h, ptr, type, count)
+    osm_status st = OSM_OK;
+    auto body = [&]() -> osm_status {
+        SALLOC(h->strips_d, StripMeta, h->N);
+        SALLOC(h->line_strip_d, int, h->Lt);
+        SALLOC(h->gmap_d, int2, h->nglob);
+        SALLOC(h->step_lines_d, int, lines_all.size());
+        SALLOC(h->step_first_d, int, first_all.size());
+        SALLOC(h->ff_lines_d, int, h->maxnx);
+        SALLOC(h->ff_first_d, int, h->maxnx);
+        {
+            hipError_t e;
+            h->F = dalloc<char>(h, fe * (size_t)h->Lt * nn, &e);
+            if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for the factor");
+            // panels for a batch of N strips in the factor precision, and for
+            // one strip in FP64 (the free factor built for L_h)
+            size_t pb = std::max(fe * (size_t)h->N, sizeof(double2)) * GJ_BK * h->n;
+            h->Rbuf = dalloc<char>(h, pb, &e);
+            if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for Rbuf");
+            h->Cbuf = dalloc<char>(h, pb, &e);
+            if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for Cbuf");
+        }
+        SALLOC(h->Dc, double2, (long)h->Lt * h->n * 3);
+        SALLOC(h->Uc, double2, (long)h->Lt * h->n * 3);
+        SALLOC(h->W_d, double, (long)h->nglob * h->n);
+        SALLOC(h->zeta, double2, (long)h->Lt * h->n);
+        SALLOC(h->res, double2, (long)h->Lt * h->n);
+        SALLOC(h->delta, double2, (long)h->Lt * h->n);
+        SALLOC(h->g, double2, h->ng);
+        SALLOC(h->gn, double2, h->ng);
+        SALLOC(h->gtmp, double2, h->ng);
+        SALLOC(h->gguess, double2, h->ng);
+        SALLOC(h->gx, double2, h->ng);
+        SALLOC(h->line_part, double, 3 * h->Lt);
+        SALLOC(h->strip_norms, double, 3 * h->N);
+        SALLOC(h->trace_part, double, 2 * 2 * h->N);
+        SALLOC(h->mass_part, double, h->nglob);
+        SALLOC(h->scal, double, 8);
+        SALLOC(h->flag_d, int, 1);
+        SALLOC(h->counters, unsigned, h->N);
+        SALLOC(h->err_d, int, 1);
+        h->nblk = 256;
+        SALLOC(h->norm_part, double, h->nblk);
+        if (h->m > 0) {
+            SALLOC(h->Vb, double2, (long)(h->m + 2) * h->ng);
+            SALLOC(h->dots_part, double2, (long)h->nblk * (h->m + 1));
+            SALLOC(h->dots, double2, 2 * (h->m + 1));
+        }
+        HIPCHK(h, hipMemcpy(h->strips_d, h->strips_h.data(), sizeof(StripMeta) * h->N, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->line_strip_d, line_strip.data(), sizeof(int) * h->Lt, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->gmap_d, gmap.data(), sizeof(int2) * h->nglob, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->step_lines_d, lines_all.data(), sizeof(int) * lines_all.size(), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->step_first_d, first_all.data(), sizeof(int) * first_all.size(), hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->ff_lines_d, ffl.data(), sizeof(int) * h->maxnx, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->ff_first_d, fff.data(), sizeof(int) * h->maxnx, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemset(h->g, 0, sizeof(double2) * h->ng));
+        HIPCHK(h, hipMemset(h->gguess, 0, sizeof(double2) * h->ng));
+        // workgroups per strip in the solve: fill the resident capacity
+        int cap = solve_max_resident_blocks(h->fp32);
+        if (cap <= 0) return fail(h, OSM_EHIP, "occupancy query failed");
+        int team = h->opt.team > 0 ? h->opt.team : std::max(1, std::min(64, cap / h->N));
+        team = std::min(team, std::max(1, cap / h->N));
+        team = std::min(team, h->n);
+        h->team = team;
+        if (h->opt.algo == OSM_PRECOND) {
+            osm_status s = build_lh(h);
+            if (s != OSM_OK) return s;
+        }
+        return OSM_OK;
+    };
+    st = body();
+    if (st != OSM_OK) {
+        g_setup_error = h->err;
+        osm_destroy(h);
+        return st;
+    }
+    *out = h;
+    return OSM_OK;
+}
+
+osm_status osm_factor(osm_handle *h, const double *W_dev) {
+    if (!h) return OSM_EINVAL;
+    if (!W_dev) return fail(h, OSM_EINVAL, "W_dev is NULL");
+    HIPCHK(h, hipMemcpyAsync(h->W_d, W_dev, sizeof(double) * (size_t)h->nglob * h->n,
+                             hipMemcpyDeviceToDevice, h->st));
+    osm_status s = do_factor(h);
+    if (s != OSM_OK) return s;
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return OSM_OK;
+}
+
+osm_status osm_factor_rotating(osm_handle *h, int32_t n) {
+    if (!h) return OSM_EINVAL;
+    if (n < 1) return fail(h, OSM_EINVAL, "step index must be >= 1");
+    double t1 = n * h->prob.dt, t0 = (n - 1) * h->prob.dt;
+    HIPCHK(h, launch_rotating_W(h->st, h->P, h->prob.xl, h->prob.yb, h->prob.omega, h->prob.vxx,
+                                h->prob.vyy, t1, t0, h->W_d));
+    osm_status s = do_factor(h);
+    if (s != OSM_OK) return s;
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return OSM_OK;
+}
+
+static osm_status mass_of(osm_handle *h, const double2 *u, double *out) {
+    HIPCHK(h, launch_mass_partials(h->st, h->P, u, h->mass_part));
+    HIPCHK(h, launch_sum(h->st, h->mass_part, h->nglob, 1, h->scal + 4));
+    HIPCHK(h, hipMemcpyAsync(out, h->scal + 4, sizeof(double), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return OSM_OK;
+}
+
+osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats) {
+    if (!h) return OSM_EINVAL;
+    if (!u_dev) return fail(h, OSM_EINVAL, "u_dev is NULL");
+    if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called before osm_step");
+    const osm_options &o = h->opt;
+    double2 *u = (double2 *)u_dev;
+    osm_step_stats S;
+    memset(&S, 0, sizeof(S));
+    osm_status s;
+    // reject non-finite input
+    HIPCHK(h, hipMemsetAsync(h->flag_d, 0, sizeof(int), h->st));
+    HIPCHK(h, launch_check_finite(h->st, u, (long)h->nglob * h->n, h->flag_d));
+    int bad = 0;
+    HIPCHK(h, hipMemcpyAsync(&bad, h->flag_d, sizeof(int), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    if (bad) return fail(h, OSM_ENONFINITE, "u_{n-1} contains NaN or Inf");
+    s = mass_of(h, u, &S.mass_before);
+    if (s != OSM_OK) return s;
+    if (o.guess == 1 && h->has_guess)
+        HIPCHK(h, hipMemcpyAsync(h->g, h->gguess, sizeof(double2) * h->ng, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
+    int nk = o.fixed_k > 0 ? o.fixed_k : o.max_k;
+    bool conv = false;
+    long ng = h->ng;
+    double prev_rel = 1.0;   // relative increment of the previous Schwarz iteration
+    for (int k = 1; k <= nk; ++k) {
+        if (k > 1 && !o.warm_start)
+            HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
+        int q = 0;
+        double inc2 = 0, gn2 = 0;
+        double tq = o.tol_q;
+        if (o.eta_q > 0) tq = std::max(o.tol_q, o.eta_q * std::min(1.0, prev_rel));
+        s = apply_R(h, u, h->g, h->gn, &q, &inc2, &gn2, tq);
+        S.q_total += q;
+        S.k = k;
+        if (s != OSM_OK) {
+            if (stats) *stats = S;
+            return s;
+        }
+        if (h->fp32) S.refine_total += q;
+        double inc, ref;
+        if (o.algo == OSM_CLASSICAL) {
+            std::swap(h->g, h->gn);
+            inc = sqrt(inc2);
+            ref = sqrt(gn2);
+        } else {
+            // y = g - R(g); x = P^{-1} y; g = g - x
+            HIPCHK(h, launch_axpby(h->st, ng, cd(1, 0), h->g, cd(-1, 0), h->gn, h->gtmp));
+            int it = 0;
+            s = gmres(h, h->gtmp, h->gx, &it);
+            S.gmres_total += it;
+            if (s != OSM_OK) {
+                if (stats) *stats = S;
+                return s;
+            }
+            HIPCHK(h, launch_axpby(h->st, ng, cd(1, 0), h->g, cd(-1, 0), h->gx, h->g));
+            inc = dev_norm(h, h->gx, ng, &s);
+            if (s != OSM_OK) return s;
+            ref = dev_norm(h, h->g, ng, &s);
+            if (s != OSM_OK) return s;
+        }
+        S.last_increment = inc;
+        prev_rel = inc / std::max(ref, 1e-300);
+        if (!isfinite(inc)) {
+            if (stats) *stats = S;
+            return fail(h, OSM_ENONFINITE, "interface increment not finite");
+        }
+        double thr = o.tol_k_relative ? o.tol_k * std::max(ref, 1e-300) : o.tol_k;
+        if (o.fixed_k <= 0 && inc < thr) { conv = true; break; }
+    }
+    if (o.fixed_k > 0) conv = true;
+    if (!conv) {
+        if (stats) *stats = S;
+        return fail(h, OSM_ENOCONV, "Schwarz iteration did not converge within max_k");
+    }
+    HIPCHK(h, launch_time_update(h->st, h->P, h->gmap_d, h->zeta, u));
+    s = mass_of(h, u, &S.mass_after);
+    if (s != OSM_OK) return s;
+    h->has_guess = false;
+    if (stats) *stats = S;
+    return OSM_OK;
+}
+
+osm_status osm_interface_apply(osm_handle *h, osm_iface_op op, const osm_c64 *u_dev,
+                               const osm_c64 *g_in_dev, osm_c64 *g_out_dev) {
+    if (!h) return OSM_EINVAL;
+    if (!g_in_dev || !g_out_dev) return fail(h, OSM_EINVAL, "null interface vector");
+    const double2 *gi = (const double2 *)g_in_dev;
+    double2 *go = (double2 *)g_out_dev;
+    long ng = h->ng;
+    if (op == OSM_IFACE_R || op == OSM_IFACE_I_MINUS_R) {
+        if (!u_dev) return fail(h, OSM_EINVAL, "u_dev is NULL");
+        if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called first");
+        const double2 *u = (const double2 *)u_dev;
+        HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
+        int q;
+        double a, b;
+        osm_status s = apply_R(h, u, gi, h->gn, &q, &a, &b, h->opt.tol_q);
+        if (s != OSM_OK) return s;
+        if (op == OSM_IFACE_R)
+            HIPCHK(h, hipMemcpyAsync(go, h->gn, sizeof(double2) * ng, hipMemcpyDeviceToDevice, h->st));
+        else
+            HIPCHK(h, launch_axpby(h->st, ng, cd(1, 0), gi, cd(-1, 0), h->gn, go));
+    } else if (op == OSM_IFACE_LH) {
+        if (h->opt.algo != OSM_PRECOND) return fail(h, OSM_ESTATE, "L_h is built only for OSM_PRECOND");
+        HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->LH, gi, go, 0));
+    } else if (op == OSM_IFACE_PINV) {
+        if (h->opt.algo != OSM_PRECOND) return fail(h, OSM_ESTATE, "L_h is built only for OSM_PRECOND");
+        int it;
+        osm_status s = gmres(h, gi, go, &it);
+        if (s != OSM_OK) return s;
+    } else {
+        return fail(h, OSM_EINVAL, "unknown interface operator");
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return OSM_OK;
+}
+
+osm_status osm_set_interface_guess(osm_handle *h, const osm_c64 *g0_dev) {
+    if (!h) return OSM_EINVAL;
+    if (!g0_dev) return fail(h, OSM_EINVAL, "g0_dev is NULL");
+    HIPCHK(h, hipMemcpyAsync(h->gguess, g0_dev, sizeof(double2) * h->ng, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    h->has_guess = true;
+    return OSM_OK;
+}
+
+osm_status osm_get_interface(osm_handle *h, osm_c64 *g_dev) {
+    if (!h) return OSM_EINVAL;
+    if (!g_dev) return fail(h, OSM_EINVAL, "g_dev is NULL");
+    HIPCHK(h, hipMemcpyAsync(g_dev, h->g, sizeof(double2) * h->ng, hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return OSM_OK;
+}
+
+osm_status osm_strip_solve(osm_handle *h, const osm_c64 *b_dev, osm_c64 *x_dev) {
+    if (!h) return OSM_EINVAL;
+    if (!b_dev || !x_dev) return fail(h, OSM_EINVAL, "null vector");
+    if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called first");
+    osm_status s = do_solve(h, (const double2 *)b_dev, (double2 *)x_dev);
+    if (s != OSM_OK) return s;
+    return check_solve_error(h);
+}
+
+osm_status osm_get_strip_solution(osm_handle *h, osm_c64 *v_dev) {
+    if (!h) return OSM_EINVAL;
+    if (!v_dev) return fail(h, OSM_EINVAL, "v_dev is NULL");
+    HIPCHK(h, hipMemcpyAsync(v_dev, h->zeta, sizeof(double2) * (size_t)h->Lt * h->n,
+                             hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return OSM_OK;
+}
+
+osm_status osm_get_lh_blocks(osm_handle *h, osm_c64 *blocks_dev) {
+    if (!h) return OSM_EINVAL;
+    if (!blocks_dev) return fail(h, OSM_EINVAL, "blocks_dev is NULL");
+    if (h->opt.algo != OSM_PRECOND) return fail(h, OSM_ESTATE, "L_h is built only for OSM_PRECOND");
+    long nn = (long)h->n * h->n;
+    double2 *out = (double2 *)blocks_dev;
+    HIPCHK(h, hipMemsetAsync(out, 0, sizeof(double2) * 4 * nn * h->N, h->st));
+    for (int j = 0; j < h->N; ++j) {
+        int c = h->strips_h[j].cls;
+        for (int b = 0; b < 4; ++b) {
+            bool has = (j >= 1 || b == 3) && (j <= h->N - 2 || b == 0);
+            if (!has) continue;
+            HIPCHK(h, hipMemcpyAsync(out + (long)(4 * j + b) * nn, h->LH + (long)(4 * c + b) * nn,
+                                     sizeof(double2) * nn, hipMemcpyDeviceToDevice, h->st));
+        }
+    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return OSM_OK;
+}
+
+osm_status osm_get_factor(osm_handle *h, void *dst_dev) {
+    if (!h) return OSM_EINVAL;
+    if (!dst_dev) return fail(h, OSM_EINVAL, "dst_dev is NULL");
+    if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called first");
+    size_t fe = h->fp32 ? sizeof(float2) : sizeof(double2);
+    HIPCHK(h, hipMemcpyAsync(dst_dev, h->F, fe * (size_t)h->Lt * h->n * h->n,
+                             hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return OSM_OK;
+}
+
+osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
+                             int64_t *solve_launches) {
+    if (!h) return OSM_EINVAL;
+    if (enable && !h->ev0) {
+        HIPCHK(h, hipEventCreate(&h->ev0));
+        HIPCHK(h, hipEventCreate(&h->ev1));
+    }
+    if (solve_ms) *solve_ms = h->solve_ms;
+    if (solve_launches) *solve_launches = h->solve_launches;
+    if (enable) {
+        h->solve_ms = 0.0;
+        h->solve_launches = 0;
+    }
+    h->prof = enable != 0;
+    return OSM_OK;
+}
+
+void osm_destroy(osm_handle *h) {
+    if (!h) return;
+    if (h->st) hipStreamSynchronize(h->st);
+    else hipDeviceSynchronize();
+    if (h->ev0) hipEventDestroy(h->ev0);
+    if (h->ev1) hipEventDestroy(h->ev1);
+    for (void *p : h->allocs) hipFree(p);
+    delete h;
+}
+
+const char *osm_last_error(const osm_handle *h) {
+    if (!h) return g_setup_error.c_str();
+    return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Internal definitions of libosm: device-side metadata, launch helpers and
+// the kernel launchers each translation unit provides.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Per-strip description (Section 2.1: strip j = cells [s_j, s_j + cells_j)).
+struct StripMeta {
+    int line0;   // global x node-line of the strip's local line 0
+    int nx;      // node-lines in the strip (cells + 1)
+    int off;     // first line of the strip in the packed strip layout
+    int cls;     // index of its L_h block set (strips with equal nx, pl, pr share)
+    double pl;   // Robin parameter on the left edge  (p, or p_bc for strip 0)
+    double pr;   // Robin parameter on the right edge (p, or p_bc for strip N-1)
+};
+
+// Mesh and equation constants passed by value to the kernels.
+struct Phys {
+    double hx, hy, dt, c, beta, p;
+    int ny;      // nodes per x-line (ncy + 1)
+    int nsub;    // strips
+    int nglob;   // global x node-lines (ncx + 1)
+    int lt;      // packed strip lines (ncx + nsub)
+};
+
+template <typename T> struct cplx_of;
+template <> struct cplx_of<double> { typedef double2 type; };
+template <> struct cplx_of<float> { typedef float2 type; };
+
+__host__ __device__ inline double2 cd(double re, double im) { double2 r; r.x = re; r.y = im; return r; }
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return cd(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return cd(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return cd(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double s, double2 a) { return cd(s * a.x, s * a.y); }
+__device__ __forceinline__ double2 cinv(double2 a) {
+    double d = a.x * a.x + a.y * a.y;
+    return cd(a.x / d, -a.y / d);
+}
+
+// Reference-element integrals of the 1-D linear shape functions psi_0 = 1-s,
+// psi_1 = s on [0,1] (Section 2.2): mass, stiffness and triple product.
+__device__ __forceinline__ double ref_mass(int a, int b) { return a == b ? (1.0 / 3.0) : (1.0 / 6.0); }
+__device__ __forceinline__ double ref_stiff(int a, int b) { return a == b ? 1.0 : -1.0; }
+__device__ __forceinline__ double ref_triple(int c, int a, int b) {
+    return (a == b && b == c) ? 0.25 : (1.0 / 12.0);
+}
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `st` and return the hipError_t of the launch.
+
+// kernels_assemble.hip
+hipError_t launch_coef(hipStream_t st, const Phys &P, const StripMeta *strips,
+                       const int *line_strip, const double *W, int w_is_zero,
+                       double2 *Dc, double2 *Uc, int line_begin, int line_count);
+hipError_t launch_residual(hipStream_t st, const Phys &P, const StripMeta *strips,
+                           const int *line_strip, const double *W, const double2 *u_old,
+                           const double2 *zeta, const double2 *g, double2 *res);
+hipError_t launch_copy_u_to_strips(hipStream_t st, const Phys &P, const StripMeta *strips,
+                                   const int *line_strip, const double2 *u, double2 *zeta);
+hipError_t launch_update_norms(hipStream_t st, const Phys &P, double2 *zeta,
+                               const double2 *delta, double *line_part);
+hipError_t launch_strip_sums(hipStream_t st, const Phys &P, const StripMeta *strips,
+                             const double *line_part, double *strip_out);
+hipError_t launch_flux(hipStream_t st, const Phys &P, const StripMeta *strips,
+                       const double2 *g, const double2 *v, double2 *gn, double *part);
+hipError_t launch_time_update(hipStream_t st, const Phys &P, const int2 *gline_map,
+                              const double2 *v, double2 *u);
+hipError_t launch_mass_partials(hipStream_t st, const Phys &P, const double2 *u, double *part);
+hipError_t launch_sum(hipStream_t st, const double *part, int n, int stride, double *out);
+hipError_t launch_rotating_W(hipStream_t st, const Phys &P, double xl, double yb,
+                             double omega, double vxx, double vyy, double t1, double t0,
+                             double *W);
+hipError_t launch_check_finite(hipStream_t st, const double2 *x, long n, int *flag);
+
+// kernels_factor.hip
+template <typename T>
+hipError_t launch_schur(hipStream_t st, int n, typename cplx_of<T>::type *F,
+                        const int *lines, const int *first, int batch,
+                        const double2 *Dc, const double2 *Uc);
+template <typename T>
+hipError_t launch_gj_panel(hipStream_t st, int n, int kb, const typename cplx_of<T>::type *F,
+                           const int *lines, int batch, typename cplx_of<T>::type *Rbuf,
+                           typename cplx_of<T>::type *Cbuf);
+template <typename T>
+struct GemmArgs {
+    int M, N, K;
+    const typename cplx_of<T>::type *A; long lda; long strideA;
+    const typename cplx_of<T>::type *B; long ldb; long strideB;
+    const typename cplx_of<T>::type *C; long ldc;     // base (may be null or alias D)
+    typename cplx_of<T>::type *D; long ldd;
+    long strideCD; const int *idxCD;                   // C/D offset = (idx ? idx[z] : z) * strideCD
+    int sign;                                          // D = base + sign * A * B
+    int mask_lo, mask_hi;                              // base rows/cols in [lo,hi) read as zero
+};
+template <typename T>
+hipError_t launch_zgemm(hipStream_t st, const GemmArgs<T> &g, int batch);
+hipError_t launch_tridiag_apply(hipStream_t st, int n, const double2 *coef, int transpose,
+                                double scale, const double2 *X, double2 *Y);
+hipError_t launch_set_tridiag_mass(hipStream_t st, int n, double hy, double scale, double2 *Y);
+hipError_t launch_lh_form(hipStream_t st, int n, const double2 *X, double coef_im, int add_eye,
+                          double2 *out);
+template <typename T>
+hipError_t launch_convert(hipStream_t st, long n, const double2 *src, typename cplx_of<T>::type *dst);
+
+// kernels_solve.hip
+struct SolveArgs {
+    int n;
+    int team;
+    int nstrips;
+    const StripMeta *strips;
+    const void *F;           // factor (double2 or float2), line stride n*n
+    const double2 *Uc;       // coupling coefficients, packed lines x n x 3
+    const double2 *b;        // right-hand side, packed
+    double2 *x;              // solution, packed
+    unsigned int *counters;  // one per strip, zero on entry
+    int *error;              // set to 1 if a barrier wait times out
+};
+// ev0/ev1 (may be null) are recorded right before and after the solve kernel
+hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipEvent_t ev0,
+                              hipEvent_t ev1);
+int solve_max_resident_blocks(int fp32);
+
+// kernels_gmres.hip
+hipError_t launch_lh_matvec(hipStream_t st, const Phys &P, const StripMeta *strips,
+                            const double2 *LH, const double2 *x, double2 *y, int mode_p);
+hipError_t launch_multidot(hipStream_t st, long n, const double2 *V, int nv, const double2 *w,
+                           double2 *part, int nblk);
+hipError_t launch_multidot_finalize(hipStream_t st, const double2 *part, int nv, int nblk,
+                                    double2 *out);
+hipError_t launch_multiaxpy(hipStream_t st, long n, const double2 *V, int nv, const double2 *h,
+                            double2 *w, int sub);
+hipError_t launch_norm_partials(hipStream_t st, long n, const double2 *x, double *part, int nblk);
+hipError_t launch_scale_copy(hipStream_t st, long n, const double2 *x, double2 s, double2 *y);
+hipError_t launch_axpby(hipStream_t st, long n, double2 a, const double2 *x, double2 b,
+                        const double2 *y, double2 *z);

@@ -1,0 +1,250 @@
+"""ctypes binding of libosm (include/osm.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of libosm.so.  Device buffers are torch tensors on the handle's device; the
+handle is bound to torch's current HIP stream at setup.  There is no CPU
+fallback: importing this module raises if libosm.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libosm.so")
+
+OSM_OK, OSM_EINVAL, OSM_ENOMEM, OSM_EHIP = 0, -1, -2, -3
+OSM_ENOCONV, OSM_ENONFINITE, OSM_ESTATE, OSM_EUNSUPPORTED = -4, -5, -6, -7
+STATUS_NAMES = {0: "OSM_OK", -1: "OSM_EINVAL", -2: "OSM_ENOMEM", -3: "OSM_EHIP",
+                -4: "OSM_ENOCONV", -5: "OSM_ENONFINITE", -6: "OSM_ESTATE",
+                -7: "OSM_EUNSUPPORTED"}
+OSM_TC_ROBIN, OSM_TC_PADE = 0, 1
+OSM_CLASSICAL, OSM_PRECOND = 0, 1
+OSM_FP64, OSM_C32_REFINE = 0, 1
+OSM_IFACE_R, OSM_IFACE_I_MINUS_R, OSM_IFACE_LH, OSM_IFACE_PINV = 0, 1, 2, 3
+
+
+class osm_problem(ctypes.Structure):
+    _fields_ = [("xl", ctypes.c_double), ("xr", ctypes.c_double),
+                ("yb", ctypes.c_double), ("yu", ctypes.c_double),
+                ("ncx", ctypes.c_int32), ("ncy", ctypes.c_int32),
+                ("nsub", ctypes.c_int32),
+                ("strip_cells", ctypes.POINTER(ctypes.c_int32)),
+                ("lap_coef", ctypes.c_double), ("beta", ctypes.c_double),
+                ("tc", ctypes.c_int32), ("p", ctypes.c_double),
+                ("p_bc", ctypes.c_double), ("dt", ctypes.c_double),
+                ("omega", ctypes.c_double), ("vxx", ctypes.c_double),
+                ("vyy", ctypes.c_double)]
+
+
+class osm_options(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("tol_k", ctypes.c_double), ("tol_k_relative", ctypes.c_int32),
+                ("max_k", ctypes.c_int32), ("tol_q", ctypes.c_double),
+                ("max_q", ctypes.c_int32), ("fixed_k", ctypes.c_int32),
+                ("fixed_q", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("tol_gmres", ctypes.c_double), ("gmres_restart", ctypes.c_int32),
+                ("max_gmres", ctypes.c_int32), ("guess", ctypes.c_int32),
+                ("team", ctypes.c_int32), ("mem_cap", ctypes.c_uint64),
+                ("eta_q", ctypes.c_double)]
+
+
+class osm_step_stats(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("q_total", ctypes.c_int32),
+                ("gmres_total", ctypes.c_int32), ("refine_total", ctypes.c_int32),
+                ("fallback_used", ctypes.c_int32), ("last_increment", ctypes.c_double),
+                ("mass_before", ctypes.c_double), ("mass_after", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class osm_footprint(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_uint64), ("host_bytes", ctypes.c_uint64)]
+
+
+EXPORTS = ["osm_query", "osm_setup", "osm_factor", "osm_factor_rotating", "osm_step",
+           "osm_interface_apply", "osm_set_interface_guess", "osm_get_interface",
+           "osm_strip_solve", "osm_get_strip_solution", "osm_get_lh_blocks", "osm_get_factor",
+           "osm_kernel_timing", "osm_destroy", "osm_last_error"]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    H = ctypes.c_void_p
+    P = ctypes.c_void_p
+    st = ctypes.c_int
+    sig = {
+        "osm_query": ([ctypes.POINTER(osm_problem), ctypes.POINTER(osm_options),
+                       ctypes.POINTER(osm_footprint)], st),
+        "osm_setup": ([ctypes.POINTER(osm_problem), ctypes.POINTER(osm_options), P,
+                       ctypes.POINTER(H)], st),
+        "osm_factor": ([H, P], st),
+        "osm_factor_rotating": ([H, ctypes.c_int32], st),
+        "osm_step": ([H, P, ctypes.POINTER(osm_step_stats)], st),
+        "osm_interface_apply": ([H, ctypes.c_int, P, P, P], st),
+        "osm_set_interface_guess": ([H, P], st),
+        "osm_get_interface": ([H, P], st),
+        "osm_strip_solve": ([H, P, P], st),
+        "osm_get_strip_solution": ([H, P], st),
+        "osm_get_lh_blocks": ([H, P], st),
+        "osm_get_factor": ([H, P], st),
+        "osm_kernel_timing": ([H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_int64)], st),
+        "osm_destroy": ([H], None),
+        "osm_last_error": ([H], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+_lib = load_library()
+
+
+class OsmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status, handle=None):
+    if status != OSM_OK:
+        msg = _lib.osm_last_error(handle)
+        raise OsmError(status, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def make_problem(pb):
+    """osm_problem from any object with the problem-statement attributes
+    (xl, xr, yb, yu, ncx, ncy, nsub, strip_cells, lap_coef, beta, p, p_bc,
+    dt and optionally omega, vxx, vyy).  Returns (struct, keep-alive)."""
+    cells = (ctypes.c_int32 * pb.nsub)(*[int(c) for c in pb.strip_cells])
+    s = osm_problem(pb.xl, pb.xr, pb.yb, pb.yu, pb.ncx, pb.ncy, pb.nsub, cells,
+                    pb.lap_coef, pb.beta, OSM_TC_ROBIN, pb.p, pb.p_bc, pb.dt,
+                    getattr(pb, "omega", 0.0), getattr(pb, "vxx", 0.0),
+                    getattr(pb, "vyy", 0.0))
+    return s, cells
+
+
+def make_options(algo="classical", prec="fp64", tol_k=1e-10, tol_k_relative=False,
+                 max_k=2000, tol_q=1e-13, max_q=100, fixed_k=0, fixed_q=0,
+                 warm_start=True, tol_gmres=1e-12, gmres_restart=50, max_gmres=1000,
+                 guess=0, team=0, mem_cap=0, eta_q=0.0):
+    return osm_options({"classical": OSM_CLASSICAL, "precond": OSM_PRECOND}[algo],
+                       {"fp64": OSM_FP64, "c32": OSM_C32_REFINE}[prec],
+                       tol_k, int(tol_k_relative), max_k, tol_q, max_q, fixed_k, fixed_q,
+                       int(warm_start), tol_gmres, gmres_restart, max_gmres, guess, team,
+                       mem_cap, eta_q)
+
+
+def osm_query(pb, **opts):
+    prob, keep = make_problem(pb)
+    opt = make_options(**opts)
+    fp = osm_footprint()
+    _check(_lib.osm_query(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(fp)))
+    return fp.device_bytes, fp.host_bytes
+
+
+class OsmSolver:
+    """Owns one osm_handle.  Tensors: u (ncx+1, ncy+1) complex128, W
+    (ncx+1, ncy+1) float64, interface vectors (2(N-1), ncy+1) complex128,
+    packed strip vectors (ncx+nsub, ncy+1) complex128, all on the device."""
+
+    def __init__(self, pb, device="cuda:0", **opts):
+        self.pb = pb
+        self.device = torch.device(device)
+        self.ny = pb.ncy + 1
+        self.nglob = pb.ncx + 1
+        self.lt = pb.ncx + pb.nsub
+        self.ntr = 2 * (pb.nsub - 1)
+        prob, self._keep = make_problem(pb)
+        self._opt = make_options(**opts)
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            h = ctypes.c_void_p()
+            _check(_lib.osm_setup(ctypes.byref(prob), ctypes.byref(self._opt),
+                                  ctypes.c_void_p(stream), ctypes.byref(h)))
+        self.h = h
+
+    def _c(self, status):
+        _check(status, self.h)
+
+    def factor(self, W: torch.Tensor):
+        assert W.dtype == torch.float64 and W.is_contiguous() and W.numel() == self.nglob * self.ny
+        self._c(_lib.osm_factor(self.h, _ptr(W)))
+
+    def factor_rotating(self, n: int):
+        self._c(_lib.osm_factor_rotating(self.h, int(n)))
+
+    def step(self, u: torch.Tensor):
+        assert u.dtype == torch.complex128 and u.is_contiguous() and u.numel() == self.nglob * self.ny
+        st = osm_step_stats()
+        status = _lib.osm_step(self.h, _ptr(u), ctypes.byref(st))
+        if status != OSM_OK:
+            err = OsmError(status, (_lib.osm_last_error(self.h) or b"").decode())
+            err.stats = st.as_dict()
+            raise err
+        return st.as_dict()
+
+    def interface_apply(self, op: int, u, g_in):
+        g_out = torch.empty_like(g_in)
+        self._c(_lib.osm_interface_apply(self.h, op, _ptr(u), _ptr(g_in), _ptr(g_out)))
+        return g_out
+
+    def set_interface_guess(self, g0):
+        self._c(_lib.osm_set_interface_guess(self.h, _ptr(g0)))
+
+    def get_interface(self):
+        g = torch.empty((self.ntr, self.ny), dtype=torch.complex128, device=self.device)
+        self._c(_lib.osm_get_interface(self.h, _ptr(g)))
+        return g
+
+    def strip_solve(self, b):
+        x = torch.empty_like(b)
+        self._c(_lib.osm_strip_solve(self.h, _ptr(b), _ptr(x)))
+        return x
+
+    def get_strip_solution(self):
+        v = torch.empty((self.lt, self.ny), dtype=torch.complex128, device=self.device)
+        self._c(_lib.osm_get_strip_solution(self.h, _ptr(v)))
+        return v
+
+    def get_lh_blocks(self):
+        b = torch.empty((self.pb.nsub, 4, self.ny, self.ny), dtype=torch.complex128,
+                        device=self.device)
+        self._c(_lib.osm_get_lh_blocks(self.h, _ptr(b)))
+        return b
+
+    def get_factor(self):
+        dt = torch.complex64 if self._opt.prec == OSM_C32_REFINE else torch.complex128
+        f = torch.empty((self.lt, self.ny, self.ny), dtype=dt, device=self.device)
+        self._c(_lib.osm_get_factor(self.h, _ptr(f)))
+        return f
+
+    def kernel_timing(self, enable: bool):
+        """Returns (summed solve-kernel ms, launches) since the last reset."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._c(_lib.osm_kernel_timing(self.h, int(enable), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if self.h:
+            _lib.osm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,73 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point that
+include/osm.h declares, sizes its footprint on the host and rejects bad
+arguments before touching the GPU."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    txt = open(os.path.join(ROOT, "include", "osm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:osm_status|void|const char \*)\s*(osm_\w+)\s*\(",
+                                 txt, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ["osm_query", "osm_setup", "osm_factor", "osm_step", "osm_interface_apply",
+              "osm_set_interface_guess", "osm_get_interface", "osm_destroy", "osm_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1603_05110_amd import osm
+    lib = osm.load_library()
+    for n in declared():
+        assert hasattr(lib, n), n
+    assert sorted(osm.EXPORTS) == declared()
+
+
+def _pb(**kw):
+    from workloads import Problem, equal_strips
+    base = dict(xl=-1.0, xr=1.0, yb=-1.0, yu=1.0, ncx=16, ncy=8, nsub=2,
+                strip_cells=equal_strips(16, 2), lap_coef=1.0, beta=1.0, p=1.0, p_bc=1.0,
+                dt=0.01)
+    base.update(kw)
+    return Problem(**base)
+
+
+def test_query_footprint_scales_with_the_factor():
+    from paper_1603_05110_amd import osm
+    d1, _ = osm.osm_query(_pb(ncy=64))
+    d2, _ = osm.osm_query(_pb(ncy=128))
+    # dominated by (ncx + nsub) dense ny x ny complex blocks
+    assert d1 >= 18 * 65 * 65 * 16
+    assert 3.0 < d2 / d1 < 4.5
+    dc, _ = osm.osm_query(_pb(ncy=128), prec="c32")
+    assert dc < d2
+
+
+@pytest.mark.parametrize("kw", [dict(strip_cells=[10, 5]), dict(strip_cells=[15, 1]),
+                                dict(p=0.0), dict(nsub=1, strip_cells=[16]), dict(dt=-1.0)])
+def test_invalid_problems_are_rejected_on_the_host(kw):
+    from paper_1603_05110_amd import osm
+    with pytest.raises(osm.OsmError) as e:
+        osm.osm_query(_pb(**kw))
+    assert e.value.status == osm.OSM_EINVAL
+
+
+def test_setup_reports_enomem_before_allocating():
+    """The paper's preconditioner ran out of memory at N = 128; here the
+    footprint check runs first and returns ENOMEM (host-forced with a cap)."""
+    import ctypes
+    from paper_1603_05110_amd import osm
+    prob, keep = osm.make_problem(_pb(ncy=64))
+    opt = osm.make_options(mem_cap=1024)
+    h = ctypes.c_void_p()
+    st = osm._lib.osm_setup(ctypes.byref(prob), ctypes.byref(opt), None, ctypes.byref(h))
+    assert st == osm.OSM_ENOMEM
+    assert not h.value
+    assert b"exceeds" in osm._lib.osm_last_error(None)
