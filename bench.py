@@ -78,9 +78,10 @@ def run_gpu(pb, u0, V, prec, steps, warmup, dev, measure=True):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kern = s.kernel_timing(False) if measure else (0.0, 0)
+    team = s.solve_team()
     s.close()
     return dict(seconds=t1 - t0, factor_s=t_fac, setup_s=t_setup, stats=stats, u=u,
-                solve_ms=kern[0], solve_launches=kern[1])
+                solve_ms=kern[0], solve_launches=kern[1], team=team)
 
 
 def main():
@@ -185,7 +186,8 @@ def main():
         "roofline": {"kernel": "strip_solve", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
-                     "launches": main_run["solve_launches"]},
+                     "launches": main_run["solve_launches"],
+                     "workgroups_per_strip": main_run["team"]},
         "setup_s": main_run["setup_s"],
         "factor_s": main_run["factor_s"],
         "fp64_gpu": fp64,

@@ -194,6 +194,11 @@ osm_status osm_get_factor(osm_handle *h, void *dst_dev);
 osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
                              int64_t *solve_launches);
 
+/* Workgroups per strip used by the strip solve: opt->team when given, else
+ * the value the autotuner picked at the first factorisation (it times a few
+ * solves for every feasible team size).  0 for a NULL handle. */
+int32_t osm_solve_team(const osm_handle *h);
+
 void osm_destroy(osm_handle *h);
 const char *osm_last_error(const osm_handle *h);
 

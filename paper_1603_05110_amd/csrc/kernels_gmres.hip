@@ -16,9 +16,19 @@ __device__ __forceinline__ double wsum(double v) {
 // l_{i+1}) by strip i through X^{i,3} l_i + X^{i,4} r_i.  LH holds, per
 // block set, the four dense blocks X^{.,1..4} (row-major ny x ny).
 // mode_p = 1: y = x - L_h x (the preconditioner P), else y = L_h x.
+__device__ __forceinline__ void lh_matvec_body(Phys P, const StripMeta *strips,
+                                               const double2 *LH, const double2 *x, double2 *y,
+                                               int mode_p);
+
 __global__ __launch_bounds__(256) void lh_matvec_kernel(Phys P, const StripMeta *strips,
                                                         const double2 *LH, const double2 *x,
                                                         double2 *y, int mode_p) {
+    lh_matvec_body(P, strips, LH, x, y, mode_p);
+}
+
+__device__ __forceinline__ void lh_matvec_body(Phys P, const StripMeta *strips,
+                                               const double2 *LH, const double2 *x, double2 *y,
+                                               int mode_p) {
     int t = blockIdx.y;
     int n = P.ny;
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -144,7 +154,201 @@ __global__ void axpby_kernel(long n, double2 a, const double2 *x, double2 b, con
     if (e < n) z[e] = cadd(cmul(a, x[e]), cmul(b, y[e]));
 }
 
+// ---------------------------------------------------------------------------
+// GMRES with the Arnoldi loop driven on the device: every kernel below reads
+// ctl->done first and returns at once when the cycle has converged, so the
+// host can enqueue several iterations ahead and synchronise once per chunk.
+
+// block k: dots[k] = V_k^H w
+__global__ __launch_bounds__(256) void cgs_dots_kernel(long n, const double2 *V, const double2 *w,
+                                                       double2 *dots, const GmresCtl *ctl) {
+    if (ctl->done) return;
+    __shared__ double rr[4], ri[4];
+    int k = blockIdx.x;
+    const double2 *vk = V + (long)k * n;
+    double sr = 0.0, si = 0.0;
+    for (long e = threadIdx.x; e < n; e += blockDim.x) {
+        double2 a = vk[e], b = w[e];
+        sr += a.x * b.x + a.y * b.y;
+        si += a.x * b.y - a.y * b.x;
+    }
+    sr = wsum(sr);
+    si = wsum(si);
+    int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { rr[wave] = sr; ri[wave] = si; }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        dots[k] = cd(rr[0] + rr[1] + rr[2] + rr[3], ri[0] + ri[1] + ri[2] + ri[3]);
+}
+
+// w -= sum_{k<nv} dots[k] V_k; with norm_part, per-block partial |w|^2
+__global__ __launch_bounds__(256) void cgs_update_kernel(long n, const double2 *V, int nv,
+                                                         const double2 *dots, double2 *w,
+                                                         double *norm_part, const GmresCtl *ctl) {
+    if (ctl->done) return;
+    __shared__ double red[4];
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (e < n) {
+        double2 acc = cd(0.0, 0.0);
+        for (int k = 0; k < nv; ++k) acc = cadd(acc, cmul(dots[k], V[(long)k * n + e]));
+        double2 o = csub(w[e], acc);
+        w[e] = o;
+        s = o.x * o.x + o.y * o.y;
+    }
+    if (norm_part) {
+        s = wsum(s);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) norm_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+__device__ __forceinline__ double wave_reduce_parts(const double *part, int np) {
+    int lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int b = lane; b < np; b += 64) s += part[b];
+    return wsum(s);
+}
+
+// Start of a cycle: beta = ||r|| from np partials, e = beta e_1, done when
+// beta is already below tol * ||y|| (first cycle: ||y|| = beta).  One wave.
+__global__ void gmres_begin_kernel(const double *part, int np, int first, double accept,
+                                   double2 *e, int m, GmresCtl *ctl) {
+    double beta = sqrt(wave_reduce_parts(part, np));
+    if (threadIdx.x != 0) return;
+    if (first) ctl->bnorm = beta;
+    ctl->beta = beta;
+    ctl->j = 0;
+    ctl->done = 0;
+    ctl->conv = 0;
+    ctl->resid = beta;
+    if (!isfinite(beta)) { ctl->bad = 1; ctl->done = 1; return; }
+    if (beta <= accept * ctl->tol * ctl->bnorm || beta == 0.0) { ctl->done = 1; ctl->conv = 1; }
+    ctl->inv_hn = beta > 0 ? 1.0 / beta : 0.0;
+    for (int i = 0; i <= m; ++i) e[i] = cd(0.0, 0.0);
+    e[0] = cd(beta, 0.0);
+}
+
+// y = s x with s = ctl->inv_hn (normalisation of the new Arnoldi vector)
+__global__ void scale_ctl_kernel(long n, const double2 *x, double2 *y, const GmresCtl *ctl) {
+    if (ctl->done && ctl->j > 0) return;
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) y[e] = cscale(ctl->inv_hn, x[e]);
+}
+
+// Column j of the Hessenberg matrix from the two Gram-Schmidt passes and
+// ||w||, the previous rotations applied, and a new complex Givens rotation
+// [[conj(c), conj(s)], [-s, c]] (c = a/rho, s = b/rho) that zeroes h_{j+1,j};
+// the rotated right-hand side e gives the residual norm |e_{j+1}|.  One wave.
+__global__ void gmres_givens_kernel(int j, int m, const double2 *dots1, const double2 *dots2,
+                                    const double *part, int np, double2 *H, double2 *cs,
+                                    double2 *sn, double2 *e, GmresCtl *ctl) {
+    if (ctl->done) return;
+    double hn = sqrt(wave_reduce_parts(part, np));
+    if (threadIdx.x != 0) return;
+    double2 *col = H + (long)j * (m + 1);    // column-major, column j
+    for (int i = 0; i <= j; ++i) col[i] = cadd(dots1[i], dots2[i]);
+    col[j + 1] = cd(hn, 0.0);
+    for (int i = 0; i < j; ++i) {
+        double2 a = col[i], b = col[i + 1];
+        double2 c = cs[i], s = sn[i];
+        double2 t = cadd(cmul(cd(c.x, -c.y), a), cmul(cd(s.x, -s.y), b));
+        col[i + 1] = csub(cmul(c, b), cmul(s, a));
+        col[i] = t;
+    }
+    double2 a = col[j];
+    double den = sqrt(a.x * a.x + a.y * a.y + hn * hn);
+    double2 c = den > 0 ? cd(a.x / den, a.y / den) : cd(1.0, 0.0);
+    double2 s = den > 0 ? cd(hn / den, 0.0) : cd(0.0, 0.0);
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = cd(den, 0.0);
+    col[j + 1] = cd(0.0, 0.0);
+    double2 ej = e[j];
+    e[j + 1] = cd(-(s.x * ej.x - s.y * ej.y), -(s.x * ej.y + s.y * ej.x));
+    e[j] = cmul(cd(c.x, -c.y), ej);
+    double res = sqrt(e[j + 1].x * e[j + 1].x + e[j + 1].y * e[j + 1].y);
+    ctl->j = j + 1;
+    ctl->resid = res;
+    ctl->inv_hn = hn > 0 ? 1.0 / hn : 0.0;
+    if (!isfinite(hn) || !isfinite(res)) { ctl->bad = 1; ctl->done = 1; return; }
+    if (res <= ctl->tol * ctl->bnorm || hn == 0.0) { ctl->done = 1; ctl->conv = 1; }
+}
+
+// y = R^{-1} e over the ctl->j columns of the rotated Hessenberg matrix,
+// then x += sum_k y_k V_k is done by multiaxpy_ctl.  One thread.
+__global__ void gmres_backsolve_kernel(int m, const double2 *H, const double2 *e, double2 *y,
+                                       const GmresCtl *ctl) {
+    if (threadIdx.x != 0) return;
+    int jd = ctl->j;
+    for (int i = jd - 1; i >= 0; --i) {
+        double2 t = e[i];
+        for (int k = i + 1; k < jd; ++k) t = csub(t, cmul(H[(long)k * (m + 1) + i], y[k]));
+        double2 d = H[(long)i * (m + 1) + i];
+        y[i] = cmul(t, cinv(d));
+    }
+}
+
+__global__ void multiaxpy_ctl_kernel(long n, const double2 *V, const double2 *h, double2 *w,
+                                     const GmresCtl *ctl) {
+    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    int nv = ctl->j;
+    double2 acc = cd(0.0, 0.0);
+    for (int k = 0; k < nv; ++k) acc = cadd(acc, cmul(h[k], V[(long)k * n + e]));
+    w[e] = cadd(w[e], acc);
+}
+
+// lh_matvec_kernel with an early exit for a finished cycle
+__global__ __launch_bounds__(256) void lh_matvec_ctl_kernel(Phys P, const StripMeta *strips,
+                                                            const double2 *LH, const double2 *x,
+                                                            double2 *y, const GmresCtl *ctl) {
+    if (ctl->done) return;
+    lh_matvec_body(P, strips, LH, x, y, 1);
+}
+
 }  // namespace
+
+hipError_t launch_gmres_iteration(hipStream_t st, const Phys &P, const StripMeta *strips,
+                                  const double2 *LH, long n, int j, int m, double2 *V,
+                                  double2 *dots1, double2 *dots2, double *norm_part,
+                                  double2 *H, double2 *cs, double2 *sn, double2 *e,
+                                  GmresCtl *ctl) {
+    double2 *vj = V + (long)j * n, *w = V + (long)(j + 1) * n;
+    unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(lh_matvec_ctl_kernel, dim3((P.ny + 3) / 4, 2 * (P.nsub - 1)), dim3(256),
+                       0, st, P, strips, LH, vj, w, ctl);
+    hipLaunchKernelGGL(cgs_dots_kernel, dim3(j + 1), dim3(256), 0, st, n, V, w, dots1, ctl);
+    hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(256), 0, st, n, V, j + 1, dots1, w,
+                       (double *)nullptr, ctl);
+    hipLaunchKernelGGL(cgs_dots_kernel, dim3(j + 1), dim3(256), 0, st, n, V, w, dots2, ctl);
+    hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(256), 0, st, n, V, j + 1, dots2, w,
+                       norm_part, ctl);
+    hipLaunchKernelGGL(gmres_givens_kernel, dim3(1), dim3(64), 0, st, j, m, dots1, dots2,
+                       norm_part, (int)nb, H, cs, sn, e, ctl);
+    hipLaunchKernelGGL(scale_ctl_kernel, dim3(nb), dim3(256), 0, st, n, w, w, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_gmres_begin(hipStream_t st, long n, const double2 *r, double *norm_part,
+                              int first, double accept, double2 *V0, double2 *e, int m,
+                              GmresCtl *ctl) {
+    unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(norm_partials_kernel, dim3(nb), dim3(256), 0, st, n, r, norm_part);
+    hipLaunchKernelGGL(gmres_begin_kernel, dim3(1), dim3(64), 0, st, norm_part, (int)nb, first,
+                       accept, e, m, ctl);
+    hipLaunchKernelGGL(scale_ctl_kernel, dim3(nb), dim3(256), 0, st, n, r, V0, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_gmres_finish(hipStream_t st, long n, int m, const double2 *H, const double2 *e,
+                               double2 *y, const double2 *V, double2 *x, const GmresCtl *ctl) {
+    hipLaunchKernelGGL(gmres_backsolve_kernel, dim3(1), dim3(64), 0, st, m, H, e, y, ctl);
+    hipLaunchKernelGGL(multiaxpy_ctl_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       n, V, y, x, ctl);
+    return hipGetLastError();
+}
 
 hipError_t launch_lh_matvec(hipStream_t st, const Phys &P, const StripMeta *strips,
                             const double2 *LH, const double2 *x, double2 *y, int mode_p) {

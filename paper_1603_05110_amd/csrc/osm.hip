@@ -57,6 +57,10 @@ struct osm_handle {
     // GMRES
     int m = 0, nblk = 0;
     double2 *Vb = nullptr, *dots_part = nullptr, *dots = nullptr;
+    GmresCtl *gctl = nullptr;
+    double2 *gH = nullptr, *gcs = nullptr, *gsn = nullptr, *ge = nullptr, *gy = nullptr;
+    double2 *gdots1 = nullptr, *gdots2 = nullptr;
+    double *gnorm_part = nullptr;
     double *norm_part = nullptr;
     // kernel timing (HIP events around every solve launch when enabled)
     bool prof = false, prof_pending = false;
@@ -65,6 +69,8 @@ struct osm_handle {
     long long solve_launches = 0;
     // state
     bool factored = false, has_guess = false;
+    int team_cap = 0;            // largest co-resident team
+    bool team_tuned = false;
     std::string err;
     std::vector<void *> allocs;
 };
@@ -319,107 +325,62 @@ double dev_norm(osm_handle *h, const double2 *x, long n, osm_status *st) {
 }
 
 // ---------------------------------------------------------------- GMRES
-// x = (I - L_h)^{-1} y by restarted GMRES, x0 = 0, classical Gram-Schmidt
-// applied twice (FP64), Givens rotations on the host.
+// x = (I - L_h)^{-1} y by restarted GMRES (Section 4.2), x0 = 0, classical
+// Gram-Schmidt applied twice, FP64.  The Arnoldi loop, the Givens rotations
+// and the convergence test run on the device; the host enqueues chunks of
+// iterations and synchronises once per chunk.
 osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
     const osm_options &o = h->opt;
     long n = h->ng;
     int m = h->m;
-    osm_status s;
     *iters = 0;
     HIPCHK(h, hipMemsetAsync(x, 0, sizeof(double2) * n, h->st));
-    double bnorm = dev_norm(h, y, n, &s);
-    if (s != OSM_OK) return s;
-    if (bnorm == 0.0) return OSM_OK;
+    GmresCtl c;
+    memset(&c, 0, sizeof(c));
+    c.tol = o.tol_gmres;
+    HIPCHK(h, hipMemcpyAsync(h->gctl, &c, sizeof(c), hipMemcpyHostToDevice, h->st));
     double2 *V = h->Vb;
-    double2 *w = h->Vb + (long)(m + 1) * n;   // scratch vector
-    std::vector<zc> H((m + 1) * m), cs(m), sn(m), e(m + 1);
-    std::vector<double2> hb(2 * (m + 1));
+    double2 *w = h->Vb + (long)(m + 1) * n;   // residual of a restart
+    const int CH = 6;
     int total = 0;
-    bool first = true;
-    bool inner_conv = false;
-    while (total < o.max_gmres) {
-        // r = y - P x
-        if (first) {
-            HIPCHK(h, hipMemcpyAsync(w, y, sizeof(double2) * n, hipMemcpyDeviceToDevice, h->st));
-        } else {
+    bool first = true, prev_conv = false;
+    while (true) {
+        const double2 *r = y;
+        if (!first) {
             HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->LH, x, w, 1));
             HIPCHK(h, launch_axpby(h->st, n, cd(1, 0), y, cd(-1, 0), w, w));
+            r = w;
         }
-        double beta = dev_norm(h, w, n, &s);
-        if (s != OSM_OK) return s;
-        if (!isfinite(beta)) return fail(h, OSM_ENONFINITE, "GMRES residual not finite");
-        // the true residual decides; after a cycle whose rotated residual
-        // met the tolerance, allow a rounding margin of 10x
-        if (beta <= o.tol_gmres * bnorm || (inner_conv && beta <= 10.0 * o.tol_gmres * bnorm))
-            break;
-        HIPCHK(h, launch_scale_copy(h->st, n, w, cd(1.0 / beta, 0), V));
-        std::fill(H.begin(), H.end(), zc(0));
-        std::fill(e.begin(), e.end(), zc(0));
-        e[0] = beta;
-        int jdone = 0;
-        bool conv = false;
-        for (int j = 0; j < m && total < o.max_gmres; ++j) {
-            double2 *vj1 = V + (long)(j + 1) * n;
-            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->LH, V + (long)j * n, vj1, 1));
-            // CGS, twice
-            for (int pass = 0; pass < 2; ++pass) {
-                HIPCHK(h, launch_multidot(h->st, n, V, j + 1, vj1, h->dots_part, h->nblk));
-                HIPCHK(h, launch_multidot_finalize(h->st, h->dots_part, j + 1, h->nblk,
-                                                   h->dots + pass * (m + 1)));
-                HIPCHK(h, launch_multiaxpy(h->st, n, V, j + 1, h->dots + pass * (m + 1), vj1, 1));
-            }
-            HIPCHK(h, launch_norm_partials(h->st, n, vj1, h->norm_part, h->nblk));
-            HIPCHK(h, launch_sum(h->st, h->norm_part, h->nblk, 1, h->scal));
-            HIPCHK(h, hipMemcpyAsync(hb.data(), h->dots, sizeof(double2) * 2 * (m + 1),
-                                     hipMemcpyDeviceToHost, h->st));
-            double hn2 = 0;
-            HIPCHK(h, hipMemcpyAsync(&hn2, h->scal, sizeof(double), hipMemcpyDeviceToHost, h->st));
+        // after a cycle whose rotated residual met the tolerance, the true
+        // residual is accepted within a rounding margin of 10x
+        HIPCHK(h, launch_gmres_begin(h->st, n, r, h->gnorm_part, first ? 1 : 0,
+                                     prev_conv ? 10.0 : 1.0, V, h->ge, m, h->gctl));
+        int j = 0;
+        while (j < m && total + j < o.max_gmres) {
+            int ch = std::min(CH, std::min(m - j, o.max_gmres - total - j));
+            for (int jj = j; jj < j + ch; ++jj)
+                HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->LH, n, jj, m, V,
+                                                 h->gdots1, h->gdots2, h->gnorm_part, h->gH,
+                                                 h->gcs, h->gsn, h->ge, h->gctl));
+            j += ch;
+            HIPCHK(h, hipMemcpyAsync(&c, h->gctl, sizeof(c), hipMemcpyDeviceToHost, h->st));
             HIPCHK(h, hipStreamSynchronize(h->st));
-            double hn = sqrt(hn2);
-            for (int i = 0; i <= j; ++i)
-                H[i * m + j] = zc(hb[i].x + hb[m + 1 + i].x, hb[i].y + hb[m + 1 + i].y);
-            H[(j + 1) * m + j] = hn;
-            if (hn > 0) HIPCHK(h, launch_scale_copy(h->st, n, vj1, cd(1.0 / hn, 0), vj1));
-            // complex Givens rotation [[conj(c), conj(s)], [-s, c]],
-            // c = a/rho, s = b/rho, maps (a, b) to (rho, 0)
-            for (int i = 0; i < j; ++i) {
-                zc t = std::conj(cs[i]) * H[i * m + j] + std::conj(sn[i]) * H[(i + 1) * m + j];
-                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-                H[i * m + j] = t;
-            }
-            zc a = H[j * m + j], bb = H[(j + 1) * m + j];
-            double den = sqrt(std::norm(a) + std::norm(bb));
-            cs[j] = den > 0 ? a / den : zc(1);
-            sn[j] = den > 0 ? bb / den : zc(0);
-            H[j * m + j] = den;
-            H[(j + 1) * m + j] = 0;
-            e[j + 1] = -sn[j] * e[j];
-            e[j] = std::conj(cs[j]) * e[j];
-            ++total;
-            jdone = j + 1;
-            if (std::abs(e[j + 1]) <= o.tol_gmres * bnorm) { conv = true; break; }
-            if (hn == 0) { conv = true; break; }
+            if (c.bad) return fail(h, OSM_ENONFINITE, "GMRES met a non-finite value");
+            if (c.done) break;
         }
-        // back substitution and x += V y
-        std::vector<zc> yv(jdone);
-        for (int i = jdone - 1; i >= 0; --i) {
-            zc t = e[i];
-            for (int k = i + 1; k < jdone; ++k) t -= H[i * m + k] * yv[k];
-            yv[i] = t / H[i * m + i];
-        }
-        std::vector<double2> yd(jdone);
-        for (int i = 0; i < jdone; ++i) yd[i] = cd(yv[i].real(), yv[i].imag());
-        HIPCHK(h, hipMemcpyAsync(h->dots, yd.data(), sizeof(double2) * jdone, hipMemcpyHostToDevice,
-                                 h->st));
-        HIPCHK(h, launch_multiaxpy(h->st, n, V, jdone, h->dots, x, 0));
+        HIPCHK(h, launch_gmres_finish(h->st, n, m, h->gH, h->ge, h->gy, V, x, h->gctl));
+        total += c.j;
         first = false;
-        inner_conv = conv;
+        if (c.done && c.j == 0) break;            // residual already small enough
+        prev_conv = c.conv != 0;
+        if (total >= o.max_gmres) {
+            HIPCHK(h, hipStreamSynchronize(h->st));
+            *iters = total;
+            if (!c.conv) return fail(h, OSM_ENOCONV, "GMRES did not converge within max_gmres");
+            return OSM_OK;
+        }
     }
-    HIPCHK(h, hipStreamSynchronize(h->st));
     *iters = total;
-    if (total >= o.max_gmres && !inner_conv)
-        return fail(h, OSM_ENOCONV, "GMRES did not converge within max_gmres");
     return OSM_OK;
 }
 
@@ -643,6 +604,15 @@ osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_
             SALLOC(h->Vb, double2, (long)(h->m + 2) * h->ng);
             SALLOC(h->dots_part, double2, (long)h->nblk * (h->m + 1));
             SALLOC(h->dots, double2, 2 * (h->m + 1));
+            SALLOC(h->gctl, GmresCtl, 1);
+            SALLOC(h->gH, double2, (long)(h->m + 1) * h->m);
+            SALLOC(h->gcs, double2, h->m);
+            SALLOC(h->gsn, double2, h->m);
+            SALLOC(h->ge, double2, h->m + 1);
+            SALLOC(h->gy, double2, h->m);
+            SALLOC(h->gdots1, double2, h->m + 1);
+            SALLOC(h->gdots2, double2, h->m + 1);
+            SALLOC(h->gnorm_part, double, (h->ng + 255) / 256);
         }
         HIPCHK(h, hipMemcpy(h->strips_d, h->strips_h.data(), sizeof(StripMeta) * h->N, hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(h->line_strip_d, line_strip.data(), sizeof(int) * h->Lt, hipMemcpyHostToDevice));
@@ -654,12 +624,12 @@ osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_
         HIPCHK(h, hipMemset(h->g, 0, sizeof(double2) * h->ng));
         HIPCHK(h, hipMemset(h->gguess, 0, sizeof(double2) * h->ng));
         // workgroups per strip in the solve: fill the resident capacity
-        int cap = solve_max_resident_blocks(h->fp32);
+        int cap = solve_max_resident_blocks(h->fp32, h->n);
         if (cap <= 0) return fail(h, OSM_EHIP, "occupancy query failed");
-        int team = h->opt.team > 0 ? h->opt.team : std::max(1, std::min(64, cap / h->N));
-        team = std::min(team, std::max(1, cap / h->N));
-        team = std::min(team, h->n);
-        h->team = team;
+        h->team_cap = std::max(1, std::min(cap / h->N, h->n));
+        int team = h->opt.team > 0 ? h->opt.team : std::min(16, h->team_cap);
+        h->team = std::min(team, h->team_cap);
+        h->team_tuned = h->opt.team > 0;
         if (h->opt.algo == OSM_PRECOND) {
             osm_status s = build_lh(h);
             if (s != OSM_OK) return s;
@@ -676,12 +646,52 @@ osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_
     return OSM_OK;
 }
 
+// Autotuner of the strip solve: workgroups per strip trade barrier cost
+// against memory-level parallelism, so time a few solves with every feasible
+// team size once, after the first factorisation, and keep the fastest.
+static osm_status autotune_team(osm_handle *h) {
+    if (h->team_tuned) return OSM_OK;
+    static const int cand[] = {4, 6, 8, 12, 16, 24, 32, 48, 64};
+    bool prof = h->prof;
+    double keep_ms = h->solve_ms;
+    long long keep_n = h->solve_launches;
+    if (!h->ev0) {
+        HIPCHK(h, hipEventCreate(&h->ev0));
+        HIPCHK(h, hipEventCreate(&h->ev1));
+    }
+    HIPCHK(h, hipMemsetAsync(h->res, 0, sizeof(double2) * (size_t)h->Lt * h->n, h->st));
+    int best = h->team;
+    double best_ms = 1e300;
+    for (int t : cand) {
+        if (t > h->team_cap) break;
+        h->team = t;
+        h->prof = true;
+        h->solve_ms = 0.0;
+        h->solve_launches = 0;
+        for (int r = 0; r < 3; ++r) {
+            osm_status s = do_solve(h, h->res, h->delta);
+            if (s == OSM_OK) s = check_solve_error(h);
+            if (s != OSM_OK) { h->prof = prof; return s; }
+        }
+        double ms = h->solve_ms / 3.0;
+        if (ms < best_ms) { best_ms = ms; best = t; }
+    }
+    h->team = best;
+    h->prof = prof;
+    h->solve_ms = keep_ms;
+    h->solve_launches = keep_n;
+    h->team_tuned = true;
+    return OSM_OK;
+}
+
 osm_status osm_factor(osm_handle *h, const double *W_dev) {
     if (!h) return OSM_EINVAL;
     if (!W_dev) return fail(h, OSM_EINVAL, "W_dev is NULL");
     HIPCHK(h, hipMemcpyAsync(h->W_d, W_dev, sizeof(double) * (size_t)h->nglob * h->n,
                              hipMemcpyDeviceToDevice, h->st));
     osm_status s = do_factor(h);
+    if (s != OSM_OK) return s;
+    s = autotune_team(h);
     if (s != OSM_OK) return s;
     HIPCHK(h, hipStreamSynchronize(h->st));
     return OSM_OK;
@@ -694,6 +704,8 @@ osm_status osm_factor_rotating(osm_handle *h, int32_t n) {
     HIPCHK(h, launch_rotating_W(h->st, h->P, h->prob.xl, h->prob.yb, h->prob.omega, h->prob.vxx,
                                 h->prob.vyy, t1, t0, h->W_d));
     osm_status s = do_factor(h);
+    if (s != OSM_OK) return s;
+    s = autotune_team(h);
     if (s != OSM_OK) return s;
     HIPCHK(h, hipStreamSynchronize(h->st));
     return OSM_OK;
@@ -907,6 +919,8 @@ osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
     h->prof = enable != 0;
     return OSM_OK;
 }
+
+int32_t osm_solve_team(const osm_handle *h) { return h ? h->team : 0; }
 
 void osm_destroy(osm_handle *h) {
     if (!h) return;

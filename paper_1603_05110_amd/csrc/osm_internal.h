@@ -128,9 +128,31 @@ struct SolveArgs {
 // ev0/ev1 (may be null) are recorded right before and after the solve kernel
 hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipEvent_t ev0,
                               hipEvent_t ev1);
-int solve_max_resident_blocks(int fp32);
+int solve_max_resident_blocks(int fp32, int n);
 
 // kernels_gmres.hip
+// Device-side state of one GMRES cycle (Arnoldi loop driven on the GPU).
+struct GmresCtl {
+    int done;       // cycle finished: converged, breakdown or non-finite
+    int conv;       // residual estimate met tol * bnorm
+    int bad;        // non-finite value met
+    int j;          // Arnoldi steps completed in this cycle
+    double bnorm;   // ||y||
+    double tol;     // relative tolerance
+    double beta;    // ||r_0|| of the cycle
+    double inv_hn;  // 1 / h_{j+1,j} (normalisation of the next basis vector)
+    double resid;   // current residual estimate
+};
+hipError_t launch_gmres_begin(hipStream_t st, long n, const double2 *r, double *norm_part,
+                              int first, double accept, double2 *V0, double2 *e, int m,
+                              GmresCtl *ctl);
+hipError_t launch_gmres_iteration(hipStream_t st, const Phys &P, const StripMeta *strips,
+                                  const double2 *LH, long n, int j, int m, double2 *V,
+                                  double2 *dots1, double2 *dots2, double *norm_part,
+                                  double2 *H, double2 *cs, double2 *sn, double2 *e,
+                                  GmresCtl *ctl);
+hipError_t launch_gmres_finish(hipStream_t st, long n, int m, const double2 *H, const double2 *e,
+                               double2 *y, const double2 *V, double2 *x, const GmresCtl *ctl);
 hipError_t launch_lh_matvec(hipStream_t st, const Phys &P, const StripMeta *strips,
                             const double2 *LH, const double2 *x, double2 *y, int mode_p);
 hipError_t launch_multidot(hipStream_t st, long n, const double2 *V, int nv, const double2 *w,

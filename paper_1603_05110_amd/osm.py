@@ -68,7 +68,7 @@ class osm_footprint(ctypes.Structure):
 EXPORTS = ["osm_query", "osm_setup", "osm_factor", "osm_factor_rotating", "osm_step",
            "osm_interface_apply", "osm_set_interface_guess", "osm_get_interface",
            "osm_strip_solve", "osm_get_strip_solution", "osm_get_lh_blocks", "osm_get_factor",
-           "osm_kernel_timing", "osm_destroy", "osm_last_error"]
+           "osm_kernel_timing", "osm_solve_team", "osm_destroy", "osm_last_error"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "osm_get_strip_solution": ([H, P], st),
         "osm_get_lh_blocks": ([H, P], st),
         "osm_get_factor": ([H, P], st),
+        "osm_solve_team": ([H], ctypes.c_int32),
         "osm_kernel_timing": ([H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int64)], st),
         "osm_destroy": ([H], None),
@@ -230,6 +231,9 @@ class OsmSolver:
         f = torch.empty((self.lt, self.ny, self.ny), dtype=dt, device=self.device)
         self._c(_lib.osm_get_factor(self.h, _ptr(f)))
         return f
+
+    def solve_team(self):
+        return int(_lib.osm_solve_team(self.h))
 
     def kernel_timing(self, enable: bool):
         """Returns (summed solve-kernel ms, launches) since the last reset."""

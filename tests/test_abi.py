@@ -11,8 +11,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared():
     txt = open(os.path.join(ROOT, "include", "osm.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:osm_status|void|const char \*)\s*(osm_\w+)\s*\(",
-                                 txt, re.M)))
+    return sorted(set(re.findall(
+        r"^\s*(?:osm_status|void|const char \*|int32_t)\s*(osm_\w+)\s*\(", txt, re.M)))
 
 
 def test_header_declares_the_boundary():
