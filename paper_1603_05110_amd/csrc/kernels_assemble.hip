@@ -85,7 +85,8 @@ __global__ void coef_kernel(Phys P, const StripMeta *strips, const int *line_str
 // K_j(W)^{-1}(F - M_{beta|zeta|^2} zeta): the paper's fixed-point update.
 __global__ void residual_kernel(Phys P, const StripMeta *strips, const int *line_strip,
                                 const double *W, const double2 *u_old, const double2 *zeta,
-                                const double2 *g, double2 *res) {
+                                const double2 *g, double2 *res, const StepCtl *c) {
+    if (c && (c->q_conv || c->k_done || c->bad)) return;
     int L = blockIdx.y;
     int a = blockIdx.x * blockDim.x + threadIdx.x;
     int ny = P.ny;
@@ -146,7 +147,9 @@ __global__ void copy_u_kernel(Phys P, const StripMeta *strips, const int *line_s
 
 // zeta += delta on one packed line; per-line partial sums |delta|^2, |zeta|^2
 // and a non-finite counter.
-__global__ void update_norms_kernel(Phys P, double2 *zeta, const double2 *delta, double *part) {
+__global__ void update_norms_kernel(Phys P, double2 *zeta, const double2 *delta, double *part,
+                                    const StepCtl *c) {
+    if (c && (c->q_conv || c->k_done || c->bad)) return;
     int L = blockIdx.x;
     int ny = P.ny;
     double s_d = 0.0, s_z = 0.0, bad = 0.0;
@@ -200,7 +203,8 @@ __global__ void strip_sums_kernel(Phys P, const StripMeta *strips, const double 
 //   new l_{i+1} = -r_i     - 2ip v_i(last line)
 // Per-trace partial sums of |gn - g|^2 and |gn|^2.
 __global__ void flux_kernel(Phys P, const StripMeta *strips, const double2 *g,
-                            const double2 *v, double2 *gn, double *part) {
+                            const double2 *v, double2 *gn, double *part, const StepCtl *c) {
+    if (c && (!c->q_conv || c->r_done || c->k_done || c->bad)) return;
     int t = blockIdx.x;           // trace 0 .. 2(N-1)-1
     int ny = P.ny;
     int i = t >> 1;
@@ -352,9 +356,10 @@ hipError_t launch_coef(hipStream_t st, const Phys &P, const StripMeta *strips,
 
 hipError_t launch_residual(hipStream_t st, const Phys &P, const StripMeta *strips,
                            const int *line_strip, const double *W, const double2 *u_old,
-                           const double2 *zeta, const double2 *g, double2 *res) {
+                           const double2 *zeta, const double2 *g, double2 *res,
+                           const StepCtl *c) {
     hipLaunchKernelGGL(residual_kernel, node_grid(P.ny, P.lt), dim3(256), 0, st, P, strips,
-                       line_strip, W, u_old, zeta, g, res);
+                       line_strip, W, u_old, zeta, g, res, c);
     return hipGetLastError();
 }
 
@@ -366,9 +371,9 @@ hipError_t launch_copy_u_to_strips(hipStream_t st, const Phys &P, const StripMet
 }
 
 hipError_t launch_update_norms(hipStream_t st, const Phys &P, double2 *zeta,
-                               const double2 *delta, double *line_part) {
+                               const double2 *delta, double *line_part, const StepCtl *c) {
     hipLaunchKernelGGL(update_norms_kernel, dim3(P.lt), dim3(256), 0, st, P, zeta, delta,
-                       line_part);
+                       line_part, c);
     return hipGetLastError();
 }
 
@@ -380,9 +385,10 @@ hipError_t launch_strip_sums(hipStream_t st, const Phys &P, const StripMeta *str
 }
 
 hipError_t launch_flux(hipStream_t st, const Phys &P, const StripMeta *strips,
-                       const double2 *g, const double2 *v, double2 *gn, double *part) {
+                       const double2 *g, const double2 *v, double2 *gn, double *part,
+                       const StepCtl *c) {
     hipLaunchKernelGGL(flux_kernel, dim3(2 * (P.nsub - 1)), dim3(256), 0, st, P, strips, g, v,
-                       gn, part);
+                       gn, part, c);
     return hipGetLastError();
 }
 

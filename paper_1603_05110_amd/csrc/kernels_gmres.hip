@@ -214,9 +214,12 @@ __device__ __forceinline__ double wave_reduce_parts(const double *part, int np) 
 // Start of a cycle: beta = ||r|| from np partials, e = beta e_1, done when
 // beta is already below tol * ||y|| (first cycle: ||y|| = beta).  One wave.
 __global__ void gmres_begin_kernel(const double *part, int np, int first, double accept,
-                                   double2 *e, int m, GmresCtl *ctl) {
+                                   double2 *e, int m, GmresCtl *ctl, const StepCtl *sc) {
+    if (sc && (sc->r_done != 1 || sc->k_done || sc->bad)) return;
     double beta = sqrt(wave_reduce_parts(part, np));
     if (threadIdx.x != 0) return;
+    ctl->finished = 0;
+    if (first) ctl->total = 0;
     if (first) ctl->bnorm = beta;
     ctl->beta = beta;
     ctl->j = 0;
@@ -276,11 +279,19 @@ __global__ void gmres_givens_kernel(int j, int m, const double2 *dots1, const do
     if (res <= ctl->tol * ctl->bnorm || hn == 0.0) { ctl->done = 1; ctl->conv = 1; }
 }
 
-// y = R^{-1} e over the ctl->j columns of the rotated Hessenberg matrix,
-// then x += sum_k y_k V_k is done by multiaxpy_ctl.  One thread.
+// End of a cycle: y = R^{-1} e over the ctl->j columns of the rotated
+// Hessenberg matrix, then x += sum_k y_k V_k (multiaxpy_ctl) and the cycle is
+// marked finished (gmres_mark).  require_done: only when the cycle has
+// stopped (the speculative end enqueued right after the first chunk).
+// One thread; ctl->skip tells the two following kernels to do nothing.
 __global__ void gmres_backsolve_kernel(int m, const double2 *H, const double2 *e, double2 *y,
-                                       const GmresCtl *ctl) {
+                                       GmresCtl *ctl, int require_done) {
     if (threadIdx.x != 0) return;
+    if (ctl->finished || (require_done && !ctl->done)) {
+        ctl->skip = 1;
+        return;
+    }
+    ctl->skip = 0;
     int jd = ctl->j;
     for (int i = jd - 1; i >= 0; --i) {
         double2 t = e[i];
@@ -292,12 +303,19 @@ __global__ void gmres_backsolve_kernel(int m, const double2 *H, const double2 *e
 
 __global__ void multiaxpy_ctl_kernel(long n, const double2 *V, const double2 *h, double2 *w,
                                      const GmresCtl *ctl) {
+    if (ctl->skip) return;
     long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     int nv = ctl->j;
     double2 acc = cd(0.0, 0.0);
     for (int k = 0; k < nv; ++k) acc = cadd(acc, cmul(h[k], V[(long)k * n + e]));
     w[e] = cadd(w[e], acc);
+}
+
+__global__ void gmres_mark_kernel(GmresCtl *ctl) {
+    if (threadIdx.x != 0 || ctl->skip) return;
+    ctl->finished = 1;
+    ctl->total += ctl->j;
 }
 
 // lh_matvec_kernel with an early exit for a finished cycle
@@ -333,20 +351,23 @@ hipError_t launch_gmres_iteration(hipStream_t st, const Phys &P, const StripMeta
 
 hipError_t launch_gmres_begin(hipStream_t st, long n, const double2 *r, double *norm_part,
                               int first, double accept, double2 *V0, double2 *e, int m,
-                              GmresCtl *ctl) {
+                              GmresCtl *ctl, const StepCtl *sctl) {
     unsigned nb = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(norm_partials_kernel, dim3(nb), dim3(256), 0, st, n, r, norm_part);
     hipLaunchKernelGGL(gmres_begin_kernel, dim3(1), dim3(64), 0, st, norm_part, (int)nb, first,
-                       accept, e, m, ctl);
+                       accept, e, m, ctl, sctl);
     hipLaunchKernelGGL(scale_ctl_kernel, dim3(nb), dim3(256), 0, st, n, r, V0, ctl);
     return hipGetLastError();
 }
 
 hipError_t launch_gmres_finish(hipStream_t st, long n, int m, const double2 *H, const double2 *e,
-                               double2 *y, const double2 *V, double2 *x, const GmresCtl *ctl) {
-    hipLaunchKernelGGL(gmres_backsolve_kernel, dim3(1), dim3(64), 0, st, m, H, e, y, ctl);
+                               double2 *y, const double2 *V, double2 *x, GmresCtl *ctl,
+                               int require_done) {
+    hipLaunchKernelGGL(gmres_backsolve_kernel, dim3(1), dim3(64), 0, st, m, H, e, y, ctl,
+                       require_done);
     hipLaunchKernelGGL(multiaxpy_ctl_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                        n, V, y, x, ctl);
+    hipLaunchKernelGGL(gmres_mark_kernel, dim3(1), dim3(64), 0, st, ctl);
     return hipGetLastError();
 }
 

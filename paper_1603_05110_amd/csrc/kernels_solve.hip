@@ -129,10 +129,17 @@ template <typename T> struct tile_shape;
 template <> struct tile_shape<float> { static constexpr int RU = 2, UN = 8; };
 template <> struct tile_shape<double> { static constexpr int RU = 2, UN = 4; };
 
+__device__ __forceinline__ bool solve_skipped(const SolveArgs &a) {
+    bool skip = a.ctl && (a.ctl->q_conv || a.ctl->k_done || a.ctl->bad);
+    if (!skip && a.ran && blockIdx.x == 0 && threadIdx.x == 0) *a.ran = 1;
+    return skip;
+}
+
 template <typename T>
 __global__ __launch_bounds__(SOLVE_THREADS) void strip_solve_kernel(SolveArgs a) {
     typedef typename cplx_of<T>::type T2;
     constexpr int RU = tile_shape<T>::RU, UN = tile_shape<T>::UN;
+    if (solve_skipped(a)) return;
     extern __shared__ unsigned char smem_raw[];
     T2 *vec = reinterpret_cast<T2 *>(smem_raw);
     int nst = a.nstrips, team = a.team;
@@ -195,6 +202,7 @@ template <typename T, int NW, int NCH, int PR>
 __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
     typedef typename cplx_of<T>::type T2;
     typedef typename acc_t<T>::type A;
+    if (solve_skipped(a)) return;
     extern __shared__ unsigned char smem_raw[];
     T2 *vec = reinterpret_cast<T2 *>(smem_raw);
     constexpr int NTHR = NW * 64;
@@ -345,10 +353,13 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
     }
 }
 
-__global__ void zero_u32_kernel(unsigned *p, int n, int *err) {
+__global__ void zero_u32_kernel(unsigned *p, int n, int *err, int *ran) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
-    if (i == 0) *err = 0;
+    if (i == 0) {
+        *err = 0;
+        if (ran) *ran = 0;
+    }
 }
 
 // Kernel variant for a column count n and a precision: the prefetching
@@ -390,7 +401,7 @@ int solve_max_resident_blocks(int fp32, int n) {
 hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipEvent_t ev0,
                               hipEvent_t ev1) {
     hipLaunchKernelGGL(zero_u32_kernel, dim3((a.nstrips + 255) / 256), dim3(256), 0, st,
-                       a.counters, a.nstrips, a.error);
+                       a.counters, a.nstrips, a.error, a.ran);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     SolveArgs args = a;

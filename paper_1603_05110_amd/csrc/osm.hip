@@ -16,6 +16,8 @@
 #include "osm_internal.h"
 
 #define GJ_BK 32
+#define PROF_SLOTS 512
+#define GMRES_CHUNK 16
 
 typedef std::complex<double> zc;
 
@@ -63,10 +65,16 @@ struct osm_handle {
     double *gnorm_part = nullptr;
     double *norm_part = nullptr;
     // kernel timing (HIP events around every solve launch when enabled)
-    bool prof = false, prof_pending = false;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool prof = false;
+    std::vector<hipEvent_t> evs;     // event pairs, one per slot
+    int *ran_d = nullptr;            // per slot: the solve kernel did work
+    int prof_used = 0;
     double solve_ms = 0.0;
     long long solve_launches = 0;
+    // device-side control of a step
+    StepCtl *sctl = nullptr;
+    double *upd_part = nullptr;
+    int q_chunk = 3;
     // state
     bool factored = false, has_guess = false;
     int team_cap = 0;            // largest co-resident team
@@ -236,8 +244,28 @@ osm_status do_factor(osm_handle *h) {
     return OSM_OK;
 }
 
-// x = K^{-1} b on every strip (packed layout)
-osm_status do_solve(osm_handle *h, const double2 *b, double2 *x) {
+// Timing of solve launches: every launch while timing is on takes a slot
+// with its own event pair and a device flag telling whether the kernel did
+// the solve or returned at once (a fixed point already converged); the
+// slots are collected after the next synchronisation.
+osm_status prof_collect(osm_handle *h) {
+    if (h->prof_used == 0) return OSM_OK;
+    std::vector<int> ran(h->prof_used);
+    HIPCHK(h, hipMemcpy(ran.data(), h->ran_d, sizeof(int) * h->prof_used, hipMemcpyDeviceToHost));
+    for (int i = 0; i < h->prof_used; ++i) {
+        if (!ran[i]) continue;
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, h->evs[2 * i], h->evs[2 * i + 1]));
+        h->solve_ms += ms;
+        h->solve_launches += 1;
+    }
+    h->prof_used = 0;
+    return OSM_OK;
+}
+
+// x = K^{-1} b on every strip (packed layout); skipped on the device when
+// ctl says the fixed point is done.
+osm_status do_solve(osm_handle *h, const double2 *b, double2 *x, const StepCtl *ctl = nullptr) {
     SolveArgs a;
     a.n = h->n;
     a.team = h->team;
@@ -249,9 +277,28 @@ osm_status do_solve(osm_handle *h, const double2 *b, double2 *x) {
     a.x = x;
     a.counters = h->counters;
     a.error = h->err_d;
-    HIPCHK(h, launch_strip_solve(h->st, a, h->fp32, h->prof ? h->ev0 : nullptr,
-                                 h->prof ? h->ev1 : nullptr));
-    h->prof_pending = h->prof;
+    a.ctl = ctl;
+    a.ran = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->prof) {
+        if (h->prof_used == PROF_SLOTS) {
+            HIPCHK(h, hipStreamSynchronize(h->st));
+            osm_status s = prof_collect(h);
+            if (s != OSM_OK) return s;
+        }
+        int slot = h->prof_used++;
+        if ((int)h->evs.size() < 2 * (slot + 1)) {
+            hipEvent_t a0, a1;
+            HIPCHK(h, hipEventCreate(&a0));
+            HIPCHK(h, hipEventCreate(&a1));
+            h->evs.push_back(a0);
+            h->evs.push_back(a1);
+        }
+        e0 = h->evs[2 * slot];
+        e1 = h->evs[2 * slot + 1];
+        a.ran = h->ran_d + slot;
+    }
+    HIPCHK(h, launch_strip_solve(h->st, a, h->fp32, e0, e1));
     return OSM_OK;
 }
 
@@ -260,14 +307,7 @@ osm_status check_solve_error(osm_handle *h) {
     HIPCHK(h, hipMemcpyAsync(&e, h->err_d, sizeof(int), hipMemcpyDeviceToHost, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
     if (e) return fail(h, OSM_EHIP, "strip solve: barrier wait timed out");
-    if (h->prof_pending) {
-        float ms = 0.f;
-        HIPCHK(h, hipEventElapsedTime(&ms, h->ev0, h->ev1));
-        h->solve_ms += ms;
-        h->solve_launches += 1;
-        h->prof_pending = false;
-    }
-    return OSM_OK;
+    return prof_collect(h);
 }
 
 // ---------------------------------------------------------------- Schwarz map
@@ -354,7 +394,7 @@ osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
         // after a cycle whose rotated residual met the tolerance, the true
         // residual is accepted within a rounding margin of 10x
         HIPCHK(h, launch_gmres_begin(h->st, n, r, h->gnorm_part, first ? 1 : 0,
-                                     prev_conv ? 10.0 : 1.0, V, h->ge, m, h->gctl));
+                                     prev_conv ? 10.0 : 1.0, V, h->ge, m, h->gctl, nullptr));
         int j = 0;
         while (j < m && total + j < o.max_gmres) {
             int ch = std::min(CH, std::min(m - j, o.max_gmres - total - j));
@@ -368,7 +408,7 @@ osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
             if (c.bad) return fail(h, OSM_ENONFINITE, "GMRES met a non-finite value");
             if (c.done) break;
         }
-        HIPCHK(h, launch_gmres_finish(h->st, n, m, h->gH, h->ge, h->gy, V, x, h->gctl));
+        HIPCHK(h, launch_gmres_finish(h->st, n, m, h->gH, h->ge, h->gy, V, x, h->gctl, 0));
         total += c.j;
         first = false;
         if (c.done && c.j == 0) break;            // residual already small enough
@@ -382,6 +422,149 @@ osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
     }
     *iters = total;
     return OSM_OK;
+}
+
+// ---------------------------------------------------------------- device-driven step
+// One Schwarz iteration is enqueued as a whole: a chunk of fixed-point
+// iterations, the flux, and then either the classical commit or the
+// preconditioned right-hand side, a first chunk of GMRES and the update.
+// Every kernel reads the StepCtl / GmresCtl flags and returns at once when
+// its phase is already complete or not yet reached, so the host
+// synchronises once per Schwarz iteration in the common case and only
+// enqueues more work when a fixed point or GMRES needs more iterations.
+
+osm_status read_ctl(osm_handle *h, StepCtl *c, GmresCtl *g) {
+    HIPCHK(h, hipMemcpyAsync(c, h->sctl, sizeof(StepCtl), hipMemcpyDeviceToHost, h->st));
+    if (g && h->m > 0)
+        HIPCHK(h, hipMemcpyAsync(g, h->gctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, h->st));
+    return check_solve_error(h);   // synchronises, checks the barrier flag, collects timing
+}
+
+osm_status fp_chunk(osm_handle *h, const double2 *u, int nq) {
+    for (int i = 0; i < nq; ++i) {
+        HIPCHK(h, launch_residual(h->st, h->P, h->strips_d, h->line_strip_d, h->W_d, u, h->zeta,
+                                  h->g, h->res, h->sctl));
+        osm_status s = do_solve(h, h->res, h->delta, h->sctl);
+        if (s != OSM_OK) return s;
+        HIPCHK(h, launch_update_norms(h->st, h->P, h->zeta, h->delta, h->line_part, h->sctl));
+        HIPCHK(h, launch_q_check(h->st, h->P, h->strips_d, h->line_part, h->sctl));
+    }
+    return OSM_OK;
+}
+
+osm_status gmres_iters(osm_handle *h, int j0, int j1) {
+    for (int j = j0; j < j1; ++j)
+        HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->LH, h->ng, j, h->m, h->Vb,
+                                         h->gdots1, h->gdots2, h->gnorm_part, h->gH, h->gcs,
+                                         h->gsn, h->ge, h->gctl));
+    return OSM_OK;
+}
+
+osm_status after_fixed_point(osm_handle *h) {
+    long ng = h->ng;
+    HIPCHK(h, launch_flux(h->st, h->P, h->strips_d, h->g, h->zeta, h->gn, h->trace_part, h->sctl));
+    HIPCHK(h, launch_flux_finalize(h->st, h->trace_part, 2 * (h->N - 1), h->sctl));
+    if (h->opt.algo == OSM_CLASSICAL) {
+        HIPCHK(h, launch_commit(h->st, ng, h->g, h->gn, h->sctl));
+        return OSM_OK;
+    }
+    // y = g - R(g) (in gtmp), x = 0 (gx), GMRES on P x = y, g <- g - x
+    HIPCHK(h, launch_precond_rhs(h->st, ng, h->g, h->gn, h->gtmp, h->gx, h->sctl));
+    HIPCHK(h, launch_gmres_begin(h->st, ng, h->gtmp, h->gnorm_part, 1, 1.0, h->Vb, h->ge, h->m,
+                                 h->gctl, h->sctl));
+    osm_status s = gmres_iters(h, 0, std::min(GMRES_CHUNK, h->m));
+    if (s != OSM_OK) return s;
+    HIPCHK(h, launch_gmres_finish(h->st, ng, h->m, h->gH, h->ge, h->gy, h->Vb, h->gx, h->gctl, 1));
+    HIPCHK(h, launch_precond_update(h->st, ng, h->g, h->gx, h->upd_part, h->sctl, h->gctl));
+    return OSM_OK;
+}
+
+// GMRES did not finish within the first chunk: more chunks, cycle ends and
+// restarts (r = y - P x) until a cycle finishes converged, then the update.
+osm_status gmres_continue(osm_handle *h, GmresCtl &gc, StepCtl &c) {
+    long ng = h->ng;
+    int m = h->m;
+    osm_status s = OSM_OK;
+    while (true) {
+        if (gc.bad) return fail(h, OSM_ENONFINITE, "GMRES met a non-finite value");
+        if (gc.finished && gc.conv) break;
+        int used = gc.total + (gc.finished ? 0 : gc.j);
+        if (used >= h->opt.max_gmres)
+            return fail(h, OSM_ENOCONV, "GMRES did not converge within max_gmres");
+        if (gc.finished) {
+            double2 *w = h->Vb + (long)(m + 1) * ng;
+            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->LH, h->gx, w, 1));
+            HIPCHK(h, launch_axpby(h->st, ng, cd(1, 0), h->gtmp, cd(-1, 0), w, w));
+            HIPCHK(h, launch_gmres_begin(h->st, ng, w, h->gnorm_part, 0, 1.0, h->Vb, h->ge, m,
+                                         h->gctl, h->sctl));
+            s = gmres_iters(h, 0, std::min(GMRES_CHUNK, m));
+        } else if (!gc.done && gc.j < m) {
+            s = gmres_iters(h, gc.j, std::min(gc.j + GMRES_CHUNK, m));
+        } else {
+            HIPCHK(h, launch_gmres_finish(h->st, ng, m, h->gH, h->ge, h->gy, h->Vb, h->gx,
+                                          h->gctl, 0));
+        }
+        if (s != OSM_OK) return s;
+        s = read_ctl(h, &c, &gc);
+        if (s != OSM_OK) return s;
+    }
+    HIPCHK(h, launch_precond_update(h->st, ng, h->g, h->gx, h->upd_part, h->sctl, h->gctl));
+    return read_ctl(h, &c, &gc);
+}
+
+osm_status schwarz_device(osm_handle *h, const double2 *u, osm_step_stats *S) {
+    const osm_options &o = h->opt;
+    StepCfg cfg;
+    cfg.tol_q = o.tol_q;
+    cfg.eta_q = o.fixed_q > 0 ? 0.0 : o.eta_q;
+    cfg.tol_k = o.tol_k;
+    cfg.tol_k_rel = o.tol_k_relative;
+    cfg.fixed_q = o.fixed_q;
+    cfg.max_q = o.max_q;
+    cfg.fixed_k = o.fixed_k;
+    cfg.classical = o.algo == OSM_CLASSICAL;
+    HIPCHK(h, launch_step_init(h->st, h->sctl, cfg));
+    HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
+    int nk = o.fixed_k > 0 ? o.fixed_k : o.max_k;
+    StepCtl c;
+    GmresCtl gc;
+    memset(&c, 0, sizeof(c));
+    memset(&gc, 0, sizeof(gc));
+    auto fill = [&]() {
+        S->k = c.k;
+        S->q_total = c.q_total;
+        S->gmres_total = c.gm_total;
+        S->last_increment = c.inc;
+        S->refine_total = h->fp32 ? c.q_total : 0;
+    };
+    osm_status s;
+    for (int k = 1; k <= nk; ++k) {
+        HIPCHK(h, launch_iter_reset(h->st, h->sctl, h->m > 0 ? h->gctl : nullptr));
+        if (k > 1 && !o.warm_start)
+            HIPCHK(h, launch_copy_u_guarded(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta,
+                                            h->sctl));
+        int nq = o.fixed_q > 0 ? o.fixed_q : std::max(1, std::min(o.max_q, h->q_chunk));
+        if ((s = fp_chunk(h, u, nq)) != OSM_OK) return s;
+        if ((s = after_fixed_point(h)) != OSM_OK) return s;
+        if ((s = read_ctl(h, &c, &gc)) != OSM_OK) return s;
+        while (!c.q_conv && !c.bad) {
+            if (c.q_fail) {
+                fill();
+                return fail(h, OSM_ENOCONV, "fixed point did not converge within max_q");
+            }
+            nq = std::max(1, std::min(h->q_chunk, o.max_q - c.q_iter));
+            if ((s = fp_chunk(h, u, nq)) != OSM_OK) return s;
+            if ((s = after_fixed_point(h)) != OSM_OK) return s;
+            if ((s = read_ctl(h, &c, &gc)) != OSM_OK) return s;
+        }
+        if (!c.bad && o.fixed_q <= 0) h->q_chunk = std::max(2, c.q_iter);
+        if (!c.bad && !cfg.classical && c.r_done == 1)
+            if ((s = gmres_continue(h, gc, c)) != OSM_OK) { fill(); return s; }
+        fill();
+        if (c.bad) return fail(h, OSM_ENONFINITE, "non-finite value in the Schwarz iteration");
+        if (c.k_done) return OSM_OK;
+    }
+    return fail(h, OSM_ENOCONV, "Schwarz iteration did not converge within max_k");
 }
 
 // ---------------------------------------------------------------- L_h build
@@ -598,6 +781,9 @@ osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_
         SALLOC(h->flag_d, int, 1);
         SALLOC(h->counters, unsigned, h->N);
         SALLOC(h->err_d, int, 1);
+        SALLOC(h->ran_d, int, PROF_SLOTS);
+        SALLOC(h->sctl, StepCtl, 1);
+        SALLOC(h->upd_part, double, 2 * ((h->ng + 255) / 256));
         h->nblk = 256;
         SALLOC(h->norm_part, double, h->nblk);
         if (h->m > 0) {
@@ -623,6 +809,13 @@ osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_
         HIPCHK(h, hipMemcpy(h->ff_first_d, fff.data(), sizeof(int) * h->maxnx, hipMemcpyHostToDevice));
         HIPCHK(h, hipMemset(h->g, 0, sizeof(double2) * h->ng));
         HIPCHK(h, hipMemset(h->gguess, 0, sizeof(double2) * h->ng));
+        if (h->m > 0) {
+            GmresCtl c0;
+            memset(&c0, 0, sizeof(c0));
+            c0.tol = h->opt.tol_gmres;
+            c0.done = 1;
+            HIPCHK(h, hipMemcpy(h->gctl, &c0, sizeof(c0), hipMemcpyHostToDevice));
+        }
         // workgroups per strip in the solve: fill the resident capacity
         int cap = solve_max_resident_blocks(h->fp32, h->n);
         if (cap <= 0) return fail(h, OSM_EHIP, "occupancy query failed");
@@ -655,10 +848,11 @@ static osm_status autotune_team(osm_handle *h) {
     bool prof = h->prof;
     double keep_ms = h->solve_ms;
     long long keep_n = h->solve_launches;
-    if (!h->ev0) {
-        HIPCHK(h, hipEventCreate(&h->ev0));
-        HIPCHK(h, hipEventCreate(&h->ev1));
-    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    osm_status s0 = prof_collect(h);
+    if (s0 != OSM_OK) return s0;
+    keep_ms = h->solve_ms;
+    keep_n = h->solve_launches;
     HIPCHK(h, hipMemsetAsync(h->res, 0, sizeof(double2) * (size_t)h->Lt * h->n, h->st));
     int best = h->team;
     double best_ms = 1e300;
@@ -740,59 +934,10 @@ osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats) {
     if (o.guess == 1 && h->has_guess)
         HIPCHK(h, hipMemcpyAsync(h->g, h->gguess, sizeof(double2) * h->ng, hipMemcpyDeviceToDevice, h->st));
     HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
-    int nk = o.fixed_k > 0 ? o.fixed_k : o.max_k;
-    bool conv = false;
-    long ng = h->ng;
-    double prev_rel = 1.0;   // relative increment of the previous Schwarz iteration
-    for (int k = 1; k <= nk; ++k) {
-        if (k > 1 && !o.warm_start)
-            HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
-        int q = 0;
-        double inc2 = 0, gn2 = 0;
-        double tq = o.tol_q;
-        if (o.eta_q > 0) tq = std::max(o.tol_q, o.eta_q * std::min(1.0, prev_rel));
-        s = apply_R(h, u, h->g, h->gn, &q, &inc2, &gn2, tq);
-        S.q_total += q;
-        S.k = k;
-        if (s != OSM_OK) {
-            if (stats) *stats = S;
-            return s;
-        }
-        if (h->fp32) S.refine_total += q;
-        double inc, ref;
-        if (o.algo == OSM_CLASSICAL) {
-            std::swap(h->g, h->gn);
-            inc = sqrt(inc2);
-            ref = sqrt(gn2);
-        } else {
-            // y = g - R(g); x = P^{-1} y; g = g - x
-            HIPCHK(h, launch_axpby(h->st, ng, cd(1, 0), h->g, cd(-1, 0), h->gn, h->gtmp));
-            int it = 0;
-            s = gmres(h, h->gtmp, h->gx, &it);
-            S.gmres_total += it;
-            if (s != OSM_OK) {
-                if (stats) *stats = S;
-                return s;
-            }
-            HIPCHK(h, launch_axpby(h->st, ng, cd(1, 0), h->g, cd(-1, 0), h->gx, h->g));
-            inc = dev_norm(h, h->gx, ng, &s);
-            if (s != OSM_OK) return s;
-            ref = dev_norm(h, h->g, ng, &s);
-            if (s != OSM_OK) return s;
-        }
-        S.last_increment = inc;
-        prev_rel = inc / std::max(ref, 1e-300);
-        if (!isfinite(inc)) {
-            if (stats) *stats = S;
-            return fail(h, OSM_ENONFINITE, "interface increment not finite");
-        }
-        double thr = o.tol_k_relative ? o.tol_k * std::max(ref, 1e-300) : o.tol_k;
-        if (o.fixed_k <= 0 && inc < thr) { conv = true; break; }
-    }
-    if (o.fixed_k > 0) conv = true;
-    if (!conv) {
+    s = schwarz_device(h, u, &S);
+    if (s != OSM_OK) {
         if (stats) *stats = S;
-        return fail(h, OSM_ENOCONV, "Schwarz iteration did not converge within max_k");
+        return s;
     }
     HIPCHK(h, launch_time_update(h->st, h->P, h->gmap_d, h->zeta, u));
     s = mass_of(h, u, &S.mass_after);
@@ -906,10 +1051,9 @@ osm_status osm_get_factor(osm_handle *h, void *dst_dev) {
 osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
                              int64_t *solve_launches) {
     if (!h) return OSM_EINVAL;
-    if (enable && !h->ev0) {
-        HIPCHK(h, hipEventCreate(&h->ev0));
-        HIPCHK(h, hipEventCreate(&h->ev1));
-    }
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    osm_status s = prof_collect(h);
+    if (s != OSM_OK) return s;
     if (solve_ms) *solve_ms = h->solve_ms;
     if (solve_launches) *solve_launches = h->solve_launches;
     if (enable) {
@@ -926,8 +1070,7 @@ void osm_destroy(osm_handle *h) {
     if (!h) return;
     if (h->st) hipStreamSynchronize(h->st);
     else hipDeviceSynchronize();
-    if (h->ev0) hipEventDestroy(h->ev0);
-    if (h->ev1) hipEventDestroy(h->ev1);
+    for (hipEvent_t e : h->evs) hipEventDestroy(e);
     for (void *p : h->allocs) hipFree(p);
     delete h;
 }

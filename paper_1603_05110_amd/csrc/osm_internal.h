@@ -58,21 +58,28 @@ __device__ __forceinline__ double ref_triple(int c, int a, int b) {
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return the hipError_t of the launch.
 
+struct StepCtl;   // device-side step control (kernels_control.hip); null = unguarded
+
 // kernels_assemble.hip
 hipError_t launch_coef(hipStream_t st, const Phys &P, const StripMeta *strips,
                        const int *line_strip, const double *W, int w_is_zero,
                        double2 *Dc, double2 *Uc, int line_begin, int line_count);
+// fixed-point kernels return at once when c says the fixed point is done
 hipError_t launch_residual(hipStream_t st, const Phys &P, const StripMeta *strips,
                            const int *line_strip, const double *W, const double2 *u_old,
-                           const double2 *zeta, const double2 *g, double2 *res);
+                           const double2 *zeta, const double2 *g, double2 *res,
+                           const StepCtl *c = nullptr);
 hipError_t launch_copy_u_to_strips(hipStream_t st, const Phys &P, const StripMeta *strips,
                                    const int *line_strip, const double2 *u, double2 *zeta);
 hipError_t launch_update_norms(hipStream_t st, const Phys &P, double2 *zeta,
-                               const double2 *delta, double *line_part);
+                               const double2 *delta, double *line_part,
+                               const StepCtl *c = nullptr);
 hipError_t launch_strip_sums(hipStream_t st, const Phys &P, const StripMeta *strips,
                              const double *line_part, double *strip_out);
+// runs only once the fixed point has converged (when c is given)
 hipError_t launch_flux(hipStream_t st, const Phys &P, const StripMeta *strips,
-                       const double2 *g, const double2 *v, double2 *gn, double *part);
+                       const double2 *g, const double2 *v, double2 *gn, double *part,
+                       const StepCtl *c = nullptr);
 hipError_t launch_time_update(hipStream_t st, const Phys &P, const int2 *gline_map,
                               const double2 *v, double2 *u);
 hipError_t launch_mass_partials(hipStream_t st, const Phys &P, const double2 *u, double *part);
@@ -124,35 +131,80 @@ struct SolveArgs {
     double2 *x;              // solution, packed
     unsigned int *counters;  // one per strip, zero on entry
     int *error;              // set to 1 if a barrier wait times out
+    const StepCtl *ctl;      // may be null; the whole solve is skipped when it
+                             // says the fixed point is done
+    int *ran;                // may be null; set to 1 when the solve was not skipped
 };
 // ev0/ev1 (may be null) are recorded right before and after the solve kernel
 hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipEvent_t ev0,
                               hipEvent_t ev1);
 int solve_max_resident_blocks(int fp32, int n);
 
+// kernels_control.hip
+// Step configuration and device-side state of one time step.
+struct StepCfg {
+    double tol_q, eta_q, tol_k;
+    int tol_k_rel, fixed_q, max_q, fixed_k, classical;
+};
+struct StepCtl {
+    StepCfg cfg;
+    int q_conv;     // fixed point of the current Schwarz map converged
+    int q_iter;     // fixed-point iterations of the current Schwarz map
+    int q_total;    // summed over the step
+    int q_fail;     // max_q reached without convergence
+    int r_done;     // 1: Schwarz map evaluated, 2: preconditioned update done
+    int k;          // Schwarz iterations completed
+    int k_done;     // Schwarz iteration converged
+    int bad;        // non-finite value met
+    int commit;     // classical: g <- R(g) pending
+    int gm_total;   // GMRES iterations summed over the step
+    double tq;      // fixed-point tolerance of the current Schwarz map
+    double inc, ref, prev_rel;
+};
+struct GmresCtl;
+hipError_t launch_step_init(hipStream_t st, StepCtl *c, const StepCfg &cfg);
+hipError_t launch_iter_reset(hipStream_t st, StepCtl *c, GmresCtl *g);
+hipError_t launch_copy_u_guarded(hipStream_t st, const Phys &P, const StripMeta *strips,
+                                 const int *line_strip, const double2 *u, double2 *zeta,
+                                 const StepCtl *c);
+hipError_t launch_q_check(hipStream_t st, const Phys &P, const StripMeta *strips,
+                          const double *part, StepCtl *c);
+hipError_t launch_flux_finalize(hipStream_t st, const double *part, int nt, StepCtl *c);
+hipError_t launch_commit(hipStream_t st, long n, double2 *g, const double2 *gn, const StepCtl *c);
+hipError_t launch_precond_rhs(hipStream_t st, long n, const double2 *g, const double2 *gn,
+                              double2 *y, double2 *x, const StepCtl *c);
+hipError_t launch_precond_update(hipStream_t st, long n, double2 *g, const double2 *x,
+                                 double *part, const StepCtl *c, const GmresCtl *gc);
+
 // kernels_gmres.hip
-// Device-side state of one GMRES cycle (Arnoldi loop driven on the GPU).
+// Device-side state of one GMRES solve (Arnoldi loop driven on the GPU).
 struct GmresCtl {
     int done;       // cycle finished: converged, breakdown or non-finite
     int conv;       // residual estimate met tol * bnorm
     int bad;        // non-finite value met
     int j;          // Arnoldi steps completed in this cycle
+    int finished;   // x updated from this cycle
+    int total;      // Arnoldi steps summed over the cycles of this solve
+    int skip;       // the current end-of-cycle launch does nothing
     double bnorm;   // ||y||
     double tol;     // relative tolerance
     double beta;    // ||r_0|| of the cycle
     double inv_hn;  // 1 / h_{j+1,j} (normalisation of the next basis vector)
     double resid;   // current residual estimate
 };
+// sctl (may be null): the cycle starts only when the Schwarz map of the
+// current iteration has been evaluated.
 hipError_t launch_gmres_begin(hipStream_t st, long n, const double2 *r, double *norm_part,
                               int first, double accept, double2 *V0, double2 *e, int m,
-                              GmresCtl *ctl);
+                              GmresCtl *ctl, const StepCtl *sctl);
 hipError_t launch_gmres_iteration(hipStream_t st, const Phys &P, const StripMeta *strips,
                                   const double2 *LH, long n, int j, int m, double2 *V,
                                   double2 *dots1, double2 *dots2, double *norm_part,
                                   double2 *H, double2 *cs, double2 *sn, double2 *e,
                                   GmresCtl *ctl);
 hipError_t launch_gmres_finish(hipStream_t st, long n, int m, const double2 *H, const double2 *e,
-                               double2 *y, const double2 *V, double2 *x, const GmresCtl *ctl);
+                               double2 *y, const double2 *V, double2 *x, GmresCtl *ctl,
+                               int require_done);
 hipError_t launch_lh_matvec(hipStream_t st, const Phys &P, const StripMeta *strips,
                             const double2 *LH, const double2 *x, double2 *y, int mode_p);
 hipError_t launch_multidot(hipStream_t st, long n, const double2 *V, int nv, const double2 *w,

@@ -209,6 +209,29 @@ def test_c1_matches_oracle():
     assert rel(ud.cpu().numpy(), ref) < 1e-10
 
 
+@pytest.mark.parametrize("prec", ["fp64", "c32"])
+def test_rotating_frame_refactor_every_step_matches_oracle(prec):
+    """Rotating-frame GPE (Section 5.2.1): W_n computed on the device from
+    the rotated anisotropic trap and refactored every step, uneven strips."""
+    log(f"rotating frame {prec}")
+    from oracle.rotating import step_potential
+    from workloads import gaussian_boost
+    osm = _osm()
+    pb = Problem(-6.0, 6.0, -6.0, 6.0, 40, 71, 3, [12, 16, 12], lap_coef=0.5, beta=-20.0,
+                 p=3.0, p_bc=3.0, dt=0.02, omega=-0.7, vxx=-0.5, vyy=-0.6)
+    u0 = gaussian_boost(pb, k=0.5, a=0.5)
+    steps = 4
+    ref = run_monolithic(pb, u0, lambda n: step_potential(pb, n), steps, tol_q=1e-14)
+    s = osm.OsmSolver(pb, DEV, algo="precond", prec=prec, tol_k=1e-12, tol_k_relative=True,
+                      tol_q=1e-14)
+    ud = to_dev(u0)
+    for n in range(1, steps + 1):
+        s.factor_rotating(n)
+        s.step(ud)
+    s.close()
+    assert rel(ud.cpu().numpy(), ref) < 1e-10
+
+
 def test_neumann_mass_invariance():
     """p_bc = 0: the discrete mass is invariant (exact identity of the
     scheme, any size); transmission p > 0 between strips."""
