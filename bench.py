@@ -34,6 +34,26 @@ sys.path.insert(0, ROOT)
 METRIC = "dof-steps/s at 1e-10 rel L2 vs FP64 oracle; Schwarz/GMRES iters per step"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per strip-solve launch from rocprofv3 FETCH_SIZE + WRITE_SIZE on
+# this workload, each scaled by the counter's reading for a 1 GiB copy
+# (fetch x2.0, write x1.0); valid only for the kernel source it was taken on.
+SOLVE_TRAFFIC = {"c32": {"bytes": 2.2718e9,
+                         "source_sha256": "1f058ed11ae34716f5b494e60d2027c1f6b9d6ac6eb7f437c70bf1e2f2885043",
+                         "summary": "profiles/strip_solve_c32_gpe512_hbm_counters.md"}}
+
+
+def measured_traffic(prec):
+    import hashlib
+    rec = SOLVE_TRAFFIC.get(prec)
+    if rec is None:
+        return None
+    path = os.path.join(ROOT, "paper_1603_05110_amd", "csrc", "kernels_solve.hip")
+    try:
+        sha = hashlib.sha256(open(path, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return rec["bytes"] if sha == rec["source_sha256"] else None
+
 
 def solver_opts(prec):
     return dict(algo="precond", prec=prec, tol_k=1e-12, tol_k_relative=True, max_k=500,
@@ -84,6 +104,38 @@ def run_gpu(pb, u0, V, prec, steps, warmup, dev, measure=True):
                 solve_ms=kern[0], solve_launches=kern[1], team=team)
 
 
+def profile_solve(pb, V, prec, launches, dev):
+    """Kernel-level measurement mode for profilers: factor once, then run
+    `launches` strip solves on a seeded right-hand side, then one
+    device-to-device copy of 1 GiB (the calibration kernel for the HBM byte
+    counters: its algorithmic traffic is 1 GiB read + 1 GiB written)."""
+    import torch
+    from paper_1603_05110_amd import osm
+    s = osm.OsmSolver(pb, dev, **solver_opts(prec))
+    s.factor(torch.from_numpy(V).to(dev))
+    gen = torch.Generator(device="cpu").manual_seed(1603)
+    b = torch.randn((s.lt, s.ny), dtype=torch.complex128, generator=gen).to(dev)
+    s.strip_solve(b)
+    torch.cuda.synchronize()
+    s.kernel_timing(True)
+    for _ in range(launches):
+        s.strip_solve(b)
+    torch.cuda.synchronize()
+    ms, n = s.kernel_timing(False)
+    team = s.solve_team()
+    s.close()
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    nbytes = solve_bytes(pb, prec)
+    avg = ms / max(n, 1)
+    print(json.dumps({"mode": "profile-solve", "prec": prec, "launches": n, "avg_launch_ms": avg,
+                      "bytes_per_launch": nbytes, "achieved_GBs": nbytes / (avg * 1e-3) / 1e9,
+                      "workgroups_per_strip": team, "copy_bytes": 2 * src.numel() * 8}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +146,8 @@ def main():
                     help="steps of the plain FP64 GPU path timed for comparison (0 = skip)")
     ap.add_argument("--parity-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-solve", type=int, default=0, metavar="LAUNCHES",
+                    help="profiler mode: only factor + LAUNCHES strip solves + a 1 GiB copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -112,6 +166,9 @@ def main():
     dof = (pb.ncx + 1) * (pb.ncy + 1)
     print(f"bench: {pb.name} dof={dof} prec={args.prec} steps={args.steps}", file=sys.stderr,
           flush=True)
+    if args.profile_solve > 0:
+        profile_solve(pb, V, args.prec, args.profile_solve, dev)
+        return
 
     main_run = run_gpu(pb, u0, V, args.prec, args.steps, args.warmup, dev)
     T = main_run["seconds"]
@@ -185,7 +242,7 @@ def main():
                   "gmres_per_step": float(np.mean(gm))},
         "roofline": {"kernel": "strip_solve", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
+                     "traffic": measured_traffic(args.prec), "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
                      "launches": main_run["solve_launches"],
                      "workgroups_per_strip": main_run["team"]},
         "setup_s": main_run["setup_s"],
