@@ -199,6 +199,51 @@ osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
  * solves for every feasible team size).  0 for a NULL handle. */
 int32_t osm_solve_team(const osm_handle *h);
 
+/* ---------------------------------------------------------------- batches
+ * nb independent instances (each its own mesh, strip layout, p and
+ * potential; Section 2: one problem statement per instance) advanced
+ * together with the classical algorithm (eq. fluxlr).  Every time-step kernel
+ * covers all instances in one launch; the strip solve takes the strips of
+ * all instances from one work queue in a persistent grid; a chunk of Schwarz
+ * iterations is captured once as a HIP graph and replayed until every
+ * instance meets its own stopping test, so each instance converges exactly
+ * as it would alone.  The single-instance entry points return OSM_ESTATE on
+ * a batch handle, and the batch entry points on a single handle.
+ * osm_kernel_timing works on a batch handle (timed steps then run the chunk
+ * launch by launch instead of as a graph). */
+
+/* Footprint of osm_setup_batch.  OSM_EUNSUPPORTED unless opt->algo is
+ * OSM_CLASSICAL. */
+osm_status osm_query_batch(const osm_problem *probs, int32_t nb,
+                           const osm_options *opt, osm_footprint *out);
+
+/* probs: host array of nb problems (strip_cells read during the call).  One
+ * opt for all.  OSM_ENOMEM before any allocation when the summed footprint
+ * exceeds free device memory or opt->mem_cap. */
+osm_status osm_setup_batch(const osm_problem *probs, int32_t nb,
+                           const osm_options *opt, void *hip_stream,
+                           osm_handle **out);
+
+/* W_devs: host array of nb device pointers, W_n of each instance (global
+ * nodes of that instance).  Factors every instance; the first call also
+ * runs the autotuner of the batched solve (tile shape x workgroups per
+ * strip, timed on the batch itself). */
+osm_status osm_factor_batch(osm_handle *h, const double *const *W_devs);
+
+/* u_devs: host array of nb device pointers, u_{n-1} in and u_n out for every
+ * instance.  stats: host array of nb entries (may be NULL).  On OSM_ENOCONV
+ * or OSM_ENONFINITE no instance's u is changed and stats hold the
+ * iteration counts reached. */
+osm_status osm_step_batch(osm_handle *h, osm_c64 *const *u_devs,
+                          osm_step_stats *stats);
+
+/* The autotuner's choice: tile-shape index, team rule alpha (0 = one
+ * workgroup per strip; else strips costing more than alpha times the mean
+ * work per workgroup get proportionally more), grid size and work items.
+ * Any output may be NULL. */
+osm_status osm_batch_tuning(const osm_handle *h, int32_t *variant, double *alpha,
+                            int32_t *workgroups, int32_t *items);
+
 void osm_destroy(osm_handle *h);
 const char *osm_last_error(const osm_handle *h);
 

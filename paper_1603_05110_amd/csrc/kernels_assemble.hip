@@ -2,50 +2,9 @@
 // coefficient assembly of the strip operator, the fixed-point residual, the
 // flux update of the interface vector (eq. fluxlr), the time update and the
 // discrete mass.  All FP64; memory-bound, one thread per node.
-#include "osm_internal.h"
+#include "step_bodies.h"
 
 namespace {
-
-// Integrals between node (i,a) and node (ip,b) of one strip with nx lines:
-// mass m, stiffness s, potential-weighted mass w = int phi_h psi psi (phi
-// replaced by its Q1 interpolant, triple products exact) and the y-mass of
-// the left/right edge lines (boundary mass M^Gamma).  Elements of the strip
-// only: a strip is its own finite-element domain.
-struct KParts {
-    double m, s, w, edge_l, edge_r;
-};
-
-template <class PhiF>
-__device__ __forceinline__ KParts kparts(int i, int a, int ip, int b, int nx, int ny,
-                                         double hx, double hy, PhiF phi) {
-    KParts k = {0.0, 0.0, 0.0, 0.0, 0.0};
-    int exlo = max(max(i, ip) - 1, 0), exhi = min(min(i, ip), nx - 2);
-    int eylo = max(max(a, b) - 1, 0), eyhi = min(min(a, b), ny - 2);
-    for (int ex = exlo; ex <= exhi; ++ex) {
-        int Ax = i - ex, Bx = ip - ex;
-        double mx = hx * ref_mass(Ax, Bx), sx = ref_stiff(Ax, Bx) / hx;
-        for (int ey = eylo; ey <= eyhi; ++ey) {
-            int Ay = a - ey, By = b - ey;
-            double my = hy * ref_mass(Ay, By), sy = ref_stiff(Ay, By) / hy;
-            k.m += mx * my;
-            k.s += sx * my + mx * sy;
-            double acc = 0.0;
-#pragma unroll
-            for (int cx = 0; cx < 2; ++cx)
-#pragma unroll
-                for (int cy = 0; cy < 2; ++cy)
-                    acc += phi(ex + cx, ey + cy) * ref_triple(cx, Ax, Bx) * ref_triple(cy, Ay, By);
-            k.w += hx * hy * acc;
-        }
-    }
-    if (i == ip && (i == 0 || i == nx - 1)) {
-        double my = 0.0;
-        for (int ey = eylo; ey <= eyhi; ++ey) my += hy * ref_mass(a - ey, b - ey);
-        if (i == 0) k.edge_l = my;
-        if (i == nx - 1) k.edge_r = my;
-    }
-    return k;
-}
 
 // D_i (diagonal block, line i with itself) and U_i (line i with line i+1) of
 // K_j(W) = 2i/dt M - c S + M_W + i c (pl M^Gamma_l + pr M^Gamma_r), stored as
@@ -86,53 +45,11 @@ __global__ void coef_kernel(Phys P, const StripMeta *strips, const int *line_str
 __global__ void residual_kernel(Phys P, const StripMeta *strips, const int *line_strip,
                                 const double *W, const double2 *u_old, const double2 *zeta,
                                 const double2 *g, double2 *res, const StepCtl *c) {
-    if (c && (c->q_conv || c->k_done || c->bad)) return;
+    if (c && fp_idle(c)) return;
     int L = blockIdx.y;
     int a = blockIdx.x * blockDim.x + threadIdx.x;
-    int ny = P.ny;
-    if (a >= ny) return;
-    int j = line_strip[L];
-    StripMeta s = strips[j];
-    int i = L - s.off;
-    const double *Wl = W + (long)s.line0 * ny;
-    const double2 *ul = u_old + (long)s.line0 * ny;
-    const double2 *zl = zeta + (long)s.off * ny;
-    double beta = P.beta;
-    auto phi = [&](int ii, int kk) -> double {
-        double2 z = zl[(long)ii * ny + kk];
-        return Wl[(long)ii * ny + kk] + beta * (z.x * z.x + z.y * z.y);
-    };
-    double2 acc = cd(0.0, 0.0);
-    const double2 *trace = nullptr;
-    if (i == 0 && j >= 1) trace = g + (long)(2 * (j - 1) + 1) * ny;             // l_j
-    if (i == s.nx - 1 && j <= P.nsub - 2) trace = g + (long)(2 * j) * ny;       // r_j
-    for (int ip = max(i - 1, 0); ip <= min(i + 1, s.nx - 1); ++ip) {
-        for (int b = max(a - 1, 0); b <= min(a + 1, ny - 1); ++b) {
-            KParts k = kparts(i, a, ip, b, s.nx, ny, P.hx, P.hy, phi);
-            double2 z = zl[(long)ip * ny + b];
-            double2 u = ul[(long)ip * ny + b];
-            // 2i/dt m (u - z)
-            double2 du = csub(u, z);
-            acc.x += -(2.0 / P.dt) * k.m * du.y;
-            acc.y += (2.0 / P.dt) * k.m * du.x;
-            // + c s z - w z
-            double cs = P.c * k.s - k.w;
-            acc.x += cs * z.x;
-            acc.y += cs * z.y;
-            // - i c (pl edge_l + pr edge_r) z
-            double e = P.c * (s.pl * k.edge_l + s.pr * k.edge_r);
-            acc.x += e * z.y;
-            acc.y += -e * z.x;
-            // - c M^Gamma trace
-            if (trace && ip == i) {
-                double my = (i == 0) ? k.edge_l : k.edge_r;
-                double2 t = trace[b];
-                acc.x -= P.c * my * t.x;
-                acc.y -= P.c * my * t.y;
-            }
-        }
-    }
-    res[(long)L * ny + a] = acc;
+    if (a >= P.ny) return;
+    res[(long)L * P.ny + a] = residual_at(P, strips, line_strip, W, u_old, zeta, g, L, a);
 }
 
 __global__ void copy_u_kernel(Phys P, const StripMeta *strips, const int *line_strip,
@@ -140,46 +57,14 @@ __global__ void copy_u_kernel(Phys P, const StripMeta *strips, const int *line_s
     int L = blockIdx.y;
     int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= P.ny) return;
-    StripMeta s = strips[line_strip[L]];
-    int gl = s.line0 + (L - s.off);
-    zeta[(long)L * P.ny + a] = u[(long)gl * P.ny + a];
+    copy_u_at(P, strips, line_strip, u, zeta, L, a);
 }
 
-// zeta += delta on one packed line; per-line partial sums |delta|^2, |zeta|^2
-// and a non-finite counter.
+// zeta += delta on one packed line, with the per-line partial norms.
 __global__ void update_norms_kernel(Phys P, double2 *zeta, const double2 *delta, double *part,
                                     const StepCtl *c) {
-    if (c && (c->q_conv || c->k_done || c->bad)) return;
-    int L = blockIdx.x;
-    int ny = P.ny;
-    double s_d = 0.0, s_z = 0.0, bad = 0.0;
-    for (int a = threadIdx.x; a < ny; a += blockDim.x) {
-        long o = (long)L * ny + a;
-        double2 d = delta[o];
-        double2 z = cadd(zeta[o], d);
-        zeta[o] = z;
-        s_d += d.x * d.x + d.y * d.y;
-        s_z += z.x * z.x + z.y * z.y;
-        if (!isfinite(d.x) || !isfinite(d.y)) bad += 1.0;
-    }
-    __shared__ double red[3][256];
-    red[0][threadIdx.x] = s_d;
-    red[1][threadIdx.x] = s_z;
-    red[2][threadIdx.x] = bad;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + w];
-            red[1][threadIdx.x] += red[1][threadIdx.x + w];
-            red[2][threadIdx.x] += red[2][threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        part[3 * L] = red[0][0];
-        part[3 * L + 1] = red[1][0];
-        part[3 * L + 2] = red[2][0];
-    }
+    if (c && fp_idle(c)) return;
+    update_norms_line(P.ny, zeta, delta, part, blockIdx.x);
 }
 
 __global__ void strip_sums_kernel(Phys P, const StripMeta *strips, const double *part,
@@ -198,118 +83,29 @@ __global__ void strip_sums_kernel(Phys P, const StripMeta *strips, const double 
     out[3 * j + 2] = c;
 }
 
-// Flux update, eq. fluxlr with S = -ip (Jacobi):
-//   new r_i     = -l_{i+1} - 2ip v_{i+1}(first line)
-//   new l_{i+1} = -r_i     - 2ip v_i(last line)
-// Per-trace partial sums of |gn - g|^2 and |gn|^2.
+// Flux update of every trace (eq. fluxlr), per-trace partial norms.
 __global__ void flux_kernel(Phys P, const StripMeta *strips, const double2 *g,
                             const double2 *v, double2 *gn, double *part, const StepCtl *c) {
     if (c && (!c->q_conv || c->r_done || c->k_done || c->bad)) return;
-    int t = blockIdx.x;           // trace 0 .. 2(N-1)-1
-    int ny = P.ny;
-    int i = t >> 1;
-    const double2 *src;
-    const double2 *vt;
-    if ((t & 1) == 0) {           // r_i from strip i+1's left line
-        src = g + (long)(2 * i + 1) * ny;
-        vt = v + (long)strips[i + 1].off * ny;
-    } else {                      // l_{i+1} from strip i's right line
-        src = g + (long)(2 * i) * ny;
-        StripMeta s = strips[i];
-        vt = v + (long)(s.off + s.nx - 1) * ny;
-    }
-    double tp = 2.0 * P.p;
-    double sd = 0.0, sn = 0.0;
-    for (int a = threadIdx.x; a < ny; a += blockDim.x) {
-        double2 x = src[a], w = vt[a];
-        // -x - 2ip w = (-x.re + 2p w.im) + i(-x.im - 2p w.re)
-        double2 r = cd(-x.x + tp * w.y, -x.y - tp * w.x);
-        double2 o = g[(long)t * ny + a];
-        gn[(long)t * ny + a] = r;
-        sd += (r.x - o.x) * (r.x - o.x) + (r.y - o.y) * (r.y - o.y);
-        sn += r.x * r.x + r.y * r.y;
-    }
-    __shared__ double red[2][256];
-    red[0][threadIdx.x] = sd;
-    red[1][threadIdx.x] = sn;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + w];
-            red[1][threadIdx.x] += red[1][threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        part[2 * t] = red[0][0];
-        part[2 * t + 1] = red[1][0];
-    }
+    flux_trace(P, strips, g, v, gn, part, blockIdx.x);
 }
 
-// u_n = 2 vbar - u_{n-1} on every global node; vbar is the strip value, the
-// mean of the two copies on an interface line.
+// u_n = 2 vbar - u_{n-1} on every global node.
 __global__ void time_update_kernel(Phys P, const int2 *gmap, const double2 *v, double2 *u) {
     int gl = blockIdx.y;
     int a = blockIdx.x * blockDim.x + threadIdx.x;
-    int ny = P.ny;
-    if (a >= ny) return;
-    int2 m = gmap[gl];
-    double2 vb = v[(long)m.x * ny + a];
-    if (m.y >= 0) vb = cscale(0.5, cadd(vb, v[(long)m.y * ny + a]));
-    long o = (long)gl * ny + a;
-    double2 uo = u[o];
-    u[o] = cd(2.0 * vb.x - uo.x, 2.0 * vb.y - uo.y);
+    if (a >= P.ny) return;
+    time_update_at(P, gmap, v, u, gl, a);
 }
 
-// Per-line partials of u* M u with the global Q1 mass M = M1x (x) M1y.
+// Per-line partials of u* M u.
 __global__ void mass_kernel(Phys P, const double2 *u, double *part) {
-    int gl = blockIdx.x;
-    int ny = P.ny, ng = P.nglob;
-    double hx = P.hx, hy = P.hy;
-    double acc = 0.0;
-    for (int a = threadIdx.x; a < ny; a += blockDim.x) {
-        double2 mu = cd(0.0, 0.0);
-        for (int ip = max(gl - 1, 0); ip <= min(gl + 1, ng - 1); ++ip) {
-            double mx;
-            if (ip != gl) mx = hx / 6.0;
-            else mx = (gl == 0 || gl == ng - 1) ? hx / 3.0 : 2.0 * hx / 3.0;
-            for (int b = max(a - 1, 0); b <= min(a + 1, ny - 1); ++b) {
-                double my;
-                if (b != a) my = hy / 6.0;
-                else my = (a == 0 || a == ny - 1) ? hy / 3.0 : 2.0 * hy / 3.0;
-                double2 x = u[(long)ip * ny + b];
-                mu.x += mx * my * x.x;
-                mu.y += mx * my * x.y;
-            }
-        }
-        double2 x = u[(long)gl * ny + a];
-        acc += x.x * mu.x + x.y * mu.y;   // Re(conj(x) * mu)
-    }
-    __shared__ double red[256];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[gl] = red[0];
+    mass_line(P, u, part, blockIdx.x);
 }
 
 // Deterministic sum of n strided values (one block).
 __global__ void sum_kernel(const double *part, int n, int stride, double *out) {
-    __shared__ double red[256];
-    for (int c = 0; c < stride; ++c) {
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[(long)i * stride + c];
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[c] = red[0];
-        __syncthreads();
-    }
+    sum_block(part, n, stride, out);
 }
 
 // W_n = (V_t(t1) + V_t(t0))/2 with V_t(t, x~) = V(A(t) x~),
@@ -342,7 +138,54 @@ __global__ void check_finite_kernel(const double2 *x, long n, int *flag) {
     if (bad) atomicOr(flag, 1);
 }
 
+// Largest |b| over one strip (one block per strip), returned as the power
+// of two that maps it into [1, 2).
+__device__ __forceinline__ void strip_scale_body(const double2 *b, long count, double *out) {
+    double m = 0.0;
+    for (long e = threadIdx.x; e < count; e += blockDim.x) {
+        double2 v = b[e];
+        m = fmax(m, fmax(fabs(v.x), fabs(v.y)));
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double mx = red[0];
+        *out = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ilogb(mx)) : 1.0;
+    }
+}
+
+__global__ void strip_scale_kernel(Phys P, const StripMeta *strips, const double2 *b,
+                                   double *scale, const StepCtl *c) {
+    if (c && fp_idle(c)) return;
+    StripMeta s = strips[blockIdx.x];
+    strip_scale_body(b + (long)s.off * P.ny, (long)s.nx * P.ny, scale + blockIdx.x);
+}
+
+__global__ void b_strip_scale_kernel(const BStrip *strips, double *scale, int guard) {
+    const BStrip &s = strips[blockIdx.x];
+    if (guard && s.ctl && fp_idle(s.ctl)) return;
+    strip_scale_body(s.b, (long)s.nx * s.n, scale + blockIdx.x);
+}
+
 }  // namespace
+
+hipError_t launch_strip_scale(hipStream_t st, const Phys &P, const StripMeta *strips,
+                              const double2 *b, double *scale, const StepCtl *c) {
+    hipLaunchKernelGGL(strip_scale_kernel, dim3(P.nsub), dim3(256), 0, st, P, strips, b, scale, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_strip_scale(hipStream_t st, const BStrip *strips, int nstrips,
+                                double *scale, int guard) {
+    hipLaunchKernelGGL(b_strip_scale_kernel, dim3(nstrips), dim3(256), 0, st, strips, scale,
+                       guard);
+    return hipGetLastError();
+}
 
 static inline dim3 node_grid(int ny, int lines) { return dim3((ny + 255) / 256, lines); }
 

@@ -15,7 +15,7 @@
 // counter barrier: stores drained, one agent-scope release by the arriving
 // wave, relaxed polling with backoff, one acquire after the wait.  The wait
 // is bounded and sets an error flag, so no wave can spin forever.
-#include "osm_internal.h"
+#include "step_bodies.h"
 
 namespace {
 
@@ -78,7 +78,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 template <typename T, int RU, int UN>
 __device__ __forceinline__ void wg_gemv(const typename cplx_of<T>::type *__restrict__ M, int n,
                                         int r0, int r1, const typename cplx_of<T>::type *vec,
-                                        double2 *__restrict__ x, int mode) {
+                                        double2 *__restrict__ x, int mode, double inv) {
     typedef typename cplx_of<T>::type T2;
     typedef typename acc_t<T>::type A;
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -115,10 +115,10 @@ __device__ __forceinline__ void wg_gemv(const typename cplx_of<T>::type *__restr
             A si = wave_sum(ai[u]);
             int r = rb + 4 * u;
             if (lane == 0 && r < r1) {
-                if (mode == 0) x[r] = cd((double)sr, (double)si);
+                if (mode == 0) x[r] = cd((double)sr * inv, (double)si * inv);
                 else {
                     double2 o = x[r];
-                    x[r] = cd(o.x - (double)sr, o.y - (double)si);
+                    x[r] = cd(o.x - (double)sr * inv, o.y - (double)si * inv);
                 }
             }
         }
@@ -152,6 +152,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void strip_solve_kernel(SolveArgs a)
     unsigned *ctr = a.counters + j;
     unsigned epoch = 0;
     const long nn = (long)n * n;
+    const double sc = a.scale ? a.scale[j] : 1.0, inv = 1.0 / sc;
     // forward sweep
     for (int i = 0; i < s.nx; ++i) {
         long L = s.off + i;
@@ -163,11 +164,11 @@ __global__ __launch_bounds__(SOLVE_THREADS) void strip_solve_kernel(SolveArgs a)
                     wv = csub(wv, cmul(u, a.x[(L - 1) * n + q]));
                 }
             }
-            T2 t; t.x = (T)wv.x; t.y = (T)wv.y;
+            T2 t; t.x = (T)(wv.x * sc); t.y = (T)(wv.y * sc);
             vec[r] = t;
         }
         __syncthreads();
-        wg_gemv<T, RU, UN>(F + L * nn, n, r0, r1, vec, a.x + L * n, 0);
+        wg_gemv<T, RU, UN>(F + L * nn, n, r0, r1, vec, a.x + L * n, 0, inv);
         team_barrier(ctr, (++epoch) * team, a.error);
         if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     }
@@ -180,11 +181,11 @@ __global__ __launch_bounds__(SOLVE_THREADS) void strip_solve_kernel(SolveArgs a)
                 double2 u = a.Uc[(L * n + r) * 3 + (q - r + 1)];             // U_i(r, q)
                 zv = cadd(zv, cmul(u, a.x[(L + 1) * n + q]));
             }
-            T2 t; t.x = (T)zv.x; t.y = (T)zv.y;
+            T2 t; t.x = (T)(zv.x * sc); t.y = (T)(zv.y * sc);
             vec[r] = t;
         }
         __syncthreads();
-        wg_gemv<T, RU, UN>(F + L * nn, n, r0, r1, vec, a.x + L * n, 1);
+        wg_gemv<T, RU, UN>(F + L * nn, n, r0, r1, vec, a.x + L * n, 1, inv);
         if (i > 0) {
             team_barrier(ctr, (++epoch) * team, a.error);
             if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
@@ -217,6 +218,7 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
     unsigned *ctr = a.counters + j;
     const long nn = (long)n * n;
     const int S = 2 * s.nx - 1;   // forward products i = 0..nx-1, then backward i = nx-2..0
+    const double sc = a.scale ? a.scale[j] : 1.0, inv = 1.0 / sc;
     T2 m[PR][NCH];
 
     auto line_of = [&](int k) -> long { return s.off + (k < s.nx ? k : 2 * s.nx - 2 - k); };
@@ -238,10 +240,10 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
         ai = wave_sum(ai);
         if (lane == 0 && r < r1) {
             double2 *xr = a.x + L * n + r;
-            if (fwd) st_agent(xr, cd((double)ar, (double)ai));
+            if (fwd) st_agent(xr, cd((double)ar * inv, (double)ai * inv));
             else {
                 double2 o = ld_agent(xr);
-                st_agent(xr, cd(o.x - (double)ar, o.y - (double)ai));
+                st_agent(xr, cd(o.x - (double)ar * inv, o.y - (double)ai * inv));
             }
         }
     };
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) acc = cadd(acc, cmul(cu[d], xv[d]));
             }
-            T2 t; t.x = (T)acc.x; t.y = (T)acc.y;
+            T2 t; t.x = (T)(acc.x * sc); t.y = (T)(acc.y * sc);
             vec[r] = t;
         }
         __syncthreads();
@@ -353,6 +355,155 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
     }
 }
 
+// Batched solve over many strips of different widths and instances.  A
+// persistent grid takes work items from a queue (one atomic per item); an
+// item is one member of the team of workgroups that solves one strip, the
+// members of a strip being consecutive items, and the items of multi-member
+// strips coming first so that every team is complete among the first
+// workgroups to start.  A member owns the rows [r0, r1) of every product of
+// its strip; wave w streams rows r0 + w, r0 + w + NW, ..., RU rows and UN
+// column chunks of 64 in flight at a time.  Teams of one synchronise with the
+// workgroup barrier only; larger teams add the strip's counter barrier with
+// device-coherent row exchange and a bounded wait.
+template <typename T, int NW, int RU, int UN>
+__global__ __launch_bounds__(NW * 64) void batch_solve_kernel(BatchSolveArgs a) {
+    typedef typename cplx_of<T>::type T2;
+    typedef typename acc_t<T>::type A;
+    extern __shared__ unsigned char smem_raw[];
+    T2 *vec = reinterpret_cast<T2 *>(smem_raw);
+    __shared__ int item_sh, err_sh;
+    constexpr int NTHR = NW * 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned *queue = a.counters + a.nstrips;
+    while (true) {
+        if (threadIdx.x == 0) {
+            int e = __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            item_sh = e ? a.nitems : (int)atomicAdd(queue, 1u);
+        }
+        __syncthreads();
+        const int it = item_sh;
+        __syncthreads();
+        if (it >= a.nitems) return;
+        const BItem I = a.items[it];
+        const BStrip s = a.strips[I.strip];
+        if (a.guard && s.ctl && fp_idle(s.ctl)) continue;
+        if (a.ran && threadIdx.x == 0) *a.ran = 1;
+        const int n = s.n, nx = s.nx, team = I.team;
+        const int rpw = (n + team - 1) / team;
+        const int r0 = min(n, I.member * rpw), r1 = min(n, r0 + rpw);
+        const T2 *F = reinterpret_cast<const T2 *>(s.F);
+        const long nn = (long)n * n;
+        unsigned *ctr = a.counters + I.strip;
+        const double sc = s.scale ? *s.scale : 1.0, inv = 1.0 / sc;
+        const int S = 2 * nx - 1;   // forward products i = 0..nx-1, then backward i = nx-2..0
+        for (int k = 0; k < S; ++k) {
+            const bool fwd = k < nx;
+            const int i = fwd ? k : 2 * nx - 2 - k;
+            // vector phase: b_i - U_{i-1}^T x_{i-1} (forward) or U_i x_{i+1} (backward)
+            for (int r = threadIdx.x; r < n; r += NTHR) {
+                double2 acc = cd(0.0, 0.0);
+                double2 cu[3], xv[3];
+                if (fwd) {
+                    acc = s.b[(long)i * n + r];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        int q = r - 1 + d;
+                        bool ok = i > 0 && q >= 0 && q < n;
+                        cu[d] = ok ? s.Uc[((long)(i - 1) * n + q) * 3 + (2 - d)] : cd(0.0, 0.0);
+                        xv[d] = ok ? ld_agent(s.x + (long)(i - 1) * n + q) : cd(0.0, 0.0);
+                    }
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) acc = csub(acc, cmul(cu[d], xv[d]));
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        int q = r - 1 + d;
+                        bool ok = q >= 0 && q < n;
+                        cu[d] = ok ? s.Uc[((long)i * n + r) * 3 + d] : cd(0.0, 0.0);
+                        xv[d] = ok ? ld_agent(s.x + (long)(i + 1) * n + q) : cd(0.0, 0.0);
+                    }
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) acc = cadd(acc, cmul(cu[d], xv[d]));
+                }
+                T2 t; t.x = (T)(acc.x * sc); t.y = (T)(acc.y * sc);
+                vec[r] = t;
+            }
+            __syncthreads();
+            const T2 *M = F + (long)i * nn;
+            for (int rb = r0 + wave; rb < r1; rb += NW * RU) {
+                A ar[RU], ai[RU];
+#pragma unroll
+                for (int u = 0; u < RU; ++u) { ar[u] = 0; ai[u] = 0; }
+                for (int c0 = 0; c0 < n; c0 += 64 * UN) {
+                    T2 m[RU][UN];
+#pragma unroll
+                    for (int u = 0; u < RU; ++u)
+#pragma unroll
+                        for (int kk = 0; kk < UN; ++kk) {
+                            int r = rb + NW * u, c = c0 + lane + 64 * kk;
+                            if (r < r1 && c < n) m[u][kk] = M[(long)r * n + c];
+                            else { m[u][kk].x = 0; m[u][kk].y = 0; }
+                        }
+#pragma unroll
+                    for (int kk = 0; kk < UN; ++kk) {
+                        int c = c0 + lane + 64 * kk;
+                        T2 v;
+                        if (c < n) v = vec[c];
+                        else { v.x = 0; v.y = 0; }
+#pragma unroll
+                        for (int u = 0; u < RU; ++u) {
+                            ar[u] += m[u][kk].x * v.x - m[u][kk].y * v.y;
+                            ai[u] += m[u][kk].x * v.y + m[u][kk].y * v.x;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    A sr = wave_sum(ar[u]);
+                    A si = wave_sum(ai[u]);
+                    int r = rb + NW * u;
+                    if (lane == 0 && r < r1) {
+                        double2 *xr = s.x + (long)i * n + r;
+                        if (fwd) st_agent(xr, cd((double)sr * inv, (double)si * inv));
+                        else {
+                            double2 o = ld_agent(xr);
+                            st_agent(xr, cd(o.x - (double)sr * inv, o.y - (double)si * inv));
+                        }
+                    }
+                }
+            }
+            if (k == S - 1) break;
+            // publish this product: stores acknowledged, workgroup barrier,
+            // and for a team the strip counter
+            __builtin_amdgcn_s_waitcnt(0);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __syncthreads();
+            if (team > 1) {
+                if (threadIdx.x == 0) {
+                    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const unsigned target = (unsigned)(k + 1) * team;
+                    unsigned spins = 0;
+                    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                           target) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (++spins > SPIN_LIMIT ||
+                            __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                    }
+                    err_sh = __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __syncthreads();
+                if (err_sh) return;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void zero_u32_kernel(unsigned *p, int n, int *err, int *ran) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -411,6 +562,66 @@ hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipE
     dim3 grid(a.nstrips * a.team), block(v.threads);
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     e = hipLaunchCooperativeKernel(v.fn, grid, block, params, (unsigned)smem, st);
+    if (e != hipSuccess) return e;
+    if (ev1) e = hipEventRecord(ev1, st);
+    return e;
+}
+
+// ---------------------------------------------------------------- batched solve
+namespace {
+
+struct BVariant {
+    const void *fn;
+    int threads;
+    const char *name;
+};
+
+BVariant batch_variant(int fp32, int v) {
+    if (fp32) {
+        switch (v) {
+        case 0: return {(const void *)batch_solve_kernel<float, 8, 2, 8>, 512, "c32 8w ru2 un8"};
+        case 1: return {(const void *)batch_solve_kernel<float, 8, 4, 8>, 512, "c32 8w ru4 un8"};
+        case 2: return {(const void *)batch_solve_kernel<float, 4, 4, 8>, 256, "c32 4w ru4 un8"};
+        default: return {(const void *)batch_solve_kernel<float, 16, 2, 8>, 1024, "c32 16w ru2 un8"};
+        }
+    }
+    switch (v) {
+    case 0: return {(const void *)batch_solve_kernel<double, 8, 2, 4>, 512, "c128 8w ru2 un4"};
+    case 1: return {(const void *)batch_solve_kernel<double, 8, 4, 4>, 512, "c128 8w ru4 un4"};
+    case 2: return {(const void *)batch_solve_kernel<double, 4, 4, 4>, 256, "c128 4w ru4 un4"};
+    default: return {(const void *)batch_solve_kernel<double, 16, 2, 4>, 1024, "c128 16w ru2 un4"};
+    }
+}
+
+}  // namespace
+
+int batch_solve_variants() { return 4; }
+
+const char *batch_solve_variant_name(int fp32, int variant) { return batch_variant(fp32, variant).name; }
+
+int batch_solve_max_resident_blocks(int fp32, int variant, int max_n) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    BVariant v = batch_variant(fp32, variant);
+    size_t smem = (size_t)max_n * (fp32 ? sizeof(float2) : sizeof(double2));
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, v.fn, v.threads, smem) != hipSuccess)
+        return 0;
+    return per * cus;
+}
+
+hipError_t launch_batch_solve(hipStream_t st, const BatchSolveArgs &a, int fp32, int variant,
+                              int grid, int max_n, hipEvent_t ev0, hipEvent_t ev1) {
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((a.nstrips + 1 + 255) / 256), dim3(256), 0, st,
+                       a.counters, a.nstrips + 1, a.error, a.ran);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    BVariant v = batch_variant(fp32, variant);
+    size_t smem = (size_t)max_n * (fp32 ? sizeof(float2) : sizeof(double2));
+    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
+    BatchSolveArgs args = a;
+    void *params[] = {&args};
+    e = hipLaunchKernel(v.fn, dim3(grid), dim3(v.threads), params, smem, st);
     if (e != hipSuccess) return e;
     if (ev1) e = hipEventRecord(ev1, st);
     return e;

@@ -50,6 +50,7 @@ struct osm_handle {
     double *mass_part = nullptr, *scal = nullptr;
     int *flag_d = nullptr;
     // solve
+    double *sscale = nullptr;        // per-strip right-hand-side scale (complex-FP32 factor)
     unsigned *counters = nullptr;
     int *err_d = nullptr;
     int team = 0;
@@ -81,6 +82,29 @@ struct osm_handle {
     bool team_tuned = false;
     std::string err;
     std::vector<void *> allocs;
+    // batch of independent instances (osm_setup_batch): per-instance handles
+    // own the buffers; this handle owns the instance table, the work items of
+    // the batched solve and the captured graph of a chunk of iterations
+    std::vector<osm_handle *> sub;
+    std::vector<InstDesc> tab_h;
+    InstDesc *tab_d = nullptr;
+    BatchDims bd;
+    std::vector<BStrip> bstrips_h;
+    BStrip *bstrips_d = nullptr;
+    BItem *bitems_d = nullptr;
+    int nitems = 0, max_n = 0, nstrips_all = 0;
+    unsigned *bcounters = nullptr;
+    int *bflags = nullptr;
+    double *bscal = nullptr;
+    double *bscale = nullptr;        // per-strip right-hand-side scale of the batched solve
+    int bvariant = 0, bgrid = 0;
+    double balpha = 0.0;
+    bool btuned = false;
+    hipStream_t cap_st = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int chunk_k = 4, chunk_q = 3;
+    std::vector<StepCtl> ctl_h;
 };
 
 namespace {
@@ -92,6 +116,12 @@ osm_status fail(osm_handle *h, osm_status s, const std::string &msg) {
     else g_setup_error = msg;
     return s;
 }
+
+#define SINGLE_ONLY(h)                                                                      \
+    do {                                                                                    \
+        if (!(h)->sub.empty())                                                              \
+            return fail(h, OSM_ESTATE, "batch handle: use the *_batch entry points");       \
+    } while (0)
 
 #define HIPCHK(h, call)                                                                     \
     do {                                                                                    \
@@ -173,7 +203,7 @@ uint64_t device_bytes(const Sizes &s) {
     b += 3ull * s.Lt * s.n * 16;                        // zeta, res, delta
     b += 5ull * s.ng * 16;                              // interface vectors
     b += 2ull * s.N * GJ_BK * s.n * fe;                 // GJ panels
-    b += (uint64_t)(3 * s.Lt + 3 * s.N + 2 * 2 * s.N + s.nglob + 64) * 8;
+    b += (uint64_t)(3 * s.Lt + 4 * s.N + 2 * 2 * s.N + s.nglob + 64) * 8;
     if (s.m > 0) {
         b += 4ull * s.ncls * s.n * s.n * 16;            // L_h blocks
         b += (uint64_t)(s.m + 2) * s.ng * 16;           // Krylov basis
@@ -279,6 +309,11 @@ osm_status do_solve(osm_handle *h, const double2 *b, double2 *x, const StepCtl *
     a.error = h->err_d;
     a.ctl = ctl;
     a.ran = nullptr;
+    a.scale = nullptr;
+    if (h->fp32) {
+        HIPCHK(h, launch_strip_scale(h->st, h->P, h->strips_d, b, h->sscale, ctl));
+        a.scale = h->sscale;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->prof) {
         if (h->prof_used == PROF_SLOTS) {
@@ -669,14 +704,8 @@ osm_status osm_query(const osm_problem *prob, const osm_options *opt, osm_footpr
     return OSM_OK;
 }
 
-osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_stream,
-                     osm_handle **out) {
-    if (!out) return OSM_EINVAL;
-    *out = nullptr;
-    std::string v = validate(prob, opt);
-    if (!v.empty()) return fail(nullptr, OSM_EINVAL, v);
-    Sizes sz = sizes_of(prob, opt);
-    uint64_t need = device_bytes(sz);
+// Device bytes available to a setup: free memory, or the caller's cap.
+static osm_status available_bytes(const osm_options *opt, uint64_t *cap) {
     size_t freeb = 0, totalb = 0;
     if (opt->mem_cap == 0 || opt->mem_cap > (uint64_t)1 << 62) {
         if (hipMemGetInfo(&freeb, &totalb) != hipSuccess)
@@ -684,17 +713,21 @@ osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_
     } else {
         freeb = (size_t)opt->mem_cap;
     }
-    uint64_t cap = opt->mem_cap ? std::min<uint64_t>(opt->mem_cap, freeb) : freeb;
-    if (need > cap)
-        return fail(nullptr, OSM_ENOMEM, "footprint " + std::to_string(need) +
-                                             " B exceeds available " + std::to_string(cap) + " B");
+    *cap = opt->mem_cap ? std::min<uint64_t>(opt->mem_cap, freeb) : freeb;
+    return OSM_OK;
+}
 
+// Allocates and initialises one instance (problem and options validated,
+// footprint already checked by the caller).
+static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hipStream_t stream,
+                            osm_handle **out) {
+    Sizes sz = sizes_of(prob, opt);
     osm_handle *h = new osm_handle();
     h->prob = *prob;
     h->prob.strip_cells = nullptr;
     h->opt = *opt;
     h->cells = strip_cells_of(prob);
-    h->st = (hipStream_t)hip_stream;
+    h->st = stream;
     hipGetDevice(&h->device);
     h->n = (int)sz.n; h->N = (int)sz.N; h->Lt = (int)sz.Lt; h->nglob = (int)sz.nglob;
     h->ng = (int)sz.ng; h->maxnx = (int)sz.maxnx; h->fp32 = sz.fp32; h->m = (int)sz.m;
@@ -780,6 +813,7 @@ osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_
         SALLOC(h->scal, double, 8);
         SALLOC(h->flag_d, int, 1);
         SALLOC(h->counters, unsigned, h->N);
+        SALLOC(h->sscale, double, h->N);
         SALLOC(h->err_d, int, 1);
         SALLOC(h->ran_d, int, PROF_SLOTS);
         SALLOC(h->sctl, StepCtl, 1);
@@ -839,6 +873,21 @@ osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_
     return OSM_OK;
 }
 
+osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_stream,
+                     osm_handle **out) {
+    if (!out) return OSM_EINVAL;
+    *out = nullptr;
+    std::string v = validate(prob, opt);
+    if (!v.empty()) return fail(nullptr, OSM_EINVAL, v);
+    uint64_t need = device_bytes(sizes_of(prob, opt)), cap = 0;
+    osm_status s = available_bytes(opt, &cap);
+    if (s != OSM_OK) return s;
+    if (need > cap)
+        return fail(nullptr, OSM_ENOMEM, "footprint " + std::to_string(need) +
+                                             " B exceeds available " + std::to_string(cap) + " B");
+    return setup_one(prob, opt, (hipStream_t)hip_stream, out);
+}
+
 // Autotuner of the strip solve: workgroups per strip trade barrier cost
 // against memory-level parallelism, so time a few solves with every feasible
 // team size once, after the first factorisation, and keep the fastest.
@@ -880,6 +929,7 @@ static osm_status autotune_team(osm_handle *h) {
 
 osm_status osm_factor(osm_handle *h, const double *W_dev) {
     if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
     if (!W_dev) return fail(h, OSM_EINVAL, "W_dev is NULL");
     HIPCHK(h, hipMemcpyAsync(h->W_d, W_dev, sizeof(double) * (size_t)h->nglob * h->n,
                              hipMemcpyDeviceToDevice, h->st));
@@ -893,6 +943,7 @@ osm_status osm_factor(osm_handle *h, const double *W_dev) {
 
 osm_status osm_factor_rotating(osm_handle *h, int32_t n) {
     if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
     if (n < 1) return fail(h, OSM_EINVAL, "step index must be >= 1");
     double t1 = n * h->prob.dt, t0 = (n - 1) * h->prob.dt;
     HIPCHK(h, launch_rotating_W(h->st, h->P, h->prob.xl, h->prob.yb, h->prob.omega, h->prob.vxx,
@@ -915,6 +966,7 @@ static osm_status mass_of(osm_handle *h, const double2 *u, double *out) {
 
 osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats) {
     if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
     if (!u_dev) return fail(h, OSM_EINVAL, "u_dev is NULL");
     if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called before osm_step");
     const osm_options &o = h->opt;
@@ -950,6 +1002,7 @@ osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats) {
 osm_status osm_interface_apply(osm_handle *h, osm_iface_op op, const osm_c64 *u_dev,
                                const osm_c64 *g_in_dev, osm_c64 *g_out_dev) {
     if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
     if (!g_in_dev || !g_out_dev) return fail(h, OSM_EINVAL, "null interface vector");
     const double2 *gi = (const double2 *)g_in_dev;
     double2 *go = (double2 *)g_out_dev;
@@ -984,6 +1037,7 @@ osm_status osm_interface_apply(osm_handle *h, osm_iface_op op, const osm_c64 *u_
 
 osm_status osm_set_interface_guess(osm_handle *h, const osm_c64 *g0_dev) {
     if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
     if (!g0_dev) return fail(h, OSM_EINVAL, "g0_dev is NULL");
     HIPCHK(h, hipMemcpyAsync(h->gguess, g0_dev, sizeof(double2) * h->ng, hipMemcpyDeviceToDevice, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
@@ -993,6 +1047,7 @@ osm_status osm_set_interface_guess(osm_handle *h, const osm_c64 *g0_dev) {
 
 osm_status osm_get_interface(osm_handle *h, osm_c64 *g_dev) {
     if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
     if (!g_dev) return fail(h, OSM_EINVAL, "g_dev is NULL");
     HIPCHK(h, hipMemcpyAsync(g_dev, h->g, sizeof(double2) * h->ng, hipMemcpyDeviceToDevice, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
@@ -1001,6 +1056,7 @@ osm_status osm_get_interface(osm_handle *h, osm_c64 *g_dev) {
 
 osm_status osm_strip_solve(osm_handle *h, const osm_c64 *b_dev, osm_c64 *x_dev) {
     if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
     if (!b_dev || !x_dev) return fail(h, OSM_EINVAL, "null vector");
     if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called first");
     osm_status s = do_solve(h, (const double2 *)b_dev, (double2 *)x_dev);
@@ -1010,6 +1066,7 @@ osm_status osm_strip_solve(osm_handle *h, const osm_c64 *b_dev, osm_c64 *x_dev) 
 
 osm_status osm_get_strip_solution(osm_handle *h, osm_c64 *v_dev) {
     if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
     if (!v_dev) return fail(h, OSM_EINVAL, "v_dev is NULL");
     HIPCHK(h, hipMemcpyAsync(v_dev, h->zeta, sizeof(double2) * (size_t)h->Lt * h->n,
                              hipMemcpyDeviceToDevice, h->st));
@@ -1019,6 +1076,7 @@ osm_status osm_get_strip_solution(osm_handle *h, osm_c64 *v_dev) {
 
 osm_status osm_get_lh_blocks(osm_handle *h, osm_c64 *blocks_dev) {
     if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
     if (!blocks_dev) return fail(h, OSM_EINVAL, "blocks_dev is NULL");
     if (h->opt.algo != OSM_PRECOND) return fail(h, OSM_ESTATE, "L_h is built only for OSM_PRECOND");
     long nn = (long)h->n * h->n;
@@ -1039,6 +1097,7 @@ osm_status osm_get_lh_blocks(osm_handle *h, osm_c64 *blocks_dev) {
 
 osm_status osm_get_factor(osm_handle *h, void *dst_dev) {
     if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
     if (!dst_dev) return fail(h, OSM_EINVAL, "dst_dev is NULL");
     if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called first");
     size_t fe = h->fp32 ? sizeof(float2) : sizeof(double2);
@@ -1066,10 +1125,483 @@ osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
 
 int32_t osm_solve_team(const osm_handle *h) { return h ? h->team : 0; }
 
+// ====================================================================== batch
+// Independent instances solved together: every time-step kernel covers all
+// instances in one launch, the strip solve takes the strips of all
+// instances from one work queue, and a chunk of Schwarz iterations is
+// captured once as a HIP graph and replayed until every instance has met
+// its stopping test.
+
+static uint64_t batch_table_bytes(long nb, long nstrips) {
+    return (uint64_t)nb * (sizeof(InstDesc) + 2 * sizeof(double) + sizeof(int)) +
+           (uint64_t)nstrips * (sizeof(BStrip) + 4 * sizeof(BItem) + sizeof(unsigned)) + 4096;
+}
+
+static std::string validate_batch(const osm_problem *probs, int32_t nb, const osm_options *opt) {
+    if (!probs || !opt) return "null problems or options";
+    if (nb < 1) return "nb must be >= 1";
+    if (opt->algo != OSM_CLASSICAL) return "batched instances run the classical algorithm";
+    for (int b = 0; b < nb; ++b) {
+        std::string v = validate(&probs[b], opt);
+        if (!v.empty()) return "instance " + std::to_string(b) + ": " + v;
+    }
+    return "";
+}
+
+osm_status osm_query_batch(const osm_problem *probs, int32_t nb, const osm_options *opt,
+                           osm_footprint *out) {
+    if (!out) return fail(nullptr, OSM_EINVAL, "out is NULL");
+    std::string v = validate_batch(probs, nb, opt);
+    if (!v.empty()) return fail(nullptr, opt && opt->algo != OSM_CLASSICAL && probs && nb >= 1
+                                             ? OSM_EUNSUPPORTED : OSM_EINVAL, v);
+    uint64_t dev = 0, host = 0;
+    long nst = 0;
+    for (int b = 0; b < nb; ++b) {
+        osm_footprint f;
+        osm_status s = osm_query(&probs[b], opt, &f);
+        if (s != OSM_OK) return s;
+        dev += f.device_bytes;
+        host += f.host_bytes;
+        nst += probs[b].nsub;
+    }
+    out->device_bytes = dev + batch_table_bytes(nb, nst);
+    out->host_bytes = host + (uint64_t)nb * (sizeof(InstDesc) + sizeof(StepCtl)) +
+                      (uint64_t)nst * sizeof(BStrip);
+    return OSM_OK;
+}
+
+// Work items of the batched solve for a team rule: a strip whose cost
+// (products x ny^2) exceeds alpha times the mean cost per workgroup gets
+// ceil(cost / (alpha mean)) members (at most 16, and together at most half
+// the grid); alpha <= 0 gives every strip one workgroup.  Multi-member
+// strips come first, then single strips, each by decreasing cost per member.
+static std::vector<BItem> make_items(const osm_handle *h, double alpha, int grid) {
+    int ns = (int)h->bstrips_h.size();
+    std::vector<double> cost(ns);
+    double tot = 0.0;
+    for (int i = 0; i < ns; ++i) {
+        const BStrip &s = h->bstrips_h[i];
+        cost[i] = (2.0 * s.nx - 1.0) * (double)s.n * s.n;
+        tot += cost[i];
+    }
+    double unit = alpha > 0 ? alpha * tot / std::max(grid, 1) : 0.0;
+    std::vector<int> team(ns, 1);
+    int budget = grid / 2, used = 0;
+    std::vector<int> order(ns);
+    for (int i = 0; i < ns; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    if (unit > 0) {
+        for (int i : order) {
+            int t = (int)ceil(cost[i] / unit);
+            t = std::max(1, std::min(t, std::min(16, std::max(1, h->bstrips_h[i].n / 32))));
+            if (t > 1 && used + t > budget) t = 1;
+            if (t > 1) used += t;
+            team[i] = t;
+        }
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        bool ma = team[a] > 1, mb = team[b] > 1;
+        if (ma != mb) return ma;
+        return cost[a] / team[a] > cost[b] / team[b];
+    });
+    std::vector<BItem> items;
+    for (int i : order)
+        for (int m = 0; m < team[i]; ++m) items.push_back(BItem{i, m, team[i], 0});
+    return items;
+}
+
+static osm_status batch_solve(osm_handle *h, int guard, hipStream_t st, hipEvent_t e0,
+                              hipEvent_t e1, int *ran) {
+    BatchSolveArgs a;
+    a.strips = h->bstrips_d;
+    a.items = h->bitems_d;
+    a.nitems = h->nitems;
+    a.nstrips = h->nstrips_all;
+    a.counters = h->bcounters;
+    a.error = h->err_d;
+    a.ran = ran;
+    a.guard = guard;
+    if (h->fp32) HIPCHK(h, launch_b_strip_scale(st, h->bstrips_d, h->nstrips_all, h->bscale, guard));
+    HIPCHK(h, launch_batch_solve(st, a, h->fp32, h->bvariant, h->bgrid, h->max_n, e0, e1));
+    return OSM_OK;
+}
+
+static osm_status set_items(osm_handle *h, double alpha, int variant) {
+    int cap = batch_solve_max_resident_blocks(h->fp32, variant, h->max_n);
+    if (cap <= 0) return fail(h, OSM_EHIP, "occupancy query of the batched solve failed");
+    std::vector<BItem> items = make_items(h, alpha, cap);
+    if ((int)items.size() > h->nstrips_all * 16)
+        return fail(h, OSM_EINVAL, "work items exceed their buffer");
+    HIPCHK(h, hipMemcpy(h->bitems_d, items.data(), sizeof(BItem) * items.size(),
+                        hipMemcpyHostToDevice));
+    h->nitems = (int)items.size();
+    h->bvariant = variant;
+    h->balpha = alpha;
+    h->bgrid = std::min(cap, h->nitems);
+    int maxteam = 1;
+    for (const BItem &it : items) maxteam = std::max(maxteam, it.team);
+    if (maxteam > h->bgrid) return fail(h, OSM_EINVAL, "team larger than the resident grid");
+    return OSM_OK;
+}
+
+// Autotuner of the batched solve: tile shape (waves per workgroup, rows and
+// column chunks in flight) x team rule, each timed over two solves of the
+// whole batch after the first factorisation; the fastest is kept.
+static osm_status batch_autotune(osm_handle *h) {
+    if (h->btuned) return OSM_OK;
+    static const double alphas[] = {0.0, 1.0, 2.0, 4.0};
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    for (osm_handle *u : h->sub)
+        HIPCHK(h, hipMemsetAsync(u->res, 0, sizeof(double2) * (size_t)u->Lt * u->n, h->st));
+    double best = 1e300;
+    int bv = 0;
+    double ba = 0.0;
+    osm_status s = OSM_OK;
+    for (int v = 0; v < batch_solve_variants() && s == OSM_OK; ++v) {
+        for (double al : alphas) {
+            if ((s = set_items(h, al, v)) != OSM_OK) break;
+            if ((s = batch_solve(h, 0, h->st, nullptr, nullptr, nullptr)) != OSM_OK) break;
+            float tot = 0.f;
+            for (int r = 0; r < 2 && s == OSM_OK; ++r) {
+                if ((s = batch_solve(h, 0, h->st, e0, e1, nullptr)) != OSM_OK) break;
+                hipError_t e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) s = fail(h, OSM_EHIP, hipGetErrorString(e));
+                tot += ms;
+            }
+            if (s != OSM_OK) break;
+            int err = 0;
+            HIPCHK(h, hipMemcpy(&err, h->err_d, sizeof(int), hipMemcpyDeviceToHost));
+            if (err) { s = fail(h, OSM_EHIP, "batched solve: barrier wait timed out"); break; }
+            if (tot < best) { best = tot; bv = v; ba = al; }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (s != OSM_OK) return s;
+    s = set_items(h, ba, bv);
+    if (s != OSM_OK) return s;
+    h->btuned = true;
+    return OSM_OK;
+}
+
+static StepCfg batch_cfg(const osm_options &o) {
+    StepCfg cfg;
+    cfg.tol_q = o.tol_q;
+    cfg.eta_q = 0.0;
+    cfg.tol_k = o.tol_k;
+    cfg.tol_k_rel = o.tol_k_relative;
+    cfg.fixed_q = o.fixed_q;
+    cfg.max_q = o.max_q;
+    cfg.fixed_k = o.fixed_k;
+    cfg.classical = 1;
+    return cfg;
+}
+
+// One chunk: chunk_k Schwarz-iteration slots of chunk_q fixed-point
+// iterations each, every launch guarded per instance.
+static osm_status batch_chunk(osm_handle *h, hipStream_t st, bool timed) {
+    const BatchDims &d = h->bd;
+    for (int it = 0; it < h->chunk_k; ++it) {
+        HIPCHK(h, launch_b_iter_reset(st, h->tab_d, d));
+        if (!h->opt.warm_start) HIPCHK(h, launch_b_copy_u(st, h->tab_d, d, 1));
+        for (int q = 0; q < h->chunk_q; ++q) {
+            HIPCHK(h, launch_b_residual(st, h->tab_d, d));
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            int *ran = nullptr;
+            if (timed) {
+                if (h->prof_used == PROF_SLOTS) {
+                    HIPCHK(h, hipStreamSynchronize(st));
+                    osm_status s = prof_collect(h);
+                    if (s != OSM_OK) return s;
+                }
+                int slot = h->prof_used++;
+                if ((int)h->evs.size() < 2 * (slot + 1)) {
+                    hipEvent_t a0, a1;
+                    HIPCHK(h, hipEventCreate(&a0));
+                    HIPCHK(h, hipEventCreate(&a1));
+                    h->evs.push_back(a0);
+                    h->evs.push_back(a1);
+                }
+                e0 = h->evs[2 * slot];
+                e1 = h->evs[2 * slot + 1];
+                ran = h->ran_d + slot;
+            }
+            osm_status s = batch_solve(h, 1, st, e0, e1, ran);
+            if (s != OSM_OK) return s;
+            HIPCHK(h, launch_b_update_norms(st, h->tab_d, d));
+            HIPCHK(h, launch_b_q_check(st, h->tab_d, d));
+        }
+        HIPCHK(h, launch_b_flux(st, h->tab_d, d));
+        HIPCHK(h, launch_b_commit(st, h->tab_d, d));
+    }
+    return OSM_OK;
+}
+
+static osm_status batch_capture(osm_handle *h) {
+    if (h->gexec) return OSM_OK;
+    if (!h->cap_st) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_st, hipStreamNonBlocking));
+    HIPCHK(h, hipStreamBeginCapture(h->cap_st, hipStreamCaptureModeThreadLocal));
+    osm_status s = batch_chunk(h, h->cap_st, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_st, &g);
+    if (s != OSM_OK) {
+        if (g) hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess) return fail(h, OSM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    h->graph = g;
+    HIPCHK(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    return OSM_OK;
+}
+
+osm_status osm_setup_batch(const osm_problem *probs, int32_t nb, const osm_options *opt,
+                           void *hip_stream, osm_handle **out) {
+    if (!out) return OSM_EINVAL;
+    *out = nullptr;
+    osm_footprint fp;
+    osm_status s = osm_query_batch(probs, nb, opt, &fp);
+    if (s != OSM_OK) return s;
+    uint64_t cap = 0;
+    if ((s = available_bytes(opt, &cap)) != OSM_OK) return s;
+    if (fp.device_bytes > cap)
+        return fail(nullptr, OSM_ENOMEM, "batch footprint " + std::to_string(fp.device_bytes) +
+                                             " B exceeds available " + std::to_string(cap) + " B");
+    osm_handle *h = new osm_handle();
+    h->opt = *opt;
+    h->prob = probs[0];
+    h->prob.strip_cells = nullptr;
+    h->st = (hipStream_t)hip_stream;
+    hipGetDevice(&h->device);
+    h->fp32 = opt->prec == OSM_C32_REFINE;
+    osm_options so = *opt;
+    so.team = 1;          // the instances' own solve is not used; skip its tuner
+    so.mem_cap = 0;
+    auto body = [&]() -> osm_status {
+        BatchDims &d = h->bd;
+        d.nb = nb;
+        d.max_ny = d.max_lt = d.max_nglob = d.max_ntr = 0;
+        d.max_ng = 0;
+        for (int b = 0; b < nb; ++b) {
+            osm_handle *u = nullptr;
+            osm_status r = setup_one(&probs[b], &so, h->st, &u);
+            if (r != OSM_OK) return fail(h, r, "instance " + std::to_string(b) + ": " + g_setup_error);
+            h->sub.push_back(u);
+            d.max_ny = std::max(d.max_ny, u->n);
+            d.max_lt = std::max(d.max_lt, u->Lt);
+            d.max_nglob = std::max(d.max_nglob, u->nglob);
+            d.max_ntr = std::max(d.max_ntr, 2 * (u->N - 1));
+            d.max_ng = std::max<long>(d.max_ng, u->ng);
+            h->max_n = std::max(h->max_n, u->n);
+            h->nstrips_all += u->N;
+        }
+        ALLOC(h, h->tab_d, InstDesc, nb);
+        ALLOC(h, h->bflags, int, nb);
+        ALLOC(h, h->bscal, double, 2 * nb);
+        ALLOC(h, h->bstrips_d, BStrip, h->nstrips_all);
+        ALLOC(h, h->bitems_d, BItem, 16 * h->nstrips_all);
+        ALLOC(h, h->bcounters, unsigned, h->nstrips_all + 1);
+        ALLOC(h, h->bscale, double, h->nstrips_all);
+        ALLOC(h, h->err_d, int, 1);
+        ALLOC(h, h->ran_d, int, PROF_SLOTS);
+        HIPCHK(h, hipMemset(h->err_d, 0, sizeof(int)));
+        size_t fe = h->fp32 ? sizeof(float2) : sizeof(double2);
+        for (int b = 0; b < nb; ++b) {
+            osm_handle *u = h->sub[b];
+            InstDesc I;
+            I.P = u->P;
+            I.strips = u->strips_d;
+            I.line_strip = u->line_strip_d;
+            I.gmap = u->gmap_d;
+            I.W = u->W_d;
+            I.u = nullptr;
+            I.zeta = u->zeta; I.res = u->res; I.delta = u->delta;
+            I.g = u->g; I.gn = u->gn;
+            I.line_part = u->line_part; I.trace_part = u->trace_part; I.mass_part = u->mass_part;
+            I.scal = h->bscal + 2 * b;
+            I.ctl = u->sctl;
+            I.flag = h->bflags + b;
+            h->tab_h.push_back(I);
+            long nn = (long)u->n * u->n;
+            for (int j = 0; j < u->N; ++j) {
+                const StripMeta &sm = u->strips_h[j];
+                BStrip bs;
+                bs.F = (const char *)u->F + (size_t)sm.off * nn * fe;
+                bs.Uc = u->Uc + (long)sm.off * u->n * 3;
+                bs.b = u->res + (long)sm.off * u->n;
+                bs.x = u->delta + (long)sm.off * u->n;
+                bs.ctl = u->sctl;
+                bs.scale = h->fp32 ? h->bscale + h->bstrips_h.size() : nullptr;
+                bs.n = u->n;
+                bs.nx = sm.nx;
+                h->bstrips_h.push_back(bs);
+            }
+        }
+        HIPCHK(h, hipMemcpy(h->tab_d, h->tab_h.data(), sizeof(InstDesc) * nb, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemcpy(h->bstrips_d, h->bstrips_h.data(), sizeof(BStrip) * h->nstrips_all,
+                            hipMemcpyHostToDevice));
+        std::vector<double> ones(h->nstrips_all, 1.0);
+        HIPCHK(h, hipMemcpy(h->bscale, ones.data(), sizeof(double) * h->nstrips_all,
+                            hipMemcpyHostToDevice));
+        h->ctl_h.resize(nb);
+        return set_items(h, 0.0, 0);
+    };
+    s = body();
+    if (s != OSM_OK) {
+        g_setup_error = h->err;
+        osm_destroy(h);
+        return s;
+    }
+    *out = h;
+    return OSM_OK;
+}
+
+osm_status osm_factor_batch(osm_handle *h, const double *const *W_devs) {
+    if (!h) return OSM_EINVAL;
+    if (h->sub.empty()) return fail(h, OSM_ESTATE, "not a batch handle (use osm_factor)");
+    if (!W_devs) return fail(h, OSM_EINVAL, "W_devs is NULL");
+    for (size_t b = 0; b < h->sub.size(); ++b)
+        if (!W_devs[b]) return fail(h, OSM_EINVAL, "W_devs[" + std::to_string(b) + "] is NULL");
+    for (size_t b = 0; b < h->sub.size(); ++b) {
+        osm_handle *u = h->sub[b];
+        HIPCHK(h, hipMemcpyAsync(u->W_d, W_devs[b], sizeof(double) * (size_t)u->nglob * u->n,
+                                 hipMemcpyDeviceToDevice, h->st));
+        osm_status s = do_factor(u);
+        if (s != OSM_OK) return fail(h, s, "instance " + std::to_string(b) + ": " + u->err);
+    }
+    osm_status s = batch_autotune(h);
+    if (s != OSM_OK) return s;
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    h->factored = true;
+    return OSM_OK;
+}
+
+osm_status osm_step_batch(osm_handle *h, osm_c64 *const *u_devs, osm_step_stats *stats) {
+    if (!h) return OSM_EINVAL;
+    if (h->sub.empty()) return fail(h, OSM_ESTATE, "not a batch handle (use osm_step)");
+    if (!u_devs) return fail(h, OSM_EINVAL, "u_devs is NULL");
+    int nb = (int)h->sub.size();
+    for (int b = 0; b < nb; ++b)
+        if (!u_devs[b]) return fail(h, OSM_EINVAL, "u_devs[" + std::to_string(b) + "] is NULL");
+    if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor_batch must be called before osm_step_batch");
+    const osm_options &o = h->opt;
+    bool changed = false;
+    for (int b = 0; b < nb; ++b) {
+        double2 *u = (double2 *)u_devs[b];
+        if (h->tab_h[b].u != u) { h->tab_h[b].u = u; changed = true; }
+    }
+    if (changed)
+        HIPCHK(h, hipMemcpy(h->tab_d, h->tab_h.data(), sizeof(InstDesc) * nb, hipMemcpyHostToDevice));
+    const BatchDims &d = h->bd;
+    // reject non-finite input
+    HIPCHK(h, launch_b_check_finite(h->st, h->tab_d, d));
+    std::vector<int> bad(nb);
+    HIPCHK(h, hipMemcpyAsync(bad.data(), h->bflags, sizeof(int) * nb, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    for (int b = 0; b < nb; ++b)
+        if (bad[b]) return fail(h, OSM_ENONFINITE, "u_{n-1} of instance " + std::to_string(b) +
+                                                      " contains NaN or Inf");
+    HIPCHK(h, launch_b_mass(h->st, h->tab_d, d, 0));
+    HIPCHK(h, launch_b_step_init(h->st, h->tab_d, d, batch_cfg(o)));
+    HIPCHK(h, launch_b_copy_u(h->st, h->tab_d, d, 0));
+    if (!h->prof) {
+        osm_status s = batch_capture(h);
+        if (s != OSM_OK) return s;
+    }
+    int nk = o.fixed_k > 0 ? o.fixed_k : o.max_k;
+    int nq = o.fixed_q > 0 ? o.fixed_q : o.max_q;
+    long max_chunks = ((long)nk * nq + (long)h->chunk_k * h->chunk_q - 1) /
+                      ((long)h->chunk_k * h->chunk_q) + nk / h->chunk_k + 2;
+    std::vector<StepCtl> &c = h->ctl_h;
+    auto fill = [&]() {
+        if (!stats) return;
+        for (int b = 0; b < nb; ++b) {
+            osm_step_stats &S = stats[b];
+            memset(&S, 0, sizeof(S));
+            S.k = c[b].k;
+            S.q_total = c[b].q_total;
+            S.refine_total = h->fp32 ? c[b].q_total : 0;
+            S.last_increment = c[b].inc;
+        }
+    };
+    osm_status s = OSM_OK;
+    bool done = false;
+    for (long ch = 0; ch < max_chunks && !done; ++ch) {
+        if (h->prof) {
+            if ((s = batch_chunk(h, h->st, true)) != OSM_OK) return s;
+        } else {
+            HIPCHK(h, hipGraphLaunch(h->gexec, h->st));
+        }
+        for (int b = 0; b < nb; ++b)
+            HIPCHK(h, hipMemcpyAsync(&c[b], h->sub[b]->sctl, sizeof(StepCtl), hipMemcpyDeviceToHost,
+                                     h->st));
+        int err = 0;
+        HIPCHK(h, hipMemcpyAsync(&err, h->err_d, sizeof(int), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(h, hipStreamSynchronize(h->st));
+        if (err) return fail(h, OSM_EHIP, "batched solve: barrier wait timed out");
+        if ((s = prof_collect(h)) != OSM_OK) return s;
+        done = true;
+        for (int b = 0; b < nb; ++b) {
+            if (c[b].bad) {
+                fill();
+                return fail(h, OSM_ENONFINITE, "non-finite value in instance " + std::to_string(b));
+            }
+            if (c[b].q_fail) {
+                fill();
+                return fail(h, OSM_ENOCONV, "fixed point of instance " + std::to_string(b) +
+                                                " did not converge within max_q");
+            }
+            if (!c[b].k_done) {
+                done = false;
+                if (c[b].k >= nk) {
+                    fill();
+                    return fail(h, OSM_ENOCONV, "Schwarz iteration of instance " +
+                                                    std::to_string(b) + " did not converge within max_k");
+                }
+            }
+        }
+    }
+    if (!done) {
+        fill();
+        return fail(h, OSM_ENOCONV, "batch did not converge within its iteration caps");
+    }
+    HIPCHK(h, launch_b_time_update(h->st, h->tab_d, d));
+    HIPCHK(h, launch_b_mass(h->st, h->tab_d, d, 1));
+    std::vector<double> mass(2 * nb);
+    HIPCHK(h, hipMemcpyAsync(mass.data(), h->bscal, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost,
+                             h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    fill();
+    if (stats)
+        for (int b = 0; b < nb; ++b) {
+            stats[b].mass_before = mass[2 * b];
+            stats[b].mass_after = mass[2 * b + 1];
+        }
+    return OSM_OK;
+}
+
+osm_status osm_batch_tuning(const osm_handle *h, int32_t *variant, double *alpha,
+                            int32_t *workgroups, int32_t *items) {
+    if (!h) return OSM_EINVAL;
+    if (h->sub.empty()) return OSM_ESTATE;
+    if (variant) *variant = h->bvariant;
+    if (alpha) *alpha = h->balpha;
+    if (workgroups) *workgroups = h->bgrid;
+    if (items) *items = h->nitems;
+    return OSM_OK;
+}
+
 void osm_destroy(osm_handle *h) {
     if (!h) return;
     if (h->st) hipStreamSynchronize(h->st);
     else hipDeviceSynchronize();
+    if (h->gexec) hipGraphExecDestroy(h->gexec);
+    if (h->graph) hipGraphDestroy(h->graph);
+    if (h->cap_st) hipStreamDestroy(h->cap_st);
+    for (osm_handle *u : h->sub) osm_destroy(u);
     for (hipEvent_t e : h->evs) hipEventDestroy(e);
     for (void *p : h->allocs) hipFree(p);
     delete h;

@@ -59,6 +59,7 @@ __device__ __forceinline__ double ref_triple(int c, int a, int b) {
 // All launchers enqueue on `st` and return the hipError_t of the launch.
 
 struct StepCtl;   // device-side step control (kernels_control.hip); null = unguarded
+struct BStrip;    // one strip of a batched solve (below)
 
 // kernels_assemble.hip
 hipError_t launch_coef(hipStream_t st, const Phys &P, const StripMeta *strips,
@@ -88,6 +89,13 @@ hipError_t launch_rotating_W(hipStream_t st, const Phys &P, double xl, double yb
                              double omega, double vxx, double vyy, double t1, double t0,
                              double *W);
 hipError_t launch_check_finite(hipStream_t st, const double2 *x, long n, int *flag);
+// scale[j] = 2^-e with 2^e <= max |b| over strip j < 2^(e+1) (1 when b_j = 0
+// or not finite), so that the right-hand side of a complex-FP32 solve stays
+// in FP32's normal range; skipped when c says the fixed point is idle.
+hipError_t launch_strip_scale(hipStream_t st, const Phys &P, const StripMeta *strips,
+                              const double2 *b, double *scale, const StepCtl *c);
+hipError_t launch_b_strip_scale(hipStream_t st, const BStrip *strips, int nstrips,
+                                double *scale, int guard);
 
 // kernels_factor.hip
 template <typename T>
@@ -134,6 +142,9 @@ struct SolveArgs {
     const StepCtl *ctl;      // may be null; the whole solve is skipped when it
                              // says the fixed point is done
     int *ran;                // may be null; set to 1 when the solve was not skipped
+    const double *scale;     // may be null (= 1); per strip, a power of two s_j:
+                             // right-hand sides enter the reduced-precision
+                             // products as s_j b, results leave divided by s_j
 };
 // ev0/ev1 (may be null) are recorded right before and after the solve kernel
 hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipEvent_t ev0,
@@ -158,6 +169,7 @@ struct StepCtl {
     int bad;        // non-finite value met
     int commit;     // classical: g <- R(g) pending
     int gm_total;   // GMRES iterations summed over the step
+    int ready;      // a new Schwarz iteration may start (batched replay)
     double tq;      // fixed-point tolerance of the current Schwarz map
     double inc, ref, prev_rel;
 };
@@ -217,3 +229,73 @@ hipError_t launch_norm_partials(hipStream_t st, long n, const double2 *x, double
 hipError_t launch_scale_copy(hipStream_t st, long n, const double2 *x, double2 s, double2 *y);
 hipError_t launch_axpby(hipStream_t st, long n, double2 a, const double2 *x, double2 b,
                         const double2 *y, double2 *z);
+
+// ---------------------------------------------------------------- batched instances
+// One entry per independent instance of a batch: its mesh constants and the
+// device buffers of its strips, interfaces and step control.  Batched kernels
+// take instance blockIdx.z (or blockIdx.y / blockIdx.x for per-line /
+// per-instance kernels) from this table; the grids cover the largest
+// instance and smaller instances return early.
+struct InstDesc {
+    Phys P;
+    const StripMeta *strips;
+    const int *line_strip;
+    const int2 *gmap;
+    const double *W;
+    double2 *u;                     // u_{n-1} in, u_n out (global nodes)
+    double2 *zeta, *res, *delta;    // packed strip vectors
+    double2 *g, *gn;                // interface vectors
+    double *line_part, *trace_part, *mass_part;
+    double *scal;                   // [0] mass before, [1] mass after
+    StepCtl *ctl;
+    int *flag;                      // non-finite input
+};
+
+// One strip of a batched solve: pointers already offset to the strip's
+// first packed line.
+struct BStrip {
+    const void *F;          // stored inverses (double2 or float2), n*n per line
+    const double2 *Uc;      // coupling coefficients, n*3 per line
+    const double2 *b;       // right-hand side
+    double2 *x;             // solution
+    const StepCtl *ctl;     // the instance's control; solve skipped when idle
+    const double *scale;    // may be null (= 1); this strip's power-of-two scale
+    int n, nx;
+};
+// One work item: member `member` of the `team` workgroups solving `strip`.
+// The members of a strip are consecutive items.
+struct BItem {
+    int strip, member, team, pad;
+};
+struct BatchSolveArgs {
+    const BStrip *strips;
+    const BItem *items;
+    int nitems, nstrips;
+    unsigned *counters;     // nstrips barrier counters, then the queue head
+    int *error;
+    int *ran;               // may be null; set to 1 when any strip was solved
+    int guard;              // 1: skip strips whose instance's fixed point is idle
+};
+struct BatchDims {
+    int nb, max_ny, max_lt, max_nglob, max_ntr;
+    long max_ng;
+};
+// kernels_batch.hip
+hipError_t launch_b_check_finite(hipStream_t st, const InstDesc *tab, const BatchDims &d);
+hipError_t launch_b_mass(hipStream_t st, const InstDesc *tab, const BatchDims &d, int slot);
+hipError_t launch_b_step_init(hipStream_t st, const InstDesc *tab, const BatchDims &d,
+                              const StepCfg &cfg);
+hipError_t launch_b_copy_u(hipStream_t st, const InstDesc *tab, const BatchDims &d, int guarded);
+hipError_t launch_b_iter_reset(hipStream_t st, const InstDesc *tab, const BatchDims &d);
+hipError_t launch_b_residual(hipStream_t st, const InstDesc *tab, const BatchDims &d);
+hipError_t launch_b_update_norms(hipStream_t st, const InstDesc *tab, const BatchDims &d);
+hipError_t launch_b_q_check(hipStream_t st, const InstDesc *tab, const BatchDims &d);
+hipError_t launch_b_flux(hipStream_t st, const InstDesc *tab, const BatchDims &d);
+hipError_t launch_b_commit(hipStream_t st, const InstDesc *tab, const BatchDims &d);
+hipError_t launch_b_time_update(hipStream_t st, const InstDesc *tab, const BatchDims &d);
+// kernels_solve.hip: variant = tile shape index (0 .. batch_solve_variants()-1)
+hipError_t launch_batch_solve(hipStream_t st, const BatchSolveArgs &a, int fp32, int variant,
+                              int grid, int max_n, hipEvent_t ev0, hipEvent_t ev1);
+int batch_solve_variants();
+const char *batch_solve_variant_name(int fp32, int variant);
+int batch_solve_max_resident_blocks(int fp32, int variant, int max_n);

@@ -1,0 +1,362 @@
+// Per-node, per-line and per-instance bodies of the time-step kernels.  The
+// single-instance kernels (kernels_assemble.hip, kernels_control.hip) and the
+// batched kernels (kernels_batch.hip, which look the instance up in a table)
+// call the same bodies, so both paths do the same arithmetic in the same
+// order.  Device code only.
+#pragma once
+
+#include "osm_internal.h"
+
+// Integrals between node (i,a) and node (ip,b) of one strip with nx lines:
+// mass m, stiffness s, potential-weighted mass w = int phi_h psi psi (phi
+// replaced by its Q1 interpolant, triple products exact) and the y-mass of
+// the left/right edge lines (boundary mass M^Gamma).  Elements of the strip
+// only: a strip is its own finite-element domain (Section 2.2).
+struct KParts {
+    double m, s, w, edge_l, edge_r;
+};
+
+template <class PhiF>
+__device__ __forceinline__ KParts kparts(int i, int a, int ip, int b, int nx, int ny,
+                                         double hx, double hy, PhiF phi) {
+    KParts k = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int exlo = max(max(i, ip) - 1, 0), exhi = min(min(i, ip), nx - 2);
+    int eylo = max(max(a, b) - 1, 0), eyhi = min(min(a, b), ny - 2);
+    for (int ex = exlo; ex <= exhi; ++ex) {
+        int Ax = i - ex, Bx = ip - ex;
+        double mx = hx * ref_mass(Ax, Bx), sx = ref_stiff(Ax, Bx) / hx;
+        for (int ey = eylo; ey <= eyhi; ++ey) {
+            int Ay = a - ey, By = b - ey;
+            double my = hy * ref_mass(Ay, By), sy = ref_stiff(Ay, By) / hy;
+            k.m += mx * my;
+            k.s += sx * my + mx * sy;
+            double acc = 0.0;
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx)
+#pragma unroll
+                for (int cy = 0; cy < 2; ++cy)
+                    acc += phi(ex + cx, ey + cy) * ref_triple(cx, Ax, Bx) * ref_triple(cy, Ay, By);
+            k.w += hx * hy * acc;
+        }
+    }
+    if (i == ip && (i == 0 || i == nx - 1)) {
+        double my = 0.0;
+        for (int ey = eylo; ey <= eyhi; ++ey) my += hy * ref_mass(a - ey, b - ey);
+        if (i == 0) k.edge_l = my;
+        if (i == nx - 1) k.edge_r = my;
+    }
+    return k;
+}
+
+// The fixed point of the current Schwarz map needs no more work.
+__device__ __forceinline__ bool fp_idle(const StepCtl *c) {
+    return c->q_conv || c->k_done || c->bad || c->q_fail;
+}
+
+// Fixed-point residual at strip node (L, a), residual form of the fixed
+// point with the nonlinearity on the right-hand side:
+//   res = 2i/dt M_j u_{j,n-1} - c M^Gamma Q^T (l_j; r_j) - K_j(W + beta|zeta|^2) zeta.
+// With the factor of K_j(W), zeta + K_j(W)^{-1} res equals
+// K_j(W)^{-1}(F - M_{beta|zeta|^2} zeta): the update of eq. localpbrobin.
+__device__ __forceinline__ double2 residual_at(const Phys &P, const StripMeta *strips,
+                                               const int *line_strip, const double *W,
+                                               const double2 *u_old, const double2 *zeta,
+                                               const double2 *g, int L, int a) {
+    int ny = P.ny;
+    int j = line_strip[L];
+    StripMeta s = strips[j];
+    int i = L - s.off;
+    const double *Wl = W + (long)s.line0 * ny;
+    const double2 *ul = u_old + (long)s.line0 * ny;
+    const double2 *zl = zeta + (long)s.off * ny;
+    double beta = P.beta;
+    auto phi = [&](int ii, int kk) -> double {
+        double2 z = zl[(long)ii * ny + kk];
+        return Wl[(long)ii * ny + kk] + beta * (z.x * z.x + z.y * z.y);
+    };
+    double2 acc = cd(0.0, 0.0);
+    const double2 *trace = nullptr;
+    if (i == 0 && j >= 1) trace = g + (long)(2 * (j - 1) + 1) * ny;             // l_j
+    if (i == s.nx - 1 && j <= P.nsub - 2) trace = g + (long)(2 * j) * ny;       // r_j
+    for (int ip = max(i - 1, 0); ip <= min(i + 1, s.nx - 1); ++ip) {
+        for (int b = max(a - 1, 0); b <= min(a + 1, ny - 1); ++b) {
+            KParts k = kparts(i, a, ip, b, s.nx, ny, P.hx, P.hy, phi);
+            double2 z = zl[(long)ip * ny + b];
+            double2 u = ul[(long)ip * ny + b];
+            // 2i/dt m (u - z)
+            double2 du = csub(u, z);
+            acc.x += -(2.0 / P.dt) * k.m * du.y;
+            acc.y += (2.0 / P.dt) * k.m * du.x;
+            // + c s z - w z
+            double cs = P.c * k.s - k.w;
+            acc.x += cs * z.x;
+            acc.y += cs * z.y;
+            // - i c (pl edge_l + pr edge_r) z
+            double e = P.c * (s.pl * k.edge_l + s.pr * k.edge_r);
+            acc.x += e * z.y;
+            acc.y += -e * z.x;
+            // - c M^Gamma trace
+            if (trace && ip == i) {
+                double my = (i == 0) ? k.edge_l : k.edge_r;
+                double2 t = trace[b];
+                acc.x -= P.c * my * t.x;
+                acc.y -= P.c * my * t.y;
+            }
+        }
+    }
+    return acc;
+}
+
+// zeta <- u_{n-1} restricted to the strips (interface lines copied).
+__device__ __forceinline__ void copy_u_at(const Phys &P, const StripMeta *strips,
+                                          const int *line_strip, const double2 *u,
+                                          double2 *zeta, int L, int a) {
+    StripMeta s = strips[line_strip[L]];
+    int gl = s.line0 + (L - s.off);
+    zeta[(long)L * P.ny + a] = u[(long)gl * P.ny + a];
+}
+
+// zeta += delta on packed line L; per-line partial sums |delta|^2, |zeta|^2
+// and a non-finite counter.  Block of 256 threads.
+__device__ __forceinline__ void update_norms_line(int ny, double2 *zeta, const double2 *delta,
+                                                  double *part, int L) {
+    double s_d = 0.0, s_z = 0.0, bad = 0.0;
+    for (int a = threadIdx.x; a < ny; a += blockDim.x) {
+        long o = (long)L * ny + a;
+        double2 d = delta[o];
+        double2 z = cadd(zeta[o], d);
+        zeta[o] = z;
+        s_d += d.x * d.x + d.y * d.y;
+        s_z += z.x * z.x + z.y * z.y;
+        if (!isfinite(d.x) || !isfinite(d.y)) bad += 1.0;
+    }
+    __shared__ double red[3][256];
+    red[0][threadIdx.x] = s_d;
+    red[1][threadIdx.x] = s_z;
+    red[2][threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+            red[2][threadIdx.x] += red[2][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[3 * L] = red[0][0];
+        part[3 * L + 1] = red[1][0];
+        part[3 * L + 2] = red[2][0];
+    }
+}
+
+// Flux update of trace t, eq. fluxlr with S = -ip (Jacobi):
+//   new r_i     = -l_{i+1} - 2ip v_{i+1}(first line)
+//   new l_{i+1} = -r_i     - 2ip v_i(last line)
+// Per-trace partial sums of |gn - g|^2 and |gn|^2.  Block of 256 threads.
+__device__ __forceinline__ void flux_trace(const Phys &P, const StripMeta *strips,
+                                           const double2 *g, const double2 *v, double2 *gn,
+                                           double *part, int t) {
+    int ny = P.ny;
+    int i = t >> 1;
+    const double2 *src;
+    const double2 *vt;
+    if ((t & 1) == 0) {           // r_i from strip i+1's left line
+        src = g + (long)(2 * i + 1) * ny;
+        vt = v + (long)strips[i + 1].off * ny;
+    } else {                      // l_{i+1} from strip i's right line
+        src = g + (long)(2 * i) * ny;
+        StripMeta s = strips[i];
+        vt = v + (long)(s.off + s.nx - 1) * ny;
+    }
+    double tp = 2.0 * P.p;
+    double sd = 0.0, sn = 0.0;
+    for (int a = threadIdx.x; a < ny; a += blockDim.x) {
+        double2 x = src[a], w = vt[a];
+        // -x - 2ip w = (-x.re + 2p w.im) + i(-x.im - 2p w.re)
+        double2 r = cd(-x.x + tp * w.y, -x.y - tp * w.x);
+        double2 o = g[(long)t * ny + a];
+        gn[(long)t * ny + a] = r;
+        sd += (r.x - o.x) * (r.x - o.x) + (r.y - o.y) * (r.y - o.y);
+        sn += r.x * r.x + r.y * r.y;
+    }
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = sd;
+    red[1][threadIdx.x] = sn;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * t] = red[0][0];
+        part[2 * t + 1] = red[1][0];
+    }
+}
+
+// u_n = 2 vbar - u_{n-1} at global node (gl, a); vbar is the strip value,
+// the mean of the two copies on an interface line.
+__device__ __forceinline__ void time_update_at(const Phys &P, const int2 *gmap, const double2 *v,
+                                               double2 *u, int gl, int a) {
+    int ny = P.ny;
+    int2 m = gmap[gl];
+    double2 vb = v[(long)m.x * ny + a];
+    if (m.y >= 0) vb = cscale(0.5, cadd(vb, v[(long)m.y * ny + a]));
+    long o = (long)gl * ny + a;
+    double2 uo = u[o];
+    u[o] = cd(2.0 * vb.x - uo.x, 2.0 * vb.y - uo.y);
+}
+
+// Partial of u* M u over global line gl with the global Q1 mass
+// M = M1x (x) M1y.  Block of 256 threads.
+__device__ __forceinline__ void mass_line(const Phys &P, const double2 *u, double *part, int gl) {
+    int ny = P.ny, ng = P.nglob;
+    double hx = P.hx, hy = P.hy;
+    double acc = 0.0;
+    for (int a = threadIdx.x; a < ny; a += blockDim.x) {
+        double2 mu = cd(0.0, 0.0);
+        for (int ip = max(gl - 1, 0); ip <= min(gl + 1, ng - 1); ++ip) {
+            double mx;
+            if (ip != gl) mx = hx / 6.0;
+            else mx = (gl == 0 || gl == ng - 1) ? hx / 3.0 : 2.0 * hx / 3.0;
+            for (int b = max(a - 1, 0); b <= min(a + 1, ny - 1); ++b) {
+                double my;
+                if (b != a) my = hy / 6.0;
+                else my = (a == 0 || a == ny - 1) ? hy / 3.0 : 2.0 * hy / 3.0;
+                double2 x = u[(long)ip * ny + b];
+                mu.x += mx * my * x.x;
+                mu.y += mx * my * x.y;
+            }
+        }
+        double2 x = u[(long)gl * ny + a];
+        acc += x.x * mu.x + x.y * mu.y;   // Re(conj(x) * mu)
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[gl] = red[0];
+}
+
+// Deterministic sum of n strided values into out[0 .. stride).  One block of
+// 256 threads.
+__device__ __forceinline__ void sum_block(const double *part, int n, int stride, double *out) {
+    __shared__ double red[256];
+    for (int c = 0; c < stride; ++c) {
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) acc += part[(long)i * stride + c];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[c] = red[0];
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ double ctl_wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double ctl_block_sum(double v, double *red) {
+    v = ctl_wsum(v);
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    return s;
+}
+
+// Thread 0 only.
+__device__ __forceinline__ void step_init_body(StepCtl *c, const StepCfg &cfg) {
+    c->cfg = cfg;
+    c->q_conv = 0; c->q_iter = 0; c->q_total = 0; c->q_fail = 0;
+    c->r_done = 0; c->k = 0; c->k_done = 0; c->bad = 0; c->commit = 0;
+    c->gm_total = 0;
+    c->ready = 1;
+    c->tq = cfg.tol_q;
+    c->inc = 0.0; c->ref = 0.0; c->prev_rel = 1.0;
+}
+
+// Start of a Schwarz iteration (thread 0 only): new fixed point, tolerance
+// from the previous increment (inexact inner solves), GMRES cycle idle.
+__device__ __forceinline__ void iter_reset_body(StepCtl *c, GmresCtl *g) {
+    c->q_conv = 0;
+    c->q_iter = 0;
+    c->q_fail = 0;
+    c->r_done = 0;
+    c->commit = 0;
+    c->ready = 0;
+    double t = c->cfg.tol_q;
+    if (c->cfg.eta_q > 0.0) t = fmax(t, c->cfg.eta_q * fmin(1.0, c->prev_rel));
+    c->tq = t;
+    if (g) { g->done = 1; g->finished = 0; g->conv = 0; g->j = 0; g->total = 0; }
+}
+
+// Fixed-point test of every strip from the per-line partial sums:
+// converged when ||dzeta_j|| <= tq ||zeta_j|| for all strips j (or after
+// fixed_q iterations).  One block.
+__device__ __forceinline__ void q_check_block(const Phys &P, const StripMeta *strips,
+                                              const double *part, StepCtl *c) {
+    __shared__ int notconv, nonfinite;
+    if (threadIdx.x == 0) { notconv = 0; nonfinite = 0; }
+    __syncthreads();
+    double tq = c->tq;
+    for (int j = threadIdx.x; j < P.nsub; j += blockDim.x) {
+        StripMeta s = strips[j];
+        double d = 0, z = 0, b = 0;
+        for (int i = 0; i < s.nx; ++i) {
+            d += part[3 * (s.off + i)];
+            z += part[3 * (s.off + i) + 1];
+            b += part[3 * (s.off + i) + 2];
+        }
+        if (b > 0 || !isfinite(d) || !isfinite(z)) atomicOr(&nonfinite, 1);
+        if (!(sqrt(d) <= tq * sqrt(z))) atomicOr(&notconv, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    c->q_iter += 1;
+    c->q_total += 1;
+    if (nonfinite) { c->bad = 1; return; }
+    bool conv = c->cfg.fixed_q > 0 ? (c->q_iter >= c->cfg.fixed_q) : !notconv;
+    if (conv) c->q_conv = 1;
+    else if (c->q_iter >= c->cfg.max_q) c->q_fail = 1;
+}
+
+// End of the Schwarz map: ||g^{k+1} - g^k||, ||g^{k+1}|| from the flux
+// partials.  Classical algorithm: decide convergence and commit g <- R(g).
+// One block.
+__device__ __forceinline__ void flux_finalize_block(const double *part, int nt, StepCtl *c) {
+    __shared__ double red[16];
+    double a = 0, b = 0;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) { a += part[2 * t]; b += part[2 * t + 1]; }
+    a = ctl_block_sum(a, red);
+    b = ctl_block_sum(b, red);
+    if (threadIdx.x != 0) return;
+    c->r_done = 1;
+    if (!c->cfg.classical) return;
+    double inc = sqrt(a), ref = sqrt(b);
+    if (!isfinite(inc)) { c->bad = 1; return; }
+    c->commit = 1;
+    c->ready = 1;
+    c->k += 1;
+    c->inc = inc;
+    c->ref = ref;
+    c->prev_rel = inc / fmax(ref, 1e-300);
+    double thr = c->cfg.tol_k_rel ? c->cfg.tol_k * fmax(ref, 1e-300) : c->cfg.tol_k;
+    if (c->cfg.fixed_k > 0) { if (c->k >= c->cfg.fixed_k) c->k_done = 1; }
+    else if (inc < thr) c->k_done = 1;
+}

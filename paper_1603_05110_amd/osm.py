@@ -68,7 +68,9 @@ class osm_footprint(ctypes.Structure):
 EXPORTS = ["osm_query", "osm_setup", "osm_factor", "osm_factor_rotating", "osm_step",
            "osm_interface_apply", "osm_set_interface_guess", "osm_get_interface",
            "osm_strip_solve", "osm_get_strip_solution", "osm_get_lh_blocks", "osm_get_factor",
-           "osm_kernel_timing", "osm_solve_team", "osm_destroy", "osm_last_error"]
+           "osm_kernel_timing", "osm_solve_team", "osm_query_batch", "osm_setup_batch",
+           "osm_factor_batch", "osm_step_batch", "osm_batch_tuning", "osm_destroy",
+           "osm_last_error"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -96,6 +98,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "osm_solve_team": ([H], ctypes.c_int32),
         "osm_kernel_timing": ([H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int64)], st),
+        "osm_query_batch": ([ctypes.POINTER(osm_problem), ctypes.c_int32,
+                             ctypes.POINTER(osm_options), ctypes.POINTER(osm_footprint)], st),
+        "osm_setup_batch": ([ctypes.POINTER(osm_problem), ctypes.c_int32,
+                             ctypes.POINTER(osm_options), P, ctypes.POINTER(H)], st),
+        "osm_factor_batch": ([H, ctypes.POINTER(ctypes.c_void_p)], st),
+        "osm_step_batch": ([H, ctypes.POINTER(ctypes.c_void_p),
+                            ctypes.POINTER(osm_step_stats)], st),
+        "osm_batch_tuning": ([H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], st),
         "osm_destroy": ([H], None),
         "osm_last_error": ([H], ctypes.c_char_p),
     }
@@ -237,6 +248,96 @@ class OsmSolver:
 
     def kernel_timing(self, enable: bool):
         """Returns (summed solve-kernel ms, launches) since the last reset."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._c(_lib.osm_kernel_timing(self.h, int(enable), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if self.h:
+            _lib.osm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _problem_array(pbs):
+    arr = (osm_problem * len(pbs))()
+    keep = []
+    for i, pb in enumerate(pbs):
+        arr[i], k = make_problem(pb)
+        keep.append(k)
+    return arr, keep
+
+
+def _ptr_array(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+def osm_query_batch(pbs, **opts):
+    arr, keep = _problem_array(pbs)
+    opt = make_options(**opts)
+    fp = osm_footprint()
+    _check(_lib.osm_query_batch(arr, len(pbs), ctypes.byref(opt), ctypes.byref(fp)))
+    return fp.device_bytes, fp.host_bytes
+
+
+class OsmBatch:
+    """Owns one batch handle over independent instances.  Per instance: u
+    (ncx+1, ncy+1) complex128 and W (ncx+1, ncy+1) float64 on the device."""
+
+    def __init__(self, pbs, device="cuda:0", **opts):
+        self.pbs = list(pbs)
+        self.nb = len(self.pbs)
+        self.device = torch.device(device)
+        arr, self._keep = _problem_array(self.pbs)
+        self._opt = make_options(**opts)
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            h = ctypes.c_void_p()
+            _check(_lib.osm_setup_batch(arr, self.nb, ctypes.byref(self._opt),
+                                        ctypes.c_void_p(stream), ctypes.byref(h)))
+        self.h = h
+
+    def _c(self, status):
+        _check(status, self.h)
+
+    def _check_fields(self, ts, dtype):
+        assert len(ts) == self.nb
+        for t, pb in zip(ts, self.pbs):
+            assert t.dtype == dtype and t.is_contiguous()
+            assert t.numel() == (pb.ncx + 1) * (pb.ncy + 1)
+
+    def factor(self, Ws):
+        self._check_fields(Ws, torch.float64)
+        self._c(_lib.osm_factor_batch(self.h, _ptr_array(Ws)))
+
+    def step(self, us):
+        """Advances every u in place; returns the list of per-instance stats."""
+        self._check_fields(us, torch.complex128)
+        st = (osm_step_stats * self.nb)()
+        status = _lib.osm_step_batch(self.h, _ptr_array(us), st)
+        stats = [st[i].as_dict() for i in range(self.nb)]
+        if status != OSM_OK:
+            err = OsmError(status, (_lib.osm_last_error(self.h) or b"").decode())
+            err.stats = stats
+            raise err
+        return stats
+
+    def tuning(self):
+        v = ctypes.c_int32()
+        a = ctypes.c_double()
+        g = ctypes.c_int32()
+        n = ctypes.c_int32()
+        self._c(_lib.osm_batch_tuning(self.h, ctypes.byref(v), ctypes.byref(a), ctypes.byref(g),
+                                      ctypes.byref(n)))
+        return {"variant": v.value, "alpha": a.value, "workgroups": g.value, "items": n.value}
+
+    def kernel_timing(self, enable: bool):
         ms = ctypes.c_double()
         n = ctypes.c_int64()
         self._c(_lib.osm_kernel_timing(self.h, int(enable), ctypes.byref(ms), ctypes.byref(n)))

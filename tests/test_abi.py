@@ -71,3 +71,37 @@ def test_setup_reports_enomem_before_allocating():
     assert st == osm.OSM_ENOMEM
     assert not h.value
     assert b"exceeds" in osm._lib.osm_last_error(None)
+
+
+def test_batch_footprint_is_the_sum_of_its_instances():
+    from paper_1603_05110_amd import osm
+    pbs = [_pb(ncy=32), _pb(ncx=24, ncy=48, nsub=3, strip_cells=[6, 8, 10])]
+    single = sum(osm.osm_query(pb)[0] for pb in pbs)
+    dev, _ = osm.osm_query_batch(pbs)
+    assert single < dev < single + 64 * 1024
+
+
+def test_batch_rejects_bad_arguments_on_the_host():
+    from paper_1603_05110_amd import osm
+    with pytest.raises(osm.OsmError) as e:
+        osm.osm_query_batch([_pb(), _pb()], algo="precond")
+    assert e.value.status == osm.OSM_EUNSUPPORTED
+    with pytest.raises(osm.OsmError) as e:
+        osm.osm_query_batch([_pb(), _pb(strip_cells=[10, 5])])
+    assert e.value.status == osm.OSM_EINVAL
+    assert b"instance 1" in osm._lib.osm_last_error(None)
+    import ctypes
+    opt = osm.make_options()
+    fp = osm.osm_footprint()
+    assert osm._lib.osm_query_batch(None, 0, ctypes.byref(opt), ctypes.byref(fp)) == osm.OSM_EINVAL
+
+
+def test_batch_setup_reports_enomem_before_allocating():
+    import ctypes
+    from paper_1603_05110_amd import osm
+    arr, keep = osm._problem_array([_pb(ncy=64), _pb(ncy=32)])
+    opt = osm.make_options(mem_cap=4096)
+    h = ctypes.c_void_p()
+    st = osm._lib.osm_setup_batch(arr, 2, ctypes.byref(opt), None, ctypes.byref(h))
+    assert st == osm.OSM_ENOMEM
+    assert not h.value
