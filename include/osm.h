@@ -194,6 +194,13 @@ osm_status osm_get_factor(osm_handle *h, void *dst_dev);
 osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
                              int64_t *solve_launches);
 
+/* Algorithmic bytes of the strip-solve launches timed since the last reset
+ * of osm_kernel_timing (stored inverses read by both sweeps, right-hand
+ * side, solution and coupling coefficients of every strip solved; a batched
+ * launch counts only the instances it did not skip).  Divided by the timed
+ * milliseconds it gives the achieved bandwidth of the solve. */
+osm_status osm_kernel_work(const osm_handle *h, double *solve_bytes);
+
 /* Workgroups per strip used by the strip solve: opt->team when given, else
  * the value the autotuner picked at the first factorisation (it times a few
  * solves for every feasible team size).  0 for a NULL handle. */

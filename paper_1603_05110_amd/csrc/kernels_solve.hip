@@ -391,6 +391,13 @@ __global__ __launch_bounds__(NW * 64) void batch_solve_kernel(BatchSolveArgs a) 
         const int n = s.n, nx = s.nx, team = I.team;
         const int rpw = (n + team - 1) / team;
         const int r0 = min(n, I.member * rpw), r1 = min(n, r0 + rpw);
+        if (a.work && threadIdx.x == 0) {
+            // stored inverses: this member's rows of every product; member 0
+            // also counts b, x and the coupling coefficients of the strip
+            unsigned long long w = (unsigned long long)(2 * nx - 1) * (r1 - r0) * n * sizeof(T2);
+            if (I.member == 0) w += (unsigned long long)nx * n * 80;
+            atomicAdd(a.work, w);
+        }
         const T2 *F = reinterpret_cast<const T2 *>(s.F);
         const long nn = (long)n * n;
         unsigned *ctr = a.counters + I.strip;

@@ -69,9 +69,11 @@ struct osm_handle {
     bool prof = false;
     std::vector<hipEvent_t> evs;     // event pairs, one per slot
     int *ran_d = nullptr;            // per slot: the solve kernel did work
+    unsigned long long *work_d = nullptr;  // per slot: algorithmic bytes (batched solve)
     int prof_used = 0;
     double solve_ms = 0.0;
     long long solve_launches = 0;
+    double solve_bytes = 0.0;
     // device-side control of a step
     StepCtl *sctl = nullptr;
     double *upd_part = nullptr;
@@ -278,16 +280,29 @@ osm_status do_factor(osm_handle *h) {
 // with its own event pair and a device flag telling whether the kernel did
 // the solve or returned at once (a fixed point already converged); the
 // slots are collected after the next synchronisation.
+// Algorithmic bytes of one single-instance strip solve: every stored
+// inverse read in the forward and the backward sweep (the last line of a
+// strip once), plus b, x and the coupling coefficients once.
+double single_solve_bytes(const osm_handle *h) {
+    double es = h->fp32 ? 8.0 : 16.0;
+    return (2.0 * h->Lt - h->N) * (double)h->n * h->n * es + (double)h->Lt * h->n * 80.0;
+}
+
 osm_status prof_collect(osm_handle *h) {
     if (h->prof_used == 0) return OSM_OK;
     std::vector<int> ran(h->prof_used);
+    std::vector<unsigned long long> work(h->prof_used, 0ull);
     HIPCHK(h, hipMemcpy(ran.data(), h->ran_d, sizeof(int) * h->prof_used, hipMemcpyDeviceToHost));
+    if (h->work_d)
+        HIPCHK(h, hipMemcpy(work.data(), h->work_d, sizeof(unsigned long long) * h->prof_used,
+                            hipMemcpyDeviceToHost));
     for (int i = 0; i < h->prof_used; ++i) {
         if (!ran[i]) continue;
         float ms = 0.f;
         HIPCHK(h, hipEventElapsedTime(&ms, h->evs[2 * i], h->evs[2 * i + 1]));
         h->solve_ms += ms;
         h->solve_launches += 1;
+        h->solve_bytes += h->work_d ? (double)work[i] : single_solve_bytes(h);
     }
     h->prof_used = 0;
     return OSM_OK;
@@ -902,6 +917,7 @@ static osm_status autotune_team(osm_handle *h) {
     if (s0 != OSM_OK) return s0;
     keep_ms = h->solve_ms;
     keep_n = h->solve_launches;
+    double keep_b = h->solve_bytes;
     HIPCHK(h, hipMemsetAsync(h->res, 0, sizeof(double2) * (size_t)h->Lt * h->n, h->st));
     int best = h->team;
     double best_ms = 1e300;
@@ -923,6 +939,7 @@ static osm_status autotune_team(osm_handle *h) {
     h->prof = prof;
     h->solve_ms = keep_ms;
     h->solve_launches = keep_n;
+    h->solve_bytes = keep_b;
     h->team_tuned = true;
     return OSM_OK;
 }
@@ -1118,8 +1135,15 @@ osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
     if (enable) {
         h->solve_ms = 0.0;
         h->solve_launches = 0;
+        h->solve_bytes = 0.0;
     }
     h->prof = enable != 0;
+    return OSM_OK;
+}
+
+osm_status osm_kernel_work(const osm_handle *h, double *solve_bytes) {
+    if (!h) return OSM_EINVAL;
+    if (solve_bytes) *solve_bytes = h->solve_bytes;
     return OSM_OK;
 }
 
@@ -1211,7 +1235,7 @@ static std::vector<BItem> make_items(const osm_handle *h, double alpha, int grid
 }
 
 static osm_status batch_solve(osm_handle *h, int guard, hipStream_t st, hipEvent_t e0,
-                              hipEvent_t e1, int *ran) {
+                              hipEvent_t e1, int *ran, unsigned long long *work = nullptr) {
     BatchSolveArgs a;
     a.strips = h->bstrips_d;
     a.items = h->bitems_d;
@@ -1220,7 +1244,9 @@ static osm_status batch_solve(osm_handle *h, int guard, hipStream_t st, hipEvent
     a.counters = h->bcounters;
     a.error = h->err_d;
     a.ran = ran;
+    a.work = work;
     a.guard = guard;
+    if (work) HIPCHK(h, hipMemsetAsync(work, 0, sizeof(unsigned long long), st));
     if (h->fp32) HIPCHK(h, launch_b_strip_scale(st, h->bstrips_d, h->nstrips_all, h->bscale, guard));
     HIPCHK(h, launch_batch_solve(st, a, h->fp32, h->bvariant, h->bgrid, h->max_n, e0, e1));
     return OSM_OK;
@@ -1312,6 +1338,7 @@ static osm_status batch_chunk(osm_handle *h, hipStream_t st, bool timed) {
             HIPCHK(h, launch_b_residual(st, h->tab_d, d));
             hipEvent_t e0 = nullptr, e1 = nullptr;
             int *ran = nullptr;
+            unsigned long long *work = nullptr;
             if (timed) {
                 if (h->prof_used == PROF_SLOTS) {
                     HIPCHK(h, hipStreamSynchronize(st));
@@ -1329,8 +1356,9 @@ static osm_status batch_chunk(osm_handle *h, hipStream_t st, bool timed) {
                 e0 = h->evs[2 * slot];
                 e1 = h->evs[2 * slot + 1];
                 ran = h->ran_d + slot;
+                work = h->work_d + slot;
             }
-            osm_status s = batch_solve(h, 1, st, e0, e1, ran);
+            osm_status s = batch_solve(h, 1, st, e0, e1, ran, work);
             if (s != OSM_OK) return s;
             HIPCHK(h, launch_b_update_norms(st, h->tab_d, d));
             HIPCHK(h, launch_b_q_check(st, h->tab_d, d));
@@ -1407,6 +1435,7 @@ osm_status osm_setup_batch(const osm_problem *probs, int32_t nb, const osm_optio
         ALLOC(h, h->bscale, double, h->nstrips_all);
         ALLOC(h, h->err_d, int, 1);
         ALLOC(h, h->ran_d, int, PROF_SLOTS);
+        ALLOC(h, h->work_d, unsigned long long, PROF_SLOTS);
         HIPCHK(h, hipMemset(h->err_d, 0, sizeof(int)));
         size_t fe = h->fp32 ? sizeof(float2) : sizeof(double2);
         for (int b = 0; b < nb; ++b) {

@@ -274,6 +274,7 @@ struct BatchSolveArgs {
     unsigned *counters;     // nstrips barrier counters, then the queue head
     int *error;
     int *ran;               // may be null; set to 1 when any strip was solved
+    unsigned long long *work;  // may be null; algorithmic bytes of the strips solved
     int guard;              // 1: skip strips whose instance's fixed point is idle
 };
 struct BatchDims {

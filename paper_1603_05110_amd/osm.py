@@ -68,7 +68,7 @@ class osm_footprint(ctypes.Structure):
 EXPORTS = ["osm_query", "osm_setup", "osm_factor", "osm_factor_rotating", "osm_step",
            "osm_interface_apply", "osm_set_interface_guess", "osm_get_interface",
            "osm_strip_solve", "osm_get_strip_solution", "osm_get_lh_blocks", "osm_get_factor",
-           "osm_kernel_timing", "osm_solve_team", "osm_query_batch", "osm_setup_batch",
+           "osm_kernel_timing", "osm_kernel_work", "osm_solve_team", "osm_query_batch", "osm_setup_batch",
            "osm_factor_batch", "osm_step_batch", "osm_batch_tuning", "osm_destroy",
            "osm_last_error"]
 
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "osm_solve_team": ([H], ctypes.c_int32),
         "osm_kernel_timing": ([H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int64)], st),
+        "osm_kernel_work": ([H, ctypes.POINTER(ctypes.c_double)], st),
         "osm_query_batch": ([ctypes.POINTER(osm_problem), ctypes.c_int32,
                              ctypes.POINTER(osm_options), ctypes.POINTER(osm_footprint)], st),
         "osm_setup_batch": ([ctypes.POINTER(osm_problem), ctypes.c_int32,
@@ -253,6 +254,12 @@ class OsmSolver:
         self._c(_lib.osm_kernel_timing(self.h, int(enable), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
+    def kernel_work(self):
+        """Algorithmic bytes of the timed solve launches since the last reset."""
+        b = ctypes.c_double()
+        self._c(_lib.osm_kernel_work(self.h, ctypes.byref(b)))
+        return b.value
+
     def close(self):
         if self.h:
             _lib.osm_destroy(self.h)
@@ -342,6 +349,11 @@ class OsmBatch:
         n = ctypes.c_int64()
         self._c(_lib.osm_kernel_timing(self.h, int(enable), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def kernel_work(self):
+        b = ctypes.c_double()
+        self._c(_lib.osm_kernel_work(self.h, ctypes.byref(b)))
+        return b.value
 
     def close(self):
         if self.h:
