@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct osm_handle osm_handle;
+typedef struct osm_net osm_net;
 typedef struct { double re, im; } osm_c64;
 
 typedef enum {
@@ -102,7 +103,14 @@ typedef struct {
     double tol_gmres;             /* relative residual of P x = y                  */
     int32_t gmres_restart, max_gmres;
     int32_t guess;                /* 0: g_n^0 = g_{n-1} converged (paper);
-                                     1: the vector of osm_set_interface_guess     */
+                                     1: the vector of osm_set_interface_guess;
+                                     2: learned prediction (osm_set_guess_net);
+                                     3: linear extrapolation 2 g_{n-1} - g_{n-2}.
+                                     2 and 3 start once two converged vectors
+                                     exist; a prediction that ended farther from
+                                     g_n than g_{n-1} did disables the next one,
+                                     and a step that fails from a prediction is
+                                     restarted from g_{n-1} (stats.fallback_used) */
     int32_t team;                 /* workgroups per strip in the solve; 0 = auto   */
     uint64_t mem_cap;             /* 0 = free device memory; else a byte cap       */
     double eta_q;                 /* > 0: inexact inner solves; Schwarz iteration k
@@ -205,6 +213,64 @@ osm_status osm_kernel_work(const osm_handle *h, double *solve_bytes);
  * the value the autotuner picked at the first factorisation (it times a few
  * solves for every feasible team size).  0 for a NULL handle. */
 int32_t osm_solve_team(const osm_handle *h);
+
+/* ---------------------------------------------------------------- learned guess
+ * A network predicts the next step's interface start from the history (the
+ * paper starts from the previous converged vector, Section 5; the converged
+ * answer does not depend on the start).  Per interface i, along its ny
+ * nodes: inputs Re/Im of (r_i, l_{i+1}) of g_{n-1} and g_{n-2}, divided by
+ * s_i = rms of g_{n-1}'s two traces (1 if zero), and W_n on the interface
+ * line divided by max(1, max|W_n| there): 9 channels.  Outputs (4 channels)
+ * are Re/Im of what linear extrapolation misses, g_n - 2 g_{n-1} + g_{n-2},
+ * of the two traces divided by s_i; the guess is 2 g_{n-1} - g_{n-2} + s_i y.
+ * Network conv1d(9 -> 64, k 5) -> GELU (erf) -> conv1d(64 -> 4, k 5), zero
+ * padding; bfloat16 parameters (rounded from an FP32 master copy), FP32
+ * accumulation.  Parameters are one FP32 vector of osm_net_nparams() values
+ * in the order W1 (64,9,5), b1 (64), W2 (4,64,5), b2 (4).  Tensors x (T,9,L),
+ * targets and outputs (T,4,L) are FP32 device arrays, row-major. */
+
+int32_t osm_net_nparams(void);
+
+/* Network with workspace for training batches of up to max_traces traces;
+ * parameters zero until osm_net_set_params. */
+osm_status osm_net_create(int32_t max_traces, void *hip_stream, osm_net **out);
+
+/* Set the FP32 master parameters (device array) and reset the optimiser. */
+osm_status osm_net_set_params(osm_net *net, const float *theta_dev);
+
+/* Copy the master parameters, or (rounded = 1) the bfloat16 values the
+ * network computes with, as FP32. */
+osm_status osm_net_get_params(const osm_net *net, int32_t rounded, float *theta_dev);
+
+/* y = network(x) for T traces of length L. */
+osm_status osm_net_forward(osm_net *net, const float *x_dev, int32_t T, int32_t L,
+                           float *y_dev);
+
+/* Mean squared error of network(x) against t over all T*4*L outputs, and its
+ * gradient with respect to the (bfloat16) parameters into grad_dev (NULL =
+ * keep internal).  loss may be NULL. */
+osm_status osm_net_loss_grad(osm_net *net, const float *x_dev, const float *t_dev,
+                             int32_t T, int32_t L, float *grad_dev, double *loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * master parameters with the gradient of the batch; the bfloat16 copy is
+ * refreshed.  *loss (may be NULL, then no synchronisation) is the loss
+ * before the update. */
+osm_status osm_net_train_step(osm_net *net, const float *x_dev, const float *t_dev,
+                              int32_t T, int32_t L, double lr, double *loss);
+
+void osm_net_destroy(osm_net *net);
+const char *osm_net_last_error(const osm_net *net);
+
+/* Network inputs x (nsub-1, 9, ny) from g1 = g_{n-1}, g2 = g_{n-2} and the
+ * handle's W_n; with g0 = g_n also the targets t (nsub-1, 4, ny) (g0_dev and
+ * t_dev both NULL or both given).  Used to build training data from the
+ * converged vectors of a run. */
+osm_status osm_guess_features(osm_handle *h, const osm_c64 *g1_dev, const osm_c64 *g2_dev,
+                              const osm_c64 *g0_dev, float *x_dev, float *t_dev);
+
+/* Network used by opt->guess == 2 (the caller keeps it alive; NULL clears). */
+osm_status osm_set_guess_net(osm_handle *h, const osm_net *net);
 
 /* ---------------------------------------------------------------- batches
  * nb independent instances (each its own mesh, strip layout, p and

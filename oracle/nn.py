@@ -4,10 +4,9 @@ its loss gradient and its optimiser.
 Oracle code (test infrastructure).  The paper starts each time step's
 Schwarz iteration from the converged interface vector of the previous step
 (Section 5, initial vectors).  The learned guess replaces that start by a
-prediction g^{NN} = g_{n-1} + Delta, where Delta is produced by a small
-1-D convolutional network from the interface history; the converged solve
-is unchanged (the Schwarz fixed point does not depend on its start), only
-the iteration count can change.
+prediction from the last two converged vectors, corrected by a small 1-D
+convolutional network; the converged solve is unchanged (the Schwarz fixed
+point does not depend on its start), only the iteration count can change.
 
 Per interface i (between strips i and i+1), along the ny nodes of the
 interface line:
@@ -17,8 +16,10 @@ interface line:
 * input channels (9): Re r, Im r, Re l, Im l of g_{n-1}, the same of g_{n-2}
   (all divided by s_i), and W_n on the interface line divided by
   max(1, max |W_n| on that line);
-* output channels (4): Re, Im of (r_i^n - r_i^{n-1}) / s_i and of
-  (l_{i+1}^n - l_{i+1}^{n-1}) / s_i;
+* output channels (4): Re, Im of the part of the change that linear
+  extrapolation misses, (r_i^n - 2 r_i^{n-1} + r_i^{n-2}) / s_i, and the same
+  for l_{i+1}; the guess is g^{NN} = 2 g_{n-1} - g_{n-2} + s_i * output, so an
+  untrained network (output near zero) starts from linear extrapolation;
 * network: conv1d(9 -> 64, kernel 5, zero padding 2) -> GELU (exact, with
   erf) -> conv1d(64 -> 4, kernel 5, zero padding 2); cross-correlation
   convention y[o, a] = b[o] + sum_{c, k} w[o, c, k] x[c, a + k - 2];
@@ -173,21 +174,22 @@ def features(pb, g1, g2, W):
     return x, s
 
 
-def targets(g0, g1, s):
-    """Outputs (N-1, 4, ny) the network is trained to produce: the change of
-    the interface vector from g_{n-1} = g1 to g_n = g0, per-trace scaled."""
+def targets(g0, g1, g2, s):
+    """Outputs (N-1, 4, ny) the network is trained to produce: what linear
+    extrapolation from g_{n-2} = g2 and g_{n-1} = g1 misses of g_n = g0,
+    per-trace scaled."""
     T = len(s)
     y = np.zeros((T, COUT, g0.shape[1]))
     for i in range(T):
-        dr = (g0[2 * i] - g1[2 * i]) / s[i]
-        dl = (g0[2 * i + 1] - g1[2 * i + 1]) / s[i]
+        dr = (g0[2 * i] - 2 * g1[2 * i] + g2[2 * i]) / s[i]
+        dl = (g0[2 * i + 1] - 2 * g1[2 * i + 1] + g2[2 * i + 1]) / s[i]
         y[i] = [dr.real, dr.imag, dl.real, dl.imag]
     return y
 
 
-def guess(g1, y, s):
-    """g^{NN} = g_{n-1} + s * (network output) in the interface layout."""
-    g = np.array(g1, dtype=complex)
+def guess(g1, g2, y, s):
+    """g^{NN} = 2 g_{n-1} - g_{n-2} + s * (network output), interface layout."""
+    g = 2 * np.array(g1, dtype=complex) - np.array(g2, dtype=complex)
     for i in range(len(s)):
         g[2 * i] += s[i] * (y[i, 0] + 1j * y[i, 1])
         g[2 * i + 1] += s[i] * (y[i, 2] + 1j * y[i, 3])

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libosm.so")
 SOURCES = ["osm.hip", "kernels_assemble.hip", "kernels_factor.hip", "kernels_solve.hip",
-           "kernels_control.hip", "kernels_batch.hip",
+           "kernels_control.hip", "kernels_batch.hip", "kernels_net.hip",
            "kernels_gmres.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

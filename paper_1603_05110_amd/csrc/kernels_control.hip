@@ -97,6 +97,7 @@ __global__ void precond_finalize_kernel(const double *part, int nb, StepCtl *c,
     c->inc = inc;
     c->ref = ref;
     c->prev_rel = inc / fmax(ref, 1e-300);
+    if (c->k == 1) c->first_rel = c->prev_rel;
     double thr = c->cfg.tol_k_rel ? c->cfg.tol_k * fmax(ref, 1e-300) : c->cfg.tol_k;
     if (c->cfg.fixed_k > 0) { if (c->k >= c->cfg.fixed_k) c->k_done = 1; }
     else if (inc < thr) c->k_done = 1;

@@ -107,6 +107,27 @@ struct osm_handle {
     hipGraphExec_t gexec = nullptr;
     int chunk_k = 4, chunk_q = 3;
     std::vector<StepCtl> ctl_h;
+    // interface guess from the history (learned network or extrapolation)
+    const osm_net *net = nullptr;
+    float *nX = nullptr, *nY = nullptr;
+    double *nS = nullptr, *judge_part = nullptr;
+    double2 *g_last = nullptr, *g_prev2 = nullptr, *g_pred = nullptr;
+    int hist = 0;
+    bool fallback_next = false;
+};
+
+// Parameters, optimiser state and workspaces of the guess network.
+struct osm_net {
+    hipStream_t st = nullptr;
+    int max_traces = 0;
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    float *gpart = nullptr, *lpart = nullptr;
+    uint16_t *pbf = nullptr;
+    double *loss_d = nullptr;
+    int t = 0;
+    bool has_params = false;
+    std::string err;
+    std::vector<void *> allocs;
 };
 
 namespace {
@@ -167,6 +188,7 @@ std::string validate(const osm_problem *p, const osm_options *o) {
     if (o->max_q < 1 && o->fixed_q < 1) return "max_q must be >= 1";
     if (o->algo == OSM_PRECOND && (o->gmres_restart < 1 || o->gmres_restart > 200))
         return "gmres_restart must be in [1, 200]";
+    if (o->guess < 0 || o->guess > 3) return "guess must be 0, 1, 2 or 3";
     return "";
 }
 
@@ -206,6 +228,8 @@ uint64_t device_bytes(const Sizes &s) {
     b += 5ull * s.ng * 16;                              // interface vectors
     b += 2ull * s.N * GJ_BK * s.n * fe;                 // GJ panels
     b += (uint64_t)(3 * s.Lt + 4 * s.N + 2 * 2 * s.N + s.nglob + 64) * 8;
+    b += (uint64_t)(s.N - 1) * s.n * 13 * 4 + (uint64_t)(s.N - 1) * 8;  // guess features
+    b += 3ull * s.ng * 16 + 2ull * ((s.ng + 255) / 256) * 8;           // guess history
     if (s.m > 0) {
         b += 4ull * s.ncls * s.n * s.n * 16;            // L_h blocks
         b += (uint64_t)(s.m + 2) * s.ng * 16;           // Krylov basis
@@ -832,6 +856,13 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         SALLOC(h->err_d, int, 1);
         SALLOC(h->ran_d, int, PROF_SLOTS);
         SALLOC(h->sctl, StepCtl, 1);
+        SALLOC(h->nX, float, (long)(h->N - 1) * 9 * h->n);
+        SALLOC(h->nY, float, (long)(h->N - 1) * 4 * h->n);
+        SALLOC(h->nS, double, h->N - 1);
+        SALLOC(h->g_last, double2, h->ng);
+        SALLOC(h->g_prev2, double2, h->ng);
+        SALLOC(h->g_pred, double2, h->ng);
+        SALLOC(h->judge_part, double, 2 * ((h->ng + 255) / 256));
         SALLOC(h->upd_part, double, 2 * ((h->ng + 255) / 256));
         h->nblk = 256;
         SALLOC(h->norm_part, double, h->nblk);
@@ -856,6 +887,7 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         HIPCHK(h, hipMemcpy(h->step_first_d, first_all.data(), sizeof(int) * first_all.size(), hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(h->ff_lines_d, ffl.data(), sizeof(int) * h->maxnx, hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(h->ff_first_d, fff.data(), sizeof(int) * h->maxnx, hipMemcpyHostToDevice));
+        HIPCHK(h, hipMemset(h->sctl, 0, sizeof(StepCtl)));
         HIPCHK(h, hipMemset(h->g, 0, sizeof(double2) * h->ng));
         HIPCHK(h, hipMemset(h->gguess, 0, sizeof(double2) * h->ng));
         if (h->m > 0) {
@@ -1000,13 +1032,68 @@ osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats) {
     if (bad) return fail(h, OSM_ENONFINITE, "u_{n-1} contains NaN or Inf");
     s = mass_of(h, u, &S.mass_before);
     if (s != OSM_OK) return s;
+    // start of the interface iteration: the previous converged vector (the
+    // paper's choice), an external guess, or a prediction from the last two
+    // converged vectors (learned network or linear extrapolation); a
+    // prediction is not used when it did worse than the previous vector on
+    // the last step
+    const size_t gbytes = sizeof(double2) * h->ng;
+    bool history = o.guess == 2 || o.guess == 3;
+    bool predicted = false, used_pred = false;
     if (o.guess == 1 && h->has_guess)
-        HIPCHK(h, hipMemcpyAsync(h->g, h->gguess, sizeof(double2) * h->ng, hipMemcpyDeviceToDevice, h->st));
+        HIPCHK(h, hipMemcpyAsync(h->g, h->gguess, gbytes, hipMemcpyDeviceToDevice, h->st));
+    if (history) {
+        if (o.guess == 2 && !h->net)
+            return fail(h, OSM_ESTATE, "guess = 2 needs osm_set_guess_net before osm_step");
+        HIPCHK(h, hipMemcpyAsync(h->g_last, h->g, gbytes, hipMemcpyDeviceToDevice, h->st));
+        if (h->hist >= 2) {
+            if (o.guess == 2) {
+                HIPCHK(h, launch_net_features(h->st, h->P, h->strips_d, h->g_last, h->g_prev2,
+                                              nullptr, h->W_d, h->nX, nullptr, h->nS));
+                HIPCHK(h, launch_net_forward(h->st, h->net->pbf, h->nX, h->N - 1, h->n, h->nY));
+                HIPCHK(h, launch_net_guess(h->st, h->P, h->g_last, h->g_prev2, h->nY, h->nS,
+                                           h->g_pred));
+            } else {
+                HIPCHK(h, launch_net_guess(h->st, h->P, h->g_last, h->g_prev2, nullptr, nullptr,
+                                           h->g_pred));
+            }
+            predicted = true;
+            if (!h->fallback_next) {
+                HIPCHK(h, hipMemcpyAsync(h->g, h->g_pred, gbytes, hipMemcpyDeviceToDevice, h->st));
+                used_pred = true;
+            }
+        }
+    }
     HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
     s = schwarz_device(h, u, &S);
+    if (used_pred && (s == OSM_ENOCONV || s == OSM_ENONFINITE)) {
+        // the predicted start failed (u is untouched): restart the step from
+        // the previous converged vector and do not predict on the next step
+        HIPCHK(h, hipMemcpyAsync(h->g, h->g_last, gbytes, hipMemcpyDeviceToDevice, h->st));
+        HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
+        used_pred = false;
+        memset(&S, 0, sizeof(S));
+        s = mass_of(h, u, &S.mass_before);
+        if (s == OSM_OK) s = schwarz_device(h, u, &S);
+    }
+    S.fallback_used = predicted && !used_pred;
     if (s != OSM_OK) {
         if (stats) *stats = S;
         return s;
+    }
+    if (history) {
+        if (predicted) {
+            // judge the prediction against the converged vector
+            int nb = (h->ng + 255) / 256;
+            HIPCHK(h, launch_net_judge(h->st, h->ng, h->g, h->g_pred, h->g_last, h->judge_part));
+            HIPCHK(h, launch_sum(h->st, h->judge_part, nb, 2, h->scal + 6));
+            double e[2];
+            HIPCHK(h, hipMemcpyAsync(e, h->scal + 6, sizeof(e), hipMemcpyDeviceToHost, h->st));
+            HIPCHK(h, hipStreamSynchronize(h->st));
+            h->fallback_next = e[0] > e[1];
+        }
+        HIPCHK(h, hipMemcpyAsync(h->g_prev2, h->g_last, gbytes, hipMemcpyDeviceToDevice, h->st));
+        h->hist += 1;
     }
     HIPCHK(h, launch_time_update(h->st, h->P, h->gmap_d, h->zeta, u));
     s = mass_of(h, u, &S.mass_after);
@@ -1148,6 +1235,159 @@ osm_status osm_kernel_work(const osm_handle *h, double *solve_bytes) {
 }
 
 int32_t osm_solve_team(const osm_handle *h) { return h ? h->team : 0; }
+
+// ====================================================================== guess network
+static osm_status nfail(osm_net *n, osm_status s, const std::string &msg) {
+    if (n) n->err = msg;
+    else g_setup_error = msg;
+    return s;
+}
+
+#define NHIPCHK(n, call)                                                                    \
+    do {                                                                                    \
+        hipError_t _e = (call);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return nfail(n, OSM_EHIP, std::string(#call) + ": " + hipGetErrorString(_e));   \
+    } while (0)
+
+int32_t osm_net_nparams(void) { return net_nparams(); }
+
+void osm_net_destroy(osm_net *n) {
+    if (!n) return;
+    if (n->st) hipStreamSynchronize(n->st);
+    else hipDeviceSynchronize();
+    for (void *p : n->allocs) hipFree(p);
+    delete n;
+}
+
+osm_status osm_net_create(int32_t max_traces, void *hip_stream, osm_net **out) {
+    if (!out) return OSM_EINVAL;
+    *out = nullptr;
+    if (max_traces < 1 || max_traces > (1 << 20))
+        return nfail(nullptr, OSM_EINVAL, "max_traces must be in [1, 2^20]");
+    osm_net *n = new osm_net();
+    n->st = (hipStream_t)hip_stream;
+    n->max_traces = max_traces;
+    int np = net_nparams();
+    auto al = [&](void **p, size_t bytes) -> bool {
+        if (hipMalloc(p, bytes) != hipSuccess) return false;
+        n->allocs.push_back(*p);
+        return true;
+    };
+    bool ok = al((void **)&n->theta, sizeof(float) * np) && al((void **)&n->m, sizeof(float) * np) &&
+              al((void **)&n->v, sizeof(float) * np) && al((void **)&n->grad, sizeof(float) * np) &&
+              al((void **)&n->pbf, sizeof(uint16_t) * np) &&
+              al((void **)&n->gpart, sizeof(float) * (size_t)np * max_traces) &&
+              al((void **)&n->lpart, sizeof(float) * max_traces) && al((void **)&n->loss_d, 64);
+    if (!ok) {
+        osm_net_destroy(n);
+        return nfail(nullptr, OSM_ENOMEM, "hipMalloc failed for the guess network");
+    }
+    if (hipMemset(n->theta, 0, sizeof(float) * np) != hipSuccess ||
+        hipMemset(n->pbf, 0, sizeof(uint16_t) * np) != hipSuccess) {
+        osm_net_destroy(n);
+        return nfail(nullptr, OSM_EHIP, "hipMemset failed");
+    }
+    *out = n;
+    return OSM_OK;
+}
+
+osm_status osm_net_set_params(osm_net *n, const float *theta_dev) {
+    if (!n) return OSM_EINVAL;
+    if (!theta_dev) return nfail(n, OSM_EINVAL, "theta_dev is NULL");
+    NHIPCHK(n, launch_net_set(n->st, theta_dev, n->theta, n->pbf, n->m, n->v));
+    NHIPCHK(n, hipStreamSynchronize(n->st));
+    n->t = 0;
+    n->has_params = true;
+    return OSM_OK;
+}
+
+osm_status osm_net_get_params(const osm_net *n, int32_t rounded, float *theta_dev) {
+    if (!n) return OSM_EINVAL;
+    if (!theta_dev) return OSM_EINVAL;
+    if (launch_net_get(n->st, n->theta, n->pbf, rounded, theta_dev) != hipSuccess) return OSM_EHIP;
+    if (hipStreamSynchronize(n->st) != hipSuccess) return OSM_EHIP;
+    return OSM_OK;
+}
+
+static osm_status net_check(osm_net *n, const void *x, const void *y, int32_t T, int32_t L) {
+    if (!x || !y) return nfail(n, OSM_EINVAL, "null tensor");
+    if (T < 1 || L < 1) return nfail(n, OSM_EINVAL, "T and L must be >= 1");
+    if (!n->has_params) return nfail(n, OSM_ESTATE, "osm_net_set_params must be called first");
+    return OSM_OK;
+}
+
+osm_status osm_net_forward(osm_net *n, const float *x_dev, int32_t T, int32_t L, float *y_dev) {
+    if (!n) return OSM_EINVAL;
+    osm_status s = net_check(n, x_dev, y_dev, T, L);
+    if (s != OSM_OK) return s;
+    NHIPCHK(n, launch_net_forward(n->st, n->pbf, x_dev, T, L, y_dev));
+    NHIPCHK(n, hipStreamSynchronize(n->st));
+    return OSM_OK;
+}
+
+osm_status osm_net_loss_grad(osm_net *n, const float *x_dev, const float *t_dev, int32_t T,
+                             int32_t L, float *grad_dev, double *loss) {
+    if (!n) return OSM_EINVAL;
+    osm_status s = net_check(n, x_dev, t_dev, T, L);
+    if (s != OSM_OK) return s;
+    if (T > n->max_traces) return nfail(n, OSM_EINVAL, "T exceeds max_traces");
+    NHIPCHK(n, launch_net_loss_grad(n->st, n->pbf, x_dev, t_dev, T, L, n->gpart, n->lpart,
+                                    grad_dev ? grad_dev : n->grad, n->loss_d));
+    if (loss) NHIPCHK(n, hipMemcpyAsync(loss, n->loss_d, sizeof(double), hipMemcpyDeviceToHost, n->st));
+    NHIPCHK(n, hipStreamSynchronize(n->st));
+    return OSM_OK;
+}
+
+osm_status osm_net_train_step(osm_net *n, const float *x_dev, const float *t_dev, int32_t T,
+                              int32_t L, double lr, double *loss) {
+    if (!n) return OSM_EINVAL;
+    osm_status s = net_check(n, x_dev, t_dev, T, L);
+    if (s != OSM_OK) return s;
+    if (T > n->max_traces) return nfail(n, OSM_EINVAL, "T exceeds max_traces");
+    if (!(lr > 0)) return nfail(n, OSM_EINVAL, "lr must be > 0");
+    NHIPCHK(n, launch_net_loss_grad(n->st, n->pbf, x_dev, t_dev, T, L, n->gpart, n->lpart, n->grad,
+                                    n->loss_d));
+    n->t += 1;
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    double c1 = 1.0 / (1.0 - pow(b1, n->t)), c2 = 1.0 / (1.0 - pow(b2, n->t));
+    NHIPCHK(n, launch_net_adam(n->st, n->theta, n->pbf, n->m, n->v, n->grad, (float)lr, (float)b1,
+                               (float)b2, (float)eps, (float)c1, (float)c2));
+    if (loss) {
+        NHIPCHK(n, hipMemcpyAsync(loss, n->loss_d, sizeof(double), hipMemcpyDeviceToHost, n->st));
+        NHIPCHK(n, hipStreamSynchronize(n->st));
+    }
+    return OSM_OK;
+}
+
+const char *osm_net_last_error(const osm_net *n) {
+    if (!n) return g_setup_error.c_str();
+    return n->err.c_str();
+}
+
+osm_status osm_set_guess_net(osm_handle *h, const osm_net *net) {
+    if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
+    if (net && !net->has_params) return fail(h, OSM_ESTATE, "the network has no parameters");
+    h->net = net;
+    h->fallback_next = false;
+    return OSM_OK;
+}
+
+osm_status osm_guess_features(osm_handle *h, const osm_c64 *g1_dev, const osm_c64 *g2_dev,
+                              const osm_c64 *g0_dev, float *x_dev, float *t_dev) {
+    if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
+    if (!g1_dev || !g2_dev || !x_dev) return fail(h, OSM_EINVAL, "null vector");
+    if ((g0_dev == nullptr) != (t_dev == nullptr))
+        return fail(h, OSM_EINVAL, "g0_dev and t_dev must both be given or both be NULL");
+    if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called first (W_n)");
+    HIPCHK(h, launch_net_features(h->st, h->P, h->strips_d, (const double2 *)g1_dev,
+                                  (const double2 *)g2_dev, (const double2 *)g0_dev, h->W_d, x_dev,
+                                  t_dev, h->nS));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return OSM_OK;
+}
 
 // ====================================================================== batch
 // Independent instances solved together: every time-step kernel covers all

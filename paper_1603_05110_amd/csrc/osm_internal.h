@@ -172,6 +172,8 @@ struct StepCtl {
     int ready;      // a new Schwarz iteration may start (batched replay)
     double tq;      // fixed-point tolerance of the current Schwarz map
     double inc, ref, prev_rel;
+    double first_rel;  // relative increment of the first Schwarz iteration of the
+                       // last step (kept across steps; 0 = none yet)
 };
 struct GmresCtl;
 hipError_t launch_step_init(hipStream_t st, StepCtl *c, const StepCfg &cfg);
@@ -300,3 +302,30 @@ hipError_t launch_batch_solve(hipStream_t st, const BatchSolveArgs &a, int fp32,
 int batch_solve_variants();
 const char *batch_solve_variant_name(int fp32, int variant);
 int batch_solve_max_resident_blocks(int fp32, int variant, int max_n);
+
+// ---------------------------------------------------------------- learned guess
+// kernels_net.hip: network conv1d(9->64,k5) -> GELU -> conv1d(64->4,k5) over
+// interface lines; bf16 parameter copy, FP32 master, FP32 accumulation.
+int net_nparams();
+hipError_t launch_net_forward(hipStream_t st, const uint16_t *pbf, const float *X, int T, int L,
+                              float *Y);
+hipError_t launch_net_loss_grad(hipStream_t st, const uint16_t *pbf, const float *X,
+                                const float *Yt, int T, int L, float *gpart, float *lpart,
+                                float *grad, double *loss);
+hipError_t launch_net_adam(hipStream_t st, float *theta, uint16_t *pbf, float *m, float *v,
+                           const float *grad, float lr, float b1, float b2, float eps, float c1,
+                           float c2);
+hipError_t launch_net_set(hipStream_t st, const float *src, float *theta, uint16_t *pbf, float *m,
+                          float *v);
+hipError_t launch_net_get(hipStream_t st, const float *theta, const uint16_t *pbf, int rounded,
+                          float *dst);
+// inputs (nsub-1, 9, ny), scales (nsub-1) and, when g0 and Yt are given, the
+// targets (nsub-1, 4, ny)
+hipError_t launch_net_features(hipStream_t st, const Phys &P, const StripMeta *strips,
+                               const double2 *g1, const double2 *g2, const double2 *g0,
+                               const double *W, float *X, float *Yt, double *S);
+// g = 2 g1 - g2 + S * Y (network output), or the linear extrapolation 2 g1 - g2 when Y is null
+hipError_t launch_net_guess(hipStream_t st, const Phys &P, const double2 *g1, const double2 *g2,
+                            const float *Y, const double *S, double2 *g);
+hipError_t launch_net_judge(hipStream_t st, long n, const double2 *g, const double2 *a,
+                            const double2 *b, double *part);

@@ -288,7 +288,10 @@ __device__ __forceinline__ void step_init_body(StepCtl *c, const StepCfg &cfg) {
     c->gm_total = 0;
     c->ready = 1;
     c->tq = cfg.tol_q;
-    c->inc = 0.0; c->ref = 0.0; c->prev_rel = 1.0;
+    c->inc = 0.0; c->ref = 0.0;
+    // the first inner tolerance of this step follows the first increment of
+    // the last one (how far the start of the iteration was from its map)
+    c->prev_rel = c->first_rel > 0.0 ? fmin(1.0, c->first_rel) : 1.0;
 }
 
 // Start of a Schwarz iteration (thread 0 only): new fixed point, tolerance
@@ -356,6 +359,7 @@ __device__ __forceinline__ void flux_finalize_block(const double *part, int nt, 
     c->inc = inc;
     c->ref = ref;
     c->prev_rel = inc / fmax(ref, 1e-300);
+    if (c->k == 1) c->first_rel = c->prev_rel;
     double thr = c->cfg.tol_k_rel ? c->cfg.tol_k * fmax(ref, 1e-300) : c->cfg.tol_k;
     if (c->cfg.fixed_k > 0) { if (c->k >= c->cfg.fixed_k) c->k_done = 1; }
     else if (inc < thr) c->k_done = 1;

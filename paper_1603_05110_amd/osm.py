@@ -68,9 +68,12 @@ class osm_footprint(ctypes.Structure):
 EXPORTS = ["osm_query", "osm_setup", "osm_factor", "osm_factor_rotating", "osm_step",
            "osm_interface_apply", "osm_set_interface_guess", "osm_get_interface",
            "osm_strip_solve", "osm_get_strip_solution", "osm_get_lh_blocks", "osm_get_factor",
-           "osm_kernel_timing", "osm_kernel_work", "osm_solve_team", "osm_query_batch", "osm_setup_batch",
-           "osm_factor_batch", "osm_step_batch", "osm_batch_tuning", "osm_destroy",
-           "osm_last_error"]
+           "osm_kernel_timing", "osm_kernel_work", "osm_solve_team",
+           "osm_net_nparams", "osm_net_create", "osm_net_set_params", "osm_net_get_params",
+           "osm_net_forward", "osm_net_loss_grad", "osm_net_train_step", "osm_net_destroy",
+           "osm_net_last_error", "osm_guess_features", "osm_set_guess_net",
+           "osm_query_batch", "osm_setup_batch", "osm_factor_batch", "osm_step_batch",
+           "osm_batch_tuning", "osm_destroy", "osm_last_error"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -99,6 +102,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "osm_kernel_timing": ([H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int64)], st),
         "osm_kernel_work": ([H, ctypes.POINTER(ctypes.c_double)], st),
+        "osm_net_nparams": ([], ctypes.c_int32),
+        "osm_net_create": ([ctypes.c_int32, P, ctypes.POINTER(H)], st),
+        "osm_net_set_params": ([H, P], st),
+        "osm_net_get_params": ([H, ctypes.c_int32, P], st),
+        "osm_net_forward": ([H, P, ctypes.c_int32, ctypes.c_int32, P], st),
+        "osm_net_loss_grad": ([H, P, P, ctypes.c_int32, ctypes.c_int32, P,
+                               ctypes.POINTER(ctypes.c_double)], st),
+        "osm_net_train_step": ([H, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                ctypes.POINTER(ctypes.c_double)], st),
+        "osm_net_destroy": ([H], None),
+        "osm_net_last_error": ([H], ctypes.c_char_p),
+        "osm_guess_features": ([H, P, P, P, P, P], st),
+        "osm_set_guess_net": ([H, H], st),
         "osm_query_batch": ([ctypes.POINTER(osm_problem), ctypes.c_int32,
                              ctypes.POINTER(osm_options), ctypes.POINTER(osm_footprint)], st),
         "osm_setup_batch": ([ctypes.POINTER(osm_problem), ctypes.c_int32,
@@ -247,6 +263,20 @@ class OsmSolver:
     def solve_team(self):
         return int(_lib.osm_solve_team(self.h))
 
+    def guess_features(self, g1, g2, g0=None):
+        """Network inputs (nsub-1, 9, ny) and, with g0, targets (nsub-1, 4, ny)."""
+        T = self.pb.nsub - 1
+        x = torch.empty((T, 9, self.ny), dtype=torch.float32, device=self.device)
+        t = None
+        if g0 is not None:
+            t = torch.empty((T, 4, self.ny), dtype=torch.float32, device=self.device)
+        self._c(_lib.osm_guess_features(self.h, _ptr(g1), _ptr(g2), _ptr(g0), _ptr(x), _ptr(t)))
+        return x, t
+
+    def set_guess_net(self, net):
+        self._c(_lib.osm_set_guess_net(self.h, net.h if net is not None else None))
+        self._net = net
+
     def kernel_timing(self, enable: bool):
         """Returns (summed solve-kernel ms, launches) since the last reset."""
         ms = ctypes.c_double()
@@ -358,6 +388,70 @@ class OsmBatch:
     def close(self):
         if self.h:
             _lib.osm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+NET_NPARAMS = int(_lib.osm_net_nparams())
+
+
+class OsmNet:
+    """The interface-guess network (include/osm.h, learned guess)."""
+
+    def __init__(self, max_traces=1024, device="cuda:0"):
+        self.device = torch.device(device)
+        self.max_traces = max_traces
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            h = ctypes.c_void_p()
+            st = _lib.osm_net_create(int(max_traces), ctypes.c_void_p(stream), ctypes.byref(h))
+            if st != OSM_OK:
+                raise OsmError(st, (_lib.osm_net_last_error(None) or b"").decode())
+        self.h = h
+
+    def _c(self, status):
+        if status != OSM_OK:
+            raise OsmError(status, (_lib.osm_net_last_error(self.h) or b"").decode())
+
+    def set_params(self, theta):
+        theta = torch.as_tensor(theta, dtype=torch.float32).to(self.device).contiguous()
+        assert theta.numel() == NET_NPARAMS
+        self._c(_lib.osm_net_set_params(self.h, _ptr(theta)))
+
+    def get_params(self, rounded=False):
+        out = torch.empty(NET_NPARAMS, dtype=torch.float32, device=self.device)
+        self._c(_lib.osm_net_get_params(self.h, int(rounded), _ptr(out)))
+        return out
+
+    def forward(self, x):
+        assert x.dtype == torch.float32 and x.is_contiguous() and x.dim() == 3
+        T, C, L = x.shape
+        y = torch.empty((T, 4, L), dtype=torch.float32, device=self.device)
+        self._c(_lib.osm_net_forward(self.h, _ptr(x), T, L, _ptr(y)))
+        return y
+
+    def loss_grad(self, x, t):
+        T, _, L = x.shape
+        g = torch.empty(NET_NPARAMS, dtype=torch.float32, device=self.device)
+        loss = ctypes.c_double()
+        self._c(_lib.osm_net_loss_grad(self.h, _ptr(x), _ptr(t), T, L, _ptr(g), ctypes.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, x, t, lr, want_loss=True):
+        T, _, L = x.shape
+        loss = ctypes.c_double()
+        self._c(_lib.osm_net_train_step(self.h, _ptr(x), _ptr(t), T, L, float(lr),
+                                        ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if self.h:
+            _lib.osm_net_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -105,3 +105,16 @@ def test_batch_setup_reports_enomem_before_allocating():
     st = osm._lib.osm_setup_batch(arr, 2, ctypes.byref(opt), None, ctypes.byref(h))
     assert st == osm.OSM_ENOMEM
     assert not h.value
+
+
+def test_guess_options_and_network_arguments_are_checked_on_the_host():
+    import ctypes
+    from paper_1603_05110_amd import osm
+    with pytest.raises(osm.OsmError) as e:
+        osm.osm_query(_pb(), guess=4)
+    assert e.value.status == osm.OSM_EINVAL
+    h = ctypes.c_void_p()
+    assert osm._lib.osm_net_create(0, None, ctypes.byref(h)) == osm.OSM_EINVAL
+    assert not h.value
+    from oracle import nn
+    assert osm.NET_NPARAMS == nn.NPARAM

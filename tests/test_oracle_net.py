@@ -106,8 +106,12 @@ def test_features_targets_guess_are_consistent():
     assert lines == [6, 13]
     assert np.allclose(x[1, 8] * max(1.0, np.max(np.abs(W[13]))), W[13])
     # the guess built from the exact targets is the next interface vector
-    y = nn.targets(g0, g1, s)
-    assert np.allclose(nn.guess(g1, y, s), g0, rtol=1e-14, atol=1e-14)
+    y = nn.targets(g0, g1, g2, s)
+    assert np.allclose(nn.guess(g1, g2, y, s), g0, rtol=1e-13, atol=1e-13)
+    # zero output is linear extrapolation; on a sequence linear in n the
+    # targets vanish
+    assert np.allclose(nn.guess(g1, g2, np.zeros_like(y), s), 2 * g1 - g2)
+    assert np.allclose(nn.targets(3 * g1 - 2 * g2, 2 * g1 - g2, g1, s), 0, atol=1e-14)
     # a zero trace gets scale 1
     g1z = g1.copy()
     g1z[0] = 0

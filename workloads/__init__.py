@@ -271,3 +271,22 @@ def c5(ncells: int = 2048, nsub: int = 64, steps: int = 1000) -> Workload:
                  vxx=-0.5, vyy=-0.6)
     u0 = vortex_gaussian(pb, rng)
     return Workload([pb], [u0], [None], algo="precond", label="C5")
+
+
+# --------------------------------------------------------------------------
+# Learned interface guess: seeded initial parameters
+# --------------------------------------------------------------------------
+
+NET_SHAPES = [(64, 9, 5), (64,), (4, 64, 5), (4,)]
+
+
+def net_init(seed: int) -> np.ndarray:
+    """Initial parameters of the guess network, flat float32 in the order
+    W1 (64,9,5), b1 (64), W2 (4,64,5), b2 (4): weights uniform in
+    +-1/sqrt(fan_in), biases zero; the output layer is scaled by 0.1 so the
+    untrained network predicts a small change."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 4000 + seed))
+    w1 = rng.uniform(-1, 1, NET_SHAPES[0]) / np.sqrt(9 * 5)
+    w2 = 0.1 * rng.uniform(-1, 1, NET_SHAPES[2]) / np.sqrt(64 * 5)
+    parts = [w1, np.zeros(64), w2, np.zeros(4)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
