@@ -248,6 +248,102 @@ def run_batch(args, dev):
     print(json.dumps(out), flush=True)
 
 
+def run_learned(args, dev):
+    """Learned interface guess: interface traces from seeded runs of the GPE
+    family V = -(x^2+y^2)/(2 w^2), w ~ U[0.5, 2], beta ~ -U[10, 200]
+    (512^2 cells, 16 strips, 200 steps each), the network trained on them by
+    the library's kernels, then a held-out 1024^2-cell, 32-strip member run
+    from the previous converged vector (the paper's start), from linear
+    extrapolation and from the learned prediction."""
+    import numpy as np
+    import torch
+
+    from paper_1603_05110_amd import learned, osm
+    from workloads import c4, c4_family, net_init, rng_for
+
+    opts = dict(solver_opts("c32"))
+    t0 = time.perf_counter()
+    Xs, Ts = [], []
+    rng = rng_for(4, salt=1)
+    for r in range(args.train_runs):
+        pb, u0, V = c4_family(rng, ncells=512, nsub=16, steps=200)
+        s = osm.OsmSolver(pb, dev, **opts)
+        s.factor(torch.from_numpy(V).to(dev))
+        X, T, _ = learned.collect_traces(s, torch.from_numpy(u0).to(dev), pb.steps)
+        s.close()
+        Xs.append(X)
+        Ts.append(T)
+        print(f"bench: training run {r}: {pb.name}, {X.shape[0]} traces", file=sys.stderr, flush=True)
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    del Xs, Ts
+    t_data = time.perf_counter() - t0
+    net = osm.OsmNet(args.batch, dev)
+    net.set_params(torch.from_numpy(net_init(0)))
+    t0 = time.perf_counter()
+    losses = learned.train(net, X, T, epochs=args.epochs, batch=args.batch, lr=args.lr, seed=0,
+                           log=lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ntr = int(X.shape[0])
+    del X, T
+    wl = c4(steps=args.steps)
+    pb, u0, V = wl.problems[0], wl.u0[0], wl.V[0]
+    dof = (pb.ncx + 1) * (pb.ncy + 1)
+    runs = {}
+    for name, guess in [("previous", 0), ("extrapolated", 3), ("learned", 2)]:
+        s = osm.OsmSolver(pb, dev, **dict(opts, guess=guess))
+        if guess == 2:
+            s.set_guess_net(net)
+        Wd = torch.from_numpy(V).to(dev)
+        u = torch.from_numpy(u0).to(dev)
+        s.factor(Wd)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        s.factor(Wd)
+        st = [s.step(u) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        T_run = time.perf_counter() - ta
+        s.close()
+        runs[name] = {"value": dof * args.steps / T_run, "ms_per_step": 1e3 * T_run / args.steps,
+                      "k_total": int(sum(x["k"] for x in st)),
+                      "k_after_step2": int(sum(x["k"] for x in st[2:])),
+                      "q_total": int(sum(x["q_total"] for x in st)),
+                      "gmres_total": int(sum(x["gmres_total"] for x in st)),
+                      "fallbacks": int(sum(x["fallback_used"] for x in st)),
+                      "u": u.cpu().numpy()}
+        print(f"bench: {name}: {runs[name]['value']:.4g} dof-steps/s, k {runs[name]['k_total']}, "
+              f"gmres {runs[name]['gmres_total']}", file=sys.stderr, flush=True)
+    ref = runs["previous"].pop("u")
+    for name in ("extrapolated", "learned"):
+        u = runs[name].pop("u")
+        runs[name]["rel_l2_vs_previous_start"] = float(np.linalg.norm(u - ref) / np.linalg.norm(ref))
+    net.close()
+    out = {
+        "metric": METRIC,
+        "value": runs["learned"]["value"],
+        "unit": "dof-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 0,
+        "ms_per_step": runs["learned"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64-refine; network bf16/f32",
+        "data": "synthetic",
+        "config": {"workload": "learned interface guess: GPE family V=-(x^2+y^2)/(2w^2), "
+                               "w~U[0.5,2], beta~-U[10,200]; inference on (-8,8)^2, 1024^2 cells, "
+                               "32 strips, p=5, dt=1e-3, preconditioned",
+                   "dof": dof, "strips": pb.nsub, "training_traces": ntr,
+                   "training_runs": args.train_runs, "epochs": args.epochs,
+                   "timed": "factor(W) + steps, per start"},
+        "starts": runs,
+        "training": {"data_s": t_data, "train_s": t_train, "loss_first": losses[0],
+                     "loss_last": losses[-1]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,9 +354,14 @@ def main():
                     help="steps of the plain FP64 GPU path timed for comparison (0 = skip)")
     ap.add_argument("--parity-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="gpe512", choices=["gpe512", "batch64"],
+    ap.add_argument("--workload", default="gpe512", choices=["gpe512", "batch64", "learned1024"],
                     help="gpe512: the single GPE instance (default); batch64: the batch of "
-                         "64 independent NLS instances")
+                         "64 independent NLS instances; learned1024: the learned interface "
+                         "guess, trained and then run on a 1024^2 GPE")
+    ap.add_argument("--train-runs", type=int, default=34)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--profile-solve", type=int, default=0, metavar="LAUNCHES",
                     help="profiler mode: only factor + LAUNCHES strip solves + a 1 GiB copy")
     args = ap.parse_args()
@@ -278,6 +379,9 @@ def main():
     dev = "cuda:0"
     if args.workload == "batch64":
         run_batch(args, dev)
+        return
+    if args.workload == "learned1024":
+        run_learned(args, dev)
         return
     wl = c2()
     pb, u0, V = wl.problems[0], wl.u0[0], wl.V[0]
