@@ -138,11 +138,12 @@ __global__ void check_finite_kernel(const double2 *x, long n, int *flag) {
     if (bad) atomicOr(flag, 1);
 }
 
-// Largest |b| over one strip (one block per strip), returned as the power
-// of two that maps it into [1, 2).
-__device__ __forceinline__ void strip_scale_body(const double2 *b, long count, double *out) {
+// Largest |b| (real and imaginary parts) of every packed line: one block
+// per line.  The complex-FP32 solve turns the largest value of a strip into
+// a power-of-two scale.
+__device__ __forceinline__ void line_absmax_body(const double2 *b, int n, double *out) {
     double m = 0.0;
-    for (long e = threadIdx.x; e < count; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
         double2 v = b[e];
         m = fmax(m, fmax(fabs(v.x), fabs(v.y)));
     }
@@ -153,36 +154,32 @@ __device__ __forceinline__ void strip_scale_body(const double2 *b, long count, d
         if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        double mx = red[0];
-        *out = (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ilogb(mx)) : 1.0;
-    }
+    if (threadIdx.x == 0) *out = red[0];
 }
 
-__global__ void strip_scale_kernel(Phys P, const StripMeta *strips, const double2 *b,
-                                   double *scale, const StepCtl *c) {
+__global__ void line_absmax_kernel(int ny, const double2 *b, double *lmax, const StepCtl *c) {
     if (c && fp_idle(c)) return;
-    StripMeta s = strips[blockIdx.x];
-    strip_scale_body(b + (long)s.off * P.ny, (long)s.nx * P.ny, scale + blockIdx.x);
+    line_absmax_body(b + (long)blockIdx.x * ny, ny, lmax + blockIdx.x);
 }
 
-__global__ void b_strip_scale_kernel(const BStrip *strips, double *scale, int guard) {
-    const BStrip &s = strips[blockIdx.x];
+__global__ void b_line_absmax_kernel(const BStrip *strips, int guard) {
+    const BStrip &s = strips[blockIdx.y];
+    if ((int)blockIdx.x >= s.nx) return;
     if (guard && s.ctl && fp_idle(s.ctl)) return;
-    strip_scale_body(s.b, (long)s.nx * s.n, scale + blockIdx.x);
+    line_absmax_body(s.b + (long)blockIdx.x * s.n, s.n, s.lmax + blockIdx.x);
 }
 
 }  // namespace
 
-hipError_t launch_strip_scale(hipStream_t st, const Phys &P, const StripMeta *strips,
-                              const double2 *b, double *scale, const StepCtl *c) {
-    hipLaunchKernelGGL(strip_scale_kernel, dim3(P.nsub), dim3(256), 0, st, P, strips, b, scale, c);
+hipError_t launch_line_absmax(hipStream_t st, const Phys &P, const double2 *b, double *lmax,
+                              const StepCtl *c) {
+    hipLaunchKernelGGL(line_absmax_kernel, dim3(P.lt), dim3(256), 0, st, P.ny, b, lmax, c);
     return hipGetLastError();
 }
 
-hipError_t launch_b_strip_scale(hipStream_t st, const BStrip *strips, int nstrips,
-                                double *scale, int guard) {
-    hipLaunchKernelGGL(b_strip_scale_kernel, dim3(nstrips), dim3(256), 0, st, strips, scale,
+hipError_t launch_b_line_absmax(hipStream_t st, const BStrip *strips, int nstrips, int max_nx,
+                                int guard) {
+    hipLaunchKernelGGL(b_line_absmax_kernel, dim3(max_nx, nstrips), dim3(256), 0, st, strips,
                        guard);
     return hipGetLastError();
 }

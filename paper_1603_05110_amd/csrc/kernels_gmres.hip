@@ -20,6 +20,17 @@ __device__ __forceinline__ void lh_matvec_body(Phys P, const StripMeta *strips,
                                                const double2 *LH, const double2 *x, double2 *y,
                                                int mode_p);
 
+// Workgroup b -> (trace, tile of 4 rows).  Workgroups are dispatched to the 8
+// XCDs round-robin; all traces of one row tile are given to consecutive
+// workgroups of one XCD, so the tile's rows of the (shared) blocks X^{.,1..4}
+// are read from HBM once and then from that XCD's L2.
+__device__ __forceinline__ bool lh_tile_of(int b, int ntr, int ntile, int *t, int *tile) {
+    int xcd = b & 7, m = b >> 3;
+    *t = m % ntr;
+    *tile = (m / ntr) * 8 + xcd;
+    return *tile < ntile;
+}
+
 __global__ __launch_bounds__(256) void lh_matvec_kernel(Phys P, const StripMeta *strips,
                                                         const double2 *LH, const double2 *x,
                                                         double2 *y, int mode_p) {
@@ -29,10 +40,11 @@ __global__ __launch_bounds__(256) void lh_matvec_kernel(Phys P, const StripMeta 
 __device__ __forceinline__ void lh_matvec_body(Phys P, const StripMeta *strips,
                                                const double2 *LH, const double2 *x, double2 *y,
                                                int mode_p) {
-    int t = blockIdx.y;
     int n = P.ny;
+    int t, tile;
+    if (!lh_tile_of(blockIdx.x, 2 * (P.nsub - 1), (n + 3) / 4, &t, &tile)) return;
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int a = blockIdx.x * 4 + wave;
+    int a = tile * 4 + wave;
     if (a >= n) return;
     int i = t >> 1;
     int strip, blk_l, blk_r, src_l, src_r;
@@ -75,6 +87,74 @@ __device__ __forceinline__ void lh_matvec_body(Phys P, const StripMeta *strips,
             y[o] = cd(xv.x - sr, xv.y - si);
         } else {
             y[o] = cd(sr, si);
+        }
+    }
+}
+
+// L_h x with every block row reused over many strips.  Workgroup
+// (tile, class, group) owns rows [a0, a0 + 2R) of the blocks of one strip
+// class.  Wave w computes output side w & 1 for R rows: side 0 is trace
+// 2(j-1) (new r_{j-1}) = X^1 l_j + X^2 r_j, side 1 is trace 2j+1
+// (new l_{j+1}) = X^3 l_j + X^4 r_j (eq. Lmpi; l_0 and r_{N-1} are zero).
+// It keeps its R rows of its two blocks in registers and loops over the
+// strips j = group, group + G, ... of that class, writing each result
+// itself; every output trace has exactly one writer and no barrier is needed.
+template <int NCH, int R>
+__global__ __launch_bounds__(256) void lh_matvec_reg_kernel(Phys P, const StripMeta *strips,
+                                                            const double2 *LH, const double2 *x,
+                                                            double2 *y, int mode_p,
+                                                            const GmresCtl *ctl) {
+    if (ctl && ctl->done) return;
+    const int n = P.ny, N = P.nsub, cls = blockIdx.y, G = gridDim.z;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int side = wave & 1, r0 = blockIdx.x * 2 * R + (wave >> 1) * R;
+    const long nn = (long)n * n;
+    const double2 *B0 = LH + ((long)cls * 4 + 2 * side) * nn;   // multiplies l_j
+    const double2 *B1 = B0 + nn;                                // multiplies r_j
+    double2 m0[R][NCH], m1[R][NCH];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            int row = r0 + rr, col = c * 64 + lane;
+            bool ok = row < n && col < n;
+            m0[rr][c] = ok ? B0[(long)row * n + col] : cd(0.0, 0.0);
+            m1[rr][c] = ok ? B1[(long)row * n + col] : cd(0.0, 0.0);
+        }
+    for (int j = blockIdx.z; j < N; j += G) {
+        if (strips[j].cls != cls) continue;
+        bool has = side == 0 ? j >= 1 : j <= N - 2;
+        if (!has) continue;
+        const double2 *vl = j >= 1 ? x + (long)(2 * (j - 1) + 1) * n : nullptr;
+        const double2 *vr = j <= N - 2 ? x + (long)(2 * j) * n : nullptr;
+        double ar[R], ai[R];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) { ar[rr] = 0.0; ai[rr] = 0.0; }
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            int col = c * 64 + lane;
+            double2 wl = (vl && col < n) ? vl[col] : cd(0.0, 0.0);
+            double2 wr = (vr && col < n) ? vr[col] : cd(0.0, 0.0);
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                ar[rr] += m0[rr][c].x * wl.x - m0[rr][c].y * wl.y + m1[rr][c].x * wr.x - m1[rr][c].y * wr.y;
+                ai[rr] += m0[rr][c].x * wl.y + m0[rr][c].y * wl.x + m1[rr][c].x * wr.y + m1[rr][c].y * wr.x;
+            }
+        }
+        int t = side == 0 ? 2 * (j - 1) : 2 * j + 1;
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            double sr = wsum(ar[rr]), si = wsum(ai[rr]);
+            int a = r0 + rr;
+            if (lane == 0 && a < n) {
+                long o = (long)t * n + a;
+                if (mode_p) {
+                    double2 xv = x[o];
+                    y[o] = cd(xv.x - sr, xv.y - si);
+                } else {
+                    y[o] = cd(sr, si);
+                }
+            }
         }
     }
 }
@@ -159,44 +239,115 @@ __global__ void axpby_kernel(long n, double2 a, const double2 *x, double2 b, con
 // ctl->done first and returns at once when the cycle has converged, so the
 // host can enqueue several iterations ahead and synchronise once per chunk.
 
-// block k: dots[k] = V_k^H w
-__global__ __launch_bounds__(256) void cgs_dots_kernel(long n, const double2 *V, const double2 *w,
-                                                       double2 *dots, const GmresCtl *ctl) {
-    if (ctl->done) return;
-    __shared__ double rr[4], ri[4];
-    int k = blockIdx.x;
-    const double2 *vk = V + (long)k * n;
-    double sr = 0.0, si = 0.0;
-    for (long e = threadIdx.x; e < n; e += blockDim.x) {
-        double2 a = vk[e], b = w[e];
-        sr += a.x * b.x + a.y * b.y;
-        si += a.x * b.y - a.y * b.x;
-    }
-    sr = wsum(sr);
-    si = wsum(si);
-    int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { rr[wave] = sr; ri[wave] = si; }
-    __syncthreads();
-    if (threadIdx.x == 0)
-        dots[k] = cd(rr[0] + rr[1] + rr[2] + rr[3], ri[0] + ri[1] + ri[2] + ri[3]);
+// Classical Gram-Schmidt, twice, split over at most 256 contiguous chunks:
+// each workgroup owns one chunk of w and writes its partial dot products
+// with every basis vector; the next kernel reduces the partials of all
+// chunks in a fixed order (deterministic).  part layout: [chunk][k], stride
+// ld = m + 1.
+
+__device__ __forceinline__ void chunk_range(long n, long *lo, long *hi) {
+    long c = (n + gridDim.x - 1) / gridDim.x;
+    *lo = min(n, (long)blockIdx.x * c);
+    *hi = min(n, *lo + c);
 }
 
-// w -= sum_{k<nv} dots[k] V_k; with norm_part, per-block partial |w|^2
+// Partial of V_k^H w over this workgroup's chunk, for k < nv, into part.
+__device__ __forceinline__ void chunk_dots(long n, const double2 *V, int nv, const double2 *w,
+                                           long lo, long hi, double2 *part, int ld) {
+    __shared__ double rr[4][64], ri[4][64];
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k0 = 0; k0 < nv; k0 += 64) {
+        int kn = min(64, nv - k0);
+        for (int kk = 0; kk < kn; ++kk) {
+            const double2 *vk = V + (long)(k0 + kk) * n;
+            double sr = 0.0, si = 0.0;
+            for (long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+                double2 a = vk[e], wv = w[e];
+                sr += a.x * wv.x + a.y * wv.y;       // conj(a) * w
+                si += a.x * wv.y - a.y * wv.x;
+            }
+            sr = wsum(sr);
+            si = wsum(si);
+            if (lane == 0) { rr[wave][kk] = sr; ri[wave][kk] = si; }
+        }
+        __syncthreads();
+        if (threadIdx.x < kn) {
+            int kk = threadIdx.x;
+            part[(long)blockIdx.x * ld + k0 + kk] =
+                cd(rr[0][kk] + rr[1][kk] + rr[2][kk] + rr[3][kk],
+                   ri[0][kk] + ri[1][kk] + ri[2][kk] + ri[3][kk]);
+        }
+        __syncthreads();
+    }
+}
+
+// dots[k] = sum over chunks of part[.][k], k < nv, into LDS (dots may be
+// added to an existing value with add = 1).  A block of 256 threads splits
+// every sum four ways (chunk b goes to quarter b % 4, four independent
+// accumulators each) and adds the quarters in a fixed order, so the result
+// is deterministic and the loads are in flight together.
+__device__ __forceinline__ void reduce_dots(const double2 *part, int nb, int ld, int nv,
+                                            double2 *dots, int add = 0) {
+    __shared__ double2 q4[4][64];
+    const int kk = threadIdx.x & 63, q = threadIdx.x >> 6;
+    for (int k0 = 0; k0 < nv; k0 += 64) {
+        int k = k0 + kk;
+        double2 a0 = cd(0.0, 0.0), a1 = a0, a2 = a0, a3 = a0;
+        if (k < nv) {
+            int b = q;
+            for (; b + 12 < nb; b += 16) {
+                a0 = cadd(a0, part[(long)b * ld + k]);
+                a1 = cadd(a1, part[(long)(b + 4) * ld + k]);
+                a2 = cadd(a2, part[(long)(b + 8) * ld + k]);
+                a3 = cadd(a3, part[(long)(b + 12) * ld + k]);
+            }
+            for (; b < nb; b += 4) a0 = cadd(a0, part[(long)b * ld + k]);
+        }
+        q4[q][kk] = cadd(cadd(a0, a1), cadd(a2, a3));
+        __syncthreads();
+        if (q == 0 && k < nv) {
+            double2 t = cadd(cadd(q4[0][kk], q4[1][kk]), cadd(q4[2][kk], q4[3][kk]));
+            dots[k] = add ? cadd(dots[k], t) : t;
+        }
+        __syncthreads();
+    }
+}
+
+// First pass: partial dots of w = V_{j+1} (the new Arnoldi vector) with V_0..V_j.
+__global__ __launch_bounds__(256) void cgs_dots_kernel(long n, const double2 *V, int nv,
+                                                       const double2 *w, double2 *part, int ld,
+                                                       const GmresCtl *ctl) {
+    if (ctl->done) return;
+    long lo, hi;
+    chunk_range(n, &lo, &hi);
+    chunk_dots(n, V, nv, w, lo, hi, part, ld);
+}
+
+// w -= sum_k dots[k] V_k with the dots reduced from the nb partials of
+// part_in; then either the partial dots of the updated w (second pass,
+// part_out) or the chunk's partial of |w|^2 (norm_part).
 __global__ __launch_bounds__(256) void cgs_update_kernel(long n, const double2 *V, int nv,
-                                                         const double2 *dots, double2 *w,
+                                                         const double2 *part_in, int nb, int ld,
+                                                         double2 *w, double2 *part_out,
                                                          double *norm_part, const GmresCtl *ctl) {
     if (ctl->done) return;
+    __shared__ double2 dots[256];
     __shared__ double red[4];
-    long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    reduce_dots(part_in, nb, ld, nv, dots);
+    long lo, hi;
+    chunk_range(n, &lo, &hi);
     double s = 0.0;
-    if (e < n) {
+    for (long e = lo + threadIdx.x; e < hi; e += blockDim.x) {
         double2 acc = cd(0.0, 0.0);
         for (int k = 0; k < nv; ++k) acc = cadd(acc, cmul(dots[k], V[(long)k * n + e]));
         double2 o = csub(w[e], acc);
         w[e] = o;
-        s = o.x * o.x + o.y * o.y;
+        s += o.x * o.x + o.y * o.y;
     }
-    if (norm_part) {
+    if (part_out) {
+        __syncthreads();   // this chunk of w is final (each element is read back by its writer)
+        chunk_dots(n, V, nv, w, lo, hi, part_out, ld);
+    } else {
         s = wsum(s);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
         __syncthreads();
@@ -244,14 +395,21 @@ __global__ void scale_ctl_kernel(long n, const double2 *x, double2 *y, const Gmr
 // ||w||, the previous rotations applied, and a new complex Givens rotation
 // [[conj(c), conj(s)], [-s, c]] (c = a/rho, s = b/rho) that zeroes h_{j+1,j};
 // the rotated right-hand side e gives the residual norm |e_{j+1}|.  One wave.
-__global__ void gmres_givens_kernel(int j, int m, const double2 *dots1, const double2 *dots2,
-                                    const double *part, int np, double2 *H, double2 *cs,
-                                    double2 *sn, double2 *e, GmresCtl *ctl) {
+__global__ __launch_bounds__(256) void gmres_givens_kernel(int j, int m, const double2 *part1,
+                                                           const double2 *part2, int nb,
+                                                           const double *part, int np, double2 *H,
+                                                           double2 *cs, double2 *sn, double2 *e,
+                                                           GmresCtl *ctl) {
     if (ctl->done) return;
+    __shared__ double2 h[256];
+    // h_{i,j} = first-pass + second-pass projections, reduced over chunks
+    reduce_dots(part1, nb, m + 1, j + 1, h, 0);
+    reduce_dots(part2, nb, m + 1, j + 1, h, 1);
     double hn = sqrt(wave_reduce_parts(part, np));
-    if (threadIdx.x != 0) return;
     double2 *col = H + (long)j * (m + 1);    // column-major, column j
-    for (int i = 0; i <= j; ++i) col[i] = cadd(dots1[i], dots2[i]);
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h[i];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     col[j + 1] = cd(hn, 0.0);
     for (int i = 0; i < j; ++i) {
         double2 a = col[i], b = col[i + 1];
@@ -328,24 +486,67 @@ __global__ __launch_bounds__(256) void lh_matvec_ctl_kernel(Phys P, const StripM
 
 }  // namespace
 
+static inline unsigned lh_grid(const Phys &P) {
+    unsigned ntr = 2 * (P.nsub - 1), ntile = (P.ny + 3) / 4;
+    return 8u * ntr * ((ntile + 7) / 8);
+}
+
+// L_h x (mode_p = 0) or x - L_h x (mode_p = 1); ctl may be null.  The
+// register-resident kernel reuses every block row over the strips of its
+// group; beyond 17 column chunks the row-per-wave kernel is used.
+static hipError_t lh_apply(hipStream_t st, const Phys &P, const StripMeta *strips, int ncls,
+                           const double2 *LH, const double2 *x, double2 *y, int mode_p,
+                           const GmresCtl *ctl) {
+    int nch = (P.ny + 63) / 64;
+    // strip groups: the grid fits one round of resident workgroups (two per
+    // CU at this register use), at most one group per strip
+    auto groups = [&](int tiles) {
+        int g = 512 / max(1, tiles * ncls);
+        return (unsigned)max(1, min(g, P.nsub));
+    };
+    if (nch <= 9) {
+        int tiles = (P.ny + 3) / 4;
+        hipLaunchKernelGGL((lh_matvec_reg_kernel<9, 2>), dim3(tiles, ncls, groups(tiles)),
+                           dim3(256), 0, st, P, strips, LH, x, y, mode_p, ctl);
+    } else if (nch <= 17) {
+        int tiles = (P.ny + 1) / 2;
+        hipLaunchKernelGGL((lh_matvec_reg_kernel<17, 1>), dim3(tiles, ncls, groups(tiles)),
+                           dim3(256), 0, st, P, strips, LH, x, y, mode_p, ctl);
+    } else if (ctl) {
+        hipLaunchKernelGGL(lh_matvec_ctl_kernel, dim3(lh_grid(P)), dim3(256), 0, st, P, strips, LH,
+                           x, y, ctl);
+    } else {
+        hipLaunchKernelGGL(lh_matvec_kernel, dim3(lh_grid(P)), dim3(256), 0, st, P, strips, LH, x,
+                           y, mode_p);
+    }
+    return hipGetLastError();
+}
+
+int gmres_chunks(long n) {
+    long nb = (n + 255) / 256;
+    return (int)(nb < 256 ? nb : 256);
+}
+
 hipError_t launch_gmres_iteration(hipStream_t st, const Phys &P, const StripMeta *strips,
-                                  const double2 *LH, long n, int j, int m, double2 *V,
-                                  double2 *dots1, double2 *dots2, double *norm_part,
+                                  int ncls, const double2 *LH, long n, int j, int m, double2 *V,
+                                  double2 *part1, double2 *part2, double *norm_part,
                                   double2 *H, double2 *cs, double2 *sn, double2 *e,
                                   GmresCtl *ctl) {
     double2 *vj = V + (long)j * n, *w = V + (long)(j + 1) * n;
-    unsigned nb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(lh_matvec_ctl_kernel, dim3((P.ny + 3) / 4, 2 * (P.nsub - 1)), dim3(256),
-                       0, st, P, strips, LH, vj, w, ctl);
-    hipLaunchKernelGGL(cgs_dots_kernel, dim3(j + 1), dim3(256), 0, st, n, V, w, dots1, ctl);
-    hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(256), 0, st, n, V, j + 1, dots1, w,
-                       (double *)nullptr, ctl);
-    hipLaunchKernelGGL(cgs_dots_kernel, dim3(j + 1), dim3(256), 0, st, n, V, w, dots2, ctl);
-    hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(256), 0, st, n, V, j + 1, dots2, w,
-                       norm_part, ctl);
-    hipLaunchKernelGGL(gmres_givens_kernel, dim3(1), dim3(64), 0, st, j, m, dots1, dots2,
-                       norm_part, (int)nb, H, cs, sn, e, ctl);
-    hipLaunchKernelGGL(scale_ctl_kernel, dim3(nb), dim3(256), 0, st, n, w, w, ctl);
+    unsigned nb = (unsigned)gmres_chunks(n);
+    unsigned ne = (unsigned)((n + 255) / 256);
+    int ld = m + 1;
+    hipError_t er = lh_apply(st, P, strips, ncls, LH, vj, w, 1, ctl);
+    if (er != hipSuccess) return er;
+    hipLaunchKernelGGL(cgs_dots_kernel, dim3(nb), dim3(256), 0, st, n, V, j + 1, w, part1, ld,
+                       ctl);
+    hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(256), 0, st, n, V, j + 1, part1,
+                       (int)nb, ld, w, part2, (double *)nullptr, ctl);
+    hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(256), 0, st, n, V, j + 1, part2,
+                       (int)nb, ld, w, (double2 *)nullptr, norm_part, ctl);
+    hipLaunchKernelGGL(gmres_givens_kernel, dim3(1), dim3(256), 0, st, j, m, part1, part2,
+                       (int)nb, norm_part, (int)nb, H, cs, sn, e, ctl);
+    hipLaunchKernelGGL(scale_ctl_kernel, dim3(ne), dim3(256), 0, st, n, w, w, ctl);
     return hipGetLastError();
 }
 
@@ -371,11 +572,9 @@ hipError_t launch_gmres_finish(hipStream_t st, long n, int m, const double2 *H, 
     return hipGetLastError();
 }
 
-hipError_t launch_lh_matvec(hipStream_t st, const Phys &P, const StripMeta *strips,
+hipError_t launch_lh_matvec(hipStream_t st, const Phys &P, const StripMeta *strips, int ncls,
                             const double2 *LH, const double2 *x, double2 *y, int mode_p) {
-    dim3 grid((P.ny + 3) / 4, 2 * (P.nsub - 1));
-    hipLaunchKernelGGL(lh_matvec_kernel, grid, dim3(256), 0, st, P, strips, LH, x, y, mode_p);
-    return hipGetLastError();
+    return lh_apply(st, P, strips, ncls, LH, x, y, mode_p, nullptr);
 }
 
 hipError_t launch_multidot(hipStream_t st, long n, const double2 *V, int nv, const double2 *w,

@@ -129,6 +129,16 @@ template <typename T> struct tile_shape;
 template <> struct tile_shape<float> { static constexpr int RU = 2, UN = 8; };
 template <> struct tile_shape<double> { static constexpr int RU = 2, UN = 4; };
 
+// Power of two s with 1 <= s * (largest |b| of the strip) < 2 (1 when the
+// right-hand side is zero or not finite); every lane reads the same nx line
+// maxima, so no exchange is needed.
+__device__ __forceinline__ double strip_scale(const double *lm, int nx) {
+    if (!lm) return 1.0;
+    double mx = 0.0;
+    for (int i = 0; i < nx; ++i) mx = fmax(mx, lm[i]);
+    return (mx > 0.0 && isfinite(mx)) ? ldexp(1.0, -ilogb(mx)) : 1.0;
+}
+
 __device__ __forceinline__ bool solve_skipped(const SolveArgs &a) {
     bool skip = a.ctl && (a.ctl->q_conv || a.ctl->k_done || a.ctl->bad);
     if (!skip && a.ran && blockIdx.x == 0 && threadIdx.x == 0) *a.ran = 1;
@@ -152,7 +162,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void strip_solve_kernel(SolveArgs a)
     unsigned *ctr = a.counters + j;
     unsigned epoch = 0;
     const long nn = (long)n * n;
-    const double sc = a.scale ? a.scale[j] : 1.0, inv = 1.0 / sc;
+    const double sc = strip_scale(a.lmax ? a.lmax + s.off : nullptr, s.nx), inv = 1.0 / sc;
     // forward sweep
     for (int i = 0; i < s.nx; ++i) {
         long L = s.off + i;
@@ -218,7 +228,7 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
     unsigned *ctr = a.counters + j;
     const long nn = (long)n * n;
     const int S = 2 * s.nx - 1;   // forward products i = 0..nx-1, then backward i = nx-2..0
-    const double sc = a.scale ? a.scale[j] : 1.0, inv = 1.0 / sc;
+    const double sc = strip_scale(a.lmax ? a.lmax + s.off : nullptr, s.nx), inv = 1.0 / sc;
     T2 m[PR][NCH];
 
     auto line_of = [&](int k) -> long { return s.off + (k < s.nx ? k : 2 * s.nx - 2 - k); };
@@ -401,7 +411,7 @@ __global__ __launch_bounds__(NW * 64) void batch_solve_kernel(BatchSolveArgs a) 
         const T2 *F = reinterpret_cast<const T2 *>(s.F);
         const long nn = (long)n * n;
         unsigned *ctr = a.counters + I.strip;
-        const double sc = s.scale ? *s.scale : 1.0, inv = 1.0 / sc;
+        const double sc = strip_scale(s.lmax, nx), inv = 1.0 / sc;
         const int S = 2 * nx - 1;   // forward products i = 0..nx-1, then backward i = nx-2..0
         for (int k = 0; k < S; ++k) {
             const bool fwd = k < nx;

@@ -50,7 +50,7 @@ struct osm_handle {
     double *mass_part = nullptr, *scal = nullptr;
     int *flag_d = nullptr;
     // solve
-    double *sscale = nullptr;        // per-strip right-hand-side scale (complex-FP32 factor)
+    double *sscale = nullptr;        // per-line largest |b| (scale of the complex-FP32 solve)
     unsigned *counters = nullptr;
     int *err_d = nullptr;
     int team = 0;
@@ -98,7 +98,8 @@ struct osm_handle {
     unsigned *bcounters = nullptr;
     int *bflags = nullptr;
     double *bscal = nullptr;
-    double *bscale = nullptr;        // per-strip right-hand-side scale of the batched solve
+    double *bscale = nullptr;        // per-line largest |b| of the batched solve
+    int max_nx = 0;
     int bvariant = 0, bgrid = 0;
     double balpha = 0.0;
     bool btuned = false;
@@ -227,12 +228,13 @@ uint64_t device_bytes(const Sizes &s) {
     b += 3ull * s.Lt * s.n * 16;                        // zeta, res, delta
     b += 5ull * s.ng * 16;                              // interface vectors
     b += 2ull * s.N * GJ_BK * s.n * fe;                 // GJ panels
-    b += (uint64_t)(3 * s.Lt + 4 * s.N + 2 * 2 * s.N + s.nglob + 64) * 8;
+    b += (uint64_t)(4 * s.Lt + 3 * s.N + 2 * 2 * s.N + s.nglob + 64) * 8;
     b += (uint64_t)(s.N - 1) * s.n * 13 * 4 + (uint64_t)(s.N - 1) * 8;  // guess features
     b += 3ull * s.ng * 16 + 2ull * ((s.ng + 255) / 256) * 8;           // guess history
     if (s.m > 0) {
         b += 4ull * s.ncls * s.n * s.n * 16;            // L_h blocks
         b += (uint64_t)(s.m + 2) * s.ng * 16;           // Krylov basis
+        b += 2ull * 256 * (s.m + 1) * 16;               // Gram-Schmidt partials
         b += 2ull * s.maxnx * s.n * s.n * 16 + (uint64_t)s.n * s.n * 16;  // L_h build temporaries
         b += 2ull * s.maxnx * s.n * 3 * 16;
     }
@@ -348,10 +350,10 @@ osm_status do_solve(osm_handle *h, const double2 *b, double2 *x, const StepCtl *
     a.error = h->err_d;
     a.ctl = ctl;
     a.ran = nullptr;
-    a.scale = nullptr;
+    a.lmax = nullptr;
     if (h->fp32) {
-        HIPCHK(h, launch_strip_scale(h->st, h->P, h->strips_d, b, h->sscale, ctl));
-        a.scale = h->sscale;
+        HIPCHK(h, launch_line_absmax(h->st, h->P, b, h->sscale, ctl));
+        a.lmax = h->sscale;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->prof) {
@@ -461,7 +463,7 @@ osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
     while (true) {
         const double2 *r = y;
         if (!first) {
-            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->LH, x, w, 1));
+            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->ncls, h->LH, x, w, 1));
             HIPCHK(h, launch_axpby(h->st, n, cd(1, 0), y, cd(-1, 0), w, w));
             r = w;
         }
@@ -473,7 +475,7 @@ osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
         while (j < m && total + j < o.max_gmres) {
             int ch = std::min(CH, std::min(m - j, o.max_gmres - total - j));
             for (int jj = j; jj < j + ch; ++jj)
-                HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->LH, n, jj, m, V,
+                HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->ncls, h->LH, n, jj, m, V,
                                                  h->gdots1, h->gdots2, h->gnorm_part, h->gH,
                                                  h->gcs, h->gsn, h->ge, h->gctl));
             j += ch;
@@ -528,7 +530,7 @@ osm_status fp_chunk(osm_handle *h, const double2 *u, int nq) {
 
 osm_status gmres_iters(osm_handle *h, int j0, int j1) {
     for (int j = j0; j < j1; ++j)
-        HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->LH, h->ng, j, h->m, h->Vb,
+        HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->ncls, h->LH, h->ng, j, h->m, h->Vb,
                                          h->gdots1, h->gdots2, h->gnorm_part, h->gH, h->gcs,
                                          h->gsn, h->ge, h->gctl));
     return OSM_OK;
@@ -567,7 +569,7 @@ osm_status gmres_continue(osm_handle *h, GmresCtl &gc, StepCtl &c) {
             return fail(h, OSM_ENOCONV, "GMRES did not converge within max_gmres");
         if (gc.finished) {
             double2 *w = h->Vb + (long)(m + 1) * ng;
-            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->LH, h->gx, w, 1));
+            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->ncls, h->LH, h->gx, w, 1));
             HIPCHK(h, launch_axpby(h->st, ng, cd(1, 0), h->gtmp, cd(-1, 0), w, w));
             HIPCHK(h, launch_gmres_begin(h->st, ng, w, h->gnorm_part, 0, 1.0, h->Vb, h->ge, m,
                                          h->gctl, h->sctl));
@@ -852,7 +854,7 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         SALLOC(h->scal, double, 8);
         SALLOC(h->flag_d, int, 1);
         SALLOC(h->counters, unsigned, h->N);
-        SALLOC(h->sscale, double, h->N);
+        SALLOC(h->sscale, double, h->Lt);
         SALLOC(h->err_d, int, 1);
         SALLOC(h->ran_d, int, PROF_SLOTS);
         SALLOC(h->sctl, StepCtl, 1);
@@ -876,8 +878,8 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             SALLOC(h->gsn, double2, h->m);
             SALLOC(h->ge, double2, h->m + 1);
             SALLOC(h->gy, double2, h->m);
-            SALLOC(h->gdots1, double2, h->m + 1);
-            SALLOC(h->gdots2, double2, h->m + 1);
+            SALLOC(h->gdots1, double2, (long)gmres_chunks(h->ng) * (h->m + 1));
+            SALLOC(h->gdots2, double2, (long)gmres_chunks(h->ng) * (h->m + 1));
             SALLOC(h->gnorm_part, double, (h->ng + 255) / 256);
         }
         HIPCHK(h, hipMemcpy(h->strips_d, h->strips_h.data(), sizeof(StripMeta) * h->N, hipMemcpyHostToDevice));
@@ -1126,7 +1128,7 @@ osm_status osm_interface_apply(osm_handle *h, osm_iface_op op, const osm_c64 *u_
             HIPCHK(h, launch_axpby(h->st, ng, cd(1, 0), gi, cd(-1, 0), h->gn, go));
     } else if (op == OSM_IFACE_LH) {
         if (h->opt.algo != OSM_PRECOND) return fail(h, OSM_ESTATE, "L_h is built only for OSM_PRECOND");
-        HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->LH, gi, go, 0));
+        HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->ncls, h->LH, gi, go, 0));
     } else if (op == OSM_IFACE_PINV) {
         if (h->opt.algo != OSM_PRECOND) return fail(h, OSM_ESTATE, "L_h is built only for OSM_PRECOND");
         int it;
@@ -1396,9 +1398,11 @@ osm_status osm_guess_features(osm_handle *h, const osm_c64 *g1_dev, const osm_c6
 // captured once as a HIP graph and replayed until every instance has met
 // its stopping test.
 
-static uint64_t batch_table_bytes(long nb, long nstrips) {
+static uint64_t batch_table_bytes(long nb, long nstrips, long nlines) {
     return (uint64_t)nb * (sizeof(InstDesc) + 2 * sizeof(double) + sizeof(int)) +
-           (uint64_t)nstrips * (sizeof(BStrip) + 4 * sizeof(BItem) + sizeof(unsigned)) + 4096;
+           (uint64_t)nstrips * (sizeof(BStrip) + 16 * sizeof(BItem) + sizeof(unsigned)) +
+           (uint64_t)nlines * sizeof(double) +
+           (uint64_t)PROF_SLOTS * (sizeof(int) + sizeof(unsigned long long)) + 4096;
 }
 
 static std::string validate_batch(const osm_problem *probs, int32_t nb, const osm_options *opt) {
@@ -1419,7 +1423,7 @@ osm_status osm_query_batch(const osm_problem *probs, int32_t nb, const osm_optio
     if (!v.empty()) return fail(nullptr, opt && opt->algo != OSM_CLASSICAL && probs && nb >= 1
                                              ? OSM_EUNSUPPORTED : OSM_EINVAL, v);
     uint64_t dev = 0, host = 0;
-    long nst = 0;
+    long nst = 0, nlines = 0;
     for (int b = 0; b < nb; ++b) {
         osm_footprint f;
         osm_status s = osm_query(&probs[b], opt, &f);
@@ -1427,8 +1431,9 @@ osm_status osm_query_batch(const osm_problem *probs, int32_t nb, const osm_optio
         dev += f.device_bytes;
         host += f.host_bytes;
         nst += probs[b].nsub;
+        nlines += probs[b].ncx + probs[b].nsub;
     }
-    out->device_bytes = dev + batch_table_bytes(nb, nst);
+    out->device_bytes = dev + batch_table_bytes(nb, nst, nlines);
     out->host_bytes = host + (uint64_t)nb * (sizeof(InstDesc) + sizeof(StepCtl)) +
                       (uint64_t)nst * sizeof(BStrip);
     return OSM_OK;
@@ -1487,7 +1492,8 @@ static osm_status batch_solve(osm_handle *h, int guard, hipStream_t st, hipEvent
     a.work = work;
     a.guard = guard;
     if (work) HIPCHK(h, hipMemsetAsync(work, 0, sizeof(unsigned long long), st));
-    if (h->fp32) HIPCHK(h, launch_b_strip_scale(st, h->bstrips_d, h->nstrips_all, h->bscale, guard));
+    if (h->fp32)
+        HIPCHK(h, launch_b_line_absmax(st, h->bstrips_d, h->nstrips_all, h->max_nx, guard));
     HIPCHK(h, launch_batch_solve(st, a, h->fp32, h->bvariant, h->bgrid, h->max_n, e0, e1));
     return OSM_OK;
 }
@@ -1664,6 +1670,7 @@ osm_status osm_setup_batch(const osm_problem *probs, int32_t nb, const osm_optio
             d.max_ntr = std::max(d.max_ntr, 2 * (u->N - 1));
             d.max_ng = std::max<long>(d.max_ng, u->ng);
             h->max_n = std::max(h->max_n, u->n);
+            h->max_nx = std::max(h->max_nx, u->maxnx);
             h->nstrips_all += u->N;
         }
         ALLOC(h, h->tab_d, InstDesc, nb);
@@ -1672,12 +1679,15 @@ osm_status osm_setup_batch(const osm_problem *probs, int32_t nb, const osm_optio
         ALLOC(h, h->bstrips_d, BStrip, h->nstrips_all);
         ALLOC(h, h->bitems_d, BItem, 16 * h->nstrips_all);
         ALLOC(h, h->bcounters, unsigned, h->nstrips_all + 1);
-        ALLOC(h, h->bscale, double, h->nstrips_all);
+        long all_lines = 0;
+        for (osm_handle *u : h->sub) all_lines += u->Lt;
+        ALLOC(h, h->bscale, double, all_lines);
         ALLOC(h, h->err_d, int, 1);
         ALLOC(h, h->ran_d, int, PROF_SLOTS);
         ALLOC(h, h->work_d, unsigned long long, PROF_SLOTS);
         HIPCHK(h, hipMemset(h->err_d, 0, sizeof(int)));
         size_t fe = h->fp32 ? sizeof(float2) : sizeof(double2);
+        long lines_so_far = 0;
         for (int b = 0; b < nb; ++b) {
             osm_handle *u = h->sub[b];
             InstDesc I;
@@ -1703,7 +1713,8 @@ osm_status osm_setup_batch(const osm_problem *probs, int32_t nb, const osm_optio
                 bs.b = u->res + (long)sm.off * u->n;
                 bs.x = u->delta + (long)sm.off * u->n;
                 bs.ctl = u->sctl;
-                bs.scale = h->fp32 ? h->bscale + h->bstrips_h.size() : nullptr;
+                bs.lmax = h->fp32 ? h->bscale + lines_so_far : nullptr;
+                lines_so_far += sm.nx;
                 bs.n = u->n;
                 bs.nx = sm.nx;
                 h->bstrips_h.push_back(bs);
@@ -1712,8 +1723,8 @@ osm_status osm_setup_batch(const osm_problem *probs, int32_t nb, const osm_optio
         HIPCHK(h, hipMemcpy(h->tab_d, h->tab_h.data(), sizeof(InstDesc) * nb, hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(h->bstrips_d, h->bstrips_h.data(), sizeof(BStrip) * h->nstrips_all,
                             hipMemcpyHostToDevice));
-        std::vector<double> ones(h->nstrips_all, 1.0);
-        HIPCHK(h, hipMemcpy(h->bscale, ones.data(), sizeof(double) * h->nstrips_all,
+        std::vector<double> ones(all_lines, 1.0);
+        HIPCHK(h, hipMemcpy(h->bscale, ones.data(), sizeof(double) * all_lines,
                             hipMemcpyHostToDevice));
         h->ctl_h.resize(nb);
         return set_items(h, 0.0, 0);

@@ -89,13 +89,14 @@ hipError_t launch_rotating_W(hipStream_t st, const Phys &P, double xl, double yb
                              double omega, double vxx, double vyy, double t1, double t0,
                              double *W);
 hipError_t launch_check_finite(hipStream_t st, const double2 *x, long n, int *flag);
-// scale[j] = 2^-e with 2^e <= max |b| over strip j < 2^(e+1) (1 when b_j = 0
-// or not finite), so that the right-hand side of a complex-FP32 solve stays
-// in FP32's normal range; skipped when c says the fixed point is idle.
-hipError_t launch_strip_scale(hipStream_t st, const Phys &P, const StripMeta *strips,
-                              const double2 *b, double *scale, const StepCtl *c);
-hipError_t launch_b_strip_scale(hipStream_t st, const BStrip *strips, int nstrips,
-                                double *scale, int guard);
+// lmax[L] = max |Re|, |Im| of b over packed line L (skipped when c says the
+// fixed point is idle).  The complex-FP32 solve scales strip j by 2^-e with
+// 2^e <= max over its lines < 2^(e+1), so that its right-hand side stays in
+// FP32's normal range.
+hipError_t launch_line_absmax(hipStream_t st, const Phys &P, const double2 *b, double *lmax,
+                              const StepCtl *c);
+hipError_t launch_b_line_absmax(hipStream_t st, const BStrip *strips, int nstrips, int max_nx,
+                                int guard);
 
 // kernels_factor.hip
 template <typename T>
@@ -142,9 +143,11 @@ struct SolveArgs {
     const StepCtl *ctl;      // may be null; the whole solve is skipped when it
                              // says the fixed point is done
     int *ran;                // may be null; set to 1 when the solve was not skipped
-    const double *scale;     // may be null (= 1); per strip, a power of two s_j:
-                             // right-hand sides enter the reduced-precision
-                             // products as s_j b, results leave divided by s_j
+    const double *lmax;      // may be null (no scaling); per packed line the
+                             // largest |b|: strip j's right-hand side enters the
+                             // reduced-precision products as s_j b with s_j the
+                             // power of two mapping its largest value into
+                             // [1, 2), results leave divided by s_j
 };
 // ev0/ev1 (may be null) are recorded right before and after the solve kernel
 hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipEvent_t ev0,
@@ -211,15 +214,18 @@ struct GmresCtl {
 hipError_t launch_gmres_begin(hipStream_t st, long n, const double2 *r, double *norm_part,
                               int first, double accept, double2 *V0, double2 *e, int m,
                               GmresCtl *ctl, const StepCtl *sctl);
+// chunks of the Gram-Schmidt partial dot products for vectors of length n
+// (part buffers hold gmres_chunks(n) x (m + 1) values)
+int gmres_chunks(long n);
 hipError_t launch_gmres_iteration(hipStream_t st, const Phys &P, const StripMeta *strips,
-                                  const double2 *LH, long n, int j, int m, double2 *V,
-                                  double2 *dots1, double2 *dots2, double *norm_part,
+                                  int ncls, const double2 *LH, long n, int j, int m, double2 *V,
+                                  double2 *part1, double2 *part2, double *norm_part,
                                   double2 *H, double2 *cs, double2 *sn, double2 *e,
                                   GmresCtl *ctl);
 hipError_t launch_gmres_finish(hipStream_t st, long n, int m, const double2 *H, const double2 *e,
                                double2 *y, const double2 *V, double2 *x, GmresCtl *ctl,
                                int require_done);
-hipError_t launch_lh_matvec(hipStream_t st, const Phys &P, const StripMeta *strips,
+hipError_t launch_lh_matvec(hipStream_t st, const Phys &P, const StripMeta *strips, int ncls,
                             const double2 *LH, const double2 *x, double2 *y, int mode_p);
 hipError_t launch_multidot(hipStream_t st, long n, const double2 *V, int nv, const double2 *w,
                            double2 *part, int nblk);
@@ -261,7 +267,8 @@ struct BStrip {
     const double2 *b;       // right-hand side
     double2 *x;             // solution
     const StepCtl *ctl;     // the instance's control; solve skipped when idle
-    const double *scale;    // may be null (= 1); this strip's power-of-two scale
+    double *lmax;           // may be null (no scaling); largest |b| of each of
+                            // the strip's lines (scale as in SolveArgs::lmax)
     int n, nx;
 };
 // One work item: member `member` of the `team` workgroups solving `strip`.
