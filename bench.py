@@ -99,9 +99,10 @@ def run_gpu(pb, u0, V, prec, steps, warmup, dev, measure=True):
     t1 = time.perf_counter()
     kern = s.kernel_timing(False) if measure else (0.0, 0)
     team = s.solve_team()
+    shape = s.solve_shape()
     s.close()
     return dict(seconds=t1 - t0, factor_s=t_fac, setup_s=t_setup, stats=stats, u=u,
-                solve_ms=kern[0], solve_launches=kern[1], team=team)
+                solve_ms=kern[0], solve_launches=kern[1], team=team, shape=shape)
 
 
 def profile_solve(pb, V, prec, launches, dev):
@@ -466,7 +467,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.prec), "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
                      "launches": main_run["solve_launches"],
-                     "workgroups_per_strip": main_run["team"]},
+                     "workgroups_per_strip": main_run["team"],
+                     "tile_shape": main_run["shape"]},
         "setup_s": main_run["setup_s"],
         "factor_s": main_run["factor_s"],
         "fp64_gpu": fp64,

@@ -189,9 +189,13 @@ osm_status osm_get_strip_solution(osm_handle *h, osm_c64 *v_dev);
 osm_status osm_get_lh_blocks(osm_handle *h, osm_c64 *blocks_dev);
 
 /* Copy the stored block-Thomas factor: for every line of the packed strip
- * layout the dense inverse S_i^{-1} of its Schur complement (ny x ny,
- * row-major), complex128 in OSM_FP64 and complex64 in OSM_C32_REFINE;
- * (ncx + nsub) * ny * ny elements. */
+ * layout the dense inverse of its Schur complement (ny x ny, row-major),
+ * complex128 in OSM_FP64 and complex64 in OSM_C32_REFINE; (ncx + nsub) * ny
+ * * ny elements.  The factor is twisted: in a strip with nx lines and middle
+ * line m = (nx-1)/2, lines i < m hold S_i^{-1} (S_0 = D_0, S_i = D_i -
+ * U_{i-1}^T S_{i-1}^{-1} U_{i-1}), lines i > m hold T_i^{-1} (T_{nx-1} =
+ * D_{nx-1}, T_i = D_i - U_i T_{i+1}^{-1} U_i^T), line m the inverse of
+ * D_m - U_{m-1}^T S_{m-1}^{-1} U_{m-1} - U_m T_{m+1}^{-1} U_m^T. */
 osm_status osm_get_factor(osm_handle *h, void *dst_dev);
 
 /* Kernel timing for measurement: enable = 1 resets the counters and brackets
@@ -213,6 +217,10 @@ osm_status osm_kernel_work(const osm_handle *h, double *solve_bytes);
  * the value the autotuner picked at the first factorisation (it times a few
  * solves for every feasible team size).  0 for a NULL handle. */
 int32_t osm_solve_team(const osm_handle *h);
+
+/* Tile shape of the strip solve picked with the team size (waves per
+ * workgroup and rows held in registers; 0 .. 2).  0 for a NULL handle. */
+int32_t osm_solve_shape(const osm_handle *h);
 
 /* ---------------------------------------------------------------- learned guess
  * A network predicts the next step's interface start from the history (the

@@ -1,8 +1,11 @@
 // Block-Thomas factorisation of the strip operators with dense ny x ny
 // Schur complements (the strip system of eq. NproblemRobinNL ordered by
-// x node-lines is block tridiagonal with tridiagonal blocks):
+// x node-lines is block tridiagonal with tridiagonal blocks; K_j is complex
+// symmetric, so the sub-diagonal block L_i equals U_{i-1}^T):
 //     S_0 = D_0,   S_i = D_i - U_{i-1}^T S_{i-1}^{-1} U_{i-1}
-// (K_j is complex symmetric, so the sub-diagonal block L_i equals U_{i-1}^T).
+// from above, and in the twisted form used by the strip solve also
+//     T_{nx-1} = D_{nx-1},   T_i = D_i - U_i T_{i+1}^{-1} U_i^T
+// from below, meeting at a middle line that eliminates both neighbours.
 // Each S_i is inverted in place by blocked Gauss-Jordan without pivoting:
 // -i K_j has a positive definite Hermitian part (2/dt M + c p M^Gamma), so
 // elimination without pivoting is well defined for every Schur complement.
@@ -39,19 +42,25 @@ template <> __device__ __forceinline__ float2 mk2<float2>(double x, double y) {
     float2 r; r.x = (float)x; r.y = (float)y; return r;
 }
 
-// S_i = D_i - U_{i-1}^T S_{i-1}^{-1} U_{i-1}, written into factor slot lines[z].
+// Schur complement of line lines[z], written into its factor slot:
+//   D_i                                      kind 0 (first line of a chain)
+//   - U_{i-1}^T F_{i-1} U_{i-1}              kind bit 0 (eliminated from above)
+//   - U_i F_{i+1} U_i^T                      kind bit 1 (eliminated from below)
+// where F_{i-1} and F_{i+1} already hold the inverses of the neighbouring
+// lines' Schur complements.
 template <typename T>
 __global__ void schur_kernel(int n, typename cplx_of<T>::type *F, const int *lines,
-                             const int *first, const double2 *Dc, const double2 *Uc) {
+                             const int *kind, const double2 *Dc, const double2 *Uc) {
     typedef typename cplx_of<T>::type T2;
     int z = blockIdx.z;
     int r = blockIdx.y * 16 + threadIdx.y;
     int c = blockIdx.x * 16 + threadIdx.x;
     if (r >= n || c >= n) return;
     long L = lines[z];
+    int kd = kind[z];
     double2 val = cd(0.0, 0.0);
     if (abs(r - c) <= 1) val = Dc[(L * n + r) * 3 + (c - r + 1)];
-    if (!first[z]) {
+    if (kd & 1) {
         long Lp = L - 1;
         const T2 *Sp = F + Lp * n * (long)n;
         for (int a = max(r - 1, 0); a <= min(r + 1, n - 1); ++a) {
@@ -63,6 +72,19 @@ __global__ void schur_kernel(int n, typename cplx_of<T>::type *F, const int *lin
                 t = cadd(t, cmul(cd(s.x, s.y), ubc));
             }
             val = csub(val, cmul(uar, t));
+        }
+    }
+    if (kd & 2) {
+        const T2 *Sn = F + (L + 1) * n * (long)n;
+        for (int a = max(r - 1, 0); a <= min(r + 1, n - 1); ++a) {
+            double2 ura = Uc[(L * n + r) * 3 + (a - r + 1)];         // U_i(r, a)
+            double2 t = cd(0.0, 0.0);
+            for (int b = max(c - 1, 0); b <= min(c + 1, n - 1); ++b) {
+                double2 ucb = Uc[(L * n + c) * 3 + (b - c + 1)];     // U_i(c, b) = U_i^T(b, c)
+                T2 s = Sn[(long)a * n + b];
+                t = cadd(t, cmul(cd(s.x, s.y), ucb));
+            }
+            val = csub(val, cmul(ura, t));
         }
     }
     F[L * n * (long)n + (long)r * n + c] = mk2<T2>(val.x, val.y);
@@ -317,9 +339,9 @@ __global__ void convert_kernel(long n, const double2 *src, typename cplx_of<T>::
 
 template <typename T>
 hipError_t launch_schur(hipStream_t st, int n, typename cplx_of<T>::type *F, const int *lines,
-                        const int *first, int batch, const double2 *Dc, const double2 *Uc) {
+                        const int *kind, int batch, const double2 *Dc, const double2 *Uc) {
     dim3 grid((n + 15) / 16, (n + 15) / 16, batch);
-    hipLaunchKernelGGL(schur_kernel<T>, grid, dim3(16, 16), 0, st, n, F, lines, first, Dc, Uc);
+    hipLaunchKernelGGL(schur_kernel<T>, grid, dim3(16, 16), 0, st, n, F, lines, kind, Dc, Uc);
     return hipGetLastError();
 }
 

@@ -1,20 +1,28 @@
-// Block-tridiagonal substitution with the stored inverses S_i^{-1}:
-//   forward   y_i = S_i^{-1} (b_i - U_{i-1}^T y_{i-1}),   i = 0 .. nx-1
-//   backward  x_i = y_i - S_i^{-1} (U_i x_{i+1}),          i = nx-2 .. 0
-// for every strip at once.  This is the local solve that the fixed point,
-// the classical iteration and every outer preconditioned iteration repeat
-// (Section 2.2, eq. NproblemRobinNL; Section 5: LU solves of the strip
-// systems).  Each step is a dense ny x ny matrix-vector product streamed
+// Block-tridiagonal substitution with the stored inverses of the twisted
+// factor, for every strip at once.  A strip with nx lines has its middle line
+// m = (nx-1)/2: lines above it hold S_i^{-1} (eliminated from above), lines
+// below hold T_i^{-1} (eliminated from below), line m holds the inverse of
+// the Schur complement that eliminates both neighbours.  The solve runs
+//   forward   y_i = S_i^{-1} (b_i - U_{i-1}^T y_{i-1})      i = 0 .. m-1
+//             z_i = T_i^{-1} (b_i - U_i z_{i+1})            i = nx-1 .. m+1
+//   middle    x_m = Z^{-1} (b_m - U_{m-1}^T y_{m-1} - U_m z_{m+1})
+//   backward  x_i = y_i - S_i^{-1} U_i x_{i+1}               i = m-1 .. 0
+//             x_i = z_i - T_i^{-1} U_{i-1}^T x_{i-1}         i = m+1 .. nx-1
+// with one line from above and one from below per step: nx + 1 dependent
+// steps (nx odd) instead of 2 nx - 1.  This is the local solve that the fixed
+// point, the classical iteration and every outer preconditioned iteration
+// repeat (Section 2.2, eq. NproblemRobinNL; Section 5: LU solves of the strip
+// systems).  Each product is a dense ny x ny matrix-vector product streamed
 // from HBM, so the kernel is bandwidth-bound.
 //
 // Launch: one persistent cooperative grid, `team` workgroups per strip; the
 // workgroup with blockIdx b serves strip b % nstrips (so with a strip count
 // that is a multiple of 8 a strip's team sits on one XCD) and owns a
-// contiguous row range of every product, spread round-robin over its four
-// waves.  Consecutive products of a strip are ordered by a per-strip
-// counter barrier: stores drained, one agent-scope release by the arriving
-// wave, relaxed polling with backoff, one acquire after the wait.  The wait
-// is bounded and sets an error flag, so no wave can spin forever.
+// contiguous row range of every product.  Consecutive steps of a strip are
+// ordered by a per-strip counter barrier: stores drained, one relaxed
+// device-scope increment by the arriving workgroup, relaxed polling, rows
+// exchanged with device-coherent loads.  The wait is bounded and sets an
+// error flag, so no wave can spin forever.
 #include "step_bodies.h"
 
 namespace {
@@ -58,6 +66,78 @@ __device__ __forceinline__ double2 ld_agent(const double2 *p) {
     const double *d = reinterpret_cast<const double *>(p);
     return cd(__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
               __hip_atomic_load(d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// ---------------------------------------------------------------- twisted schedule
+enum { TOP_F = 0, BOT_F = 1, MID = 2, TOP_B = 3, BOT_B = 4 };
+
+// Products of step s of a strip with nx lines: local line and kind of the
+// product from above (lt) and from below (lb); -1 = none.
+struct TwStep {
+    int lt, kt, lb, kb;
+};
+
+__device__ __forceinline__ int tw_steps(int nx) { return 2 * (nx - 1 - (nx - 1) / 2) + 1; }
+
+__device__ __forceinline__ TwStep tw_step(int nx, int s) {
+    const int m = (nx - 1) / 2, nb = nx - 1 - m;
+    TwStep t;
+    if (s < nb) {
+        t.lt = s < m ? s : -1; t.kt = TOP_F;
+        t.lb = nx - 1 - s;     t.kb = BOT_F;
+    } else if (s == nb) {
+        t.lt = m;  t.kt = MID;
+        t.lb = -1; t.kb = BOT_F;
+    } else {
+        int e = s - nb - 1;
+        t.lt = m - 1 - e >= 0 ? m - 1 - e : -1; t.kt = TOP_B;
+        t.lb = m + 1 + e;                        t.kb = BOT_B;
+    }
+    return t;
+}
+
+__device__ __forceinline__ bool tw_backward(int kind) { return kind == TOP_B || kind == BOT_B; }
+
+// Element r of the vector a product multiplies, in FP64: b_i minus (forward,
+// middle) or plus (backward) the coupling terms U_{i-1}^T x_{i-1} ("up") and
+// U_i x_{i+1} ("down") with the neighbouring lines' rows; L is the packed
+// line, i = L - (strip's first line).  xl(line, q) loads x[line * n + q].
+template <class XL>
+__device__ __forceinline__ double2 tw_vec(int kind, long L, int i, int nx, int n, int r,
+                                          const double2 *b, const double2 *Uc, XL xl) {
+    double2 acc = cd(0.0, 0.0);
+    bool up = false, down = false;
+    if (kind == TOP_F) { acc = b[L * n + r]; up = i > 0; }
+    else if (kind == BOT_F) { acc = b[L * n + r]; down = i < nx - 1; }
+    else if (kind == MID) { acc = b[L * n + r]; up = true; down = true; }
+    else if (kind == TOP_B) down = true;
+    else up = true;
+    const double sg = tw_backward(kind) ? 1.0 : -1.0;
+    if (up) {
+        double2 cu[3], xv[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int q = r - 1 + d;
+            bool ok = q >= 0 && q < n;
+            cu[d] = ok ? Uc[((L - 1) * n + q) * 3 + (2 - d)] : cd(0.0, 0.0);   // U_{i-1}(q, r)
+            xv[d] = ok ? xl(L - 1, q) : cd(0.0, 0.0);
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc = cadd(acc, cscale(sg, cmul(cu[d], xv[d])));
+    }
+    if (down) {
+        double2 cu[3], xv[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int q = r - 1 + d;
+            bool ok = q >= 0 && q < n;
+            cu[d] = ok ? Uc[(L * n + r) * 3 + d] : cd(0.0, 0.0);               // U_i(r, q)
+            xv[d] = ok ? xl(L + 1, q) : cd(0.0, 0.0);
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc = cadd(acc, cscale(sg, cmul(cu[d], xv[d])));
+    }
+    return acc;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -151,7 +231,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void strip_solve_kernel(SolveArgs a)
     constexpr int RU = tile_shape<T>::RU, UN = tile_shape<T>::UN;
     if (solve_skipped(a)) return;
     extern __shared__ unsigned char smem_raw[];
-    T2 *vec = reinterpret_cast<T2 *>(smem_raw);
+    T2 *vecs = reinterpret_cast<T2 *>(smem_raw);   // 2 n: product from above, from below
     int nst = a.nstrips, team = a.team;
     int j = blockIdx.x % nst, w = blockIdx.x / nst;
     StripMeta s = a.strips[j];
@@ -163,141 +243,125 @@ __global__ __launch_bounds__(SOLVE_THREADS) void strip_solve_kernel(SolveArgs a)
     unsigned epoch = 0;
     const long nn = (long)n * n;
     const double sc = strip_scale(a.lmax ? a.lmax + s.off : nullptr, s.nx), inv = 1.0 / sc;
-    // forward sweep
-    for (int i = 0; i < s.nx; ++i) {
-        long L = s.off + i;
-        for (int r = threadIdx.x; r < n; r += SOLVE_THREADS) {
-            double2 wv = a.b[L * n + r];
-            if (i > 0) {
-                for (int q = max(r - 1, 0); q <= min(r + 1, n - 1); ++q) {
-                    double2 u = a.Uc[((L - 1) * n + q) * 3 + (r - q + 1)];   // U_{i-1}(q, r)
-                    wv = csub(wv, cmul(u, a.x[(L - 1) * n + q]));
-                }
+    auto xl = [&](long line, int q) -> double2 { return ld_agent(a.x + line * n + q); };
+    const int S = tw_steps(s.nx);
+    for (int st = 0; st < S; ++st) {
+        const TwStep t = tw_step(s.nx, st);
+        
+        for (int p = 0; p < 2; ++p) {
+            if ((p == 0 ? t.lt : t.lb) < 0) continue;
+            long L = s.off + (p == 0 ? t.lt : t.lb);
+            for (int r = threadIdx.x; r < n; r += SOLVE_THREADS) {
+                double2 v = tw_vec((p == 0 ? t.kt : t.kb), L, (p == 0 ? t.lt : t.lb), s.nx, n, r, a.b, a.Uc, xl);
+                T2 tv; tv.x = (T)(v.x * sc); tv.y = (T)(v.y * sc);
+                vecs[p * n + r] = tv;
             }
-            T2 t; t.x = (T)(wv.x * sc); t.y = (T)(wv.y * sc);
-            vec[r] = t;
         }
         __syncthreads();
-        wg_gemv<T, RU, UN>(F + L * nn, n, r0, r1, vec, a.x + L * n, 0, inv);
+        for (int p = 0; p < 2; ++p) {
+            if ((p == 0 ? t.lt : t.lb) < 0) continue;
+            long L = s.off + (p == 0 ? t.lt : t.lb);
+            wg_gemv<T, RU, UN>(F + L * nn, n, r0, r1, vecs + p * n, a.x + L * n,
+                               tw_backward((p == 0 ? t.kt : t.kb)) ? 1 : 0, inv);
+        }
+        if (st == S - 1) break;
         team_barrier(ctr, (++epoch) * team, a.error);
         if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     }
-    // backward sweep
-    for (int i = s.nx - 2; i >= 0; --i) {
-        long L = s.off + i;
-        for (int r = threadIdx.x; r < n; r += SOLVE_THREADS) {
-            double2 zv = cd(0.0, 0.0);
-            for (int q = max(r - 1, 0); q <= min(r + 1, n - 1); ++q) {
-                double2 u = a.Uc[(L * n + r) * 3 + (q - r + 1)];             // U_i(r, q)
-                zv = cadd(zv, cmul(u, a.x[(L + 1) * n + q]));
-            }
-            T2 t; t.x = (T)(zv.x * sc); t.y = (T)(zv.y * sc);
-            vec[r] = t;
-        }
-        __syncthreads();
-        wg_gemv<T, RU, UN>(F + L * nn, n, r0, r1, vec, a.x + L * n, 1, inv);
-        if (i > 0) {
-            team_barrier(ctr, (++epoch) * team, a.error);
-            if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-        }
-    }
 }
 
-// Prefetching variant for ny <= 64 NCH.  Each of the NW waves owns whole
-// rows (r0 + wave + NW u) and keeps the first PR of them, NCH column chunks
-// of 64, in registers.  Right after the workgroup has published its rows of
-// product k and arrived at the strip barrier, it loads its rows of product
-// k+1 (the stored inverses do not depend on the vector), so the HBM stream
-// overlaps the barrier wait and the next vector phase.
+// Prefetching variant for ny <= 64 NCH.  A step's rows of both products
+// form one list (the rows [r0, r1) of the product from above, then of the
+// product from below), dealt round-robin to the NW waves; each wave keeps its
+// first PR rows, NCH column chunks of 64, in registers.  Right after the
+// workgroup has published a step and arrived at the strip barrier, it loads
+// its rows of the next step (the stored inverses do not depend on the
+// vectors), so the HBM stream overlaps the barrier wait and the next vector
+// phase.
 template <typename T, int NW, int NCH, int PR>
 __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
     typedef typename cplx_of<T>::type T2;
     typedef typename acc_t<T>::type A;
     if (solve_skipped(a)) return;
     extern __shared__ unsigned char smem_raw[];
-    T2 *vec = reinterpret_cast<T2 *>(smem_raw);
+    T2 *vecs = reinterpret_cast<T2 *>(smem_raw);   // 2 n: product from above, from below
     constexpr int NTHR = NW * 64;
     const int nst = a.nstrips, team = a.team;
     const int j = blockIdx.x % nst, w = blockIdx.x / nst;
     const StripMeta s = a.strips[j];
     const int n = a.n;
     const int rpw = (n + team - 1) / team;
-    const int r0 = min(n, w * rpw), r1 = min(n, r0 + rpw);
+    const int r0 = min(n, w * rpw), r1 = min(n, r0 + rpw), R = r1 - r0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const T2 *F = reinterpret_cast<const T2 *>(a.F);
     unsigned *ctr = a.counters + j;
     const long nn = (long)n * n;
-    const int S = 2 * s.nx - 1;   // forward products i = 0..nx-1, then backward i = nx-2..0
+    const int S = tw_steps(s.nx);
     const double sc = strip_scale(a.lmax ? a.lmax + s.off : nullptr, s.nx), inv = 1.0 / sc;
     T2 m[PR][NCH];
 
-    auto line_of = [&](int k) -> long { return s.off + (k < s.nx ? k : 2 * s.nx - 2 - k); };
-    auto prefetch = [&](long L) {
-        const T2 *M = F + L * nn;
+    // entry rho of a step's row list -> product p (0 above, 1 below) and row
+    // r, packed as p * 65536 + r; -1 past the end
+    auto entry = [&](const TwStep &t, int rho) -> int {
+        if (t.lt >= 0) {
+            if (rho < R) return r0 + rho;
+            rho -= R;
+        }
+        if (t.lb >= 0 && rho < R) return 65536 + r0 + rho;
+        return -1;
+    };
+    auto line_of = [&](const TwStep &t, int p) -> long { return s.off + (p == 0 ? t.lt : t.lb); };
+    auto prefetch = [&](const TwStep &t) {
 #pragma unroll
         for (int u = 0; u < PR; ++u) {
-            int r = r0 + wave + NW * u;
+            const int e = entry(t, wave + NW * u);
+            const bool ok = e >= 0;
+            const int p = e >> 16, r = e & 0xFFFF;
+            const T2 *M = ok ? F + line_of(t, p) * nn + (long)r * n : F;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 int col = c * 64 + lane;
-                if (r < r1 && col < n) m[u][c] = M[(long)r * n + col];
+                if (ok && col < n) m[u][c] = M[col];
                 else { m[u][c].x = 0; m[u][c].y = 0; }
             }
         }
     };
-    auto finish_row = [&](long L, int r, bool fwd, A ar, A ai) {
+    auto finish_row = [&](long L, int r, bool bwd, A ar, A ai) {
         ar = wave_sum(ar);
         ai = wave_sum(ai);
-        if (lane == 0 && r < r1) {
+        if (lane == 0) {
             double2 *xr = a.x + L * n + r;
-            if (fwd) st_agent(xr, cd((double)ar * inv, (double)ai * inv));
+            if (!bwd) st_agent(xr, cd((double)ar * inv, (double)ai * inv));
             else {
                 double2 o = ld_agent(xr);
                 st_agent(xr, cd(o.x - (double)ar * inv, o.y - (double)ai * inv));
             }
         }
     };
+    auto xl = [&](long line, int q) -> double2 { return ld_agent(a.x + line * n + q); };
 
-    prefetch(line_of(0));
-    for (int k = 0; k < S; ++k) {
-        const long L = line_of(k);
-        const bool fwd = k < s.nx;
-        const int i = (int)(L - s.off);
-        // vector phase: all loads of an entry issued together
-        for (int r = threadIdx.x; r < n; r += NTHR) {
-            double2 acc = cd(0.0, 0.0);
-            double2 cu[3], xv[3];
-            if (fwd) {
-                acc = a.b[L * n + r];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    int q = r - 1 + d;
-                    bool ok = i > 0 && q >= 0 && q < n;
-                    // U_{i-1}(q, r)
-                    cu[d] = ok ? a.Uc[((L - 1) * n + q) * 3 + (2 - d)] : cd(0.0, 0.0);
-                    xv[d] = ok ? ld_agent(a.x + (L - 1) * n + q) : cd(0.0, 0.0);
-                }
-#pragma unroll
-                for (int d = 0; d < 3; ++d) acc = csub(acc, cmul(cu[d], xv[d]));
-            } else {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    int q = r - 1 + d;
-                    bool ok = q >= 0 && q < n;
-                    // U_i(r, q)
-                    cu[d] = ok ? a.Uc[(L * n + r) * 3 + d] : cd(0.0, 0.0);
-                    xv[d] = ok ? ld_agent(a.x + (L + 1) * n + q) : cd(0.0, 0.0);
-                }
-#pragma unroll
-                for (int d = 0; d < 3; ++d) acc = cadd(acc, cmul(cu[d], xv[d]));
+    TwStep t = tw_step(s.nx, 0);
+    prefetch(t);
+    for (int st = 0; st < S; ++st) {
+        
+        // vector phase: both products' vectors, all loads of an entry issued together
+        for (int p = 0; p < 2; ++p) {
+            if ((p == 0 ? t.lt : t.lb) < 0) continue;
+            const long L = s.off + (p == 0 ? t.lt : t.lb);
+            for (int r = threadIdx.x; r < n; r += NTHR) {
+                double2 v = tw_vec((p == 0 ? t.kt : t.kb), L, (p == 0 ? t.lt : t.lb), s.nx, n, r, a.b, a.Uc, xl);
+                T2 tv; tv.x = (T)(v.x * sc); tv.y = (T)(v.y * sc);
+                vecs[p * n + r] = tv;
             }
-            T2 t; t.x = (T)(acc.x * sc); t.y = (T)(acc.y * sc);
-            vec[r] = t;
         }
         __syncthreads();
         // rows held in registers
 #pragma unroll
         for (int u = 0; u < PR; ++u) {
+            const int e = entry(t, wave + NW * u);
+            if (e < 0) continue;
+            const int p = e >> 16, r = e & 0xFFFF;
+            const T2 *vec = vecs + p * n;
             A ar = 0, ai = 0;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
@@ -308,12 +372,16 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
                 ar += m[u][c].x * v.x - m[u][c].y * v.y;
                 ai += m[u][c].x * v.y + m[u][c].y * v.x;
             }
-            finish_row(L, r0 + wave + NW * u, fwd, ar, ai);
+            finish_row(line_of(t, p), r, tw_backward((p == 0 ? t.kt : t.kb)), ar, ai);
         }
         // further rows streamed, UN chunks in flight at a time
         constexpr int UN = NCH < 8 ? NCH : 8;
-        for (int r = r0 + wave + NW * PR; r < r1; r += NW) {
-            const T2 *row = F + L * nn + (long)r * n;
+        for (int rho = wave + NW * PR;; rho += NW) {
+            const int e = entry(t, rho);
+            if (e < 0) break;
+            const int p = e >> 16, r = e & 0xFFFF;
+            const T2 *vec = vecs + p * n;
+            const T2 *row = F + line_of(t, p) * nn + (long)r * n;
             A ar = 0, ai = 0;
             for (int c0 = 0; c0 < NCH; c0 += UN) {
                 T2 mm[UN];
@@ -333,10 +401,10 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
                     ai += mm[c].x * v.y + mm[c].y * v.x;
                 }
             }
-            finish_row(L, r, fwd, ar, ai);
+            finish_row(line_of(t, p), r, tw_backward((p == 0 ? t.kt : t.kb)), ar, ai);
         }
-        if (k == S - 1) break;
-        // Publish this product, start loading the next one, then wait.  The
+        if (st == S - 1) break;
+        // Publish this step, start loading the next one, then wait.  The
         // rows went out as device-coherent stores; once every wave has seen
         // them acknowledged (s_waitcnt before the workgroup barrier) one
         // counter increment publishes them, and readers fetch them with
@@ -344,10 +412,11 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
         __builtin_amdgcn_s_waitcnt(0);   // only this wave's row stores are outstanding
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __syncthreads();
-        const unsigned target = (unsigned)(k + 1) * team;
+        const unsigned target = (unsigned)(st + 1) * team;
         if (threadIdx.x == 0)
             __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        prefetch(line_of(k + 1));
+        t = tw_step(s.nx, st + 1);
+        prefetch(t);
         if (threadIdx.x == 0) {
             unsigned spins = 0;
             while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -412,85 +481,72 @@ __global__ __launch_bounds__(NW * 64) void batch_solve_kernel(BatchSolveArgs a) 
         const long nn = (long)n * n;
         unsigned *ctr = a.counters + I.strip;
         const double sc = strip_scale(s.lmax, nx), inv = 1.0 / sc;
-        const int S = 2 * nx - 1;   // forward products i = 0..nx-1, then backward i = nx-2..0
+        const int S = tw_steps(nx);
+        auto xl = [&](long line, int q) -> double2 { return ld_agent(s.x + line * n + q); };
         for (int k = 0; k < S; ++k) {
-            const bool fwd = k < nx;
-            const int i = fwd ? k : 2 * nx - 2 - k;
-            // vector phase: b_i - U_{i-1}^T x_{i-1} (forward) or U_i x_{i+1} (backward)
-            for (int r = threadIdx.x; r < n; r += NTHR) {
-                double2 acc = cd(0.0, 0.0);
-                double2 cu[3], xv[3];
-                if (fwd) {
-                    acc = s.b[(long)i * n + r];
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        int q = r - 1 + d;
-                        bool ok = i > 0 && q >= 0 && q < n;
-                        cu[d] = ok ? s.Uc[((long)(i - 1) * n + q) * 3 + (2 - d)] : cd(0.0, 0.0);
-                        xv[d] = ok ? ld_agent(s.x + (long)(i - 1) * n + q) : cd(0.0, 0.0);
-                    }
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) acc = csub(acc, cmul(cu[d], xv[d]));
-                } else {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        int q = r - 1 + d;
-                        bool ok = q >= 0 && q < n;
-                        cu[d] = ok ? s.Uc[((long)i * n + r) * 3 + d] : cd(0.0, 0.0);
-                        xv[d] = ok ? ld_agent(s.x + (long)(i + 1) * n + q) : cd(0.0, 0.0);
-                    }
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) acc = cadd(acc, cmul(cu[d], xv[d]));
+            const TwStep t = tw_step(nx, k);
+            
+            // vector phase: the vectors of both products of this step
+            for (int p = 0; p < 2; ++p) {
+                if ((p == 0 ? t.lt : t.lb) < 0) continue;
+                for (int r = threadIdx.x; r < n; r += NTHR) {
+                    double2 v = tw_vec((p == 0 ? t.kt : t.kb), (p == 0 ? t.lt : t.lb), (p == 0 ? t.lt : t.lb), nx, n, r, s.b, s.Uc, xl);
+                    T2 tv; tv.x = (T)(v.x * sc); tv.y = (T)(v.y * sc);
+                    vec[p * n + r] = tv;
                 }
-                T2 t; t.x = (T)(acc.x * sc); t.y = (T)(acc.y * sc);
-                vec[r] = t;
             }
             __syncthreads();
-            const T2 *M = F + (long)i * nn;
-            for (int rb = r0 + wave; rb < r1; rb += NW * RU) {
-                A ar[RU], ai[RU];
+            for (int p = 0; p < 2; ++p) {
+                if ((p == 0 ? t.lt : t.lb) < 0) continue;
+                const int i = (p == 0 ? t.lt : t.lb);
+                const bool bwd = tw_backward((p == 0 ? t.kt : t.kb));
+                const T2 *M = F + (long)i * nn;
+                const T2 *vp = vec + p * n;
+                for (int rb = r0 + wave; rb < r1; rb += NW * RU) {
+                    A ar[RU], ai[RU];
 #pragma unroll
-                for (int u = 0; u < RU; ++u) { ar[u] = 0; ai[u] = 0; }
-                for (int c0 = 0; c0 < n; c0 += 64 * UN) {
-                    T2 m[RU][UN];
+                    for (int u = 0; u < RU; ++u) { ar[u] = 0; ai[u] = 0; }
+                    for (int c0 = 0; c0 < n; c0 += 64 * UN) {
+                        T2 mm[RU][UN];
 #pragma unroll
-                    for (int u = 0; u < RU; ++u)
+                        for (int u = 0; u < RU; ++u)
+#pragma unroll
+                            for (int kk = 0; kk < UN; ++kk) {
+                                int r = rb + NW * u, c = c0 + lane + 64 * kk;
+                                if (r < r1 && c < n) mm[u][kk] = M[(long)r * n + c];
+                                else { mm[u][kk].x = 0; mm[u][kk].y = 0; }
+                            }
 #pragma unroll
                         for (int kk = 0; kk < UN; ++kk) {
-                            int r = rb + NW * u, c = c0 + lane + 64 * kk;
-                            if (r < r1 && c < n) m[u][kk] = M[(long)r * n + c];
-                            else { m[u][kk].x = 0; m[u][kk].y = 0; }
-                        }
+                            int c = c0 + lane + 64 * kk;
+                            T2 v;
+                            if (c < n) v = vp[c];
+                            else { v.x = 0; v.y = 0; }
 #pragma unroll
-                    for (int kk = 0; kk < UN; ++kk) {
-                        int c = c0 + lane + 64 * kk;
-                        T2 v;
-                        if (c < n) v = vec[c];
-                        else { v.x = 0; v.y = 0; }
-#pragma unroll
-                        for (int u = 0; u < RU; ++u) {
-                            ar[u] += m[u][kk].x * v.x - m[u][kk].y * v.y;
-                            ai[u] += m[u][kk].x * v.y + m[u][kk].y * v.x;
+                            for (int u = 0; u < RU; ++u) {
+                                ar[u] += mm[u][kk].x * v.x - mm[u][kk].y * v.y;
+                                ai[u] += mm[u][kk].x * v.y + mm[u][kk].y * v.x;
+                            }
                         }
                     }
-                }
 #pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    A sr = wave_sum(ar[u]);
-                    A si = wave_sum(ai[u]);
-                    int r = rb + NW * u;
-                    if (lane == 0 && r < r1) {
-                        double2 *xr = s.x + (long)i * n + r;
-                        if (fwd) st_agent(xr, cd((double)sr * inv, (double)si * inv));
-                        else {
-                            double2 o = ld_agent(xr);
-                            st_agent(xr, cd(o.x - (double)sr * inv, o.y - (double)si * inv));
+                    for (int u = 0; u < RU; ++u) {
+                        A sr = wave_sum(ar[u]);
+                        A si = wave_sum(ai[u]);
+                        int r = rb + NW * u;
+                        if (lane == 0 && r < r1) {
+                            double2 *xr = s.x + (long)i * n + r;
+                            if (!bwd) st_agent(xr, cd((double)sr * inv, (double)si * inv));
+                            else {
+                                double2 o = ld_agent(xr);
+                                st_agent(xr, cd(o.x - (double)sr * inv, o.y - (double)si * inv));
+                            }
                         }
                     }
                 }
             }
             if (k == S - 1) break;
-            // publish this product: stores acknowledged, workgroup barrier,
+            // publish this step: stores acknowledged, workgroup barrier,
             // and for a team the strip counter
             __builtin_amdgcn_s_waitcnt(0);
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -538,29 +594,58 @@ struct Variant {
     int threads;
 };
 
-Variant variant_for(int n, int fp32) {
+// Tile shapes of the strip solve for a column count n and a precision: the
+// prefetching kernel with NW waves and PR rows in registers per wave (lighter
+// shapes fit two workgroups per CU, and so larger teams), or the generic
+// kernel beyond 33 column chunks.  The autotuner times every shape with
+// every feasible team size.
+constexpr int SOLVE_SHAPES = 3;
+
+Variant variant_for(int n, int fp32, int shape = 0) {
     int nch = (n + 63) / 64;
+    shape = shape < 0 ? 0 : (shape >= SOLVE_SHAPES ? SOLVE_SHAPES - 1 : shape);
     if (fp32) {
-        if (nch <= 3) return {(const void *)strip_solve_pf_kernel<float, 8, 3, 8>, 512};
-        if (nch <= 9) return {(const void *)strip_solve_pf_kernel<float, 8, 9, 5>, 512};
-        if (nch <= 17) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 3>, 512};
+        if (nch <= 3) {
+            if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 3, 8>, 512};
+            if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 3, 3>, 512};
+            return {(const void *)strip_solve_pf_kernel<float, 16, 3, 2>, 1024};
+        }
+        if (nch <= 9) {
+            if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 9, 5>, 512};
+            if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 9, 2>, 512};
+            return {(const void *)strip_solve_pf_kernel<float, 16, 9, 2>, 1024};
+        }
+        if (nch <= 17) {
+            if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 3>, 512};
+            if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 1>, 512};
+            return {(const void *)strip_solve_pf_kernel<float, 16, 17, 1>, 1024};
+        }
         if (nch <= 33) return {(const void *)strip_solve_pf_kernel<float, 8, 33, 1>, 512};
         return {(const void *)strip_solve_kernel<float>, SOLVE_THREADS};
     }
-    if (nch <= 3) return {(const void *)strip_solve_pf_kernel<double, 16, 3, 4>, 1024};
-    if (nch <= 9) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 3>, 512};
+    if (nch <= 3) {
+        if (shape == 1) return {(const void *)strip_solve_pf_kernel<double, 8, 3, 4>, 512};
+        return {(const void *)strip_solve_pf_kernel<double, 16, 3, 4>, 1024};
+    }
+    if (nch <= 9) {
+        if (shape == 0) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 3>, 512};
+        if (shape == 1) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 1>, 512};
+        return {(const void *)strip_solve_pf_kernel<double, 16, 9, 1>, 1024};
+    }
     if (nch <= 17) return {(const void *)strip_solve_pf_kernel<double, 8, 17, 1>, 512};
     return {(const void *)strip_solve_kernel<double>, SOLVE_THREADS};
 }
 
 }  // namespace
 
-int solve_max_resident_blocks(int fp32, int n) {
+int solve_shapes() { return SOLVE_SHAPES; }
+
+int solve_max_resident_blocks(int fp32, int n, int shape) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    Variant v = variant_for(n, fp32);
-    size_t smem = (size_t)n * (fp32 ? sizeof(float2) : sizeof(double2));
+    Variant v = variant_for(n, fp32, shape);
+    size_t smem = 2 * (size_t)n * (fp32 ? sizeof(float2) : sizeof(double2));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, v.fn, v.threads, smem) != hipSuccess)
         return 0;
     return per * cus;
@@ -574,8 +659,8 @@ hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipE
     if (e != hipSuccess) return e;
     SolveArgs args = a;
     void *params[] = {&args};
-    Variant v = variant_for(a.n, fp32);
-    size_t smem = (size_t)a.n * (fp32 ? sizeof(float2) : sizeof(double2));
+    Variant v = variant_for(a.n, fp32, a.shape);
+    size_t smem = 2 * (size_t)a.n * (fp32 ? sizeof(float2) : sizeof(double2));
     dim3 grid(a.nstrips * a.team), block(v.threads);
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     e = hipLaunchCooperativeKernel(v.fn, grid, block, params, (unsigned)smem, st);
@@ -621,7 +706,7 @@ int batch_solve_max_resident_blocks(int fp32, int variant, int max_n) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     BVariant v = batch_variant(fp32, variant);
-    size_t smem = (size_t)max_n * (fp32 ? sizeof(float2) : sizeof(double2));
+    size_t smem = 2 * (size_t)max_n * (fp32 ? sizeof(float2) : sizeof(double2));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, v.fn, v.threads, smem) != hipSuccess)
         return 0;
     return per * cus;
@@ -634,7 +719,7 @@ hipError_t launch_batch_solve(hipStream_t st, const BatchSolveArgs &a, int fp32,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     BVariant v = batch_variant(fp32, variant);
-    size_t smem = (size_t)max_n * (fp32 ? sizeof(float2) : sizeof(double2));
+    size_t smem = 2 * (size_t)max_n * (fp32 ? sizeof(float2) : sizeof(double2));
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     BatchSolveArgs args = a;
     void *params[] = {&args};

@@ -39,7 +39,7 @@ struct osm_handle {
     double2 *Dc = nullptr, *Uc = nullptr;
     double *W_d = nullptr;
     std::vector<int> step_batch, step_off;
-    int *step_lines_d = nullptr, *step_first_d = nullptr;
+    int *step_lines_d = nullptr, *step_first_d = nullptr;   // twisted factor steps (lines, kinds)
     int *ff_lines_d = nullptr, *ff_first_d = nullptr;
     void *Rbuf = nullptr, *Cbuf = nullptr;
     // strip vectors
@@ -80,7 +80,8 @@ struct osm_handle {
     int q_chunk = 3;
     // state
     bool factored = false, has_guess = false;
-    int team_cap = 0;            // largest co-resident team
+    int team_cap = 0;            // largest co-resident team of the current shape
+    int shape = 0;               // tile shape of the strip solve
     bool team_tuned = false;
     std::string err;
     std::vector<void *> allocs;
@@ -227,7 +228,7 @@ uint64_t device_bytes(const Sizes &s) {
     b += (uint64_t)s.nglob * s.n * 8;                   // W
     b += 3ull * s.Lt * s.n * 16;                        // zeta, res, delta
     b += 5ull * s.ng * 16;                              // interface vectors
-    b += 2ull * s.N * GJ_BK * s.n * fe;                 // GJ panels
+    b += 4ull * s.N * GJ_BK * s.n * fe;                 // GJ panels
     b += (uint64_t)(4 * s.Lt + 3 * s.N + 2 * 2 * s.N + s.nglob + 64) * 8;
     b += (uint64_t)(s.N - 1) * s.n * 13 * 4 + (uint64_t)(s.N - 1) * 8;  // guess features
     b += 3ull * s.ng * 16 + 2ull * ((s.ng + 255) / 256) * 8;           // guess history
@@ -260,7 +261,7 @@ void *dalloc(osm_handle *h, size_t bytes, hipError_t *e) {
 template <typename T>
 osm_status factor_chain(osm_handle *h, typename cplx_of<T>::type *F, const double2 *Dc,
                         const double2 *Uc, int nsteps, const std::vector<int> &batch,
-                        const std::vector<int> &off, const int *lines_d, const int *first_d) {
+                        const std::vector<int> &off, const int *lines_d, const int *kind_d) {
     typedef typename cplx_of<T>::type T2;
     int n = h->n;
     int nblk = (n + GJ_BK - 1) / GJ_BK;
@@ -269,8 +270,8 @@ osm_status factor_chain(osm_handle *h, typename cplx_of<T>::type *F, const doubl
         int bt = batch[i];
         if (bt == 0) continue;
         const int *lines = lines_d + off[i];
-        const int *first = first_d + off[i];
-        HIPCHK(h, launch_schur<T>(h->st, n, F, lines, first, bt, Dc, Uc));
+        const int *kind = kind_d + off[i];
+        HIPCHK(h, launch_schur<T>(h->st, n, F, lines, kind, bt, Dc, Uc));
         for (int kb = 0; kb < nblk; ++kb) {
             int k0 = kb * GJ_BK, b = std::min(GJ_BK, n - k0);
             HIPCHK(h, launch_gj_panel<T>(h->st, n, kb, F, lines, bt, R, C));
@@ -291,11 +292,12 @@ osm_status do_factor(osm_handle *h) {
     HIPCHK(h, launch_coef(h->st, h->P, h->strips_d, h->line_strip_d, h->W_d, 0, h->Dc, h->Uc, 0,
                           h->Lt));
     osm_status s;
+    int depth = (int)h->step_batch.size();
     if (h->fp32)
-        s = factor_chain<float>(h, (float2 *)h->F, h->Dc, h->Uc, h->maxnx, h->step_batch,
+        s = factor_chain<float>(h, (float2 *)h->F, h->Dc, h->Uc, depth, h->step_batch,
                                 h->step_off, h->step_lines_d, h->step_first_d);
     else
-        s = factor_chain<double>(h, (double2 *)h->F, h->Dc, h->Uc, h->maxnx, h->step_batch,
+        s = factor_chain<double>(h, (double2 *)h->F, h->Dc, h->Uc, depth, h->step_batch,
                                  h->step_off, h->step_lines_d, h->step_first_d);
     if (s != OSM_OK) return s;
     h->factored = true;
@@ -340,6 +342,7 @@ osm_status do_solve(osm_handle *h, const double2 *b, double2 *x, const StepCtl *
     SolveArgs a;
     a.n = h->n;
     a.team = h->team;
+    a.shape = h->shape;
     a.nstrips = h->N;
     a.strips = h->strips_d;
     a.F = h->F;
@@ -796,21 +799,46 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         line += h->cells[j];
         off += s.nx;
     }
-    // chain steps of the factor: step i factors local line i of every strip with nx > i
+    // Steps of the twisted factor.  A strip with nx lines and middle line
+    // m = (nx-1)/2 is eliminated from above on lines 0..m-1 and from below on
+    // lines nx-1..m+1; at depth d it factors line d (if d < m) and line
+    // nx-1-d (if nx-1-d > m), and at depth nx-1-m the middle line, which
+    // eliminates both neighbours.  Every strip's lines of one depth are
+    // factored together.
     std::vector<int> lines_all, first_all;
-    for (int i = 0; i < h->maxnx; ++i) {
+    int maxdepth = 0;
+    for (int j = 0; j < h->N; ++j) {
+        const StripMeta &sm = h->strips_h[j];
+        int m = (sm.nx - 1) / 2;
+        maxdepth = std::max(maxdepth, sm.nx - m);
+    }
+    for (int d = 0; d < maxdepth; ++d) {
         h->step_off.push_back((int)lines_all.size());
         int bt = 0;
-        for (int j = 0; j < h->N; ++j)
-            if (h->strips_h[j].nx > i) {
-                lines_all.push_back(h->strips_h[j].off + i);
-                first_all.push_back(i == 0);
+        for (int j = 0; j < h->N; ++j) {
+            const StripMeta &sm = h->strips_h[j];
+            int m = (sm.nx - 1) / 2, nb = sm.nx - 1 - m;
+            if (d < m) {                            // from above
+                lines_all.push_back(sm.off + d);
+                first_all.push_back(d > 0 ? 1 : 0);
                 ++bt;
             }
+            if (d < nb) {                           // from below
+                lines_all.push_back(sm.off + sm.nx - 1 - d);
+                first_all.push_back(d > 0 ? 2 : 0);
+                ++bt;
+            }
+            if (d == nb) {                          // middle line
+                lines_all.push_back(sm.off + m);
+                first_all.push_back(3);
+                ++bt;
+            }
+        }
         h->step_batch.push_back(bt);
     }
+    // one-directional chain of one strip (the free factor of the L_h build)
     std::vector<int> ffl(h->maxnx), fff(h->maxnx);
-    for (int i = 0; i < h->maxnx; ++i) { ffl[i] = i; fff[i] = i == 0; }
+    for (int i = 0; i < h->maxnx; ++i) { ffl[i] = i; fff[i] = i == 0 ? 0 : 1; }
 
     long nn = (long)h->n * h->n;
     size_t fe = h->fp32 ? sizeof(float2) : sizeof(double2);
@@ -828,9 +856,9 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             hipError_t e;
             h->F = dalloc<char>(h, fe * (size_t)h->Lt * nn, &e);
             if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for the factor");
-            // panels for a batch of N strips in the factor precision, and for
-            // one strip in FP64 (the free factor built for L_h)
-            size_t pb = std::max(fe * (size_t)h->N, sizeof(double2)) * GJ_BK * h->n;
+            // panels for a batch of 2 lines per strip in the factor precision,
+            // and for one strip in FP64 (the free factor built for L_h)
+            size_t pb = std::max(fe * 2 * (size_t)h->N, sizeof(double2)) * GJ_BK * h->n;
             h->Rbuf = dalloc<char>(h, pb, &e);
             if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for Rbuf");
             h->Cbuf = dalloc<char>(h, pb, &e);
@@ -853,7 +881,7 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         SALLOC(h->mass_part, double, h->nglob);
         SALLOC(h->scal, double, 8);
         SALLOC(h->flag_d, int, 1);
-        SALLOC(h->counters, unsigned, h->N);
+        SALLOC(h->counters, unsigned, h->N);      // one barrier counter per strip
         SALLOC(h->sscale, double, h->Lt);
         SALLOC(h->err_d, int, 1);
         SALLOC(h->ran_d, int, PROF_SLOTS);
@@ -900,7 +928,7 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             HIPCHK(h, hipMemcpy(h->gctl, &c0, sizeof(c0), hipMemcpyHostToDevice));
         }
         // workgroups per strip in the solve: fill the resident capacity
-        int cap = solve_max_resident_blocks(h->fp32, h->n);
+        int cap = solve_max_resident_blocks(h->fp32, h->n, 0);
         if (cap <= 0) return fail(h, OSM_EHIP, "occupancy query failed");
         h->team_cap = std::max(1, std::min(cap / h->N, h->n));
         int team = h->opt.team > 0 ? h->opt.team : std::min(16, h->team_cap);
@@ -937,39 +965,47 @@ osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_
     return setup_one(prob, opt, (hipStream_t)hip_stream, out);
 }
 
-// Autotuner of the strip solve: workgroups per strip trade barrier cost
-// against memory-level parallelism, so time a few solves with every feasible
-// team size once, after the first factorisation, and keep the fastest.
+// Autotuner of the strip solve: the tile shape (waves per workgroup, rows
+// kept in registers) and the workgroups per strip trade occupancy and barrier
+// cost against memory-level parallelism, so after the first factorisation
+// time a few solves with every shape and every feasible team size, and keep
+// the fastest pair.
 static osm_status autotune_team(osm_handle *h) {
     if (h->team_tuned) return OSM_OK;
     static const int cand[] = {4, 6, 8, 12, 16, 24, 32, 48, 64};
     bool prof = h->prof;
-    double keep_ms = h->solve_ms;
-    long long keep_n = h->solve_launches;
     HIPCHK(h, hipStreamSynchronize(h->st));
     osm_status s0 = prof_collect(h);
     if (s0 != OSM_OK) return s0;
-    keep_ms = h->solve_ms;
-    keep_n = h->solve_launches;
+    double keep_ms = h->solve_ms;
+    long long keep_n = h->solve_launches;
     double keep_b = h->solve_bytes;
     HIPCHK(h, hipMemsetAsync(h->res, 0, sizeof(double2) * (size_t)h->Lt * h->n, h->st));
-    int best = h->team;
+    int best = h->team, best_shape = h->shape;
     double best_ms = 1e300;
-    for (int t : cand) {
-        if (t > h->team_cap) break;
-        h->team = t;
-        h->prof = true;
-        h->solve_ms = 0.0;
-        h->solve_launches = 0;
-        for (int r = 0; r < 3; ++r) {
-            osm_status s = do_solve(h, h->res, h->delta);
-            if (s == OSM_OK) s = check_solve_error(h);
-            if (s != OSM_OK) { h->prof = prof; return s; }
+    for (int shape = 0; shape < solve_shapes(); ++shape) {
+        int cap = solve_max_resident_blocks(h->fp32, h->n, shape);
+        int tcap = std::max(1, std::min(std::min(cap / h->N, h->n), 64));
+        for (int t : cand) {
+            if (t > tcap) break;
+            h->team = t;
+            h->shape = shape;
+            h->prof = true;
+            h->solve_ms = 0.0;
+            h->solve_launches = 0;
+            for (int r = 0; r < 3; ++r) {
+                osm_status s = do_solve(h, h->res, h->delta);
+                if (s == OSM_OK) s = check_solve_error(h);
+                if (s != OSM_OK) { h->prof = prof; return s; }
+            }
+            double ms = h->solve_ms / 3.0;
+            if (ms < best_ms) { best_ms = ms; best = t; best_shape = shape; }
         }
-        double ms = h->solve_ms / 3.0;
-        if (ms < best_ms) { best_ms = ms; best = t; }
     }
     h->team = best;
+    h->shape = best_shape;
+    h->team_cap = std::max(1, std::min(std::min(
+        solve_max_resident_blocks(h->fp32, h->n, best_shape) / h->N, h->n), 64));
     h->prof = prof;
     h->solve_ms = keep_ms;
     h->solve_launches = keep_n;
@@ -1237,6 +1273,8 @@ osm_status osm_kernel_work(const osm_handle *h, double *solve_bytes) {
 }
 
 int32_t osm_solve_team(const osm_handle *h) { return h ? h->team : 0; }
+
+int32_t osm_solve_shape(const osm_handle *h) { return h ? h->shape : 0; }
 
 // ====================================================================== guess network
 static osm_status nfail(osm_net *n, osm_status s, const std::string &msg) {

@@ -99,9 +99,10 @@ hipError_t launch_b_line_absmax(hipStream_t st, const BStrip *strips, int nstrip
                                 int guard);
 
 // kernels_factor.hip
+// kind[z]: bit 0 = eliminate the line above (L-1), bit 1 = the line below (L+1)
 template <typename T>
 hipError_t launch_schur(hipStream_t st, int n, typename cplx_of<T>::type *F,
-                        const int *lines, const int *first, int batch,
+                        const int *lines, const int *kind, int batch,
                         const double2 *Dc, const double2 *Uc);
 template <typename T>
 hipError_t launch_gj_panel(hipStream_t st, int n, int kb, const typename cplx_of<T>::type *F,
@@ -132,6 +133,7 @@ hipError_t launch_convert(hipStream_t st, long n, const double2 *src, typename c
 struct SolveArgs {
     int n;
     int team;
+    int shape;               // tile shape, 0 .. solve_shapes()-1
     int nstrips;
     const StripMeta *strips;
     const void *F;           // factor (double2 or float2), line stride n*n
@@ -152,7 +154,8 @@ struct SolveArgs {
 // ev0/ev1 (may be null) are recorded right before and after the solve kernel
 hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipEvent_t ev0,
                               hipEvent_t ev1);
-int solve_max_resident_blocks(int fp32, int n);
+int solve_shapes();
+int solve_max_resident_blocks(int fp32, int n, int shape);
 
 // kernels_control.hip
 // Step configuration and device-side state of one time step.

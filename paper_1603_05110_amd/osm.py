@@ -68,7 +68,7 @@ class osm_footprint(ctypes.Structure):
 EXPORTS = ["osm_query", "osm_setup", "osm_factor", "osm_factor_rotating", "osm_step",
            "osm_interface_apply", "osm_set_interface_guess", "osm_get_interface",
            "osm_strip_solve", "osm_get_strip_solution", "osm_get_lh_blocks", "osm_get_factor",
-           "osm_kernel_timing", "osm_kernel_work", "osm_solve_team",
+           "osm_kernel_timing", "osm_kernel_work", "osm_solve_team", "osm_solve_shape",
            "osm_net_nparams", "osm_net_create", "osm_net_set_params", "osm_net_get_params",
            "osm_net_forward", "osm_net_loss_grad", "osm_net_train_step", "osm_net_destroy",
            "osm_net_last_error", "osm_guess_features", "osm_set_guess_net",
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "osm_get_lh_blocks": ([H, P], st),
         "osm_get_factor": ([H, P], st),
         "osm_solve_team": ([H], ctypes.c_int32),
+        "osm_solve_shape": ([H], ctypes.c_int32),
         "osm_kernel_timing": ([H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int64)], st),
         "osm_kernel_work": ([H, ctypes.POINTER(ctypes.c_double)], st),
@@ -262,6 +263,9 @@ class OsmSolver:
 
     def solve_team(self):
         return int(_lib.osm_solve_team(self.h))
+
+    def solve_shape(self):
+        return int(_lib.osm_solve_shape(self.h))
 
     def guess_features(self, g1, g2, g0=None):
         """Network inputs (nsub-1, 9, ny) and, with g0, targets (nsub-1, 4, ny)."""
