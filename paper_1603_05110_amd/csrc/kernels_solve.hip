@@ -599,7 +599,7 @@ struct Variant {
 // shapes fit two workgroups per CU, and so larger teams), or the generic
 // kernel beyond 33 column chunks.  The autotuner times every shape with
 // every feasible team size.
-constexpr int SOLVE_SHAPES = 3;
+constexpr int SOLVE_SHAPES = 4;
 
 Variant variant_for(int n, int fp32, int shape = 0) {
     int nch = (n + 63) / 64;
@@ -613,12 +613,14 @@ Variant variant_for(int n, int fp32, int shape = 0) {
         if (nch <= 9) {
             if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 9, 5>, 512};
             if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 9, 2>, 512};
-            return {(const void *)strip_solve_pf_kernel<float, 16, 9, 2>, 1024};
+            if (shape == 2) return {(const void *)strip_solve_pf_kernel<float, 16, 9, 2>, 1024};
+            return {(const void *)strip_solve_pf_kernel<float, 8, 9, 9>, 512};
         }
         if (nch <= 17) {
             if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 3>, 512};
             if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 1>, 512};
-            return {(const void *)strip_solve_pf_kernel<float, 16, 17, 1>, 1024};
+            if (shape == 2) return {(const void *)strip_solve_pf_kernel<float, 16, 17, 1>, 1024};
+            return {(const void *)strip_solve_pf_kernel<float, 8, 17, 4>, 512};
         }
         if (nch <= 33) return {(const void *)strip_solve_pf_kernel<float, 8, 33, 1>, 512};
         return {(const void *)strip_solve_kernel<float>, SOLVE_THREADS};
@@ -630,7 +632,8 @@ Variant variant_for(int n, int fp32, int shape = 0) {
     if (nch <= 9) {
         if (shape == 0) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 3>, 512};
         if (shape == 1) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 1>, 512};
-        return {(const void *)strip_solve_pf_kernel<double, 16, 9, 1>, 1024};
+        if (shape == 2) return {(const void *)strip_solve_pf_kernel<double, 16, 9, 1>, 1024};
+        return {(const void *)strip_solve_pf_kernel<double, 8, 9, 4>, 512};
     }
     if (nch <= 17) return {(const void *)strip_solve_pf_kernel<double, 8, 17, 1>, 512};
     return {(const void *)strip_solve_kernel<double>, SOLVE_THREADS};
