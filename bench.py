@@ -37,8 +37,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per strip-solve launch from rocprofv3 FETCH_SIZE + WRITE_SIZE on
 # this workload, each scaled by the counter's reading for a 1 GiB copy
 # (fetch x2.0, write x1.0); valid only for the kernel source it was taken on.
-SOLVE_TRAFFIC = {"c32": {"bytes": 2.2718e9,
-                         "source_sha256": "1f058ed11ae34716f5b494e60d2027c1f6b9d6ac6eb7f437c70bf1e2f2885043",
+SOLVE_TRAFFIC = {"c32": {"bytes": 2.2731e+09,
+                         "source_sha256": "5bf97e13243aa5a7a7a1d2342f478d2f7fd6d523afe0d5ccf2f65d81a4fb456b",
                          "summary": "profiles/strip_solve_c32_gpe512_hbm_counters.md"}}
 
 
