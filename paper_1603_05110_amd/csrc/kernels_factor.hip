@@ -6,15 +6,17 @@
 // from above, and in the twisted form used by the strip solve also
 //     T_{nx-1} = D_{nx-1},   T_i = D_i - U_i T_{i+1}^{-1} U_i^T
 // from below, meeting at a middle line that eliminates both neighbours.
-// Each S_i is inverted in place by blocked Gauss-Jordan without pivoting:
-// -i K_j has a positive definite Hermitian part (2/dt M + c p M^Gamma), so
-// elimination without pivoting is well defined for every Schur complement.
-// The rank-BK updates run as complex GEMMs on the matrix cores
-// (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32, complex product as four
-// real products on split real/imaginary tiles).
+// Each S_i is inverted in place by a blocked symmetric sweep (Gauss-Jordan
+// in the form that keeps the matrix symmetric) without pivoting: -i K_j has
+// a positive definite Hermitian part (2/dt M + c p M^Gamma), so elimination
+// without pivoting is well defined for every Schur complement, and S_i, its
+// inverse and every intermediate of the sweep are complex symmetric.  The
+// rank-64 updates run on the matrix cores (v_mfma_f64_16x16x4f64 /
+// v_mfma_f32_16x16x4f32, complex product as four real products on split
+// real/imaginary tiles).
 #include "osm_internal.h"
 
-#define GJ_BK 32
+#define SW 64   // pivot block edge of the sweep = output tile edge
 
 namespace {
 
@@ -90,101 +92,340 @@ __global__ void schur_kernel(int n, typename cplx_of<T>::type *F, const int *lin
     F[L * n * (long)n + (long)r * n + c] = mk2<T2>(val.x, val.y);
 }
 
-// One Gauss-Jordan pivot block step, panel part.  Block k covers rows and
-// columns [k0, k0+b).  Every workgroup inverts the b x b pivot block P in LDS
-// (redundantly), then
-//   R[:, tile]  = P A[k-rows, tile]   (with R[:, k-cols] = P)
-//   C'[tile, :] = A[tile, k-cols]     (with C'[k-rows, :] = -I)
-// so that the whole update is one GEMM:  A <- A|masked - C' R, where the
-// base drops block row k and block column k.
+// ---------------------------------------------------------------- sweep
+// One pivot block K (rows/columns [k0, k0+b), b <= 64) of the symmetric
+// sweep maps M to
+//     M'[K,K] = -P,   M'[K,j] = P M[K,j],   M'[i,K] = M[i,K] P,
+//     M'[i,j] = M[i,j] - M[i,K] P M[K,j],          P = M[K,K]^{-1},
+// which keeps M symmetric; after every block has been swept M = -S^{-1}.
+// Symmetry lets each pass compute and store only the upper 64 x 64 tiles
+// (I <= J, the diagonal tiles in full); the last pass negates and also
+// writes each off-diagonal tile's transpose, leaving the full inverse.
+//   sweep_pivot_kernel   P of every line (one workgroup per line)
+//   sweep_panel_kernel   C = M[K,:] before the pass, and R = P C
+//   sweep_update_kernel  every upper tile: M[I,J] - C[:,I]^T R[:,J]
+
+template <typename T> struct sweep_lds { static constexpr int LS = 80; };   // 80 words = 16 mod 32
+template <> struct sweep_lds<double> { static constexpr int LS = 72; };     // 144 words = 16 mod 32
+
+// LDS operand chunks of one 64 x 64 x KC product: a[k][i] = A(i, k),
+// b[k][j] = B(k, j), real and imaginary parts split.
 template <typename T>
-__global__ __launch_bounds__(256) void gj_panel_kernel(int n, int kb,
-                                                       const typename cplx_of<T>::type *F,
-                                                       const int *lines,
-                                                       typename cplx_of<T>::type *Rbuf,
-                                                       typename cplx_of<T>::type *Cbuf) {
+struct SweepTile {
+    static constexpr int KC = 32, LS = sweep_lds<T>::LS;
+    T ar[KC][LS], ai[KC][LS], br[KC][LS], bi[KC][LS];
+};
+
+// acc (+)= A B over one chunk: 4 waves, 32 x 32 outputs each as 2 x 2
+// blocks of 16 x 16 accumulators.
+template <typename T, typename V4>
+__device__ __forceinline__ void sweep_mma(const SweepTile<T> &s, int lane, int wr, int wc,
+                                          V4 (&acc_r)[2][2], V4 (&acc_i)[2][2]) {
+    const int cl = lane & 15;
+#pragma unroll
+    for (int ks = 0; ks < SweepTile<T>::KC; ks += 4) {
+        const int kr = ks + (lane >> 4);
+        T a_r[2], a_i[2], b_r[2], b_i[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            a_r[q] = s.ar[kr][wr + q * 16 + cl];
+            a_i[q] = s.ai[kr][wr + q * 16 + cl];
+            b_r[q] = s.br[kr][wc + q * 16 + cl];
+            b_i[q] = s.bi[kr][wc + q * 16 + cl];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                acc_r[bi][bj] = mfma16(a_r[bi], b_r[bj], acc_r[bi][bj]);
+                acc_r[bi][bj] = mfma16(-a_i[bi], b_i[bj], acc_r[bi][bj]);
+                acc_i[bi][bj] = mfma16(a_r[bi], b_i[bj], acc_i[bi][bj]);
+                acc_i[bi][bj] = mfma16(a_i[bi], b_r[bj], acc_i[bi][bj]);
+            }
+    }
+}
+
+// P = M[K,K]^{-1} by in-place Gauss-Jordan on a 64 x 64 block held in
+// registers (thread t owns column t % 64 and rows t / 64 + 4 s); the pivot
+// row and column of each step go through LDS (double-buffered, one barrier
+// per pivot).  Identity-padded beyond b.  Stored k-major:
+// Pbuf[z][k * 64 + i] = P(i, k).
+template <typename T>
+__global__ __launch_bounds__(256) void sweep_pivot_kernel(int n, int kb,
+                                                          const typename cplx_of<T>::type *F,
+                                                          const int *lines,
+                                                          typename cplx_of<T>::type *Pbuf) {
     typedef typename cplx_of<T>::type T2;
-    int z = blockIdx.y, J = blockIdx.x;
-    const T2 *A = F + (long)lines[z] * n * (long)n;
-    int k0 = kb * GJ_BK;
-    int b = min(GJ_BK, n - k0);
-    __shared__ T Pr[GJ_BK][GJ_BK + 1], Pi[GJ_BK][GJ_BK + 1];
-    __shared__ T Ar[GJ_BK][65], Ai[GJ_BK][65];
-    int tid = threadIdx.x;
-    for (int e = tid; e < GJ_BK * GJ_BK; e += 256) {
-        int r = e / GJ_BK, c = e % GJ_BK;
-        T2 v;
-        if (r < b && c < b) v = A[(long)(k0 + r) * n + k0 + c];
-        else { v.x = (r == c) ? (T)1 : (T)0; v.y = 0; }
-        Pr[r][c] = v.x; Pi[r][c] = v.y;
+    const int z = blockIdx.x, t = threadIdx.x;
+    const int c = t & 63, g = t >> 6;
+    const int k0 = kb * SW, b = min(SW, n - k0);
+    const T2 *M = F + (long)lines[z] * n * (long)n;
+    __shared__ T rowb[2][2][SW], colb[2][2][SW];
+    __shared__ T tr[SW][SW + 1], ti[SW][SW + 1];
+    T xr[16], xi[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int r = g + 4 * s;
+        if (r < b && c < b) {
+            T2 v = M[(long)(k0 + r) * n + k0 + c];
+            xr[s] = v.x; xi[s] = v.y;
+        } else {
+            xr[s] = (r == c) ? (T)1 : (T)0; xi[s] = 0;
+        }
     }
-    for (int e = tid; e < GJ_BK * 64; e += 256) {
-        int t = e / 64, cc = e % 64, col = J * 64 + cc;
-        T2 v;
-        if (t < b && col < n) v = A[(long)(k0 + t) * n + col];
-        else { v.x = 0; v.y = 0; }
-        Ar[t][cc] = v.x; Ai[t][cc] = v.y;
-    }
+    auto publish = [&](int p, int buf) {
+        if (g == (p & 3)) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+                if (s == (p >> 2)) { rowb[buf][0][c] = xr[s]; rowb[buf][1][c] = xi[s]; }
+        }
+        if (c == p) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) { colb[buf][0][g + 4 * s] = xr[s]; colb[buf][1][g + 4 * s] = xi[s]; }
+        }
+    };
+    publish(0, 0);
     __syncthreads();
-    // in-place Gauss-Jordan inversion of the b x b pivot block
     for (int p = 0; p < b; ++p) {
-        T ar = Pr[p][p], ai = Pi[p][p];
-        T den = ar * ar + ai * ai;
-        T ivr = ar / den, ivi = -ai / den;
-        T nv_r[4], nv_i[4];
-        int cnt = 0;
-        for (int e = tid; e < GJ_BK * GJ_BK; e += 256, ++cnt) {
-            int r = e / GJ_BK, c = e % GJ_BK;
-            T xr = Pr[r][c], xi = Pi[r][c];
-            T yr, yi;
-            if (r >= b || c >= b) { yr = xr; yi = xi; }
-            else if (r == p && c == p) { yr = ivr; yi = ivi; }
-            else if (r == p) { yr = ivr * xr - ivi * xi; yi = ivr * xi + ivi * xr; }
-            else {
-                T fr = Pr[r][p], fi = Pi[r][p];
-                T gr = fr * ivr - fi * ivi, gi = fr * ivi + fi * ivr;     // A[r][p] / A[p][p]
-                if (c == p) { yr = -gr; yi = -gi; }
-                else {
-                    T pr = Pr[p][c], pi = Pi[p][c];
-                    yr = xr - (gr * pr - gi * pi);
-                    yi = xi - (gr * pi + gi * pr);
+        const int buf = p & 1;
+        const T pr = rowb[buf][0][p], pim = rowb[buf][1][p];
+        const T den = pr * pr + pim * pim;
+        const T ivr = pr / den, ivi = -pim / den;
+        const T rr = rowb[buf][0][c], ri = rowb[buf][1][c];
+        const T qr = ivr * rr - ivi * ri, qi = ivr * ri + ivi * rr;     // a_pc / a_pp
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int r = g + 4 * s;
+            const T cr = colb[buf][0][r], ci = colb[buf][1][r];       // a_rp
+            if (r == p) {
+                if (c == p) { xr[s] = ivr; xi[s] = ivi; }
+                else { xr[s] = qr; xi[s] = qi; }
+            } else if (c == p) {
+                xr[s] = -(cr * ivr - ci * ivi);
+                xi[s] = -(cr * ivi + ci * ivr);
+            } else {
+                xr[s] -= cr * qr - ci * qi;
+                xi[s] -= cr * qi + ci * qr;
+            }
+        }
+        if (p + 1 < b) publish(p + 1, buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) { tr[g + 4 * s][c] = xr[s]; ti[g + 4 * s][c] = xi[s]; }
+    __syncthreads();
+    T2 *P = Pbuf + (long)z * SW * SW;
+    for (int e = t; e < SW * SW; e += 256) {
+        const int k = e >> 6, i = e & 63;
+        P[e] = mk2<T2>(tr[i][k], ti[i][k]);
+    }
+}
+
+// Panel of pivot block kb for column tile J of line z: the raw pivot rows
+// C[k][j] = M[k0 + k][j] (read from the stored upper tile (J, kb) when
+// J < kb) and R = P C; R[:, K] = P.  Rbuf, Cbuf: 64 x n per line.
+template <typename T>
+__global__ __launch_bounds__(256) void sweep_panel_kernel(int n, int kb,
+                                                          const typename cplx_of<T>::type *F,
+                                                          const int *lines,
+                                                          const typename cplx_of<T>::type *Pbuf,
+                                                          typename cplx_of<T>::type *Rbuf,
+                                                          typename cplx_of<T>::type *Cbuf) {
+    typedef typename cplx_of<T>::type T2;
+    typedef typename vec4_of<T>::type V4;
+    constexpr int KC = SweepTile<T>::KC;
+    const int J = blockIdx.x, z = blockIdx.y, tid = threadIdx.x;
+    const int k0 = kb * SW, b = min(SW, n - k0);
+    const int j0 = J * SW, w = min(SW, n - j0);
+    const T2 *M = F + (long)lines[z] * n * (long)n;
+    const T2 *P = Pbuf + (long)z * SW * SW;
+    T2 *R = Rbuf + (long)z * SW * n;
+    T2 *C = Cbuf + (long)z * SW * n;
+    if (J == kb) {
+        for (int e = tid; e < SW * SW; e += 256) {
+            const int r = e >> 6, cc = e & 63;
+            if (r < b && cc < b) R[(long)r * n + k0 + cc] = P[cc * SW + r];
+        }
+        return;
+    }
+    __shared__ SweepTile<T> sh;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    V4 acc_r[2][2], acc_i[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) { acc_r[bi][bj][v] = 0; acc_i[bi][bj][v] = 0; }
+    for (int kc = 0; kc < b; kc += KC) {
+        for (int e = tid; e < KC * SW; e += 256) {
+            const int kk = e >> 6, i = e & 63;
+            T2 v = P[(kc + kk) * SW + i];        // rows kc+kk >= b never reach R
+            sh.ar[kk][i] = v.x; sh.ai[kk][i] = v.y;
+        }
+        if (J > kb) {
+            for (int e = tid; e < KC * SW; e += 256) {
+                const int kk = e >> 6, j = e & 63;
+                T2 v;
+                if (kc + kk < b && j < w) v = M[(long)(k0 + kc + kk) * n + j0 + j];
+                else { v.x = 0; v.y = 0; }
+                sh.br[kk][j] = v.x; sh.bi[kk][j] = v.y;
+            }
+        } else {
+            for (int e = tid; e < KC * SW; e += 256) {
+                const int j = e / KC, kk = e % KC;
+                T2 v;
+                if (kc + kk < b && j < w) v = M[(long)(j0 + j) * n + k0 + kc + kk];
+                else { v.x = 0; v.y = 0; }
+                sh.br[kk][j] = v.x; sh.bi[kk][j] = v.y;
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < KC * SW; e += 256) {
+            const int kk = e >> 6, j = e & 63;
+            if (kc + kk < b && j < w) C[(long)(kc + kk) * n + j0 + j] = mk2<T2>(sh.br[kk][j], sh.bi[kk][j]);
+        }
+        sweep_mma<T, V4>(sh, lane, wr, wc, acc_r, acc_i);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wr + bi * 16 + acc_row<T>(lane, v);
+                const int j = wc + bj * 16 + (lane & 15);
+                if (r < b && j < w) R[(long)r * n + j0 + j] = mk2<T2>(acc_r[bi][bj][v], acc_i[bi][bj][v]);
+            }
+}
+
+// Upper tiles (I <= J) of every line after pivot block kb.  Lines are
+// spread over the 8 XCDs by blockIdx % 8 (a line's tiles share its panels,
+// so they stay in one XCD's L2) when the batch has 8 lines or more.  On the
+// last pass (last != 0) the result is negated and off-diagonal tiles are
+// also written transposed.
+template <typename T>
+__global__ __launch_bounds__(256) void sweep_update_kernel(int n, int kb,
+                                                           typename cplx_of<T>::type *F,
+                                                           const int *lines, int bt,
+                                                           const typename cplx_of<T>::type *Rbuf,
+                                                           const typename cplx_of<T>::type *Cbuf,
+                                                           int last) {
+    typedef typename cplx_of<T>::type T2;
+    typedef typename vec4_of<T>::type V4;
+    constexpr int KC = SweepTile<T>::KC;
+    const int TT = (n + SW - 1) / SW, nt = TT * (TT + 1) / 2;
+    int z, t;
+    if (bt >= 8) {
+        const int x = blockIdx.x & 7, sidx = blockIdx.x >> 3;
+        const int li = sidx / nt;
+        t = sidx - li * nt;
+        z = li * 8 + x;
+        if (z >= bt) return;
+    } else {
+        z = blockIdx.x / nt;
+        t = blockIdx.x - z * nt;
+    }
+    int I = 0, rem = t;
+    while (rem >= TT - I) { rem -= TT - I; ++I; }
+    const int J = I + rem;
+    const int i0 = I * SW, j0 = J * SW, h = min(SW, n - i0), w = min(SW, n - j0);
+    const int k0 = kb * SW, b = min(SW, n - k0);
+    T2 *M = F + (long)lines[z] * n * (long)n;
+    const T2 *R = Rbuf + (long)z * SW * n;
+    const T2 *C = Cbuf + (long)z * SW * n;
+    const T so = last ? (T)-1 : (T)1;
+    const int tid = threadIdx.x;
+    __shared__ SweepTile<T> sh;
+    if (I == kb) {
+        // rows of the pivot block: R (and -P on the diagonal tile)
+        const T f = (J == kb) ? -so : so;
+        for (int e = tid; e < SW * SW; e += 256) {
+            const int r = e >> 6, cc = e & 63;
+            if (r < h && cc < w) {
+                T2 v = R[(long)r * n + j0 + cc];
+                v.x *= f; v.y *= f;
+                M[(long)(i0 + r) * n + j0 + cc] = v;
+                if (last && J != I) M[(long)(j0 + cc) * n + i0 + r] = v;
+            }
+        }
+        return;
+    }
+    if (J == kb) {
+        // columns of the pivot block: M'[i, k0 + jj] = R[jj][i]
+        for (int jc = 0; jc < w; jc += KC) {
+            for (int e = tid; e < KC * SW; e += 256) {
+                const int jj = e >> 6, i = e & 63;
+                T2 v;
+                if (jc + jj < w && i < h) v = R[(long)(jc + jj) * n + i0 + i];
+                else { v.x = 0; v.y = 0; }
+                sh.ar[jj][i] = so * v.x; sh.ai[jj][i] = so * v.y;
+            }
+            __syncthreads();
+            for (int e = tid; e < KC * SW; e += 256) {
+                const int i = e / KC, jj = e % KC;
+                if (jc + jj < w && i < h)
+                    M[(long)(i0 + i) * n + j0 + jc + jj] = mk2<T2>(sh.ar[jj][i], sh.ai[jj][i]);
+            }
+            if (last) {
+                for (int e = tid; e < KC * SW; e += 256) {
+                    const int jj = e >> 6, i = e & 63;
+                    if (jc + jj < w && i < h)
+                        M[(long)(j0 + jc + jj) * n + i0 + i] = mk2<T2>(sh.ar[jj][i], sh.ai[jj][i]);
                 }
             }
-            nv_r[cnt] = yr; nv_i[cnt] = yi;
+            __syncthreads();
         }
-        __syncthreads();
-        cnt = 0;
-        for (int e = tid; e < GJ_BK * GJ_BK; e += 256, ++cnt) {
-            int r = e / GJ_BK, c = e % GJ_BK;
-            Pr[r][c] = nv_r[cnt]; Pi[r][c] = nv_i[cnt];
-        }
-        __syncthreads();
+        return;
     }
-    T2 *R = Rbuf + (long)z * GJ_BK * n;
-    for (int e = tid; e < GJ_BK * 64; e += 256) {
-        int t = e / 64, cc = e % 64, col = J * 64 + cc;
-        if (t >= b || col >= n) continue;
-        T vr = 0, vi = 0;
-        if (col >= k0 && col < k0 + b) { vr = Pr[t][col - k0]; vi = Pi[t][col - k0]; }
-        else {
-            for (int s = 0; s < b; ++s) {
-                T pr = Pr[t][s], pi = Pi[t][s], xr = Ar[s][cc], xi = Ai[s][cc];
-                vr += pr * xr - pi * xi;
-                vi += pr * xi + pi * xr;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    V4 acc_r[2][2], acc_i[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wr + bi * 16 + acc_row<T>(lane, v);
+                const int j = wc + bj * 16 + (lane & 15);
+                T2 x;
+                if (r < h && j < w) x = M[(long)(i0 + r) * n + j0 + j];
+                else { x.x = 0; x.y = 0; }
+                acc_r[bi][bj][v] = x.x;
+                acc_i[bi][bj][v] = x.y;
             }
+    for (int kc = 0; kc < b; kc += KC) {
+        for (int e = tid; e < KC * SW; e += 256) {
+            const int kk = e >> 6, i = e & 63;
+            T2 a, r;
+            if (kc + kk < b && i < h) a = C[(long)(kc + kk) * n + i0 + i];
+            else { a.x = 0; a.y = 0; }
+            if (kc + kk < b && i < w) r = R[(long)(kc + kk) * n + j0 + i];
+            else { r.x = 0; r.y = 0; }
+            sh.ar[kk][i] = -a.x; sh.ai[kk][i] = -a.y;
+            sh.br[kk][i] = r.x; sh.bi[kk][i] = r.y;
         }
-        T2 o; o.x = vr; o.y = vi;
-        R[(long)t * n + col] = o;
+        __syncthreads();
+        sweep_mma<T, V4>(sh, lane, wr, wc, acc_r, acc_i);
+        __syncthreads();
     }
-    T2 *C = Cbuf + (long)z * n * GJ_BK;
-    for (int e = tid; e < 64 * GJ_BK; e += 256) {
-        int rr = e / GJ_BK, t = e % GJ_BK, row = J * 64 + rr;
-        if (row >= n || t >= b) continue;
-        T2 v;
-        if (row >= k0 && row < k0 + b) { v.x = (row - k0 == t) ? (T)-1 : (T)0; v.y = 0; }
-        else v = A[(long)row * n + k0 + t];
-        C[(long)row * GJ_BK + t] = v;
-    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wr + bi * 16 + acc_row<T>(lane, v);
+                const int j = wc + bj * 16 + (lane & 15);
+                if (r < h && j < w) {
+                    const T2 o = mk2<T2>(so * acc_r[bi][bj][v], so * acc_i[bi][bj][v]);
+                    M[(long)(i0 + r) * n + j0 + j] = o;
+                    if (last && I != J) M[(long)(j0 + j) * n + i0 + r] = o;
+                }
+            }
 }
 
 // D = base + sign * A B for complex matrices (row-major, interleaved re/im),
@@ -346,12 +587,25 @@ hipError_t launch_schur(hipStream_t st, int n, typename cplx_of<T>::type *F, con
 }
 
 template <typename T>
-hipError_t launch_gj_panel(hipStream_t st, int n, int kb, const typename cplx_of<T>::type *F,
-                           const int *lines, int batch, typename cplx_of<T>::type *Rbuf,
-                           typename cplx_of<T>::type *Cbuf) {
-    dim3 grid((n + 63) / 64, batch);
-    hipLaunchKernelGGL(gj_panel_kernel<T>, grid, dim3(256), 0, st, n, kb, F, lines, Rbuf, Cbuf);
-    return hipGetLastError();
+hipError_t launch_sweep(hipStream_t st, int n, typename cplx_of<T>::type *F, const int *lines,
+                        int batch, typename cplx_of<T>::type *Pbuf,
+                        typename cplx_of<T>::type *Rbuf, typename cplx_of<T>::type *Cbuf) {
+    const int TT = (n + SW - 1) / SW, nt = TT * (TT + 1) / 2;
+    const long ublocks = batch >= 8 ? 8L * ((batch + 7) / 8) * nt : (long)batch * nt;
+    if (ublocks > 0x7fffffffL) return hipErrorInvalidConfiguration;
+    for (int kb = 0; kb < TT; ++kb) {
+        hipLaunchKernelGGL(sweep_pivot_kernel<T>, dim3(batch), dim3(256), 0, st, n, kb,
+                           (const typename cplx_of<T>::type *)F, lines, Pbuf);
+        hipLaunchKernelGGL(sweep_panel_kernel<T>, dim3(TT, batch), dim3(256), 0, st, n, kb,
+                           (const typename cplx_of<T>::type *)F, lines,
+                           (const typename cplx_of<T>::type *)Pbuf, Rbuf, Cbuf);
+        hipLaunchKernelGGL(sweep_update_kernel<T>, dim3((unsigned)ublocks), dim3(256), 0, st, n,
+                           kb, F, lines, batch, (const typename cplx_of<T>::type *)Rbuf,
+                           (const typename cplx_of<T>::type *)Cbuf, kb == TT - 1 ? 1 : 0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename T>
@@ -393,10 +647,10 @@ template hipError_t launch_schur<double>(hipStream_t, int, double2 *, const int 
                                          int, const double2 *, const double2 *);
 template hipError_t launch_schur<float>(hipStream_t, int, float2 *, const int *, const int *,
                                         int, const double2 *, const double2 *);
-template hipError_t launch_gj_panel<double>(hipStream_t, int, int, const double2 *, const int *,
-                                            int, double2 *, double2 *);
-template hipError_t launch_gj_panel<float>(hipStream_t, int, int, const float2 *, const int *,
-                                           int, float2 *, float2 *);
+template hipError_t launch_sweep<double>(hipStream_t, int, double2 *, const int *, int, double2 *,
+                                         double2 *, double2 *);
+template hipError_t launch_sweep<float>(hipStream_t, int, float2 *, const int *, int, float2 *,
+                                        float2 *, float2 *);
 template hipError_t launch_zgemm<double>(hipStream_t, const GemmArgs<double> &, int);
 template hipError_t launch_zgemm<float>(hipStream_t, const GemmArgs<float> &, int);
 template hipError_t launch_convert<double>(hipStream_t, long, const double2 *, double2 *);

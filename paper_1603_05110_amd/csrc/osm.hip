@@ -15,7 +15,7 @@
 #include "../../include/osm.h"
 #include "osm_internal.h"
 
-#define GJ_BK 32
+#define SWEEP_BK 64   // pivot block edge of the factor's sweep
 #define PROF_SLOTS 512
 #define GMRES_CHUNK 16
 
@@ -41,7 +41,7 @@ struct osm_handle {
     std::vector<int> step_batch, step_off;
     int *step_lines_d = nullptr, *step_first_d = nullptr;   // twisted factor steps (lines, kinds)
     int *ff_lines_d = nullptr, *ff_first_d = nullptr;
-    void *Rbuf = nullptr, *Cbuf = nullptr;
+    void *Rbuf = nullptr, *Cbuf = nullptr, *Pbuf = nullptr;
     // strip vectors
     double2 *zeta = nullptr, *res = nullptr, *delta = nullptr;
     // interface vectors
@@ -228,7 +228,10 @@ uint64_t device_bytes(const Sizes &s) {
     b += (uint64_t)s.nglob * s.n * 8;                   // W
     b += 3ull * s.Lt * s.n * 16;                        // zeta, res, delta
     b += 5ull * s.ng * 16;                              // interface vectors
-    b += 4ull * s.N * GJ_BK * s.n * fe;                 // GJ panels
+    {
+        uint64_t lb = std::max<uint64_t>(fe * 2 * s.N, 16);                 // sweep panels
+        b += lb * SWEEP_BK * (2ull * s.n + SWEEP_BK);
+    }
     b += (uint64_t)(4 * s.Lt + 3 * s.N + 2 * 2 * s.N + s.nglob + 64) * 8;
     b += (uint64_t)(s.N - 1) * s.n * 13 * 4 + (uint64_t)(s.N - 1) * 8;  // guess features
     b += 3ull * s.ng * 16 + 2ull * ((s.ng + 255) / 256) * 8;           // guess history
@@ -264,26 +267,14 @@ osm_status factor_chain(osm_handle *h, typename cplx_of<T>::type *F, const doubl
                         const std::vector<int> &off, const int *lines_d, const int *kind_d) {
     typedef typename cplx_of<T>::type T2;
     int n = h->n;
-    int nblk = (n + GJ_BK - 1) / GJ_BK;
-    T2 *R = (T2 *)h->Rbuf, *C = (T2 *)h->Cbuf;
+    T2 *R = (T2 *)h->Rbuf, *C = (T2 *)h->Cbuf, *Pb = (T2 *)h->Pbuf;
     for (int i = 0; i < nsteps; ++i) {
         int bt = batch[i];
         if (bt == 0) continue;
         const int *lines = lines_d + off[i];
         const int *kind = kind_d + off[i];
         HIPCHK(h, launch_schur<T>(h->st, n, F, lines, kind, bt, Dc, Uc));
-        for (int kb = 0; kb < nblk; ++kb) {
-            int k0 = kb * GJ_BK, b = std::min(GJ_BK, n - k0);
-            HIPCHK(h, launch_gj_panel<T>(h->st, n, kb, F, lines, bt, R, C));
-            GemmArgs<T> g;
-            g.M = n; g.N = n; g.K = b;
-            g.A = C; g.lda = GJ_BK; g.strideA = (long)n * GJ_BK;
-            g.B = R; g.ldb = n; g.strideB = (long)GJ_BK * n;
-            g.C = F; g.ldc = n; g.D = F; g.ldd = n;
-            g.strideCD = (long)n * n; g.idxCD = lines;
-            g.sign = -1; g.mask_lo = k0; g.mask_hi = k0 + b;
-            HIPCHK(h, launch_zgemm<T>(h->st, g, bt));
-        }
+        HIPCHK(h, launch_sweep<T>(h->st, n, F, lines, bt, Pb, R, C));
     }
     return OSM_OK;
 }
@@ -766,6 +757,21 @@ static osm_status available_bytes(const osm_options *opt, uint64_t *cap) {
 static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hipStream_t stream,
                             osm_handle **out) {
     Sizes sz = sizes_of(prob, opt);
+    {
+        // the strip solve keeps both products of a step (2 ny complex values)
+        // in one workgroup's LDS
+        int dev = 0, lim = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess)
+            return fail(nullptr, OSM_EHIP, "device attribute query failed");
+        size_t need = 2 * (size_t)sz.n * (sz.fp32 ? 8 : 16);
+        if (need > (size_t)lim)
+            return fail(nullptr, OSM_EINVAL,
+                        "ncy + 1 = " + std::to_string(sz.n) + " needs " + std::to_string(need) +
+                            " B of LDS per workgroup in the solve; the device allows " +
+                            std::to_string(lim));
+    }
     osm_handle *h = new osm_handle();
     h->prob = *prob;
     h->prob.strip_cells = nullptr;
@@ -858,11 +864,14 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for the factor");
             // panels for a batch of 2 lines per strip in the factor precision,
             // and for one strip in FP64 (the free factor built for L_h)
-            size_t pb = std::max(fe * 2 * (size_t)h->N, sizeof(double2)) * GJ_BK * h->n;
+            size_t lb = std::max(fe * 2 * (size_t)h->N, sizeof(double2));
+            size_t pb = lb * SWEEP_BK * h->n;
             h->Rbuf = dalloc<char>(h, pb, &e);
             if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for Rbuf");
             h->Cbuf = dalloc<char>(h, pb, &e);
             if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for Cbuf");
+            h->Pbuf = dalloc<char>(h, lb * SWEEP_BK * SWEEP_BK, &e);
+            if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for Pbuf");
         }
         SALLOC(h->Dc, double2, (long)h->Lt * h->n * 3);
         SALLOC(h->Uc, double2, (long)h->Lt * h->n * 3);

@@ -104,10 +104,12 @@ template <typename T>
 hipError_t launch_schur(hipStream_t st, int n, typename cplx_of<T>::type *F,
                         const int *lines, const int *kind, int batch,
                         const double2 *Dc, const double2 *Uc);
+// In-place inversion of the Schur complements of lines[0..batch) by the
+// blocked symmetric sweep; Pbuf: batch x 64 x 64, Rbuf/Cbuf: batch x 64 x n.
 template <typename T>
-hipError_t launch_gj_panel(hipStream_t st, int n, int kb, const typename cplx_of<T>::type *F,
-                           const int *lines, int batch, typename cplx_of<T>::type *Rbuf,
-                           typename cplx_of<T>::type *Cbuf);
+hipError_t launch_sweep(hipStream_t st, int n, typename cplx_of<T>::type *F, const int *lines,
+                        int batch, typename cplx_of<T>::type *Pbuf,
+                        typename cplx_of<T>::type *Rbuf, typename cplx_of<T>::type *Cbuf);
 template <typename T>
 struct GemmArgs {
     int M, N, K;

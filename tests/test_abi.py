@@ -41,12 +41,12 @@ def _pb(**kw):
 
 def test_query_footprint_scales_with_the_factor():
     from paper_1603_05110_amd import osm
-    d1, _ = osm.osm_query(_pb(ncy=64))
-    d2, _ = osm.osm_query(_pb(ncy=128))
+    d1, _ = osm.osm_query(_pb(ncy=128))
+    d2, _ = osm.osm_query(_pb(ncy=256))
     # dominated by (ncx + nsub) dense ny x ny complex blocks
-    assert d1 >= 18 * 65 * 65 * 16
+    assert d1 >= 18 * 129 * 129 * 16
     assert 3.0 < d2 / d1 < 4.5
-    dc, _ = osm.osm_query(_pb(ncy=128), prec="c32")
+    dc, _ = osm.osm_query(_pb(ncy=256), prec="c32")
     assert dc < d2
 
 

@@ -270,3 +270,31 @@ def test_c32_with_values_below_fp32_range_matches_monolithic(algo):
         s.step(ud)
     s.close()
     assert rel(ud.cpu().numpy(), ref) < 1e-10
+
+
+@pytest.mark.parametrize("ncy", [1024, 2048])
+@pytest.mark.parametrize("prec", ["fp64", "c32"])
+def test_wide_lines_match_monolithic(ncy, prec):
+    """Lines of 1025 and 2049 nodes (the widths of the 1024^2 and 2048^2
+    workloads: 17 and 33 column chunks) on a few x-cells: the wide-line
+    kernels of the factor, the solve and the L_h matvec against the oracle."""
+    log(f"wide lines ny={ncy + 1} {prec}")
+    osm = _osm()
+    from workloads import gaussian_boost
+    pb = Problem(-3.0, 3.0, -16.0, 16.0, 12, ncy, 3, [4, 5, 3], lap_coef=0.5, beta=-20.0,
+                 p=4.0, p_bc=4.0, dt=5e-3)
+    u = gaussian_boost(pb, k=0.5, a=0.7)
+    x = pb.xl + pb.hx * np.arange(pb.ncx + 1)
+    y = pb.yb + pb.hy * np.arange(pb.ncy + 1)
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    W = -0.5 * (X ** 2 + 1.2 * Y ** 2) / 16.0
+    ref = run_monolithic(pb, u, W, 2, tol_q=1e-14)
+    s = osm.OsmSolver(pb, DEV, algo="precond", prec=prec, tol_k=1e-12, tol_k_relative=True,
+                      tol_q=1e-14)
+    s.factor(to_dev(W))
+    ud = to_dev(u)
+    for _ in range(2):
+        st = s.step(ud)
+        log(f"  k={st['k']} q={st['q_total']} gmres={st['gmres_total']}")
+    s.close()
+    assert rel(ud.cpu().numpy(), ref) < 1e-10
