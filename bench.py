@@ -33,6 +33,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "dof-steps/s at 1e-10 rel L2 vs FP64 oracle; Schwarz/GMRES iters per step"
 HBM_PEAK_GBS = 8000.0
+MFMA_FP32_PEAK_TFLOPS = 157.3
+MFMA_FP64_PEAK_TFLOPS = 78.6
 
 # HBM bytes per strip-solve launch from rocprofv3 FETCH_SIZE + WRITE_SIZE on
 # this workload, each scaled by the counter's reading for a 1 GiB copy
@@ -383,6 +385,7 @@ def run_rotating(args, dev):
     torch.cuda.synchronize()
     s.kernel_timing(True)
     stats, t_fac = [], 0.0
+    u_first = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for n in range(1, args.steps + 1):
@@ -391,24 +394,60 @@ def run_rotating(args, dev):
         torch.cuda.synchronize()
         t_fac += time.perf_counter() - ta
         stats.append(s.step(u))
+        if n == 1:
+            u_first = u.clone()
         print(f"bench: step {n}: k {stats[-1]['k']} gmres {stats[-1]['gmres_total']} "
               f"q {stats[-1]['q_total']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     kern = s.kernel_timing(False)
+    fac_ms, fac_n, fac_fl = s.factor_timing()
     team, shape = s.solve_team(), s.solve_shape()
     s.close()
     value = dof * args.steps / T
     avg_ms = kern[0] / max(kern[1], 1)
     nbytes = solve_bytes(pb, args.prec)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    n = pb.ncy + 1
-    lt = pb.ncx + pb.nsub
-    # factor work: one dense complex inversion of an n x n block per line
-    # (8 n^3 real flops) dominates; the tridiagonal Schur updates are O(n^2)
-    fac_flops = 8.0 * lt * float(n) ** 3
+    upd_avg_ms = fac_ms / max(fac_n, 1)
+    upd_tflops = fac_fl / (fac_ms * 1e-3) / 1e12 if fac_ms > 0 else 0.0
     print(f"bench: {T:.2f}s for {args.steps} steps ({t_fac:.2f}s factor), {value:.4g} dof-steps/s",
           file=sys.stderr, flush=True)
+    # the FP64 oracle: the first step checked against the discrete equation
+    # with the oracle's assembled operators (a monolithic direct solve at
+    # 4.2 M nodes is out of reach), and the oracle's throughput on the same
+    # problem at 512^2 cells
+    check, cpu = None, None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle.fem import StripMatrices, weighted_mass_2d
+        from oracle.rotating import step_potential
+        from oracle.step import run_monolithic
+        u1 = u_first.cpu().numpy()
+        del u_first
+        mats = StripMatrices(pb.ncx, pb.ncy, pb.hx, pb.hy)
+        K = mats.operator(step_potential(pb, 1), pb.dt, pb.lap_coef, pb.p_bc, pb.p_bc)
+        v = 0.5 * (u0 + u1).ravel()
+        F = (2j / pb.dt) * (mats.M @ u0.ravel())
+        r = K @ v + weighted_mass_2d((pb.beta * np.abs(v) ** 2).reshape(u0.shape), pb.hx,
+                                     pb.hy) @ v - F
+        check = {"step": 1, "rel_residual_discrete_equation": float(np.linalg.norm(r) / np.linalg.norm(F)),
+                 "bound": 2.5e-11}
+        del K, r, v, F, mats
+        print(f"bench: step-1 residual {check['rel_residual_discrete_equation']:.3e}",
+              file=sys.stderr, flush=True)
+        sw = c5(ncells=512, nsub=16, steps=1)
+        spb, su0 = sw.problems[0], sw.u0[0]
+        with threadpool_limits(1):
+            t1 = time.perf_counter()
+            run_monolithic(spb, su0, lambda k: step_potential(spb, k), 1, tol_q=1e-14)
+            tc = time.perf_counter() - t1
+        sdof = (spb.ncx + 1) * (spb.ncy + 1)
+        cpu = {"value": sdof / tc, "unit": "dof-steps/s", "cores": 1, "kind": "oracle",
+               "sample": (f"FP64 monolithic oracle (SciPy splu, form B) on the same rotating "
+                          f"problem at 512^2 cells ({sdof} dofs), one step including its "
+                          f"factorisation ({tc:.1f}s); the 2048^2 system is 16x larger")}
+        print(f"bench: oracle {cpu['value']:.4g} dof-steps/s", file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
         "value": value,
@@ -432,16 +471,24 @@ def run_rotating(args, dev):
         "iters": {"k_mean": float(np.mean([x["k"] for x in stats])),
                   "q_total": int(sum(x["q_total"] for x in stats)),
                   "gmres_total": int(sum(x["gmres_total"] for x in stats))},
-        "roofline": {"kernel": "strip_solve", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
-                     "launches": kern[1], "workgroups_per_strip": team, "tile_shape": shape},
+        "roofline": {"kernel": "sweep_update", "bound": "mfma", "achieved": upd_tflops,
+                     "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": upd_tflops / MFMA_FP32_PEAK_TFLOPS if args.prec == "c32"
+                     else upd_tflops / MFMA_FP64_PEAK_TFLOPS,
+                     "traffic": None, "flops_timed": fac_fl, "avg_launch_ms": upd_avg_ms,
+                     "launches": fac_n,
+                     "note": ("8 real flops per complex multiply-add; the kernel issues 6 "
+                              "(three real products)")},
+        "solve": {"kernel": "strip_solve", "bound": "hbm", "achieved": achieved,
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                  "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms, "launches": kern[1],
+                  "workgroups_per_strip": team, "tile_shape": shape},
         "factor": {"s_per_step": t_fac / args.steps,
-                   "tflops": fac_flops / (t_fac / args.steps) / 1e12,
-                   "flops_per_factor": fac_flops},
+                   "update_ms_per_step": fac_ms / args.steps},
         "setup_s": t_setup,
         "first_factor_and_autotune_s": t_first,
-        "cpu_baseline": None,
+        "check": check,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

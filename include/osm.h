@@ -213,6 +213,15 @@ osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
  * milliseconds it gives the achieved bandwidth of the solve. */
 osm_status osm_kernel_work(const osm_handle *h, double *solve_bytes);
 
+/* While osm_kernel_timing is enabled, every update kernel of the factor's
+ * symmetric sweep (one per pivot block of 128 and factor step) is also
+ * bracketed by HIP events.  Returns the summed kernel time, the launch count
+ * and the algorithmic flops of those launches since the last reset (8 real
+ * flops per complex multiply-add over the upper 64 x 64 tiles that each pass
+ * updates).  Single-instance handles only; the batch factor is not timed. */
+osm_status osm_factor_timing(osm_handle *h, double *update_ms, int64_t *update_launches,
+                             double *update_flops);
+
 /* Workgroups per strip used by the strip solve: opt->team when given, else
  * the value the autotuner picked at the first factorisation (it times a few
  * solves for every feasible team size).  0 for a NULL handle. */

@@ -15,7 +15,7 @@
 #include "../../include/osm.h"
 #include "osm_internal.h"
 
-#define SWEEP_BK 64   // pivot block edge of the factor's sweep
+#define SWEEP_BK 128   // pivot block edge of the factor's sweep
 #define PROF_SLOTS 512
 #define GMRES_CHUNK 16
 
@@ -74,6 +74,12 @@ struct osm_handle {
     double solve_ms = 0.0;
     long long solve_launches = 0;
     double solve_bytes = 0.0;
+    // the same for the factor's sweep-update launches
+    std::vector<hipEvent_t> fevs;
+    std::vector<double> fflops;      // per slot: algorithmic flops of the launch
+    int fprof_used = 0;
+    double fac_ms = 0.0, fac_flops = 0.0;
+    long long fac_launches = 0;
     // device-side control of a step
     StepCtl *sctl = nullptr;
     double *upd_part = nullptr;
@@ -261,6 +267,42 @@ void *dalloc(osm_handle *h, size_t bytes, hipError_t *e) {
     } while (0)
 
 // ---------------------------------------------------------------- factor
+#define FPROF_SLOTS 1024
+
+osm_status fprof_collect(osm_handle *h) {
+    for (int i = 0; i < h->fprof_used; ++i) {
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, h->fevs[2 * i], h->fevs[2 * i + 1]));
+        h->fac_ms += ms;
+        h->fac_flops += h->fflops[i];
+        h->fac_launches += 1;
+    }
+    h->fprof_used = 0;
+    return OSM_OK;
+}
+
+// Event pair for the next timed sweep-update launch.
+osm_status fslot(osm_handle *h, double flops, hipEvent_t *e0, hipEvent_t *e1) {
+    if (h->fprof_used == FPROF_SLOTS) {
+        HIPCHK(h, hipStreamSynchronize(h->st));
+        osm_status s = fprof_collect(h);
+        if (s != OSM_OK) return s;
+    }
+    int slot = h->fprof_used++;
+    if ((int)h->fevs.size() < 2 * (slot + 1)) {
+        hipEvent_t a0, a1;
+        HIPCHK(h, hipEventCreate(&a0));
+        HIPCHK(h, hipEventCreate(&a1));
+        h->fevs.push_back(a0);
+        h->fevs.push_back(a1);
+        h->fflops.push_back(0.0);
+    }
+    h->fflops[slot] = flops;
+    *e0 = h->fevs[2 * slot];
+    *e1 = h->fevs[2 * slot + 1];
+    return OSM_OK;
+}
+
 template <typename T>
 osm_status factor_chain(osm_handle *h, typename cplx_of<T>::type *F, const double2 *Dc,
                         const double2 *Uc, int nsteps, const std::vector<int> &batch,
@@ -274,7 +316,14 @@ osm_status factor_chain(osm_handle *h, typename cplx_of<T>::type *F, const doubl
         const int *lines = lines_d + off[i];
         const int *kind = kind_d + off[i];
         HIPCHK(h, launch_schur<T>(h->st, n, F, lines, kind, bt, Dc, Uc));
-        HIPCHK(h, launch_sweep<T>(h->st, n, F, lines, bt, Pb, R, C));
+        for (int kb = 0; kb < sweep_passes(n); ++kb) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (h->prof) {
+                osm_status s = fslot(h, bt * sweep_pass_flops(n, kb), &e0, &e1);
+                if (s != OSM_OK) return s;
+            }
+            HIPCHK(h, launch_sweep_pass<T>(h->st, n, kb, F, lines, bt, Pb, R, C, e0, e1));
+        }
     }
     return OSM_OK;
 }
@@ -1263,6 +1312,7 @@ osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
     if (!h) return OSM_EINVAL;
     HIPCHK(h, hipStreamSynchronize(h->st));
     osm_status s = prof_collect(h);
+    if (s == OSM_OK) s = fprof_collect(h);
     if (s != OSM_OK) return s;
     if (solve_ms) *solve_ms = h->solve_ms;
     if (solve_launches) *solve_launches = h->solve_launches;
@@ -1270,6 +1320,9 @@ osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
         h->solve_ms = 0.0;
         h->solve_launches = 0;
         h->solve_bytes = 0.0;
+        h->fac_ms = 0.0;
+        h->fac_flops = 0.0;
+        h->fac_launches = 0;
     }
     h->prof = enable != 0;
     return OSM_OK;
@@ -1278,6 +1331,18 @@ osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
 osm_status osm_kernel_work(const osm_handle *h, double *solve_bytes) {
     if (!h) return OSM_EINVAL;
     if (solve_bytes) *solve_bytes = h->solve_bytes;
+    return OSM_OK;
+}
+
+osm_status osm_factor_timing(osm_handle *h, double *update_ms, int64_t *update_launches,
+                             double *update_flops) {
+    if (!h) return OSM_EINVAL;
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    osm_status s = fprof_collect(h);
+    if (s != OSM_OK) return s;
+    if (update_ms) *update_ms = h->fac_ms;
+    if (update_launches) *update_launches = h->fac_launches;
+    if (update_flops) *update_flops = h->fac_flops;
     return OSM_OK;
 }
 
@@ -1930,6 +1995,7 @@ void osm_destroy(osm_handle *h) {
     if (h->cap_st) hipStreamDestroy(h->cap_st);
     for (osm_handle *u : h->sub) osm_destroy(u);
     for (hipEvent_t e : h->evs) hipEventDestroy(e);
+    for (hipEvent_t e : h->fevs) hipEventDestroy(e);
     for (void *p : h->allocs) hipFree(p);
     delete h;
 }

@@ -105,11 +105,16 @@ hipError_t launch_schur(hipStream_t st, int n, typename cplx_of<T>::type *F,
                         const int *lines, const int *kind, int batch,
                         const double2 *Dc, const double2 *Uc);
 // In-place inversion of the Schur complements of lines[0..batch) by the
-// blocked symmetric sweep; Pbuf: batch x 64 x 64, Rbuf/Cbuf: batch x 64 x n.
+// blocked symmetric sweep, one pass (pivot block kb) per call, passes
+// 0 .. sweep_passes(n)-1 in order; Pbuf: batch x 128 x 128, Rbuf/Cbuf:
+// batch x 128 x n.  ev0/ev1 (may be null) bracket the update kernel.
+int sweep_passes(int n);
+double sweep_pass_flops(int n, int kb);
 template <typename T>
-hipError_t launch_sweep(hipStream_t st, int n, typename cplx_of<T>::type *F, const int *lines,
-                        int batch, typename cplx_of<T>::type *Pbuf,
-                        typename cplx_of<T>::type *Rbuf, typename cplx_of<T>::type *Cbuf);
+hipError_t launch_sweep_pass(hipStream_t st, int n, int kb, typename cplx_of<T>::type *F,
+                             const int *lines, int batch, typename cplx_of<T>::type *Pbuf,
+                             typename cplx_of<T>::type *Rbuf, typename cplx_of<T>::type *Cbuf,
+                             hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 struct GemmArgs {
     int M, N, K;

@@ -72,7 +72,7 @@ EXPORTS = ["osm_query", "osm_setup", "osm_factor", "osm_factor_rotating", "osm_s
            "osm_net_nparams", "osm_net_create", "osm_net_set_params", "osm_net_get_params",
            "osm_net_forward", "osm_net_loss_grad", "osm_net_train_step", "osm_net_destroy",
            "osm_net_last_error", "osm_guess_features", "osm_set_guess_net",
-           "osm_query_batch", "osm_setup_batch", "osm_factor_batch", "osm_step_batch",
+           "osm_factor_timing", "osm_query_batch", "osm_setup_batch", "osm_factor_batch", "osm_step_batch",
            "osm_batch_tuning", "osm_destroy", "osm_last_error"]
 
 
@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "osm_kernel_timing": ([H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int64)], st),
         "osm_kernel_work": ([H, ctypes.POINTER(ctypes.c_double)], st),
+        "osm_factor_timing": ([H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(ctypes.c_double)], st),
         "osm_net_nparams": ([], ctypes.c_int32),
         "osm_net_create": ([ctypes.c_int32, P, ctypes.POINTER(H)], st),
         "osm_net_set_params": ([H, P], st),
@@ -293,6 +295,14 @@ class OsmSolver:
         b = ctypes.c_double()
         self._c(_lib.osm_kernel_work(self.h, ctypes.byref(b)))
         return b.value
+
+    def factor_timing(self):
+        """(summed ms, launches, algorithmic flops) of the factor's timed
+        sweep-update launches since the last kernel_timing reset."""
+        ms, f = ctypes.c_double(), ctypes.c_double()
+        n = ctypes.c_int64()
+        self._c(_lib.osm_factor_timing(self.h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(f)))
+        return ms.value, n.value, f.value
 
     def close(self):
         if self.h:
