@@ -59,7 +59,7 @@ def measured_traffic(prec):
 
 def solver_opts(prec):
     return dict(algo="precond", prec=prec, tol_k=1e-12, tol_k_relative=True, max_k=500,
-                tol_q=1e-13, max_q=200, warm_start=True, tol_gmres=1e-4,
+                tol_q=1e-13, max_q=200, warm_start=True, tol_gmres=1e-2,
                 gmres_restart=50, max_gmres=2000, eta_q=1e-2)
 
 
