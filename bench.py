@@ -63,17 +63,6 @@ def solver_opts(prec):
                 gmres_restart=50, max_gmres=2000, eta_q=1e-2)
 
 
-def solve_bytes(pb, prec):
-    """Algorithmic bytes of one strip-solve launch: the stored inverse of
-    every line is read once in the forward sweep and once in the backward
-    sweep (the last line of a strip only once), plus the right-hand side,
-    the solution and the coupling coefficients once."""
-    n = pb.ncy + 1
-    lt = pb.ncx + pb.nsub
-    es = 8 if prec == "c32" else 16
-    return (2 * lt - pb.nsub) * n * n * es + lt * n * (16 + 16 + 48)
-
-
 def run_gpu(pb, u0, V, prec, steps, warmup, dev, measure=True):
     import torch
     from paper_1603_05110_amd import osm
@@ -100,11 +89,12 @@ def run_gpu(pb, u0, V, prec, steps, warmup, dev, measure=True):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kern = s.kernel_timing(False) if measure else (0.0, 0)
+    work = s.kernel_work() if measure else 0.0
     team = s.solve_team()
     shape = s.solve_shape()
     s.close()
     return dict(seconds=t1 - t0, factor_s=t_fac, setup_s=t_setup, stats=stats, u=u,
-                solve_ms=kern[0], solve_launches=kern[1], team=team, shape=shape)
+                solve_ms=kern[0], solve_launches=kern[1], solve_work=work, team=team, shape=shape)
 
 
 def profile_solve(pb, V, prec, launches, dev):
@@ -125,13 +115,13 @@ def profile_solve(pb, V, prec, launches, dev):
         s.strip_solve(b)
     torch.cuda.synchronize()
     ms, n = s.kernel_timing(False)
+    nbytes = s.kernel_work() / max(n, 1)
     team = s.solve_team()
     s.close()
     src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    nbytes = solve_bytes(pb, prec)
     avg = ms / max(n, 1)
     print(json.dumps({"mode": "profile-solve", "prec": prec, "launches": n, "avg_launch_ms": avg,
                       "bytes_per_launch": nbytes, "achieved_GBs": nbytes / (avg * 1e-3) / 1e9,
@@ -401,12 +391,13 @@ def run_rotating(args, dev):
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     kern = s.kernel_timing(False)
+    solve_work = s.kernel_work()
     fac_ms, fac_n, fac_fl = s.factor_timing()
     team, shape = s.solve_team(), s.solve_shape()
     s.close()
     value = dof * args.steps / T
     avg_ms = kern[0] / max(kern[1], 1)
-    nbytes = solve_bytes(pb, args.prec)
+    nbytes = solve_work / max(kern[1], 1)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     upd_avg_ms = fac_ms / max(fac_n, 1)
     upd_tflops = fac_fl / (fac_ms * 1e-3) / 1e12 if fac_ms > 0 else 0.0
@@ -556,7 +547,7 @@ def main():
           file=sys.stderr, flush=True)
 
     avg_ms = main_run["solve_ms"] / max(main_run["solve_launches"], 1)
-    nbytes = solve_bytes(pb, args.prec)
+    nbytes = main_run["solve_work"] / max(main_run["solve_launches"], 1)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
 
     fp64 = None

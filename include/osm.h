@@ -119,6 +119,13 @@ typedef struct {
                                      iteration k-1)), iteration 1 at
                                      max(tol_q, eta_q); the converged answer is
                                      unchanged.  0 = always tol_q                 */
+    int32_t solve_shape;          /* 0 = the autotuner picks the strip solve's kernel
+                                     and tile shape; k = 1 .. 8 fixes shape k-1:
+                                     0 .. 3 read full rows of the stored inverses,
+                                     4 .. 7 only their upper triangles (the
+                                     inverses are complex symmetric; ny up to 2112
+                                     in c32, 1088 in FP64); the team is still tuned
+                                     unless team > 0                             */
 } osm_options;
 
 typedef struct {
@@ -209,8 +216,10 @@ osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
 /* Algorithmic bytes of the strip-solve launches timed since the last reset
  * of osm_kernel_timing (stored inverses read by both sweeps, right-hand
  * side, solution and coupling coefficients of every strip solved; a batched
- * launch counts only the instances it did not skip).  Divided by the timed
- * milliseconds it gives the achieved bandwidth of the solve. */
+ * launch counts only the instances it did not skip).  The
+ * upper-triangle kernels (osm_solve_shape() >= 4) count n (n + 1) / 2
+ * elements per inverse.  Divided by the timed milliseconds it gives the
+ * achieved bandwidth of the solve. */
 osm_status osm_kernel_work(const osm_handle *h, double *solve_bytes);
 
 /* While osm_kernel_timing is enabled, every update kernel of the factor's
@@ -227,8 +236,10 @@ osm_status osm_factor_timing(osm_handle *h, double *update_ms, int64_t *update_l
  * solves for every feasible team size).  0 for a NULL handle. */
 int32_t osm_solve_team(const osm_handle *h);
 
-/* Tile shape of the strip solve picked with the team size (waves per
- * workgroup and rows held in registers; 0 .. 2).  0 for a NULL handle. */
+/* Kernel and tile shape of the strip solve picked with the team size: 0 .. 3
+ * stream full rows of the stored inverses, 4 .. 7 only their upper triangles
+ * (waves per workgroup x rows kept in registers as for 0 .. 3).  0 for a
+ * NULL handle. */
 int32_t osm_solve_shape(const osm_handle *h);
 
 /* ---------------------------------------------------------------- learned guess

@@ -52,8 +52,9 @@ template <> __device__ __forceinline__ float2 mk2<float2>(double x, double y) {
 //   - U_{i-1}^T F_{i-1} U_{i-1}              kind bit 0 (eliminated from above)
 //   - U_i F_{i+1} U_i^T                      kind bit 1 (eliminated from below)
 // where F_{i-1} and F_{i+1} already hold the inverses of the neighbouring
-// lines' Schur complements.  The complement is symmetric and the sweep
-// reads only its upper 64 x 64 tiles (I <= J), so only those are formed.
+// lines' Schur complements (read through their upper triangles).  The
+// complement is symmetric and the sweep reads only its upper 64 x 64 tiles
+// (I <= J), so only those are formed.
 // A workgroup forms one tile; thread t owns column t % 64 and 16
 // consecutive rows, sliding the three-row window of F U over them.
 template <typename T>
@@ -103,7 +104,10 @@ __global__ __launch_bounds__(256) void schur_kernel(int n, typename cplx_of<T>::
             for (int d = 0; d < 3; ++d) {
                 const int bb = c - 1 + d;
                 if (bb >= 0 && bb < n) {
-                    const T2 g = G[(long)a * n + bb];
+                    // the neighbour's inverse may be stored as its upper
+                    // triangle only: read G(a, bb) = G(min, max)
+                    const int lo = min(a, bb), hi = max(a, bb);
+                    const T2 g = G[(long)lo * n + hi];
                     t = cadd(t, cmul(cd(g.x, g.y), ur[d]));
                 }
             }
@@ -397,15 +401,15 @@ __global__ __launch_bounds__(256) void sweep_panel_kernel(int n, int kb,
 // so they stay in one XCD's L2) when the batch has 8 lines or more.  The
 // next chunk of C and R is loaded into registers while the current one is
 // multiplied, and the tile's old value is added at the end.  On the last
-// pass (last != 0) the result is negated and off-diagonal tiles are also
-// written transposed.
+// pass (last != 0) the result is negated, and with mirror != 0 (only on the
+// last pass) off-diagonal tiles are also written transposed.
 template <typename T>
 __global__ __launch_bounds__(256) void sweep_update_kernel(int n, int kb,
                                                            typename cplx_of<T>::type *F,
                                                            const int *lines, int bt,
                                                            const typename cplx_of<T>::type *Rbuf,
                                                            const typename cplx_of<T>::type *Cbuf,
-                                                           int last) {
+                                                           int last, int mirror) {
     typedef typename cplx_of<T>::type T2;
     typedef typename vec4_of<T>::type V4;
     constexpr int KC = SweepTile<T>::KC;
@@ -444,7 +448,7 @@ __global__ __launch_bounds__(256) void sweep_update_kernel(int n, int kb,
                 T2 v = R[(long)(rr + r) * n + j0 + cc];
                 v.x *= f; v.y *= f;
                 M[(long)(i0 + r) * n + j0 + cc] = v;
-                if (last && J != I) M[(long)(j0 + cc) * n + i0 + r] = v;
+                if (mirror && J != I) M[(long)(j0 + cc) * n + i0 + r] = v;
             }
         }
         return;
@@ -466,7 +470,7 @@ __global__ __launch_bounds__(256) void sweep_update_kernel(int n, int kb,
                 if (jc + jj < w && i < h)
                     M[(long)(i0 + i) * n + j0 + jc + jj] = mk2<T2>(sh.ar[jj][i], sh.ai[jj][i]);
             }
-            if (last) {
+            if (mirror) {
                 for (int e = tid; e < KC * SW; e += 256) {
                     const int jj = e >> 6, i = e & 63;
                     if (jc + jj < w && i < h)
@@ -537,7 +541,7 @@ __global__ __launch_bounds__(256) void sweep_update_kernel(int n, int kb,
                     const T2 o = mk2<T2>(so * (base[bi][bj][v].x + acc3_re<T, V4>(acc, bi, bj, v)),
                                          so * (base[bi][bj][v].y + acc3_im<T, V4>(acc, bi, bj, v)));
                     M[(i0 + r) * n + j0 + j] = o;
-                    if (last && I != J) M[(j0 + j) * n + i0 + r] = o;
+                    if (mirror && I != J) M[(j0 + j) * n + i0 + r] = o;
                 }
             }
 }
@@ -724,12 +728,14 @@ double sweep_pass_flops(int n, int kb) {
 }
 
 // One pass of the sweep over lines[0..batch): pivot inverses, panels, then
-// the update (bracketed by ev0/ev1 when given).
+// the update (bracketed by ev0/ev1 when given).  full != 0: the last pass
+// also writes the lower triangles (full storage); else the inverses keep
+// only their upper 64 x 64 tiles.
 template <typename T>
 hipError_t launch_sweep_pass(hipStream_t st, int n, int kb, typename cplx_of<T>::type *F,
                              const int *lines, int batch, typename cplx_of<T>::type *Pbuf,
                              typename cplx_of<T>::type *Rbuf, typename cplx_of<T>::type *Cbuf,
-                             hipEvent_t ev0, hipEvent_t ev1) {
+                             int full, hipEvent_t ev0, hipEvent_t ev1) {
     typedef typename cplx_of<T>::type T2;
     const int TT = (n + SW - 1) / SW, nt = TT * (TT + 1) / 2, passes = sweep_passes(n);
     const long ublocks = batch >= 8 ? 8L * ((batch + 7) / 8) * nt : (long)batch * nt;
@@ -743,7 +749,7 @@ hipError_t launch_sweep_pass(hipStream_t st, int n, int kb, typename cplx_of<T>:
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(sweep_update_kernel<T>, dim3((unsigned)ublocks), dim3(256), 0, st, n, kb,
                        F, lines, batch, (const T2 *)Rbuf, (const T2 *)Cbuf,
-                       kb == passes - 1 ? 1 : 0);
+                       kb == passes - 1 ? 1 : 0, (kb == passes - 1 && full) ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
     return hipSuccess;
@@ -789,10 +795,10 @@ template hipError_t launch_schur<double>(hipStream_t, int, double2 *, const int 
 template hipError_t launch_schur<float>(hipStream_t, int, float2 *, const int *, const int *,
                                         int, const double2 *, const double2 *);
 template hipError_t launch_sweep_pass<double>(hipStream_t, int, int, double2 *, const int *, int,
-                                              double2 *, double2 *, double2 *, hipEvent_t,
+                                              double2 *, double2 *, double2 *, int, hipEvent_t,
                                               hipEvent_t);
 template hipError_t launch_sweep_pass<float>(hipStream_t, int, int, float2 *, const int *, int,
-                                             float2 *, float2 *, float2 *, hipEvent_t,
+                                             float2 *, float2 *, float2 *, int, hipEvent_t,
                                              hipEvent_t);
 template hipError_t launch_zgemm<double>(hipStream_t, const GemmArgs<double> &, int);
 template hipError_t launch_zgemm<float>(hipStream_t, const GemmArgs<float> &, int);

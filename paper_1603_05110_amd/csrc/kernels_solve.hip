@@ -434,6 +434,303 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- half storage
+// The stored inverses are complex symmetric, so only their upper triangles
+// need to be read: y = F v has y_r = sum_{c >= r} F[r][c] v_c (row part) +
+// sum_{c < r} F[c][r] v_c (the column parts of the rows above).  Member w of
+// a strip's team owns the rows w, w + team, ... of both products, so every
+// member streams about the same number of rows and of upper-triangle
+// elements; a wave forms the row dot of each of its rows and accumulates
+// the rows' column contributions F[r][c] v_r per lane in registers; both go
+// into the workgroup's LDS partial (LDS atomics, the column sums once per
+// product), which the workgroup publishes for columns c >= w.  After the team barrier every member sums the members'
+// partials in member order, finishes the lines (scaling, or the backward
+// subtraction from the forward result), keeps them in LDS for its next
+// vector phase and stores its own rows to x.  Partials are double-buffered
+// by step parity, so a member writing step s + 1 never meets a slower member
+// still reading step s.
+
+__device__ __forceinline__ void st_agent2(double2 *p, double2 v) { st_agent(p, v); }
+__device__ __forceinline__ double2 ld_agent2(const double2 *p) { return ld_agent(p); }
+__device__ __forceinline__ void st_agent2(float2 *p, float2 v) {
+    unsigned long long u;
+    __builtin_memcpy(&u, &v, sizeof(u));
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float2 ld_agent2(const float2 *p) {
+    unsigned long long u = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    float2 v;
+    __builtin_memcpy(&v, &u, sizeof(v));
+    return v;
+}
+
+template <typename T, int NW, int NCH, int PR>
+__global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
+    typedef typename cplx_of<T>::type T2;
+    typedef typename acc_t<T>::type A;
+    if (solve_skipped(a)) return;
+    constexpr int NTHR = NW * 64;
+    const int n = a.n;
+    // LDS: the kernel has no static LDS, so the dynamic block starts at 0 and
+    // every array is aligned to its element (the 64-bit LDS atomics need
+    // it); the atomically updated partial comes first, within the low 64 KiB
+    extern __shared__ unsigned char smem_raw[];
+    A *pre = reinterpret_cast<A *>(smem_raw);                    // [2][n] partial, real
+    A *pim = pre + 2 * n;                                        // [2][n] partial, imaginary
+    T2 *vecs = reinterpret_cast<T2 *>(pim + 2 * n);              // [2][n] product vectors
+    double2 *red = reinterpret_cast<double2 *>(vecs + 2 * n);    // [2][n] lines finished last step
+    const int nst = a.nstrips, team = a.team;
+    const int j = blockIdx.x % nst, w = blockIdx.x / nst;
+    const StripMeta s = a.strips[j];
+    // member w owns the rows w, w + team, w + 2 team, ...: every member gets
+    // long and short rows alike, so row counts and element counts balance
+    const int R = w < n ? (n - w + team - 1) / team : 0;
+    // the wave index is uniform across the wave: in an SGPR, every per-row
+    // quantity derived from it (row, product, chunk range) stays scalar
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const T2 *F = reinterpret_cast<const T2 *>(a.F);
+    T2 *parts = reinterpret_cast<T2 *>(a.part) + (long)j * 2 * SOLVE_MAX_TEAM * 2 * n;
+    unsigned *ctr = a.counters + j;
+    const long nn = (long)n * n;
+    const int S = tw_steps(s.nx);
+    const double sc = strip_scale(a.lmax ? a.lmax + s.off : nullptr, s.nx), inv = 1.0 / sc;
+    T2 m[PR][NCH];
+
+    auto entry = [&](const TwStep &t, int rho) -> int {
+        if (t.lt >= 0) {
+            if (rho < R) return w + team * rho;
+            rho -= R;
+        }
+        if (t.lb >= 0 && rho < R) return 65536 + w + team * rho;
+        return -1;
+    };
+    auto line_of = [&](const TwStep &t, int p) -> long { return s.off + (p == 0 ? t.lt : t.lb); };
+    auto kind_of = [&](const TwStep &t, int p) -> int { return p == 0 ? t.kt : t.kb; };
+    auto own = [&](int c) -> bool { return c % team == w; };
+    auto has = [&](const TwStep &t, int p) -> bool { return (p == 0 ? t.lt : t.lb) >= 0; };
+    // rows of a step: only the upper-triangle part (columns >= r) is loaded
+    auto prefetch = [&](const TwStep &t) {
+#pragma unroll
+        for (int u = 0; u < PR; ++u) {
+            const int e = entry(t, wave + NW * u);
+            const bool ok = e >= 0;
+            const int p = e >> 16, r = e & 0xFFFF;
+            const T2 *M = ok ? F + line_of(t, p) * nn + (long)r * n : F;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int col = c * 64 + lane;
+                if (ok && col < n && col >= r) m[u][c] = M[col];
+                else { m[u][c].x = 0; m[u][c].y = 0; }
+            }
+        }
+    };
+
+    // Backward lines overwrite the forward result that every member reads
+    // while finishing them, so their rows go to x one barrier later, from
+    // red, before red is reused (forward lines are stored at once).  The
+    // thread that stores red[c] is the one that overwrites it next.
+    auto store_backward = [&](const TwStep &tr) {
+        for (int p = 0; p < 2; ++p) {
+            if (!has(tr, p) || !tw_backward(kind_of(tr, p))) continue;
+            const long L = line_of(tr, p);
+            for (int c = threadIdx.x; c < n; c += NTHR)
+                if (own(c)) st_agent(a.x + L * n + c, red[p * n + c]);
+        }
+    };
+    auto team_wait = [&](unsigned target) {
+        if (threadIdx.x == 0) {
+            unsigned spins = 0;
+            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > SPIN_LIMIT ||
+                    __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __syncthreads();
+    };
+
+    TwStep t = tw_step(s.nx, 0), tp = t, tr = t;
+    bool red_valid = false;
+    prefetch(t);
+    for (int st = 0; st <= S; ++st) {
+        if (st > 0) {
+            if (red_valid) store_backward(tr);   // the lines of step st - 2
+            // finish the previous step's lines from the members' partials
+            // members u <= c (first row u) hold a partial for column c; their
+            // loads go out in batches of 8 and are summed in member order
+            const T2 *pb = parts + (long)((st - 1) & 1) * SOLVE_MAX_TEAM * 2 * n;
+            for (int c = threadIdx.x; c < n; c += NTHR) {
+                const int mc = min(team, c + 1);
+                for (int p = 0; p < 2; ++p) {
+                    if (!has(tp, p)) continue;
+                    const long L = line_of(tp, p);
+                    A yr = 0, yi = 0;
+                    for (int u0 = 0; u0 < mc; u0 += 8) {
+                        T2 v[8];
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            if (u0 + q < mc) v[q] = ld_agent2(pb + ((long)(u0 + q) * 2 + p) * n + c);
+                            else { v[q].x = 0; v[q].y = 0; }
+                        }
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) { yr += v[q].x; yi += v[q].y; }
+                    }
+                    double2 xv = cd((double)yr * inv, (double)yi * inv);
+                    if (tw_backward(kind_of(tp, p))) {
+                        const double2 o = ld_agent(a.x + L * n + c);
+                        xv = cd(o.x - xv.x, o.y - xv.y);
+                    } else if (own(c)) {
+                        st_agent(a.x + L * n + c, xv);
+                    }
+                    red[p * n + c] = xv;
+                }
+            }
+            tr = tp;
+            red_valid = true;
+        }
+        if (st == S) break;
+        __syncthreads();
+        // vector phase; lines finished last step come from LDS
+        auto xl = [&](long line, int q) -> double2 {
+            if (st > 0) {
+                if (has(tp, 0) && line == line_of(tp, 0)) return red[q];
+                if (has(tp, 1) && line == line_of(tp, 1)) return red[n + q];
+            }
+            return ld_agent(a.x + line * n + q);
+        };
+        for (int p = 0; p < 2; ++p) {
+            if (!has(t, p)) continue;
+            const long L = line_of(t, p);
+            for (int r = threadIdx.x; r < n; r += NTHR) {
+                double2 v = tw_vec(kind_of(t, p), L, (p == 0 ? t.lt : t.lb), s.nx, n, r, a.b, a.Uc, xl);
+                T2 tv; tv.x = (T)(v.x * sc); tv.y = (T)(v.y * sc);
+                vecs[p * n + r] = tv;
+            }
+        }
+        for (int i = threadIdx.x; i < 4 * n; i += NTHR) pre[i] = 0;
+        __syncthreads();
+        // row phase: each row's dot goes to the LDS partial at once (one lane);
+        // its column contributions F[r][c] v_r (c > r) accumulate per lane in
+        // registers over the wave's rows of a product and are added to the
+        // LDS partial once per product.  One loop, one row body and one flush
+        // for the rows held in registers (k < PR) and the streamed ones.
+        A cr[NCH], ci[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) { cr[c] = 0; ci[c] = 0; }
+        int cur = -1;
+        for (int k = 0;; ++k) {
+            const int e = entry(t, wave + NW * k);
+            const int p = e < 0 ? -1 : e >> 16;
+            if (p != cur) {
+                if (cur >= 0) {
+                    // the waves start at different chunks, so their atomic
+                    // adds rarely meet on one address at the same time
+                    A *qre = pre + cur * n, *qim = pim + cur * n;
+                    const int c0 = (wave * NCH) / NW;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            if ((c >= c0) != (h == 0)) continue;
+                            const int col = c * 64 + lane;
+                            if (col < n) {
+                                atomicAdd(&qre[col], cr[c]);
+                                atomicAdd(&qim[col], ci[c]);
+                            }
+                            cr[c] = 0;
+                            ci[c] = 0;
+                        }
+                }
+                cur = p;
+            }
+            if (e < 0) break;
+            const int r = e & 0xFFFF;
+            // the row sits in m[0]: rows held in registers are shifted down
+            // one slot per row, streamed rows are loaded into the freed slot
+            if (k > 0 && k < PR) {
+#pragma unroll
+                for (int u = 0; u + 1 < PR; ++u)
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) m[u][c] = m[u + 1][c];
+            }
+            if (k >= PR) {
+                const T2 *M = F + line_of(t, p) * nn + (long)r * n;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int col = c * 64 + lane;
+                    if (col < n && col >= r) m[0][c] = M[col];
+                    else { m[0][c].x = 0; m[0][c].y = 0; }
+                }
+            }
+            const T2 (&mm)[NCH] = m[0];
+            const T2 *vec = vecs + p * n;
+            const T2 vr = vec[r];
+            A dr = 0, di = 0;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                if (c * 64 + 63 < r) continue;          // chunk left of the diagonal
+                const int col = c * 64 + lane;
+                T2 v;
+                if (col < n) v = vec[col];
+                else { v.x = 0; v.y = 0; }
+                const A mx = mm[c].x, my = mm[c].y;
+                dr += mx * v.x - my * v.y;
+                di += mx * v.y + my * v.x;
+                const A ox = col > r ? mx : (A)0, oy = col > r ? my : (A)0;
+                cr[c] += ox * (A)vr.x - oy * (A)vr.y;
+                ci[c] += ox * (A)vr.y + oy * (A)vr.x;
+            }
+            dr = wave_sum(dr);
+            di = wave_sum(di);
+            if (lane == 0) {
+                atomicAdd(&pre[p * n + r], dr);
+                atomicAdd(&pim[p * n + r], di);
+            }
+        }
+        __syncthreads();
+        // publish this member's partial (columns >= w) for this step
+        {
+            T2 *pw = parts + (long)(st & 1) * SOLVE_MAX_TEAM * 2 * n + (long)w * 2 * n;
+            for (int p = 0; p < 2; ++p) {
+                if (!has(t, p)) continue;
+                for (int c = w + threadIdx.x; c < n; c += NTHR) {
+                    T2 v; v.x = (T)pre[p * n + c]; v.y = (T)pim[p * n + c];
+                    st_agent2(pw + (long)p * n + c, v);
+                }
+            }
+        }
+        // team barrier; the next step's rows are loaded while waiting
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __syncthreads();
+        const unsigned target = (unsigned)(st + 1) * team;
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        tp = t;
+        if (st + 1 < S) {
+            t = tw_step(s.nx, st + 1);
+            prefetch(t);
+        }
+        team_wait(target);
+        if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    }
+    // the last backward lines: once every member has finished them
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    team_wait((unsigned)(S + 1) * team);
+    if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    store_backward(tr);
+}
+
 // Batched solve over many strips of different widths and instances.  A
 // persistent grid takes work items from a queue (one atomic per item); an
 // item is one member of the team of workgroups that solves one strip, the
@@ -639,17 +936,82 @@ Variant variant_for(int n, int fp32, int shape = 0) {
     return {(const void *)strip_solve_kernel<double>, SOLVE_THREADS};
 }
 
+// Half-storage kernels, same tile shapes; null beyond 33 (c32) or 17 (FP64)
+// column chunks.
+Variant variant_sym_for(int n, int fp32, int shape) {
+    int nch = (n + 63) / 64;
+    shape = shape < 0 ? 0 : (shape >= SOLVE_SHAPES ? SOLVE_SHAPES - 1 : shape);
+    if (fp32) {
+        if (nch <= 3) {
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 3, 8>, 512};
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 3, 3>, 512};
+            return {(const void *)strip_solve_sym_kernel<float, 16, 3, 2>, 1024};
+        }
+        if (nch <= 9) {
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 5>, 512};
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 2>, 512};
+            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 16, 9, 2>, 1024};
+            return {(const void *)strip_solve_sym_kernel<float, 8, 9, 9>, 512};
+        }
+        if (nch <= 17) {
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 3>, 512};
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 1>, 512};
+            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 16, 17, 1>, 1024};
+            return {(const void *)strip_solve_sym_kernel<float, 8, 17, 4>, 512};
+        }
+        if (nch <= 33) return {(const void *)strip_solve_sym_kernel<float, 8, 33, 1>, 512};
+        return {nullptr, 0};
+    }
+    if (nch <= 3) {
+        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 3, 4>, 512};
+        return {(const void *)strip_solve_sym_kernel<double, 16, 3, 4>, 1024};
+    }
+    if (nch <= 9) {
+        if (shape == 0) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 3>, 512};
+        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 1>, 512};
+        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 16, 9, 1>, 1024};
+        return {(const void *)strip_solve_sym_kernel<double, 8, 9, 4>, 512};
+    }
+    if (nch <= 17) return {(const void *)strip_solve_sym_kernel<double, 8, 17, 1>, 512};
+    return {nullptr, 0};
+}
+
+size_t solve_smem(int n, int fp32, int sym) {
+    const size_t e2 = fp32 ? sizeof(float2) : sizeof(double2), ea = fp32 ? 4 : 8;
+    return sym ? 2 * (size_t)n * e2 + 2 * (size_t)n * sizeof(double2) + 4 * (size_t)n * ea
+               : 2 * (size_t)n * e2;
+}
+
+Variant pick(int n, int fp32, int shape, int sym) {
+    return sym ? variant_sym_for(n, fp32, shape) : variant_for(n, fp32, shape);
+}
+
 }  // namespace
 
-int solve_shapes() { return SOLVE_SHAPES; }
+// Shapes 0 .. 3 are the full-row kernels, 4 .. 7 the upper-triangle
+// kernels with the same tile (absent beyond their column-chunk limits).
+int solve_shapes() { return 2 * SOLVE_SHAPES; }
+int solve_shape_is_sym(int shape) { return shape >= SOLVE_SHAPES ? 1 : 0; }
+
+int solve_sym_supported(int n, int fp32) {
+    int dev = 0, lim = 0;
+    if (!variant_sym_for(n, fp32, 0).fn) return 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    return solve_smem(n, fp32, 1) <= (size_t)lim ? 1 : 0;
+}
 
 int solve_max_resident_blocks(int fp32, int n, int shape) {
     int dev = 0, cus = 0, per = 0;
+    const int sym = solve_shape_is_sym(shape);
+    if (sym && !solve_sym_supported(n, fp32)) return 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    Variant v = variant_for(n, fp32, shape);
-    size_t smem = 2 * (size_t)n * (fp32 ? sizeof(float2) : sizeof(double2));
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, v.fn, v.threads, smem) != hipSuccess)
+    Variant v = pick(n, fp32, shape % SOLVE_SHAPES, sym);
+    if (!v.fn) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, v.fn, v.threads,
+                                                     solve_smem(n, fp32, sym)) != hipSuccess)
         return 0;
     return per * cus;
 }
@@ -662,8 +1024,11 @@ hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipE
     if (e != hipSuccess) return e;
     SolveArgs args = a;
     void *params[] = {&args};
-    Variant v = variant_for(a.n, fp32, a.shape);
-    size_t smem = 2 * (size_t)a.n * (fp32 ? sizeof(float2) : sizeof(double2));
+    const int sym = solve_shape_is_sym(a.shape);
+    if (sym && (a.team > SOLVE_MAX_TEAM || !a.part)) return hipErrorInvalidConfiguration;
+    Variant v = pick(a.n, fp32, a.shape % SOLVE_SHAPES, sym);
+    if (!v.fn) return hipErrorInvalidConfiguration;
+    size_t smem = solve_smem(a.n, fp32, sym);
     dim3 grid(a.nstrips * a.team), block(v.threads);
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     e = hipLaunchCooperativeKernel(v.fn, grid, block, params, (unsigned)smem, st);

@@ -42,6 +42,8 @@ struct osm_handle {
     int *step_lines_d = nullptr, *step_first_d = nullptr;   // twisted factor steps (lines, kinds)
     int *ff_lines_d = nullptr, *ff_first_d = nullptr;
     void *Rbuf = nullptr, *Cbuf = nullptr, *Pbuf = nullptr;
+    bool sym = false;                // factor holds upper triangles only
+    void *spart = nullptr;           // half-storage solve: members' partials
     // strip vectors
     double2 *zeta = nullptr, *res = nullptr, *delta = nullptr;
     // interface vectors
@@ -181,6 +183,7 @@ std::string validate(const osm_problem *p, const osm_options *o) {
     if (!(p->p > 0)) return "Robin parameter p must be > 0";
     if (!(p->p_bc >= 0)) return "p_bc must be >= 0";
     if (!(p->dt > 0) || !(p->lap_coef > 0)) return "dt and lap_coef must be > 0";
+    if (o->solve_shape < 0 || o->solve_shape > 8) return "solve_shape must be 0 (tuned) or 1..8";
     if (!isfinite(p->beta)) return "beta not finite";
     std::vector<int> c = strip_cells_of(p);
     if ((int)c.size() != p->nsub) return "strip_cells NULL but ncx not divisible by nsub";
@@ -203,7 +206,12 @@ std::string validate(const osm_problem *p, const osm_options *o) {
 struct Sizes {
     long n, N, Lt, nglob, ng, maxnx, ncls, m;
     int fp32;
+    int sym;    // the upper-triangle solve kernels are available (partials buffer)
 };
+
+// Column counts the upper-triangle solve has kernels for (33 chunks of 64 in
+// c32, 17 in FP64); the setup also checks the device's LDS.
+static int sym_eligible(long n, int fp32) { return (n + 63) / 64 <= (fp32 ? 33 : 17); }
 
 Sizes sizes_of(const osm_problem *p, const osm_options *o) {
     Sizes s;
@@ -223,6 +231,7 @@ Sizes sizes_of(const osm_problem *p, const osm_options *o) {
     s.ncls = (long)cls.size();
     s.m = o->algo == OSM_PRECOND ? o->gmres_restart : 0;
     s.fp32 = o->prec == OSM_C32_REFINE;
+    s.sym = sym_eligible(s.n, s.fp32);
     return s;
 }
 
@@ -238,6 +247,7 @@ uint64_t device_bytes(const Sizes &s) {
         uint64_t lb = std::max<uint64_t>(fe * 2 * s.N, 16);                 // sweep panels
         b += lb * SWEEP_BK * (2ull * s.n + SWEEP_BK);
     }
+    if (s.sym) b += (uint64_t)s.N * 2 * SOLVE_MAX_TEAM * 2 * s.n * fe;  // solve partials
     b += (uint64_t)(4 * s.Lt + 3 * s.N + 2 * 2 * s.N + s.nglob + 64) * 8;
     b += (uint64_t)(s.N - 1) * s.n * 13 * 4 + (uint64_t)(s.N - 1) * 8;  // guess features
     b += 3ull * s.ng * 16 + 2ull * ((s.ng + 255) / 256) * 8;           // guess history
@@ -306,7 +316,8 @@ osm_status fslot(osm_handle *h, double flops, hipEvent_t *e0, hipEvent_t *e1) {
 template <typename T>
 osm_status factor_chain(osm_handle *h, typename cplx_of<T>::type *F, const double2 *Dc,
                         const double2 *Uc, int nsteps, const std::vector<int> &batch,
-                        const std::vector<int> &off, const int *lines_d, const int *kind_d) {
+                        const std::vector<int> &off, const int *lines_d, const int *kind_d,
+                        bool full) {
     typedef typename cplx_of<T>::type T2;
     int n = h->n;
     T2 *R = (T2 *)h->Rbuf, *C = (T2 *)h->Cbuf, *Pb = (T2 *)h->Pbuf;
@@ -322,7 +333,8 @@ osm_status factor_chain(osm_handle *h, typename cplx_of<T>::type *F, const doubl
                 osm_status s = fslot(h, bt * sweep_pass_flops(n, kb), &e0, &e1);
                 if (s != OSM_OK) return s;
             }
-            HIPCHK(h, launch_sweep_pass<T>(h->st, n, kb, F, lines, bt, Pb, R, C, e0, e1));
+            HIPCHK(h, launch_sweep_pass<T>(h->st, n, kb, F, lines, bt, Pb, R, C, full ? 1 : 0,
+                                           e0, e1));
         }
     }
     return OSM_OK;
@@ -335,10 +347,10 @@ osm_status do_factor(osm_handle *h) {
     int depth = (int)h->step_batch.size();
     if (h->fp32)
         s = factor_chain<float>(h, (float2 *)h->F, h->Dc, h->Uc, depth, h->step_batch,
-                                h->step_off, h->step_lines_d, h->step_first_d);
+                                h->step_off, h->step_lines_d, h->step_first_d, true);
     else
         s = factor_chain<double>(h, (double2 *)h->F, h->Dc, h->Uc, depth, h->step_batch,
-                                 h->step_off, h->step_lines_d, h->step_first_d);
+                                 h->step_off, h->step_lines_d, h->step_first_d, true);
     if (s != OSM_OK) return s;
     h->factored = true;
     return OSM_OK;
@@ -353,7 +365,9 @@ osm_status do_factor(osm_handle *h) {
 // strip once), plus b, x and the coupling coefficients once.
 double single_solve_bytes(const osm_handle *h) {
     double es = h->fp32 ? 8.0 : 16.0;
-    return (2.0 * h->Lt - h->N) * (double)h->n * h->n * es + (double)h->Lt * h->n * 80.0;
+    double per = solve_shape_is_sym(h->shape) ? 0.5 * (double)h->n * (h->n + 1)
+                                              : (double)h->n * h->n;
+    return (2.0 * h->Lt - h->N) * per * es + (double)h->Lt * h->n * 80.0;
 }
 
 osm_status prof_collect(osm_handle *h) {
@@ -394,6 +408,7 @@ osm_status do_solve(osm_handle *h, const double2 *b, double2 *x, const StepCtl *
     a.ctl = ctl;
     a.ran = nullptr;
     a.lmax = nullptr;
+    a.part = h->spart;
     if (h->fp32) {
         HIPCHK(h, launch_line_absmax(h->st, h->P, b, h->sscale, ctl));
         a.lmax = h->sscale;
@@ -725,7 +740,8 @@ osm_status build_lh(osm_handle *h) {
         const StripMeta &sm = h->strips_h[rep[cl]];
         int nx = sm.nx;
         HIPCHK(h, launch_coef(h->st, h->P, h->strips_d, h->line_strip_d, nullptr, 1, fD, fU, sm.off, nx));
-        s = factor_chain<double>(h, FF, fD, fU, nx, one, offs, h->ff_lines_d, h->ff_first_d);
+        s = factor_chain<double>(h, FF, fD, fU, nx, one, offs, h->ff_lines_d, h->ff_first_d,
+                                 true);
         if (s != OSM_OK) break;
         double2 *X1 = h->LH + (long)(4 * cl + 0) * nn, *X2 = h->LH + (long)(4 * cl + 1) * nn;
         double2 *X3 = h->LH + (long)(4 * cl + 2) * nn, *X4 = h->LH + (long)(4 * cl + 3) * nn;
@@ -804,8 +820,9 @@ static osm_status available_bytes(const osm_options *opt, uint64_t *cap) {
 // Allocates and initialises one instance (problem and options validated,
 // footprint already checked by the caller).
 static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hipStream_t stream,
-                            osm_handle **out) {
+                            osm_handle **out, bool allow_sym) {
     Sizes sz = sizes_of(prob, opt);
+    sz.sym = allow_sym && sz.sym && solve_sym_supported((int)sz.n, sz.fp32);
     {
         // the strip solve keeps both products of a step (2 ny complex values)
         // in one workgroup's LDS
@@ -921,6 +938,11 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for Cbuf");
             h->Pbuf = dalloc<char>(h, lb * SWEEP_BK * SWEEP_BK, &e);
             if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for Pbuf");
+            h->sym = sz.sym != 0;
+            if (h->sym) {
+                h->spart = dalloc<char>(h, fe * (size_t)h->N * 2 * SOLVE_MAX_TEAM * 2 * h->n, &e);
+                if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for solve partials");
+            }
         }
         SALLOC(h->Dc, double2, (long)h->Lt * h->n * 3);
         SALLOC(h->Uc, double2, (long)h->Lt * h->n * 3);
@@ -986,9 +1008,13 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             HIPCHK(h, hipMemcpy(h->gctl, &c0, sizeof(c0), hipMemcpyHostToDevice));
         }
         // workgroups per strip in the solve: fill the resident capacity
-        int cap = solve_max_resident_blocks(h->fp32, h->n, 0);
+        if (h->opt.solve_shape > 0) h->shape = h->opt.solve_shape - 1;
+        if (solve_shape_is_sym(h->shape) && !h->spart)
+            return fail(h, OSM_EINVAL, "solve_shape: no upper-triangle kernel for this ny and precision");
+        int cap = solve_max_resident_blocks(h->fp32, h->n, h->shape);
         if (cap <= 0) return fail(h, OSM_EHIP, "occupancy query failed");
         h->team_cap = std::max(1, std::min(cap / h->N, h->n));
+        if (solve_shape_is_sym(h->shape)) h->team_cap = std::min(h->team_cap, SOLVE_MAX_TEAM);
         int team = h->opt.team > 0 ? h->opt.team : std::min(16, h->team_cap);
         h->team = std::min(team, h->team_cap);
         h->team_tuned = h->opt.team > 0;
@@ -1020,7 +1046,7 @@ osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_
     if (need > cap)
         return fail(nullptr, OSM_ENOMEM, "footprint " + std::to_string(need) +
                                              " B exceeds available " + std::to_string(cap) + " B");
-    return setup_one(prob, opt, (hipStream_t)hip_stream, out);
+    return setup_one(prob, opt, (hipStream_t)hip_stream, out, true);
 }
 
 // Autotuner of the strip solve: the tile shape (waves per workgroup, rows
@@ -1042,7 +1068,10 @@ static osm_status autotune_team(osm_handle *h) {
     int best = h->team, best_shape = h->shape;
     double best_ms = 1e300;
     for (int shape = 0; shape < solve_shapes(); ++shape) {
+        if (h->opt.solve_shape > 0 && shape != h->opt.solve_shape - 1) continue;
+        if (solve_shape_is_sym(shape) && !h->spart) continue;
         int cap = solve_max_resident_blocks(h->fp32, h->n, shape);
+        if (cap <= 0) continue;
         int tcap = std::max(1, std::min(std::min(cap / h->N, h->n), 64));
         for (int t : cand) {
             if (t > tcap) break;
@@ -1540,7 +1569,9 @@ osm_status osm_query_batch(const osm_problem *probs, int32_t nb, const osm_optio
         osm_footprint f;
         osm_status s = osm_query(&probs[b], opt, &f);
         if (s != OSM_OK) return s;
-        dev += f.device_bytes;
+        Sizes sz = sizes_of(&probs[b], opt);
+        sz.sym = 0;     // batched instances use the batched solve only
+        dev += device_bytes(sz);
         host += f.host_bytes;
         nst += probs[b].nsub;
         nlines += probs[b].ncx + probs[b].nsub;
@@ -1773,7 +1804,7 @@ osm_status osm_setup_batch(const osm_problem *probs, int32_t nb, const osm_optio
         d.max_ng = 0;
         for (int b = 0; b < nb; ++b) {
             osm_handle *u = nullptr;
-            osm_status r = setup_one(&probs[b], &so, h->st, &u);
+            osm_status r = setup_one(&probs[b], &so, h->st, &u, false);
             if (r != OSM_OK) return fail(h, r, "instance " + std::to_string(b) + ": " + g_setup_error);
             h->sub.push_back(u);
             d.max_ny = std::max(d.max_ny, u->n);

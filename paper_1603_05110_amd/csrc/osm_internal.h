@@ -107,14 +107,15 @@ hipError_t launch_schur(hipStream_t st, int n, typename cplx_of<T>::type *F,
 // In-place inversion of the Schur complements of lines[0..batch) by the
 // blocked symmetric sweep, one pass (pivot block kb) per call, passes
 // 0 .. sweep_passes(n)-1 in order; Pbuf: batch x 128 x 128, Rbuf/Cbuf:
-// batch x 128 x n.  ev0/ev1 (may be null) bracket the update kernel.
+// batch x 128 x n.  full != 0 leaves full storage, else upper triangles
+// only.  ev0/ev1 (may be null) bracket the update kernel.
 int sweep_passes(int n);
 double sweep_pass_flops(int n, int kb);
 template <typename T>
 hipError_t launch_sweep_pass(hipStream_t st, int n, int kb, typename cplx_of<T>::type *F,
                              const int *lines, int batch, typename cplx_of<T>::type *Pbuf,
                              typename cplx_of<T>::type *Rbuf, typename cplx_of<T>::type *Cbuf,
-                             hipEvent_t ev0, hipEvent_t ev1);
+                             int full, hipEvent_t ev0, hipEvent_t ev1);
 template <typename T>
 struct GemmArgs {
     int M, N, K;
@@ -137,10 +138,13 @@ template <typename T>
 hipError_t launch_convert(hipStream_t st, long n, const double2 *src, typename cplx_of<T>::type *dst);
 
 // kernels_solve.hip
+#define SOLVE_MAX_TEAM 64   // workgroups per strip in the solve, at most
+
 struct SolveArgs {
     int n;
     int team;
-    int shape;               // tile shape, 0 .. solve_shapes()-1
+    int shape;               // tile shape, 0 .. solve_shapes()-1 (the upper half
+                             // are the kernels that read upper triangles only)
     int nstrips;
     const StripMeta *strips;
     const void *F;           // factor (double2 or float2), line stride n*n
@@ -152,6 +156,9 @@ struct SolveArgs {
     const StepCtl *ctl;      // may be null; the whole solve is skipped when it
                              // says the fixed point is done
     int *ran;                // may be null; set to 1 when the solve was not skipped
+    void *part;              // upper-triangle shapes: the members' partial buffer,
+                             // nstrips x 2 x SOLVE_MAX_TEAM x 2 x n values of
+                             // the factor's complex type; else unused
     const double *lmax;      // may be null (no scaling); per packed line the
                              // largest |b|: strip j's right-hand side enters the
                              // reduced-precision products as s_j b with s_j the
@@ -163,6 +170,10 @@ hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipE
                               hipEvent_t ev1);
 int solve_shapes();
 int solve_max_resident_blocks(int fp32, int n, int shape);
+// 1 for the shapes of the upper-triangle (half-storage) solve kernels
+int solve_shape_is_sym(int shape);
+// 1 when the half-storage solve has a kernel for n and fits the device's LDS
+int solve_sym_supported(int n, int fp32);
 
 // kernels_control.hip
 // Step configuration and device-side state of one time step.

@@ -80,6 +80,33 @@ def test_strip_solve_matches_oracle(prec, tol, shape):
     assert rel(x, packed(orc, ref)) < tol
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("c32", 2e-6)])
+@pytest.mark.parametrize("ncy", [99, 512])
+@pytest.mark.parametrize("solve_shape", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_every_solve_tile_shape_matches_oracle(prec, tol, ncy, solve_shape):
+    """Every kernel and tile shape of the strip solve (full rows or upper
+    triangles of the stored inverses, waves per workgroup x rows held in
+    registers), forced instead of autotuned, at 2 and 9 column chunks."""
+    log(f"strip_solve shape {solve_shape} {prec} ny={ncy + 1}")
+    osm = _osm()
+    cells = (4, 5, 3)
+    pb = Problem(-3.0, 3.0, -16.0, 16.0, sum(cells), ncy, 3, list(cells), lap_coef=0.5, beta=-20.0,
+                 p=4.0, p_bc=4.0, dt=5e-3)
+    _, W = rand_state(pb, 7)
+    orc = SchwarzOracle(pb, W)
+    rng = np.random.default_rng(8)
+    bs = [rng.standard_normal((c + 1, pb.ncy + 1)) + 1j * rng.standard_normal((c + 1, pb.ncy + 1))
+          for c in cells]
+    ref = [orc._lu[j].solve(bs[j].ravel()).reshape(bs[j].shape) for j in range(len(cells))]
+    for team in (0, 4):
+        s = osm.OsmSolver(pb, DEV, prec=prec, solve_shape=solve_shape, team=team)
+        s.factor(to_dev(W))
+        x = s.strip_solve(to_dev(packed(orc, bs))).cpu().numpy()
+        assert s.solve_shape() == solve_shape - 1
+        s.close()
+        assert rel(x, packed(orc, ref)) < tol, team
+
+
 @pytest.mark.parametrize("fixed_k,fixed_q", [(1, 1), (3, 2)])
 def test_fixed_iteration_classical_matches_oracle(fixed_k, fixed_q):
     """Same (k, q) counts, cold fixed-point start: rounding-level agreement of
