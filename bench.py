@@ -38,22 +38,39 @@ MFMA_FP64_PEAK_TFLOPS = 78.6
 
 # HBM bytes per strip-solve launch from rocprofv3 FETCH_SIZE + WRITE_SIZE on
 # this workload, each scaled by the counter's reading for a 1 GiB copy
-# (fetch x2.0, write x1.0); valid only for the kernel source it was taken on.
-SOLVE_TRAFFIC = {"c32": {"bytes": 2.2731e+09,
-                         "source_sha256": "5bf97e13243aa5a7a7a1d2342f478d2f7fd6d523afe0d5ccf2f65d81a4fb456b",
+# (fetch x2.0, write x1.0); valid only for the full-row kernel whose source
+# text (the strip_solve_pf_kernel template) hashes to source_sha256.
+SOLVE_TRAFFIC = {"c32": {"bytes": 2.2735e+09,
+                         "source_sha256": "427dd2531ba5469ab300de4e91e0f9200a5ad9efd470d7320c82d5afbecaaade",
                          "summary": "profiles/strip_solve_c32_gpe512_hbm_counters.md"}}
 
 
-def measured_traffic(prec):
-    import hashlib
-    rec = SOLVE_TRAFFIC.get(prec)
-    if rec is None:
-        return None
+def pf_kernel_source():
+    """Source text of the full-row strip-solve kernel template (its
+    definition up to the closing brace), which the counters describe."""
     path = os.path.join(ROOT, "paper_1603_05110_amd", "csrc", "kernels_solve.hip")
     try:
-        sha = hashlib.sha256(open(path, "rb").read()).hexdigest()
+        src = open(path).read()
     except OSError:
         return None
+    key = "void strip_solve_pf_kernel(SolveArgs a) {"
+    i = src.find(key)
+    if i < 0:
+        return None
+    i = src.rfind("template <", 0, i)
+    j = src.find("\n}\n", i)
+    return src[i:j + 3] if j > 0 else None
+
+
+def measured_traffic(prec, kernel_name):
+    import hashlib
+    rec = SOLVE_TRAFFIC.get(prec)
+    if rec is None or not kernel_name.startswith("strip_solve_pf_kernel"):
+        return None
+    src = pf_kernel_source()
+    if src is None:
+        return None
+    sha = hashlib.sha256(src.encode()).hexdigest()
     return rec["bytes"] if sha == rec["source_sha256"] else None
 
 
@@ -548,6 +565,8 @@ def main():
 
     avg_ms = main_run["solve_ms"] / max(main_run["solve_launches"], 1)
     nbytes = main_run["solve_work"] / max(main_run["solve_launches"], 1)
+    # tile shapes 0-3: full-row kernel, 4-7: upper-triangle kernel
+    solve_kernel = "strip_solve_pf_kernel" if main_run["shape"] < 4 else "strip_solve_sym_kernel"
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
 
     fp64 = None
@@ -606,9 +625,10 @@ def main():
         "iters": {"k_mean": float(np.mean(ks)), "k_max": int(np.max(ks)),
                   "q_total": int(np.sum(qs)), "gmres_total": int(np.sum(gm)),
                   "gmres_per_step": float(np.mean(gm))},
-        "roofline": {"kernel": "strip_solve", "bound": "hbm", "achieved": achieved,
+        "roofline": {"kernel": solve_kernel, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.prec), "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms,
+                     "traffic": measured_traffic(args.prec, solve_kernel), "bytes_per_launch": nbytes,
+                     "avg_launch_ms": avg_ms,
                      "launches": main_run["solve_launches"],
                      "workgroups_per_strip": main_run["team"],
                      "tile_shape": main_run["shape"]},

@@ -629,23 +629,17 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
             const int p = e < 0 ? -1 : e >> 16;
             if (p != cur) {
                 if (cur >= 0) {
-                    // the waves start at different chunks, so their atomic
-                    // adds rarely meet on one address at the same time
                     A *qre = pre + cur * n, *qim = pim + cur * n;
-                    const int c0 = (wave * NCH) / NW;
 #pragma unroll
-                    for (int h = 0; h < 2; ++h)
-#pragma unroll
-                        for (int c = 0; c < NCH; ++c) {
-                            if ((c >= c0) != (h == 0)) continue;
-                            const int col = c * 64 + lane;
-                            if (col < n) {
-                                atomicAdd(&qre[col], cr[c]);
-                                atomicAdd(&qim[col], ci[c]);
-                            }
-                            cr[c] = 0;
-                            ci[c] = 0;
+                    for (int c = 0; c < NCH; ++c) {
+                        const int col = c * 64 + lane;
+                        if (col < n) {
+                            atomicAdd(&qre[col], cr[c]);
+                            atomicAdd(&qim[col], ci[c]);
                         }
+                        cr[c] = 0;
+                        ci[c] = 0;
+                    }
                 }
                 cur = p;
             }
@@ -951,15 +945,18 @@ Variant variant_sym_for(int n, int fp32, int shape) {
             if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 5>, 512};
             if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 2>, 512};
             if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 16, 9, 2>, 1024};
-            return {(const void *)strip_solve_sym_kernel<float, 8, 9, 9>, 512};
+            return {(const void *)strip_solve_sym_kernel<float, 8, 9, 3>, 512};
         }
         if (nch <= 17) {
-            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 3>, 512};
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 2>, 512};
             if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 1>, 512};
             if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 16, 17, 1>, 1024};
-            return {(const void *)strip_solve_sym_kernel<float, 8, 17, 4>, 512};
+            return {(const void *)strip_solve_sym_kernel<float, 4, 17, 2>, 256};
         }
-        if (nch <= 33) return {(const void *)strip_solve_sym_kernel<float, 8, 33, 1>, 512};
+        if (nch <= 33) {
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 4, 33, 1>, 256};
+            return {(const void *)strip_solve_sym_kernel<float, 8, 33, 1>, 512};
+        }
         return {nullptr, 0};
     }
     if (nch <= 3) {
@@ -970,9 +967,12 @@ Variant variant_sym_for(int n, int fp32, int shape) {
         if (shape == 0) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 3>, 512};
         if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 1>, 512};
         if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 16, 9, 1>, 1024};
-        return {(const void *)strip_solve_sym_kernel<double, 8, 9, 4>, 512};
+        return {(const void *)strip_solve_sym_kernel<double, 8, 9, 2>, 512};
     }
-    if (nch <= 17) return {(const void *)strip_solve_sym_kernel<double, 8, 17, 1>, 512};
+    if (nch <= 17) {
+        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 4, 17, 1>, 256};
+        return {(const void *)strip_solve_sym_kernel<double, 8, 17, 1>, 512};
+    }
     return {nullptr, 0};
 }
 

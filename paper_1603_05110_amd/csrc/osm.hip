@@ -1073,6 +1073,16 @@ static osm_status autotune_team(osm_handle *h) {
         int cap = solve_max_resident_blocks(h->fp32, h->n, shape);
         if (cap <= 0) continue;
         int tcap = std::max(1, std::min(std::min(cap / h->N, h->n), 64));
+        {
+            // one untimed launch per shape: a kernel's first launch can pay
+            // one-time costs (code and scratch set-up) that would skew it
+            h->team = std::min(cand[0], tcap);
+            h->shape = shape;
+            h->prof = false;
+            osm_status s = do_solve(h, h->res, h->delta);
+            if (s == OSM_OK) s = check_solve_error(h);
+            if (s != OSM_OK) { h->prof = prof; return s; }
+        }
         for (int t : cand) {
             if (t > tcap) break;
             h->team = t;
