@@ -112,6 +112,42 @@ hipError_t launch_step_init(hipStream_t st, StepCtl *c, const StepCfg &cfg) {
     return hipGetLastError();
 }
 
+// one thread per 32-bit word of each structure; the stores go to pinned
+// host memory and are visible to the host once the stream has synchronised
+__global__ void ctl_gather_kernel(const StepCtl *s, const GmresCtl *g, const int *err,
+                                  CtlMirror *out) {
+    const int t = threadIdx.x;
+    constexpr int ws = (int)(sizeof(StepCtl) / sizeof(int)), wg = (int)(sizeof(GmresCtl) / sizeof(int));
+    static_assert(sizeof(StepCtl) % sizeof(int) == 0 && sizeof(GmresCtl) % sizeof(int) == 0,
+                  "control structures are copied as 32-bit words");
+    static_assert(ws + wg + 1 <= 256, "one thread per word");
+    if (t < ws) reinterpret_cast<int *>(&out->s)[t] = reinterpret_cast<const int *>(s)[t];
+    else if (t < ws + wg) {
+        if (g) reinterpret_cast<int *>(&out->g)[t - ws] = reinterpret_cast<const int *>(g)[t - ws];
+    } else if (t == ws + wg) {
+        out->err = *err;
+    }
+}
+
+hipError_t launch_ctl_gather(hipStream_t st, const StepCtl *s, const GmresCtl *g, const int *err,
+                             CtlMirror *out) {
+    hipLaunchKernelGGL(ctl_gather_kernel, dim3(1), dim3(256), 0, st, s, g, err, out);
+    return hipGetLastError();
+}
+
+__global__ void scalar_gather_kernel(const int *flag, const double *val, CtlMirror *out) {
+    if (threadIdx.x == 0) {
+        if (flag) out->flag = *flag;
+        out->val = *val;
+    }
+}
+
+hipError_t launch_scalar_gather(hipStream_t st, const int *flag, const double *val,
+                                CtlMirror *out) {
+    hipLaunchKernelGGL(scalar_gather_kernel, dim3(1), dim3(64), 0, st, flag, val, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_iter_reset(hipStream_t st, StepCtl *c, GmresCtl *g) {
     hipLaunchKernelGGL(iter_reset_kernel, dim3(1), dim3(64), 0, st, c, g);
     return hipGetLastError();

@@ -98,13 +98,22 @@ __device__ __forceinline__ void lh_matvec_body(Phys P, const StripMeta *strips,
 // (new l_{j+1}) = X^3 l_j + X^4 r_j (eq. Lmpi; l_0 and r_{N-1} are zero).
 // It keeps its R rows of its two blocks in registers and loops over the
 // strips j = group, group + G, ... of that class, writing each result
-// itself; every output trace has exactly one writer and no barrier is needed.
-template <int NCH, int R>
-__global__ __launch_bounds__(256) void lh_matvec_reg_kernel(Phys P, const StripMeta *strips,
-                                                            const double2 *LH, const double2 *x,
-                                                            double2 *y, int mode_p,
-                                                            const GmresCtl *ctl) {
+// itself; every output trace has exactly one writer.  The inputs l_j, r_j
+// of SB strips at a time are loaded together and staged in LDS, so one
+// memory latency serves SB strips.
+//
+// DOTS (Arnoldi step, y = x - L_h x with x = V_{nv-1}): the kernel also
+// forms the first Gram-Schmidt pass's partial products V_k^H y over the
+// outputs it wrote, k < nv <= 64: lane k loads V_k at each output (lane
+// nv-1 thereby holds x), accumulates conj(V_k) y, and the workgroup writes
+// its nv partials to part[block][k] (stride ld), summed in a fixed order.
+template <int NCH, int R, int SB, bool DOTS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void lh_matvec_reg_kernel(
+    Phys P, const StripMeta *strips, const double2 *LH, const double2 *x, double2 *y,
+    int mode_p, const GmresCtl *ctl, const double2 *V, long ng, int nv, double2 *part, int ld) {
     if (ctl && ctl->done) return;
+    constexpr int W = NCH * 64, SPT = (2 * W + 255) / 256;
+    __shared__ double2 stage[SB][2 * W];   // [strip of the batch][l_j | r_j]
     const int n = P.ny, N = P.nsub, cls = blockIdx.y, G = gridDim.z;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int side = wave & 1, r0 = blockIdx.x * 2 * R + (wave >> 1) * R;
@@ -121,40 +130,104 @@ __global__ __launch_bounds__(256) void lh_matvec_reg_kernel(Phys P, const StripM
             m0[rr][c] = ok ? B0[(long)row * n + col] : cd(0.0, 0.0);
             m1[rr][c] = ok ? B1[(long)row * n + col] : cd(0.0, 0.0);
         }
-    for (int j = blockIdx.z; j < N; j += G) {
-        if (strips[j].cls != cls) continue;
-        bool has = side == 0 ? j >= 1 : j <= N - 2;
-        if (!has) continue;
-        const double2 *vl = j >= 1 ? x + (long)(2 * (j - 1) + 1) * n : nullptr;
-        const double2 *vr = j <= N - 2 ? x + (long)(2 * j) * n : nullptr;
-        double ar[R], ai[R];
+    auto next_strip = [&](int j) {
+        for (j += G; j < N && strips[j].cls != cls; j += G) {}
+        return j;
+    };
+    auto has_out = [&](int j) { return side == 0 ? j >= 1 : j <= N - 2; };
+    auto out_trace = [&](int j) { return side == 0 ? 2 * (j - 1) : 2 * j + 1; };
+    double2 acc = cd(0.0, 0.0);
+    int j0 = next_strip(blockIdx.z - G);
+    while (j0 < N) {
+        int js[SB];
+        js[0] = j0;
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) { ar[rr] = 0.0; ai[rr] = 0.0; }
+        for (int b = 1; b < SB; ++b) js[b] = js[b - 1] < N ? next_strip(js[b - 1]) : N;
+        // every load of the batch in flight together
+        double2 stg[SB][SPT];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            int col = c * 64 + lane;
-            double2 wl = (vl && col < n) ? vl[col] : cd(0.0, 0.0);
-            double2 wr = (vr && col < n) ? vr[col] : cd(0.0, 0.0);
+        for (int b = 0; b < SB; ++b)
 #pragma unroll
-            for (int rr = 0; rr < R; ++rr) {
-                ar[rr] += m0[rr][c].x * wl.x - m0[rr][c].y * wl.y + m1[rr][c].x * wr.x - m1[rr][c].y * wr.y;
-                ai[rr] += m0[rr][c].x * wl.y + m0[rr][c].y * wl.x + m1[rr][c].x * wr.y + m1[rr][c].y * wr.x;
+            for (int q = 0; q < SPT; ++q) {
+                const int e = threadIdx.x + 256 * q, v = e >= W, col = e - v * W, j = js[b];
+                const double2 *src =
+                    j >= N ? nullptr
+                           : (v == 0 ? (j >= 1 ? x + (long)(2 * (j - 1) + 1) * n : nullptr)
+                                     : (j <= N - 2 ? x + (long)(2 * j) * n : nullptr));
+                stg[b][q] = (e < 2 * W && src && col < n) ? src[col] : cd(0.0, 0.0);
             }
-        }
-        int t = side == 0 ? 2 * (j - 1) : 2 * j + 1;
+        double2 vk[SB][R];
+        if constexpr (DOTS) {
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) {
-            double sr = wsum(ar[rr]), si = wsum(ai[rr]);
-            int a = r0 + rr;
-            if (lane == 0 && a < n) {
-                long o = (long)t * n + a;
-                if (mode_p) {
-                    double2 xv = x[o];
-                    y[o] = cd(xv.x - sr, xv.y - si);
-                } else {
-                    y[o] = cd(sr, si);
+            for (int b = 0; b < SB; ++b)
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    const int j = js[b], a = r0 + rr;
+                    const bool ok = j < N && has_out(j) && lane < nv && a < n;
+                    vk[b][rr] = ok ? V[(long)lane * ng + (long)out_trace(j) * n + a]
+                                   : cd(0.0, 0.0);
+                }
+        }
+        __syncthreads();   // the previous batch is no longer read
+#pragma unroll
+        for (int b = 0; b < SB; ++b)
+#pragma unroll
+            for (int q = 0; q < SPT; ++q) {
+                const int e = threadIdx.x + 256 * q;
+                if (e < 2 * W) stage[b][e] = stg[b][q];
+            }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+            const int j = js[b];
+            if (j >= N || !has_out(j)) continue;
+            const int t = out_trace(j);
+            const double2 *sl = stage[b], *sr_ = stage[b] + W;
+            double ar[R], ai[R];
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) { ar[rr] = 0.0; ai[rr] = 0.0; }
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const double2 wl = sl[c * 64 + lane], wr = sr_[c * 64 + lane];
+#pragma unroll
+                for (int rr = 0; rr < R; ++rr) {
+                    ar[rr] += m0[rr][c].x * wl.x - m0[rr][c].y * wl.y + m1[rr][c].x * wr.x - m1[rr][c].y * wr.y;
+                    ai[rr] += m0[rr][c].x * wl.y + m0[rr][c].y * wl.x + m1[rr][c].x * wr.y + m1[rr][c].y * wr.x;
                 }
             }
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr) {
+                double sr = wsum(ar[rr]), si = wsum(ai[rr]);
+                int a = r0 + rr;
+                if (a >= n) continue;
+                long o = (long)t * n + a;
+                if constexpr (DOTS) {
+                    const double2 v = vk[b][rr];
+                    const double xr = __shfl(v.x, nv - 1, 64), xi = __shfl(v.y, nv - 1, 64);
+                    const double2 wo = cd(xr - sr, xi - si);
+                    if (lane == 0) y[o] = wo;
+                    acc.x += v.x * wo.x + v.y * wo.y;   // conj(V_k) y
+                    acc.y += v.x * wo.y - v.y * wo.x;
+                } else if (lane == 0) {
+                    if (mode_p) {
+                        double2 xv = x[o];
+                        y[o] = cd(xv.x - sr, xv.y - si);
+                    } else {
+                        y[o] = cd(sr, si);
+                    }
+                }
+            }
+        }
+        j0 = js[SB - 1] < N ? next_strip(js[SB - 1]) : N;
+    }
+    if constexpr (DOTS) {
+        __shared__ double2 red[4][64];
+        red[wave][lane] = acc;
+        __syncthreads();
+        if (threadIdx.x < nv) {
+            const int k = threadIdx.x;
+            const long b = blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
+            part[b * ld + k] = cadd(cadd(red[0][k], red[1][k]), cadd(red[2][k], red[3][k]));
         }
     }
 }
@@ -313,6 +386,34 @@ __device__ __forceinline__ void reduce_dots(const double2 *part, int nb, int ld,
     }
 }
 
+// dots[k] = sum over b < np of part[b * ld + k], k < nv <= 64, with all
+// 256 threads: thread t sums the partials b = t / nv (mod S), S = 256 / nv,
+// of k = t % nv, then the S slot sums are added in slot order (the result
+// depends only on np and nv, so it is the same in every workgroup).
+__device__ __forceinline__ void reduce_parts_wide(const double2 *part, int np, int ld, int nv,
+                                                  double2 *dots) {
+    __shared__ double2 slot_sum[256];
+    const int S = 256 / nv, t = threadIdx.x;
+    if (t < S * nv) {
+        const int k = t % nv, sl = t / nv;
+        double2 a0 = cd(0.0, 0.0), a1 = a0;
+        int b = sl;
+        for (; b + S < np; b += 2 * S) {
+            a0 = cadd(a0, part[(long)b * ld + k]);
+            a1 = cadd(a1, part[(long)(b + S) * ld + k]);
+        }
+        if (b < np) a0 = cadd(a0, part[(long)b * ld + k]);
+        slot_sum[t] = cadd(a0, a1);
+    }
+    __syncthreads();
+    if (t < nv) {
+        double2 s = cd(0.0, 0.0);
+        for (int sl = 0; sl < S; ++sl) s = cadd(s, slot_sum[sl * nv + t]);
+        dots[t] = s;
+    }
+    __syncthreads();
+}
+
 // First pass: partial dots of w = V_{j+1} (the new Arnoldi vector) with V_0..V_j.
 __global__ __launch_bounds__(256) void cgs_dots_kernel(long n, const double2 *V, int nv,
                                                        const double2 *w, double2 *part, int ld,
@@ -391,21 +492,14 @@ __global__ void scale_ctl_kernel(long n, const double2 *x, double2 *y, const Gmr
     if (e < n) y[e] = cscale(ctl->inv_hn, x[e]);
 }
 
-// Column j of the Hessenberg matrix from the two Gram-Schmidt passes and
-// ||w||, the previous rotations applied, and a new complex Givens rotation
-// [[conj(c), conj(s)], [-s, c]] (c = a/rho, s = b/rho) that zeroes h_{j+1,j};
-// the rotated right-hand side e gives the residual norm |e_{j+1}|.  One wave.
-__global__ __launch_bounds__(256) void gmres_givens_kernel(int j, int m, const double2 *part1,
-                                                           const double2 *part2, int nb,
-                                                           const double *part, int np, double2 *H,
-                                                           double2 *cs, double2 *sn, double2 *e,
-                                                           GmresCtl *ctl) {
-    if (ctl->done) return;
-    __shared__ double2 h[256];
-    // h_{i,j} = first-pass + second-pass projections, reduced over chunks
-    reduce_dots(part1, nb, m + 1, j + 1, h, 0);
-    reduce_dots(part2, nb, m + 1, j + 1, h, 1);
-    double hn = sqrt(wave_reduce_parts(part, np));
+// Column j of the Hessenberg matrix (h[0..j] in LDS, subdiagonal hn) is
+// stored, the previous rotations applied, and a new complex Givens rotation
+// [[conj(c), conj(s)], [-s, c]] (c = a/rho, s = b/rho) zeroes h_{j+1,j}; the
+// rotated right-hand side e gives the residual norm |e_{j+1}|.  Called by
+// one whole workgroup at the end of its kernel; thread 0 does the serial part.
+__device__ __forceinline__ void givens_column(int j, int m, const double2 *h, double hn,
+                                              double2 *H, double2 *cs, double2 *sn, double2 *e,
+                                              GmresCtl *ctl) {
     double2 *col = H + (long)j * (m + 1);    // column-major, column j
     for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h[i];
     __syncthreads();
@@ -435,6 +529,91 @@ __global__ __launch_bounds__(256) void gmres_givens_kernel(int j, int m, const d
     ctl->inv_hn = hn > 0 ? 1.0 / hn : 0.0;
     if (!isfinite(hn) || !isfinite(res)) { ctl->bad = 1; ctl->done = 1; return; }
     if (res <= ctl->tol * ctl->bnorm || hn == 0.0) { ctl->done = 1; ctl->conv = 1; }
+}
+
+// Column j from the two Gram-Schmidt passes' partials and ||w|| (one
+// workgroup).
+__global__ __launch_bounds__(256) void gmres_givens_kernel(int j, int m, const double2 *part1,
+                                                           const double2 *part2, int nb,
+                                                           const double *part, int np, double2 *H,
+                                                           double2 *cs, double2 *sn, double2 *e,
+                                                           GmresCtl *ctl) {
+    if (ctl->done) return;
+    __shared__ double2 h[256];
+    // h_{i,j} = first-pass + second-pass projections, reduced over chunks
+    reduce_dots(part1, nb, m + 1, j + 1, h, 0);
+    reduce_dots(part2, nb, m + 1, j + 1, h, 1);
+    double hn = sqrt(wave_reduce_parts(part, np));
+    givens_column(j, m, h, hn, H, cs, sn, e, ctl);
+}
+
+// Fused Arnoldi step, after lh_matvec_reg_kernel<.., true>: the first-pass
+// projections h1 reduced from the matvec's np partials, w <- w - V h1 over
+// this chunk, then the chunk's partials of V^H w (second pass, part_out) and
+// of |w|^2 (norm_part).  Workgroup 0 stores h1 as column j of H.
+__global__ __launch_bounds__(256) void cgs_pass1_kernel(long n, const double2 *V, int nv,
+                                                        const double2 *part_in, int np, int ld,
+                                                        double2 *w, double2 *part_out,
+                                                        double *norm_part, double2 *hcol,
+                                                        const GmresCtl *ctl) {
+    if (ctl->done) return;
+    __shared__ double2 dots[256];
+    __shared__ double red[4];
+    reduce_parts_wide(part_in, np, ld, nv, dots);
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < nv; i += blockDim.x) hcol[i] = dots[i];
+    long lo, hi;
+    chunk_range(n, &lo, &hi);
+    double s = 0.0;
+    for (long el = lo + threadIdx.x; el < hi; el += blockDim.x) {
+        double2 acc = cd(0.0, 0.0);
+        for (int k = 0; k < nv; ++k) acc = cadd(acc, cmul(dots[k], V[(long)k * n + el]));
+        double2 o = csub(w[el], acc);
+        w[el] = o;
+        s += o.x * o.x + o.y * o.y;
+    }
+    __syncthreads();   // this chunk of w is final (each element is read back by its writer)
+    chunk_dots(n, V, nv, w, lo, hi, part_out, ld);
+    s = wsum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) norm_part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Fused Arnoldi step, last kernel: the second-pass projections h2 from the
+// nb partials; the new vector's norm from |w|^2 - |h2|^2 (w minus its
+// projection on the orthonormal basis: the two are orthogonal, so their
+// squared norms add up); w <- (w - V h2) / hn over this chunk, which makes
+// w the next basis vector; workgroup 0 adds h2 to column j (h1, stored by
+// cgs_pass1_kernel) and applies the rotations.
+__global__ __launch_bounds__(256) void cgs_pass2_kernel(int j, int m, long n, const double2 *V,
+                                                        double2 *w, const double2 *part2, int nb,
+                                                        const double *norm_part, double2 *H,
+                                                        double2 *cs, double2 *sn, double2 *e,
+                                                        GmresCtl *ctl) {
+    if (ctl->done) return;
+    __shared__ double2 h2[256];
+    const int nv = j + 1;
+    reduce_parts_wide(part2, nb, m + 1, nv, h2);
+    const double n1 = wave_reduce_parts(norm_part, nb);
+    double s2 = 0.0;
+    for (int k = 0; k < nv; ++k) s2 += h2[k].x * h2[k].x + h2[k].y * h2[k].y;
+    const double hn2 = n1 - s2;
+    const double hn = !isfinite(hn2) ? hn2 : (hn2 > 0.0 ? sqrt(hn2) : 0.0);
+    const double inv = hn > 0.0 && isfinite(hn) ? 1.0 / hn : 0.0;
+    long lo, hi;
+    chunk_range(n, &lo, &hi);
+    for (long el = lo + threadIdx.x; el < hi; el += blockDim.x) {
+        double2 acc = cd(0.0, 0.0);
+        for (int k = 0; k < nv; ++k) acc = cadd(acc, cmul(h2[k], V[(long)k * n + el]));
+        w[el] = cscale(inv, csub(w[el], acc));
+    }
+    if (blockIdx.x != 0) return;
+    __syncthreads();
+    const double2 *col = H + (long)j * (m + 1);
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) h2[i] = cadd(col[i], h2[i]);
+    __syncthreads();
+    givens_column(j, m, h2, hn, H, cs, sn, e, ctl);
 }
 
 // End of a cycle: y = R^{-1} e over the ctl->j columns of the rotated
@@ -491,27 +670,53 @@ static inline unsigned lh_grid(const Phys &P) {
     return 8u * ntr * ((ntile + 7) / 8);
 }
 
+// Grid of the register-resident L_h kernel: (row tiles, classes, strip
+// groups), the groups chosen so the grid fits one round of resident
+// workgroups (two per CU at this register use), at most one group per
+// strip.  x = 0 when ny needs more than 17 column chunks.
+static dim3 lh_reg_grid(const Phys &P, int ncls) {
+    int nch = (P.ny + 63) / 64;
+    if (nch > 17) return dim3(0, 0, 0);
+    int tiles = (P.ny + 1) / 2;
+    int g = 512 / max(1, tiles * ncls);
+    return dim3(tiles, ncls, (unsigned)max(1, min(g, P.nsub)));
+}
+
+int lh_fused_blocks(int ny, int nsub, int ncls) {
+    Phys P;
+    P.ny = ny;
+    P.nsub = nsub;
+    dim3 g = lh_reg_grid(P, ncls);
+    return (int)(g.x * g.y * g.z);
+}
+
 // L_h x (mode_p = 0) or x - L_h x (mode_p = 1); ctl may be null.  The
 // register-resident kernel reuses every block row over the strips of its
-// group; beyond 17 column chunks the row-per-wave kernel is used.
+// group; beyond 17 column chunks the row-per-wave kernel is used.  With
+// part given (register-resident kernel only, mode_p = 1, x = V_{nv-1},
+// nv <= 64) the first Gram-Schmidt pass's partials go to part.
 static hipError_t lh_apply(hipStream_t st, const Phys &P, const StripMeta *strips, int ncls,
                            const double2 *LH, const double2 *x, double2 *y, int mode_p,
-                           const GmresCtl *ctl) {
+                           const GmresCtl *ctl, const double2 *V = nullptr, long ng = 0,
+                           int nv = 0, double2 *part = nullptr, int ld = 0) {
     int nch = (P.ny + 63) / 64;
-    // strip groups: the grid fits one round of resident workgroups (two per
-    // CU at this register use), at most one group per strip
-    auto groups = [&](int tiles) {
-        int g = 512 / max(1, tiles * ncls);
-        return (unsigned)max(1, min(g, P.nsub));
-    };
+    dim3 grid = lh_reg_grid(P, ncls);
+    if (part && (nch > 17 || mode_p != 1 || nv < 1 || nv > 64 || !V))
+        return hipErrorInvalidValue;
     if (nch <= 9) {
-        int tiles = (P.ny + 3) / 4;
-        hipLaunchKernelGGL((lh_matvec_reg_kernel<9, 2>), dim3(tiles, ncls, groups(tiles)),
-                           dim3(256), 0, st, P, strips, LH, x, y, mode_p, ctl);
+        if (part)
+            hipLaunchKernelGGL((lh_matvec_reg_kernel<9, 1, 4, true>), grid, dim3(256), 0, st, P,
+                               strips, LH, x, y, mode_p, ctl, V, ng, nv, part, ld);
+        else
+            hipLaunchKernelGGL((lh_matvec_reg_kernel<9, 1, 4, false>), grid, dim3(256), 0, st, P,
+                               strips, LH, x, y, mode_p, ctl, V, ng, nv, part, ld);
     } else if (nch <= 17) {
-        int tiles = (P.ny + 1) / 2;
-        hipLaunchKernelGGL((lh_matvec_reg_kernel<17, 1>), dim3(tiles, ncls, groups(tiles)),
-                           dim3(256), 0, st, P, strips, LH, x, y, mode_p, ctl);
+        if (part)
+            hipLaunchKernelGGL((lh_matvec_reg_kernel<17, 1, 1, true>), grid, dim3(256), 0, st, P,
+                               strips, LH, x, y, mode_p, ctl, V, ng, nv, part, ld);
+        else
+            hipLaunchKernelGGL((lh_matvec_reg_kernel<17, 1, 1, false>), grid, dim3(256), 0, st, P,
+                               strips, LH, x, y, mode_p, ctl, V, ng, nv, part, ld);
     } else if (ctl) {
         hipLaunchKernelGGL(lh_matvec_ctl_kernel, dim3(lh_grid(P)), dim3(256), 0, st, P, strips, LH,
                            x, y, ctl);
@@ -531,11 +736,26 @@ hipError_t launch_gmres_iteration(hipStream_t st, const Phys &P, const StripMeta
                                   int ncls, const double2 *LH, long n, int j, int m, double2 *V,
                                   double2 *part1, double2 *part2, double *norm_part,
                                   double2 *H, double2 *cs, double2 *sn, double2 *e,
-                                  GmresCtl *ctl) {
+                                  GmresCtl *ctl, double2 *mvpart) {
     double2 *vj = V + (long)j * n, *w = V + (long)(j + 1) * n;
     unsigned nb = (unsigned)gmres_chunks(n);
     unsigned ne = (unsigned)((n + 255) / 256);
     int ld = m + 1;
+    const int np1 = lh_fused_blocks(P.ny, P.nsub, ncls);
+    if (mvpart && np1 > 0 && j + 1 <= 64) {
+        // three kernels: matvec with the first pass's partials, first update
+        // with the second pass's partials, second update with normalisation
+        // and rotation
+        hipError_t er = lh_apply(st, P, strips, ncls, LH, vj, w, 1, ctl, V, n, j + 1, mvpart, ld);
+        if (er != hipSuccess) return er;
+        hipLaunchKernelGGL(cgs_pass1_kernel, dim3(nb), dim3(256), 0, st, n, (const double2 *)V,
+                           j + 1, (const double2 *)mvpart, np1, ld, w, part2, norm_part,
+                           H + (long)j * ld, (const GmresCtl *)ctl);
+        hipLaunchKernelGGL(cgs_pass2_kernel, dim3(nb), dim3(256), 0, st, j, m, n,
+                           (const double2 *)V, w, (const double2 *)part2, (int)nb,
+                           (const double *)norm_part, H, cs, sn, e, ctl);
+        return hipGetLastError();
+    }
     hipError_t er = lh_apply(st, P, strips, ncls, LH, vj, w, 1, ctl);
     if (er != hipSuccess) return er;
     hipLaunchKernelGGL(cgs_dots_kernel, dim3(nb), dim3(256), 0, st, n, V, j + 1, w, part1, ld,

@@ -55,6 +55,7 @@ struct osm_handle {
     double *sscale = nullptr;        // per-line largest |b| (scale of the complex-FP32 solve)
     unsigned *counters = nullptr;
     int *err_d = nullptr;
+    CtlMirror *mirror = nullptr;   // pinned host memory (hipHostMalloc)
     int team = 0;
     // L_h
     int ncls = 0;
@@ -65,6 +66,7 @@ struct osm_handle {
     GmresCtl *gctl = nullptr;
     double2 *gH = nullptr, *gcs = nullptr, *gsn = nullptr, *ge = nullptr, *gy = nullptr;
     double2 *gdots1 = nullptr, *gdots2 = nullptr;
+    double2 *gmv = nullptr;        // partials of the fused matvec (may stay null)
     double *gnorm_part = nullptr;
     double *norm_part = nullptr;
     // kernel timing (HIP events around every solve launch when enabled)
@@ -86,6 +88,9 @@ struct osm_handle {
     StepCtl *sctl = nullptr;
     double *upd_part = nullptr;
     int q_chunk = 3;
+    // GMRES iterations enqueued with the first chunk of Schwarz iteration k:
+    // one more than iteration k of the previous step needed (0: GMRES_CHUNK)
+    std::vector<int> gm_chunk;
     // state
     bool factored = false, has_guess = false;
     int team_cap = 0;            // largest co-resident team of the current shape
@@ -255,6 +260,7 @@ uint64_t device_bytes(const Sizes &s) {
         b += 4ull * s.ncls * s.n * s.n * 16;            // L_h blocks
         b += (uint64_t)(s.m + 2) * s.ng * 16;           // Krylov basis
         b += 2ull * 256 * (s.m + 1) * 16;               // Gram-Schmidt partials
+        b += (uint64_t)lh_fused_blocks((int)s.n, (int)s.N, (int)s.ncls) * (s.m + 1) * 16;
         b += 2ull * s.maxnx * s.n * s.n * 16 + (uint64_t)s.n * s.n * 16;  // L_h build temporaries
         b += 2ull * s.maxnx * s.n * 3 * 16;
     }
@@ -535,7 +541,7 @@ osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
             for (int jj = j; jj < j + ch; ++jj)
                 HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->ncls, h->LH, n, jj, m, V,
                                                  h->gdots1, h->gdots2, h->gnorm_part, h->gH,
-                                                 h->gcs, h->gsn, h->ge, h->gctl));
+                                                 h->gcs, h->gsn, h->ge, h->gctl, h->gmv));
             j += ch;
             HIPCHK(h, hipMemcpyAsync(&c, h->gctl, sizeof(c), hipMemcpyDeviceToHost, h->st));
             HIPCHK(h, hipStreamSynchronize(h->st));
@@ -567,11 +573,17 @@ osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
 // synchronises once per Schwarz iteration in the common case and only
 // enqueues more work when a fixed point or GMRES needs more iterations.
 
+// Synchronises and reads the step control, the GMRES control and the solve's
+// barrier flag.  Timing slots are collected only when they run out or when
+// timing is queried, so the step loop pays no extra copies for them.
 osm_status read_ctl(osm_handle *h, StepCtl *c, GmresCtl *g) {
-    HIPCHK(h, hipMemcpyAsync(c, h->sctl, sizeof(StepCtl), hipMemcpyDeviceToHost, h->st));
-    if (g && h->m > 0)
-        HIPCHK(h, hipMemcpyAsync(g, h->gctl, sizeof(GmresCtl), hipMemcpyDeviceToHost, h->st));
-    return check_solve_error(h);   // synchronises, checks the barrier flag, collects timing
+    const bool wg = g && h->m > 0;
+    HIPCHK(h, launch_ctl_gather(h->st, h->sctl, wg ? h->gctl : nullptr, h->err_d, h->mirror));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    *c = h->mirror->s;
+    if (wg) *g = h->mirror->g;
+    if (h->mirror->err) return fail(h, OSM_EHIP, "strip solve: barrier wait timed out");
+    return OSM_OK;
 }
 
 osm_status fp_chunk(osm_handle *h, const double2 *u, int nq) {
@@ -590,11 +602,11 @@ osm_status gmres_iters(osm_handle *h, int j0, int j1) {
     for (int j = j0; j < j1; ++j)
         HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->ncls, h->LH, h->ng, j, h->m, h->Vb,
                                          h->gdots1, h->gdots2, h->gnorm_part, h->gH, h->gcs,
-                                         h->gsn, h->ge, h->gctl));
+                                         h->gsn, h->ge, h->gctl, h->gmv));
     return OSM_OK;
 }
 
-osm_status after_fixed_point(osm_handle *h) {
+osm_status after_fixed_point(osm_handle *h, int gchunk) {
     long ng = h->ng;
     HIPCHK(h, launch_flux(h->st, h->P, h->strips_d, h->g, h->zeta, h->gn, h->trace_part, h->sctl));
     HIPCHK(h, launch_flux_finalize(h->st, h->trace_part, 2 * (h->N - 1), h->sctl));
@@ -606,7 +618,7 @@ osm_status after_fixed_point(osm_handle *h) {
     HIPCHK(h, launch_precond_rhs(h->st, ng, h->g, h->gn, h->gtmp, h->gx, h->sctl));
     HIPCHK(h, launch_gmres_begin(h->st, ng, h->gtmp, h->gnorm_part, 1, 1.0, h->Vb, h->ge, h->m,
                                  h->gctl, h->sctl));
-    osm_status s = gmres_iters(h, 0, std::min(GMRES_CHUNK, h->m));
+    osm_status s = gmres_iters(h, 0, std::min(gchunk, h->m));
     if (s != OSM_OK) return s;
     HIPCHK(h, launch_gmres_finish(h->st, ng, h->m, h->gH, h->ge, h->gy, h->Vb, h->gx, h->gctl, 1));
     HIPCHK(h, launch_precond_update(h->st, ng, h->g, h->gx, h->upd_part, h->sctl, h->gctl));
@@ -672,14 +684,17 @@ osm_status schwarz_device(osm_handle *h, const double2 *u, osm_step_stats *S) {
         S->refine_total = h->fp32 ? c.q_total : 0;
     };
     osm_status s;
+    int gm_prev = 0;
     for (int k = 1; k <= nk; ++k) {
+        const int gchunk =
+            k < (int)h->gm_chunk.size() && h->gm_chunk[k] > 0 ? h->gm_chunk[k] : GMRES_CHUNK;
         HIPCHK(h, launch_iter_reset(h->st, h->sctl, h->m > 0 ? h->gctl : nullptr));
         if (k > 1 && !o.warm_start)
             HIPCHK(h, launch_copy_u_guarded(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta,
                                             h->sctl));
         int nq = o.fixed_q > 0 ? o.fixed_q : std::max(1, std::min(o.max_q, h->q_chunk));
         if ((s = fp_chunk(h, u, nq)) != OSM_OK) return s;
-        if ((s = after_fixed_point(h)) != OSM_OK) return s;
+        if ((s = after_fixed_point(h, gchunk)) != OSM_OK) return s;
         if ((s = read_ctl(h, &c, &gc)) != OSM_OK) return s;
         while (!c.q_conv && !c.bad) {
             if (c.q_fail) {
@@ -688,13 +703,20 @@ osm_status schwarz_device(osm_handle *h, const double2 *u, osm_step_stats *S) {
             }
             nq = std::max(1, std::min(h->q_chunk, o.max_q - c.q_iter));
             if ((s = fp_chunk(h, u, nq)) != OSM_OK) return s;
-            if ((s = after_fixed_point(h)) != OSM_OK) return s;
+            if ((s = after_fixed_point(h, gchunk)) != OSM_OK) return s;
             if ((s = read_ctl(h, &c, &gc)) != OSM_OK) return s;
         }
         if (!c.bad && o.fixed_q <= 0) h->q_chunk = std::max(2, c.q_iter);
         if (!c.bad && !cfg.classical && c.r_done == 1)
             if ((s = gmres_continue(h, gc, c)) != OSM_OK) { fill(); return s; }
         fill();
+        if (!cfg.classical && h->m > 0) {
+            // GMRES iterations left over in a chunk still cost their launches
+            // (each returns at once), a chunk too short costs a host round trip
+            if ((int)h->gm_chunk.size() <= k) h->gm_chunk.resize(k + 1, 0);
+            h->gm_chunk[k] = std::max(2, std::min(h->m, c.gm_total - gm_prev + 1));
+            gm_prev = c.gm_total;
+        }
         if (c.bad) return fail(h, OSM_ENONFINITE, "non-finite value in the Schwarz iteration");
         if (c.k_done) return OSM_OK;
     }
@@ -966,6 +988,11 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         SALLOC(h->err_d, int, 1);
         SALLOC(h->ran_d, int, PROF_SLOTS);
         SALLOC(h->sctl, StepCtl, 1);
+        if (hipHostMalloc((void **)&h->mirror, sizeof(CtlMirror), hipHostMallocDefault) !=
+            hipSuccess) {
+            h->mirror = nullptr;
+            return fail(h, OSM_ENOMEM, "hipHostMalloc failed for the control mirror");
+        }
         SALLOC(h->nX, float, (long)(h->N - 1) * 9 * h->n);
         SALLOC(h->nY, float, (long)(h->N - 1) * 4 * h->n);
         SALLOC(h->nS, double, h->N - 1);
@@ -989,6 +1016,8 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             SALLOC(h->gdots1, double2, (long)gmres_chunks(h->ng) * (h->m + 1));
             SALLOC(h->gdots2, double2, (long)gmres_chunks(h->ng) * (h->m + 1));
             SALLOC(h->gnorm_part, double, (h->ng + 255) / 256);
+            if (long nb1 = lh_fused_blocks(h->n, h->N, (int)sz.ncls))
+                SALLOC(h->gmv, double2, nb1 * (h->m + 1));
         }
         HIPCHK(h, hipMemcpy(h->strips_d, h->strips_h.data(), sizeof(StripMeta) * h->N, hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(h->line_strip_d, line_strip.data(), sizeof(int) * h->Lt, hipMemcpyHostToDevice));
@@ -1143,8 +1172,9 @@ osm_status osm_factor_rotating(osm_handle *h, int32_t n) {
 static osm_status mass_of(osm_handle *h, const double2 *u, double *out) {
     HIPCHK(h, launch_mass_partials(h->st, h->P, u, h->mass_part));
     HIPCHK(h, launch_sum(h->st, h->mass_part, h->nglob, 1, h->scal + 4));
-    HIPCHK(h, hipMemcpyAsync(out, h->scal + 4, sizeof(double), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, launch_scalar_gather(h->st, nullptr, h->scal + 4, h->mirror));
     HIPCHK(h, hipStreamSynchronize(h->st));
+    *out = h->mirror->val;
     return OSM_OK;
 }
 
@@ -1158,15 +1188,16 @@ osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats) {
     osm_step_stats S;
     memset(&S, 0, sizeof(S));
     osm_status s;
-    // reject non-finite input
+    // reject non-finite input; the mass of u_{n-1} comes back with the same
+    // synchronisation
     HIPCHK(h, hipMemsetAsync(h->flag_d, 0, sizeof(int), h->st));
     HIPCHK(h, launch_check_finite(h->st, u, (long)h->nglob * h->n, h->flag_d));
-    int bad = 0;
-    HIPCHK(h, hipMemcpyAsync(&bad, h->flag_d, sizeof(int), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, launch_mass_partials(h->st, h->P, u, h->mass_part));
+    HIPCHK(h, launch_sum(h->st, h->mass_part, h->nglob, 1, h->scal + 4));
+    HIPCHK(h, launch_scalar_gather(h->st, h->flag_d, h->scal + 4, h->mirror));
     HIPCHK(h, hipStreamSynchronize(h->st));
-    if (bad) return fail(h, OSM_ENONFINITE, "u_{n-1} contains NaN or Inf");
-    s = mass_of(h, u, &S.mass_before);
-    if (s != OSM_OK) return s;
+    if (h->mirror->flag) return fail(h, OSM_ENONFINITE, "u_{n-1} contains NaN or Inf");
+    S.mass_before = h->mirror->val;
     // start of the interface iteration: the previous converged vector (the
     // paper's choice), an external guess, or a prediction from the last two
     // converged vectors (learned network or linear extrapolation); a
@@ -2038,6 +2069,7 @@ void osm_destroy(osm_handle *h) {
     for (hipEvent_t e : h->evs) hipEventDestroy(e);
     for (hipEvent_t e : h->fevs) hipEventDestroy(e);
     for (void *p : h->allocs) hipFree(p);
+    if (h->mirror) hipHostFree(h->mirror);
     delete h;
 }
 

@@ -230,6 +230,22 @@ struct GmresCtl {
     double inv_hn;  // 1 / h_{j+1,j} (normalisation of the next basis vector)
     double resid;   // current residual estimate
 };
+// Host-visible copy of the step's control state: one small kernel writes
+// the step control, the GMRES control (when g is given) and the solve's error
+// flag into pinned host memory, so the host reads all three after one
+// synchronisation instead of three device-to-host copies.
+struct CtlMirror {
+    StepCtl s;
+    GmresCtl g;
+    int err;
+    int flag;     // launch_scalar_gather: a device flag
+    double val;   // launch_scalar_gather: a device scalar
+};
+hipError_t launch_ctl_gather(hipStream_t st, const StepCtl *s, const GmresCtl *g, const int *err,
+                             CtlMirror *out);
+// copies *flag (when given) and *val into out->flag and out->val
+hipError_t launch_scalar_gather(hipStream_t st, const int *flag, const double *val,
+                                CtlMirror *out);
 // sctl (may be null): the cycle starts only when the Schwarz map of the
 // current iteration has been evaluated.
 hipError_t launch_gmres_begin(hipStream_t st, long n, const double2 *r, double *norm_part,
@@ -238,11 +254,17 @@ hipError_t launch_gmres_begin(hipStream_t st, long n, const double2 *r, double *
 // chunks of the Gram-Schmidt partial dot products for vectors of length n
 // (part buffers hold gmres_chunks(n) x (m + 1) values)
 int gmres_chunks(long n);
+// One Arnoldi step j.  mvpart (may be null): lh_fused_blocks(P, ncls) x
+// (m + 1) partials of the fused three-kernel form, used when that is > 0
+// and j < 64; otherwise the six-kernel form (matvec, dots, two updates,
+// rotation, normalisation).
 hipError_t launch_gmres_iteration(hipStream_t st, const Phys &P, const StripMeta *strips,
                                   int ncls, const double2 *LH, long n, int j, int m, double2 *V,
                                   double2 *part1, double2 *part2, double *norm_part,
                                   double2 *H, double2 *cs, double2 *sn, double2 *e,
-                                  GmresCtl *ctl);
+                                  GmresCtl *ctl, double2 *mvpart);
+// workgroups of the register-resident L_h kernel (0: not used for this ny)
+int lh_fused_blocks(int ny, int nsub, int ncls);
 hipError_t launch_gmres_finish(hipStream_t st, long n, int m, const double2 *H, const double2 *e,
                                double2 *y, const double2 *V, double2 *x, GmresCtl *ctl,
                                int require_done);
