@@ -466,20 +466,38 @@ __device__ __forceinline__ float2 ld_agent2(const float2 *p) {
     return v;
 }
 
+// Per-wave partial regions in LDS: when NW regions of both products fit
+// (with the product vectors and the finished lines) in 120 KiB, each wave
+// writes its own column sums with plain stores and the workgroup adds the
+// regions in wave order; otherwise the waves add into one partial with LDS
+// atomics.  The bound uses the instance's widest line, NCH * 64.
+template <typename T, int NW, int NCH>
+constexpr bool sym_wave_regions() {
+    return (size_t)NW * 2 * NCH * 64 * 2 * sizeof(typename acc_t<T>::type) +
+               (size_t)2 * NCH * 64 * 2 * sizeof(T) + (size_t)2 * NCH * 64 * 16 <=
+           (size_t)120 * 1024;
+}
+
 template <typename T, int NW, int NCH, int PR>
 __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
     typedef typename cplx_of<T>::type T2;
     typedef typename acc_t<T>::type A;
+    typedef typename cplx_of<A>::type A2;
+    constexpr bool WR = sym_wave_regions<T, NW, NCH>();
     if (solve_skipped(a)) return;
     constexpr int NTHR = NW * 64;
     const int n = a.n;
     // LDS: the kernel has no static LDS, so the dynamic block starts at 0 and
     // every array is aligned to its element (the 64-bit LDS atomics need
-    // it); the atomically updated partial comes first, within the low 64 KiB
+    // it); the partial comes first: either NW per-wave regions [NW][2][n]
+    // of complex sums, or one atomically updated [2][n] real and [2][n]
+    // imaginary partial
     extern __shared__ unsigned char smem_raw[];
-    A *pre = reinterpret_cast<A *>(smem_raw);                    // [2][n] partial, real
-    A *pim = pre + 2 * n;                                        // [2][n] partial, imaginary
-    T2 *vecs = reinterpret_cast<T2 *>(pim + 2 * n);              // [2][n] product vectors
+    A2 *wreg = reinterpret_cast<A2 *>(smem_raw);
+    A *pre = reinterpret_cast<A *>(smem_raw);
+    A *pim = pre + 2 * n;
+    T2 *vecs = WR ? reinterpret_cast<T2 *>(wreg + (size_t)NW * 2 * n)
+                  : reinterpret_cast<T2 *>(pim + 2 * n);         // [2][n] product vectors
     double2 *red = reinterpret_cast<double2 *>(vecs + 2 * n);    // [2][n] lines finished last step
     const int nst = a.nstrips, team = a.team;
     const int j = blockIdx.x % nst, w = blockIdx.x / nst;
@@ -562,29 +580,47 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
         if (st > 0) {
             if (red_valid) store_backward(tr);   // the lines of step st - 2
             // finish the previous step's lines from the members' partials
-            // members u <= c (first row u) hold a partial for column c; their
-            // loads go out in batches of 8 and are summed in member order
+            // members u <= c (first row u) hold a partial for column c; the
+            // loads of both products go out together in batches of members
+            // (after the forward result a backward line subtracts from) and
+            // are summed in member order
             const T2 *pb = parts + (long)((st - 1) & 1) * SOLVE_MAX_TEAM * 2 * n;
             for (int c = threadIdx.x; c < n; c += NTHR) {
                 const int mc = min(team, c + 1);
-                for (int p = 0; p < 2; ++p) {
-                    if (!has(tp, p)) continue;
-                    const long L = line_of(tp, p);
-                    A yr = 0, yi = 0;
-                    for (int u0 = 0; u0 < mc; u0 += 8) {
-                        T2 v[8];
+                const bool h0 = has(tp, 0), h1 = has(tp, 1);
+                double2 o[2];
+                A yr[2] = {0, 0}, yi[2] = {0, 0};
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) {
-                            if (u0 + q < mc) v[q] = ld_agent2(pb + ((long)(u0 + q) * 2 + p) * n + c);
-                            else { v[q].x = 0; v[q].y = 0; }
+                for (int p = 0; p < 2; ++p) {
+                    const bool hp = p == 0 ? h0 : h1;
+                    o[p] = hp && tw_backward(kind_of(tp, p)) ? ld_agent(a.x + line_of(tp, p) * n + c)
+                                                             : cd(0.0, 0.0);
+                }
+                // (4 members per batch in the 16-wave tiles, whose waves
+                // have half the registers)
+                constexpr int UB = NW >= 16 ? (sizeof(T) == 8 ? 2 : 4) : 8;
+                for (int u0 = 0; u0 < mc; u0 += UB) {
+                    T2 v[2][UB];
+#pragma unroll
+                    for (int p = 0; p < 2; ++p)
+#pragma unroll
+                        for (int q = 0; q < UB; ++q) {
+                            const bool hp = p == 0 ? h0 : h1;
+                            if (hp && u0 + q < mc) v[p][q] = ld_agent2(pb + ((long)(u0 + q) * 2 + p) * n + c);
+                            else { v[p][q].x = 0; v[p][q].y = 0; }
                         }
 #pragma unroll
-                        for (int q = 0; q < 8; ++q) { yr += v[q].x; yi += v[q].y; }
-                    }
-                    double2 xv = cd((double)yr * inv, (double)yi * inv);
+                    for (int p = 0; p < 2; ++p)
+#pragma unroll
+                        for (int q = 0; q < UB; ++q) { yr[p] += v[p][q].x; yi[p] += v[p][q].y; }
+                }
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    if (!(p == 0 ? h0 : h1)) continue;
+                    const long L = line_of(tp, p);
+                    double2 xv = cd((double)yr[p] * inv, (double)yi[p] * inv);
                     if (tw_backward(kind_of(tp, p))) {
-                        const double2 o = ld_agent(a.x + L * n + c);
-                        xv = cd(o.x - xv.x, o.y - xv.y);
+                        xv = cd(o[p].x - xv.x, o[p].y - xv.y);
                     } else if (own(c)) {
                         st_agent(a.x + L * n + c, xv);
                     }
@@ -613,7 +649,8 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
                 vecs[p * n + r] = tv;
             }
         }
-        for (int i = threadIdx.x; i < 4 * n; i += NTHR) pre[i] = 0;
+        if constexpr (!WR)
+            for (int i = threadIdx.x; i < 4 * n; i += NTHR) pre[i] = 0;
         __syncthreads();
         // row phase: each row's dot goes to the LDS partial at once (one lane);
         // its column contributions F[r][c] v_r (c > r) accumulate per lane in
@@ -623,22 +660,39 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
         A cr[NCH], ci[NCH];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) { cr[c] = 0; ci[c] = 0; }
-        int cur = -1;
+        int cur = -1, flushed = 0;
         for (int k = 0;; ++k) {
             const int e = entry(t, wave + NW * k);
             const int p = e < 0 ? -1 : e >> 16;
             if (p != cur) {
                 if (cur >= 0) {
-                    A *qre = pre + cur * n, *qim = pim + cur * n;
+                    if constexpr (WR) {
+                        A2 *q = wreg + (size_t)(wave * 2 + cur) * n;
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) {
-                        const int col = c * 64 + lane;
-                        if (col < n) {
-                            atomicAdd(&qre[col], cr[c]);
-                            atomicAdd(&qim[col], ci[c]);
+                        for (int c = 0; c < NCH; ++c) {
+                            const int col = c * 64 + lane;
+                            if (col < n) {
+                                A2 v;
+                                v.x = cr[c];
+                                v.y = ci[c];
+                                q[col] = v;
+                            }
+                            cr[c] = 0;
+                            ci[c] = 0;
                         }
-                        cr[c] = 0;
-                        ci[c] = 0;
+                        flushed |= 1 << cur;
+                    } else {
+                        A *qre = pre + cur * n, *qim = pim + cur * n;
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            const int col = c * 64 + lane;
+                            if (col < n) {
+                                atomicAdd(&qre[col], cr[c]);
+                                atomicAdd(&qim[col], ci[c]);
+                            }
+                            cr[c] = 0;
+                            ci[c] = 0;
+                        }
                     }
                 }
                 cur = p;
@@ -682,9 +736,29 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
             }
             dr = wave_sum(dr);
             di = wave_sum(di);
-            if (lane == 0) {
+            if constexpr (WR) {
+                // the row's own result joins column r of the column sums,
+                // held by lane r % 64 in chunk r / 64 (every lane has the sum)
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+                    if (c == (r >> 6) && lane == (r & 63)) {
+                        cr[c] += dr;
+                        ci[c] += di;
+                    }
+            } else if (lane == 0) {
                 atomicAdd(&pre[p * n + r], dr);
                 atomicAdd(&pim[p * n + r], di);
+            }
+        }
+        if constexpr (WR) {
+            // a product this wave had no rows of gets a zero region
+            for (int p = 0; p < 2; ++p) {
+                if (!has(t, p) || (flushed >> p & 1)) continue;
+                A2 *q = wreg + (size_t)(wave * 2 + p) * n;
+                A2 z;
+                z.x = 0;
+                z.y = 0;
+                for (int col = lane; col < n; col += 64) q[col] = z;
             }
         }
         __syncthreads();
@@ -694,7 +768,21 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
             for (int p = 0; p < 2; ++p) {
                 if (!has(t, p)) continue;
                 for (int c = w + threadIdx.x; c < n; c += NTHR) {
-                    T2 v; v.x = (T)pre[p * n + c]; v.y = (T)pim[p * n + c];
+                    T2 v;
+                    if constexpr (WR) {
+                        A sr = 0, si = 0;
+#pragma unroll
+                        for (int u = 0; u < NW; ++u) {
+                            const A2 q = wreg[(size_t)(u * 2 + p) * n + c];
+                            sr += q.x;
+                            si += q.y;
+                        }
+                        v.x = (T)sr;
+                        v.y = (T)si;
+                    } else {
+                        v.x = (T)pre[p * n + c];
+                        v.y = (T)pim[p * n + c];
+                    }
                     st_agent2(pw + (long)p * n + c, v);
                 }
             }
@@ -883,6 +971,7 @@ __global__ void zero_u32_kernel(unsigned *p, int n, int *err, int *ran) {
 struct Variant {
     const void *fn;
     int threads;
+    int wregs;   // upper-triangle kernel with per-wave partial regions
 };
 
 // Tile shapes of the strip solve for a column count n and a precision: the
@@ -937,49 +1026,73 @@ Variant variant_sym_for(int n, int fp32, int shape) {
     shape = shape < 0 ? 0 : (shape >= SOLVE_SHAPES ? SOLVE_SHAPES - 1 : shape);
     if (fp32) {
         if (nch <= 3) {
-            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 3, 8>, 512};
-            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 3, 3>, 512};
-            return {(const void *)strip_solve_sym_kernel<float, 16, 3, 2>, 1024};
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 3, 8>, 512,
+                    (int)sym_wave_regions<float, 8, 3>()};
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 3, 3>, 512,
+                    (int)sym_wave_regions<float, 8, 3>()};
+            return {(const void *)strip_solve_sym_kernel<float, 16, 3, 2>, 1024,
+                    (int)sym_wave_regions<float, 16, 3>()};
         }
         if (nch <= 9) {
-            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 5>, 512};
-            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 2>, 512};
-            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 16, 9, 2>, 1024};
-            return {(const void *)strip_solve_sym_kernel<float, 8, 9, 3>, 512};
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 5>, 512,
+                    (int)sym_wave_regions<float, 8, 9>()};
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 2>, 512,
+                    (int)sym_wave_regions<float, 8, 9>()};
+            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 16, 9, 2>, 1024,
+                    (int)sym_wave_regions<float, 16, 9>()};
+            return {(const void *)strip_solve_sym_kernel<float, 8, 9, 3>, 512,
+                    (int)sym_wave_regions<float, 8, 9>()};
         }
         if (nch <= 17) {
-            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 2>, 512};
-            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 1>, 512};
-            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 16, 17, 1>, 1024};
-            return {(const void *)strip_solve_sym_kernel<float, 4, 17, 2>, 256};
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 2>, 512,
+                    (int)sym_wave_regions<float, 8, 17>()};
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 1>, 512,
+                    (int)sym_wave_regions<float, 8, 17>()};
+            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 16, 17, 1>, 1024,
+                    (int)sym_wave_regions<float, 16, 17>()};
+            return {(const void *)strip_solve_sym_kernel<float, 4, 17, 2>, 256,
+                    (int)sym_wave_regions<float, 4, 17>()};
         }
         if (nch <= 33) {
-            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 4, 33, 1>, 256};
-            return {(const void *)strip_solve_sym_kernel<float, 8, 33, 1>, 512};
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 4, 33, 1>, 256,
+                    (int)sym_wave_regions<float, 4, 33>()};
+            return {(const void *)strip_solve_sym_kernel<float, 8, 33, 1>, 512,
+                    (int)sym_wave_regions<float, 8, 33>()};
         }
         return {nullptr, 0};
     }
     if (nch <= 3) {
-        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 3, 4>, 512};
-        return {(const void *)strip_solve_sym_kernel<double, 16, 3, 4>, 1024};
+        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 3, 4>, 512,
+                    (int)sym_wave_regions<double, 8, 3>()};
+        return {(const void *)strip_solve_sym_kernel<double, 16, 3, 4>, 1024,
+                    (int)sym_wave_regions<double, 16, 3>()};
     }
     if (nch <= 9) {
-        if (shape == 0) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 3>, 512};
-        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 1>, 512};
-        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 16, 9, 1>, 1024};
-        return {(const void *)strip_solve_sym_kernel<double, 8, 9, 2>, 512};
+        if (shape == 0) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 3>, 512,
+                    (int)sym_wave_regions<double, 8, 9>()};
+        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 1>, 512,
+                    (int)sym_wave_regions<double, 8, 9>()};
+        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 16, 9, 1>, 1024,
+                    (int)sym_wave_regions<double, 16, 9>()};
+        return {(const void *)strip_solve_sym_kernel<double, 8, 9, 2>, 512,
+                    (int)sym_wave_regions<double, 8, 9>()};
     }
     if (nch <= 17) {
-        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 4, 17, 1>, 256};
-        return {(const void *)strip_solve_sym_kernel<double, 8, 17, 1>, 512};
+        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 4, 17, 1>, 256,
+                    (int)sym_wave_regions<double, 4, 17>()};
+        return {(const void *)strip_solve_sym_kernel<double, 8, 17, 1>, 512,
+                    (int)sym_wave_regions<double, 8, 17>()};
     }
-    return {nullptr, 0};
+    return {nullptr, 0, 0};
 }
 
-size_t solve_smem(int n, int fp32, int sym) {
+// dynamic LDS of a strip-solve variant for lines of n nodes
+size_t solve_smem(int n, int fp32, int sym, const Variant &v) {
     const size_t e2 = fp32 ? sizeof(float2) : sizeof(double2), ea = fp32 ? 4 : 8;
-    return sym ? 2 * (size_t)n * e2 + 2 * (size_t)n * sizeof(double2) + 4 * (size_t)n * ea
-               : 2 * (size_t)n * e2;
+    if (!sym) return 2 * (size_t)n * e2;
+    const size_t rest = 2 * (size_t)n * e2 + 2 * (size_t)n * sizeof(double2);
+    if (v.wregs) return (size_t)(v.threads / 64) * 2 * n * 2 * ea + rest;
+    return rest + 4 * (size_t)n * ea;
 }
 
 Variant pick(int n, int fp32, int shape, int sym) {
@@ -999,7 +1112,11 @@ int solve_sym_supported(int n, int fp32) {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return 0;
-    return solve_smem(n, fp32, 1) <= (size_t)lim ? 1 : 0;
+    for (int shape = 0; shape < SOLVE_SHAPES; ++shape) {
+        Variant v = variant_sym_for(n, fp32, shape);
+        if (v.fn && solve_smem(n, fp32, 1, v) > (size_t)lim) return 0;
+    }
+    return 1;
 }
 
 int solve_max_resident_blocks(int fp32, int n, int shape) {
@@ -1011,7 +1128,7 @@ int solve_max_resident_blocks(int fp32, int n, int shape) {
     Variant v = pick(n, fp32, shape % SOLVE_SHAPES, sym);
     if (!v.fn) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, v.fn, v.threads,
-                                                     solve_smem(n, fp32, sym)) != hipSuccess)
+                                                     solve_smem(n, fp32, sym, v)) != hipSuccess)
         return 0;
     return per * cus;
 }
@@ -1028,7 +1145,7 @@ hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipE
     if (sym && (a.team > SOLVE_MAX_TEAM || !a.part)) return hipErrorInvalidConfiguration;
     Variant v = pick(a.n, fp32, a.shape % SOLVE_SHAPES, sym);
     if (!v.fn) return hipErrorInvalidConfiguration;
-    size_t smem = solve_smem(a.n, fp32, sym);
+    size_t smem = solve_smem(a.n, fp32, sym, v);
     dim3 grid(a.nstrips * a.team), block(v.threads);
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     e = hipLaunchCooperativeKernel(v.fn, grid, block, params, (unsigned)smem, st);
