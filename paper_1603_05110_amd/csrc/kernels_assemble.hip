@@ -42,7 +42,7 @@ __global__ void coef_kernel(Phys P, const StripMeta *strips, const int *line_str
 //   res = 2i/dt M_j u_{j,n-1} - c M^Gamma Q^T (l_j; r_j) - K_j(W + beta|zeta|^2) zeta.
 // With the factor of K_j(W), zeta + K_j(W)^{-1} res equals
 // K_j(W)^{-1}(F - M_{beta|zeta|^2} zeta): the paper's fixed-point update.
-__global__ void residual_kernel(Phys P, const StripMeta *strips, const int *line_strip,
+__global__ __launch_bounds__(256) void residual_kernel(Phys P, const StripMeta *strips, const int *line_strip,
                                 const double *W, const double2 *u_old, const double2 *zeta,
                                 const double2 *g, double2 *res, const StepCtl *c) {
     if (c && fp_idle(c)) return;

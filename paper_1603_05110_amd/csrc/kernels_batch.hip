@@ -70,7 +70,7 @@ __global__ void b_iter_reset_kernel(const InstDesc *tab) {
     iter_reset_body(c, nullptr);
 }
 
-__global__ void b_residual_kernel(const InstDesc *tab) {
+__global__ __launch_bounds__(256) void b_residual_kernel(const InstDesc *tab) {
     const InstDesc &I = tab[blockIdx.z];
     const Phys P = I.P;
     int L = blockIdx.y;

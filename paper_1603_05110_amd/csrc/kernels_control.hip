@@ -163,7 +163,7 @@ hipError_t launch_copy_u_guarded(hipStream_t st, const Phys &P, const StripMeta 
 
 hipError_t launch_q_check(hipStream_t st, const Phys &P, const StripMeta *strips,
                           const double *part, StepCtl *c) {
-    hipLaunchKernelGGL(q_check_kernel, dim3(1), dim3(256), 0, st, P, strips, part, c);
+    hipLaunchKernelGGL(q_check_kernel, dim3(1), dim3(1024), 0, st, P, strips, part, c);
     return hipGetLastError();
 }
 

@@ -58,50 +58,93 @@ __device__ __forceinline__ bool fp_idle(const StepCtl *c) {
 //   res = 2i/dt M_j u_{j,n-1} - c M^Gamma Q^T (l_j; r_j) - K_j(W + beta|zeta|^2) zeta.
 // With the factor of K_j(W), zeta + K_j(W)^{-1} res equals
 // K_j(W)^{-1}(F - M_{beta|zeta|^2} zeta): the update of eq. localpbrobin.
+//
+// The Q1 integrals are summed element by element: the node's 3 x 3
+// neighbourhood of zeta, u and phi = W + beta|zeta|^2 is loaded once, then
+// each of the (up to) four elements around the node adds its entries with
+// every corner (the same terms kparts() sums neighbour by neighbour).
 __device__ __forceinline__ double2 residual_at(const Phys &P, const StripMeta *strips,
                                                const int *line_strip, const double *W,
                                                const double2 *u_old, const double2 *zeta,
                                                const double2 *g, int L, int a) {
-    int ny = P.ny;
-    int j = line_strip[L];
-    StripMeta s = strips[j];
-    int i = L - s.off;
+    const int ny = P.ny;
+    const int j = line_strip[L];
+    const StripMeta s = strips[j];
+    const int i = L - s.off, nx = s.nx;
     const double *Wl = W + (long)s.line0 * ny;
     const double2 *ul = u_old + (long)s.line0 * ny;
     const double2 *zl = zeta + (long)s.off * ny;
-    double beta = P.beta;
-    auto phi = [&](int ii, int kk) -> double {
-        double2 z = zl[(long)ii * ny + kk];
-        return Wl[(long)ii * ny + kk] + beta * (z.x * z.x + z.y * z.y);
-    };
-    double2 acc = cd(0.0, 0.0);
+    const double beta = P.beta, hx = P.hx, hy = P.hy, c = P.c, m2 = 2.0 / P.dt;
     const double2 *trace = nullptr;
     if (i == 0 && j >= 1) trace = g + (long)(2 * (j - 1) + 1) * ny;             // l_j
-    if (i == s.nx - 1 && j <= P.nsub - 2) trace = g + (long)(2 * j) * ny;       // r_j
-    for (int ip = max(i - 1, 0); ip <= min(i + 1, s.nx - 1); ++ip) {
-        for (int b = max(a - 1, 0); b <= min(a + 1, ny - 1); ++b) {
-            KParts k = kparts(i, a, ip, b, s.nx, ny, P.hx, P.hy, phi);
-            double2 z = zl[(long)ip * ny + b];
-            double2 u = ul[(long)ip * ny + b];
-            // 2i/dt m (u - z)
-            double2 du = csub(u, z);
-            acc.x += -(2.0 / P.dt) * k.m * du.y;
-            acc.y += (2.0 / P.dt) * k.m * du.x;
-            // + c s z - w z
-            double cs = P.c * k.s - k.w;
-            acc.x += cs * z.x;
-            acc.y += cs * z.y;
-            // - i c (pl edge_l + pr edge_r) z
-            double e = P.c * (s.pl * k.edge_l + s.pr * k.edge_r);
-            acc.x += e * z.y;
-            acc.y += -e * z.x;
-            // - c M^Gamma trace
-            if (trace && ip == i) {
-                double my = (i == 0) ? k.edge_l : k.edge_r;
-                double2 t = trace[b];
-                acc.x -= P.c * my * t.x;
-                acc.y -= P.c * my * t.y;
-            }
+    if (i == nx - 1 && j <= P.nsub - 2) trace = g + (long)(2 * j) * ny;        // r_j
+    // edge coefficient of M^Gamma on this line (Robin terms of the strip)
+    const double pe = (i == 0 ? s.pl : 0.0) + (i == nx - 1 ? s.pr : 0.0);
+    const bool edge = i == 0 || i == nx - 1;
+    double2 z[3][3], u[3][3], tr[3];
+    double ph[3][3];
+#pragma unroll
+    for (int di = 0; di < 3; ++di)
+#pragma unroll
+        for (int db = 0; db < 3; ++db) {
+            const int ip = i + di - 1, b = a + db - 1;
+            const bool ok = ip >= 0 && ip < nx && b >= 0 && b < ny;
+            const long o = (long)ip * ny + b;
+            z[di][db] = ok ? zl[o] : cd(0.0, 0.0);
+            u[di][db] = ok ? ul[o] : cd(0.0, 0.0);
+            const double wv = ok ? Wl[o] : 0.0;
+            ph[di][db] = wv + beta * (z[di][db].x * z[di][db].x + z[di][db].y * z[di][db].y);
+        }
+#pragma unroll
+    for (int db = 0; db < 3; ++db) {
+        const int b = a + db - 1;
+        tr[db] = (trace && b >= 0 && b < ny) ? trace[b] : cd(0.0, 0.0);
+    }
+    double2 acc = cd(0.0, 0.0);
+#pragma unroll
+    for (int exo = -1; exo <= 0; ++exo) {
+        const int ex = i + exo;
+        if (ex < 0 || ex > nx - 2) continue;
+        const int Ax = -exo;
+#pragma unroll
+        for (int eyo = -1; eyo <= 0; ++eyo) {
+            const int ey = a + eyo;
+            if (ey < 0 || ey > ny - 2) continue;
+            const int Ay = -eyo;
+#pragma unroll
+            for (int Bx = 0; Bx < 2; ++Bx)
+#pragma unroll
+                for (int By = 0; By < 2; ++By) {
+                    const int di = exo + Bx + 1, db = eyo + By + 1;   // corner in the 3 x 3 block
+                    const double mx = hx * ref_mass(Ax, Bx), sx = ref_stiff(Ax, Bx) / hx;
+                    const double my = hy * ref_mass(Ay, By), sy = ref_stiff(Ay, By) / hy;
+                    const double m = mx * my, st = sx * my + mx * sy;
+                    double w = 0.0;
+#pragma unroll
+                    for (int cx = 0; cx < 2; ++cx)
+#pragma unroll
+                        for (int cy = 0; cy < 2; ++cy)
+                            w += ph[exo + cx + 1][eyo + cy + 1] * ref_triple(cx, Ax, Bx) *
+                                 ref_triple(cy, Ay, By);
+                    w *= hx * hy;
+                    const double2 zb = z[di][db], ub = u[di][db];
+                    // 2i/dt m (u - z)
+                    const double2 du = csub(ub, zb);
+                    acc.x += -m2 * m * du.y;
+                    acc.y += m2 * m * du.x;
+                    // + c s z - w z
+                    const double cs = c * st - w;
+                    acc.x += cs * zb.x;
+                    acc.y += cs * zb.y;
+                    if (edge && Bx == Ax) {
+                        // - i c pe M^Gamma z - c M^Gamma trace (same line only)
+                        const double e = c * pe * my;
+                        acc.x += e * zb.y;
+                        acc.y += -e * zb.x;
+                        acc.x -= c * my * tr[db].x;
+                        acc.y -= c * my * tr[db].y;
+                    }
+                }
         }
     }
     return acc;
@@ -318,16 +361,24 @@ __device__ __forceinline__ void q_check_block(const Phys &P, const StripMeta *st
     if (threadIdx.x == 0) { notconv = 0; nonfinite = 0; }
     __syncthreads();
     double tq = c->tq;
-    for (int j = threadIdx.x; j < P.nsub; j += blockDim.x) {
-        StripMeta s = strips[j];
+    // one wave per strip, its lanes over the strip's lines (all loads of a
+    // strip in flight together), summed by the fixed butterfly of ctl_wsum
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    for (int j = wave; j < P.nsub; j += nw) {
+        const StripMeta s = strips[j];
         double d = 0, z = 0, b = 0;
-        for (int i = 0; i < s.nx; ++i) {
+        for (int i = lane; i < s.nx; i += 64) {
             d += part[3 * (s.off + i)];
             z += part[3 * (s.off + i) + 1];
             b += part[3 * (s.off + i) + 2];
         }
-        if (b > 0 || !isfinite(d) || !isfinite(z)) atomicOr(&nonfinite, 1);
-        if (!(sqrt(d) <= tq * sqrt(z))) atomicOr(&notconv, 1);
+        d = ctl_wsum(d);
+        z = ctl_wsum(z);
+        b = ctl_wsum(b);
+        if (lane == 0) {
+            if (b > 0 || !isfinite(d) || !isfinite(z)) atomicOr(&nonfinite, 1);
+            if (!(sqrt(d) <= tq * sqrt(z))) atomicOr(&notconv, 1);
+        }
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
