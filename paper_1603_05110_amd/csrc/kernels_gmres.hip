@@ -130,19 +130,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
             m0[rr][c] = ok ? B0[(long)row * n + col] : cd(0.0, 0.0);
             m1[rr][c] = ok ? B1[(long)row * n + col] : cd(0.0, 0.0);
         }
-    auto next_strip = [&](int j) {
-        for (j += G; j < N && strips[j].cls != cls; j += G) {}
-        return j;
-    };
     auto has_out = [&](int j) { return side == 0 ? j >= 1 : j <= N - 2; };
     auto out_trace = [&](int j) { return side == 0 ? 2 * (j - 1) : 2 * j + 1; };
     double2 acc = cd(0.0, 0.0);
-    int j0 = next_strip(blockIdx.z - G);
-    while (j0 < N) {
+    // this workgroup's strips (group, group + G, ... of its class), listed in
+    // LDS up to LC candidates at a time: the class tests are loaded in
+    // parallel, not one dependent load per strip
+    constexpr int LC = 256;
+    __shared__ int slist[LC + 1];
+    const int ncand = (N - (int)blockIdx.z + G - 1) / G;
+    for (int cb = 0; cb < ncand; cb += LC) {
+    {
+        const int t = threadIdx.x, jc = blockIdx.z + G * (cb + t);
+        const int hit = cb + t < ncand && t < LC && strips[jc].cls == cls;
+        __syncthreads();   // the previous list is no longer read
+        slist[t] = hit;
+        __syncthreads();
+        if (t == 0) {
+            int k = 0;
+            for (int q = 0; q < LC && cb + q < ncand; ++q)
+                if (slist[q]) slist[k++] = blockIdx.z + G * (cb + q);
+            slist[LC] = k;
+        }
+        __syncthreads();
+    }
+    const int ns = slist[LC];
+    for (int i0 = 0; i0 < ns; i0 += SB) {
         int js[SB];
-        js[0] = j0;
 #pragma unroll
-        for (int b = 1; b < SB; ++b) js[b] = js[b - 1] < N ? next_strip(js[b - 1]) : N;
+        for (int b = 0; b < SB; ++b) js[b] = i0 + b < ns ? slist[i0 + b] : N;
         // every load of the batch in flight together
         double2 stg[SB][SPT];
 #pragma unroll
@@ -218,7 +234,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
                 }
             }
         }
-        j0 = js[SB - 1] < N ? next_strip(js[SB - 1]) : N;
+    }
     }
     if constexpr (DOTS) {
         __shared__ double2 red[4][64];
