@@ -5,11 +5,7 @@
 
 namespace {
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ __forceinline__ double wsum(double v) { return wave_sum_f64(v); }
 
 // Row a of output trace t of L_h x (eq. Lmpi): trace 2i (new r_i) is fed by
 // strip i+1 through X^{i+1,1} l_{i+1} + X^{i+1,2} r_{i+1}; trace 2i+1 (new

@@ -140,16 +140,8 @@ __device__ __forceinline__ double2 tw_vec(int kind, long L, int i, int nx, int n
     return acc;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_f64(v); }
+__device__ __forceinline__ float wave_sum(float v) { return wave_sum_f32(v); }
 
 // out[r] = sum_c M[r][c] vec[c] for rows r in [r0, r1) of one workgroup.
 // Wave w takes rows r0 + w, r0 + w + 4, ...; RU of its rows at a time, and

@@ -47,6 +47,45 @@ __device__ __forceinline__ double2 cinv(double2 a) {
     return cd(a.x / d, -a.y / d);
 }
 
+// Sums over the 64 lanes of a wave, the same value in every lane.  The
+// lanes of each row of 16 are combined with DPP moves (VALU, no LDS
+// round trip): swap neighbours, swap pairs, mirror half-rows, mirror the
+// row; then the four row sums are read from lanes 0, 16, 32, 48 and added
+// in that order.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float wave_sum_f32(float v) {
+    v += __int_as_float(dpp_i32<0xB1>(__float_as_int(v)));    // quad_perm [1,0,3,2]
+    v += __int_as_float(dpp_i32<0x4E>(__float_as_int(v)));    // quad_perm [2,3,0,1]
+    v += __int_as_float(dpp_i32<0x141>(__float_as_int(v)));   // row_half_mirror
+    v += __int_as_float(dpp_i32<0x140>(__float_as_int(v)));   // row_mirror
+    const int b = __float_as_int(v);
+    return (__int_as_float(__builtin_amdgcn_readlane(b, 0)) +
+            __int_as_float(__builtin_amdgcn_readlane(b, 16))) +
+           (__int_as_float(__builtin_amdgcn_readlane(b, 32)) +
+            __int_as_float(__builtin_amdgcn_readlane(b, 48)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i32<CTRL>((int)b), hi = dpp_i32<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
 // Reference-element integrals of the 1-D linear shape functions psi_0 = 1-s,
 // psi_1 = s on [0,1] (Section 2.2): mass, stiffness and triple product.
 __device__ __forceinline__ double ref_mass(int a, int b) { return a == b ? (1.0 / 3.0) : (1.0 / 6.0); }
