@@ -40,17 +40,19 @@ MFMA_FP64_PEAK_TFLOPS = 78.6
 # this workload, each scaled by the counter's reading for a 1 GiB copy
 # (fetch x2.0, write x1.0); valid only for the full-row kernel whose source
 # text (the strip_solve_pf_kernel template) hashes to source_sha256.
-SOLVE_TRAFFIC = {"c32": {"bytes": 2.2735e+09,
-                         "source_sha256": "427dd2531ba5469ab300de4e91e0f9200a5ad9efd470d7320c82d5afbecaaade",
+SOLVE_TRAFFIC = {"c32": {"bytes": 2.2733e+09,
+                         "source_sha256": "7aaa291110034f6d175fa5063b31eb5ded2510984b29840918fd077dc3e2929a",
                          "summary": "profiles/strip_solve_c32_gpe512_hbm_counters.md"}}
 
 
 def pf_kernel_source():
-    """Source text of the full-row strip-solve kernel template (its
-    definition up to the closing brace), which the counters describe."""
-    path = os.path.join(ROOT, "paper_1603_05110_amd", "csrc", "kernels_solve.hip")
+    """Source text the counters describe: the full-row strip-solve kernel
+    template (its definition up to the closing brace) and the wave-sum
+    helpers it calls."""
+    csrc = os.path.join(ROOT, "paper_1603_05110_amd", "csrc")
     try:
-        src = open(path).read()
+        src = open(os.path.join(csrc, "kernels_solve.hip")).read()
+        hdr = open(os.path.join(csrc, "osm_internal.h")).read()
     except OSError:
         return None
     key = "void strip_solve_pf_kernel(SolveArgs a) {"
@@ -59,7 +61,11 @@ def pf_kernel_source():
         return None
     i = src.rfind("template <", 0, i)
     j = src.find("\n}\n", i)
-    return src[i:j + 3] if j > 0 else None
+    a = hdr.find("template <int CTRL>")
+    b = hdr.find("\n}\n", hdr.find("double wave_sum_f64(double v)"))
+    if j < 0 or a < 0 or b < 0:
+        return None
+    return src[i:j + 3] + hdr[a:b + 3]
 
 
 def measured_traffic(prec, kernel_name):
