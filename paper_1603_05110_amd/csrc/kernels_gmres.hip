@@ -682,15 +682,35 @@ static inline unsigned lh_grid(const Phys &P) {
     return 8u * ntr * ((ntile + 7) / 8);
 }
 
+// Workgroups of one register-resident L_h kernel that fit on the device at
+// once (queried once per kernel and process).
+static int lh_resident(int nch, bool dots) {
+    static int cache[2][2] = {{-1, -1}, {-1, -1}};
+    const int a = nch <= 9 ? 0 : 1, b = dots ? 1 : 0;
+    if (cache[a][b] < 0) {
+        const void *fn = a == 0 ? (dots ? (const void *)lh_matvec_reg_kernel<9, 1, 2, true>
+                                        : (const void *)lh_matvec_reg_kernel<9, 1, 2, false>)
+                                : (dots ? (const void *)lh_matvec_reg_kernel<17, 1, 1, true>
+                                        : (const void *)lh_matvec_reg_kernel<17, 1, 1, false>);
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, 256, 0) != hipSuccess)
+            return 512;
+        cache[a][b] = max(1, per * cus);
+    }
+    return cache[a][b];
+}
+
 // Grid of the register-resident L_h kernel: (row tiles, classes, strip
 // groups), the groups chosen so the grid fits one round of resident
-// workgroups (two per CU at this register use), at most one group per
-// strip.  x = 0 when ny needs more than 17 column chunks.
-static dim3 lh_reg_grid(const Phys &P, int ncls) {
+// workgroups, at most one group per strip.  x = 0 when ny needs more than
+// 17 column chunks.
+static dim3 lh_reg_grid(const Phys &P, int ncls, bool dots) {
     int nch = (P.ny + 63) / 64;
     if (nch > 17) return dim3(0, 0, 0);
     int tiles = (P.ny + 1) / 2;
-    int g = 512 / max(1, tiles * ncls);
+    int g = lh_resident(nch, dots) / max(1, tiles * ncls);
     return dim3(tiles, ncls, (unsigned)max(1, min(g, P.nsub)));
 }
 
@@ -698,7 +718,7 @@ int lh_fused_blocks(int ny, int nsub, int ncls) {
     Phys P;
     P.ny = ny;
     P.nsub = nsub;
-    dim3 g = lh_reg_grid(P, ncls);
+    dim3 g = lh_reg_grid(P, ncls, true);
     return (int)(g.x * g.y * g.z);
 }
 
@@ -712,15 +732,15 @@ static hipError_t lh_apply(hipStream_t st, const Phys &P, const StripMeta *strip
                            const GmresCtl *ctl, const double2 *V = nullptr, long ng = 0,
                            int nv = 0, double2 *part = nullptr, int ld = 0) {
     int nch = (P.ny + 63) / 64;
-    dim3 grid = lh_reg_grid(P, ncls);
+    dim3 grid = lh_reg_grid(P, ncls, part != nullptr);
     if (part && (nch > 17 || mode_p != 1 || nv < 1 || nv > 64 || !V))
         return hipErrorInvalidValue;
     if (nch <= 9) {
         if (part)
-            hipLaunchKernelGGL((lh_matvec_reg_kernel<9, 1, 4, true>), grid, dim3(256), 0, st, P,
+            hipLaunchKernelGGL((lh_matvec_reg_kernel<9, 1, 2, true>), grid, dim3(256), 0, st, P,
                                strips, LH, x, y, mode_p, ctl, V, ng, nv, part, ld);
         else
-            hipLaunchKernelGGL((lh_matvec_reg_kernel<9, 1, 4, false>), grid, dim3(256), 0, st, P,
+            hipLaunchKernelGGL((lh_matvec_reg_kernel<9, 1, 2, false>), grid, dim3(256), 0, st, P,
                                strips, LH, x, y, mode_p, ctl, V, ng, nv, part, ld);
     } else if (nch <= 17) {
         if (part)
