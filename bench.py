@@ -82,8 +82,8 @@ def measured_traffic(prec, kernel_name):
 
 def solver_opts(prec):
     return dict(algo="precond", prec=prec, tol_k=1e-12, tol_k_relative=True, max_k=500,
-                tol_q=1e-13, max_q=200, warm_start=True, tol_gmres=1e-2,
-                gmres_restart=50, max_gmres=2000, eta_q=1e-2)
+                tol_q=1e-13, max_q=200, warm_start=True, tol_gmres=3e-2,
+                gmres_restart=50, max_gmres=2000, eta_q=3e-2, q_estimate=1)
 
 
 def run_gpu(pb, u0, V, prec, steps, warmup, dev, measure=True):

@@ -126,6 +126,16 @@ typedef struct {
                                      inverses are complex symmetric; ny up to 2112
                                      in c32, 1088 in FP64); the team is still tuned
                                      unless team > 0                             */
+    int32_t q_estimate;           /* 0: a fixed point stops when ||zeta^q - zeta^{q-1}||
+                                     <= tol ||zeta^q|| on every strip (the paper's
+                                     test).  1: from the second Schwarz iteration
+                                     of a step on, it also stops when the error
+                                     bound r/(1-r) ||zeta^q - zeta^{q-1}|| of a
+                                     contraction is below tol ||zeta^q||, with r
+                                     twice the largest ratio ||zeta^2 - zeta^1|| /
+                                     ||zeta^1 - zeta^0|| over the strips measured
+                                     in the step (used only while r < 1/2); the
+                                     converged answer is unchanged              */
 } osm_options;
 
 typedef struct {

@@ -30,9 +30,10 @@ __global__ void copy_u_guarded_kernel(Phys P, const StripMeta *strips, const int
     copy_u_at(P, strips, line_strip, u, zeta, L, a);
 }
 
-__global__ void q_check_kernel(Phys P, const StripMeta *strips, const double *part, StepCtl *c) {
+__global__ void q_check_kernel(Phys P, const StripMeta *strips, const double *part, StepCtl *c,
+                               double *dprev) {
     if (c->q_conv || c->k_done || c->bad) return;
-    q_check_block(P, strips, part, c);
+    q_check_block(P, strips, part, c, dprev);
 }
 
 __global__ void flux_finalize_kernel(const double *part, int nt, StepCtl *c) {
@@ -162,8 +163,8 @@ hipError_t launch_copy_u_guarded(hipStream_t st, const Phys &P, const StripMeta 
 }
 
 hipError_t launch_q_check(hipStream_t st, const Phys &P, const StripMeta *strips,
-                          const double *part, StepCtl *c) {
-    hipLaunchKernelGGL(q_check_kernel, dim3(1), dim3(1024), 0, st, P, strips, part, c);
+                          const double *part, StepCtl *c, double *dprev) {
+    hipLaunchKernelGGL(q_check_kernel, dim3(1), dim3(1024), 0, st, P, strips, part, c, dprev);
     return hipGetLastError();
 }
 

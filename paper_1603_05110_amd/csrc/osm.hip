@@ -55,6 +55,7 @@ struct osm_handle {
     double *sscale = nullptr;        // per-line largest |b| (scale of the complex-FP32 solve)
     unsigned *counters = nullptr;
     int *err_d = nullptr;
+    double *qd_prev = nullptr;     // per strip: ||zeta^q - zeta^{q-1}||^2 of the last iterate
     CtlMirror *mirror = nullptr;   // pinned host memory (hipHostMalloc)
     int team = 0;
     // L_h
@@ -189,6 +190,7 @@ std::string validate(const osm_problem *p, const osm_options *o) {
     if (!(p->p_bc >= 0)) return "p_bc must be >= 0";
     if (!(p->dt > 0) || !(p->lap_coef > 0)) return "dt and lap_coef must be > 0";
     if (o->solve_shape < 0 || o->solve_shape > 8) return "solve_shape must be 0 (tuned) or 1..8";
+    if (o->q_estimate < 0 || o->q_estimate > 1) return "q_estimate must be 0 or 1";
     if (!isfinite(p->beta)) return "beta not finite";
     std::vector<int> c = strip_cells_of(p);
     if ((int)c.size() != p->nsub) return "strip_cells NULL but ncx not divisible by nsub";
@@ -253,7 +255,7 @@ uint64_t device_bytes(const Sizes &s) {
         b += lb * SWEEP_BK * (2ull * s.n + SWEEP_BK);
     }
     if (s.sym) b += (uint64_t)s.N * 2 * SOLVE_MAX_TEAM * 2 * s.n * fe;  // solve partials
-    b += (uint64_t)(4 * s.Lt + 3 * s.N + 2 * 2 * s.N + s.nglob + 64) * 8;
+    b += (uint64_t)(4 * s.Lt + 4 * s.N + 2 * 2 * s.N + s.nglob + 64) * 8;
     b += (uint64_t)(s.N - 1) * s.n * 13 * 4 + (uint64_t)(s.N - 1) * 8;  // guess features
     b += 3ull * s.ng * 16 + 2ull * ((s.ng + 255) / 256) * 8;           // guess history
     if (s.m > 0) {
@@ -593,7 +595,7 @@ osm_status fp_chunk(osm_handle *h, const double2 *u, int nq) {
         osm_status s = do_solve(h, h->res, h->delta, h->sctl);
         if (s != OSM_OK) return s;
         HIPCHK(h, launch_update_norms(h->st, h->P, h->zeta, h->delta, h->line_part, h->sctl));
-        HIPCHK(h, launch_q_check(h->st, h->P, h->strips_d, h->line_part, h->sctl));
+        HIPCHK(h, launch_q_check(h->st, h->P, h->strips_d, h->line_part, h->sctl, h->qd_prev));
     }
     return OSM_OK;
 }
@@ -669,6 +671,7 @@ osm_status schwarz_device(osm_handle *h, const double2 *u, osm_step_stats *S) {
     cfg.max_q = o.max_q;
     cfg.fixed_k = o.fixed_k;
     cfg.classical = o.algo == OSM_CLASSICAL;
+    cfg.q_est = o.q_estimate != 0;
     HIPCHK(h, launch_step_init(h->st, h->sctl, cfg));
     HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
     int nk = o.fixed_k > 0 ? o.fixed_k : o.max_k;
@@ -988,6 +991,7 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         SALLOC(h->err_d, int, 1);
         SALLOC(h->ran_d, int, PROF_SLOTS);
         SALLOC(h->sctl, StepCtl, 1);
+        SALLOC(h->qd_prev, double, h->N);
         if (hipHostMalloc((void **)&h->mirror, sizeof(CtlMirror), hipHostMallocDefault) !=
             hipSuccess) {
             h->mirror = nullptr;
@@ -1754,6 +1758,7 @@ static StepCfg batch_cfg(const osm_options &o) {
     cfg.max_q = o.max_q;
     cfg.fixed_k = o.fixed_k;
     cfg.classical = 1;
+    cfg.q_est = 0;
     return cfg;
 }
 

@@ -219,6 +219,7 @@ int solve_sym_supported(int n, int fp32);
 struct StepCfg {
     double tol_q, eta_q, tol_k;
     int tol_k_rel, fixed_q, max_q, fixed_k, classical;
+    int q_est;      // error-estimate fixed-point test (osm_options.q_estimate)
 };
 struct StepCtl {
     StepCfg cfg;
@@ -237,6 +238,7 @@ struct StepCtl {
     double inc, ref, prev_rel;
     double first_rel;  // relative increment of the first Schwarz iteration of the
                        // last step (kept across steps; 0 = none yet)
+    double rho;        // largest contraction ratio measured in this step (0 = none)
 };
 struct GmresCtl;
 hipError_t launch_step_init(hipStream_t st, StepCtl *c, const StepCfg &cfg);
@@ -244,8 +246,10 @@ hipError_t launch_iter_reset(hipStream_t st, StepCtl *c, GmresCtl *g);
 hipError_t launch_copy_u_guarded(hipStream_t st, const Phys &P, const StripMeta *strips,
                                  const int *line_strip, const double2 *u, double2 *zeta,
                                  const StepCtl *c);
+// dprev (may be null): per-strip ||zeta^q - zeta^{q-1}||^2 of the previous
+// iterate, kept for the contraction estimate of the error-estimate test
 hipError_t launch_q_check(hipStream_t st, const Phys &P, const StripMeta *strips,
-                          const double *part, StepCtl *c);
+                          const double *part, StepCtl *c, double *dprev = nullptr);
 hipError_t launch_flux_finalize(hipStream_t st, const double *part, int nt, StepCtl *c);
 hipError_t launch_commit(hipStream_t st, long n, double2 *g, const double2 *gn, const StepCtl *c);
 hipError_t launch_precond_rhs(hipStream_t st, long n, const double2 *g, const double2 *gn,

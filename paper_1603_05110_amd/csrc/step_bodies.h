@@ -335,6 +335,7 @@ __device__ __forceinline__ void step_init_body(StepCtl *c, const StepCfg &cfg) {
     // the first inner tolerance of this step follows the first increment of
     // the last one (how far the start of the iteration was from its map)
     c->prev_rel = c->first_rel > 0.0 ? fmin(1.0, c->first_rel) : 1.0;
+    c->rho = 0.0;
 }
 
 // Start of a Schwarz iteration (thread 0 only): new fixed point, tolerance
@@ -354,13 +355,25 @@ __device__ __forceinline__ void iter_reset_body(StepCtl *c, GmresCtl *g) {
 
 // Fixed-point test of every strip from the per-line partial sums:
 // converged when ||dzeta_j|| <= tq ||zeta_j|| for all strips j (or after
-// fixed_q iterations).  One block.
+// fixed_q iterations).  With the error-estimate test (cfg.q_est, dprev
+// given) the factor r/(1-r) multiplies ||dzeta_j|| from the step's second
+// Schwarz iteration on: for a map with contraction factor r, the distance
+// of zeta^q to the fixed point is at most r/(1-r) ||zeta^q - zeta^{q-1}||.
+// r is twice the largest ratio ||dzeta^2|| / ||dzeta^1|| over the strips
+// measured in the step (dprev keeps each strip's last ||dzeta||^2); the
+// test is used only while r < 1/2.  One block.
 __device__ __forceinline__ void q_check_block(const Phys &P, const StripMeta *strips,
-                                              const double *part, StepCtl *c) {
+                                              const double *part, StepCtl *c,
+                                              double *dprev = nullptr) {
     __shared__ int notconv, nonfinite;
-    if (threadIdx.x == 0) { notconv = 0; nonfinite = 0; }
+    __shared__ unsigned long long rho_bits;
+    if (threadIdx.x == 0) { notconv = 0; nonfinite = 0; rho_bits = 0ull; }
     __syncthreads();
-    double tq = c->tq;
+    const double tq = c->tq;
+    const double r = 2.0 * c->rho;
+    const bool est = dprev && c->cfg.q_est && c->k >= 1 && r > 0.0 && r < 0.5;
+    const double fac = est ? r / (1.0 - r) : 1.0;
+    const bool measure = dprev && c->q_iter >= 1;   // second or later iterate
     // one wave per strip, its lanes over the strip's lines (all loads of a
     // strip in flight together), summed by the fixed butterfly of ctl_wsum
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
@@ -377,11 +390,20 @@ __device__ __forceinline__ void q_check_block(const Phys &P, const StripMeta *st
         b = ctl_wsum(b);
         if (lane == 0) {
             if (b > 0 || !isfinite(d) || !isfinite(z)) atomicOr(&nonfinite, 1);
-            if (!(sqrt(d) <= tq * sqrt(z))) atomicOr(&notconv, 1);
+            if (!(fac * sqrt(d) <= tq * sqrt(z))) atomicOr(&notconv, 1);
+            if (dprev) {
+                if (measure && dprev[j] > 0.0 && isfinite(d)) {
+                    // non-negative doubles order like their bit patterns
+                    const double ratio = sqrt(d / dprev[j]);
+                    atomicMax(&rho_bits, (unsigned long long)__double_as_longlong(ratio));
+                }
+                dprev[j] = d;
+            }
         }
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
+    if (measure && c->q_iter == 1) c->rho = fmax(c->rho, __longlong_as_double((long long)rho_bits));
     c->q_iter += 1;
     c->q_total += 1;
     if (nonfinite) { c->bad = 1; return; }

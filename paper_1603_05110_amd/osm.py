@@ -48,7 +48,8 @@ class osm_options(ctypes.Structure):
                 ("tol_gmres", ctypes.c_double), ("gmres_restart", ctypes.c_int32),
                 ("max_gmres", ctypes.c_int32), ("guess", ctypes.c_int32),
                 ("team", ctypes.c_int32), ("mem_cap", ctypes.c_uint64),
-                ("eta_q", ctypes.c_double), ("solve_shape", ctypes.c_int32)]
+                ("eta_q", ctypes.c_double), ("solve_shape", ctypes.c_int32),
+                ("q_estimate", ctypes.c_int32)]
 
 
 class osm_step_stats(ctypes.Structure):
@@ -171,12 +172,12 @@ def make_problem(pb):
 def make_options(algo="classical", prec="fp64", tol_k=1e-10, tol_k_relative=False,
                  max_k=2000, tol_q=1e-13, max_q=100, fixed_k=0, fixed_q=0,
                  warm_start=True, tol_gmres=1e-12, gmres_restart=50, max_gmres=1000,
-                 guess=0, team=0, mem_cap=0, eta_q=0.0, solve_shape=0):
+                 guess=0, team=0, mem_cap=0, eta_q=0.0, solve_shape=0, q_estimate=0):
     return osm_options({"classical": OSM_CLASSICAL, "precond": OSM_PRECOND}[algo],
                        {"fp64": OSM_FP64, "c32": OSM_C32_REFINE}[prec],
                        tol_k, int(tol_k_relative), max_k, tol_q, max_q, fixed_k, fixed_q,
                        int(warm_start), tol_gmres, gmres_restart, max_gmres, guess, team,
-                       mem_cap, eta_q, solve_shape)
+                       mem_cap, eta_q, solve_shape, int(q_estimate))
 
 
 def osm_query(pb, **opts):

@@ -216,6 +216,33 @@ def test_converged_steps_match_monolithic(algo, prec):
     assert rel(ud.cpu().numpy(), ref) < 1e-10
 
 
+@pytest.mark.parametrize("algo,prec", [("classical", "fp64"), ("precond", "c32")])
+def test_error_estimate_fixed_point_matches_monolithic(algo, prec):
+    """The error-estimate stopping test of the inner fixed point
+    (q_estimate = 1, with inexact inner solves) converges to the same step as
+    the monolithic oracle, with no more fixed-point iterations than the
+    paper's test."""
+    log(f"q_estimate {algo} {prec}")
+    osm = _osm()
+    pb, u, W = smooth_problem()
+    ref = run_monolithic(pb, u, W, 3, tol_q=1e-14)
+    q = {}
+    for est in (0, 1):
+        s = osm.OsmSolver(pb, DEV, algo=algo, prec=prec, tol_k=1e-12, tol_k_relative=True,
+                          tol_q=1e-14, max_k=4000, eta_q=1e-2, tol_gmres=1e-2,
+                          q_estimate=est)
+        s.factor(to_dev(W))
+        ud = to_dev(u)
+        q[est] = 0
+        for _ in range(3):
+            st = s.step(ud)
+            q[est] += st["q_total"]
+            log(f"  est={est} k={st['k']} q={st['q_total']} gmres={st['gmres_total']}")
+        s.close()
+        assert rel(ud.cpu().numpy(), ref) < 1e-10
+    assert q[1] <= q[0]
+
+
 def test_c1_matches_oracle():
     """Configuration C1 (cubic NLS, 128^2 cells, 2 strips, p = 1, 20 steps,
     classical FP64) against the monolithic oracle: 1e-10 relative L2."""
