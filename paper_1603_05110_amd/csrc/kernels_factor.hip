@@ -55,28 +55,32 @@ template <> __device__ __forceinline__ float2 mk2<float2>(double x, double y) {
 // lines' Schur complements (read through their upper triangles).  The
 // complement is symmetric and the sweep reads only its upper 64 x 64 tiles
 // (I <= J), so only those are formed.
-// A workgroup forms one tile; thread t owns column t % 64 and 16
-// consecutive rows, sliding the three-row window of F U over them.
+// A tile is formed by SCHUR_QP workgroups, each on a band of
+// 4 * SCHUR_RW rows; thread t owns column t % 64 and SCHUR_RW consecutive
+// rows, sliding the three-row window of F U over them (short bands give
+// many more waves to hide the loads' latency).
+constexpr int SCHUR_RW = 4, SCHUR_QP = SW / (4 * SCHUR_RW);
 template <typename T>
 __global__ __launch_bounds__(256) void schur_kernel(int n, typename cplx_of<T>::type *F,
                                                     const int *lines, const int *kind,
                                                     const double2 *Dc, const double2 *Uc) {
     typedef typename cplx_of<T>::type T2;
     const int TT = (n + SW - 1) / SW, nt = TT * (TT + 1) / 2;
-    const int z = blockIdx.x / nt;
-    int I = 0, rem = blockIdx.x - z * nt;
+    const int z = blockIdx.x / (nt * SCHUR_QP), rest = blockIdx.x - z * nt * SCHUR_QP;
+    const int qq = rest % SCHUR_QP;
+    int I = 0, rem = rest / SCHUR_QP;
     while (rem >= TT - I) { rem -= TT - I; ++I; }
     const int J = I + rem;
     const int c = J * SW + (threadIdx.x & 63);
-    const int rb = I * SW + (threadIdx.x >> 6) * 16;
+    const int rb = I * SW + qq * 4 * SCHUR_RW + (threadIdx.x >> 6) * SCHUR_RW;
     if (c >= n || rb >= n) return;
-    const int re = min(rb + 16, n);
+    const int re = min(rb + SCHUR_RW, n);
     const long L = lines[z];
     const int kd = kind[z];
     const long nn = (long)n * n;
-    double2 acc[16];
+    double2 acc[SCHUR_RW];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < SCHUR_RW; ++q) {
         const int r = rb + q;
         acc[q] = (r < n && abs(r - c) <= 1) ? Dc[(L * n + r) * 3 + (c - r + 1)] : cd(0.0, 0.0);
     }
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(256) void schur_kernel(int n, typename cplx_of<T>::
         };
         double2 tm = trow(rb - 1), t0 = trow(rb);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < SCHUR_RW; ++q) {
             const int r = rb + q;
             if (r < re) {
                 const double2 tp = trow(r + 1);
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(256) void schur_kernel(int n, typename cplx_of<T>::
     }
     T2 *S = F + L * nn;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < SCHUR_RW; ++q) {
         const int r = rb + q;
         if (r < re) S[(long)r * n + c] = mk2<T2>(acc[q].x, acc[q].y);
     }
@@ -700,7 +704,7 @@ template <typename T>
 hipError_t launch_schur(hipStream_t st, int n, typename cplx_of<T>::type *F, const int *lines,
                         const int *kind, int batch, const double2 *Dc, const double2 *Uc) {
     const int TT = (n + SW - 1) / SW;
-    const long blocks = (long)batch * (TT * (TT + 1) / 2);
+    const long blocks = (long)batch * (TT * (TT + 1) / 2) * SCHUR_QP;
     if (blocks > 0x7fffffffL) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL(schur_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, n, F, lines,
                        kind, Dc, Uc);
