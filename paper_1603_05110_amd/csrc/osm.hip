@@ -709,7 +709,10 @@ osm_status schwarz_device(osm_handle *h, const double2 *u, osm_step_stats *S) {
             if ((s = after_fixed_point(h, gchunk)) != OSM_OK) return s;
             if ((s = read_ctl(h, &c, &gc)) != OSM_OK) return s;
         }
-        if (!c.bad && o.fixed_q <= 0) h->q_chunk = std::max(2, c.q_iter);
+        // fixed-point iterations enqueued ahead: as many as the last Schwarz
+        // iteration needed (at least 2 with the paper's test, which always
+        // takes a second iterate; 1 with the error-estimate test)
+        if (!c.bad && o.fixed_q <= 0) h->q_chunk = std::max(o.q_estimate ? 1 : 2, c.q_iter);
         if (!c.bad && !cfg.classical && c.r_done == 1)
             if ((s = gmres_continue(h, gc, c)) != OSM_OK) { fill(); return s; }
         fill();
