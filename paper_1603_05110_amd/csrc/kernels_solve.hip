@@ -875,8 +875,16 @@ __global__ __launch_bounds__(NW * 64) void batch_solve_kernel(BatchSolveArgs a) 
                 const T2 *vp = vec + p * n;
                 for (int rb = r0 + wave; rb < r1; rb += NW * RU) {
                     A ar[RU], ai[RU];
+                    // forward results of backward rows, loaded ahead of the
+                    // products so their latency overlaps them
+                    double2 o[RU];
 #pragma unroll
-                    for (int u = 0; u < RU; ++u) { ar[u] = 0; ai[u] = 0; }
+                    for (int u = 0; u < RU; ++u) {
+                        ar[u] = 0;
+                        ai[u] = 0;
+                        const int r = rb + NW * u;
+                        o[u] = bwd && r < r1 ? ld_agent(s.x + (long)i * n + r) : cd(0.0, 0.0);
+                    }
                     for (int c0 = 0; c0 < n; c0 += 64 * UN) {
                         T2 mm[RU][UN];
 #pragma unroll
@@ -908,10 +916,7 @@ __global__ __launch_bounds__(NW * 64) void batch_solve_kernel(BatchSolveArgs a) 
                         if (lane == 0 && r < r1) {
                             double2 *xr = s.x + (long)i * n + r;
                             if (!bwd) st_agent(xr, cd((double)sr * inv, (double)si * inv));
-                            else {
-                                double2 o = ld_agent(xr);
-                                st_agent(xr, cd(o.x - (double)sr * inv, o.y - (double)si * inv));
-                            }
+                            else st_agent(xr, cd(o[u].x - (double)sr * inv, o[u].y - (double)si * inv));
                         }
                     }
                 }
