@@ -137,17 +137,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
     const int ncand = (N - (int)blockIdx.z + G - 1) / G;
     for (int cb = 0; cb < ncand; cb += LC) {
     {
+        // compaction in candidate order: a ballot per wave, the waves' counts
+        // added in wave order
         const int t = threadIdx.x, jc = blockIdx.z + G * (cb + t);
-        const int hit = cb + t < ncand && t < LC && strips[jc].cls == cls;
+        const bool hit = cb + t < ncand && strips[jc].cls == cls;
+        const unsigned long long mask = __ballot(hit);
+        __shared__ int wcount[4];
         __syncthreads();   // the previous list is no longer read
-        slist[t] = hit;
+        if (lane == 0) wcount[wave] = __popcll(mask);
         __syncthreads();
-        if (t == 0) {
-            int k = 0;
-            for (int q = 0; q < LC && cb + q < ncand; ++q)
-                if (slist[q]) slist[k++] = blockIdx.z + G * (cb + q);
-            slist[LC] = k;
-        }
+        int off = 0;
+        for (int u = 0; u < wave; ++u) off += wcount[u];
+        if (hit) slist[off + __popcll(mask & ((1ull << lane) - 1ull))] = jc;
+        if (t == 0) slist[LC] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
         __syncthreads();
     }
     const int ns = slist[LC];
