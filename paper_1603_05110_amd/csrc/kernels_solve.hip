@@ -289,6 +289,14 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
     unsigned *ctr = a.counters + j;
     const long nn = (long)n * n;
     const int S = tw_steps(s.nx);
+    // 2 n after vecs: forward results of this member's rows of the step's
+    // backward lines, loaded while the team barrier is pending (tiles with
+    // two or more rows in registers; with one, the FP64 tile returned wrong
+    // results for a cause not found, and the value is loaded when the row
+    // is finished)
+    constexpr bool OFWD = PR >= 2;
+    double2 *ofwd = reinterpret_cast<double2 *>(vecs + 2 * n);
+    TwStep t = tw_step(s.nx, 0);
     const double sc = strip_scale(a.lmax ? a.lmax + s.off : nullptr, s.nx), inv = 1.0 / sc;
     T2 m[PR][NCH];
 
@@ -325,14 +333,26 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
             double2 *xr = a.x + L * n + r;
             if (!bwd) st_agent(xr, cd((double)ar * inv, (double)ai * inv));
             else {
-                double2 o = ld_agent(xr);
+                double2 o;
+                if constexpr (OFWD) {
+                    const int p = (t.lt >= 0 && L == line_of(t, 0)) ? 0 : 1;
+                    o = ofwd[p * n + (r - r0)];
+                } else {
+                    o = ld_agent(xr);
+                }
                 st_agent(xr, cd(o.x - (double)ar * inv, o.y - (double)ai * inv));
             }
         }
     };
     auto xl = [&](long line, int q) -> double2 { return ld_agent(a.x + line * n + q); };
+    auto prefetch_o = [&](const TwStep &tn) {
+        for (int p = 0; p < 2; ++p) {
+            if ((p == 0 ? tn.lt : tn.lb) < 0 || !tw_backward(p == 0 ? tn.kt : tn.kb)) continue;
+            const long L = line_of(tn, p);
+            for (int q = threadIdx.x; q < R; q += NTHR) ofwd[p * n + q] = ld_agent(a.x + L * n + r0 + q);
+        }
+    };
 
-    TwStep t = tw_step(s.nx, 0);
     prefetch(t);
     for (int st = 0; st < S; ++st) {
         
@@ -409,6 +429,7 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
             __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         t = tw_step(s.nx, st + 1);
         prefetch(t);
+        if constexpr (OFWD) prefetch_o(t);
         if (threadIdx.x == 0) {
             unsigned spins = 0;
             while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -969,6 +990,7 @@ struct Variant {
     const void *fn;
     int threads;
     int wregs;   // upper-triangle kernel with per-wave partial regions
+    int ofwd;    // full-row kernel staging backward rows' forward results in LDS
 };
 
 // Tile shapes of the strip solve for a column count n and a precision: the
@@ -983,36 +1005,36 @@ Variant variant_for(int n, int fp32, int shape = 0) {
     shape = shape < 0 ? 0 : (shape >= SOLVE_SHAPES ? SOLVE_SHAPES - 1 : shape);
     if (fp32) {
         if (nch <= 3) {
-            if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 3, 8>, 512};
-            if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 3, 3>, 512};
-            return {(const void *)strip_solve_pf_kernel<float, 16, 3, 2>, 1024};
+            if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 3, 8>, 512, 0, 1};
+            if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 3, 3>, 512, 0, 1};
+            return {(const void *)strip_solve_pf_kernel<float, 16, 3, 2>, 1024, 0, 1};
         }
         if (nch <= 9) {
-            if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 9, 5>, 512};
-            if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 9, 2>, 512};
-            if (shape == 2) return {(const void *)strip_solve_pf_kernel<float, 16, 9, 2>, 1024};
-            return {(const void *)strip_solve_pf_kernel<float, 8, 9, 9>, 512};
+            if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 9, 5>, 512, 0, 1};
+            if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 9, 2>, 512, 0, 1};
+            if (shape == 2) return {(const void *)strip_solve_pf_kernel<float, 16, 9, 2>, 1024, 0, 1};
+            return {(const void *)strip_solve_pf_kernel<float, 8, 9, 9>, 512, 0, 1};
         }
         if (nch <= 17) {
-            if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 3>, 512};
-            if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 1>, 512};
-            if (shape == 2) return {(const void *)strip_solve_pf_kernel<float, 16, 17, 1>, 1024};
-            return {(const void *)strip_solve_pf_kernel<float, 8, 17, 4>, 512};
+            if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 3>, 512, 0, 1};
+            if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 1>, 512, 0, 0};
+            if (shape == 2) return {(const void *)strip_solve_pf_kernel<float, 16, 17, 1>, 1024, 0, 0};
+            return {(const void *)strip_solve_pf_kernel<float, 8, 17, 4>, 512, 0, 1};
         }
-        if (nch <= 33) return {(const void *)strip_solve_pf_kernel<float, 8, 33, 1>, 512};
+        if (nch <= 33) return {(const void *)strip_solve_pf_kernel<float, 8, 33, 1>, 512, 0, 0};
         return {(const void *)strip_solve_kernel<float>, SOLVE_THREADS};
     }
     if (nch <= 3) {
-        if (shape == 1) return {(const void *)strip_solve_pf_kernel<double, 8, 3, 4>, 512};
-        return {(const void *)strip_solve_pf_kernel<double, 16, 3, 4>, 1024};
+        if (shape == 1) return {(const void *)strip_solve_pf_kernel<double, 8, 3, 4>, 512, 0, 1};
+        return {(const void *)strip_solve_pf_kernel<double, 16, 3, 4>, 1024, 0, 1};
     }
     if (nch <= 9) {
-        if (shape == 0) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 3>, 512};
-        if (shape == 1) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 1>, 512};
-        if (shape == 2) return {(const void *)strip_solve_pf_kernel<double, 16, 9, 1>, 1024};
-        return {(const void *)strip_solve_pf_kernel<double, 8, 9, 4>, 512};
+        if (shape == 0) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 3>, 512, 0, 1};
+        if (shape == 1) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 1>, 512, 0, 0};
+        if (shape == 2) return {(const void *)strip_solve_pf_kernel<double, 16, 9, 1>, 1024, 0, 0};
+        return {(const void *)strip_solve_pf_kernel<double, 8, 9, 4>, 512, 0, 1};
     }
-    if (nch <= 17) return {(const void *)strip_solve_pf_kernel<double, 8, 17, 1>, 512};
+    if (nch <= 17) return {(const void *)strip_solve_pf_kernel<double, 8, 17, 1>, 512, 0, 0};
     return {(const void *)strip_solve_kernel<double>, SOLVE_THREADS};
 }
 
@@ -1086,7 +1108,7 @@ Variant variant_sym_for(int n, int fp32, int shape) {
 // dynamic LDS of a strip-solve variant for lines of n nodes
 size_t solve_smem(int n, int fp32, int sym, const Variant &v) {
     const size_t e2 = fp32 ? sizeof(float2) : sizeof(double2), ea = fp32 ? 4 : 8;
-    if (!sym) return 2 * (size_t)n * e2;
+    if (!sym) return 2 * (size_t)n * e2 + (v.ofwd ? 2 * (size_t)n * sizeof(double2) : 0);
     const size_t rest = 2 * (size_t)n * e2 + 2 * (size_t)n * sizeof(double2);
     if (v.wregs) return (size_t)(v.threads / 64) * 2 * n * 2 * ea + rest;
     return rest + 4 * (size_t)n * ea;
@@ -1102,6 +1124,15 @@ Variant pick(int n, int fp32, int shape, int sym) {
 // kernels with the same tile (absent beyond their column-chunk limits).
 int solve_shapes() { return 2 * SOLVE_SHAPES; }
 int solve_shape_is_sym(int shape) { return shape >= SOLVE_SHAPES ? 1 : 0; }
+
+// largest dynamic LDS of the full-row solve's tile shapes (or of the
+// generic kernel beyond their column-chunk limit) for lines of n nodes
+size_t solve_pf_smem(int n, int fp32) {
+    size_t m = 0;
+    for (int shape = 0; shape < SOLVE_SHAPES; ++shape)
+        m = std::max(m, solve_smem(n, fp32, 0, variant_for(n, fp32, shape)));
+    return m;
+}
 
 int solve_sym_supported(int n, int fp32) {
     int dev = 0, lim = 0;

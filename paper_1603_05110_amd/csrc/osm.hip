@@ -859,7 +859,7 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
                 hipSuccess)
             return fail(nullptr, OSM_EHIP, "device attribute query failed");
-        size_t need = 2 * (size_t)sz.n * (sz.fp32 ? 8 : 16);
+        size_t need = solve_pf_smem((int)sz.n, sz.fp32);
         if (need > (size_t)lim)
             return fail(nullptr, OSM_EINVAL,
                         "ncy + 1 = " + std::to_string(sz.n) + " needs " + std::to_string(need) +

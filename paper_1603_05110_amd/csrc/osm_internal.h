@@ -213,6 +213,7 @@ int solve_max_resident_blocks(int fp32, int n, int shape);
 int solve_shape_is_sym(int shape);
 // 1 when the half-storage solve has a kernel for n and fits the device's LDS
 int solve_sym_supported(int n, int fp32);
+size_t solve_pf_smem(int n, int fp32);
 
 // kernels_control.hip
 // Step configuration and device-side state of one time step.
