@@ -40,8 +40,8 @@ MFMA_FP64_PEAK_TFLOPS = 78.6
 # this workload, each scaled by the counter's reading for a 1 GiB copy
 # (fetch x2.0, write x1.0); valid only for the full-row kernel whose source
 # text (the strip_solve_pf_kernel template) hashes to source_sha256.
-SOLVE_TRAFFIC = {"c32": {"bytes": 2.2733e+09,
-                         "source_sha256": "7aaa291110034f6d175fa5063b31eb5ded2510984b29840918fd077dc3e2929a",
+SOLVE_TRAFFIC = {"c32": {"bytes": 2.2672e+09,
+                         "source_sha256": "f9cd27c1f2eef86c94452add056158ca7fb70bf24c4a5a5bf5c6fdc5c1de7edc",
                          "summary": "profiles/strip_solve_c32_gpe512_hbm_counters.md"}}
 
 
