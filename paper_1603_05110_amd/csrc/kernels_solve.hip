@@ -846,15 +846,16 @@ __global__ __launch_bounds__(NW * 64) void batch_solve_kernel(BatchSolveArgs a) 
     constexpr int NTHR = NW * 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     unsigned *queue = a.counters + a.nstrips;
+    const int nitems = *a.nitems;
     while (true) {
         if (threadIdx.x == 0) {
             int e = __hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            item_sh = e ? a.nitems : (int)atomicAdd(queue, 1u);
+            item_sh = e ? nitems : (int)atomicAdd(queue, 1u);
         }
         __syncthreads();
         const int it = item_sh;
         __syncthreads();
-        if (it >= a.nitems) return;
+        if (it >= nitems) return;
         const BItem I = a.items[it];
         const BStrip s = a.strips[I.strip];
         if (a.guard && s.ctl && fp_idle(s.ctl)) continue;
@@ -978,10 +979,11 @@ __global__ void zero_u32_kernel(unsigned *p, int n, int *err, int *ran) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
     if (i == 0) {
-        *err = 0;
+        if (err) *err = 0;
         if (ran) *ran = 0;
     }
 }
+
 
 // Kernel variant for a column count n and a precision: the prefetching
 // kernel with a register tile sized to stay under the VGPR budget, or the
@@ -1164,7 +1166,7 @@ int solve_max_resident_blocks(int fp32, int n, int shape) {
 hipError_t launch_strip_solve(hipStream_t st, const SolveArgs &a, int fp32, hipEvent_t ev0,
                               hipEvent_t ev1) {
     hipLaunchKernelGGL(zero_u32_kernel, dim3((a.nstrips + 255) / 256), dim3(256), 0, st,
-                       a.counters, a.nstrips, a.error, a.ran);
+                       a.counters, a.nstrips, (int *)nullptr, a.ran);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     SolveArgs args = a;
@@ -1225,10 +1227,16 @@ int batch_solve_max_resident_blocks(int fp32, int variant, int max_n) {
     return per * cus;
 }
 
+hipError_t launch_clear_flag(hipStream_t st, int *flag) {
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, (unsigned *)nullptr, 0, flag,
+                       (int *)nullptr);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_solve(hipStream_t st, const BatchSolveArgs &a, int fp32, int variant,
                               int grid, int max_n, hipEvent_t ev0, hipEvent_t ev1) {
     hipLaunchKernelGGL(zero_u32_kernel, dim3((a.nstrips + 1 + 255) / 256), dim3(256), 0, st,
-                       a.counters, a.nstrips + 1, a.error, a.ran);
+                       a.counters, a.nstrips + 1, (int *)nullptr, a.ran);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     BVariant v = batch_variant(fp32, variant);

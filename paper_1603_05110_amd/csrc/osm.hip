@@ -109,7 +109,10 @@ struct osm_handle {
     std::vector<BStrip> bstrips_h;
     BStrip *bstrips_d = nullptr;
     BItem *bitems_d = nullptr;
-    int nitems = 0, max_n = 0, nstrips_all = 0;
+    int *bnitems_d = nullptr;        // live item count read by the batched solve
+    int nitems = 0, max_n = 0, nstrips_all = 0;   // nitems: items of the tuned plan
+    std::vector<int> bstrip_inst;    // instance of each strip
+    std::vector<char> plan_active;   // instances the live plan covers
     unsigned *bcounters = nullptr;
     int *bflags = nullptr;
     double *bscal = nullptr;
@@ -1101,6 +1104,7 @@ static osm_status autotune_team(osm_handle *h) {
     long long keep_n = h->solve_launches;
     double keep_b = h->solve_bytes;
     HIPCHK(h, hipMemsetAsync(h->res, 0, sizeof(double2) * (size_t)h->Lt * h->n, h->st));
+    HIPCHK(h, launch_clear_flag(h->st, h->err_d));
     int best = h->team, best_shape = h->shape;
     double best_ms = 1e300;
     for (int shape = 0; shape < solve_shapes(); ++shape) {
@@ -1198,6 +1202,7 @@ osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats) {
     // reject non-finite input; the mass of u_{n-1} comes back with the same
     // synchronisation
     HIPCHK(h, hipMemsetAsync(h->flag_d, 0, sizeof(int), h->st));
+    HIPCHK(h, launch_clear_flag(h->st, h->err_d));
     HIPCHK(h, launch_check_finite(h->st, u, (long)h->nglob * h->n, h->flag_d));
     HIPCHK(h, launch_mass_partials(h->st, h->P, u, h->mass_part));
     HIPCHK(h, launch_sum(h->st, h->mass_part, h->nglob, 1, h->scal + 4));
@@ -1288,6 +1293,7 @@ osm_status osm_interface_apply(osm_handle *h, osm_iface_op op, const osm_c64 *u_
         if (!u_dev) return fail(h, OSM_EINVAL, "u_dev is NULL");
         if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called first");
         const double2 *u = (const double2 *)u_dev;
+        HIPCHK(h, launch_clear_flag(h->st, h->err_d));
         HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
         int q;
         double a, b;
@@ -1336,6 +1342,7 @@ osm_status osm_strip_solve(osm_handle *h, const osm_c64 *b_dev, osm_c64 *x_dev) 
     SINGLE_ONLY(h);
     if (!b_dev || !x_dev) return fail(h, OSM_EINVAL, "null vector");
     if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called first");
+    HIPCHK(h, launch_clear_flag(h->st, h->err_d));
     osm_status s = do_solve(h, (const double2 *)b_dev, (double2 *)x_dev);
     if (s != OSM_OK) return s;
     return check_solve_error(h);
@@ -1635,20 +1642,25 @@ osm_status osm_query_batch(const osm_problem *probs, int32_t nb, const osm_optio
 // ceil(cost / (alpha mean)) members (at most 16, and together at most half
 // the grid); alpha <= 0 gives every strip one workgroup.  Multi-member
 // strips come first, then single strips, each by decreasing cost per member.
-static std::vector<BItem> make_items(const osm_handle *h, double alpha, int grid) {
-    int ns = (int)h->bstrips_h.size();
-    std::vector<double> cost(ns);
+// With an instance mask only the strips of the marked instances get items,
+// and the mean is taken over them: as instances converge, the strips of those
+// still iterating get larger teams and the grid stays busy.
+static std::vector<BItem> make_items(const osm_handle *h, double alpha, int grid,
+                                     const std::vector<char> *active = nullptr) {
+    int ns0 = (int)h->bstrips_h.size();
+    std::vector<int> order;
+    for (int i = 0; i < ns0; ++i)
+        if (!active || (*active)[h->bstrip_inst[i]]) order.push_back(i);
+    std::vector<double> cost(ns0, 0.0);
     double tot = 0.0;
-    for (int i = 0; i < ns; ++i) {
+    for (int i : order) {
         const BStrip &s = h->bstrips_h[i];
         cost[i] = (2.0 * s.nx - 1.0) * (double)s.n * s.n;
         tot += cost[i];
     }
     double unit = alpha > 0 ? alpha * tot / std::max(grid, 1) : 0.0;
-    std::vector<int> team(ns, 1);
+    std::vector<int> team(ns0, 1);
     int budget = grid / 2, used = 0;
-    std::vector<int> order(ns);
-    for (int i = 0; i < ns; ++i) order[i] = i;
     std::sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     if (unit > 0) {
         for (int i : order) {
@@ -1675,7 +1687,7 @@ static osm_status batch_solve(osm_handle *h, int guard, hipStream_t st, hipEvent
     BatchSolveArgs a;
     a.strips = h->bstrips_d;
     a.items = h->bitems_d;
-    a.nitems = h->nitems;
+    a.nitems = h->bnitems_d;
     a.nstrips = h->nstrips_all;
     a.counters = h->bcounters;
     a.error = h->err_d;
@@ -1689,22 +1701,43 @@ static osm_status batch_solve(osm_handle *h, int guard, hipStream_t st, hipEvent
     return OSM_OK;
 }
 
+// Upload a plan (items and their count); the stream is idle when this runs.
+static osm_status upload_items(osm_handle *h, const std::vector<BItem> &items) {
+    if ((int)items.size() > h->nstrips_all * 16)
+        return fail(h, OSM_EINVAL, "work items exceed their buffer");
+    int maxteam = 1;
+    for (const BItem &it : items) maxteam = std::max(maxteam, it.team);
+    if (maxteam > h->bgrid) return fail(h, OSM_EINVAL, "team larger than the resident grid");
+    int cnt = (int)items.size();
+    if (cnt > 0)
+        HIPCHK(h, hipMemcpy(h->bitems_d, items.data(), sizeof(BItem) * items.size(),
+                            hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->bnitems_d, &cnt, sizeof(int), hipMemcpyHostToDevice));
+    return OSM_OK;
+}
+
+// The tuned plan over every instance.  The grid is the resident capacity
+// whatever the item count (workgroups without an item return at once), so a
+// captured launch stays valid when the plan changes.
 static osm_status set_items(osm_handle *h, double alpha, int variant) {
     int cap = batch_solve_max_resident_blocks(h->fp32, variant, h->max_n);
     if (cap <= 0) return fail(h, OSM_EHIP, "occupancy query of the batched solve failed");
     std::vector<BItem> items = make_items(h, alpha, cap);
-    if ((int)items.size() > h->nstrips_all * 16)
-        return fail(h, OSM_EINVAL, "work items exceed their buffer");
-    HIPCHK(h, hipMemcpy(h->bitems_d, items.data(), sizeof(BItem) * items.size(),
-                        hipMemcpyHostToDevice));
-    h->nitems = (int)items.size();
     h->bvariant = variant;
     h->balpha = alpha;
-    h->bgrid = std::min(cap, h->nitems);
-    int maxteam = 1;
-    for (const BItem &it : items) maxteam = std::max(maxteam, it.team);
-    if (maxteam > h->bgrid) return fail(h, OSM_EINVAL, "team larger than the resident grid");
-    return OSM_OK;
+    h->bgrid = cap;
+    h->nitems = (int)items.size();
+    h->plan_active.assign(h->sub.size(), 1);
+    return upload_items(h, items);
+}
+
+// Re-plan the items over the instances marked active (same tile shape and
+// team rule) when that set differs from the live plan's.
+static osm_status replan_items(osm_handle *h, const std::vector<char> &active) {
+    if (active == h->plan_active) return OSM_OK;
+    std::vector<BItem> items = make_items(h, h->balpha, h->bgrid, &active);
+    h->plan_active = active;
+    return upload_items(h, items);
 }
 
 // Autotuner of the batched solve: tile shape (waves per workgroup, rows and
@@ -1718,6 +1751,7 @@ static osm_status batch_autotune(osm_handle *h) {
     HIPCHK(h, hipEventCreate(&e1));
     for (osm_handle *u : h->sub)
         HIPCHK(h, hipMemsetAsync(u->res, 0, sizeof(double2) * (size_t)u->Lt * u->n, h->st));
+    HIPCHK(h, launch_clear_flag(h->st, h->err_d));
     double best = 1e300;
     int bv = 0;
     double ba = 0.0;
@@ -1870,6 +1904,7 @@ osm_status osm_setup_batch(const osm_problem *probs, int32_t nb, const osm_optio
         ALLOC(h, h->bscal, double, 2 * nb);
         ALLOC(h, h->bstrips_d, BStrip, h->nstrips_all);
         ALLOC(h, h->bitems_d, BItem, 16 * h->nstrips_all);
+        ALLOC(h, h->bnitems_d, int, 1);
         ALLOC(h, h->bcounters, unsigned, h->nstrips_all + 1);
         long all_lines = 0;
         for (osm_handle *u : h->sub) all_lines += u->Lt;
@@ -1910,6 +1945,7 @@ osm_status osm_setup_batch(const osm_problem *probs, int32_t nb, const osm_optio
                 bs.n = u->n;
                 bs.nx = sm.nx;
                 h->bstrips_h.push_back(bs);
+                h->bstrip_inst.push_back(b);
             }
         }
         HIPCHK(h, hipMemcpy(h->tab_d, h->tab_h.data(), sizeof(InstDesc) * nb, hipMemcpyHostToDevice));
@@ -1976,13 +2012,14 @@ osm_status osm_step_batch(osm_handle *h, osm_c64 *const *u_devs, osm_step_stats 
     for (int b = 0; b < nb; ++b)
         if (bad[b]) return fail(h, OSM_ENONFINITE, "u_{n-1} of instance " + std::to_string(b) +
                                                       " contains NaN or Inf");
+    HIPCHK(h, launch_clear_flag(h->st, h->err_d));
+    std::vector<char> active(nb, 1);
+    osm_status s = replan_items(h, active);
+    if (s != OSM_OK) return s;
     HIPCHK(h, launch_b_mass(h->st, h->tab_d, d, 0));
     HIPCHK(h, launch_b_step_init(h->st, h->tab_d, d, batch_cfg(o)));
     HIPCHK(h, launch_b_copy_u(h->st, h->tab_d, d, 0));
-    if (!h->prof) {
-        osm_status s = batch_capture(h);
-        if (s != OSM_OK) return s;
-    }
+    if (!h->prof && (s = batch_capture(h)) != OSM_OK) return s;
     int nk = o.fixed_k > 0 ? o.fixed_k : o.max_k;
     int nq = o.fixed_q > 0 ? o.fixed_q : o.max_q;
     long max_chunks = ((long)nk * nq + (long)h->chunk_k * h->chunk_q - 1) /
@@ -1999,7 +2036,6 @@ osm_status osm_step_batch(osm_handle *h, osm_c64 *const *u_devs, osm_step_stats 
             S.last_increment = c[b].inc;
         }
     };
-    osm_status s = OSM_OK;
     bool done = false;
     for (long ch = 0; ch < max_chunks && !done; ++ch) {
         if (h->prof) {
@@ -2026,6 +2062,7 @@ osm_status osm_step_batch(osm_handle *h, osm_c64 *const *u_devs, osm_step_stats 
                 return fail(h, OSM_ENOCONV, "fixed point of instance " + std::to_string(b) +
                                                 " did not converge within max_q");
             }
+            active[b] = !c[b].k_done;
             if (!c[b].k_done) {
                 done = false;
                 if (c[b].k >= nk) {
@@ -2035,6 +2072,7 @@ osm_status osm_step_batch(osm_handle *h, osm_c64 *const *u_devs, osm_step_stats 
                 }
             }
         }
+        if (!done && (s = replan_items(h, active)) != OSM_OK) return s;
     }
     if (!done) {
         fill();

@@ -191,7 +191,9 @@ struct SolveArgs {
     const double2 *b;        // right-hand side, packed
     double2 *x;              // solution, packed
     unsigned int *counters;  // one per strip, zero on entry
-    int *error;              // set to 1 if a barrier wait times out
+    int *error;              // set to 1 if a barrier wait times out; sticky: no
+                             // solve clears it (launch_clear_flag does), and a
+                             // team that finds it set stops at its next barrier
     const StepCtl *ctl;      // may be null; the whole solve is skipped when it
                              // says the fixed point is done
     int *ran;                // may be null; set to 1 when the solve was not skipped
@@ -366,9 +368,11 @@ struct BItem {
 struct BatchSolveArgs {
     const BStrip *strips;
     const BItem *items;
-    int nitems, nstrips;
+    const int *nitems;      // device: the live item count (the host may re-plan
+                            // the items between launches)
+    int nstrips;
     unsigned *counters;     // nstrips barrier counters, then the queue head
-    int *error;
+    int *error;             // sticky, as SolveArgs::error
     int *ran;               // may be null; set to 1 when any strip was solved
     unsigned long long *work;  // may be null; algorithmic bytes of the strips solved
     int guard;              // 1: skip strips whose instance's fixed point is idle
@@ -391,6 +395,8 @@ hipError_t launch_b_flux(hipStream_t st, const InstDesc *tab, const BatchDims &d
 hipError_t launch_b_commit(hipStream_t st, const InstDesc *tab, const BatchDims &d);
 hipError_t launch_b_time_update(hipStream_t st, const InstDesc *tab, const BatchDims &d);
 // kernels_solve.hip: variant = tile shape index (0 .. batch_solve_variants()-1)
+// *flag = 0 on the stream (a kernel, so the call may sit in a captured graph)
+hipError_t launch_clear_flag(hipStream_t st, int *flag);
 hipError_t launch_batch_solve(hipStream_t st, const BatchSolveArgs &a, int fp32, int variant,
                               int grid, int max_n, hipEvent_t ev0, hipEvent_t ev1);
 int batch_solve_variants();
