@@ -3,6 +3,8 @@
 // vector primitives of GMRES on P x = y, P = I - L_h.  FP64.
 #include "osm_internal.h"
 
+#include <algorithm>
+
 namespace {
 
 __device__ __forceinline__ double wsum(double v) { return wave_sum_f64(v); }
@@ -88,15 +90,15 @@ __device__ __forceinline__ void lh_matvec_body(Phys P, const StripMeta *strips,
 }
 
 // L_h x with every block row reused over many strips.  Workgroup
-// (tile, class, group) owns rows [a0, a0 + 2R) of the blocks of one strip
-// class.  Wave w computes output side w & 1 for R rows: side 0 is trace
-// 2(j-1) (new r_{j-1}) = X^1 l_j + X^2 r_j, side 1 is trace 2j+1
+// (class, group, tile) of the plan owns rows [a0, a0 + 2R) of the blocks of
+// one strip class.  Wave w computes output side w & 1 for R rows: side 0 is
+// trace 2(j-1) (new r_{j-1}) = X^1 l_j + X^2 r_j, side 1 is trace 2j+1
 // (new l_{j+1}) = X^3 l_j + X^4 r_j (eq. Lmpi; l_0 and r_{N-1} are zero).
-// It keeps its R rows of its two blocks in registers and loops over the
-// strips j = group, group + G, ... of that class, writing each result
-// itself; every output trace has exactly one writer.  The inputs l_j, r_j
-// of SB strips at a time are loaded together and staged in LDS, so one
-// memory latency serves SB strips.
+// It keeps its R rows of its two blocks in registers and loops over its
+// group's strips of that class, writing each result itself; every output
+// trace has exactly one writer.  The inputs l_j, r_j of SB strips at a time
+// are loaded together and staged in LDS, so one memory latency serves SB
+// strips.
 //
 // DOTS (Arnoldi step, y = x - L_h x with x = V_{nv-1}): the kernel also
 // forms the first Gram-Schmidt pass's partial products V_k^H y over the
@@ -105,14 +107,22 @@ __device__ __forceinline__ void lh_matvec_body(Phys P, const StripMeta *strips,
 // its nv partials to part[block][k] (stride ld), summed in a fixed order.
 template <int NCH, int R, int SB, bool DOTS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void lh_matvec_reg_kernel(
-    Phys P, const StripMeta *strips, const double2 *LH, const double2 *x, double2 *y,
-    int mode_p, const GmresCtl *ctl, const double2 *V, long ng, int nv, double2 *part, int ld) {
+    Phys P, const LhClass *ctab, int ncls, const int *clist, int tiles, const double2 *LH,
+    const double2 *x, double2 *y, int mode_p, const GmresCtl *ctl, const double2 *V, long ng,
+    int nv, double2 *part, int ld) {
     if (ctl && ctl->done) return;
     constexpr int W = NCH * 64, SPT = (2 * W + 255) / 256;
     __shared__ double2 stage[SB][2 * W];   // [strip of the batch][l_j | r_j]
-    const int n = P.ny, N = P.nsub, cls = blockIdx.y, G = gridDim.z;
+    const int n = P.ny, N = P.nsub;
+    int pc = 0;
+    while (pc + 1 < ncls && (int)blockIdx.x >= ctab[pc + 1].block_off) ++pc;
+    const LhClass C = ctab[pc];
+    const int cls = C.cls, G = C.groups, loc = (int)blockIdx.x - C.block_off;
+    const int tile = loc % tiles, group = loc / tiles;
+    const int ns = (C.count - group + G - 1) / G;   // this group's strips (ranks group + G i)
+    const int *mine = clist + C.list_off + group;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int side = wave & 1, r0 = blockIdx.x * 2 * R + (wave >> 1) * R;
+    const int side = wave & 1, r0 = tile * 2 * R + (wave >> 1) * R;
     const long nn = (long)n * n;
     const double2 *B0 = LH + ((long)cls * 4 + 2 * side) * nn;   // multiplies l_j
     const double2 *B1 = B0 + nn;                                // multiplies r_j
@@ -129,34 +139,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
     auto has_out = [&](int j) { return side == 0 ? j >= 1 : j <= N - 2; };
     auto out_trace = [&](int j) { return side == 0 ? 2 * (j - 1) : 2 * j + 1; };
     double2 acc = cd(0.0, 0.0);
-    // this workgroup's strips (group, group + G, ... of its class), listed in
-    // LDS up to LC candidates at a time: the class tests are loaded in
-    // parallel, not one dependent load per strip
-    constexpr int LC = 256;
-    __shared__ int slist[LC + 1];
-    const int ncand = (N - (int)blockIdx.z + G - 1) / G;
-    for (int cb = 0; cb < ncand; cb += LC) {
-    {
-        // compaction in candidate order: a ballot per wave, the waves' counts
-        // added in wave order
-        const int t = threadIdx.x, jc = blockIdx.z + G * (cb + t);
-        const bool hit = cb + t < ncand && strips[jc].cls == cls;
-        const unsigned long long mask = __ballot(hit);
-        __shared__ int wcount[4];
-        __syncthreads();   // the previous list is no longer read
-        if (lane == 0) wcount[wave] = __popcll(mask);
-        __syncthreads();
-        int off = 0;
-        for (int u = 0; u < wave; ++u) off += wcount[u];
-        if (hit) slist[off + __popcll(mask & ((1ull << lane) - 1ull))] = jc;
-        if (t == 0) slist[LC] = wcount[0] + wcount[1] + wcount[2] + wcount[3];
-        __syncthreads();
-    }
-    const int ns = slist[LC];
     for (int i0 = 0; i0 < ns; i0 += SB) {
         int js[SB];
 #pragma unroll
-        for (int b = 0; b < SB; ++b) js[b] = i0 + b < ns ? slist[i0 + b] : N;
+        for (int b = 0; b < SB; ++b) js[b] = i0 + b < ns ? mine[G * (i0 + b)] : N;
         // every load of the batch in flight together
         double2 stg[SB][SPT];
 #pragma unroll
@@ -233,14 +219,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void l
             }
         }
     }
-    }
     if constexpr (DOTS) {
         __shared__ double2 red[4][64];
         red[wave][lane] = acc;
         __syncthreads();
         if (threadIdx.x < nv) {
             const int k = threadIdx.x;
-            const long b = blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z);
+            const long b = blockIdx.x;
             part[b * ld + k] = cadd(cadd(red[0][k], red[1][k]), cadd(red[2][k], red[3][k]));
         }
     }
@@ -704,24 +689,54 @@ static int lh_resident(int nch, bool dots) {
     return cache[a][b];
 }
 
-// Grid of the register-resident L_h kernel: (row tiles, classes, strip
-// groups), the groups chosen so the grid fits one round of resident
-// workgroups, at most one group per strip.  x = 0 when ny needs more than
-// 17 column chunks.
-static dim3 lh_reg_grid(const Phys &P, int ncls, bool dots) {
-    int nch = (P.ny + 63) / 64;
-    if (nch > 17) return dim3(0, 0, 0);
-    int tiles = (P.ny + 1) / 2;
-    int g = lh_resident(nch, dots) / max(1, tiles * ncls);
-    return dim3(tiles, ncls, (unsigned)max(1, min(g, P.nsub)));
+// Plan of the register-resident L_h kernel.  R = resident workgroups per
+// row tile; class c with n_c of the N strips gets ceil(R n_c / N) strip
+// groups (at least 1, at most n_c), so the resident slots are shared out in
+// proportion to the strips and no group is empty.  Classes with the most
+// strips per group come first in the dispatch order.
+int lh_plan_build(int ny, int nsub, const int *strip_cls, int ncls, std::vector<LhClass> &tab,
+                  std::vector<int> &list) {
+    tab.clear();
+    list.clear();
+    const int nch = (ny + 63) / 64;
+    if (nch > 17 || nsub < 1 || ncls < 1) return 0;
+    const int tiles = (ny + 1) / 2;
+    const int R = max(1, lh_resident(nch, true) / tiles);
+    std::vector<std::vector<int>> members(ncls);
+    for (int j = 0; j < nsub; ++j)
+        if (strip_cls[j] >= 0 && strip_cls[j] < ncls) members[strip_cls[j]].push_back(j);
+    std::vector<LhClass> cl;
+    for (int c = 0; c < ncls; ++c) {
+        const int cnt = (int)members[c].size();
+        if (cnt == 0) continue;
+        LhClass e;
+        e.cls = c;
+        e.count = cnt;
+        e.groups = (int)std::min<long>(cnt, std::max<long>(1, ((long)R * cnt + nsub - 1) / nsub));
+        e.list_off = 0;
+        e.block_off = 0;
+        cl.push_back(e);
+    }
+    std::stable_sort(cl.begin(), cl.end(), [](const LhClass &a, const LhClass &b) {
+        return (a.count + a.groups - 1) / a.groups > (b.count + b.groups - 1) / b.groups;
+    });
+    long blocks = 0;
+    for (LhClass &e : cl) {
+        e.list_off = (int)list.size();
+        list.insert(list.end(), members[e.cls].begin(), members[e.cls].end());
+        e.block_off = (int)blocks;
+        blocks += (long)tiles * e.groups;
+        tab.push_back(e);
+    }
+    return blocks > INT32_MAX ? 0 : (int)blocks;
 }
 
-int lh_fused_blocks(int ny, int nsub, int ncls) {
-    Phys P;
-    P.ny = ny;
-    P.nsub = nsub;
-    dim3 g = lh_reg_grid(P, ncls, true);
-    return (int)(g.x * g.y * g.z);
+int lh_fused_blocks_bound(int ny, int nsub, int ncls) {
+    const int nch = (ny + 63) / 64;
+    if (nch > 17 || nsub < 1 || ncls < 1) return 0;
+    const int tiles = (ny + 1) / 2;
+    const int R = max(1, lh_resident(nch, true) / tiles);
+    return tiles * min(nsub, R + ncls);
 }
 
 // L_h x (mode_p = 0) or x - L_h x (mode_p = 1); ctl may be null.  The
@@ -730,27 +745,33 @@ int lh_fused_blocks(int ny, int nsub, int ncls) {
 // part given (register-resident kernel only, mode_p = 1, x = V_{nv-1},
 // nv <= 64) the first Gram-Schmidt pass's partials go to part.
 static hipError_t lh_apply(hipStream_t st, const Phys &P, const StripMeta *strips, int ncls,
-                           const double2 *LH, const double2 *x, double2 *y, int mode_p,
-                           const GmresCtl *ctl, const double2 *V = nullptr, long ng = 0,
-                           int nv = 0, double2 *part = nullptr, int ld = 0) {
+                           const LhPlan &pl, const double2 *LH, const double2 *x, double2 *y,
+                           int mode_p, const GmresCtl *ctl, const double2 *V = nullptr,
+                           long ng = 0, int nv = 0, double2 *part = nullptr, int ld = 0) {
     int nch = (P.ny + 63) / 64;
-    dim3 grid = lh_reg_grid(P, ncls, part != nullptr);
-    if (part && (nch > 17 || mode_p != 1 || nv < 1 || nv > 64 || !V))
+    const bool reg = nch <= 17 && pl.blocks > 0 && pl.tab && pl.list &&
+                     pl.tiles == (P.ny + 1) / 2;
+    if (part && (!reg || mode_p != 1 || nv < 1 || nv > 64 || !V))
         return hipErrorInvalidValue;
-    if (nch <= 9) {
+    const dim3 grid((unsigned)pl.blocks);
+    if (reg && nch <= 9) {
         if (part)
             hipLaunchKernelGGL((lh_matvec_reg_kernel<9, 1, 2, true>), grid, dim3(256), 0, st, P,
-                               strips, LH, x, y, mode_p, ctl, V, ng, nv, part, ld);
+                               pl.tab, pl.ncls, pl.list, pl.tiles, LH, x, y, mode_p, ctl, V, ng,
+                               nv, part, ld);
         else
             hipLaunchKernelGGL((lh_matvec_reg_kernel<9, 1, 2, false>), grid, dim3(256), 0, st, P,
-                               strips, LH, x, y, mode_p, ctl, V, ng, nv, part, ld);
-    } else if (nch <= 17) {
+                               pl.tab, pl.ncls, pl.list, pl.tiles, LH, x, y, mode_p, ctl, V, ng,
+                               nv, part, ld);
+    } else if (reg) {
         if (part)
             hipLaunchKernelGGL((lh_matvec_reg_kernel<17, 1, 1, true>), grid, dim3(256), 0, st, P,
-                               strips, LH, x, y, mode_p, ctl, V, ng, nv, part, ld);
+                               pl.tab, pl.ncls, pl.list, pl.tiles, LH, x, y, mode_p, ctl, V, ng,
+                               nv, part, ld);
         else
             hipLaunchKernelGGL((lh_matvec_reg_kernel<17, 1, 1, false>), grid, dim3(256), 0, st, P,
-                               strips, LH, x, y, mode_p, ctl, V, ng, nv, part, ld);
+                               pl.tab, pl.ncls, pl.list, pl.tiles, LH, x, y, mode_p, ctl, V, ng,
+                               nv, part, ld);
     } else if (ctl) {
         hipLaunchKernelGGL(lh_matvec_ctl_kernel, dim3(lh_grid(P)), dim3(256), 0, st, P, strips, LH,
                            x, y, ctl);
@@ -767,20 +788,21 @@ int gmres_chunks(long n) {
 }
 
 hipError_t launch_gmres_iteration(hipStream_t st, const Phys &P, const StripMeta *strips,
-                                  int ncls, const double2 *LH, long n, int j, int m, double2 *V,
-                                  double2 *part1, double2 *part2, double *norm_part,
-                                  double2 *H, double2 *cs, double2 *sn, double2 *e,
-                                  GmresCtl *ctl, double2 *mvpart) {
+                                  int ncls, const LhPlan &pl, const double2 *LH, long n, int j,
+                                  int m, double2 *V, double2 *part1, double2 *part2,
+                                  double *norm_part, double2 *H, double2 *cs, double2 *sn,
+                                  double2 *e, GmresCtl *ctl, double2 *mvpart) {
     double2 *vj = V + (long)j * n, *w = V + (long)(j + 1) * n;
     unsigned nb = (unsigned)gmres_chunks(n);
     unsigned ne = (unsigned)((n + 255) / 256);
     int ld = m + 1;
-    const int np1 = lh_fused_blocks(P.ny, P.nsub, ncls);
+    const int np1 = pl.blocks;
     if (mvpart && np1 > 0 && j + 1 <= 64) {
         // three kernels: matvec with the first pass's partials, first update
         // with the second pass's partials, second update with normalisation
         // and rotation
-        hipError_t er = lh_apply(st, P, strips, ncls, LH, vj, w, 1, ctl, V, n, j + 1, mvpart, ld);
+        hipError_t er = lh_apply(st, P, strips, ncls, pl, LH, vj, w, 1, ctl, V, n, j + 1, mvpart,
+                                 ld);
         if (er != hipSuccess) return er;
         hipLaunchKernelGGL(cgs_pass1_kernel, dim3(nb), dim3(256), 0, st, n, (const double2 *)V,
                            j + 1, (const double2 *)mvpart, np1, ld, w, part2, norm_part,
@@ -790,7 +812,7 @@ hipError_t launch_gmres_iteration(hipStream_t st, const Phys &P, const StripMeta
                            (const double *)norm_part, H, cs, sn, e, ctl);
         return hipGetLastError();
     }
-    hipError_t er = lh_apply(st, P, strips, ncls, LH, vj, w, 1, ctl);
+    hipError_t er = lh_apply(st, P, strips, ncls, pl, LH, vj, w, 1, ctl);
     if (er != hipSuccess) return er;
     hipLaunchKernelGGL(cgs_dots_kernel, dim3(nb), dim3(256), 0, st, n, V, j + 1, w, part1, ld,
                        ctl);
@@ -827,8 +849,9 @@ hipError_t launch_gmres_finish(hipStream_t st, long n, int m, const double2 *H, 
 }
 
 hipError_t launch_lh_matvec(hipStream_t st, const Phys &P, const StripMeta *strips, int ncls,
-                            const double2 *LH, const double2 *x, double2 *y, int mode_p) {
-    return lh_apply(st, P, strips, ncls, LH, x, y, mode_p, nullptr);
+                            const LhPlan &pl, const double2 *LH, const double2 *x, double2 *y,
+                            int mode_p) {
+    return lh_apply(st, P, strips, ncls, pl, LH, x, y, mode_p, nullptr);
 }
 
 hipError_t launch_multidot(hipStream_t st, long n, const double2 *V, int nv, const double2 *w,

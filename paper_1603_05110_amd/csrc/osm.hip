@@ -68,6 +68,10 @@ struct osm_handle {
     double2 *gH = nullptr, *gcs = nullptr, *gsn = nullptr, *ge = nullptr, *gy = nullptr;
     double2 *gdots1 = nullptr, *gdots2 = nullptr;
     double2 *gmv = nullptr;        // partials of the fused matvec (may stay null)
+    int gmv_blocks = 0;            // workgroups gmv holds partials for
+    LhClass *lh_tab_d = nullptr;   // work plan of the register-resident L_h kernel
+    int *lh_list_d = nullptr;
+    LhPlan lhp;
     double *gnorm_part = nullptr;
     double *norm_part = nullptr;
     // kernel timing (HIP events around every solve launch when enabled)
@@ -265,7 +269,8 @@ uint64_t device_bytes(const Sizes &s) {
         b += 4ull * s.ncls * s.n * s.n * 16;            // L_h blocks
         b += (uint64_t)(s.m + 2) * s.ng * 16;           // Krylov basis
         b += 2ull * 256 * (s.m + 1) * 16;               // Gram-Schmidt partials
-        b += (uint64_t)lh_fused_blocks((int)s.n, (int)s.N, (int)s.ncls) * (s.m + 1) * 16;
+        b += (uint64_t)lh_fused_blocks_bound((int)s.n, (int)s.N, (int)s.ncls) * (s.m + 1) * 16;
+        b += (uint64_t)s.ncls * sizeof(LhClass) + (uint64_t)s.N * 4;   // L_h kernel plan
         b += 2ull * s.maxnx * s.n * s.n * 16 + (uint64_t)s.n * s.n * 16;  // L_h build temporaries
         b += 2ull * s.maxnx * s.n * 3 * 16;
     }
@@ -532,7 +537,7 @@ osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
     while (true) {
         const double2 *r = y;
         if (!first) {
-            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->ncls, h->LH, x, w, 1));
+            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->ncls, h->lhp, h->LH, x, w, 1));
             HIPCHK(h, launch_axpby(h->st, n, cd(1, 0), y, cd(-1, 0), w, w));
             r = w;
         }
@@ -544,7 +549,7 @@ osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
         while (j < m && total + j < o.max_gmres) {
             int ch = std::min(CH, std::min(m - j, o.max_gmres - total - j));
             for (int jj = j; jj < j + ch; ++jj)
-                HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->ncls, h->LH, n, jj, m, V,
+                HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->ncls, h->lhp, h->LH, n, jj, m, V,
                                                  h->gdots1, h->gdots2, h->gnorm_part, h->gH,
                                                  h->gcs, h->gsn, h->ge, h->gctl, h->gmv));
             j += ch;
@@ -605,7 +610,7 @@ osm_status fp_chunk(osm_handle *h, const double2 *u, int nq) {
 
 osm_status gmres_iters(osm_handle *h, int j0, int j1) {
     for (int j = j0; j < j1; ++j)
-        HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->ncls, h->LH, h->ng, j, h->m, h->Vb,
+        HIPCHK(h, launch_gmres_iteration(h->st, h->P, h->strips_d, h->ncls, h->lhp, h->LH, h->ng, j, h->m, h->Vb,
                                          h->gdots1, h->gdots2, h->gnorm_part, h->gH, h->gcs,
                                          h->gsn, h->ge, h->gctl, h->gmv));
     return OSM_OK;
@@ -644,7 +649,7 @@ osm_status gmres_continue(osm_handle *h, GmresCtl &gc, StepCtl &c) {
             return fail(h, OSM_ENOCONV, "GMRES did not converge within max_gmres");
         if (gc.finished) {
             double2 *w = h->Vb + (long)(m + 1) * ng;
-            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->ncls, h->LH, h->gx, w, 1));
+            HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->ncls, h->lhp, h->LH, h->gx, w, 1));
             HIPCHK(h, launch_axpby(h->st, ng, cd(1, 0), h->gtmp, cd(-1, 0), w, w));
             HIPCHK(h, launch_gmres_begin(h->st, ng, w, h->gnorm_part, 0, 1.0, h->Vb, h->ge, m,
                                          h->gctl, h->sctl));
@@ -755,6 +760,28 @@ osm_status build_lh(osm_handle *h) {
     h->ncls = (int)rep.size();
     HIPCHK(h, hipMemcpy(h->strips_d, h->strips_h.data(), sizeof(StripMeta) * h->N,
                         hipMemcpyHostToDevice));
+    // work plan of the register-resident L_h kernel (within the buffers
+    // sized at setup; without one the unfused kernels are used)
+    h->lhp = LhPlan();
+    if (h->gmv && h->lh_tab_d && h->lh_list_d) {
+        std::vector<int> scls(h->N);
+        for (int j = 0; j < h->N; ++j) scls[j] = h->strips_h[j].cls;
+        std::vector<LhClass> ptab;
+        std::vector<int> plist;
+        int nb1 = lh_plan_build(n, h->N, scls.data(), h->ncls, ptab, plist);
+        if (nb1 > 0 && nb1 <= h->gmv_blocks && (long)ptab.size() <= h->ncls &&
+            (int)plist.size() == h->N) {
+            HIPCHK(h, hipMemcpy(h->lh_tab_d, ptab.data(), sizeof(LhClass) * ptab.size(),
+                                hipMemcpyHostToDevice));
+            HIPCHK(h, hipMemcpy(h->lh_list_d, plist.data(), sizeof(int) * plist.size(),
+                                hipMemcpyHostToDevice));
+            h->lhp.tab = h->lh_tab_d;
+            h->lhp.list = h->lh_list_d;
+            h->lhp.ncls = (int)ptab.size();
+            h->lhp.tiles = (n + 1) / 2;
+            h->lhp.blocks = nb1;
+        }
+    }
     ALLOC(h, h->LH, double2, 4 * h->ncls * nn);
     double2 *FF, *Y, *Tb, *fD, *fU;
     size_t keep = h->allocs.size();
@@ -1026,8 +1053,13 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             SALLOC(h->gdots1, double2, (long)gmres_chunks(h->ng) * (h->m + 1));
             SALLOC(h->gdots2, double2, (long)gmres_chunks(h->ng) * (h->m + 1));
             SALLOC(h->gnorm_part, double, (h->ng + 255) / 256);
-            if (long nb1 = lh_fused_blocks(h->n, h->N, (int)sz.ncls))
-                SALLOC(h->gmv, double2, nb1 * (h->m + 1));
+            // the plan itself is built with the strip classes (build_lh)
+            if (int nb1 = lh_fused_blocks_bound(h->n, h->N, (int)sz.ncls)) {
+                SALLOC(h->gmv, double2, (long)nb1 * (h->m + 1));
+                SALLOC(h->lh_tab_d, LhClass, sz.ncls);
+                SALLOC(h->lh_list_d, int, h->N);
+                h->gmv_blocks = nb1;
+            }
         }
         HIPCHK(h, hipMemcpy(h->strips_d, h->strips_h.data(), sizeof(StripMeta) * h->N, hipMemcpyHostToDevice));
         HIPCHK(h, hipMemcpy(h->line_strip_d, line_strip.data(), sizeof(int) * h->Lt, hipMemcpyHostToDevice));
@@ -1305,7 +1337,7 @@ osm_status osm_interface_apply(osm_handle *h, osm_iface_op op, const osm_c64 *u_
             HIPCHK(h, launch_axpby(h->st, ng, cd(1, 0), gi, cd(-1, 0), h->gn, go));
     } else if (op == OSM_IFACE_LH) {
         if (h->opt.algo != OSM_PRECOND) return fail(h, OSM_ESTATE, "L_h is built only for OSM_PRECOND");
-        HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->ncls, h->LH, gi, go, 0));
+        HIPCHK(h, launch_lh_matvec(h->st, h->P, h->strips_d, h->ncls, h->lhp, h->LH, gi, go, 0));
     } else if (op == OSM_IFACE_PINV) {
         if (h->opt.algo != OSM_PRECOND) return fail(h, OSM_ESTATE, "L_h is built only for OSM_PRECOND");
         int it;

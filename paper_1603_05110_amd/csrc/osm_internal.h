@@ -300,22 +300,43 @@ hipError_t launch_gmres_begin(hipStream_t st, long n, const double2 *r, double *
 // chunks of the Gram-Schmidt partial dot products for vectors of length n
 // (part buffers hold gmres_chunks(n) x (m + 1) values)
 int gmres_chunks(long n);
-// One Arnoldi step j.  mvpart (may be null): lh_fused_blocks(P, ncls) x
-// (m + 1) partials of the fused three-kernel form, used when that is > 0
-// and j < 64; otherwise the six-kernel form (matvec, dots, two updates,
-// rotation, normalisation).
+// Work plan of the register-resident L_h kernel (built once per handle).
+// Class c of the plan (classes ordered by decreasing strips per workgroup,
+// so the longest workgroups are dispatched first) owns the workgroups
+// [block_off, block_off + tiles * groups): `groups` strip groups for every
+// row tile.  Its `count` strips are list[list_off ...] in increasing index,
+// and group g takes the ranks g, g + groups, ...
+struct LhClass {
+    int cls, list_off, count, groups, block_off;
+};
+struct LhPlan {
+    const LhClass *tab = nullptr;   // device, ncls entries
+    const int *list = nullptr;      // device, nsub entries
+    int ncls = 0, tiles = 0;
+    int blocks = 0;                 // 0: the register-resident kernel is not used
+};
+// Host side of the plan: strip_cls[j] is strip j's class.  Fills tab and
+// list and returns the workgroup count (0 when ny needs more than 17 column
+// chunks).
+int lh_plan_build(int ny, int nsub, const int *strip_cls, int ncls, std::vector<LhClass> &tab,
+                  std::vector<int> &list);
+// an upper bound of lh_plan_build's workgroup count from the sizes alone
+int lh_fused_blocks_bound(int ny, int nsub, int ncls);
+// One Arnoldi step j.  mvpart (may be null): pl.blocks x (m + 1) partials of
+// the fused three-kernel form, used when pl.blocks > 0 and j < 64;
+// otherwise the six-kernel form (matvec, dots, two updates, rotation,
+// normalisation).
 hipError_t launch_gmres_iteration(hipStream_t st, const Phys &P, const StripMeta *strips,
-                                  int ncls, const double2 *LH, long n, int j, int m, double2 *V,
-                                  double2 *part1, double2 *part2, double *norm_part,
-                                  double2 *H, double2 *cs, double2 *sn, double2 *e,
-                                  GmresCtl *ctl, double2 *mvpart);
-// workgroups of the register-resident L_h kernel (0: not used for this ny)
-int lh_fused_blocks(int ny, int nsub, int ncls);
+                                  int ncls, const LhPlan &pl, const double2 *LH, long n, int j,
+                                  int m, double2 *V, double2 *part1, double2 *part2,
+                                  double *norm_part, double2 *H, double2 *cs, double2 *sn,
+                                  double2 *e, GmresCtl *ctl, double2 *mvpart);
 hipError_t launch_gmres_finish(hipStream_t st, long n, int m, const double2 *H, const double2 *e,
                                double2 *y, const double2 *V, double2 *x, GmresCtl *ctl,
                                int require_done);
 hipError_t launch_lh_matvec(hipStream_t st, const Phys &P, const StripMeta *strips, int ncls,
-                            const double2 *LH, const double2 *x, double2 *y, int mode_p);
+                            const LhPlan &pl, const double2 *LH, const double2 *x, double2 *y,
+                            int mode_p);
 hipError_t launch_multidot(hipStream_t st, long n, const double2 *V, int nv, const double2 *w,
                            double2 *part, int nblk);
 hipError_t launch_multidot_finalize(hipStream_t st, const double2 *part, int nv, int nblk,
