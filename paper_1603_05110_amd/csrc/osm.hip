@@ -1692,12 +1692,25 @@ static std::vector<BItem> make_items(const osm_handle *h, double alpha, int grid
     }
     double unit = alpha > 0 ? alpha * tot / std::max(grid, 1) : 0.0;
     std::vector<int> team(ns0, 1);
-    int budget = grid / 2, used = 0;
+    // multi-member items must all be taken by the first `grid` workgroups
+    // (every team complete among the resident ones); the whole-batch plan
+    // keeps half the grid for single strips, a re-plan may use all of it
+    const int budget = active ? grid : grid / 2;
     std::sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     if (unit > 0) {
+        long want = 0;
         for (int i : order) {
             int t = (int)ceil(cost[i] / unit);
             t = std::max(1, std::min(t, std::min(16, std::max(1, h->bstrips_h[i].n / 32))));
+            team[i] = t;
+            if (t > 1) want += t;
+        }
+        // over budget: every team shrinks by the same factor, so no strip is
+        // left with one workgroup while others keep full teams
+        const double f = want > budget ? (double)budget / (double)want : 1.0;
+        int used = 0;
+        for (int i : order) {
+            int t = team[i] > 1 ? std::max(1, (int)floor(team[i] * f)) : 1;
             if (t > 1 && used + t > budget) t = 1;
             if (t > 1) used += t;
             team[i] = t;
