@@ -1671,9 +1671,11 @@ osm_status osm_query_batch(const osm_problem *probs, int32_t nb, const osm_optio
 
 // Work items of the batched solve for a team rule: a strip whose cost
 // (products x ny^2) exceeds alpha times the mean cost per workgroup gets
-// ceil(cost / (alpha mean)) members (at most 16, and together at most half
-// the grid); alpha <= 0 gives every strip one workgroup.  Multi-member
-// strips come first, then single strips, each by decreasing cost per member.
+// ceil(cost / (alpha mean)) members (at most 16 and ny / 32); alpha <= 0
+// gives every strip one workgroup.  The members of multi-member strips
+// together stay within a budget (below), all teams shrinking by one factor
+// when they would exceed it.  Multi-member strips come first, then single
+// strips, each by decreasing cost per member.
 // With an instance mask only the strips of the marked instances get items,
 // and the mean is taken over them: as instances converge, the strips of those
 // still iterating get larger teams and the grid stays busy.
