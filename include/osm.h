@@ -350,8 +350,10 @@ osm_status osm_step_batch(osm_handle *h, osm_c64 *const *u_devs,
 
 /* The autotuner's choice: tile-shape index, team rule alpha (0 = one
  * workgroup per strip; else strips costing more than alpha times the mean
- * work per workgroup get proportionally more), grid size and work items.
- * Any output may be NULL. */
+ * work per workgroup get proportionally more), grid size (the resident
+ * capacity of the chosen shape) and the work items of the whole-batch plan.
+ * During a step the items are re-planned, with the same shape and rule,
+ * over the instances still iterating.  Any output may be NULL. */
 osm_status osm_batch_tuning(const osm_handle *h, int32_t *variant, double *alpha,
                             int32_t *workgroups, int32_t *items);
 
