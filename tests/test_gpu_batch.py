@@ -149,3 +149,16 @@ def test_c3_batch_full_size():
     for i in small:
         ref = run_monolithic(pbs[i], wl.u0[i], wl.V[i], 1, tol_q=1e-14)
         assert rel(got[i], ref) < 1e-10, i
+    # the slowest instance runs the step's last launches alone, where the
+    # items are re-planned with the largest teams: against the same instance
+    # solved alone by the single-instance path
+    i = int(np.argmax(ks))
+    log(f"  slowest instance {i}: {pbs[i].ncx}x{pbs[i].ncy}, {pbs[i].nsub} strips, k {ks[i]}")
+    s = osm.OsmSolver(pbs[i], DEV, prec="c32", tol_k=1e-12, tol_k_relative=True, tol_q=1e-14,
+                      max_k=4000)
+    s.factor(to_dev(wl.V[i]))
+    u1 = to_dev(wl.u0[i])
+    s1 = s.step(u1)
+    s.close()
+    assert abs(s1["k"] - ks[i]) <= 2
+    assert rel(got[i], u1.cpu().numpy()) < 1e-10, i
