@@ -297,6 +297,26 @@ osm_status osm_net_loss_grad(osm_net *net, const float *x_dev, const float *t_de
 osm_status osm_net_train_step(osm_net *net, const float *x_dev, const float *t_dev,
                               int32_t T, int32_t L, double lr, double *loss);
 
+/* Largest T of osm_net_loss_grad_noalloc. */
+#define OSM_NET_NOALLOC_MAX_TRACES 256
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the loss
+ * and gradient of osm_net_loss_grad, from the same kernels in the same
+ * order of summation, so the same bits, but with the per-trace partials in
+ * one static device array per GPU (about 4.3 MB, held until the process
+ * ends) instead of the network's workspace.  The call allocates nothing
+ * and does not synchronise: it enqueues on the network's stream, on the
+ * network's device, and returns.  T may exceed the network's max_traces,
+ * up to OSM_NET_NOALLOC_MAX_TRACES (larger T: OSM_EINVAL, nothing
+ * enqueued).  grad_dev (required) receives osm_net_nparams() FP32 values;
+ * loss_dev (device, may be NULL) the loss as one double.  Every call on
+ * one GPU uses the same array: calls that overlap on one GPU (from several
+ * host threads or on several streams) race and must be serialised by the
+ * caller. */
+osm_status osm_net_loss_grad_noalloc(const osm_net *net, const float *x_dev, const float *t_dev,
+                                     int32_t T, int32_t L, float *grad_dev, double *loss_dev);
+
 void osm_net_destroy(osm_net *net);
 const char *osm_net_last_error(const osm_net *net);
 

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <complex>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -142,6 +143,7 @@ struct osm_handle {
 // Parameters, optimiser state and workspaces of the guess network.
 struct osm_net {
     hipStream_t st = nullptr;
+    int device = 0;                  // device current at osm_net_create
     int max_traces = 0;
     float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
     float *gpart = nullptr, *lpart = nullptr;
@@ -1480,6 +1482,45 @@ static osm_status nfail(osm_net *n, osm_status s, const std::string &msg) {
             return nfail(n, OSM_EHIP, std::string(#call) + ": " + hipGetErrorString(_e));   \
     } while (0)
 
+// ---------------------------------------------------------------- no-allocation loss and gradient
+// Workspace of osm_net_loss_grad_noalloc: one static device array per GPU,
+// which each GPU running the library holds until the process ends.  Layout
+// in bytes: the loss (used when the caller passes no loss pointer), the
+// per-trace loss partials, then the per-trace gradient partials, for up to
+// OSM_NET_NOALLOC_MAX_TRACES traces.  On the host the array's name is only a
+// stand-in for the device variable, so host code never passes it to a
+// kernel: every use goes through the device address that
+// hipGetSymbolAddress returned for the current device (noalloc_scratch).
+#define NOALLOC_NPAR_CAP 4352   // >= net_nparams(), a multiple of 64
+#define NOALLOC_LOSS_BYTES 256
+#define NOALLOC_LPART_BYTES (OSM_NET_NOALLOC_MAX_TRACES * 4)
+#define NOALLOC_BYTES \
+    (NOALLOC_LOSS_BYTES + NOALLOC_LPART_BYTES + (size_t)OSM_NET_NOALLOC_MAX_TRACES * NOALLOC_NPAR_CAP * 4)
+static __device__ __align__(256) double scratch[NOALLOC_BYTES / sizeof(double)];
+
+#define NOALLOC_MAX_DEVICES 64
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of `scratch` on the current device: looked up once per
+// device, with that device current, and kept.
+static hipError_t noalloc_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 int32_t osm_net_nparams(void) { return net_nparams(); }
 
 void osm_net_destroy(osm_net *n) {
@@ -1498,6 +1539,10 @@ osm_status osm_net_create(int32_t max_traces, void *hip_stream, osm_net **out) {
     osm_net *n = new osm_net();
     n->st = (hipStream_t)hip_stream;
     n->max_traces = max_traces;
+    if (hipGetDevice(&n->device) != hipSuccess) {
+        delete n;
+        return nfail(nullptr, OSM_EHIP, "hipGetDevice failed");
+    }
     int np = net_nparams();
     auto al = [&](void **p, size_t bytes) -> bool {
         if (hipMalloc(p, bytes) != hipSuccess) return false;
@@ -1518,6 +1563,10 @@ osm_status osm_net_create(int32_t max_traces, void *hip_stream, osm_net **out) {
         osm_net_destroy(n);
         return nfail(nullptr, OSM_EHIP, "hipMemset failed");
     }
+    // set-up of osm_net_loss_grad_noalloc on this device; a failure here is
+    // reported by that entry point, which looks the address up again
+    void *sp = nullptr;
+    (void)noalloc_scratch(&sp);
     *out = n;
     return OSM_OK;
 }
@@ -1566,6 +1615,38 @@ osm_status osm_net_loss_grad(osm_net *n, const float *x_dev, const float *t_dev,
                                     grad_dev ? grad_dev : n->grad, n->loss_d));
     if (loss) NHIPCHK(n, hipMemcpyAsync(loss, n->loss_d, sizeof(double), hipMemcpyDeviceToHost, n->st));
     NHIPCHK(n, hipStreamSynchronize(n->st));
+    return OSM_OK;
+}
+
+osm_status osm_net_loss_grad_noalloc(const osm_net *net, const float *x_dev, const float *t_dev,
+                                     int32_t T, int32_t L, float *grad_dev, double *loss_dev) {
+    if (!net) return OSM_EINVAL;
+    osm_net *n = const_cast<osm_net *>(net);   // error message only
+    if (!x_dev || !t_dev || !grad_dev) return nfail(n, OSM_EINVAL, "null tensor");
+    if (T < 1 || L < 1) return nfail(n, OSM_EINVAL, "T and L must be >= 1");
+    if (T > OSM_NET_NOALLOC_MAX_TRACES)
+        return nfail(n, OSM_EINVAL, "T = " + std::to_string(T) +
+                                        " exceeds OSM_NET_NOALLOC_MAX_TRACES = " +
+                                        std::to_string(OSM_NET_NOALLOC_MAX_TRACES));
+    if (!n->has_params) return nfail(n, OSM_ESTATE, "osm_net_set_params must be called first");
+    if (net_nparams() > NOALLOC_NPAR_CAP)
+        return nfail(n, OSM_EUNSUPPORTED, "the static workspace is smaller than the network");
+    int cur = 0;
+    NHIPCHK(n, hipGetDevice(&cur));
+    if (cur != n->device) NHIPCHK(n, hipSetDevice(n->device));
+    void *sp = nullptr;
+    hipError_t e = noalloc_scratch(&sp);
+    std::string what = "hipGetSymbolAddress(scratch)";
+    if (e == hipSuccess) {
+        char *base = (char *)sp;
+        double *lossp = loss_dev ? loss_dev : (double *)base;
+        float *lpart = (float *)(base + NOALLOC_LOSS_BYTES);
+        float *gpart = (float *)(base + NOALLOC_LOSS_BYTES + NOALLOC_LPART_BYTES);
+        e = launch_net_loss_grad(n->st, n->pbf, x_dev, t_dev, T, L, gpart, lpart, grad_dev, lossp);
+        what = "launch_net_loss_grad";
+    }
+    if (cur != n->device) hipSetDevice(cur);
+    if (e != hipSuccess) return nfail(n, OSM_EHIP, what + ": " + hipGetErrorString(e));
     return OSM_OK;
 }
 

@@ -71,7 +71,8 @@ EXPORTS = ["osm_query", "osm_setup", "osm_factor", "osm_factor_rotating", "osm_s
            "osm_strip_solve", "osm_get_strip_solution", "osm_get_lh_blocks", "osm_get_factor",
            "osm_kernel_timing", "osm_kernel_work", "osm_solve_team", "osm_solve_shape",
            "osm_net_nparams", "osm_net_create", "osm_net_set_params", "osm_net_get_params",
-           "osm_net_forward", "osm_net_loss_grad", "osm_net_train_step", "osm_net_destroy",
+           "osm_net_forward", "osm_net_loss_grad", "osm_net_loss_grad_noalloc",
+           "osm_net_train_step", "osm_net_destroy",
            "osm_net_last_error", "osm_guess_features", "osm_set_guess_net",
            "osm_factor_timing", "osm_query_batch", "osm_setup_batch", "osm_factor_batch", "osm_step_batch",
            "osm_batch_tuning", "osm_destroy", "osm_last_error"]
@@ -113,6 +114,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "osm_net_forward": ([H, P, ctypes.c_int32, ctypes.c_int32, P], st),
         "osm_net_loss_grad": ([H, P, P, ctypes.c_int32, ctypes.c_int32, P,
                                ctypes.POINTER(ctypes.c_double)], st),
+        "osm_net_loss_grad_noalloc": ([H, P, P, ctypes.c_int32, ctypes.c_int32, P, P], st),
         "osm_net_train_step": ([H, P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                 ctypes.POINTER(ctypes.c_double)], st),
         "osm_net_destroy": ([H], None),
@@ -413,6 +415,7 @@ class OsmBatch:
 
 
 NET_NPARAMS = int(_lib.osm_net_nparams())
+NET_NOALLOC_MAX_TRACES = 256   # OSM_NET_NOALLOC_MAX_TRACES of include/osm.h
 
 
 class OsmNet:
@@ -456,6 +459,14 @@ class OsmNet:
         loss = ctypes.c_double()
         self._c(_lib.osm_net_loss_grad(self.h, _ptr(x), _ptr(t), T, L, _ptr(g), ctypes.byref(loss)))
         return loss.value, g
+
+    def loss_grad_noalloc(self, x, t, grad, loss=None):
+        """osm_net_loss_grad_noalloc into the caller's device tensors grad
+        (NET_NPARAMS float32) and loss (one float64, or None); enqueued on
+        the network's stream, not synchronised."""
+        T, _, L = x.shape
+        self._c(_lib.osm_net_loss_grad_noalloc(self.h, _ptr(x), _ptr(t), T, L, _ptr(grad),
+                                               _ptr(loss)))
 
     def train_step(self, x, t, lr, want_loss=True):
         T, _, L = x.shape
