@@ -290,11 +290,12 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
     const long nn = (long)n * n;
     const int S = tw_steps(s.nx);
     // 2 n after vecs: forward results of this member's rows of the step's
-    // backward lines, loaded while the team barrier is pending (tiles with
-    // two or more rows in registers; with one, the FP64 tile returned wrong
-    // results for a cause not found, and the value is loaded when the row
-    // is finished)
-    constexpr bool OFWD = PR >= 2;
+    // backward lines, loaded while the team barrier is pending, so that a
+    // backward row does not wait for a device-coherent load when it is
+    // finished.  (The one-row tiles need the library built without IR-level
+    // common-code sinking: it merged the last store of the two finish_row
+    // call sites below, and the structurized loop then ran its wave sums
+    // with lane 0 masked off.)
     double2 *ofwd = reinterpret_cast<double2 *>(vecs + 2 * n);
     TwStep t = tw_step(s.nx, 0);
     const double sc = strip_scale(a.lmax ? a.lmax + s.off : nullptr, s.nx), inv = 1.0 / sc;
@@ -333,13 +334,8 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
             double2 *xr = a.x + L * n + r;
             if (!bwd) st_agent(xr, cd((double)ar * inv, (double)ai * inv));
             else {
-                double2 o;
-                if constexpr (OFWD) {
-                    const int p = (t.lt >= 0 && L == line_of(t, 0)) ? 0 : 1;
-                    o = ofwd[p * n + (r - r0)];
-                } else {
-                    o = ld_agent(xr);
-                }
+                const int p = (t.lt >= 0 && L == line_of(t, 0)) ? 0 : 1;
+                const double2 o = ofwd[p * n + (r - r0)];
                 st_agent(xr, cd(o.x - (double)ar * inv, o.y - (double)ai * inv));
             }
         }
@@ -429,7 +425,7 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_pf_kernel(SolveArgs a) {
             __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         t = tw_step(s.nx, st + 1);
         prefetch(t);
-        if constexpr (OFWD) prefetch_o(t);
+        prefetch_o(t);
         if (threadIdx.x == 0) {
             unsigned spins = 0;
             while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -1019,11 +1015,11 @@ Variant variant_for(int n, int fp32, int shape = 0) {
         }
         if (nch <= 17) {
             if (shape == 0) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 3>, 512, 0, 1};
-            if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 1>, 512, 0, 0};
-            if (shape == 2) return {(const void *)strip_solve_pf_kernel<float, 16, 17, 1>, 1024, 0, 0};
+            if (shape == 1) return {(const void *)strip_solve_pf_kernel<float, 8, 17, 1>, 512, 0, 1};
+            if (shape == 2) return {(const void *)strip_solve_pf_kernel<float, 16, 17, 1>, 1024, 0, 1};
             return {(const void *)strip_solve_pf_kernel<float, 8, 17, 4>, 512, 0, 1};
         }
-        if (nch <= 33) return {(const void *)strip_solve_pf_kernel<float, 8, 33, 1>, 512, 0, 0};
+        if (nch <= 33) return {(const void *)strip_solve_pf_kernel<float, 8, 33, 1>, 512, 0, 1};
         return {(const void *)strip_solve_kernel<float>, SOLVE_THREADS};
     }
     if (nch <= 3) {
@@ -1032,11 +1028,11 @@ Variant variant_for(int n, int fp32, int shape = 0) {
     }
     if (nch <= 9) {
         if (shape == 0) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 3>, 512, 0, 1};
-        if (shape == 1) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 1>, 512, 0, 0};
-        if (shape == 2) return {(const void *)strip_solve_pf_kernel<double, 16, 9, 1>, 1024, 0, 0};
+        if (shape == 1) return {(const void *)strip_solve_pf_kernel<double, 8, 9, 1>, 512, 0, 1};
+        if (shape == 2) return {(const void *)strip_solve_pf_kernel<double, 16, 9, 1>, 1024, 0, 1};
         return {(const void *)strip_solve_pf_kernel<double, 8, 9, 4>, 512, 0, 1};
     }
-    if (nch <= 17) return {(const void *)strip_solve_pf_kernel<double, 8, 17, 1>, 512, 0, 0};
+    if (nch <= 17) return {(const void *)strip_solve_pf_kernel<double, 8, 17, 1>, 512, 0, 1};
     return {(const void *)strip_solve_kernel<double>, SOLVE_THREADS};
 }
 

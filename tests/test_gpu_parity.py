@@ -98,13 +98,21 @@ def test_every_solve_tile_shape_matches_oracle(prec, tol, ncy, solve_shape):
     bs = [rng.standard_normal((c + 1, pb.ncy + 1)) + 1j * rng.standard_normal((c + 1, pb.ncy + 1))
           for c in cells]
     ref = [orc._lu[j].solve(bs[j].ravel()).reshape(bs[j].shape) for j in range(len(cells))]
+    want = packed(orc, ref)
     for team in (0, 4):
         s = osm.OsmSolver(pb, DEV, prec=prec, solve_shape=solve_shape, team=team)
         s.factor(to_dev(W))
         x = s.strip_solve(to_dev(packed(orc, bs))).cpu().numpy()
         assert s.solve_shape() == solve_shape - 1
         s.close()
-        assert rel(x, packed(orc, ref)) < tol, team
+        assert np.all(np.isfinite(x)), team
+        assert rel(x, want) < tol, team
+        # every strip on its own, and the largest entry error
+        for j in range(len(cells)):
+            o = orc.starts[j] + j
+            sl = slice(o, o + cells[j] + 1)
+            assert rel(x[sl], want[sl]) < tol, (team, j)
+        assert np.max(np.abs(x - want)) < tol * np.max(np.abs(want)), team
 
 
 @pytest.mark.parametrize("fixed_k,fixed_q", [(1, 1), (3, 2)])
