@@ -99,6 +99,31 @@ def weighted_mass_2d(W: np.ndarray, hx: float, hy: float) -> sp.csr_matrix:
                                                  np.concatenate(cols))), shape=(n, n))
 
 
+def weighted_mass_apply(W: np.ndarray, v: np.ndarray, hx: float, hy: float) -> np.ndarray:
+    """M_W v without assembling M_W: (M_W v)_I = sum over elements e, local
+    potential node L and local trial node J of W_L v_J int_e psi_L psi_I psi_J,
+    the same exact triple products as weighted_mass_2d.  W and v are nodal
+    arrays (ncx+1, ncy+1); the element sums run over whole shifted slices of
+    the node grid (element (ex, ey) has local node (a, b) at (ex+a, ey+b))."""
+    W = np.asarray(W, dtype=float)
+    v = np.asarray(v)
+    ncx, ncy = W.shape[0] - 1, W.shape[1] - 1
+    out = np.zeros(v.shape, dtype=np.result_type(v, W))
+    local = [(0, 0), (0, 1), (1, 0), (1, 1)]
+
+    def sl(a, b):
+        return (slice(a, a + ncx), slice(b, b + ncy))
+
+    for (ai, ak) in local:          # test function psi_I
+        acc = np.zeros((ncx, ncy), dtype=out.dtype)
+        for (bi, bk) in local:      # trial function psi_J
+            for (ci, ck) in local:  # interpolant of W
+                coef = hx * triple_1d(ci, ai, bi) * hy * triple_1d(ck, ak, bk)
+                acc += coef * W[sl(ci, ck)] * v[sl(bi, bk)]
+        out[sl(ai, ak)] += acc
+    return out
+
+
 class StripMatrices:
     """The constant matrices of one (sub)domain made of `ncx` cells in x and
     `ncy` cells in y with mesh sizes hx, hy."""

@@ -35,8 +35,35 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .fem import StripMatrices, weighted_mass_2d
+from .fem import StripMatrices, weighted_mass_apply
 from .step import NoConvergence
+
+
+def splitmix64(seed: int, j: np.ndarray) -> np.ndarray:
+    """Output j (0-based) of SplitMix64 seeded with `seed` (Steele, Lea and
+    Flood, "Fast splittable pseudorandom number generators", 2014): the state
+    after j + 1 increments by the golden-ratio constant, mixed by two
+    xor-shift-multiply rounds and a final xor-shift.  uint64 arithmetic
+    wraps modulo 2^64."""
+    j = np.asarray(j, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (j + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def random_interface(seed: int, shape) -> np.ndarray:
+    """The random first interface vector g_1^0 (Section 5, initial vectors):
+    entry k (row-major) is u(2k) + i u(2k+1), u(j) = (output j >> 11) 2^-53,
+    uniform on [0, 1) (the paper does not state the distribution; this is a
+    PETSc-style uniform real and imaginary part)."""
+    n = int(np.prod(shape))
+    k = np.arange(n, dtype=np.uint64)
+    scale = 2.0 ** -53
+    re = (splitmix64(seed, 2 * k) >> np.uint64(11)).astype(np.float64) * scale
+    im = (splitmix64(seed, 2 * k + np.uint64(1)) >> np.uint64(11)).astype(np.float64) * scale
+    return (re + 1j * im).reshape(shape)
 
 
 def gmres(matvec, b, rtol=1e-12, restart=50, maxiter=2000):
@@ -174,8 +201,8 @@ class SchwarzOracle:
                                self.pl[j], self.pr[j])
                 znew = spla.spsolve(K, F)
             else:
-                Mrho = weighted_mass_2d(rho.reshape(shape), pb.hx, pb.hy)
-                znew = self._lu[j].solve(F - Mrho @ zeta)
+                Mz = weighted_mass_apply(rho.reshape(shape), zeta.reshape(shape), pb.hx, pb.hy)
+                znew = self._lu[j].solve(F - Mz.ravel())
             inc = np.linalg.norm(znew - zeta)
             zeta = znew
             if not np.isfinite(inc):

@@ -23,7 +23,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse.linalg as spla
 
-from .fem import StripMatrices, weighted_mass_2d
+from .fem import StripMatrices, weighted_mass_apply
 
 
 class NoConvergence(RuntimeError):
@@ -61,8 +61,8 @@ class MonolithicStepper:
                                        pb.lap_coef, pb.p_bc, pb.p_bc)
                 znew = spla.spsolve(K, F)
             else:
-                Mrho = weighted_mass_2d(rho.reshape(shape), pb.hx, pb.hy)
-                znew = self._lu.solve(F - Mrho @ zeta)
+                Mz = weighted_mass_apply(rho.reshape(shape), zeta.reshape(shape), pb.hx, pb.hy)
+                znew = self._lu.solve(F - Mz.ravel())
             inc = np.linalg.norm(znew - zeta)
             zeta = znew
             if not np.isfinite(inc):

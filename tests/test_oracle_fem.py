@@ -76,3 +76,17 @@ def test_operator_is_complex_symmetric_with_definite_imaginary_part():
     K = m.operator(W, 0.01, 0.5, 3.0, 1.0).toarray()
     assert np.max(np.abs(K - K.T)) < 1e-12
     assert np.linalg.eigvalsh(K.imag).min() > 0
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (5, 8), (17, 3)])
+def test_matrix_free_weighted_mass_equals_the_assembled_matrix(shape):
+    """The fixed point applies M_phi without assembling it; element by
+    element it must give the assembled matrix's product (same exact triple
+    products), for a complex vector and an arbitrary potential."""
+    from oracle.fem import weighted_mass_2d, weighted_mass_apply
+    rng = np.random.default_rng(sum(shape))
+    W = rng.standard_normal(shape)
+    v = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    a = (weighted_mass_2d(W, 0.37, 0.61) @ v.ravel()).reshape(shape)
+    b = weighted_mass_apply(W, v, 0.37, 0.61)
+    assert np.max(np.abs(a - b)) <= 1e-15 * np.max(np.abs(a)) * 10

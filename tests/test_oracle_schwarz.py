@@ -135,3 +135,26 @@ def test_preconditioner_cuts_iterations():
     _, _, sc, _ = run_schwarz(pb, u, W, 1, algo="classical", tol=1e-10)
     _, _, sp_, _ = run_schwarz(pb, u, W, 1, algo="precond", tol=1e-10)
     assert sp_[0]["k"] * 3 < sc[0]["k"]
+
+
+def test_random_interface_generator_matches_published_splitmix64():
+    """The random first interface vector (Section 5, initial vectors) is
+    drawn from SplitMix64; its outputs must be the generator's published
+    test values (seed 0, and seed 1234567), and the derived uniforms must
+    have the mean and variance of U[0, 1)."""
+    from oracle.schwarz import random_interface, splitmix64
+    got0 = [int(v) for v in splitmix64(0, np.arange(4))]
+    assert got0 == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F,
+                    0xF88BB8A8724C81EC]
+    got1 = [int(v) for v in splitmix64(1234567, np.arange(5))]
+    assert got1 == [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                    4593380528125082431, 16408922859458223821]
+    g = random_interface(42, (6, 20001))
+    for part in (g.real, g.imag):
+        assert part.min() >= 0.0 and part.max() < 1.0
+        n = part.size
+        assert abs(part.mean() - 0.5) < 4 * np.sqrt(1 / 12 / n)
+        assert abs(part.var() - 1 / 12) < 0.002
+    # entry k takes outputs 2k (real part) and 2k + 1 (imaginary part)
+    first = splitmix64(42, np.arange(2)) >> np.uint64(11)
+    assert g[0, 0] == complex(float(first[0]) * 2.0 ** -53, float(first[1]) * 2.0 ** -53)

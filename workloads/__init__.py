@@ -274,6 +274,44 @@ def c5(ncells: int = 2048, nsub: int = 64, steps: int = 1000) -> Workload:
 
 
 # --------------------------------------------------------------------------
+# The paper's own experiments (Section 5)
+# --------------------------------------------------------------------------
+
+def nls_mesh1(nsub: int, p: float, steps: int = 50) -> Workload:
+    """Section 5.1, first mesh: cubic NLS (V = 0, f(u) = |u|^2) on
+    (-16,16) x (-8,8), dx = 1/128, dy = 1/8 (4096 x 128 cells, 4097 x 129
+    nodes), N equal strips, Robin p on interfaces and physical x-edges,
+    dt = 0.01, T = 0.5, u0 = exp(-x^2 - y^2 - 0.5 i x)."""
+    ncx, ncy = 4096, 128
+    pb = Problem(-16, 16, -8, 8, ncx, ncy, nsub, equal_strips(ncx, nsub), lap_coef=1.0,
+                 beta=1.0, p=p, p_bc=p, dt=0.01, steps=steps,
+                 name=f"nls-mesh1-{nsub}strips-p{p:g}")
+    x, y = node_coords(pb)
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    u0 = np.exp(-X ** 2 - Y ** 2 - 0.5j * X)
+    return Workload([pb], [u0], [np.zeros((ncx + 1, ncy + 1))], algo="classical",
+                    label="paper-5.1-mesh1")
+
+
+def bec_1025(nsub: int, p: float = 180.0, steps: int = 1000) -> Workload:
+    """Section 5.2.2, first mesh: rotating GPE on (-16,16)^2 with
+    dx = dy = 1/32 (1024^2 cells), omega = 0.4, beta = 10.15, dt = 1e-4,
+    T = 0.1 (1000 steps), u0 = pi^(-1/4) exp(-(x^2 + 2 y^2)/2), Robin p.
+    The trap V = (gamma_x^2 x^2 + gamma_y^2 y^2)/2 is read with gamma_x = 1,
+    gamma_y = 2 (u0 is the linear ground state of that trap), and the GPE of
+    eq. GPE is put in the sign convention of eq. Sch: c = 1/2, V -> -V,
+    beta -> -beta; solved in the rotating frame."""
+    ncx = 1024
+    pb = Problem(-16, 16, -16, 16, ncx, ncx, nsub, equal_strips(ncx, nsub), lap_coef=0.5,
+                 beta=-10.15, p=p, p_bc=p, dt=1e-4, steps=steps,
+                 name=f"bec-1025sq-{nsub}strips-p{p:g}", omega=0.4, vxx=-0.5, vyy=-2.0)
+    x, y = node_coords(pb)
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    u0 = (np.pi ** -0.25 * np.exp(-(X ** 2 + 2 * Y ** 2) / 2)).astype(complex)
+    return Workload([pb], [u0], [None], algo="precond", label="paper-5.2.2-1025")
+
+
+# --------------------------------------------------------------------------
 # Learned interface guess: seeded initial parameters
 # --------------------------------------------------------------------------
 
