@@ -1,0 +1,130 @@
+"""Pins of the S_pade^m oracle (oracle/pade.py): the Pade coefficients of
+eq. TCS against the square root they approximate, the arrow system of eq.
+NproblemSPL against its eliminated form (the one equation for v the paper
+writes after it), the Schwarz iteration with this condition against the
+monolithic solve, and the free problem's L_h (Proposition 3.2)."""
+import numpy as np
+import pytest
+
+from oracle.fem import mass_1d
+from oracle.pade import (PadeSchwarz, PadeStrip, edge_operator, pade_coefficients,
+                         pade_monolithic, pade_sqrt)
+from workloads import Problem
+
+
+def test_pade_coefficients_approximate_the_square_root():
+    """Unrotated (theta = 0): sum a_s z/(z + d_s) is the classical Pade
+    approximant of sqrt(z): exact at z = 1 for every m, and converging on
+    the positive axis.  Rotated by pi/4 it converges on z = 2i/dt + lambda
+    with lambda <= 0 (the symbols of the edge operator), where the
+    unrotated one does not."""
+    for m in (1, 4, 17):
+        assert abs(pade_sqrt(1.0, m, 0.0) - 1.0) < 1e-14
+    z = np.array([0.05, 0.5, 4.0, 30.0])
+    e8 = np.abs(pade_sqrt(z, 8, 0.0) - np.sqrt(z)).max()
+    e32 = np.abs(pade_sqrt(z, 32, 0.0) - np.sqrt(z)).max()
+    assert e32 < e8 / 10
+    # z = 2i/dt + lambda, dt = 0.01, lambda in [-400, 0]: the rotated
+    # approximant converges (poles -d_s off the path of z), the unrotated
+    # one far more slowly (its cut is the negative real axis, which z nears)
+    zz = 200j + np.linspace(-400.0, 0.0, 41)
+    ex = np.sqrt(zz)
+    err = lambda m, th: np.abs(pade_sqrt(zz, m, th) - ex).max() / np.abs(ex).max()
+    rot = [err(m, np.pi / 4) for m in (16, 32, 64)]
+    assert rot[2] < rot[1] / 10 < rot[0] / 20
+    assert rot[2] < 3e-3
+    assert err(64, 0.0) > 30 * rot[2]
+    a, d = pade_coefficients(5)
+    assert np.allclose(np.angle(a), np.pi / 8) and np.allclose(np.angle(d), np.pi / 4)
+
+
+def small(m=6, ncx=10, ncy=9, beta=0.0, c=1.0, cells=(5, 5)):
+    return Problem(-2.0, 2.0, -1.0, 1.0, ncx, ncy, len(cells), list(cells), lap_coef=c,
+                   beta=beta, p=0.0, p_bc=0.0, dt=0.05, tc="pade", pade_m=m)
+
+
+def test_arrow_system_equals_its_eliminated_form():
+    """Eq. NproblemSPL solved as the arrow system equals the single equation
+    for v, (A + i c sum a_s M^G - sum_s B_s D_s^{-1} C_s) v = rhs, with the
+    Schur complement formed densely."""
+    pb = small(c=0.5)
+    rng = np.random.default_rng(2)
+    W = rng.standard_normal((pb.ncx + 1, pb.ncy + 1))
+    st = PadeStrip(pb, pb.ncx, W)
+    F = rng.standard_normal(st.nz) + 1j * rng.standard_normal(st.nz)
+    rhs = np.concatenate([F, np.zeros(2 * st.m * st.ny)])
+    full = st.lu.solve(rhs)[:st.nz]
+    A = st.A.toarray()
+    nz = st.nz
+    K = A[:nz, :nz].copy()
+    for k in range(2 * st.m):
+        sl = slice(nz + k * st.ny, nz + (k + 1) * st.ny)
+        K -= A[:nz, sl] @ np.linalg.solve(A[sl, sl], A[sl, :nz])
+    elim = np.linalg.solve(K, F)
+    assert np.linalg.norm(full - elim) < 1e-12 * np.linalg.norm(elim)
+    # the eliminated edge block is complex symmetric (so are the Schur
+    # complements of the block factor)
+    assert np.allclose(K, K.T, atol=1e-12 * np.abs(K).max())
+
+
+@pytest.mark.parametrize("beta", [0.0, 3.0])
+def test_schwarz_with_pade_converges_to_the_monolithic_step(beta):
+    """At the converged iterate the traces and the edge functions of the two
+    sides agree, so the strips assemble the monolithic solution (whose
+    physical x-edges carry the same condition)."""
+    pb = small(beta=beta, ncx=14, cells=(4, 6, 4), c=0.5)
+    rng = np.random.default_rng(5)
+    s = (pb.ncx + 1, pb.ncy + 1)
+    u = 0.4 * (rng.standard_normal(s) + 1j * rng.standard_normal(s))
+    W = rng.standard_normal(s)
+    ref = pade_monolithic(pb, u, W, 1, tol_q=1e-14)
+    orc = PadeSchwarz(pb, W, tol_q=1e-14)
+    g0 = np.zeros((2 * (pb.nsub - 1), pb.ncy + 1), complex)
+    res = orc.classical(u, g0, tol=1e-13, relative=True)
+    got = orc.assemble_global(res["vs"], u)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
+    pre = PadeSchwarz(pb, W, tol_q=1e-14).precond(u, g0, tol=1e-13, relative=True)
+    got = orc.assemble_global(pre["vs"], u)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
+    assert pre["k"] < res["k"]
+
+
+def test_free_lh_is_the_linear_part_and_preconditions_exactly():
+    """Free problem (V = 0, f = 0): R(g) - R(0) = L_h g, and the
+    preconditioned iteration converges in one outer step."""
+    pb = small(ncx=12, cells=(4, 4, 4))
+    orc = PadeSchwarz(pb, np.zeros((pb.ncx + 1, pb.ncy + 1)), tol_q=1e-14)
+    L = orc.build_Lh()
+    rng = np.random.default_rng(8)
+    nt = 2 * (pb.nsub - 1)
+    g = rng.standard_normal((nt, pb.ncy + 1)) + 1j * rng.standard_normal((nt, pb.ncy + 1))
+    u = rng.standard_normal((pb.ncx + 1, pb.ncy + 1)) + 0j
+    R0, _, _ = orc.R(np.zeros_like(g), u)
+    Rg, _, _ = orc.R(g, u)
+    assert np.linalg.norm((Rg - R0).ravel() - L @ g.ravel()) < 1e-11 * np.linalg.norm(Rg - R0)
+    # equal strips: the blocks of the inner strip are those of Proposition 3.2
+    ny = pb.ncy + 1
+    blk = lambda r, c: L[r * ny:(r + 1) * ny, c * ny:(c + 1) * ny]
+    assert np.linalg.norm(blk(0, 1) - blk(2, 3)) < 1e-12 * np.linalg.norm(blk(0, 1))
+    pre = orc.precond(u, np.zeros_like(g), tol=1e-12, relative=True)
+    assert pre["k"] <= 2
+
+
+def test_edge_operator_is_the_one_dimensional_problem():
+    """D_s applied to a smooth edge function against the 1-D continuous
+    operator (2i/dt + c d_yy + W + d_s) integrated against the hat functions:
+    second order in h (closed form on a cosine with Neumann ends)."""
+    errs = []
+    for ncy in (16, 32, 64):
+        pb = Problem(-1.0, 1.0, 0.0, np.pi, 4, ncy, 2, [2, 2], lap_coef=0.5, beta=0.0,
+                     p=0.0, p_bc=0.0, dt=0.1, tc="pade", pade_m=3)
+        y = np.linspace(0.0, np.pi, ncy + 1)
+        f = np.cos(2 * y)
+        w = np.full(ncy + 1, 0.7)
+        ds = 0.3 + 0.2j
+        D = edge_operator(pb, w, ds)
+        My = mass_1d(ncy, pb.hy)
+        # continuous: (2i/dt - 4c + w + d_s) cos(2y); Galerkin load M f times that factor
+        ref = (2j / pb.dt - 4 * 0.5 + 0.7 + ds) * (My @ f)
+        errs.append(np.abs(D @ f - ref).max() / np.abs(ref).max())
+    assert errs[1] < errs[0] / 3.5 and errs[2] < errs[1] / 3.5

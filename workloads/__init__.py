@@ -50,6 +50,12 @@ class Problem:
     omega: float = 0.0
     vxx: float = 0.0
     vyy: float = 0.0
+    # transmission (and physical x-edge) condition: "robin" (S = -ip, eq.
+    # TCSRobin) or "pade" (S_pade^m of eq. TCS with m terms and branch-cut
+    # rotation theta, Section 2.1; the paper takes theta = pi/4)
+    tc: str = "robin"
+    pade_m: int = 0
+    pade_theta: float = float(np.pi / 4)
 
     @property
     def hx(self) -> float:
