@@ -25,6 +25,10 @@ Oracle code (test infrastructure).  Follows the paper's discrete algorithm:
   (Section 3, eq. Lmpi).  L_h is built numerically, column by column, as the
   free map applied to unit vectors (Section 4.2 does the same with the
   formulas of Proposition 3.1); P x = y is solved by GMRES or directly.
+* Krylov solvers: P x = y by GMRES or by BiCGStab (Section 4.2 names both);
+  for f = 0, where R is affine, the interface problem (I - L) g = d
+  (eq. interfacepb_d) solved directly by GMRES with one Schwarz map per
+  product (interface_krylov).
 * The output v_{j,n} comes from the last evaluation of R; the global u_n
   takes 2 v - u_{n-1} on every line, the mean of the two copies on interface
   lines.
@@ -121,6 +125,38 @@ def gmres(matvec, b, rtol=1e-12, restart=50, maxiter=2000):
             if np.linalg.norm(r) <= 10 * rtol * bnorm:
                 return x, total
     return x, total
+
+
+def bicgstab(matvec, b, rtol=1e-12, maxiter=2000):
+    """BiCGStab without preconditioning (van der Vorst, 1992), x0 = 0 and
+    the shadow residual equal to the first residual; the complex inner
+    product is conjugate-linear in its first argument.  Stops when
+    ||r|| <= rtol ||b||.  Returns (x, iterations)."""
+    x = np.zeros_like(b)
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return x, 0
+    r = b.copy()
+    rh = b.copy()
+    rho_old = alpha = omega = 1.0 + 0.0j
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    for it in range(1, maxiter + 1):
+        rho = np.vdot(rh, r)
+        beta = (rho / rho_old) * (alpha / omega)
+        rho_old = rho
+        p = r + beta * (p - omega * v)
+        v = matvec(p)
+        alpha = rho / np.vdot(rh, v)
+        s = r - alpha * v
+        t = matvec(s)
+        tt = np.vdot(t, t).real
+        omega = np.vdot(t, s) / tt if tt > 0 else 0.0
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        if np.linalg.norm(r) <= rtol * bnorm:
+            return x, it
+    return x, maxiter
 
 
 class SchwarzOracle:
@@ -360,6 +396,9 @@ class SchwarzOracle:
             y = (g - Rg).ravel()
             if pinv == "direct":
                 x = Plu.solve(y)
+            elif pinv == "bicgstab":
+                x, it = bicgstab(lambda z: z - self.Lh_matvec(z), y, rtol=gmres_rtol)
+                gm_total += it
             else:
                 x, it = gmres(lambda z: z - self.Lh_matvec(z), y, rtol=gmres_rtol,
                               restart=gmres_restart)
@@ -371,6 +410,35 @@ class SchwarzOracle:
         if fixed_k is None:
             raise NoConvergence(f"preconditioned Schwarz did not converge in {max_k}")
         return dict(g=g, vs=vs, k=nk, q_total=q_total, gmres_total=gm_total, inc=inc)
+
+
+def interface_krylov(orc, u_old, g0, tol=1e-10, relative=False, restart=50, maxiter=5000):
+    """For f = 0 the Schwarz map is affine in g, R(g) = L g + d with
+    d = R(0), so the fixed point of eq. algo_d solves the interface problem
+    (I - L) g = d (eq. interfacepb_d), here by GMRES on the correction
+    delta = g - g0: (I - L) delta = R(g0) - g0, every product
+    x -> x - (R(x) - d) being one Schwarz map (all strip solves).  Stops
+    when the residual is below tol (or tol ||R(g0) - g0|| when relative).
+    Returns the converged g, the strip solutions of R(g), the Schwarz maps
+    applied (products plus the three maps at d, g0 and g) and the GMRES
+    iterations."""
+    assert orc.pb.beta == 0.0, "the interface problem is linear only for f = 0"
+    d, _, _ = orc.R(np.zeros_like(g0), u_old)
+    Rg0, _, _ = orc.R(g0, u_old)
+    b = (Rg0 - g0).ravel()
+    maps = [0]
+
+    def matvec(x):
+        maps[0] += 1
+        Rx, _, _ = orc.R(x.reshape(g0.shape), u_old)
+        return x - (Rx - d).ravel()
+
+    bn = np.linalg.norm(b)
+    rtol = (tol if relative else tol / bn) if bn > 0 else 1.0
+    delta, its = gmres(matvec, b, rtol=rtol, restart=restart, maxiter=maxiter)
+    g = g0 + delta.reshape(g0.shape)
+    _, vs, _ = orc.R(g, u_old)
+    return dict(g=g, vs=vs, k=maps[0] + 3, gmres_total=its)
 
 
 def run_schwarz(pb, u0, W, steps, algo="classical", g0=None, tol=1e-10,
@@ -388,6 +456,8 @@ def run_schwarz(pb, u0, W, steps, algo="classical", g0=None, tol=1e-10,
             orc.set_potential(W(n))
         if algo == "classical":
             res = orc.classical(u, g, tol=tol, relative=relative, warm=warm, **kw)
+        elif algo == "interface":
+            res = interface_krylov(orc, u, g, tol=tol, relative=relative, **kw)
         else:
             res = orc.precond(u, g, tol=tol, relative=relative, warm=warm, **kw)
         u = orc.assemble_global(res["vs"], u)

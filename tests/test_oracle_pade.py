@@ -128,3 +128,27 @@ def test_edge_operator_is_the_one_dimensional_problem():
         ref = (2j / pb.dt - 4 * 0.5 + 0.7 + ds) * (My @ f)
         errs.append(np.abs(D @ f - ref).max() / np.abs(ref).max())
     assert errs[1] < errs[0] / 3.5 and errs[2] < errs[1] / 3.5
+
+
+FULL = pytest.mark.skipif(__import__("os").environ.get("OSM_FULL_PINS") != "1",
+                          reason="minutes per entry; set OSM_FULL_PINS=1")
+
+
+@FULL
+@pytest.mark.slow
+@pytest.mark.parametrize("N,algo,paper", [(2, "classical", 18), (32, "classical", 18),
+                                          (2, "precond", 6)])
+def test_first_step_counts_mesh1(N, algo, paper):
+    """Section 5.1.2, Table Niter_Time_2_32_NL_abc2p: S_pade^m on the first
+    mesh, zero start, 18 classical and 6 preconditioned iterations for every
+    N.  The paper does not state m; with m = 6 the classical count is 19 for
+    N = 2 and for N = 32 (m = 5: 22, m = 7: 16) and the preconditioned one
+    is 5 for N = 2."""
+    from workloads import nls_mesh1
+    wl = nls_mesh1(N, 0.0)
+    pb = wl.problems[0].replace(tc="pade", pade_m=6, p=0.0, p_bc=0.0)
+    orc = PadeSchwarz(pb, wl.V[0], tol_q=1e-13)
+    g0 = np.zeros((2 * (N - 1), pb.ncy + 1), complex)
+    r = (orc.classical(wl.u0[0], g0, tol=1e-10) if algo == "classical"
+         else orc.precond(wl.u0[0], g0, tol=1e-10))
+    assert abs(r["k"] - paper) <= 0.2 * paper, r["k"]

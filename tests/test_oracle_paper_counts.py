@@ -70,9 +70,11 @@ def test_table_entries_zero_start(N, p, algo, paper):
 
 @FULL
 @pytest.mark.slow
-def test_preconditioned_count_from_a_random_start():
-    """The preconditioned count does not depend on the start (6 in every
-    column of the table); the classical count from a random start depends
-    on the random vector's distribution, which the paper does not state."""
-    k = first_step_count(2, 15.0, "precond", start=1)
-    assert within(k, 6), k
+@pytest.mark.parametrize("algo,paper", [("classical", 227), ("precond", 6)])
+def test_counts_from_a_random_start(algo, paper):
+    """The random column of the table at p = 15, N = 2.  The paper does not
+    state the random vector's distribution; with real and imaginary parts
+    uniform on [0, 1) (PETSc's default for complex vectors) the oracle takes
+    226 classical iterations against the printed 227."""
+    k = first_step_count(2, 15.0, algo, start=1)
+    assert within(k, paper), k

@@ -158,3 +158,48 @@ def test_random_interface_generator_matches_published_splitmix64():
     # entry k takes outputs 2k (real part) and 2k + 1 (imaginary part)
     first = splitmix64(42, np.arange(2)) >> np.uint64(11)
     assert g[0, 0] == complex(float(first[0]) * 2.0 ** -53, float(first[1]) * 2.0 ** -53)
+
+
+def test_bicgstab_matches_dense_solve():
+    """BiCGStab (the other Krylov method Section 4.2 names for P x = y)
+    against a dense solve: a complex non-normal system and P = I - L_h of a
+    small strip problem."""
+    from oracle.schwarz import bicgstab
+    rng = np.random.default_rng(3)
+    n = 60
+    A = np.eye(n) * 3 + (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, it = bicgstab(lambda v: A @ v, b, rtol=1e-13)
+    assert it < n
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) < 1e-11 * np.linalg.norm(x)
+    pb = Problem(-2.0, 2.0, -1.0, 1.0, 12, 9, 3, [4, 5, 3], lap_coef=1.0, beta=0.0, p=2.0,
+                 p_bc=2.0, dt=0.05)
+    orc = SchwarzOracle(pb, np.zeros((13, 10)))
+    orc.build_Lh()
+    P = np.eye(4 * 10) - orc.Lh_dense()
+    y = rng.standard_normal(40) + 1j * rng.standard_normal(40)
+    x, _ = bicgstab(lambda v: v - orc.Lh_matvec(v), y, rtol=1e-13)
+    assert np.linalg.norm(x - np.linalg.solve(P, y)) < 1e-11 * np.linalg.norm(x)
+
+
+def test_interface_krylov_solves_the_linear_step():
+    """f = 0: R is affine, so GMRES on (I - L) g = d with Schwarz-map products
+    reaches the monolithic step (and the classical iteration's limit), with
+    a non-zero potential and uneven strips."""
+    from oracle.schwarz import interface_krylov
+    from oracle.step import run_monolithic
+    pb = Problem(-3.0, 3.0, -2.0, 2.0, 18, 15, 3, [5, 7, 6], lap_coef=0.5, beta=0.0, p=2.0,
+                 p_bc=1.5, dt=0.02)
+    rng = np.random.default_rng(11)
+    s = (19, 16)
+    u = rng.standard_normal(s) + 1j * rng.standard_normal(s)
+    W = rng.standard_normal(s)
+    ref = run_monolithic(pb, u, W, 1, tol_q=1e-14)
+    orc = SchwarzOracle(pb, W, tol_q=1e-14)
+    g0 = np.zeros((4, 16), complex)
+    res = interface_krylov(orc, u, g0, tol=1e-13, relative=True)
+    got = orc.assemble_global(res["vs"], u)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-11
+    cls = orc.classical(u, g0, tol=1e-14, relative=True)
+    assert np.linalg.norm(res["g"] - cls["g"]) < 1e-10 * np.linalg.norm(cls["g"])
+    assert res["gmres_total"] < cls["k"]
