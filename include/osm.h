@@ -58,7 +58,18 @@ typedef enum {
 } osm_status;
 
 typedef enum { OSM_TC_ROBIN = 0, OSM_TC_PADE = 1 } osm_tc;
-typedef enum { OSM_CLASSICAL = 0, OSM_PRECOND = 1 } osm_algo;
+typedef enum {
+    OSM_CLASSICAL = 0,          /* g <- R(g) (eqs. fluxlr, AlgoGraph)              */
+    OSM_PRECOND = 1,            /* g <- g - P^{-1}(g - R(g)) (eq. algo_pd)         */
+    OSM_INTERFACE_KRYLOV = 2    /* f = 0 only: R is affine, R(g) = L g + d, and the
+                                   interface problem (I - L) g = d (eq.
+                                   interfacepb_d) is solved by restarted GMRES
+                                   whose every product is one Schwarz map (all
+                                   strip solves); stats.k counts Schwarz maps,
+                                   stats.gmres_total GMRES iterations; stopping
+                                   rule ||residual|| < tol_k (x ||d|| when
+                                   tol_k_relative)                              */
+} osm_algo;
 typedef enum { OSM_FP64 = 0, OSM_C32_REFINE = 1 } osm_prec;
 typedef enum {
     OSM_IFACE_R = 0,          /* g_out = R(g_in): the nonlinear Schwarz map      */
@@ -77,7 +88,11 @@ typedef struct {
     double lap_coef;              /* c in i u_t + c Lap u + V u + f(u) u = 0:
                                      1 (NLS) or 1/2 (GPE, Section 5.2)            */
     double beta;                  /* f(u) = beta |u|^2, sign as in eq. Sch        */
-    int32_t tc;                   /* osm_tc; only OSM_TC_ROBIN is built            */
+    int32_t tc;                   /* osm_tc: OSM_TC_ROBIN, or OSM_TC_PADE for the
+                                     absorbing condition S_pade^m of eq. TCS (with
+                                     eq. TCS_phi) on every interface and on the
+                                     physical x-edges (eq. BC with eq. BCS2p);
+                                     p and p_bc are then not used                 */
     double p;                     /* Robin transmission parameter, S = -ip, p > 0  */
     double p_bc;                  /* Robin parameter on the physical x-edges
                                      (the paper uses p_bc = p; 0 = Neumann)        */
@@ -85,6 +100,12 @@ typedef struct {
     double omega, vxx, vyy;       /* rotating-frame potential (Section 5.2.1):
                                      V(x,y) = vxx x^2 + vyy y^2 seen at A(t) x~;
                                      used only by osm_factor_rotating              */
+    int32_t pade_m;               /* OSM_TC_PADE: number of terms m (1 .. 512) of
+                                     a_s = e^{i theta/2} / (m cos^2((2s-1)pi/(4m))),
+                                     d_s = e^{i theta} tan^2((2s-1)pi/(4m)),
+                                     s = 1 .. m (the sums of eq. TCS start at 1)   */
+    double pade_theta;            /* branch-cut rotation theta in (0, pi); the
+                                     paper takes pi/4                              */
 } osm_problem;
 
 typedef struct {
@@ -95,7 +116,15 @@ typedef struct {
                                      (paper: 1e-10 absolute, Section 5)            */
     int32_t tol_k_relative;       /* 1: tol_k * ||g^{k+1}||_2 instead             */
     int32_t max_k;
-    double tol_q;                 /* fixed point: ||dzeta|| <= tol_q ||zeta||      */
+    double tol_q;                 /* fixed point: ||dzeta|| <= tol_q ||zeta||.  The
+                                     fixed point of eq. localpbrobin is run in
+                                     residual form, zeta <- zeta + K(W)^{-1} (F -
+                                     K(W + beta|zeta|^2) zeta), with K(W) factored
+                                     once per W_n: with an exact K(W)^{-1} this is
+                                     the nonlinearity-on-the-right form the paper
+                                     writes for S_pade (eq. NproblemSPNL), and it
+                                     has the fixed point of eq. NproblemRobinNL.
+                                     The form is fixed; there is no switch.      */
     int32_t max_q;
     int32_t fixed_k, fixed_q;     /* > 0: run exactly that many iterations         */
     int32_t warm_start;           /* 1: each fixed point starts from the previous
@@ -136,6 +165,20 @@ typedef struct {
                                      ||zeta^1 - zeta^0|| over the strips measured
                                      in the step (used only while r < 1/2); the
                                      converged answer is unchanged              */
+    int32_t g1_init;              /* first step's interface start g_1^0 (Section 5,
+                                     initial vectors): 0 = zero; 1 = seeded random,
+                                     entry k of the interface array (row-major) is
+                                     u(2k) + i u(2k+1) with u(j) uniform on [0, 1)
+                                     from the (j+1)-th output of SplitMix64
+                                     seeded with `seed` (the top 53 bits times
+                                     2^-53).  Instance b of a batch uses seed + b. */
+    uint64_t seed;
+    int32_t krylov;               /* solver of P x = y in OSM_PRECOND (Section 4.2
+                                     names GMRES or BiCGStab): 0 = restarted
+                                     GMRES, 1 = BiCGStab (needs gmres_restart >= 4,
+                                     its work vectors share the GMRES basis);
+                                     stats.gmres_total then counts BiCGStab
+                                     iterations                                   */
 } osm_options;
 
 typedef struct {

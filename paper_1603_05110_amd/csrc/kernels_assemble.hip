@@ -26,7 +26,9 @@ __global__ void coef_kernel(Phys P, const StripMeta *strips, const int *line_str
         double2 dv = cd(0.0, 0.0), uv = cd(0.0, 0.0);
         if (b >= 0 && b < ny) {
             KParts k = kparts(i, a, i, b, s.nx, ny, P.hx, P.hy, phi);
-            dv = cd(-P.c * k.s + k.w, (2.0 / P.dt) * k.m + P.c * (s.pl * k.edge_l + s.pr * k.edge_r));
+            // + i c (pl + i pl_im) M^Gamma_l + i c (pr + i pr_im) M^Gamma_r
+            dv = cd(-P.c * k.s + k.w - P.c * (s.pl_im * k.edge_l + s.pr_im * k.edge_r),
+                    (2.0 / P.dt) * k.m + P.c * (s.pl * k.edge_l + s.pr * k.edge_r));
             if (i + 1 < s.nx) {
                 KParts ku = kparts(i, a, i + 1, b, s.nx, ny, P.hx, P.hy, phi);
                 uv = cd(-P.c * ku.s + ku.w, (2.0 / P.dt) * ku.m);
@@ -44,12 +46,13 @@ __global__ void coef_kernel(Phys P, const StripMeta *strips, const int *line_str
 // K_j(W)^{-1}(F - M_{beta|zeta|^2} zeta): the paper's fixed-point update.
 __global__ __launch_bounds__(256) void residual_kernel(Phys P, const StripMeta *strips, const int *line_strip,
                                 const double *W, const double2 *u_old, const double2 *zeta,
-                                const double2 *g, double2 *res, const StepCtl *c) {
+                                const double2 *g, double2 *res, const StepCtl *c,
+                                const double2 *psi) {
     if (c && fp_idle(c)) return;
     int L = blockIdx.y;
     int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= P.ny) return;
-    res[(long)L * P.ny + a] = residual_at(P, strips, line_strip, W, u_old, zeta, g, L, a);
+    res[(long)L * P.ny + a] = residual_at(P, strips, line_strip, W, u_old, zeta, g, L, a, psi);
 }
 
 __global__ void copy_u_kernel(Phys P, const StripMeta *strips, const int *line_strip,
@@ -85,9 +88,10 @@ __global__ void strip_sums_kernel(Phys P, const StripMeta *strips, const double 
 
 // Flux update of every trace (eq. fluxlr), per-trace partial norms.
 __global__ void flux_kernel(Phys P, const StripMeta *strips, const double2 *g,
-                            const double2 *v, double2 *gn, double *part, const StepCtl *c) {
+                            const double2 *v, double2 *gn, double *part, const StepCtl *c,
+                            const double2 *psi) {
     if (c && (!c->q_conv || c->r_done || c->k_done || c->bad)) return;
-    flux_trace(P, strips, g, v, gn, part, blockIdx.x);
+    flux_trace(P, strips, g, v, gn, part, blockIdx.x, psi);
 }
 
 // u_n = 2 vbar - u_{n-1} on every global node.
@@ -197,9 +201,9 @@ hipError_t launch_coef(hipStream_t st, const Phys &P, const StripMeta *strips,
 hipError_t launch_residual(hipStream_t st, const Phys &P, const StripMeta *strips,
                            const int *line_strip, const double *W, const double2 *u_old,
                            const double2 *zeta, const double2 *g, double2 *res,
-                           const StepCtl *c) {
+                           const StepCtl *c, const double2 *psi) {
     hipLaunchKernelGGL(residual_kernel, node_grid(P.ny, P.lt), dim3(256), 0, st, P, strips,
-                       line_strip, W, u_old, zeta, g, res, c);
+                       line_strip, W, u_old, zeta, g, res, c, psi);
     return hipGetLastError();
 }
 
@@ -226,9 +230,9 @@ hipError_t launch_strip_sums(hipStream_t st, const Phys &P, const StripMeta *str
 
 hipError_t launch_flux(hipStream_t st, const Phys &P, const StripMeta *strips,
                        const double2 *g, const double2 *v, double2 *gn, double *part,
-                       const StepCtl *c) {
+                       const StepCtl *c, const double2 *psi) {
     hipLaunchKernelGGL(flux_kernel, dim3(2 * (P.nsub - 1)), dim3(256), 0, st, P, strips, g, v,
-                       gn, part, c);
+                       gn, part, c, psi);
     return hipGetLastError();
 }
 

@@ -108,6 +108,32 @@ __global__ void precond_finalize_kernel(const double *part, int nb, StepCtl *c,
 
 static inline dim3 vgrid(long n) { return dim3((unsigned)((n + 255) / 256)); }
 
+// Random first interface vector (Section 5, initial vectors).  SplitMix64
+// (Steele, Lea and Flood, "Fast splittable pseudorandom number generators",
+// 2014): state_j = seed + (j + 1) * 0x9E3779B97F4A7C15, output = the mix of
+// state_j by two xor-shift-multiply rounds and a final xor-shift, so output
+// j is computed on its own (counter-based); u(j) = (output >> 11) * 2^-53.
+namespace {
+__device__ __forceinline__ double splitmix_unit(uint64_t seed, uint64_t j) {
+    uint64_t z = seed + (j + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-53;
+}
+
+__global__ void random_interface_kernel(double2 *g, long n, uint64_t seed) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) g[k] = cd(splitmix_unit(seed, 2 * (uint64_t)k), splitmix_unit(seed, 2 * (uint64_t)k + 1));
+}
+}  // namespace
+
+hipError_t launch_random_interface(hipStream_t st, double2 *g, long n, uint64_t seed) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(random_interface_kernel, vgrid(n), dim3(256), 0, st, g, n, seed);
+    return hipGetLastError();
+}
+
 hipError_t launch_step_init(hipStream_t st, StepCtl *c, const StepCfg &cfg) {
     hipLaunchKernelGGL(step_init_kernel, dim3(1), dim3(64), 0, st, c, cfg);
     return hipGetLastError();

@@ -69,6 +69,17 @@ struct osm_handle {
     double2 *gH = nullptr, *gcs = nullptr, *gsn = nullptr, *ge = nullptr, *gy = nullptr;
     double2 *gdots1 = nullptr, *gdots2 = nullptr;
     double2 *gmv = nullptr;        // partials of the fused matvec (may stay null)
+    // S_pade^m (tc = OSM_TC_PADE): coefficients, LU of the edge operators
+    // (2 N edges + the free edge), edge functions and their psi, dense
+    // edge blocks G (pm_eb edges at a time) and the free edge's G and 2i G
+    int pm = 0, pm_eb = 0;
+    double2 pm_sa = {0.0, 0.0};     // sum_s a_s
+    double2 *pad = nullptr, *psub = nullptr, *pcp = nullptr, *pinv = nullptr;
+    double2 *pphi = nullptr, *pz = nullptr, *pwork = nullptr, *ppsi = nullptr;
+    double2 *pG = nullptr, *pX = nullptr, *pGf = nullptr, *pGf2 = nullptr;
+    int *pedge = nullptr;           // 0 .. 2N (the last: the free edge)
+    BicgState *bstate = nullptr;   // BiCGStab scalars (osm_options.krylov = 1)
+    double *bpart = nullptr;       // BiCGStab dot-product partials
     int gmv_blocks = 0;            // workgroups gmv holds partials for
     LhClass *lh_tab_d = nullptr;   // work plan of the register-resident L_h kernel
     int *lh_list_d = nullptr;
@@ -194,12 +205,18 @@ std::string validate(const osm_problem *p, const osm_options *o) {
     if (p->ncx < 4 || p->ncy < 2) return "mesh too small (ncx >= 4, ncy >= 2)";
     if (p->ncy + 1 > 4096) return "ncy + 1 > 4096 not supported";
     if (p->nsub < 2) return "nsub must be >= 2";
-    if (p->tc != OSM_TC_ROBIN) return "only the Robin transmission condition is built";
-    if (!(p->p > 0)) return "Robin parameter p must be > 0";
-    if (!(p->p_bc >= 0)) return "p_bc must be >= 0";
+    if (p->tc != OSM_TC_ROBIN && p->tc != OSM_TC_PADE) return "tc must be OSM_TC_ROBIN or OSM_TC_PADE";
+    if (p->tc == OSM_TC_ROBIN) {
+        if (!(p->p > 0)) return "Robin parameter p must be > 0";
+        if (!(p->p_bc >= 0)) return "p_bc must be >= 0";
+    } else {
+        if (p->pade_m < 1 || p->pade_m > 512) return "pade_m must be in [1, 512]";
+        if (!(p->pade_theta > 0 && p->pade_theta < M_PI)) return "pade_theta must be in (0, pi)";
+    }
     if (!(p->dt > 0) || !(p->lap_coef > 0)) return "dt and lap_coef must be > 0";
     if (o->solve_shape < 0 || o->solve_shape > 8) return "solve_shape must be 0 (tuned) or 1..8";
     if (o->q_estimate < 0 || o->q_estimate > 1) return "q_estimate must be 0 or 1";
+    if (o->g1_init < 0 || o->g1_init > 1) return "g1_init must be 0 (zero) or 1 (seeded random)";
     if (!isfinite(p->beta)) return "beta not finite";
     std::vector<int> c = strip_cells_of(p);
     if ((int)c.size() != p->nsub) return "strip_cells NULL but ncx not divisible by nsub";
@@ -209,11 +226,19 @@ std::string validate(const osm_problem *p, const osm_options *o) {
         sum += v;
     }
     if (sum != p->ncx) return "strip_cells do not sum to ncx";
-    if (o->algo != OSM_CLASSICAL && o->algo != OSM_PRECOND) return "bad algo";
+    if (o->algo != OSM_CLASSICAL && o->algo != OSM_PRECOND && o->algo != OSM_INTERFACE_KRYLOV)
+        return "bad algo";
+    if (o->algo == OSM_INTERFACE_KRYLOV && p->beta != 0.0)
+        return "OSM_INTERFACE_KRYLOV needs f = 0 (beta = 0): only then is R affine";
+    if (o->algo == OSM_INTERFACE_KRYLOV && (o->fixed_k > 0 || o->guess > 1))
+        return "OSM_INTERFACE_KRYLOV takes neither fixed_k nor a predicted start";
+    if (o->krylov < 0 || o->krylov > 1) return "krylov must be 0 (GMRES) or 1 (BiCGStab)";
+    if (o->algo == OSM_PRECOND && o->krylov == 1 && o->gmres_restart < 4)
+        return "BiCGStab keeps its 6 work vectors in the GMRES basis: gmres_restart >= 4";
     if (o->prec != OSM_FP64 && o->prec != OSM_C32_REFINE) return "bad prec";
     if (o->max_k < 1 && o->fixed_k < 1) return "max_k must be >= 1";
     if (o->max_q < 1 && o->fixed_q < 1) return "max_q must be >= 1";
-    if (o->algo == OSM_PRECOND && (o->gmres_restart < 1 || o->gmres_restart > 200))
+    if (o->algo != OSM_CLASSICAL && (o->gmres_restart < 1 || o->gmres_restart > 200))
         return "gmres_restart must be in [1, 200]";
     if (o->guess < 0 || o->guess > 3) return "guess must be 0, 1, 2 or 3";
     return "";
@@ -221,6 +246,9 @@ std::string validate(const osm_problem *p, const osm_options *o) {
 
 struct Sizes {
     long n, N, Lt, nglob, ng, maxnx, ncls, m;
+    long pm;    // S_pade^m terms (0 for Robin)
+    long peb;   // S_pade^m edges per batch of the dense edge blocks
+    int lh;     // L_h and its kernels are built (OSM_PRECOND)
     int fp32;
     int sym;    // the upper-triangle solve kernels are available (partials buffer)
 };
@@ -245,7 +273,11 @@ Sizes sizes_of(const osm_problem *p, const osm_options *o) {
         cls.emplace(std::make_tuple(c[j] + 1, pl, pr), 0);
     }
     s.ncls = (long)cls.size();
-    s.m = o->algo == OSM_PRECOND ? o->gmres_restart : 0;
+    s.m = o->algo != OSM_CLASSICAL ? o->gmres_restart : 0;
+    s.lh = o->algo == OSM_PRECOND;
+    s.pm = p->tc == OSM_TC_PADE ? p->pade_m : 0;
+    // dense edge blocks in batches of at most 256 MB (at least one edge)
+    s.peb = s.pm ? std::max(1L, std::min(2 * s.N, (256L << 20) / (s.n * s.n * 16))) : 0;
     s.fp32 = o->prec == OSM_C32_REFINE;
     s.sym = sym_eligible(s.n, s.fp32);
     return s;
@@ -268,9 +300,19 @@ uint64_t device_bytes(const Sizes &s) {
     b += (uint64_t)(s.N - 1) * s.n * 13 * 4 + (uint64_t)(s.N - 1) * 8;  // guess features
     b += 3ull * s.ng * 16 + 2ull * ((s.ng + 255) / 256) * 8;           // guess history
     if (s.m > 0) {
-        b += 4ull * s.ncls * s.n * s.n * 16;            // L_h blocks
         b += (uint64_t)(s.m + 2) * s.ng * 16;           // Krylov basis
         b += 2ull * 256 * (s.m + 1) * 16;               // Gram-Schmidt partials
+        b += (uint64_t)bicg_partials() * 8 + sizeof(BicgState);
+    }
+    if (s.pm) {
+        b += 3ull * (2 * s.N + 1) * s.pm * s.n * 16;    // LU of the edge operators
+        b += 3ull * 2 * s.N * s.pm * s.n * 16;          // edge functions, z, work
+        b += 2ull * s.N * s.n * 16 + 2 * s.pm * 16 + (2 * s.N + 1) * 4;
+        b += 2ull * s.peb * s.n * s.n * 16;             // dense edge blocks, scratch
+        if (s.lh) b += 2ull * s.n * s.n * 16;           // free edge blocks (L_h)
+    }
+    if (s.lh) {
+        b += 4ull * s.ncls * s.n * s.n * 16;            // L_h blocks
         b += (uint64_t)lh_fused_blocks_bound((int)s.n, (int)s.N, (int)s.ncls) * (s.m + 1) * 16;
         b += (uint64_t)s.ncls * sizeof(LhClass) + (uint64_t)s.N * 4;   // L_h kernel plan
         b += 2ull * s.maxnx * s.n * s.n * 16 + (uint64_t)s.n * s.n * 16;  // L_h build temporaries
@@ -317,14 +359,8 @@ osm_status fslot(osm_handle *h, double flops, hipEvent_t *e0, hipEvent_t *e1) {
         if (s != OSM_OK) return s;
     }
     int slot = h->fprof_used++;
-    if ((int)h->fevs.size() < 2 * (slot + 1)) {
-        hipEvent_t a0, a1;
-        HIPCHK(h, hipEventCreate(&a0));
-        HIPCHK(h, hipEventCreate(&a1));
-        h->fevs.push_back(a0);
-        h->fevs.push_back(a1);
-        h->fflops.push_back(0.0);
-    }
+    if ((int)h->fevs.size() < 2 * (slot + 1))
+        return fail(h, OSM_ESTATE, "timing events not created (osm_kernel_timing)");
     h->fflops[slot] = flops;
     *e0 = h->fevs[2 * slot];
     *e1 = h->fevs[2 * slot + 1];
@@ -335,7 +371,7 @@ template <typename T>
 osm_status factor_chain(osm_handle *h, typename cplx_of<T>::type *F, const double2 *Dc,
                         const double2 *Uc, int nsteps, const std::vector<int> &batch,
                         const std::vector<int> &off, const int *lines_d, const int *kind_d,
-                        bool full) {
+                        bool full, int pade_mode = 0) {
     typedef typename cplx_of<T>::type T2;
     int n = h->n;
     T2 *R = (T2 *)h->Rbuf, *C = (T2 *)h->Cbuf, *Pb = (T2 *)h->Pbuf;
@@ -345,6 +381,23 @@ osm_status factor_chain(osm_handle *h, typename cplx_of<T>::type *F, const doubl
         const int *lines = lines_d + off[i];
         const int *kind = kind_d + off[i];
         HIPCHK(h, launch_schur<T>(h->st, n, F, lines, kind, bt, Dc, Uc));
+        // S_pade^m: the eliminated edge functions' dense block on the edge
+        // lines, added to their Schur complements before the inversion.
+        // Mode 1 (twisted factor): the first step factors exactly the 2 N
+        // edge lines, edge b on batch entry b.  Mode 2 (one strip's chain,
+        // free problem): its first and last lines, with the free edge.
+        if (pade_mode == 1 && i == 0) {
+            for (int e0 = 0; e0 < 2 * h->N; e0 += h->pm_eb) {
+                const int cnt = std::min(h->pm_eb, 2 * h->N - e0);
+                HIPCHK(h, launch_pade_G(h->st, n, h->P.hy, e0, cnt, h->pm, h->pad, h->psub,
+                                        h->pcp, h->pinv, h->pX, h->pG, cd(1.0, 0.0)));
+                HIPCHK(h, launch_pade_edge_add<T>(h->st, n, F, lines + e0, h->pedge + e0, cnt,
+                                                  e0, h->pG, h->P.c, h->P.hy));
+            }
+        }
+        if (pade_mode == 2 && (i == 0 || i == nsteps - 1))
+            HIPCHK(h, launch_pade_edge_add<T>(h->st, n, F, lines, h->pedge + 2 * h->N, bt,
+                                              2 * h->N, h->pGf, h->P.c, h->P.hy));
         for (int kb = 0; kb < sweep_passes(n); ++kb) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (h->prof) {
@@ -361,14 +414,18 @@ osm_status factor_chain(osm_handle *h, typename cplx_of<T>::type *F, const doubl
 osm_status do_factor(osm_handle *h) {
     HIPCHK(h, launch_coef(h->st, h->P, h->strips_d, h->line_strip_d, h->W_d, 0, h->Dc, h->Uc, 0,
                           h->Lt));
+    if (h->pm)   // LU of every edge operator D_{e,s}(W_n)
+        HIPCHK(h, launch_pade_lu(h->st, h->P, h->strips_d, h->W_d, 2 * h->N, 0, h->pm, h->pad,
+                                 h->psub, h->pcp, h->pinv));
     osm_status s;
     int depth = (int)h->step_batch.size();
+    const int pmode = h->pm ? 1 : 0;
     if (h->fp32)
         s = factor_chain<float>(h, (float2 *)h->F, h->Dc, h->Uc, depth, h->step_batch,
-                                h->step_off, h->step_lines_d, h->step_first_d, true);
+                                h->step_off, h->step_lines_d, h->step_first_d, true, pmode);
     else
         s = factor_chain<double>(h, (double2 *)h->F, h->Dc, h->Uc, depth, h->step_batch,
-                                 h->step_off, h->step_lines_d, h->step_first_d, true);
+                                 h->step_off, h->step_lines_d, h->step_first_d, true, pmode);
     if (s != OSM_OK) return s;
     h->factored = true;
     return OSM_OK;
@@ -439,13 +496,8 @@ osm_status do_solve(osm_handle *h, const double2 *b, double2 *x, const StepCtl *
             if (s != OSM_OK) return s;
         }
         int slot = h->prof_used++;
-        if ((int)h->evs.size() < 2 * (slot + 1)) {
-            hipEvent_t a0, a1;
-            HIPCHK(h, hipEventCreate(&a0));
-            HIPCHK(h, hipEventCreate(&a1));
-            h->evs.push_back(a0);
-            h->evs.push_back(a1);
-        }
+        if ((int)h->evs.size() < 2 * (slot + 1))
+            return fail(h, OSM_ESTATE, "timing events not created (osm_kernel_timing)");
         e0 = h->evs[2 * slot];
         e1 = h->evs[2 * slot + 1];
         a.ran = h->ran_d + slot;
@@ -474,9 +526,17 @@ osm_status apply_R(osm_handle *h, const double2 *u, const double2 *g_in, double2
     std::vector<double> sn(3 * h->N);
     for (q = 1; q <= nq; ++q) {
         HIPCHK(h, launch_residual(h->st, h->P, h->strips_d, h->line_strip_d, h->W_d, u, h->zeta,
-                                  g_in, h->res));
+                                  g_in, h->res, nullptr, h->ppsi));
+        if (h->pm)
+            HIPCHK(h, launch_pade_fp_residual(h->st, h->P, h->strips_d, h->W_d, 2 * h->N, h->pm,
+                                              h->pad, h->psub, h->pcp, h->pinv, h->zeta, h->pphi,
+                                              h->pz, h->res, nullptr));
         osm_status s = do_solve(h, h->res, h->delta);
         if (s != OSM_OK) return s;
+        if (h->pm)
+            HIPCHK(h, launch_pade_fp_update(h->st, h->P, h->strips_d, 2 * h->N, h->pm, h->pad,
+                                            h->psub, h->pcp, h->pinv, h->delta, h->pz, h->pphi,
+                                            h->pwork, h->ppsi, nullptr));
         HIPCHK(h, launch_update_norms(h->st, h->P, h->zeta, h->delta, h->line_part));
         HIPCHK(h, launch_strip_sums(h->st, h->P, h->strips_d, h->line_part, h->strip_norms));
         HIPCHK(h, hipMemcpyAsync(sn.data(), h->strip_norms, sizeof(double) * 3 * h->N,
@@ -495,7 +555,8 @@ osm_status apply_R(osm_handle *h, const double2 *u, const double2 *g_in, double2
     if (!conv) return fail(h, OSM_ENOCONV, "fixed point did not converge within max_q");
     *q_out = q;
     int nt = 2 * (h->N - 1);
-    HIPCHK(h, launch_flux(h->st, h->P, h->strips_d, g_in, h->zeta, g_out, h->trace_part));
+    HIPCHK(h, launch_flux(h->st, h->P, h->strips_d, g_in, h->zeta, g_out, h->trace_part,
+                          nullptr, h->ppsi));
     HIPCHK(h, launch_sum(h->st, h->trace_part, nt, 2, h->scal));
     double sc[2];
     HIPCHK(h, hipMemcpyAsync(sc, h->scal, sizeof(sc), hipMemcpyDeviceToHost, h->st));
@@ -521,7 +582,34 @@ double dev_norm(osm_handle *h, const double2 *x, long n, osm_status *st) {
 // Gram-Schmidt applied twice, FP64.  The Arnoldi loop, the Givens rotations
 // and the convergence test run on the device; the host enqueues chunks of
 // iterations and synchronises once per chunk.
+// x = (I - L_h)^{-1} y by BiCGStab (osm_options.krylov = 1), scalars on the
+// device, the host checking every few iterations.
+osm_status bicgstab_solve(osm_handle *h, const double2 *y, double2 *x, int *iters) {
+    const long n = h->ng;
+    *iters = 0;
+    GmresCtl c;
+    memset(&c, 0, sizeof(c));
+    c.tol = h->opt.tol_gmres;
+    c.done = 1;
+    HIPCHK(h, hipMemcpyAsync(h->gctl, &c, sizeof(c), hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, launch_bicg_start(h->st, n, y, x, h->Vb, h->bpart, h->bstate, h->gctl, nullptr));
+    while (true) {
+        for (int i = 0; i < 6; ++i)
+            HIPCHK(h, launch_bicg_iteration(h->st, h->P, h->strips_d, h->ncls, h->lhp, h->LH, n,
+                                            h->Vb, x, h->bpart, h->bstate, h->gctl, nullptr,
+                                            h->opt.max_gmres));
+        HIPCHK(h, hipMemcpyAsync(&c, h->gctl, sizeof(c), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(h, hipStreamSynchronize(h->st));
+        if (c.bad) return fail(h, OSM_ENONFINITE, "BiCGStab broke down or met a non-finite value");
+        if (c.finished) break;
+    }
+    *iters = c.total;
+    if (!c.conv) return fail(h, OSM_ENOCONV, "BiCGStab did not converge within max_gmres");
+    return OSM_OK;
+}
+
 osm_status gmres(osm_handle *h, const double2 *y, double2 *x, int *iters) {
+    if (h->opt.krylov == 1) return bicgstab_solve(h, y, x, iters);
     const osm_options &o = h->opt;
     long n = h->ng;
     int m = h->m;
@@ -598,12 +686,26 @@ osm_status read_ctl(osm_handle *h, StepCtl *c, GmresCtl *g) {
     return OSM_OK;
 }
 
+// Edge functions back to phi^0 = 0 (with zeta^0 = u_{n-1}, eq. localpbS2p).
+hipError_t pade_reset(osm_handle *h, const StepCtl *c) {
+    const long ne = 2L * h->N;
+    return launch_pade_reset(h->st, ne * h->pm * h->n, h->pphi, ne * h->n, h->ppsi, c);
+}
+
 osm_status fp_chunk(osm_handle *h, const double2 *u, int nq) {
     for (int i = 0; i < nq; ++i) {
         HIPCHK(h, launch_residual(h->st, h->P, h->strips_d, h->line_strip_d, h->W_d, u, h->zeta,
-                                  h->g, h->res, h->sctl));
+                                  h->g, h->res, h->sctl, h->ppsi));
+        if (h->pm)
+            HIPCHK(h, launch_pade_fp_residual(h->st, h->P, h->strips_d, h->W_d, 2 * h->N, h->pm,
+                                              h->pad, h->psub, h->pcp, h->pinv, h->zeta, h->pphi,
+                                              h->pz, h->res, h->sctl));
         osm_status s = do_solve(h, h->res, h->delta, h->sctl);
         if (s != OSM_OK) return s;
+        if (h->pm)
+            HIPCHK(h, launch_pade_fp_update(h->st, h->P, h->strips_d, 2 * h->N, h->pm, h->pad,
+                                            h->psub, h->pcp, h->pinv, h->delta, h->pz, h->pphi,
+                                            h->pwork, h->ppsi, h->sctl));
         HIPCHK(h, launch_update_norms(h->st, h->P, h->zeta, h->delta, h->line_part, h->sctl));
         HIPCHK(h, launch_q_check(h->st, h->P, h->strips_d, h->line_part, h->sctl, h->qd_prev));
     }
@@ -618,9 +720,20 @@ osm_status gmres_iters(osm_handle *h, int j0, int j1) {
     return OSM_OK;
 }
 
+// BiCGStab iterations of the preconditioned update, each guarded on the
+// device by the step and Krylov controls.
+osm_status bicg_iters(osm_handle *h, int count) {
+    for (int i = 0; i < count; ++i)
+        HIPCHK(h, launch_bicg_iteration(h->st, h->P, h->strips_d, h->ncls, h->lhp, h->LH, h->ng,
+                                        h->Vb, h->gx, h->bpart, h->bstate, h->gctl, h->sctl,
+                                        h->opt.max_gmres));
+    return OSM_OK;
+}
+
 osm_status after_fixed_point(osm_handle *h, int gchunk) {
     long ng = h->ng;
-    HIPCHK(h, launch_flux(h->st, h->P, h->strips_d, h->g, h->zeta, h->gn, h->trace_part, h->sctl));
+    HIPCHK(h, launch_flux(h->st, h->P, h->strips_d, h->g, h->zeta, h->gn, h->trace_part, h->sctl,
+                          h->ppsi));
     HIPCHK(h, launch_flux_finalize(h->st, h->trace_part, 2 * (h->N - 1), h->sctl));
     if (h->opt.algo == OSM_CLASSICAL) {
         HIPCHK(h, launch_commit(h->st, ng, h->g, h->gn, h->sctl));
@@ -628,6 +741,14 @@ osm_status after_fixed_point(osm_handle *h, int gchunk) {
     }
     // y = g - R(g) (in gtmp), x = 0 (gx), GMRES on P x = y, g <- g - x
     HIPCHK(h, launch_precond_rhs(h->st, ng, h->g, h->gn, h->gtmp, h->gx, h->sctl));
+    if (h->opt.krylov == 1) {
+        HIPCHK(h, launch_bicg_start(h->st, ng, h->gtmp, h->gx, h->Vb, h->bpart, h->bstate,
+                                    h->gctl, h->sctl));
+        osm_status s = bicg_iters(h, std::max(1, gchunk / 2));
+        if (s != OSM_OK) return s;
+        HIPCHK(h, launch_precond_update(h->st, ng, h->g, h->gx, h->upd_part, h->sctl, h->gctl));
+        return OSM_OK;
+    }
     HIPCHK(h, launch_gmres_begin(h->st, ng, h->gtmp, h->gnorm_part, 1, 1.0, h->Vb, h->ge, h->m,
                                  h->gctl, h->sctl));
     osm_status s = gmres_iters(h, 0, std::min(gchunk, h->m));
@@ -670,6 +791,21 @@ osm_status gmres_continue(osm_handle *h, GmresCtl &gc, StepCtl &c) {
     return read_ctl(h, &c, &gc);
 }
 
+// BiCGStab did not finish within the first chunk: more chunks until it has
+// converged, then the update.
+osm_status bicg_continue(osm_handle *h, GmresCtl &gc, StepCtl &c) {
+    while (true) {
+        if (gc.bad) return fail(h, OSM_ENONFINITE, "BiCGStab broke down or met a non-finite value");
+        if (gc.finished && gc.conv) break;
+        if (gc.finished) return fail(h, OSM_ENOCONV, "BiCGStab did not converge within max_gmres");
+        osm_status s = bicg_iters(h, GMRES_CHUNK / 2);
+        if (s != OSM_OK) return s;
+        if ((s = read_ctl(h, &c, &gc)) != OSM_OK) return s;
+    }
+    HIPCHK(h, launch_precond_update(h->st, h->ng, h->g, h->gx, h->upd_part, h->sctl, h->gctl));
+    return read_ctl(h, &c, &gc);
+}
+
 osm_status schwarz_device(osm_handle *h, const double2 *u, osm_step_stats *S) {
     const osm_options &o = h->opt;
     StepCfg cfg;
@@ -702,9 +838,11 @@ osm_status schwarz_device(osm_handle *h, const double2 *u, osm_step_stats *S) {
         const int gchunk =
             k < (int)h->gm_chunk.size() && h->gm_chunk[k] > 0 ? h->gm_chunk[k] : GMRES_CHUNK;
         HIPCHK(h, launch_iter_reset(h->st, h->sctl, h->m > 0 ? h->gctl : nullptr));
-        if (k > 1 && !o.warm_start)
+        if (k > 1 && !o.warm_start) {
             HIPCHK(h, launch_copy_u_guarded(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta,
                                             h->sctl));
+            if (h->pm) HIPCHK(h, pade_reset(h, h->sctl));
+        }
         int nq = o.fixed_q > 0 ? o.fixed_q : std::max(1, std::min(o.max_q, h->q_chunk));
         if ((s = fp_chunk(h, u, nq)) != OSM_OK) return s;
         if ((s = after_fixed_point(h, gchunk)) != OSM_OK) return s;
@@ -723,8 +861,10 @@ osm_status schwarz_device(osm_handle *h, const double2 *u, osm_step_stats *S) {
         // iteration needed (at least 2 with the paper's test, which always
         // takes a second iterate; 1 with the error-estimate test)
         if (!c.bad && o.fixed_q <= 0) h->q_chunk = std::max(o.q_estimate ? 1 : 2, c.q_iter);
-        if (!c.bad && !cfg.classical && c.r_done == 1)
-            if ((s = gmres_continue(h, gc, c)) != OSM_OK) { fill(); return s; }
+        if (!c.bad && !cfg.classical && c.r_done == 1) {
+            s = o.krylov == 1 ? bicg_continue(h, gc, c) : gmres_continue(h, gc, c);
+            if (s != OSM_OK) { fill(); return s; }
+        }
         fill();
         if (!cfg.classical && h->m > 0) {
             // GMRES iterations left over in a chunk still cost their launches
@@ -737,6 +877,110 @@ osm_status schwarz_device(osm_handle *h, const double2 *u, osm_step_stats *S) {
         if (c.k_done) return OSM_OK;
     }
     return fail(h, OSM_ENOCONV, "Schwarz iteration did not converge within max_k");
+}
+
+// ---------------------------------------------------------------- interface Krylov (f = 0)
+// With f = 0 the Schwarz map is affine, R(g) = L g + d with d = R(0), and the
+// converged interface vector solves (I - L) g = d (eq. interfacepb_d).
+// Restarted GMRES from the start in h->g (the previous step's vector, or
+// g_1^0), every product one Schwarz map: (I - L) x = x - (R(x) - d).  The
+// Arnoldi vectors and the Gram-Schmidt passes (classical, applied twice)
+// stay on the device; the small Hessenberg problem is solved on the host.
+// Every cycle begins with the true residual R(x) - x, whose map also leaves
+// the strip solutions of R(x) in zeta for the time update.
+osm_status interface_step(osm_handle *h, const double2 *u, osm_step_stats *S) {
+    const osm_options &o = h->opt;
+    const long n = h->ng;
+    const int m = h->m;
+    double2 *V = h->Vb;                               // m + 1 basis vectors
+    double2 *w = h->Vb + (long)(m + 1) * n;
+    double2 *x = h->g, *d = h->g_pred, *Rx = h->gn, *zero = h->g_prev2;
+    int maps = 0, its = 0, qsum = 0;
+    double a2, b2;
+    int q;
+    auto map = [&](const double2 *gin) -> osm_status {
+        osm_status s = apply_R(h, u, gin, Rx, &q, &a2, &b2, o.tol_q);
+        maps += 1;
+        qsum += q;
+        return s;
+    };
+    HIPCHK(h, hipMemsetAsync(zero, 0, sizeof(double2) * n, h->st));
+    osm_status s = map(zero);
+    if (s != OSM_OK) return s;
+    HIPCHK(h, hipMemcpyAsync(d, Rx, sizeof(double2) * n, hipMemcpyDeviceToDevice, h->st));
+    const double dn = dev_norm(h, d, n, &s);
+    if (s != OSM_OK) return s;
+    const double tol = o.tol_k * (o.tol_k_relative ? std::max(dn, 1e-300) : 1.0);
+    std::vector<zc> H((size_t)(m + 1) * m), cs(m), sn(m), e(m + 1), hc(m + 1), h2(m + 1), y(m);
+    double resid = 0.0;
+    auto fill = [&]() {
+        S->k = maps;
+        S->q_total = qsum;
+        S->gmres_total = its;
+        S->refine_total = h->fp32 ? qsum : 0;
+        S->last_increment = resid;
+    };
+    while (true) {
+        // true residual r = d - (x - (R(x) - d)) = R(x) - x
+        if ((s = map(x)) != OSM_OK) { fill(); return s; }
+        HIPCHK(h, launch_axpby(h->st, n, cd(1, 0), Rx, cd(-1, 0), x, w));
+        const double beta = dev_norm(h, w, n, &s);
+        if (s != OSM_OK) return s;
+        resid = beta;
+        if (!isfinite(beta)) { fill(); return fail(h, OSM_ENONFINITE, "non-finite interface residual"); }
+        if (beta <= tol) break;
+        if (maps >= o.max_k) { fill(); return fail(h, OSM_ENOCONV, "interface GMRES: max_k Schwarz maps"); }
+        HIPCHK(h, launch_scale_copy(h->st, n, w, cd(1.0 / beta, 0), V));
+        std::fill(e.begin(), e.end(), zc(0, 0));
+        e[0] = beta;
+        int jd = 0;
+        for (int j = 0; j < m; ++j) {
+            double2 *vj = V + (long)j * n;
+            if ((s = map(vj)) != OSM_OK) { fill(); return s; }
+            HIPCHK(h, launch_axpby(h->st, n, cd(1, 0), vj, cd(-1, 0), Rx, w));
+            HIPCHK(h, launch_axpby(h->st, n, cd(1, 0), w, cd(1, 0), d, w));
+            // classical Gram-Schmidt, twice
+            for (int pass = 0; pass < 2; ++pass) {
+                HIPCHK(h, launch_multidot(h->st, n, V, j + 1, w, h->dots_part, h->nblk));
+                HIPCHK(h, launch_multidot_finalize(h->st, h->dots_part, j + 1, h->nblk, h->dots));
+                HIPCHK(h, launch_multiaxpy(h->st, n, V, j + 1, h->dots, w, 1));
+                HIPCHK(h, hipMemcpyAsync(pass ? h2.data() : hc.data(), h->dots,
+                                         sizeof(double2) * (j + 1), hipMemcpyDeviceToHost, h->st));
+            }
+            const double hn = dev_norm(h, w, n, &s);     // synchronises
+            if (s != OSM_OK) return s;
+            for (int i = 0; i <= j; ++i) hc[i] += h2[i];
+            if (!isfinite(hn)) { fill(); return fail(h, OSM_ENONFINITE, "non-finite Arnoldi vector"); }
+            if (hn > 0) HIPCHK(h, launch_scale_copy(h->st, n, w, cd(1.0 / hn, 0), V + (long)(j + 1) * n));
+            // rotations on column j, then a new one that zeroes h_{j+1,j}
+            for (int i = 0; i < j; ++i) {
+                zc t = std::conj(cs[i]) * hc[i] + std::conj(sn[i]) * hc[i + 1];
+                hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+                hc[i] = t;
+            }
+            const zc a = hc[j];
+            const double rho = std::sqrt(std::norm(a) + hn * hn);
+            cs[j] = rho > 0 ? a / rho : zc(1, 0);
+            sn[j] = rho > 0 ? zc(hn / rho, 0) : zc(0, 0);
+            hc[j] = rho;
+            for (int i = 0; i <= j; ++i) H[(size_t)j * (m + 1) + i] = hc[i];
+            e[j + 1] = -sn[j] * e[j];
+            e[j] = std::conj(cs[j]) * e[j];
+            its += 1;
+            jd = j + 1;
+            if (std::abs(e[j + 1]) <= tol || hn == 0 || maps >= o.max_k) break;
+        }
+        // y = R^{-1} e (upper triangular), x += V y
+        for (int i = jd - 1; i >= 0; --i) {
+            zc acc = e[i];
+            for (int k = i + 1; k < jd; ++k) acc -= H[(size_t)k * (m + 1) + i] * y[k];
+            y[i] = acc / H[(size_t)i * (m + 1) + i];
+        }
+        HIPCHK(h, hipMemcpyAsync(h->gy, y.data(), sizeof(double2) * jd, hipMemcpyHostToDevice, h->st));
+        HIPCHK(h, launch_multiaxpy(h->st, n, V, jd, h->gy, x, 0));
+    }
+    fill();
+    return OSM_OK;
 }
 
 // ---------------------------------------------------------------- L_h build
@@ -796,12 +1040,39 @@ osm_status build_lh(osm_handle *h) {
     for (int i = 0; i < h->maxnx; ++i) offs[i] = i;
     double p = h->prob.p, c = h->prob.lap_coef;
     osm_status s = OSM_OK;
+    if (h->pm) {
+        // the free edge (W = 0): its LU, G (added to the free strip factor's
+        // edge lines) and 2i G (the edge functions' part of each block)
+        HIPCHK(h, launch_pade_lu(h->st, h->P, h->strips_d, h->W_d, 2 * h->N, 1, h->pm, h->pad,
+                                 h->psub, h->pcp, h->pinv, 2 * h->N));
+        HIPCHK(h, launch_pade_G(h->st, n, h->P.hy, 2 * h->N, 1, h->pm, h->pad, h->psub, h->pcp,
+                                h->pinv, h->pX, h->pGf, cd(1.0, 0.0)));
+        HIPCHK(h, launch_pade_G(h->st, n, h->P.hy, 2 * h->N, 1, h->pm, h->pad, h->psub, h->pcp,
+                                h->pinv, h->pX, h->pGf2, cd(0.0, 2.0)));
+    }
+    // a block of L_h from the edge response Y: -2ip Y (Robin), or with
+    // S_pade^m 2 S Y = -2i (sum a_s) Y + 2i G Y; minus I on the input's edge
+    auto form = [&](const double2 *Yedge, int add_eye, double2 *Xout) -> osm_status {
+        if (!h->pm) {
+            HIPCHK(h, launch_lh_form(h->st, n, Yedge, -2.0 * p, add_eye, Xout));
+            return OSM_OK;
+        }
+        HIPCHK(h, launch_pade_lh_form(h->st, n, Yedge, h->pm_sa, add_eye, Xout));
+        GemmArgs<double> q;
+        q.M = n; q.N = n; q.K = n;
+        q.lda = n; q.ldb = n; q.ldc = n; q.ldd = n;
+        q.strideA = 0; q.strideB = 0; q.strideCD = 0; q.idxCD = nullptr;
+        q.mask_lo = 0; q.mask_hi = 0;
+        q.A = h->pGf2; q.B = Yedge; q.C = Xout; q.D = Xout; q.sign = 1;
+        HIPCHK(h, launch_zgemm<double>(h->st, q, 1));
+        return OSM_OK;
+    };
     for (int cl = 0; cl < h->ncls && s == OSM_OK; ++cl) {
         const StripMeta &sm = h->strips_h[rep[cl]];
         int nx = sm.nx;
         HIPCHK(h, launch_coef(h->st, h->P, h->strips_d, h->line_strip_d, nullptr, 1, fD, fU, sm.off, nx));
         s = factor_chain<double>(h, FF, fD, fU, nx, one, offs, h->ff_lines_d, h->ff_first_d,
-                                 true);
+                                 true, h->pm ? 2 : 0);
         if (s != OSM_OK) break;
         double2 *X1 = h->LH + (long)(4 * cl + 0) * nn, *X2 = h->LH + (long)(4 * cl + 1) * nn;
         double2 *X3 = h->LH + (long)(4 * cl + 2) * nn, *X4 = h->LH + (long)(4 * cl + 3) * nn;
@@ -819,7 +1090,7 @@ osm_status build_lh(osm_handle *h) {
             g.A = FF + (long)i * nn; g.B = Tb; g.C = nullptr; g.D = Y + (long)i * nn; g.sign = 1;
             HIPCHK(h, launch_zgemm<double>(h->st, g, 1));
         }
-        HIPCHK(h, launch_lh_form(h->st, n, Y + (long)(nx - 1) * nn, -2.0 * p, 0, X3));
+        if ((s = form(Y + (long)(nx - 1) * nn, 0, X3)) != OSM_OK) break;
         for (int i = nx - 2; i >= 0; --i) {
             HIPCHK(h, launch_tridiag_apply(h->st, n, fU + (long)i * n * 3, 0, 1.0,
                                            Y + (long)(i + 1) * nn, Tb));
@@ -827,20 +1098,20 @@ osm_status build_lh(osm_handle *h) {
             g.sign = -1;
             HIPCHK(h, launch_zgemm<double>(h->st, g, 1));
         }
-        HIPCHK(h, launch_lh_form(h->st, n, Y, -2.0 * p, 1, X1));
+        if ((s = form(Y, 1, X1)) != OSM_OK) break;
         // right-hand sides -c M^Gamma Q_r^T e_s: only the last line is nonzero
         HIPCHK(h, launch_set_tridiag_mass(h->st, n, h->P.hy, -c, Tb));
         g.A = FF + (long)(nx - 1) * nn; g.B = Tb; g.C = nullptr; g.D = Y + (long)(nx - 1) * nn;
         g.sign = 1;
         HIPCHK(h, launch_zgemm<double>(h->st, g, 1));
-        HIPCHK(h, launch_lh_form(h->st, n, Y + (long)(nx - 1) * nn, -2.0 * p, 1, X4));
+        if ((s = form(Y + (long)(nx - 1) * nn, 1, X4)) != OSM_OK) break;
         for (int i = nx - 2; i >= 0; --i) {
             HIPCHK(h, launch_tridiag_apply(h->st, n, fU + (long)i * n * 3, 0, 1.0,
                                            Y + (long)(i + 1) * nn, Tb));
             g.A = FF + (long)i * nn; g.B = Tb; g.C = nullptr; g.D = Y + (long)i * nn; g.sign = -1;
             HIPCHK(h, launch_zgemm<double>(h->st, g, 1));
         }
-        HIPCHK(h, launch_lh_form(h->st, n, Y, -2.0 * p, 0, X2));
+        if ((s = form(Y, 0, X2)) != OSM_OK) break;
     }
     HIPCHK(h, hipStreamSynchronize(h->st));
     // release the build temporaries
@@ -911,6 +1182,28 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
     P.hx = (prob->xr - prob->xl) / prob->ncx;
     P.hy = (prob->yu - prob->yb) / prob->ncy;
     P.dt = prob->dt; P.c = prob->lap_coef; P.beta = prob->beta; P.p = prob->p;
+    P.tre = prob->p;
+    P.tim = 0.0;
+    std::vector<double2> pad_h;
+    if (prob->tc == OSM_TC_PADE) {
+        // eq. TCS: a_s = e^{i th/2} / (m cos^2 t_s), d_s = e^{i th} tan^2 t_s,
+        // t_s = (2s - 1) pi / (4m), s = 1 .. m
+        h->pm = prob->pade_m;
+        const double th = prob->pade_theta;
+        zc sa(0.0, 0.0);
+        for (int k = 1; k <= h->pm; ++k) {
+            const double t = (2.0 * k - 1.0) * M_PI / (4.0 * h->pm);
+            const zc a = std::polar(1.0, th / 2) / (h->pm * cos(t) * cos(t));
+            const zc d = std::polar(1.0, th) * (tan(t) * tan(t));
+            pad_h.push_back(cd(a.real(), a.imag()));
+            pad_h.push_back(cd(d.real(), d.imag()));
+            sa += a;
+        }
+        h->pm_sa = cd(sa.real(), sa.imag());
+        P.tre = sa.real();
+        P.tim = sa.imag();
+        h->pm_eb = (int)sz.peb;
+    }
     P.ny = h->n; P.nsub = h->N; P.nglob = h->nglob; P.lt = h->Lt;
     // strips
     int line = 0, off = 0;
@@ -921,6 +1214,11 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         s.line0 = line; s.nx = h->cells[j] + 1; s.off = off; s.cls = 0;
         s.pl = j == 0 ? prob->p_bc : prob->p;
         s.pr = j == h->N - 1 ? prob->p_bc : prob->p;
+        s.pl_im = s.pr_im = 0.0;
+        if (h->pm) {   // S_pade^m on every edge, the physical ones included
+            s.pl = s.pr = P.tre;
+            s.pl_im = s.pr_im = P.tim;
+        }
         h->strips_h.push_back(s);
         for (int i = 0; i < s.nx; ++i) {
             line_strip[off + i] = j;
@@ -1027,6 +1325,31 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         SALLOC(h->ran_d, int, PROF_SLOTS);
         SALLOC(h->sctl, StepCtl, 1);
         SALLOC(h->qd_prev, double, h->N);
+        if (h->pm) {
+            const long ne = 2L * h->N, pmn = (long)h->pm * h->n, nn2 = (long)h->n * h->n;
+            SALLOC(h->pad, double2, 2 * h->pm);
+            SALLOC(h->psub, double2, (ne + 1) * pmn);
+            SALLOC(h->pcp, double2, (ne + 1) * pmn);
+            SALLOC(h->pinv, double2, (ne + 1) * pmn);
+            SALLOC(h->pphi, double2, ne * pmn);
+            SALLOC(h->pz, double2, ne * pmn);
+            SALLOC(h->pwork, double2, ne * pmn);
+            SALLOC(h->ppsi, double2, ne * h->n);
+            SALLOC(h->pG, double2, (long)h->pm_eb * nn2);
+            SALLOC(h->pX, double2, (long)h->pm_eb * nn2);
+            SALLOC(h->pedge, int, ne + 1);
+            if (sz.lh) {
+                SALLOC(h->pGf, double2, nn2);
+                SALLOC(h->pGf2, double2, nn2);
+            }
+            std::vector<int> ids(ne + 1);
+            for (long e = 0; e <= ne; ++e) ids[e] = (int)e;
+            HIPCHK(h, hipMemcpy(h->pedge, ids.data(), sizeof(int) * (ne + 1), hipMemcpyHostToDevice));
+            HIPCHK(h, hipMemcpy(h->pad, pad_h.data(), sizeof(double2) * pad_h.size(),
+                                hipMemcpyHostToDevice));
+            HIPCHK(h, hipMemset(h->pphi, 0, sizeof(double2) * ne * pmn));
+            HIPCHK(h, hipMemset(h->ppsi, 0, sizeof(double2) * ne * h->n));
+        }
         if (hipHostMalloc((void **)&h->mirror, sizeof(CtlMirror), hipHostMallocDefault) !=
             hipSuccess) {
             h->mirror = nullptr;
@@ -1055,8 +1378,11 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             SALLOC(h->gdots1, double2, (long)gmres_chunks(h->ng) * (h->m + 1));
             SALLOC(h->gdots2, double2, (long)gmres_chunks(h->ng) * (h->m + 1));
             SALLOC(h->gnorm_part, double, (h->ng + 255) / 256);
+            SALLOC(h->bstate, BicgState, 1);
+            SALLOC(h->bpart, double, bicg_partials());
             // the plan itself is built with the strip classes (build_lh)
-            if (int nb1 = lh_fused_blocks_bound(h->n, h->N, (int)sz.ncls)) {
+            int nb1 = sz.lh ? lh_fused_blocks_bound(h->n, h->N, (int)sz.ncls) : 0;
+            if (nb1 > 0) {
                 SALLOC(h->gmv, double2, (long)nb1 * (h->m + 1));
                 SALLOC(h->lh_tab_d, LhClass, sz.ncls);
                 SALLOC(h->lh_list_d, int, h->N);
@@ -1072,6 +1398,10 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         HIPCHK(h, hipMemcpy(h->ff_first_d, fff.data(), sizeof(int) * h->maxnx, hipMemcpyHostToDevice));
         HIPCHK(h, hipMemset(h->sctl, 0, sizeof(StepCtl)));
         HIPCHK(h, hipMemset(h->g, 0, sizeof(double2) * h->ng));
+        if (h->opt.g1_init == 1) {
+            HIPCHK(h, launch_random_interface(h->st, h->g, h->ng, h->opt.seed));
+            HIPCHK(h, hipStreamSynchronize(h->st));
+        }
         HIPCHK(h, hipMemset(h->gguess, 0, sizeof(double2) * h->ng));
         if (h->m > 0) {
             GmresCtl c0;
@@ -1127,8 +1457,12 @@ osm_status osm_setup(const osm_problem *prob, const osm_options *opt, void *hip_
 // cost against memory-level parallelism, so after the first factorisation
 // time a few solves with every shape and every feasible team size, and keep
 // the fastest pair.
+static osm_status create_timing_events(osm_handle *h);
+
 static osm_status autotune_team(osm_handle *h) {
     if (h->team_tuned) return OSM_OK;
+    osm_status se = create_timing_events(h);   // the trial solves are timed
+    if (se != OSM_OK) return se;
     static const int cand[] = {4, 6, 8, 12, 16, 24, 32, 48, 64};
     bool prof = h->prof;
     HIPCHK(h, hipStreamSynchronize(h->st));
@@ -1277,12 +1611,14 @@ osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats) {
         }
     }
     HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
-    s = schwarz_device(h, u, &S);
+    if (h->pm) HIPCHK(h, pade_reset(h, nullptr));
+    s = o.algo == OSM_INTERFACE_KRYLOV ? interface_step(h, u, &S) : schwarz_device(h, u, &S);
     if (used_pred && (s == OSM_ENOCONV || s == OSM_ENONFINITE)) {
         // the predicted start failed (u is untouched): restart the step from
         // the previous converged vector and do not predict on the next step
         HIPCHK(h, hipMemcpyAsync(h->g, h->g_last, gbytes, hipMemcpyDeviceToDevice, h->st));
         HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
+        if (h->pm) HIPCHK(h, pade_reset(h, nullptr));
         used_pred = false;
         memset(&S, 0, sizeof(S));
         s = mass_of(h, u, &S.mass_before);
@@ -1329,6 +1665,7 @@ osm_status osm_interface_apply(osm_handle *h, osm_iface_op op, const osm_c64 *u_
         const double2 *u = (const double2 *)u_dev;
         HIPCHK(h, launch_clear_flag(h->st, h->err_d));
         HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
+        if (h->pm) HIPCHK(h, pade_reset(h, nullptr));
         int q;
         double a, b;
         osm_status s = apply_R(h, u, gi, h->gn, &q, &a, &b, h->opt.tol_q);
@@ -1425,6 +1762,26 @@ osm_status osm_get_factor(osm_handle *h, void *dst_dev) {
     return OSM_OK;
 }
 
+// Every event pair a timed launch may use, created once (when timing is
+// switched on, and by the solve autotuner), so that timed steps allocate
+// nothing.
+static osm_status create_timing_events(osm_handle *h) {
+    while ((int)h->evs.size() < 2 * PROF_SLOTS) {
+        hipEvent_t a;
+        HIPCHK(h, hipEventCreate(&a));
+        h->evs.push_back(a);
+    }
+    if (h->sub.empty()) {
+        while ((int)h->fevs.size() < 2 * FPROF_SLOTS) {
+            hipEvent_t a;
+            HIPCHK(h, hipEventCreate(&a));
+            h->fevs.push_back(a);
+        }
+        h->fflops.resize(FPROF_SLOTS, 0.0);
+    }
+    return OSM_OK;
+}
+
 osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
                              int64_t *solve_launches) {
     if (!h) return OSM_EINVAL;
@@ -1435,6 +1792,8 @@ osm_status osm_kernel_timing(osm_handle *h, int32_t enable, double *solve_ms,
     if (solve_ms) *solve_ms = h->solve_ms;
     if (solve_launches) *solve_launches = h->solve_launches;
     if (enable) {
+        s = create_timing_events(h);
+        if (s != OSM_OK) return s;
         h->solve_ms = 0.0;
         h->solve_launches = 0;
         h->solve_bytes = 0.0;
@@ -1718,6 +2077,9 @@ static std::string validate_batch(const osm_problem *probs, int32_t nb, const os
     if (!probs || !opt) return "null problems or options";
     if (nb < 1) return "nb must be >= 1";
     if (opt->algo != OSM_CLASSICAL) return "batched instances run the classical algorithm";
+    for (int b = 0; b < nb; ++b)
+        if (probs[b].tc != OSM_TC_ROBIN)
+            return "instance " + std::to_string(b) + ": batched instances use the Robin condition";
     for (int b = 0; b < nb; ++b) {
         std::string v = validate(&probs[b], opt);
         if (!v.empty()) return "instance " + std::to_string(b) + ": " + v;
@@ -1946,13 +2308,8 @@ static osm_status batch_chunk(osm_handle *h, hipStream_t st, bool timed) {
                     if (s != OSM_OK) return s;
                 }
                 int slot = h->prof_used++;
-                if ((int)h->evs.size() < 2 * (slot + 1)) {
-                    hipEvent_t a0, a1;
-                    HIPCHK(h, hipEventCreate(&a0));
-                    HIPCHK(h, hipEventCreate(&a1));
-                    h->evs.push_back(a0);
-                    h->evs.push_back(a1);
-                }
+                if ((int)h->evs.size() < 2 * (slot + 1))
+                    return fail(h, OSM_ESTATE, "timing events not created (osm_kernel_timing)");
                 e0 = h->evs[2 * slot];
                 e1 = h->evs[2 * slot + 1];
                 ran = h->ran_d + slot;
@@ -2110,6 +2467,9 @@ osm_status osm_factor_batch(osm_handle *h, const double *const *W_devs) {
     }
     osm_status s = batch_autotune(h);
     if (s != OSM_OK) return s;
+    // the chunk of Schwarz iterations replayed by every step is captured
+    // and instantiated here (once, with the tuned solve), not in a step
+    if ((s = batch_capture(h)) != OSM_OK) return s;
     HIPCHK(h, hipStreamSynchronize(h->st));
     h->factored = true;
     return OSM_OK;
@@ -2147,7 +2507,7 @@ osm_status osm_step_batch(osm_handle *h, osm_c64 *const *u_devs, osm_step_stats 
     HIPCHK(h, launch_b_mass(h->st, h->tab_d, d, 0));
     HIPCHK(h, launch_b_step_init(h->st, h->tab_d, d, batch_cfg(o)));
     HIPCHK(h, launch_b_copy_u(h->st, h->tab_d, d, 0));
-    if (!h->prof && (s = batch_capture(h)) != OSM_OK) return s;
+    if (!h->prof && !h->gexec) return fail(h, OSM_ESTATE, "the step graph is captured by osm_factor_batch");
     int nk = o.fixed_k > 0 ? o.fixed_k : o.max_k;
     int nq = o.fixed_q > 0 ? o.fixed_q : o.max_q;
     long max_chunks = ((long)nk * nq + (long)h->chunk_k * h->chunk_q - 1) /

@@ -19,11 +19,17 @@ struct StripMeta {
     int cls;     // index of its L_h block set (strips with equal nx, pl, pr share)
     double pl;   // Robin parameter on the left edge  (p, or p_bc for strip 0)
     double pr;   // Robin parameter on the right edge (p, or p_bc for strip N-1)
+    // imaginary parts of the edge coefficients: the operator carries
+    // i c (pl + i pl_im) M^Gamma on the left edge (likewise right); zero for
+    // Robin, sum_s a_s for S_pade^m (whose real part is then pl / pr)
+    double pl_im, pr_im;
 };
 
 // Mesh and equation constants passed by value to the kernels.
 struct Phys {
     double hx, hy, dt, c, beta, p;
+    double tre, tim;   // transmission coefficient t of S v = -i t v (+ i psi):
+                       // (p, 0) for Robin, sum_s a_s for S_pade^m
     int ny;      // nodes per x-line (ncy + 1)
     int nsub;    // strips
     int nglob;   // global x node-lines (ncx + 1)
@@ -105,10 +111,12 @@ hipError_t launch_coef(hipStream_t st, const Phys &P, const StripMeta *strips,
                        const int *line_strip, const double *W, int w_is_zero,
                        double2 *Dc, double2 *Uc, int line_begin, int line_count);
 // fixed-point kernels return at once when c says the fixed point is done
+// psi (may be null): per strip edge (index 2 j + side) the S_pade^m term
+// sum_s a_s d_s phi_s of that edge, ny values each
 hipError_t launch_residual(hipStream_t st, const Phys &P, const StripMeta *strips,
                            const int *line_strip, const double *W, const double2 *u_old,
                            const double2 *zeta, const double2 *g, double2 *res,
-                           const StepCtl *c = nullptr);
+                           const StepCtl *c = nullptr, const double2 *psi = nullptr);
 hipError_t launch_copy_u_to_strips(hipStream_t st, const Phys &P, const StripMeta *strips,
                                    const int *line_strip, const double2 *u, double2 *zeta);
 hipError_t launch_update_norms(hipStream_t st, const Phys &P, double2 *zeta,
@@ -119,7 +127,7 @@ hipError_t launch_strip_sums(hipStream_t st, const Phys &P, const StripMeta *str
 // runs only once the fixed point has converged (when c is given)
 hipError_t launch_flux(hipStream_t st, const Phys &P, const StripMeta *strips,
                        const double2 *g, const double2 *v, double2 *gn, double *part,
-                       const StepCtl *c = nullptr);
+                       const StepCtl *c = nullptr, const double2 *psi = nullptr);
 hipError_t launch_time_update(hipStream_t st, const Phys &P, const int2 *gline_map,
                               const double2 *v, double2 *u);
 hipError_t launch_mass_partials(hipStream_t st, const Phys &P, const double2 *u, double *part);
@@ -244,6 +252,9 @@ struct StepCtl {
     double rho;        // largest contraction ratio measured in this step (0 = none)
 };
 struct GmresCtl;
+// g[k] = u(2k) + i u(2k+1), u(j) uniform on [0, 1) from the (j+1)-th output of
+// SplitMix64 seeded with `seed` (Section 5: a random first interface vector)
+hipError_t launch_random_interface(hipStream_t st, double2 *g, long n, uint64_t seed);
 hipError_t launch_step_init(hipStream_t st, StepCtl *c, const StepCfg &cfg);
 hipError_t launch_iter_reset(hipStream_t st, StepCtl *c, GmresCtl *g);
 hipError_t launch_copy_u_guarded(hipStream_t st, const Phys &P, const StripMeta *strips,
@@ -347,6 +358,56 @@ hipError_t launch_norm_partials(hipStream_t st, long n, const double2 *x, double
 hipError_t launch_scale_copy(hipStream_t st, long n, const double2 *x, double2 s, double2 *y);
 hipError_t launch_axpby(hipStream_t st, long n, double2 a, const double2 *x, double2 b,
                         const double2 *y, double2 *z);
+
+// kernels_pade.hip: the S_pade^m condition on the 2 nsub strip edges (edge
+// 2 j + side, side 0 = the strip's first line); ad = (a_s, d_s) pairs; sub,
+// cp, inv: LU of each D_{e,s} (edge-major, ny values per (e, s)); the free
+// edge (W = 0, for L_h) has index nedge.
+// (edges e_first .. nedge - 1, and the free edge when with_free)
+hipError_t launch_pade_lu(hipStream_t st, const Phys &P, const StripMeta *strips, const double *W,
+                          int nedge, int with_free, int m, const double2 *ad, double2 *sub,
+                          double2 *cp, double2 *inv, int e_first = 0);
+// G_e = scale sum_s a_s d_s D_{e,s}^{-1} M^G for edges [e0, e0 + ecount),
+// into G (ecount x ny x ny); X: ecount x ny x ny scratch
+hipError_t launch_pade_G(hipStream_t st, int ny, double hy, int e0, int ecount, int m,
+                         const double2 *ad, const double2 *sub, const double2 *cp,
+                         const double2 *inv, double2 *X, double2 *G, double2 scale);
+// F[lines[b]] += -i c M^G G_{edges[b]} on the upper tiles, b < batch
+template <typename T>
+hipError_t launch_pade_edge_add(hipStream_t st, int n, typename cplx_of<T>::type *F,
+                                const int *lines, const int *edges, int batch, int e0,
+                                const double2 *G, double c, double hy);
+// fixed point: z and the eliminated edge right-hand side added to res ...
+hipError_t launch_pade_fp_residual(hipStream_t st, const Phys &P, const StripMeta *strips,
+                                   const double *W, int nedge, int m, const double2 *ad,
+                                   const double2 *sub, const double2 *cp, const double2 *inv,
+                                   const double2 *zeta, const double2 *phi, double2 *z,
+                                   double2 *res, const StepCtl *c);
+// ... and, after the strip solve (delta), the edge functions and psi
+hipError_t launch_pade_fp_update(hipStream_t st, const Phys &P, const StripMeta *strips, int nedge,
+                                 int m, const double2 *ad, const double2 *sub, const double2 *cp,
+                                 const double2 *inv, const double2 *delta, const double2 *z,
+                                 double2 *phi, double2 *work, double2 *psi, const StepCtl *c);
+hipError_t launch_pade_reset(hipStream_t st, long nphi, double2 *phi, long npsi, double2 *psi,
+                             const StepCtl *c);
+// out = -2i sa X (- I when add_eye)
+hipError_t launch_pade_lh_form(hipStream_t st, int n, const double2 *X, double2 sa, int add_eye,
+                               double2 *out);
+
+// kernels_krylov.hip: BiCGStab for P x = y (P = I - L_h) with device-side
+// scalars; ctl carries done / conv / finished / bad / total as for GMRES.
+// V holds the 6 work vectors r, rh, p, v, s, t (6 n values); part holds
+// bicg_partials() doubles.
+struct BicgState {
+    double2 rho, alpha, omega, beta;
+};
+int bicg_partials();
+hipError_t launch_bicg_start(hipStream_t st, long n, const double2 *y, double2 *x, double2 *V,
+                             double *part, BicgState *S, GmresCtl *ctl, const StepCtl *sc);
+hipError_t launch_bicg_iteration(hipStream_t st, const Phys &P, const StripMeta *strips, int ncls,
+                                 const LhPlan &pl, const double2 *LH, long n, double2 *V,
+                                 double2 *x, double *part, BicgState *S, GmresCtl *ctl,
+                                 const StepCtl *sc, int max_it);
 
 // ---------------------------------------------------------------- batched instances
 // One entry per independent instance of a batch: its mesh constants and the

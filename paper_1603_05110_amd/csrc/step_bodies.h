@@ -66,7 +66,8 @@ __device__ __forceinline__ bool fp_idle(const StepCtl *c) {
 __device__ __forceinline__ double2 residual_at(const Phys &P, const StripMeta *strips,
                                                const int *line_strip, const double *W,
                                                const double2 *u_old, const double2 *zeta,
-                                               const double2 *g, int L, int a) {
+                                               const double2 *g, int L, int a,
+                                               const double2 *psi = nullptr) {
     const int ny = P.ny;
     const int j = line_strip[L];
     const StripMeta s = strips[j];
@@ -78,10 +79,14 @@ __device__ __forceinline__ double2 residual_at(const Phys &P, const StripMeta *s
     const double2 *trace = nullptr;
     if (i == 0 && j >= 1) trace = g + (long)(2 * (j - 1) + 1) * ny;             // l_j
     if (i == nx - 1 && j <= P.nsub - 2) trace = g + (long)(2 * j) * ny;        // r_j
-    // edge coefficient of M^Gamma on this line (Robin terms of the strip)
+    // edge coefficient of M^Gamma on this line: i c (pe + i pe_im) M^Gamma
+    // (Robin: p; S_pade^m: sum_s a_s), and with S_pade^m the edge functions'
+    // term -sum_s B_s phi_s = i c M^Gamma psi (psi of this edge)
     const double pe = (i == 0 ? s.pl : 0.0) + (i == nx - 1 ? s.pr : 0.0);
+    const double pe_im = (i == 0 ? s.pl_im : 0.0) + (i == nx - 1 ? s.pr_im : 0.0);
     const bool edge = i == 0 || i == nx - 1;
-    double2 z[3][3], u[3][3], tr[3];
+    const double2 *pse = (psi && edge) ? psi + (long)(2 * j + (i == 0 ? 0 : 1)) * ny : nullptr;
+    double2 z[3][3], u[3][3], tr[3], ps[3];
     double ph[3][3];
 #pragma unroll
     for (int di = 0; di < 3; ++di)
@@ -99,6 +104,7 @@ __device__ __forceinline__ double2 residual_at(const Phys &P, const StripMeta *s
     for (int db = 0; db < 3; ++db) {
         const int b = a + db - 1;
         tr[db] = (trace && b >= 0 && b < ny) ? trace[b] : cd(0.0, 0.0);
+        ps[db] = (pse && b >= 0 && b < ny) ? pse[b] : cd(0.0, 0.0);
     }
     double2 acc = cd(0.0, 0.0);
 #pragma unroll
@@ -137,12 +143,15 @@ __device__ __forceinline__ double2 residual_at(const Phys &P, const StripMeta *s
                     acc.x += cs * zb.x;
                     acc.y += cs * zb.y;
                     if (edge && Bx == Ax) {
-                        // - i c pe M^Gamma z - c M^Gamma trace (same line only)
-                        const double e = c * pe * my;
-                        acc.x += e * zb.y;
-                        acc.y += -e * zb.x;
-                        acc.x -= c * my * tr[db].x;
-                        acc.y -= c * my * tr[db].y;
+                        // - i c (pe + i pe_im) M^Gamma z - c M^Gamma trace
+                        // + i c M^Gamma psi (same line only)
+                        const double e = c * pe * my, ei = c * pe_im * my, cm = c * my;
+                        acc.x += e * zb.y + ei * zb.x;
+                        acc.y += -e * zb.x + ei * zb.y;
+                        acc.x -= cm * tr[db].x;
+                        acc.y -= cm * tr[db].y;
+                        acc.x -= cm * ps[db].y;
+                        acc.y += cm * ps[db].x;
                     }
                 }
         }
@@ -199,25 +208,34 @@ __device__ __forceinline__ void update_norms_line(int ny, double2 *zeta, const d
 // Per-trace partial sums of |gn - g|^2 and |gn|^2.  Block of 256 threads.
 __device__ __forceinline__ void flux_trace(const Phys &P, const StripMeta *strips,
                                            const double2 *g, const double2 *v, double2 *gn,
-                                           double *part, int t) {
+                                           double *part, int t, const double2 *psi = nullptr) {
     int ny = P.ny;
     int i = t >> 1;
     const double2 *src;
     const double2 *vt;
+    const double2 *pe = nullptr;
     if ((t & 1) == 0) {           // r_i from strip i+1's left line
         src = g + (long)(2 * i + 1) * ny;
         vt = v + (long)strips[i + 1].off * ny;
+        if (psi) pe = psi + (long)(2 * (i + 1)) * ny;
     } else {                      // l_{i+1} from strip i's right line
         src = g + (long)(2 * i) * ny;
         StripMeta s = strips[i];
         vt = v + (long)(s.off + s.nx - 1) * ny;
+        if (psi) pe = psi + (long)(2 * i + 1) * ny;
     }
-    double tp = 2.0 * P.p;
+    // new trace = -x + 2 S w with S w = -i t w + i psi, t = P.tre + i P.tim
+    // (Robin: t = p, psi = 0)
+    const double tr2 = 2.0 * P.tre, ti2 = 2.0 * P.tim;
     double sd = 0.0, sn = 0.0;
     for (int a = threadIdx.x; a < ny; a += blockDim.x) {
         double2 x = src[a], w = vt[a];
-        // -x - 2ip w = (-x.re + 2p w.im) + i(-x.im - 2p w.re)
-        double2 r = cd(-x.x + tp * w.y, -x.y - tp * w.x);
+        double2 r = cd(-x.x + tr2 * w.y + ti2 * w.x, -x.y - tr2 * w.x + ti2 * w.y);
+        if (pe) {
+            const double2 q = pe[a];
+            r.x -= 2.0 * q.y;
+            r.y += 2.0 * q.x;
+        }
         double2 o = g[(long)t * ny + a];
         gn[(long)t * ny + a] = r;
         sd += (r.x - o.x) * (r.x - o.x) + (r.y - o.y) * (r.y - o.y);

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OSM_OK", -1: "OSM_EINVAL", -2: "OSM_ENOMEM", -3: "OSM_EHIP",
                 -4: "OSM_ENOCONV", -5: "OSM_ENONFINITE", -6: "OSM_ESTATE",
                 -7: "OSM_EUNSUPPORTED"}
 OSM_TC_ROBIN, OSM_TC_PADE = 0, 1
-OSM_CLASSICAL, OSM_PRECOND = 0, 1
+OSM_CLASSICAL, OSM_PRECOND, OSM_INTERFACE_KRYLOV = 0, 1, 2
 OSM_FP64, OSM_C32_REFINE = 0, 1
 OSM_IFACE_R, OSM_IFACE_I_MINUS_R, OSM_IFACE_LH, OSM_IFACE_PINV = 0, 1, 2, 3
 
@@ -36,7 +36,8 @@ class osm_problem(ctypes.Structure):
                 ("tc", ctypes.c_int32), ("p", ctypes.c_double),
                 ("p_bc", ctypes.c_double), ("dt", ctypes.c_double),
                 ("omega", ctypes.c_double), ("vxx", ctypes.c_double),
-                ("vyy", ctypes.c_double)]
+                ("vyy", ctypes.c_double), ("pade_m", ctypes.c_int32),
+                ("pade_theta", ctypes.c_double)]
 
 
 class osm_options(ctypes.Structure):
@@ -49,7 +50,8 @@ class osm_options(ctypes.Structure):
                 ("max_gmres", ctypes.c_int32), ("guess", ctypes.c_int32),
                 ("team", ctypes.c_int32), ("mem_cap", ctypes.c_uint64),
                 ("eta_q", ctypes.c_double), ("solve_shape", ctypes.c_int32),
-                ("q_estimate", ctypes.c_int32)]
+                ("q_estimate", ctypes.c_int32), ("g1_init", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("krylov", ctypes.c_int32)]
 
 
 class osm_step_stats(ctypes.Structure):
@@ -162,24 +164,30 @@ def _ptr(t):
 def make_problem(pb):
     """osm_problem from any object with the problem-statement attributes
     (xl, xr, yb, yu, ncx, ncy, nsub, strip_cells, lap_coef, beta, p, p_bc,
-    dt and optionally omega, vxx, vyy).  Returns (struct, keep-alive)."""
+    dt and optionally omega, vxx, vyy, tc ("robin" | "pade"), pade_m,
+    pade_theta).  Returns (struct, keep-alive)."""
     cells = (ctypes.c_int32 * pb.nsub)(*[int(c) for c in pb.strip_cells])
+    tc = {"robin": OSM_TC_ROBIN, "pade": OSM_TC_PADE}[getattr(pb, "tc", "robin")]
     s = osm_problem(pb.xl, pb.xr, pb.yb, pb.yu, pb.ncx, pb.ncy, pb.nsub, cells,
-                    pb.lap_coef, pb.beta, OSM_TC_ROBIN, pb.p, pb.p_bc, pb.dt,
+                    pb.lap_coef, pb.beta, tc, pb.p, pb.p_bc, pb.dt,
                     getattr(pb, "omega", 0.0), getattr(pb, "vxx", 0.0),
-                    getattr(pb, "vyy", 0.0))
+                    getattr(pb, "vyy", 0.0), int(getattr(pb, "pade_m", 0)),
+                    float(getattr(pb, "pade_theta", 0.7853981633974483)))
     return s, cells
 
 
 def make_options(algo="classical", prec="fp64", tol_k=1e-10, tol_k_relative=False,
                  max_k=2000, tol_q=1e-13, max_q=100, fixed_k=0, fixed_q=0,
                  warm_start=True, tol_gmres=1e-12, gmres_restart=50, max_gmres=1000,
-                 guess=0, team=0, mem_cap=0, eta_q=0.0, solve_shape=0, q_estimate=0):
-    return osm_options({"classical": OSM_CLASSICAL, "precond": OSM_PRECOND}[algo],
+                 guess=0, team=0, mem_cap=0, eta_q=0.0, solve_shape=0, q_estimate=0,
+                 g1_init=0, seed=0, krylov="gmres"):
+    return osm_options({"classical": OSM_CLASSICAL, "precond": OSM_PRECOND,
+                        "interface": OSM_INTERFACE_KRYLOV}[algo],
                        {"fp64": OSM_FP64, "c32": OSM_C32_REFINE}[prec],
                        tol_k, int(tol_k_relative), max_k, tol_q, max_q, fixed_k, fixed_q,
                        int(warm_start), tol_gmres, gmres_restart, max_gmres, guess, team,
-                       mem_cap, eta_q, solve_shape, int(q_estimate))
+                       mem_cap, eta_q, solve_shape, int(q_estimate), int(g1_init),
+                       int(seed) & 0xFFFFFFFFFFFFFFFF, {"gmres": 0, "bicgstab": 1}[krylov])
 
 
 def osm_query(pb, **opts):

@@ -124,11 +124,65 @@ def test_guess_options_and_network_arguments_are_checked_on_the_host():
     assert osm.NET_NPARAMS == nn.NPARAM
 
 
-@pytest.mark.parametrize("kw", [dict(q_estimate=2), dict(q_estimate=-1), dict(solve_shape=9)])
+@pytest.mark.parametrize("kw", [dict(q_estimate=2), dict(q_estimate=-1), dict(solve_shape=9),
+                                dict(g1_init=2), dict(g1_init=-1), dict(krylov_code=2),
+                                dict(algo="interface"),
+                                dict(algo="precond", krylov="bicgstab", gmres_restart=3)])
 def test_solver_switches_are_checked_on_the_host(kw):
-    """Out-of-range values of the inner stopping-test and solve-shape
-    switches are rejected by osm_query (EINVAL) before any device work."""
+    """Out-of-range values of the solver switches are rejected by osm_query
+    (EINVAL) before any device work: the inner stopping test, the solve
+    shape, the first interface vector, the Krylov solver of P (BiCGStab
+    needs room for its work vectors), and the interface Krylov algorithm on
+    a nonlinear problem (beta != 0)."""
+    import ctypes
     from paper_1603_05110_amd import osm
+    if "krylov_code" in kw:
+        prob, keep = osm.make_problem(_pb())
+        opt = osm.make_options()
+        opt.krylov = kw["krylov_code"]
+        fp = osm.osm_footprint()
+        st = osm._lib.osm_query(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(fp))
+        assert st == osm.OSM_EINVAL
+        return
     with pytest.raises(osm.OsmError) as e:
         osm.osm_query(_pb(), **kw)
     assert e.value.status == osm.OSM_EINVAL
+
+
+def test_interface_krylov_is_accepted_for_the_linear_problem():
+    from paper_1603_05110_amd import osm
+    d, _ = osm.osm_query(_pb(beta=0.0), algo="interface")
+    dc, _ = osm.osm_query(_pb(beta=0.0))
+    dp, _ = osm.osm_query(_pb(beta=0.0), algo="precond")
+    assert dc < d < dp      # a Krylov basis, but no L_h
+
+
+def test_options_struct_matches_the_header():
+    """The ctypes mirror of osm_options ends with g1_init, seed and krylov, laid out
+    as the C compiler lays out include/osm.h (checked with the C compiler
+    of the build)."""
+    import ctypes
+    import shutil
+    import subprocess
+    import tempfile
+    from paper_1603_05110_amd import osm
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = (
+        '#include <stddef.h>\n#include <stdio.h>\n#include "osm.h"\n'
+        'int main(void) { printf("%zu %zu %zu %zu %zu\\n", sizeof(osm_options), '
+        'offsetof(osm_options, g1_init), offsetof(osm_options, seed), '
+        'offsetof(osm_options, krylov), sizeof(osm_problem)); return 0; }\n')
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    size, off_g1, off_seed, off_kr, psize = map(int, out)
+    assert size == ctypes.sizeof(osm.osm_options)
+    assert off_g1 == osm.osm_options.g1_init.offset
+    assert off_seed == osm.osm_options.seed.offset
+    assert off_kr == osm.osm_options.krylov.offset
+    assert psize == ctypes.sizeof(osm.osm_problem)

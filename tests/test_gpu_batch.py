@@ -123,9 +123,12 @@ def _edge_term(pb, u_old, u_new):
 
 def test_c3_batch_full_size():
     """The 64-instance batch at full size (grids 256..768, 8-32 uneven
-    strips), one complex-FP32 step: sampled instances against the monolithic
-    FP64 oracle, and the discrete mass identity of the scheme in every
-    instance (mass change = -2 c p dt v* M^Gamma v, exact at convergence)."""
+    strips), one complex-FP32 step: one instance of every grid size and the
+    slowest instance against the monolithic FP64 oracle (relative L2 and
+    largest entry error of each), and the discrete mass identity of the
+    scheme in every instance (mass change = -2 c p dt v* M^Gamma v, exact at
+    convergence).  The slowest instance runs the step's last launches alone,
+    with the largest re-planned teams."""
     from paper_1603_05110_amd import osm
     log("C3 full batch, 1 step c32")
     wl = c3()
@@ -145,20 +148,16 @@ def test_c3_batch_full_size():
         d_mass = st[i]["mass_after"] - st[i]["mass_before"]
         rhs = -2.0 * pb.lap_coef * pb.p_bc * pb.dt * _edge_term(pb, wl.u0[i], got[i])
         assert abs(d_mass - rhs) < 1e-11 * st[i]["mass_before"], i
-    small = sorted(range(len(pbs)), key=lambda i: pbs[i].ncx * pbs[i].ncy)[:2]
-    for i in small:
-        ref = run_monolithic(pbs[i], wl.u0[i], wl.V[i], 1, tol_q=1e-14)
-        assert rel(got[i], ref) < 1e-10, i
-    # the slowest instance runs the step's last launches alone, where the
-    # items are re-planned with the largest teams: against the same instance
-    # solved alone by the single-instance path
-    i = int(np.argmax(ks))
-    log(f"  slowest instance {i}: {pbs[i].ncx}x{pbs[i].ncy}, {pbs[i].nsub} strips, k {ks[i]}")
-    s = osm.OsmSolver(pbs[i], DEV, prec="c32", tol_k=1e-12, tol_k_relative=True, tol_q=1e-14,
-                      max_k=4000)
-    s.factor(to_dev(wl.V[i]))
-    u1 = to_dev(wl.u0[i])
-    s1 = s.step(u1)
-    s.close()
-    assert abs(s1["k"] - ks[i]) <= 2
-    assert rel(got[i], u1.cpu().numpy()) < 1e-10, i
+    picks = {}
+    for i, pb in enumerate(pbs):
+        picks.setdefault(pb.ncx, i)
+    slowest = int(np.argmax(ks))
+    check = sorted(set(picks.values()) | {slowest})
+    for i in check:
+        pb = pbs[i]
+        ref = run_monolithic(pb, wl.u0[i], wl.V[i], 1, tol_q=1e-14)
+        e = rel(got[i], ref)
+        mx = float(np.max(np.abs(got[i] - ref)) / np.max(np.abs(ref)))
+        log(f"  instance {i}: {pb.ncx}^2, {pb.nsub} strips, k {ks[i]}: rel L2 {e:.3e}, "
+            f"max-abs {mx:.3e}")
+        assert e < 1e-10 and mx < 1e-10, i

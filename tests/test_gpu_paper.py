@@ -1,0 +1,49 @@
+"""The paper's own Robin experiment on the GPU (Section 5.1.3, Table
+Influence_p_NL_2_32): the first time step of the cubic NLS on the first
+mesh (4097 x 129 nodes), zero first interface vector, the paper's stopping
+rule ||g^{k+1} - g^k||_2 < 1e-10 (absolute) and its fixed-point start
+zeta^0 = u_{n-1}.  The GPU's counts must be the paper's within +-20% (the
+oracle gives the printed counts exactly), and its step the oracle's
+monolithic step."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle.step import run_monolithic  # noqa: E402
+from workloads import nls_mesh1  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("N,p,algo,prec,paper", [
+    (2, 15.0, "classical", "fp64", 32), (2, 15.0, "precond", "fp64", 6),
+    (32, 15.0, "classical", "c32", 33), (32, 5.0, "precond", "c32", 6),
+    (2, 50.0, "classical", "c32", 73),
+])
+def test_mesh1_first_step_counts(N, p, algo, prec, paper):
+    from paper_1603_05110_amd import osm
+    wl = nls_mesh1(N, p, steps=1)
+    pb, u0, W = wl.problems[0], wl.u0[0], wl.V[0]
+    log(f"mesh 1, N={N}, p={p}, {algo}, {prec}")
+    s = osm.OsmSolver(pb, DEV, algo=algo, prec=prec, tol_k=1e-10, tol_k_relative=False,
+                      max_k=2000, tol_q=1e-13, max_q=200, warm_start=True, tol_gmres=1e-12)
+    s.factor(torch.from_numpy(W).to(DEV))
+    u = torch.from_numpy(u0).to(DEV)
+    st = s.step(u)
+    s.close()
+    log(f"  k={st['k']} (paper {paper}), q={st['q_total']}, gmres={st['gmres_total']}")
+    assert abs(st["k"] - paper) <= 0.2 * paper
+    if N == 2 and algo == "precond":
+        ref = run_monolithic(pb, u0, W, 1, tol_q=1e-14)
+        got = u.cpu().numpy()
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
