@@ -1,24 +1,29 @@
 #!/usr/bin/env python3
 """Throughput of the optimized Schwarz time loop on one MI355X.
 
-Workload: the GPE with harmonic trap V = -(x^2+y^2)/2, f(u) = -50|u|^2,
-c = 1/2 on (-8,8)^2 with 512 x 512 cells (263,169 nodes), 16 equal x-strips,
-Robin p = 5 (transmission and physical), dt = 1e-3, preconditioned algorithm
-with GMRES on P = I - L_h; u0 = normalised Gaussian + 1e-3 seeded complex
-noise.  Synthetic, seeded inputs.
+Default workload (the largest configuration that fits one GPU): the rotating
+GPE solved in the rotating frame (Section 5.2.1), V = -(x^2 + 1.2 y^2)/2,
+f(u) = -500|u|^2, c = 1/2 on (-16,16)^2 with 2048 x 2048 cells (4,198,401
+nodes), 64 uneven x-strips, Robin p = 5, dt = 5e-4, a vortex Gaussian u0,
+preconditioned algorithm with GMRES on P = I - L_h, complex-FP32 factors
+with FP64 refinement.  The step potential W_n changes every step, so every
+step refactors all strip lines before its Schwarz iterations.  Synthetic,
+seeded inputs.
 
-A "step" is one time step: the stationary nonlinear problem of the step is
-solved by preconditioned Schwarz iterations, each of which runs the strip
-fixed point (residual stencil + block-tridiagonal substitution per
-iteration) and GMRES on the interface.  The timed region covers the
-factorisation of the strip operators for W_n plus K steps with the inputs
-resident in HBM; L_h is built once at setup (outside the timed region, its
-time is reported).
+A "step" is one time step: factor(W_n) plus the stationary nonlinear
+problem of the step, solved by preconditioned Schwarz iterations (strip
+fixed points: residual stencil + block-tridiagonal substitution, then GMRES
+on the interface).  The timed region covers --steps steps with the inputs
+resident in HBM; L_h is built once at setup (outside, its time reported).
 
-Printed: one JSON line with dof-steps/s, iterations, a roofline entry for
-the strip-solve kernel (live HIP-event timing of every launch in the timed
-region), the plain FP64 GPU path for comparison, the parity of the first
-steps against the FP64 CPU oracle, and the oracle's own throughput.
+Printed: one JSON line with dof-steps/s, iterations, the roofline of the
+dominant kernel (the factor's sweep update on the matrix cores, live HIP
+event timing of every launch in the timed region), the strip solve's HBM
+roofline, the plain FP64 GPU path over the first steps (with the relative
+L2 difference of the two), the first step checked against the discrete
+equation the FP64 oracle solves, and the oracle's throughput on a bounded
+sample of the same workload.  Other workloads: --workload gpe512 | batch64 |
+learned1024 | paper-e5 | paper-e6.
 """
 from __future__ import annotations
 
@@ -78,6 +83,37 @@ def measured_traffic(prec, kernel_name):
         return None
     sha = hashlib.sha256(src.encode()).hexdigest()
     return rec["bytes"] if sha == rec["source_sha256"] else None
+
+
+# HBM bytes per sweep-update launch of the rotating 2048^2 factor from
+# rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled as above), valid only while the
+# update kernel's source text (sweep_update_kernel and the MMA helpers above
+# it) hashes to source_sha256.
+FACTOR_TRAFFIC = {}
+
+
+def factor_kernel_source():
+    """Source text the factor counters describe: kernels_factor.hip from the
+    sweep's LDS layout through the end of sweep_update_kernel."""
+    try:
+        src = open(os.path.join(ROOT, "paper_1603_05110_amd", "csrc", "kernels_factor.hip")).read()
+    except OSError:
+        return None
+    i = src.find("template <typename T> struct sweep_lds")
+    k = src.find("void sweep_update_kernel(")
+    j = src.find("\n}\n", k)
+    if i < 0 or k < 0 or j < 0:
+        return None
+    return src[i:j + 3]
+
+
+def measured_factor_traffic(prec):
+    import hashlib
+    rec = FACTOR_TRAFFIC.get(prec)
+    src = factor_kernel_source()
+    if rec is None or src is None:
+        return None
+    return rec["bytes"] if hashlib.sha256(src.encode()).hexdigest() == rec["source_sha256"] else None
 
 
 def solver_opts(prec):
@@ -360,12 +396,82 @@ def run_learned(args, dev):
     print(json.dumps(out), flush=True)
 
 
+def cpu_sample_rotating(pb, W1, u0, k_per_step, nsample=40):
+    """The FP64 oracle's throughput estimated on a bounded sample of the same
+    workload: the first `nsample` strips of the rotating problem cut out as a
+    domain of their own (same mesh size, potential and initial data), the
+    sequential Schwarz oracle (form B) set up on them (one sparse LU per
+    strip) and one Schwarz map evaluated (every strip's fixed point to
+    1e-13).  Scaled by (strips / nsample) and by the GPU's Schwarz iterations
+    per step; the oracle's L_h build and GMRES are not counted, so this
+    overstates the oracle's rate."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.schwarz import SchwarzOracle
+    nsample = min(nsample, pb.nsub)
+    cells = list(pb.strip_cells[:nsample])
+    ncx = sum(cells)
+    sub = pb.replace(ncx=ncx, nsub=nsample, strip_cells=cells, xr=pb.xl + pb.hx * ncx)
+    Wsub = np.ascontiguousarray(W1[:ncx + 1])
+    usub = np.ascontiguousarray(u0[:ncx + 1])
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        orc = SchwarzOracle(sub, Wsub, form="B", tol_q=1e-13)
+        t_fac = time.perf_counter() - t0
+        g0 = np.zeros((2 * (nsample - 1), pb.ncy + 1), complex)
+        t1 = time.perf_counter()
+        orc.R(g0, usub)
+        t_map = time.perf_counter() - t1
+    scale = pb.nsub / nsample
+    per_step = scale * (t_fac + k_per_step * t_map)
+    dof = (pb.ncx + 1) * (pb.ncy + 1)
+    return {"value": dof / per_step, "unit": "dof-steps/s", "cores": 1, "kind": "oracle",
+            "host_nproc": os.cpu_count(),
+            "sample": (f"FP64 sequential Schwarz oracle (form B) on {nsample} of the {pb.nsub} "
+                       f"strips of this workload ({(ncx + 1) * (pb.ncy + 1)} nodes): strip LUs "
+                       f"{t_fac:.1f}s + one Schwarz map {t_map:.1f}s, scaled by "
+                       f"{pb.nsub}/{nsample} strips and {k_per_step:.1f} Schwarz iterations per "
+                       f"step (the GPU's); L_h build and GMRES not counted"),
+            "seconds": t_fac + t_map}
+
+
+def profile_factor(pb, factors, dev, prec):
+    """Profiler mode for the factor: setup, then `factors` refactorisations
+    of the rotating problem (osm_factor_rotating), then one 1 GiB device copy
+    (the calibration kernel of the HBM byte counters)."""
+    import torch
+    from paper_1603_05110_amd import osm
+    s = osm.OsmSolver(pb, dev, **solver_opts(prec))
+    s.factor_rotating(1)
+    torch.cuda.synchronize()
+    s.kernel_timing(True)
+    for n in range(2, 2 + factors):
+        s.factor_rotating(n)
+    torch.cuda.synchronize()
+    s.kernel_timing(False)
+    ms, n, fl = s.factor_timing()
+    s.close()
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "profile-factor", "prec": prec, "factors": factors,
+                      "update_launches": n, "update_avg_ms": ms / max(n, 1),
+                      "update_tflops": fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0,
+                      "update_flops": fl, "copy_bytes": 2 * src.numel() * 8}), flush=True)
+
+
 def run_rotating(args, dev):
     """Rotating GPE at full size (2048^2 cells, 64 uneven strips), solved in
     the rotating frame: the step potential changes every step, so every step
     refactors all 2112 strip lines (osm_factor_rotating) before its Schwarz
     iterations.  A truncated horizon of --steps steps is timed (the full
-    1000-step horizon is the same work repeated)."""
+    1000-step horizon is the same work repeated).  Beside it: the plain FP64
+    GPU path over the first --fp64-steps steps (throughput, and the relative
+    L2 difference of the two after those steps), the first step checked
+    against the discrete equation the oracle solves, and the oracle's rate on
+    a bounded sample of the same workload."""
     import numpy as np
     import torch
 
@@ -375,6 +481,9 @@ def run_rotating(args, dev):
     wl = c5(steps=args.steps)
     pb, u0 = wl.problems[0], wl.u0[0]
     dof = (pb.ncx + 1) * (pb.ncy + 1)
+    if args.profile_factor > 0:
+        profile_factor(pb, args.profile_factor, dev, args.prec)
+        return
     print(f"bench: {pb.name} dof={dof} prec={args.prec} steps={args.steps}", file=sys.stderr,
           flush=True)
     opts = solver_opts(args.prec)
@@ -398,7 +507,8 @@ def run_rotating(args, dev):
     torch.cuda.synchronize()
     s.kernel_timing(True)
     stats, t_fac = [], 0.0
-    u_first = None
+    u_first = u_cmp = None
+    ncmp = min(args.fp64_steps, args.steps) if args.fp64_steps > 0 else 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for n in range(1, args.steps + 1):
@@ -409,6 +519,8 @@ def run_rotating(args, dev):
         stats.append(s.step(u))
         if n == 1:
             u_first = u.clone()
+        if n == ncmp:
+            u_cmp = u.clone()
         print(f"bench: step {n}: k {stats[-1]['k']} gmres {stats[-1]['gmres_total']} "
               f"q {stats[-1]['q_total']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -418,6 +530,8 @@ def run_rotating(args, dev):
     fac_ms, fac_n, fac_fl = s.factor_timing()
     team, shape = s.solve_team(), s.solve_shape()
     s.close()
+    del u
+    torch.cuda.empty_cache()
     value = dof * args.steps / T
     avg_ms = kern[0] / max(kern[1], 1)
     nbytes = solve_work / max(kern[1], 1)
@@ -426,21 +540,45 @@ def run_rotating(args, dev):
     upd_tflops = fac_fl / (fac_ms * 1e-3) / 1e12 if fac_ms > 0 else 0.0
     print(f"bench: {T:.2f}s for {args.steps} steps ({t_fac:.2f}s factor), {value:.4g} dof-steps/s",
           file=sys.stderr, flush=True)
-    # the FP64 oracle: the first step checked against the discrete equation
-    # with the oracle's assembled operators (a monolithic direct solve at
-    # 4.2 M nodes is out of reach), and the oracle's throughput on the same
-    # problem at 512^2 cells
+
+    # the plain FP64 GPU path over the first ncmp steps, from the same u0
+    fp64 = None
+    if ncmp > 0 and args.prec != "fp64":
+        ta = time.perf_counter()
+        s64 = osm.OsmSolver(pb, dev, **solver_opts("fp64"))
+        torch.cuda.synchronize()
+        t_setup64 = time.perf_counter() - ta
+        u64 = torch.from_numpy(u0).to(dev)
+        s64.factor_rotating(1)      # first factor, with the solve autotune
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        k64 = []
+        for n in range(1, ncmp + 1):
+            s64.factor_rotating(n)
+            k64.append(s64.step(u64)["k"])
+        torch.cuda.synchronize()
+        T64 = time.perf_counter() - ta
+        s64.close()
+        diff = float(torch.linalg.vector_norm(u_cmp - u64) / torch.linalg.vector_norm(u64))
+        fp64 = {"value": dof * ncmp / T64, "steps": ncmp, "ms_per_step": 1e3 * T64 / ncmp,
+                "setup_s": t_setup64, "k": k64,
+                "rel_l2_c32_vs_fp64": diff,
+                "note": "same steps from the same u0; factor(W_n) inside the timed steps"}
+        print(f"bench: fp64 {fp64['value']:.4g} dof-steps/s; c32 vs fp64 after {ncmp} steps "
+              f"{diff:.3e}", file=sys.stderr, flush=True)
+        del u64
+    del u_cmp
+    torch.cuda.empty_cache()
+
     check, cpu = None, None
     if not args.no_cpu_baseline:
-        from threadpoolctl import threadpool_limits
-
         from oracle.fem import StripMatrices, weighted_mass_2d
         from oracle.rotating import step_potential
-        from oracle.step import run_monolithic
         u1 = u_first.cpu().numpy()
         del u_first
+        W1 = step_potential(pb, 1)
         mats = StripMatrices(pb.ncx, pb.ncy, pb.hx, pb.hy)
-        K = mats.operator(step_potential(pb, 1), pb.dt, pb.lap_coef, pb.p_bc, pb.p_bc)
+        K = mats.operator(W1, pb.dt, pb.lap_coef, pb.p_bc, pb.p_bc)
         v = 0.5 * (u0 + u1).ravel()
         F = (2j / pb.dt) * (mats.M @ u0.ravel())
         r = K @ v + weighted_mass_2d((pb.beta * np.abs(v) ** 2).reshape(u0.shape), pb.hx,
@@ -450,18 +588,10 @@ def run_rotating(args, dev):
         del K, r, v, F, mats
         print(f"bench: step-1 residual {check['rel_residual_discrete_equation']:.3e}",
               file=sys.stderr, flush=True)
-        sw = c5(ncells=512, nsub=16, steps=1)
-        spb, su0 = sw.problems[0], sw.u0[0]
-        with threadpool_limits(1):
-            t1 = time.perf_counter()
-            run_monolithic(spb, su0, lambda k: step_potential(spb, k), 1, tol_q=1e-14)
-            tc = time.perf_counter() - t1
-        sdof = (spb.ncx + 1) * (spb.ncy + 1)
-        cpu = {"value": sdof / tc, "unit": "dof-steps/s", "cores": 1, "kind": "oracle",
-               "sample": (f"FP64 monolithic oracle (SciPy splu, form B) on the same rotating "
-                          f"problem at 512^2 cells ({sdof} dofs), one step including its "
-                          f"factorisation ({tc:.1f}s); the 2048^2 system is 16x larger")}
-        print(f"bench: oracle {cpu['value']:.4g} dof-steps/s", file=sys.stderr, flush=True)
+        kps = float(np.mean([x["k"] for x in stats]))
+        cpu = cpu_sample_rotating(pb, W1, u0, kps)
+        print(f"bench: oracle {cpu['value']:.4g} dof-steps/s ({cpu['seconds']:.1f}s sampled)",
+              file=sys.stderr, flush=True)
     out = {
         "metric": METRIC,
         "value": value,
@@ -483,15 +613,18 @@ def run_rotating(args, dev):
                    "timed": "per step: factor(W_n) + Schwarz/GMRES",
                    "horizon": f"{args.steps} of 1000 steps"},
         "iters": {"k_mean": float(np.mean([x["k"] for x in stats])),
+                  "k_max": int(np.max([x["k"] for x in stats])),
                   "q_total": int(sum(x["q_total"] for x in stats)),
                   "gmres_total": int(sum(x["gmres_total"] for x in stats))},
         "roofline": {"kernel": "sweep_update", "bound": "mfma", "achieved": upd_tflops,
-                     "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "peak": MFMA_FP32_PEAK_TFLOPS if args.prec == "c32" else MFMA_FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s",
                      "frac": upd_tflops / MFMA_FP32_PEAK_TFLOPS if args.prec == "c32"
                      else upd_tflops / MFMA_FP64_PEAK_TFLOPS,
-                     "traffic": None, "flops_timed": fac_fl, "avg_launch_ms": upd_avg_ms,
-                     "launches": fac_n,
-                     "note": ("8 real flops per complex multiply-add; the kernel issues 6 "
+                     "traffic": measured_factor_traffic(args.prec), "flops_timed": fac_fl,
+                     "avg_launch_ms": upd_avg_ms, "launches": fac_n,
+                     "note": ("algorithmic flops: 8 real flops per complex multiply-add over "
+                              "the upper 64x64 tiles each pass updates; the kernel issues 6 "
                               "(three real products)")},
         "solve": {"kernel": "strip_solve", "bound": "hbm", "achieved": achieved,
                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -501,34 +634,177 @@ def run_rotating(args, dev):
                    "update_ms_per_step": fac_ms / args.steps},
         "setup_s": t_setup,
         "first_factor_and_autotune_s": t_first,
+        "fp64_gpu": fp64,
         "check": check,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
 
+# Section 5.1.3, Table Influence_p_NL_2_32: first-step iterations on the
+# first mesh, {p: (N=2 zero cls, pd, random cls, pd, N=32 zero cls, pd,
+# random cls, pd)}
+PAPER_E5 = {5: (57, 6, 548, 6, 57, 6, 582, 6), 10: (35, 6, 297, 6, 35, 6, 316, 6),
+            15: (32, 6, 227, 6, 33, 6, 241, 6), 20: (36, 6, 200, 6, 36, 6, 212, 6),
+            25: (41, 6, 189, 6, 41, 6, 200, 6), 30: (46, 6, 186, 6, 47, 6, 200, 6),
+            35: (53, 6, 188, 6, 53, 6, 204, 6), 40: (59, 6, 194, 6, 60, 6, 211, 6),
+            45: (66, 6, 208, 6, 66, 6, 223, 6), 50: (73, 6, 216, 6, 73, 6, 234, 6)}
+
+# Section 5.2.2, Table time_dx32, Robin p = 180: hours for T = 0.1 (1000
+# steps) on 92 x 16 Sandy Bridge cores, one MPI rank per strip
+PAPER_E6_HOURS = {"classical": {2: 5.68, 4: 2.66, 8: 1.28, 16: 0.68, 32: 0.33},
+                  "precond": {2: 3.49, 4: 1.60, 8: 0.77, 16: 0.44, 32: 0.24}}
+
+
+def run_paper_e5(args, dev):
+    """The paper's Robin p-sweep (Section 5.1.3): the first time step of the
+    cubic NLS on the first mesh (4097 x 129 nodes), N = 2 and 32 strips,
+    zero and seeded random first interface vectors (SplitMix64, uniform
+    real and imaginary parts), classical and preconditioned, with the
+    paper's stopping rule (1e-10, absolute).  Prints every iteration count
+    beside the printed one."""
+    import torch
+
+    from paper_1603_05110_amd import osm
+    from workloads import nls_mesh1
+
+    plist = [float(x) for x in args.p_list.split(",")] if args.p_list else sorted(PAPER_E5)
+    rows = []
+    t_all = time.perf_counter()
+    for N in (2, 32):
+        for p in plist:
+            wl = nls_mesh1(N, p, steps=1)
+            pb, u0, W = wl.problems[0], wl.u0[0], wl.V[0]
+            paper = PAPER_E5.get(int(p))
+            for si, start in enumerate(("zero", "random")):
+                for ai, algo in enumerate(("classical", "precond")):
+                    s = osm.OsmSolver(pb, dev, algo=algo, prec=args.prec, tol_k=1e-10,
+                                      tol_k_relative=False, max_k=5000, tol_q=1e-13,
+                                      max_q=200, warm_start=True, tol_gmres=1e-12,
+                                      g1_init=1 if start == "random" else 0, seed=1)
+                    s.factor(torch.from_numpy(W).to(dev))
+                    u = torch.from_numpy(u0).to(dev)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st = s.step(u)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    s.close()
+                    col = (0 if N == 2 else 4) + 2 * si + ai
+                    ref = paper[col] if paper else None
+                    rows.append({"N": N, "p": p, "start": start, "algo": algo, "k": st["k"],
+                                 "paper_k": ref, "q": st["q_total"],
+                                 "gmres": st["gmres_total"], "step_s": dt})
+                    print(f"bench: N={N} p={p:g} {start} {algo}: k {st['k']} (paper {ref}), "
+                          f"{dt:.2f}s", file=sys.stderr, flush=True)
+    ratio = [r["k"] / r["paper_k"] for r in rows if r["paper_k"]]
+    dof = 4097 * 129
+    out = {"metric": "first-step Schwarz iterations vs the paper's Table Influence_p_NL_2_32",
+           "value": float(max(abs(x - 1.0) for x in ratio)) if ratio else None,
+           "unit": "max relative deviation of k from the paper", "n_gpus": 1,
+           "higher_is_better": False, "dtype": "c64+f64-refine" if args.prec == "c32" else "c128",
+           "data": "synthetic",
+           "config": {"workload": "paper Section 5.1 mesh 1: cubic NLS, (-16,16)x(-8,8), "
+                                  "dx=1/128, dy=1/8, dt=0.01, u0=exp(-x^2-y^2-0.5ix), first step",
+                      "dof": dof, "p": plist, "strips": [2, 32]},
+           "rows": rows, "seconds": time.perf_counter() - t_all}
+    print(json.dumps(out), flush=True)
+
+
+def run_paper_e6(args, dev):
+    """The paper's BEC runs with Robin p = 180 (Section 5.2.2, Table
+    time_dx32): the rotating GPE on (-16,16)^2 with 1025^2 nodes, N = 2..32
+    equal strips, classical and preconditioned, dt = 1e-4, refactored every
+    step (rotating frame).  --steps of the 1000-step horizon are timed; the
+    paper's hours are converted to dof-steps/s for context (its machine: 92
+    nodes of 16 Sandy Bridge cores, one MPI rank per strip)."""
+    import numpy as np
+    import torch
+
+    from paper_1603_05110_amd import osm
+    from workloads import bec_1025
+
+    runs = []
+    for algo in ("classical", "precond"):
+        for N in (2, 4, 8, 16, 32):
+            wl = bec_1025(N, steps=args.steps)
+            pb, u0 = wl.problems[0], wl.u0[0]
+            dof = (pb.ncx + 1) * (pb.ncy + 1)
+            opts = dict(algo=algo, prec=args.prec, tol_k=1e-10, tol_k_relative=False,
+                        max_k=5000, tol_q=1e-13, max_q=200, warm_start=True,
+                        tol_gmres=3e-2, gmres_restart=50, max_gmres=4000)
+            s = osm.OsmSolver(pb, dev, **opts)
+            s.factor_rotating(1)
+            u = torch.from_numpy(u0).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ks = []
+            for n in range(1, args.steps + 1):
+                s.factor_rotating(n)
+                ks.append(s.step(u)["k"])
+            torch.cuda.synchronize()
+            T = time.perf_counter() - t0
+            s.close()
+            hours = PAPER_E6_HOURS[algo][N]
+            runs.append({"algo": algo, "N": N, "value": dof * args.steps / T,
+                         "ms_per_step": 1e3 * T / args.steps, "k_mean": float(np.mean(ks)),
+                         "k_max": int(np.max(ks)),
+                         "paper_hours_T0.1": hours,
+                         "paper_dof_steps_per_s": dof * 1000 / (hours * 3600.0)})
+            print(f"bench: {algo} N={N}: {runs[-1]['value']:.4g} dof-steps/s, k mean "
+                  f"{runs[-1]['k_mean']:.1f} (paper {runs[-1]['paper_dof_steps_per_s']:.3g})",
+                  file=sys.stderr, flush=True)
+    best = max(runs, key=lambda r: r["value"])
+    out = {"metric": METRIC, "value": best["value"], "unit": "dof-steps/s", "n_gpus": 1,
+           "steps": args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "c64+f64-refine" if args.prec == "c32" else "c128",
+           "data": "synthetic",
+           "config": {"workload": "paper Section 5.2.2: rotating GPE, (-16,16)^2, 1024^2 cells, "
+                                  "omega=0.4, beta=10.15, dt=1e-4, Robin p=180, refactor every "
+                                  "step", "dof": 1025 * 1025,
+                      "horizon": f"{args.steps} of 1000 steps", "best": {"algo": best["algo"],
+                                                                          "N": best["N"]}},
+           "runs": runs}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 20 for rot2048, 200 for gpe512)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="c32", choices=["fp64", "c32"])
-    ap.add_argument("--fp64-steps", type=int, default=50,
-                    help="steps of the plain FP64 GPU path timed for comparison (0 = skip)")
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="steps of the plain FP64 GPU path timed for comparison (0 = skip; "
+                         "default 3 for rot2048, 50 for gpe512)")
     ap.add_argument("--parity-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="gpe512", choices=["gpe512", "batch64", "learned1024", "rot2048"],
-                    help="gpe512: the single GPE instance (default); batch64: the batch of "
-                         "64 independent NLS instances; learned1024: the learned interface "
-                         "guess, trained and then run on a 1024^2 GPE; rot2048: the rotating "
-                         "GPE on 2048^2 cells and 64 strips, refactored every step")
+    ap.add_argument("--workload", default="rot2048",
+                    choices=["rot2048", "gpe512", "batch64", "learned1024", "paper-e5",
+                             "paper-e6"],
+                    help="rot2048: the rotating GPE on 2048^2 cells and 64 strips, refactored "
+                         "every step (default, the largest single-GPU configuration); gpe512: "
+                         "the 512^2 GPE instance; batch64: the batch of 64 independent NLS "
+                         "instances; learned1024: the learned interface guess, trained and "
+                         "then run on a 1024^2 GPE; paper-e5: the paper's Robin p-sweep on "
+                         "its first NLS mesh (first-step iteration counts); paper-e6: the "
+                         "paper's BEC runs on 1025^2 nodes with Robin p=180")
     ap.add_argument("--train-runs", type=int, default=34)
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--profile-solve", type=int, default=0, metavar="LAUNCHES",
-                    help="profiler mode: only factor + LAUNCHES strip solves + a 1 GiB copy")
+                    help="profiler mode (gpe512): only factor + LAUNCHES strip solves + a 1 GiB copy")
+    ap.add_argument("--p-list", default="",
+                    help="paper-e5: comma-separated Robin parameters (default: 5,10,...,50)")
+    ap.add_argument("--profile-factor", type=int, default=0, metavar="FACTORS",
+                    help="profiler mode (rot2048): setup + FACTORS refactorisations + a 1 GiB copy")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = {"rot2048": 20, "gpe512": 200, "paper-e6": 20}.get(args.workload, 2)
+    if args.fp64_steps is None:
+        args.fp64_steps = 3 if args.workload == "rot2048" else 50
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the strips of one instance are spread over the workgroups of one MI355X.",
@@ -549,6 +825,12 @@ def main():
         return
     if args.workload == "rot2048":
         run_rotating(args, dev)
+        return
+    if args.workload == "paper-e5":
+        run_paper_e5(args, dev)
+        return
+    if args.workload == "paper-e6":
+        run_paper_e6(args, dev)
         return
     wl = c2()
     pb, u0, V = wl.problems[0], wl.u0[0], wl.V[0]
