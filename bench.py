@@ -41,79 +41,49 @@ HBM_PEAK_GBS = 8000.0
 MFMA_FP32_PEAK_TFLOPS = 157.3
 MFMA_FP64_PEAK_TFLOPS = 78.6
 
-# HBM bytes per strip-solve launch from rocprofv3 FETCH_SIZE + WRITE_SIZE on
-# this workload, each scaled by the counter's reading for a 1 GiB copy
-# (fetch x2.0, write x1.0); valid only for the full-row kernel whose source
-# text (the strip_solve_pf_kernel template) hashes to source_sha256.
-SOLVE_TRAFFIC = {"c32": {"bytes": 2.2672e+09,
-                         "source_sha256": "f9cd27c1f2eef86c94452add056158ca7fb70bf24c4a5a5bf5c6fdc5c1de7edc",
-                         "summary": "profiles/strip_solve_c32_gpe512_hbm_counters.md"}}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch), each scaled by the counter's reading for a 1 GiB device copy in
+# the same run (fetch x2.0, write x1.0).  A record holds only while the
+# source files of its kernel hash to source_sha256: any edit to them turns the
+# reported traffic back to null until the counters are taken again.
+TRAFFIC = {
+    ("rot2048", "c32", "sweep_update"): {
+        "bytes": 4.0256e+09,
+        "source_sha256": "0188a515ae068128f803335738cdd412be490495c3eb45af7f1614408e1640bd",
+        "summary": "profiles/sweep_update_c32_rot2048_hbm_counters.md"},
+}
+
+TRAFFIC_SOURCES = {"strip_solve": "kernels_solve.hip", "sweep_update": "kernels_factor.hip"}
 
 
-def pf_kernel_source():
-    """Source text the counters describe: the full-row strip-solve kernel
-    template (its definition up to the closing brace) and the wave-sum
-    helpers it calls."""
+def kernel_source_sha256(kernel):
+    """sha256 over the kernel's source file and the device part of the
+    shared header (its text before the launcher declarations)."""
+    import hashlib
     csrc = os.path.join(ROOT, "paper_1603_05110_amd", "csrc")
     try:
-        src = open(os.path.join(csrc, "kernels_solve.hip")).read()
-        hdr = open(os.path.join(csrc, "osm_internal.h")).read()
+        with open(os.path.join(csrc, TRAFFIC_SOURCES[kernel]), "rb") as fh:
+            src = fh.read()
+        with open(os.path.join(csrc, "osm_internal.h"), "rb") as fh:
+            hdr = fh.read()
     except OSError:
         return None
-    key = "void strip_solve_pf_kernel(SolveArgs a) {"
-    i = src.find(key)
-    if i < 0:
+    cut = hdr.find(b"// ---------------------------------------------------------------- launchers")
+    if cut < 0:
         return None
-    i = src.rfind("template <", 0, i)
-    j = src.find("\n}\n", i)
-    a = hdr.find("template <int CTRL>")
-    b = hdr.find("\n}\n", hdr.find("double wave_sum_f64(double v)"))
-    if j < 0 or a < 0 or b < 0:
+    return hashlib.sha256(src + hdr[:cut]).hexdigest()
+
+
+def measured_traffic(workload, prec, kernel, shape=None):
+    """Counted HBM bytes per launch, or None when no record matches the
+    current sources (and, for the strip solve, the tile shape the
+    autotuner picked)."""
+    rec = TRAFFIC.get((workload, prec, kernel))
+    if rec is None or kernel_source_sha256(kernel) != rec["source_sha256"]:
         return None
-    return src[i:j + 3] + hdr[a:b + 3]
-
-
-def measured_traffic(prec, kernel_name):
-    import hashlib
-    rec = SOLVE_TRAFFIC.get(prec)
-    if rec is None or not kernel_name.startswith("strip_solve_pf_kernel"):
+    if shape is not None and rec.get("shape") not in (None, shape):
         return None
-    src = pf_kernel_source()
-    if src is None:
-        return None
-    sha = hashlib.sha256(src.encode()).hexdigest()
-    return rec["bytes"] if sha == rec["source_sha256"] else None
-
-
-# HBM bytes per sweep-update launch of the rotating 2048^2 factor from
-# rocprofv3 FETCH_SIZE + WRITE_SIZE (scaled as above), valid only while the
-# update kernel's source text (sweep_update_kernel and the MMA helpers above
-# it) hashes to source_sha256.
-FACTOR_TRAFFIC = {}
-
-
-def factor_kernel_source():
-    """Source text the factor counters describe: kernels_factor.hip from the
-    sweep's LDS layout through the end of sweep_update_kernel."""
-    try:
-        src = open(os.path.join(ROOT, "paper_1603_05110_amd", "csrc", "kernels_factor.hip")).read()
-    except OSError:
-        return None
-    i = src.find("template <typename T> struct sweep_lds")
-    k = src.find("void sweep_update_kernel(")
-    j = src.find("\n}\n", k)
-    if i < 0 or k < 0 or j < 0:
-        return None
-    return src[i:j + 3]
-
-
-def measured_factor_traffic(prec):
-    import hashlib
-    rec = FACTOR_TRAFFIC.get(prec)
-    src = factor_kernel_source()
-    if rec is None or src is None:
-        return None
-    return rec["bytes"] if hashlib.sha256(src.encode()).hexdigest() == rec["source_sha256"] else None
+    return rec["bytes"]
 
 
 def solver_opts(prec):
@@ -156,14 +126,14 @@ def run_gpu(pb, u0, V, prec, steps, warmup, dev, measure=True):
                 solve_ms=kern[0], solve_launches=kern[1], solve_work=work, team=team, shape=shape)
 
 
-def profile_solve(pb, V, prec, launches, dev):
+def profile_solve(pb, V, prec, launches, dev, team=0, solve_shape=0):
     """Kernel-level measurement mode for profilers: factor once, then run
     `launches` strip solves on a seeded right-hand side, then one
     device-to-device copy of 1 GiB (the calibration kernel for the HBM byte
     counters: its algorithmic traffic is 1 GiB read + 1 GiB written)."""
     import torch
     from paper_1603_05110_amd import osm
-    s = osm.OsmSolver(pb, dev, **solver_opts(prec))
+    s = osm.OsmSolver(pb, dev, **dict(solver_opts(prec), team=team, solve_shape=solve_shape))
     s.factor(torch.from_numpy(V).to(dev))
     gen = torch.Generator(device="cpu").manual_seed(1603)
     b = torch.randn((s.lt, s.ny), dtype=torch.complex128, generator=gen).to(dev)
@@ -175,7 +145,7 @@ def profile_solve(pb, V, prec, launches, dev):
     torch.cuda.synchronize()
     ms, n = s.kernel_timing(False)
     nbytes = s.kernel_work() / max(n, 1)
-    team = s.solve_team()
+    team, shape = s.solve_team(), s.solve_shape()
     s.close()
     src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
@@ -184,7 +154,9 @@ def profile_solve(pb, V, prec, launches, dev):
     avg = ms / max(n, 1)
     print(json.dumps({"mode": "profile-solve", "prec": prec, "launches": n, "avg_launch_ms": avg,
                       "bytes_per_launch": nbytes, "achieved_GBs": nbytes / (avg * 1e-3) / 1e9,
-                      "workgroups_per_strip": team, "copy_bytes": 2 * src.numel() * 8}),
+                      "workgroups_per_strip": team, "tile_shape": shape,
+                      "source_sha256": kernel_source_sha256("strip_solve"),
+                      "copy_bytes": 2 * src.numel() * 8}),
           flush=True)
 
 
@@ -361,7 +333,8 @@ def run_learned(args, dev):
                       "k_after_step2": int(sum(x["k"] for x in st[2:])),
                       "q_total": int(sum(x["q_total"] for x in st)),
                       "gmres_total": int(sum(x["gmres_total"] for x in st)),
-                      "fallbacks": int(sum(x["fallback_used"] for x in st)),
+                      "fallbacks": int(sum(x["fallback_used"] > 0 for x in st)),
+                      "restarts": int(sum(x["fallback_used"] == 2 for x in st)),
                       "u": u.cpu().numpy()}
         print(f"bench: {name}: {runs[name]['value']:.4g} dof-steps/s, k {runs[name]['k_total']}, "
               f"gmres {runs[name]['gmres_total']}", file=sys.stderr, flush=True)
@@ -436,30 +409,55 @@ def cpu_sample_rotating(pb, W1, u0, k_per_step, nsample=40):
             "seconds": t_fac + t_map}
 
 
-def profile_factor(pb, factors, dev, prec):
-    """Profiler mode for the factor: setup, then `factors` refactorisations
-    of the rotating problem (osm_factor_rotating), then one 1 GiB device copy
-    (the calibration kernel of the HBM byte counters)."""
+def profile_factor(pb, args, dev):
+    """Profiler mode of the rotating workload: setup with the classical
+    algorithm (the factor and the strip solve do not depend on the
+    algorithm; it skips the L_h build), the first factorisation, then
+    --profile-factor refactorisations of the rotating problem
+    (osm_factor_rotating), then --profile-solves strip solves of a seeded
+    right-hand side, then one 1 GiB device-to-device copy (the calibration
+    kernel of the HBM byte counters).  --team and --solve-shape fix the
+    solve's team and tile shape; with both given no solve runs before the
+    timed ones (no autotuning)."""
     import torch
     from paper_1603_05110_amd import osm
-    s = osm.OsmSolver(pb, dev, **solver_opts(prec))
+    opts = dict(solver_opts(args.prec), algo="classical", team=args.team,
+                solve_shape=args.solve_shape)
+    s = osm.OsmSolver(pb, dev, **opts)
     s.factor_rotating(1)
     torch.cuda.synchronize()
     s.kernel_timing(True)
-    for n in range(2, 2 + factors):
+    for n in range(2, 2 + args.profile_factor):
         s.factor_rotating(n)
     torch.cuda.synchronize()
     s.kernel_timing(False)
     ms, n, fl = s.factor_timing()
+    solve = None
+    if args.profile_solves > 0:
+        gen = torch.Generator(device="cpu").manual_seed(1603)
+        b = torch.randn((s.lt, s.ny), dtype=torch.complex128, generator=gen).to(dev)
+        torch.cuda.synchronize()
+        s.kernel_timing(True)
+        for _ in range(args.profile_solves):
+            s.strip_solve(b)
+        torch.cuda.synchronize()
+        sms, sn = s.kernel_timing(False)
+        nbytes = s.kernel_work() / max(sn, 1)
+        savg = sms / max(sn, 1)
+        solve = {"launches": sn, "avg_launch_ms": savg, "bytes_per_launch": nbytes,
+                 "achieved_GBs": nbytes / (savg * 1e-3) / 1e9 if savg > 0 else 0.0,
+                 "workgroups_per_strip": s.solve_team(), "tile_shape": s.solve_shape(),
+                 "source_sha256": kernel_source_sha256("strip_solve")}
     s.close()
     src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"mode": "profile-factor", "prec": prec, "factors": factors,
+    print(json.dumps({"mode": "profile-factor", "prec": args.prec, "factors": args.profile_factor,
                       "update_launches": n, "update_avg_ms": ms / max(n, 1),
                       "update_tflops": fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0,
-                      "update_flops": fl, "copy_bytes": 2 * src.numel() * 8}), flush=True)
+                      "update_flops": fl, "update_source_sha256": kernel_source_sha256("sweep_update"),
+                      "solve": solve, "copy_bytes": 2 * src.numel() * 8}), flush=True)
 
 
 def run_rotating(args, dev):
@@ -482,7 +480,7 @@ def run_rotating(args, dev):
     pb, u0 = wl.problems[0], wl.u0[0]
     dof = (pb.ncx + 1) * (pb.ncy + 1)
     if args.profile_factor > 0:
-        profile_factor(pb, args.profile_factor, dev, args.prec)
+        profile_factor(pb, args, dev)
         return
     print(f"bench: {pb.name} dof={dof} prec={args.prec} steps={args.steps}", file=sys.stderr,
           flush=True)
@@ -621,13 +619,15 @@ def run_rotating(args, dev):
                      "unit": "TFLOP/s",
                      "frac": upd_tflops / MFMA_FP32_PEAK_TFLOPS if args.prec == "c32"
                      else upd_tflops / MFMA_FP64_PEAK_TFLOPS,
-                     "traffic": measured_factor_traffic(args.prec), "flops_timed": fac_fl,
+                     "traffic": measured_traffic("rot2048", args.prec, "sweep_update"),
+                     "flops_timed": fac_fl,
                      "avg_launch_ms": upd_avg_ms, "launches": fac_n,
                      "note": ("algorithmic flops: 8 real flops per complex multiply-add over "
                               "the upper 64x64 tiles each pass updates; the kernel issues 6 "
                               "(three real products)")},
         "solve": {"kernel": "strip_solve", "bound": "hbm", "achieved": achieved,
                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                  "traffic": measured_traffic("rot2048", args.prec, "strip_solve", shape),
                   "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms, "launches": kern[1],
                   "workgroups_per_strip": team, "tile_shape": shape},
         "factor": {"s_per_step": t_fac / args.steps,
@@ -799,7 +799,13 @@ def main():
     ap.add_argument("--p-list", default="",
                     help="paper-e5: comma-separated Robin parameters (default: 5,10,...,50)")
     ap.add_argument("--profile-factor", type=int, default=0, metavar="FACTORS",
-                    help="profiler mode (rot2048): setup + FACTORS refactorisations + a 1 GiB copy")
+                    help="profiler mode (rot2048): setup + FACTORS refactorisations + "
+                         "--profile-solves strip solves + a 1 GiB copy")
+    ap.add_argument("--profile-solves", type=int, default=5)
+    ap.add_argument("--team", type=int, default=0,
+                    help="profiler modes: workgroups per strip in the solve (0 = autotune)")
+    ap.add_argument("--solve-shape", type=int, default=0,
+                    help="profiler modes: strip-solve tile shape + 1 (0 = autotune)")
     args = ap.parse_args()
     if args.steps is None:
         args.steps = {"rot2048": 20, "gpe512": 200, "paper-e6": 20}.get(args.workload, 2)
@@ -838,7 +844,7 @@ def main():
     print(f"bench: {pb.name} dof={dof} prec={args.prec} steps={args.steps}", file=sys.stderr,
           flush=True)
     if args.profile_solve > 0:
-        profile_solve(pb, V, args.prec, args.profile_solve, dev)
+        profile_solve(pb, V, args.prec, args.profile_solve, dev, args.team, args.solve_shape)
         return
 
     main_run = run_gpu(pb, u0, V, args.prec, args.steps, args.warmup, dev)
@@ -915,7 +921,9 @@ def main():
                   "gmres_per_step": float(np.mean(gm))},
         "roofline": {"kernel": solve_kernel, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.prec, solve_kernel), "bytes_per_launch": nbytes,
+                     "traffic": measured_traffic("gpe512", args.prec, "strip_solve",
+                                                 main_run["shape"]),
+                     "bytes_per_launch": nbytes,
                      "avg_launch_ms": avg_ms,
                      "launches": main_run["solve_launches"],
                      "workgroups_per_strip": main_run["team"],

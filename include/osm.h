@@ -139,7 +139,8 @@ typedef struct {
                                      exist; a prediction that ended farther from
                                      g_n than g_{n-1} did disables the next one,
                                      and a step that fails from a prediction is
-                                     restarted from g_{n-1} (stats.fallback_used) */
+                                     restarted from g_{n-1}, and the step after it
+                                     starts from its g_{n-1} (stats.fallback_used) */
     int32_t team;                 /* workgroups per strip in the solve; 0 = auto   */
     uint64_t mem_cap;             /* 0 = free device memory; else a byte cap       */
     double eta_q;                 /* > 0: inexact inner solves; Schwarz iteration k
@@ -186,7 +187,11 @@ typedef struct {
     int32_t q_total;              /* fixed-point iterations summed over k          */
     int32_t gmres_total;          /* GMRES iterations summed over k                */
     int32_t refine_total;         /* FP32 solves corrected by an FP64 residual     */
-    int32_t fallback_used;        /* guess rejected, previous g used instead       */
+    int32_t fallback_used;        /* 0: the start mode's vector was used; 1: the
+                                     prediction was rejected before the step (the
+                                     last judge found it worse than g_{n-1}), g_{n-1}
+                                     used; 2: the step failed from the prediction and
+                                     was restarted from g_{n-1}                     */
     double last_increment;        /* last ||g^{k+1} - g^k||_2                      */
     double mass_before, mass_after; /* u* M u before and after the step           */
 } osm_step_stats;

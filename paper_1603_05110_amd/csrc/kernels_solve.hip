@@ -475,6 +475,21 @@ __device__ __forceinline__ float2 ld_agent2(const float2 *p) {
     return v;
 }
 
+// Loads through a buffer resource (base, byte range): an offset outside the
+// range returns zeros without a memory access (the hardware's range check of
+// raw buffers, dword 3 of the resource as on every gfx9 chip).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_range(const void *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ void range_load(float2 &d, __amdgpu_buffer_rsrc_t rs, unsigned off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+    __builtin_memcpy(&d, &v, sizeof(d));
+}
+__device__ __forceinline__ void range_load(double2 &d, __amdgpu_buffer_rsrc_t rs, unsigned off) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    __builtin_memcpy(&d, &v, sizeof(d));
+}
+
 // Per-wave partial regions in LDS: when NW regions of both products fit
 // (with the product vectors and the finished lines) in 120 KiB, each wave
 // writes its own column sums with plain stores and the workgroup adds the
@@ -482,7 +497,7 @@ __device__ __forceinline__ float2 ld_agent2(const float2 *p) {
 // atomics.  The bound uses the instance's widest line, NCH * 64.
 template <typename T, int NW, int NCH>
 constexpr bool sym_wave_regions() {
-    return (size_t)NW * 2 * NCH * 64 * 2 * sizeof(typename acc_t<T>::type) +
+    return (size_t)(NW + 1) * 2 * NCH * 64 * 2 * sizeof(typename acc_t<T>::type) +
                (size_t)2 * NCH * 64 * 2 * sizeof(T) + (size_t)2 * NCH * 64 * 16 <=
            (size_t)120 * 1024;
 }
@@ -499,8 +514,9 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
     // LDS: the kernel has no static LDS, so the dynamic block starts at 0 and
     // every array is aligned to its element (the 64-bit LDS atomics need
     // it); the partial comes first: either NW per-wave regions [NW][2][n]
-    // of complex sums, or one atomically updated [2][n] real and [2][n]
-    // imaginary partial
+    // of complex column sums (and, after the other arrays, the rows' own
+    // results [2][n]), or one atomically updated [2][n] real and [2][n]
+    // imaginary partial that takes both
     extern __shared__ unsigned char smem_raw[];
     A2 *wreg = reinterpret_cast<A2 *>(smem_raw);
     A *pre = reinterpret_cast<A *>(smem_raw);
@@ -508,6 +524,7 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
     T2 *vecs = WR ? reinterpret_cast<T2 *>(wreg + (size_t)NW * 2 * n)
                   : reinterpret_cast<T2 *>(pim + 2 * n);         // [2][n] product vectors
     double2 *red = reinterpret_cast<double2 *>(vecs + 2 * n);    // [2][n] lines finished last step
+    A2 *rres = reinterpret_cast<A2 *>(red + 2 * n);              // [2][n] row results (WR)
     const int nst = a.nstrips, team = a.team;
     const int j = blockIdx.x % nst, w = blockIdx.x / nst;
     const StripMeta s = a.strips[j];
@@ -523,7 +540,15 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
     const long nn = (long)n * n;
     const int S = tw_steps(s.nx);
     const double sc = strip_scale(a.lmax ? a.lmax + s.off : nullptr, s.nx), inv = 1.0 / sc;
-    T2 m[PR][NCH];
+    // The wave's rows k = 0, 1, ... of a step go in groups of PR: the loads of
+    // a whole group are issued together, PR rows in flight, and its rows are
+    // then multiplied in order as their chunks arrive.  A row is loaded
+    // through a buffer resource whose range is its upper part [r, n): the
+    // lanes left of the diagonal and past the end of the line get zeros from
+    // the range check, without a memory access, and a row past the end of the
+    // wave's list has an empty range.  Every group thus issues exactly
+    // PR * NCH loads with no branch and no mask.
+    T2 m[PR][NCH], dg[PR];
 
     auto entry = [&](const TwStep &t, int rho) -> int {
         if (t.lt >= 0) {
@@ -537,22 +562,34 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
     auto kind_of = [&](const TwStep &t, int p) -> int { return p == 0 ? t.kt : t.kb; };
     auto own = [&](int c) -> bool { return c % team == w; };
     auto has = [&](const TwStep &t, int p) -> bool { return (p == 0 ? t.lt : t.lb) >= 0; };
-    // rows of a step: only the upper-triangle part (columns >= r) is loaded
-    auto prefetch = [&](const TwStep &t) {
+    // The per-chunk quantities (column index, clamps, masks, LDS addresses)
+    // are cheap to recompute but invariant across rows; the lane index and n
+    // pass through an empty asm once per group so that they are recomputed
+    // there instead of being hoisted out of the row loop, where 2 x NCH of
+    // them would stay live next to the row buffers.
+    auto opaque_v = [](int v) { asm volatile("" : "+v"(v)); return v; };
+    auto opaque_s = [](int v) { asm volatile("" : "+s"(v)); return v; };
+    // rows k .. k + PR - 1 of the wave's list, those from k1 on not wanted
+    auto load_group = [&](const TwStep &t, int k, int k1, T2 (&m)[PR][NCH], T2 (&dg)[PR]) {
+        const int lane_ = opaque_v(lane);
 #pragma unroll
         for (int u = 0; u < PR; ++u) {
-            const int e = entry(t, wave + NW * u);
+            const int e = k + u < k1 ? entry(t, wave + NW * (k + u)) : -1;
             const bool ok = e >= 0;
-            const int p = e >> 16, r = e & 0xFFFF;
-            const T2 *M = ok ? F + line_of(t, p) * nn + (long)r * n : F;
+            const int p = e >> 16, r = ok ? e & 0xFFFF : 0;
+            const T2 *D = ok ? F + line_of(t, p) * nn + (long)r * n + r : F;
+            const __amdgpu_buffer_rsrc_t rs = row_range(D, ok ? (n - r) * (int)sizeof(T2) : 0);
+            dg[u] = *D;                                 // the diagonal element (uniform)
+            // byte offset of column c * 64 + lane from the diagonal: negative
+            // offsets wrap past the range
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const int col = c * 64 + lane;
-                if (ok && col < n && col >= r) m[u][c] = M[col];
-                else { m[u][c].x = 0; m[u][c].y = 0; }
-            }
+            for (int c = 0; c < NCH; ++c)
+                range_load(m[u][c], rs, (unsigned)(c * 64 + lane_ - r) * (unsigned)sizeof(T2));
         }
     };
+    // the wave's first rows of a step (its product from above, else from
+    // below), loaded before the team barrier
+    auto prefetch = [&](const TwStep &t) { load_group(t, 0, 0x7FFFFFFF, m, dg); };
 
     // Backward lines overwrite the forward result that every member reads
     // while finishing them, so their rows go to x one barrier later, from
@@ -660,105 +697,117 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
         }
         if constexpr (!WR)
             for (int i = threadIdx.x; i < 4 * n; i += NTHR) pre[i] = 0;
+        else
+            for (int i = threadIdx.x; i < 2 * n; i += NTHR) {
+                A2 z;
+                z.x = 0;
+                z.y = 0;
+                rres[i] = z;
+            }
         __syncthreads();
-        // row phase: each row's dot goes to the LDS partial at once (one lane);
+        // row phase: each row's dot goes to the partial (its own column);
         // its column contributions F[r][c] v_r (c > r) accumulate per lane in
         // registers over the wave's rows of a product and are added to the
-        // LDS partial once per product.  One loop, one row body and one flush
-        // for the rows held in registers (k < PR) and the streamed ones.
+        // partial once per product
         A cr[NCH], ci[NCH];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) { cr[c] = 0; ci[c] = 0; }
-        int cur = -1, flushed = 0;
-        for (int k = 0;; ++k) {
-            const int e = entry(t, wave + NW * k);
-            const int p = e < 0 ? -1 : e >> 16;
-            if (p != cur) {
-                if (cur >= 0) {
-                    if constexpr (WR) {
-                        A2 *q = wreg + (size_t)(wave * 2 + cur) * n;
-#pragma unroll
-                        for (int c = 0; c < NCH; ++c) {
-                            const int col = c * 64 + lane;
-                            if (col < n) {
-                                A2 v;
-                                v.x = cr[c];
-                                v.y = ci[c];
-                                q[col] = v;
-                            }
-                            cr[c] = 0;
-                            ci[c] = 0;
-                        }
-                        flushed |= 1 << cur;
-                    } else {
-                        A *qre = pre + cur * n, *qim = pim + cur * n;
-#pragma unroll
-                        for (int c = 0; c < NCH; ++c) {
-                            const int col = c * 64 + lane;
-                            if (col < n) {
-                                atomicAdd(&qre[col], cr[c]);
-                                atomicAdd(&qim[col], ci[c]);
-                            }
-                            cr[c] = 0;
-                            ci[c] = 0;
-                        }
-                    }
-                }
-                cur = p;
-            }
-            if (e < 0) break;
-            const int r = e & 0xFFFF;
-            // the row sits in m[0]: rows held in registers are shifted down
-            // one slot per row, streamed rows are loaded into the freed slot
-            if (k > 0 && k < PR) {
-#pragma unroll
-                for (int u = 0; u + 1 < PR; ++u)
-#pragma unroll
-                    for (int c = 0; c < NCH; ++c) m[u][c] = m[u + 1][c];
-            }
-            if (k >= PR) {
-                const T2 *M = F + line_of(t, p) * nn + (long)r * n;
+        int flushed = 0;
+        auto flush = [&](int p) {
+            const int lane_ = opaque_v(lane), n_ = opaque_s(n);
+            if constexpr (WR) {
+                A2 *q = wreg + (size_t)(wave * 2 + p) * n;
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
-                    const int col = c * 64 + lane;
-                    if (col < n && col >= r) m[0][c] = M[col];
-                    else { m[0][c].x = 0; m[0][c].y = 0; }
+                    const int col = c * 64 + lane_;
+                    if (col < n_) {
+                        A2 v;
+                        v.x = cr[c];
+                        v.y = ci[c];
+                        q[col] = v;
+                    }
+                    cr[c] = 0;
+                    ci[c] = 0;
+                }
+            } else {
+                A *qre = pre + p * n, *qim = pim + p * n;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int col = c * 64 + lane_;
+                    if (col < n_) {
+                        atomicAdd(&qre[col], cr[c]);
+                        atomicAdd(&qim[col], ci[c]);
+                    }
+                    cr[c] = 0;
+                    ci[c] = 0;
                 }
             }
-            const T2 (&mm)[NCH] = m[0];
+            flushed |= 1 << p;
+        };
+        // the product's vector, chunk c of it in lane order, is the same for
+        // every row of the product: held in registers, one LDS read per
+        // chunk and product
+        T2 vv[NCH];
+        auto load_vec = [&](int p) {
+            const int lane_ = opaque_v(lane), n_ = opaque_s(n);
             const T2 *vec = vecs + p * n;
-            const T2 vr = vec[r];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) vv[c] = vec[min(c * 64 + lane_, n_ - 1)];
+        };
+        // A row adds its dot to column r and F[r][c] v_r to every column
+        // c >= r; the diagonal term, in both, is taken out of the first once.
+        // Every chunk is multiplied (the zeros left of the diagonal too): a
+        // skipped chunk would leave its load unwaited on that path, and a
+        // later write of its register would wait for every load in flight.
+        auto row = [&](int k, const T2 (&mm)[NCH], const T2 &d) {
+            const int e = entry(t, wave + NW * k);
+            const int p = e >> 16, r = e & 0xFFFF;
+            const T2 vr = vecs[p * n + r];
             A dr = 0, di = 0;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                if (c * 64 + 63 < r) continue;          // chunk left of the diagonal
-                const int col = c * 64 + lane;
-                T2 v;
-                if (col < n) v = vec[col];
-                else { v.x = 0; v.y = 0; }
-                const A mx = mm[c].x, my = mm[c].y;
-                dr += mx * v.x - my * v.y;
-                di += mx * v.y + my * v.x;
-                const A ox = col > r ? mx : (A)0, oy = col > r ? my : (A)0;
-                cr[c] += ox * (A)vr.x - oy * (A)vr.y;
-                ci[c] += ox * (A)vr.y + oy * (A)vr.x;
+                const A mx = (A)mm[c].x, my = (A)mm[c].y;
+                const T2 v = vv[c];
+                dr += mx * (A)v.x - my * (A)v.y;
+                di += mx * (A)v.y + my * (A)v.x;
+                cr[c] += mx * (A)vr.x - my * (A)vr.y;
+                ci[c] += mx * (A)vr.y + my * (A)vr.x;
             }
             dr = wave_sum(dr);
             di = wave_sum(di);
-            if constexpr (WR) {
-                // the row's own result joins column r of the column sums,
-                // held by lane r % 64 in chunk r / 64 (every lane has the sum)
-#pragma unroll
-                for (int c = 0; c < NCH; ++c)
-                    if (c == (r >> 6) && lane == (r & 63)) {
-                        cr[c] += dr;
-                        ci[c] += di;
-                    }
-            } else if (lane == 0) {
-                atomicAdd(&pre[p * n + r], dr);
-                atomicAdd(&pim[p * n + r], di);
+            if (lane == 0) {
+                const A gx = (A)d.x * (A)vr.x - (A)d.y * (A)vr.y;
+                const A gy = (A)d.x * (A)vr.y + (A)d.y * (A)vr.x;
+                if constexpr (WR) {
+                    // row r belongs to one wave of one member: a plain store
+                    A2 q;
+                    q.x = dr - gx;
+                    q.y = di - gy;
+                    rres[p * n + r] = q;
+                } else {
+                    atomicAdd(&pre[p * n + r], dr - gx);
+                    atomicAdd(&pim[p * n + r], di - gy);
+                }
             }
-        }
+        };
+        // this wave's rows of the step: k < K0 in the product from above
+        const int R0 = has(t, 0) ? R : 0, Rt = R0 + (has(t, 1) ? R : 0);
+        const int K0 = R0 > wave ? (R0 - wave + NW - 1) / NW : 0;
+        const int Kt = Rt > wave ? (Rt - wave + NW - 1) / NW : 0;
+        // one loop per product: rows k0 .. k1 - 1 in groups of PR, the first
+        // group already loaded when it was prefetched
+        auto run = [&](int p, int k0, int k1, bool first_loaded) {
+            load_vec(p);
+            for (int k = k0; k < k1; k += PR) {
+                if (k > k0 || !first_loaded) load_group(t, k, k1, m, dg);
+#pragma unroll
+                for (int u = 0; u < PR; ++u)
+                    if (k + u < k1) row(k + u, m[u], dg[u]);
+            }
+            flush(p);
+        };
+        if (K0 > 0) run(0, 0, K0, true);
+        if (Kt > K0) run(1, K0, Kt, K0 == 0);
         if constexpr (WR) {
             // a product this wave had no rows of gets a zero region
             for (int p = 0; p < 2; ++p) {
@@ -786,8 +835,9 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
                             sr += q.x;
                             si += q.y;
                         }
-                        v.x = (T)sr;
-                        v.y = (T)si;
+                        const A2 q = rres[p * n + c];
+                        v.x = (T)(sr + q.x);
+                        v.y = (T)(si + q.y);
                     } else {
                         v.x = (T)pre[p * n + c];
                         v.y = (T)pim[p * n + c];
@@ -1065,23 +1115,29 @@ Variant variant_sym_for(int n, int fp32, int shape) {
                     (int)sym_wave_regions<float, 8, 17>()};
             if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 1>, 512,
                     (int)sym_wave_regions<float, 8, 17>()};
-            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 16, 17, 1>, 1024,
-                    (int)sym_wave_regions<float, 16, 17>()};
-            return {(const void *)strip_solve_sym_kernel<float, 4, 17, 2>, 256,
+            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 4, 17, 4>, 256,
+                    (int)sym_wave_regions<float, 4, 17>()};
+            return {(const void *)strip_solve_sym_kernel<float, 4, 17, 3>, 256,
                     (int)sym_wave_regions<float, 4, 17>()};
         }
         if (nch <= 33) {
-            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 4, 33, 1>, 256,
-                    (int)sym_wave_regions<float, 4, 33>()};
-            return {(const void *)strip_solve_sym_kernel<float, 8, 33, 1>, 512,
+            // one workgroup per CU (the LDS of ny ~ 2049): rows in flight per
+            // CU = waves x rows per group
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 33, 1>, 512,
                     (int)sym_wave_regions<float, 8, 33>()};
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 4, 33, 2>, 256,
+                    (int)sym_wave_regions<float, 4, 33>()};
+            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 4, 33, 3>, 256,
+                    (int)sym_wave_regions<float, 4, 33>()};
+            return {(const void *)strip_solve_sym_kernel<float, 4, 33, 4>, 256,
+                    (int)sym_wave_regions<float, 4, 33>()};
         }
         return {nullptr, 0};
     }
     if (nch <= 3) {
         if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 3, 4>, 512,
                     (int)sym_wave_regions<double, 8, 3>()};
-        return {(const void *)strip_solve_sym_kernel<double, 16, 3, 4>, 1024,
+        return {(const void *)strip_solve_sym_kernel<double, 16, 3, 2>, 1024,
                     (int)sym_wave_regions<double, 16, 3>()};
     }
     if (nch <= 9) {
@@ -1089,16 +1145,20 @@ Variant variant_sym_for(int n, int fp32, int shape) {
                     (int)sym_wave_regions<double, 8, 9>()};
         if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 1>, 512,
                     (int)sym_wave_regions<double, 8, 9>()};
-        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 16, 9, 1>, 1024,
-                    (int)sym_wave_regions<double, 16, 9>()};
+        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 4, 9, 4>, 256,
+                    (int)sym_wave_regions<double, 4, 9>()};
         return {(const void *)strip_solve_sym_kernel<double, 8, 9, 2>, 512,
                     (int)sym_wave_regions<double, 8, 9>()};
     }
     if (nch <= 17) {
-        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 4, 17, 1>, 256,
-                    (int)sym_wave_regions<double, 4, 17>()};
-        return {(const void *)strip_solve_sym_kernel<double, 8, 17, 1>, 512,
+        if (shape == 0) return {(const void *)strip_solve_sym_kernel<double, 8, 17, 1>, 512,
                     (int)sym_wave_regions<double, 8, 17>()};
+        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 4, 17, 2>, 256,
+                    (int)sym_wave_regions<double, 4, 17>()};
+        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 4, 17, 3>, 256,
+                    (int)sym_wave_regions<double, 4, 17>()};
+        return {(const void *)strip_solve_sym_kernel<double, 4, 17, 1>, 256,
+                    (int)sym_wave_regions<double, 4, 17>()};
     }
     return {nullptr, 0, 0};
 }
@@ -1108,7 +1168,7 @@ size_t solve_smem(int n, int fp32, int sym, const Variant &v) {
     const size_t e2 = fp32 ? sizeof(float2) : sizeof(double2), ea = fp32 ? 4 : 8;
     if (!sym) return 2 * (size_t)n * e2 + (v.ofwd ? 2 * (size_t)n * sizeof(double2) : 0);
     const size_t rest = 2 * (size_t)n * e2 + 2 * (size_t)n * sizeof(double2);
-    if (v.wregs) return (size_t)(v.threads / 64) * 2 * n * 2 * ea + rest;
+    if (v.wregs) return (size_t)(v.threads / 64 + 1) * 2 * n * 2 * ea + rest;
     return rest + 4 * (size_t)n * ea;
 }
 

@@ -1613,9 +1613,11 @@ osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats) {
     HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
     if (h->pm) HIPCHK(h, pade_reset(h, nullptr));
     s = o.algo == OSM_INTERFACE_KRYLOV ? interface_step(h, u, &S) : schwarz_device(h, u, &S);
+    bool retried = false;
     if (used_pred && (s == OSM_ENOCONV || s == OSM_ENONFINITE)) {
         // the predicted start failed (u is untouched): restart the step from
         // the previous converged vector and do not predict on the next step
+        retried = true;
         HIPCHK(h, hipMemcpyAsync(h->g, h->g_last, gbytes, hipMemcpyDeviceToDevice, h->st));
         HIPCHK(h, launch_copy_u_to_strips(h->st, h->P, h->strips_d, h->line_strip_d, u, h->zeta));
         if (h->pm) HIPCHK(h, pade_reset(h, nullptr));
@@ -1624,13 +1626,17 @@ osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats) {
         s = mass_of(h, u, &S.mass_before);
         if (s == OSM_OK) s = schwarz_device(h, u, &S);
     }
-    S.fallback_used = predicted && !used_pred;
+    S.fallback_used = retried ? 2 : (predicted && !used_pred ? 1 : 0);
     if (s != OSM_OK) {
         if (stats) *stats = S;
         return s;
     }
     if (history) {
-        if (predicted) {
+        if (retried) {
+            // a start that did not converge is not judged by its distance:
+            // the next step starts from its previous converged vector
+            h->fallback_next = true;
+        } else if (predicted) {
             // judge the prediction against the converged vector
             int nb = (h->ng + 255) / 256;
             HIPCHK(h, launch_net_judge(h->st, h->ng, h->g, h->g_pred, h->g_last, h->judge_part));

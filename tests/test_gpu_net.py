@@ -215,4 +215,11 @@ def test_bad_network_falls_back_and_keeps_the_answer():
     u, st = _run(pb, u0, V, pb.steps, 2, net)
     net.close()
     assert rel(u, ref) < 1e-10
-    assert sum(x["fallback_used"] for x in st) >= 1
+    codes = [x["fallback_used"] for x in st]
+    log(f"  fallback codes per step {codes}")
+    assert sum(c > 0 for c in codes) >= 1
+    # a step restarted after its predicted start failed is followed by a
+    # step that does not use the prediction
+    for a, b in zip(codes, codes[1:]):
+        if a == 2:
+            assert b >= 1, codes

@@ -47,3 +47,33 @@ def test_mesh1_first_step_counts(N, p, algo, prec, paper):
         ref = run_monolithic(pb, u0, W, 1, tol_q=1e-14)
         got = u.cpu().numpy()
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
+
+
+@pytest.mark.parametrize("N,algo,prec,paper", [
+    (2, "classical", "fp64", 18), (32, "classical", "c32", 18),
+    (2, "precond", "fp64", 6), (32, "precond", "c32", 6),
+])
+def test_mesh1_pade_first_step_counts(N, algo, prec, paper):
+    """Section 5.1.2, Table Niter_Time_2_32_NL_abc2p: S_pade^m on the first
+    mesh, zero first interface vector, the same stopping rule; the paper
+    prints 18 classical and 6 preconditioned iterations for every N.  The
+    paper does not state m; with m = 6 the oracle takes 19 (N = 2 and 32)
+    and 5 (N = 2, preconditioned)."""
+    from oracle.pade import pade_monolithic
+    from paper_1603_05110_amd import osm
+    wl = nls_mesh1(N, 0.0, steps=1)
+    pb = wl.problems[0].replace(tc="pade", pade_m=6, p=0.0, p_bc=0.0)
+    u0, W = wl.u0[0], wl.V[0]
+    log(f"mesh 1, S_pade m=6, N={N}, {algo}, {prec}")
+    s = osm.OsmSolver(pb, DEV, algo=algo, prec=prec, tol_k=1e-10, tol_k_relative=False,
+                      max_k=2000, tol_q=1e-13, max_q=200, warm_start=True, tol_gmres=1e-12)
+    s.factor(torch.from_numpy(W).to(DEV))
+    u = torch.from_numpy(u0).to(DEV)
+    st = s.step(u)
+    s.close()
+    log(f"  k={st['k']} (paper {paper}), q={st['q_total']}, gmres={st['gmres_total']}")
+    assert abs(st["k"] - paper) <= 0.2 * paper
+    if N == 2 and algo == "precond":
+        ref = pade_monolithic(pb, u0, W, 1, tol_q=1e-14)
+        got = u.cpu().numpy()
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10

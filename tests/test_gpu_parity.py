@@ -115,6 +115,41 @@ def test_every_solve_tile_shape_matches_oracle(prec, tol, ncy, solve_shape):
         assert np.max(np.abs(x - want)) < tol * np.max(np.abs(want)), team
 
 
+@pytest.mark.parametrize("prec,tol,ncy", [("c32", 2e-6, 1000), ("c32", 2e-6, 2048),
+                                          ("fp64", 1e-12, 1000)])
+@pytest.mark.parametrize("solve_shape", [5, 6, 7, 8])
+def test_upper_triangle_tiles_on_long_lines(prec, tol, ncy, solve_shape):
+    """The upper-triangle kernel's tiles for 17 and 33 column chunks (lines of
+    1001 and 2049 nodes, the rotating workload's), forced, with the
+    autotuned team and a team of 3: rows read through range-checked buffer
+    loads, the diagonal taken out once, rows past the end of a wave's list."""
+    log(f"upper-triangle shape {solve_shape} {prec} ny={ncy + 1}")
+    osm = _osm()
+    cells = (4, 6, 3)
+    pb = Problem(-3.0, 3.0, -16.0, 16.0, sum(cells), ncy, 3, list(cells), lap_coef=0.5, beta=-20.0,
+                 p=4.0, p_bc=4.0, dt=5e-3)
+    _, W = rand_state(pb, 9)
+    orc = SchwarzOracle(pb, W)
+    rng = np.random.default_rng(10)
+    bs = [rng.standard_normal((c + 1, pb.ncy + 1)) + 1j * rng.standard_normal((c + 1, pb.ncy + 1))
+          for c in cells]
+    ref = [orc._lu[j].solve(bs[j].ravel()).reshape(bs[j].shape) for j in range(len(cells))]
+    want = packed(orc, ref)
+    for team in (0, 3):
+        s = osm.OsmSolver(pb, DEV, prec=prec, solve_shape=solve_shape, team=team)
+        s.factor(to_dev(W))
+        x = s.strip_solve(to_dev(packed(orc, bs))).cpu().numpy()
+        assert s.solve_shape() == solve_shape - 1
+        s.close()
+        assert np.all(np.isfinite(x)), team
+        assert rel(x, want) < tol, team
+        for j in range(len(cells)):
+            o = orc.starts[j] + j
+            sl = slice(o, o + cells[j] + 1)
+            assert rel(x[sl], want[sl]) < tol, (team, j)
+        assert np.max(np.abs(x - want)) < tol * np.max(np.abs(want)), team
+
+
 @pytest.mark.parametrize("fixed_k,fixed_q", [(1, 1), (3, 2)])
 def test_fixed_iteration_classical_matches_oracle(fixed_k, fixed_q):
     """Same (k, q) counts, cold fixed-point start: rounding-level agreement of
