@@ -502,7 +502,7 @@ constexpr bool sym_wave_regions() {
            (size_t)120 * 1024;
 }
 
-template <typename T, int NW, int NCH, int PR>
+template <typename T, int NW, int NCH, int PR, int SPLIT>
 __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
     typedef typename cplx_of<T>::type T2;
     typedef typename acc_t<T>::type A;
@@ -540,15 +540,22 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
     const long nn = (long)n * n;
     const int S = tw_steps(s.nx);
     const double sc = strip_scale(a.lmax ? a.lmax + s.off : nullptr, s.nx), inv = 1.0 / sc;
-    // The wave's rows k = 0, 1, ... of a step go in groups of PR: the loads of
-    // a whole group are issued together, PR rows in flight, and its rows are
-    // then multiplied in order as their chunks arrive.  A row is loaded
-    // through a buffer resource whose range is its upper part [r, n): the
-    // lanes left of the diagonal and past the end of the line get zeros from
-    // the range check, without a memory access, and a row past the end of the
-    // wave's list has an empty range.  Every group thus issues exactly
-    // PR * NCH loads with no branch and no mask.
-    T2 m[PR][NCH], dg[PR];
+    // The waves form NG groups of SPLIT: the waves of a group share their
+    // rows, wave h of the group taking the chunks c = jj SPLIT + h of each
+    // (interleaved, so that the halves of the triangle balance), which
+    // divides the registers a row, the vector and the column sums need by
+    // SPLIT.  A group's rows k = 0, 1, ... of a step go in groups of PR: the
+    // loads of a whole group are issued together, PR rows in flight, and
+    // its rows are then multiplied in order as their chunks arrive.  A row
+    // is loaded through a buffer resource whose range is its upper part
+    // [r, n): the lanes left of the diagonal and past the end of the line
+    // get zeros from the range check, without a memory access, and a row
+    // past the end of the list has an empty range.  Every group thus issues
+    // exactly PR * NCW loads with no branch and no mask.
+    constexpr int NG = NW / SPLIT, NCW = (NCH + SPLIT - 1) / SPLIT;
+    static_assert(NW % SPLIT == 0, "waves must form whole groups");
+    const int h = wave % SPLIT, grp = wave / SPLIT;
+    T2 m[PR][NCW], dg[PR];
 
     auto entry = [&](const TwStep &t, int rho) -> int {
         if (t.lt >= 0) {
@@ -570,11 +577,11 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
     auto opaque_v = [](int v) { asm volatile("" : "+v"(v)); return v; };
     auto opaque_s = [](int v) { asm volatile("" : "+s"(v)); return v; };
     // rows k .. k + PR - 1 of the wave's list, those from k1 on not wanted
-    auto load_group = [&](const TwStep &t, int k, int k1, T2 (&m)[PR][NCH], T2 (&dg)[PR]) {
-        const int lane_ = opaque_v(lane);
+    auto load_group = [&](const TwStep &t, int k, int k1, T2 (&m)[PR][NCW], T2 (&dg)[PR]) {
+        const int lane_ = opaque_v(lane) + 64 * h;
 #pragma unroll
         for (int u = 0; u < PR; ++u) {
-            const int e = k + u < k1 ? entry(t, wave + NW * (k + u)) : -1;
+            const int e = k + u < k1 ? entry(t, grp + NG * (k + u)) : -1;
             const bool ok = e >= 0;
             const int p = e >> 16, r = ok ? e & 0xFFFF : 0;
             const T2 *D = ok ? F + line_of(t, p) * nn + (long)r * n + r : F;
@@ -583,8 +590,8 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
             // byte offset of column c * 64 + lane from the diagonal: negative
             // offsets wrap past the range
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                range_load(m[u][c], rs, (unsigned)(c * 64 + lane_ - r) * (unsigned)sizeof(T2));
+            for (int jj = 0; jj < NCW; ++jj)
+                range_load(m[u][jj], rs, (unsigned)(jj * SPLIT * 64 + lane_ - r) * (unsigned)sizeof(T2));
         }
     };
     // the wave's first rows of a step (its product from above, else from
@@ -709,17 +716,17 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
         // its column contributions F[r][c] v_r (c > r) accumulate per lane in
         // registers over the wave's rows of a product and are added to the
         // partial once per product
-        A cr[NCH], ci[NCH];
+        A cr[NCW], ci[NCW];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) { cr[c] = 0; ci[c] = 0; }
+        for (int c = 0; c < NCW; ++c) { cr[c] = 0; ci[c] = 0; }
         int flushed = 0;
         auto flush = [&](int p) {
-            const int lane_ = opaque_v(lane), n_ = opaque_s(n);
+            const int lane_ = opaque_v(lane) + 64 * h, n_ = opaque_s(n);
             if constexpr (WR) {
                 A2 *q = wreg + (size_t)(wave * 2 + p) * n;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    const int col = c * 64 + lane_;
+                for (int c = 0; c < NCW; ++c) {
+                    const int col = c * SPLIT * 64 + lane_;
                     if (col < n_) {
                         A2 v;
                         v.x = cr[c];
@@ -732,8 +739,8 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
             } else {
                 A *qre = pre + p * n, *qim = pim + p * n;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    const int col = c * 64 + lane_;
+                for (int c = 0; c < NCW; ++c) {
+                    const int col = c * SPLIT * 64 + lane_;
                     if (col < n_) {
                         atomicAdd(&qre[col], cr[c]);
                         atomicAdd(&qim[col], ci[c]);
@@ -747,25 +754,25 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
         // the product's vector, chunk c of it in lane order, is the same for
         // every row of the product: held in registers, one LDS read per
         // chunk and product
-        T2 vv[NCH];
+        T2 vv[NCW];
         auto load_vec = [&](int p) {
-            const int lane_ = opaque_v(lane), n_ = opaque_s(n);
+            const int lane_ = opaque_v(lane) + 64 * h, n_ = opaque_s(n);
             const T2 *vec = vecs + p * n;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) vv[c] = vec[min(c * 64 + lane_, n_ - 1)];
+            for (int c = 0; c < NCW; ++c) vv[c] = vec[min(c * SPLIT * 64 + lane_, n_ - 1)];
         };
         // A row adds its dot to column r and F[r][c] v_r to every column
         // c >= r; the diagonal term, in both, is taken out of the first once.
         // Every chunk is multiplied (the zeros left of the diagonal too): a
         // skipped chunk would leave its load unwaited on that path, and a
         // later write of its register would wait for every load in flight.
-        auto row = [&](int k, const T2 (&mm)[NCH], const T2 &d) {
-            const int e = entry(t, wave + NW * k);
+        auto row = [&](int k, const T2 (&mm)[NCW], const T2 &d) {
+            const int e = entry(t, grp + NG * k);
             const int p = e >> 16, r = e & 0xFFFF;
             const T2 vr = vecs[p * n + r];
             A dr = 0, di = 0;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
+            for (int c = 0; c < NCW; ++c) {
                 const A mx = (A)mm[c].x, my = (A)mm[c].y;
                 const T2 v = vv[c];
                 dr += mx * (A)v.x - my * (A)v.y;
@@ -776,24 +783,28 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
             dr = wave_sum(dr);
             di = wave_sum(di);
             if (lane == 0) {
-                const A gx = (A)d.x * (A)vr.x - (A)d.y * (A)vr.y;
-                const A gy = (A)d.x * (A)vr.y + (A)d.y * (A)vr.x;
-                if constexpr (WR) {
+                // the group's first wave takes the diagonal out
+                const A gx = h == 0 ? (A)d.x * (A)vr.x - (A)d.y * (A)vr.y : (A)0;
+                const A gy = h == 0 ? (A)d.x * (A)vr.y + (A)d.y * (A)vr.x : (A)0;
+                if constexpr (WR && SPLIT == 1) {
                     // row r belongs to one wave of one member: a plain store
                     A2 q;
                     q.x = dr - gx;
                     q.y = di - gy;
                     rres[p * n + r] = q;
+                } else if constexpr (WR) {
+                    atomicAdd(&rres[p * n + r].x, dr - gx);
+                    atomicAdd(&rres[p * n + r].y, di - gy);
                 } else {
                     atomicAdd(&pre[p * n + r], dr - gx);
                     atomicAdd(&pim[p * n + r], di - gy);
                 }
             }
         };
-        // this wave's rows of the step: k < K0 in the product from above
+        // this wave group's rows of the step: k < K0 in the product from above
         const int R0 = has(t, 0) ? R : 0, Rt = R0 + (has(t, 1) ? R : 0);
-        const int K0 = R0 > wave ? (R0 - wave + NW - 1) / NW : 0;
-        const int Kt = Rt > wave ? (Rt - wave + NW - 1) / NW : 0;
+        const int K0 = R0 > grp ? (R0 - grp + NG - 1) / NG : 0;
+        const int Kt = Rt > grp ? (Rt - grp + NG - 1) / NG : 0;
         // one loop per product: rows k0 .. k1 - 1 in groups of PR, the first
         // group already loaded when it was prefetched
         auto run = [&](int p, int k0, int k1, bool first_loaded) {
@@ -828,10 +839,13 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
                 for (int c = w + threadIdx.x; c < n; c += NTHR) {
                     T2 v;
                     if constexpr (WR) {
+                        // column c's sums are in the regions of the waves
+                        // that take its chunk
                         A sr = 0, si = 0;
+                        const int hc = (c >> 6) % SPLIT;
 #pragma unroll
-                        for (int u = 0; u < NW; ++u) {
-                            const A2 q = wreg[(size_t)(u * 2 + p) * n + c];
+                        for (int u = 0; u < NW; u += SPLIT) {
+                            const A2 q = wreg[(size_t)((u + hc) * 2 + p) * n + c];
                             sr += q.x;
                             si += q.y;
                         }
@@ -1093,72 +1107,72 @@ Variant variant_sym_for(int n, int fp32, int shape) {
     shape = shape < 0 ? 0 : (shape >= SOLVE_SHAPES ? SOLVE_SHAPES - 1 : shape);
     if (fp32) {
         if (nch <= 3) {
-            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 3, 8>, 512,
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 3, 8, 1>, 512,
                     (int)sym_wave_regions<float, 8, 3>()};
-            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 3, 3>, 512,
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 3, 3, 1>, 512,
                     (int)sym_wave_regions<float, 8, 3>()};
-            return {(const void *)strip_solve_sym_kernel<float, 16, 3, 2>, 1024,
+            return {(const void *)strip_solve_sym_kernel<float, 16, 3, 2, 1>, 1024,
                     (int)sym_wave_regions<float, 16, 3>()};
         }
         if (nch <= 9) {
-            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 5>, 512,
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 5, 1>, 512,
                     (int)sym_wave_regions<float, 8, 9>()};
-            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 2>, 512,
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 9, 2, 1>, 512,
                     (int)sym_wave_regions<float, 8, 9>()};
-            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 16, 9, 2>, 1024,
+            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 16, 9, 2, 1>, 1024,
                     (int)sym_wave_regions<float, 16, 9>()};
-            return {(const void *)strip_solve_sym_kernel<float, 8, 9, 3>, 512,
+            return {(const void *)strip_solve_sym_kernel<float, 8, 9, 3, 1>, 512,
                     (int)sym_wave_regions<float, 8, 9>()};
         }
         if (nch <= 17) {
-            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 2>, 512,
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 2, 1>, 512,
                     (int)sym_wave_regions<float, 8, 17>()};
-            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 1>, 512,
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 17, 1, 1>, 512,
                     (int)sym_wave_regions<float, 8, 17>()};
-            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 4, 17, 4>, 256,
+            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 4, 17, 4, 1>, 256,
                     (int)sym_wave_regions<float, 4, 17>()};
-            return {(const void *)strip_solve_sym_kernel<float, 4, 17, 3>, 256,
+            return {(const void *)strip_solve_sym_kernel<float, 4, 17, 3, 1>, 256,
                     (int)sym_wave_regions<float, 4, 17>()};
         }
         if (nch <= 33) {
             // one workgroup per CU (the LDS of ny ~ 2049): rows in flight per
             // CU = waves x rows per group
-            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 33, 1>, 512,
+            if (shape == 0) return {(const void *)strip_solve_sym_kernel<float, 8, 33, 1, 1>, 512,
                     (int)sym_wave_regions<float, 8, 33>()};
-            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 4, 33, 2>, 256,
-                    (int)sym_wave_regions<float, 4, 33>()};
-            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 4, 33, 3>, 256,
-                    (int)sym_wave_regions<float, 4, 33>()};
-            return {(const void *)strip_solve_sym_kernel<float, 4, 33, 4>, 256,
-                    (int)sym_wave_regions<float, 4, 33>()};
+            if (shape == 1) return {(const void *)strip_solve_sym_kernel<float, 8, 33, 3, 2>, 512,
+                    (int)sym_wave_regions<float, 8, 33>()};
+            if (shape == 2) return {(const void *)strip_solve_sym_kernel<float, 8, 33, 4, 2>, 512,
+                    (int)sym_wave_regions<float, 8, 33>()};
+            return {(const void *)strip_solve_sym_kernel<float, 16, 33, 3, 4>, 1024,
+                    (int)sym_wave_regions<float, 16, 33>()};
         }
         return {nullptr, 0};
     }
     if (nch <= 3) {
-        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 3, 4>, 512,
+        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 3, 4, 1>, 512,
                     (int)sym_wave_regions<double, 8, 3>()};
-        return {(const void *)strip_solve_sym_kernel<double, 16, 3, 2>, 1024,
+        return {(const void *)strip_solve_sym_kernel<double, 16, 3, 2, 1>, 1024,
                     (int)sym_wave_regions<double, 16, 3>()};
     }
     if (nch <= 9) {
-        if (shape == 0) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 3>, 512,
+        if (shape == 0) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 3, 1>, 512,
                     (int)sym_wave_regions<double, 8, 9>()};
-        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 1>, 512,
+        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 1, 1>, 512,
                     (int)sym_wave_regions<double, 8, 9>()};
-        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 4, 9, 4>, 256,
-                    (int)sym_wave_regions<double, 4, 9>()};
-        return {(const void *)strip_solve_sym_kernel<double, 8, 9, 2>, 512,
+        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 16, 9, 2, 2>, 1024,
+                    (int)sym_wave_regions<double, 16, 9>()};
+        return {(const void *)strip_solve_sym_kernel<double, 8, 9, 2, 1>, 512,
                     (int)sym_wave_regions<double, 8, 9>()};
     }
     if (nch <= 17) {
-        if (shape == 0) return {(const void *)strip_solve_sym_kernel<double, 8, 17, 1>, 512,
+        if (shape == 0) return {(const void *)strip_solve_sym_kernel<double, 8, 17, 1, 1>, 512,
                     (int)sym_wave_regions<double, 8, 17>()};
-        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 4, 17, 2>, 256,
-                    (int)sym_wave_regions<double, 4, 17>()};
-        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 4, 17, 3>, 256,
-                    (int)sym_wave_regions<double, 4, 17>()};
-        return {(const void *)strip_solve_sym_kernel<double, 4, 17, 1>, 256,
-                    (int)sym_wave_regions<double, 4, 17>()};
+        if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 17, 2, 2>, 512,
+                    (int)sym_wave_regions<double, 8, 17>()};
+        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 8, 17, 3, 2>, 512,
+                    (int)sym_wave_regions<double, 8, 17>()};
+        return {(const void *)strip_solve_sym_kernel<double, 16, 17, 2, 4>, 1024,
+                    (int)sym_wave_regions<double, 16, 17>()};
     }
     return {nullptr, 0, 0};
 }
