@@ -166,7 +166,9 @@ def run_batch(args, dev):
     timed region is the refactorisation of every instance plus K steps, each
     step replaying the captured graph of a chunk of Schwarz iterations; the
     solve roofline comes from one more step run launch by launch with HIP
-    events around every batched solve."""
+    events around every batched solve.  Beside it (--sequential, on by
+    default): the same instances run one by one on the single-instance path,
+    complex FP32 and FP64, with the same timed work."""
     import numpy as np
     import torch
 
@@ -215,6 +217,38 @@ def run_batch(args, dev):
           flush=True)
     ks = np.array([[s["k"] for s in st] for st in stats])
     qs = np.array([[s["q_total"] for s in st] for st in stats])
+    # the same instances one by one on the single-instance path, with the
+    # same options and the same timed work (factor + steps), in both
+    # precisions; the first factorisation of each (with its solve autotune)
+    # is outside the timed region, as the batch's is
+    sequential = {}
+    if args.sequential:
+        del us
+        torch.cuda.empty_cache()
+        for prec in ("c32", "fp64"):
+            t_run, t_first, kk, gm = 0.0, 0.0, [], []
+            for i, pb in enumerate(pbs):
+                ta = time.perf_counter()
+                s1 = osm.OsmSolver(pb, dev, **dict(opts, prec=prec))
+                u1 = torch.from_numpy(wl.u0[i]).to(dev)
+                s1.factor(Ws[i])
+                torch.cuda.synchronize()
+                tb = time.perf_counter()
+                s1.factor(Ws[i])
+                for _ in range(args.steps):
+                    kk.append(s1.step(u1)["k"])
+                torch.cuda.synchronize()
+                tc = time.perf_counter()
+                s1.close()
+                t_first += tb - ta
+                t_run += tc - tb
+                del u1
+            sequential[prec] = {"value": dof * args.steps / t_run,
+                                "ms_per_step": 1e3 * t_run / args.steps,
+                                "setup_and_first_factor_s": t_first,
+                                "k_mean": float(np.mean(kk)), "k_max": int(np.max(kk))}
+            print(f"bench: one by one, {prec}: {sequential[prec]['value']:.4g} dof-steps/s",
+                  file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_limits
@@ -267,6 +301,7 @@ def run_batch(args, dev):
         "tuning": tuning,
         "setup_s": t_setup,
         "first_factor_and_autotune_s": t_tune,
+        "one_by_one": sequential or None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -335,9 +370,16 @@ def run_learned(args, dev):
                       "gmres_total": int(sum(x["gmres_total"] for x in st)),
                       "fallbacks": int(sum(x["fallback_used"] > 0 for x in st)),
                       "restarts": int(sum(x["fallback_used"] == 2 for x in st)),
+                      # ||g_n - prediction|| / ||g_n - g_{n-1}|| over the steps that
+                      # formed a prediction (the fallback's judge)
+                      "guess_ratio": ({"mean": float(np.mean(gr)), "median": float(np.median(gr)),
+                                       "steps": len(gr)}
+                                      if (gr := [x["guess_ratio"] for x in st
+                                                 if x["guess_ratio"] > 0]) else None),
                       "u": u.cpu().numpy()}
         print(f"bench: {name}: {runs[name]['value']:.4g} dof-steps/s, k {runs[name]['k_total']}, "
-              f"gmres {runs[name]['gmres_total']}", file=sys.stderr, flush=True)
+              f"gmres {runs[name]['gmres_total']}, guess ratio {runs[name]['guess_ratio']}",
+              file=sys.stderr, flush=True)
     ref = runs["previous"].pop("u")
     for name in ("extrapolated", "learned"):
         u = runs[name].pop("u")
@@ -796,6 +838,8 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--profile-solve", type=int, default=0, metavar="LAUNCHES",
                     help="profiler mode (gpe512): only factor + LAUNCHES strip solves + a 1 GiB copy")
+    ap.add_argument("--sequential", action=argparse.BooleanOptionalAction, default=True,
+                    help="batch64: also run the 64 instances one by one (FP64 and c32)")
     ap.add_argument("--p-list", default="",
                     help="paper-e5: comma-separated Robin parameters (default: 5,10,...,50)")
     ap.add_argument("--profile-factor", type=int, default=0, metavar="FACTORS",

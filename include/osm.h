@@ -194,6 +194,11 @@ typedef struct {
                                      was restarted from g_{n-1}                     */
     double last_increment;        /* last ||g^{k+1} - g^k||_2                      */
     double mass_before, mass_after; /* u* M u before and after the step           */
+    double guess_ratio;           /* guess 2 or 3, once a prediction was formed:
+                                     ||g_n - prediction|| / ||g_n - g_{n-1}|| (the
+                                     fallback's judge; < 1: the prediction was the
+                                     closer start), g_n the converged vector; 0
+                                     otherwise                                    */
 } osm_step_stats;
 
 typedef struct { uint64_t device_bytes, host_bytes; } osm_footprint;

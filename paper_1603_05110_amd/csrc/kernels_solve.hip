@@ -479,16 +479,28 @@ __device__ __forceinline__ float2 ld_agent2(const float2 *p) {
 // range returns zeros without a memory access (the hardware's range check of
 // raw buffers, dword 3 of the resource as on every gfx9 chip).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_range(const void *base, int bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, 0x00020000);
+    // base and range are the same in every lane: the resource lives in
+    // scalar registers, stated explicitly for the compiler
+    const unsigned long long b = reinterpret_cast<unsigned long long>(base);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    void *p = reinterpret_cast<void *>(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, __builtin_amdgcn_readfirstlane(bytes),
+                                             0x00020000);
 }
 __device__ __forceinline__ void range_load(float2 &d, __amdgpu_buffer_rsrc_t rs, unsigned off) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
-    __builtin_memcpy(&d, &v, sizeof(d));
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+    d.x = __uint_as_float(v.x);
+    d.y = __uint_as_float(v.y);
 }
 __device__ __forceinline__ void range_load(double2 &d, __amdgpu_buffer_rsrc_t rs, unsigned off) {
     const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
     __builtin_memcpy(&d, &v, sizeof(d));
 }
+
+__device__ __forceinline__ float fma_acc(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_acc(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Per-wave partial regions in LDS: when NW regions of both products fit
 // (with the product vectors and the finished lines) in 120 KiB, each wave
@@ -763,25 +775,36 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
         };
         // A row adds its dot to column r and F[r][c] v_r to every column
         // c >= r; the diagonal term, in both, is taken out of the first once.
-        // Every chunk is multiplied (the zeros left of the diagonal too): a
-        // skipped chunk would leave its load unwaited on that path, and a
-        // later write of its register would wait for every load in flight.
+        // The arithmetic is 8 fused multiply-adds per chunk (two chains per
+        // component of the dot), and a chunk wholly left of the diagonal
+        // (zeros from the range check) is skipped by a uniform branch: its
+        // load is older than the row's later chunks, so it has completed
+        // once they are waited for, and nothing waits for it.
         auto row = [&](int k, const T2 (&mm)[NCW], const T2 &d) {
             const int e = entry(t, grp + NG * k);
             const int p = e >> 16, r = e & 0xFFFF;
             const T2 vr = vecs[p * n + r];
-            A dr = 0, di = 0;
+            const A vrx = (A)vr.x, vry = (A)vr.y;
+            // two chains where registers allow (16-wave tiles have half)
+            constexpr int NCHAIN = NW >= 16 ? 1 : 2;
+            A dr[2] = {0, 0}, di[2] = {0, 0};
 #pragma unroll
             for (int c = 0; c < NCW; ++c) {
+                if ((c * SPLIT + SPLIT - 1) * 64 + 63 < r) continue;
                 const A mx = (A)mm[c].x, my = (A)mm[c].y;
-                const T2 v = vv[c];
-                dr += mx * (A)v.x - my * (A)v.y;
-                di += mx * (A)v.y + my * (A)v.x;
-                cr[c] += mx * (A)vr.x - my * (A)vr.y;
-                ci[c] += mx * (A)vr.y + my * (A)vr.x;
+                const A vx = (A)vv[c].x, vy = (A)vv[c].y;
+                const int q = c % NCHAIN;
+                dr[q] = fma_acc(mx, vx, dr[q]);
+                dr[q] = fma_acc(-my, vy, dr[q]);
+                di[q] = fma_acc(mx, vy, di[q]);
+                di[q] = fma_acc(my, vx, di[q]);
+                cr[c] = fma_acc(mx, vrx, cr[c]);
+                cr[c] = fma_acc(-my, vry, cr[c]);
+                ci[c] = fma_acc(mx, vry, ci[c]);
+                ci[c] = fma_acc(my, vrx, ci[c]);
             }
-            dr = wave_sum(dr);
-            di = wave_sum(di);
+            A dre = wave_sum(dr[0] + dr[1]);
+            A die = wave_sum(di[0] + di[1]);
             if (lane == 0) {
                 // the group's first wave takes the diagonal out
                 const A gx = h == 0 ? (A)d.x * (A)vr.x - (A)d.y * (A)vr.y : (A)0;
@@ -789,15 +812,15 @@ __global__ __launch_bounds__(NW * 64) void strip_solve_sym_kernel(SolveArgs a) {
                 if constexpr (WR && SPLIT == 1) {
                     // row r belongs to one wave of one member: a plain store
                     A2 q;
-                    q.x = dr - gx;
-                    q.y = di - gy;
+                    q.x = dre - gx;
+                    q.y = die - gy;
                     rres[p * n + r] = q;
                 } else if constexpr (WR) {
-                    atomicAdd(&rres[p * n + r].x, dr - gx);
-                    atomicAdd(&rres[p * n + r].y, di - gy);
+                    atomicAdd(&rres[p * n + r].x, dre - gx);
+                    atomicAdd(&rres[p * n + r].y, die - gy);
                 } else {
-                    atomicAdd(&pre[p * n + r], dr - gx);
-                    atomicAdd(&pim[p * n + r], di - gy);
+                    atomicAdd(&pre[p * n + r], dre - gx);
+                    atomicAdd(&pim[p * n + r], die - gy);
                 }
             }
         };
@@ -1159,7 +1182,7 @@ Variant variant_sym_for(int n, int fp32, int shape) {
                     (int)sym_wave_regions<double, 8, 9>()};
         if (shape == 1) return {(const void *)strip_solve_sym_kernel<double, 8, 9, 1, 1>, 512,
                     (int)sym_wave_regions<double, 8, 9>()};
-        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 16, 9, 2, 2>, 1024,
+        if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 16, 9, 1, 2>, 1024,
                     (int)sym_wave_regions<double, 16, 9>()};
         return {(const void *)strip_solve_sym_kernel<double, 8, 9, 2, 1>, 512,
                     (int)sym_wave_regions<double, 8, 9>()};
@@ -1171,7 +1194,7 @@ Variant variant_sym_for(int n, int fp32, int shape) {
                     (int)sym_wave_regions<double, 8, 17>()};
         if (shape == 2) return {(const void *)strip_solve_sym_kernel<double, 8, 17, 3, 2>, 512,
                     (int)sym_wave_regions<double, 8, 17>()};
-        return {(const void *)strip_solve_sym_kernel<double, 16, 17, 2, 4>, 1024,
+        return {(const void *)strip_solve_sym_kernel<double, 16, 17, 1, 4>, 1024,
                     (int)sym_wave_regions<double, 16, 17>()};
     }
     return {nullptr, 0, 0};

@@ -1645,6 +1645,7 @@ osm_status osm_step(osm_handle *h, osm_c64 *u_dev, osm_step_stats *stats) {
             HIPCHK(h, hipMemcpyAsync(e, h->scal + 6, sizeof(e), hipMemcpyDeviceToHost, h->st));
             HIPCHK(h, hipStreamSynchronize(h->st));
             h->fallback_next = e[0] > e[1];
+            S.guess_ratio = e[1] > 0.0 ? std::sqrt(e[0] / e[1]) : 0.0;
         }
         HIPCHK(h, hipMemcpyAsync(h->g_prev2, h->g_last, gbytes, hipMemcpyDeviceToDevice, h->st));
         h->hist += 1;

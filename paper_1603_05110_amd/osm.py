@@ -58,7 +58,8 @@ class osm_step_stats(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("q_total", ctypes.c_int32),
                 ("gmres_total", ctypes.c_int32), ("refine_total", ctypes.c_int32),
                 ("fallback_used", ctypes.c_int32), ("last_increment", ctypes.c_double),
-                ("mass_before", ctypes.c_double), ("mass_after", ctypes.c_double)]
+                ("mass_before", ctypes.c_double), ("mass_after", ctypes.c_double),
+                ("guess_ratio", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -173,14 +173,18 @@ def test_options_struct_matches_the_header():
         '#include <stddef.h>\n#include <stdio.h>\n#include "osm.h"\n'
         'int main(void) { printf("%zu %zu %zu %zu %zu\\n", sizeof(osm_options), '
         'offsetof(osm_options, g1_init), offsetof(osm_options, seed), '
-        'offsetof(osm_options, krylov), sizeof(osm_problem)); return 0; }\n')
+        'offsetof(osm_options, krylov), sizeof(osm_problem)); '
+        'printf("%zu %zu\\n", sizeof(osm_step_stats), offsetof(osm_step_stats, guess_ratio)); '
+        'return 0; }\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
         exe = os.path.join(d, "t")
         open(c, "w").write(src)
         subprocess.run([cc, "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
-    size, off_g1, off_seed, off_kr, psize = map(int, out)
+    size, off_g1, off_seed, off_kr, psize, ssize, off_gr = map(int, out)
+    assert ssize == ctypes.sizeof(osm.osm_step_stats)
+    assert off_gr == osm.osm_step_stats.guess_ratio.offset
     assert size == ctypes.sizeof(osm.osm_options)
     assert off_g1 == osm.osm_options.g1_init.offset
     assert off_seed == osm.osm_options.seed.offset

@@ -196,6 +196,10 @@ def test_learned_guess_gains_over_previous_vector():
         k[name] = sum(x["k"] for x in st[2:])
         if guess == 2:
             assert sum(x["fallback_used"] for x in st) == 0
+            # the library's own judge ratio agrees with the host's measure
+            gr = [x["guess_ratio"] for x in st if x["guess_ratio"] > 0]
+            log(f"  device guess ratio, learned: mean {np.mean(gr):.4f} over {len(gr)} steps")
+            assert len(gr) == pb.steps - 2 and np.mean(gr) < 0.5
     log(f"  classical Schwarz iterations, steps 3..{pb.steps}: {k}")
     assert k["learned"] < k["previous"]
     assert np.mean(r_nn) < np.mean(r_ex)
@@ -216,10 +220,16 @@ def test_bad_network_falls_back_and_keeps_the_answer():
     net.close()
     assert rel(u, ref) < 1e-10
     codes = [x["fallback_used"] for x in st]
-    log(f"  fallback codes per step {codes}")
+    ratios = [x["guess_ratio"] for x in st]
+    log(f"  fallback codes per step {codes}, guess ratios {[round(r, 3) for r in ratios]}")
     assert sum(c > 0 for c in codes) >= 1
     # a step restarted after its predicted start failed is followed by a
     # step that does not use the prediction
     for a, b in zip(codes, codes[1:]):
         if a == 2:
             assert b >= 1, codes
+    # the judge: a prediction that ended farther from g_n than g_{n-1}
+    # (ratio > 1) is not used on the next step, a closer one is
+    for n in range(len(st) - 1):
+        if ratios[n] > 0 and codes[n] != 2:
+            assert (codes[n + 1] == 1) == (ratios[n] > 1.0), (n, ratios, codes)
