@@ -180,9 +180,11 @@ def run_batch(args, dev):
     dofs = [(pb.ncx + 1) * (pb.ncy + 1) for pb in pbs]
     dof = sum(dofs)
     opts = dict(prec=args.prec, tol_k=1e-12, tol_k_relative=True, tol_q=1e-13, max_k=5000,
-                max_q=200)
-    print(f"bench: C3 batch {len(pbs)} instances, {dof} dofs, prec={args.prec}", file=sys.stderr,
-          flush=True)
+                max_q=200, algo=args.batch_algo)
+    if args.batch_algo == "precond":
+        opts.update(tol_gmres=3e-2, gmres_restart=50, max_gmres=2000)
+    print(f"bench: C3 batch {len(pbs)} instances, {dof} dofs, prec={args.prec}, "
+          f"{args.batch_algo}", file=sys.stderr, flush=True)
     t = time.perf_counter()
     b = osm.OsmBatch(pbs, dev, **opts)
     Ws = [torch.from_numpy(V).to(dev) for V in wl.V]
@@ -287,12 +289,13 @@ def run_batch(args, dev):
         "data": "synthetic",
         "config": {"workload": "batch of 64 independent cubic-NLS instances, grids "
                                "{256,384,512,768}^2 seeded, 8-32 uneven strips, Robin p~U[1,10], "
-                               "V = 8 seeded Gaussians (max|V|=5), dt=0.01, classical, "
+                               f"V = 8 seeded Gaussians (max|V|=5), dt=0.01, {args.batch_algo}, "
                                "graph-replayed chunks, autotuned solve tiles",
                    "dof": dof, "instances": len(pbs), "strips": sum(pb.nsub for pb in pbs),
-                   "algo": "classical", "prec": args.prec, "timed": "factor(W) + steps"},
+                   "algo": args.batch_algo, "prec": args.prec, "timed": "factor(W) + steps"},
         "iters": {"k_mean": float(ks.mean()), "k_max": int(ks.max()),
-                  "q_total": int(qs.sum())},
+                  "q_total": int(qs.sum()),
+                  "gmres_total": int(sum(x["gmres_total"] for st in stats for x in st))},
         "roofline": {"kernel": "batch_solve", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "bytes_timed": nbytes, "launches": launches,
@@ -838,6 +841,8 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--profile-solve", type=int, default=0, metavar="LAUNCHES",
                     help="profiler mode (gpe512): only factor + LAUNCHES strip solves + a 1 GiB copy")
+    ap.add_argument("--batch-algo", default="classical", choices=["classical", "precond"],
+                    help="batch64: the Schwarz algorithm of every instance")
     ap.add_argument("--sequential", action=argparse.BooleanOptionalAction, default=True,
                     help="batch64: also run the 64 instances one by one (FP64 and c32)")
     ap.add_argument("--p-list", default="",

@@ -396,8 +396,11 @@ osm_status osm_set_guess_net(osm_handle *h, const osm_net *net);
  * osm_kernel_timing works on a batch handle (timed steps then run the chunk
  * launch by launch instead of as a graph). */
 
-/* Footprint of osm_setup_batch.  OSM_EUNSUPPORTED unless opt->algo is
- * OSM_CLASSICAL. */
+/* Footprint of osm_setup_batch.  opt->algo is OSM_CLASSICAL or OSM_PRECOND
+ * (Section 3, eq. algo_pd; every instance builds the L_h of its own strip
+ * classes, and its preconditioned update runs inside the replayed step with
+ * GMRES, krylov = 0); OSM_EUNSUPPORTED for OSM_INTERFACE_KRYLOV, EINVAL for
+ * the S_pade^m condition or BiCGStab in a batch. */
 osm_status osm_query_batch(const osm_problem *probs, int32_t nb,
                            const osm_options *opt, osm_footprint *out);
 

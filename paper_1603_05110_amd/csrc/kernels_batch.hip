@@ -67,7 +67,7 @@ __global__ void b_iter_reset_kernel(const InstDesc *tab) {
     if (threadIdx.x != 0) return;
     StepCtl *c = tab[blockIdx.x].ctl;
     if (c->k_done || c->bad || !c->ready) return;
-    iter_reset_body(c, nullptr);
+    iter_reset_body(c, tab[blockIdx.x].gctl);
 }
 
 __global__ __launch_bounds__(256) void b_residual_kernel(const InstDesc *tab) {

@@ -92,6 +92,7 @@ __global__ void precond_finalize_kernel(const double *part, int nb, StepCtl *c,
     if (threadIdx.x != 0) return;
     double inc = sqrt(a), ref = sqrt(b);
     c->r_done = 2;
+    c->ready = 1;                 // a batched replay may start the next iteration
     c->gm_total += gc->total;
     if (!isfinite(inc)) { c->bad = 1; return; }
     c->k += 1;

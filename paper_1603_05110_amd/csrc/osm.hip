@@ -2083,7 +2083,10 @@ static uint64_t batch_table_bytes(long nb, long nstrips, long nlines) {
 static std::string validate_batch(const osm_problem *probs, int32_t nb, const osm_options *opt) {
     if (!probs || !opt) return "null problems or options";
     if (nb < 1) return "nb must be >= 1";
-    if (opt->algo != OSM_CLASSICAL) return "batched instances run the classical algorithm";
+    if (opt->algo != OSM_CLASSICAL && opt->algo != OSM_PRECOND)
+        return "batched instances run the classical or the preconditioned algorithm";
+    if (opt->algo == OSM_PRECOND && opt->krylov != 0)
+        return "preconditioned batched instances solve P x = y by GMRES (krylov = 0)";
     for (int b = 0; b < nb; ++b)
         if (probs[b].tc != OSM_TC_ROBIN)
             return "instance " + std::to_string(b) + ": batched instances use the Robin condition";
@@ -2098,8 +2101,9 @@ osm_status osm_query_batch(const osm_problem *probs, int32_t nb, const osm_optio
                            osm_footprint *out) {
     if (!out) return fail(nullptr, OSM_EINVAL, "out is NULL");
     std::string v = validate_batch(probs, nb, opt);
-    if (!v.empty()) return fail(nullptr, opt && opt->algo != OSM_CLASSICAL && probs && nb >= 1
-                                             ? OSM_EUNSUPPORTED : OSM_EINVAL, v);
+    if (!v.empty())
+        return fail(nullptr, opt && opt->algo != OSM_CLASSICAL && opt->algo != OSM_PRECOND &&
+                                     probs && nb >= 1 ? OSM_EUNSUPPORTED : OSM_EINVAL, v);
     uint64_t dev = 0, host = 0;
     long nst = 0, nlines = 0;
     for (int b = 0; b < nb; ++b) {
@@ -2291,7 +2295,7 @@ static StepCfg batch_cfg(const osm_options &o) {
     cfg.fixed_q = o.fixed_q;
     cfg.max_q = o.max_q;
     cfg.fixed_k = o.fixed_k;
-    cfg.classical = 1;
+    cfg.classical = o.algo == OSM_CLASSICAL;
     cfg.q_est = 0;
     return cfg;
 }
@@ -2328,6 +2332,29 @@ static osm_status batch_chunk(osm_handle *h, hipStream_t st, bool timed) {
             HIPCHK(h, launch_b_q_check(st, h->tab_d, d));
         }
         HIPCHK(h, launch_b_flux(st, h->tab_d, d));
+        if (h->opt.algo == OSM_PRECOND) {
+            // each instance's preconditioned update (eq. algo_pd): y = g -
+            // R(g), a first chunk of GMRES on P x = y, g <- g - x, all guarded
+            // by the instance's controls (an instance whose map is not done,
+            // or whose GMRES needs more, is left to the host after the replay)
+            for (osm_handle *u : h->sub) {
+                hipStream_t keep = u->st;
+                u->st = st;
+                long ng = u->ng;
+                HIPCHK(h, launch_precond_rhs(st, ng, u->g, u->gn, u->gtmp, u->gx, u->sctl));
+                HIPCHK(h, launch_gmres_begin(st, ng, u->gtmp, u->gnorm_part, 1, 1.0, u->Vb, u->ge,
+                                             u->m, u->gctl, u->sctl));
+                osm_status s = gmres_iters(u, 0, std::min(GMRES_CHUNK, u->m));
+                if (s == OSM_OK)
+                    s = launch_gmres_finish(st, ng, u->m, u->gH, u->ge, u->gy, u->Vb, u->gx,
+                                            u->gctl, 1) == hipSuccess ? OSM_OK : OSM_EHIP;
+                if (s == OSM_OK)
+                    s = launch_precond_update(st, ng, u->g, u->gx, u->upd_part, u->sctl,
+                                              u->gctl) == hipSuccess ? OSM_OK : OSM_EHIP;
+                u->st = keep;
+                if (s != OSM_OK) return fail(h, s, "preconditioned update of an instance: " + u->err);
+            }
+        }
         HIPCHK(h, launch_b_commit(st, h->tab_d, d));
     }
     return OSM_OK;
@@ -2369,6 +2396,9 @@ osm_status osm_setup_batch(const osm_problem *probs, int32_t nb, const osm_optio
     h->st = (hipStream_t)hip_stream;
     hipGetDevice(&h->device);
     h->fp32 = opt->prec == OSM_C32_REFINE;
+    // preconditioned instances: one Schwarz iteration per replay, so that the
+    // host can continue an instance's GMRES before its next iteration
+    if (opt->algo == OSM_PRECOND) h->chunk_k = 1;
     osm_options so = *opt;
     so.team = 1;          // the instances' own solve is not used; skip its tuner
     so.mem_cap = 0;
@@ -2421,6 +2451,7 @@ osm_status osm_setup_batch(const osm_problem *probs, int32_t nb, const osm_optio
             I.line_part = u->line_part; I.trace_part = u->trace_part; I.mass_part = u->mass_part;
             I.scal = h->bscal + 2 * b;
             I.ctl = u->sctl;
+            I.gctl = opt->algo == OSM_PRECOND ? u->gctl : nullptr;
             I.flag = h->bflags + b;
             h->tab_h.push_back(I);
             long nn = (long)u->n * u->n;
@@ -2527,6 +2558,7 @@ osm_status osm_step_batch(osm_handle *h, osm_c64 *const *u_devs, osm_step_stats 
             memset(&S, 0, sizeof(S));
             S.k = c[b].k;
             S.q_total = c[b].q_total;
+            S.gmres_total = c[b].gm_total;
             S.refine_total = h->fp32 ? c[b].q_total : 0;
             S.last_increment = c[b].inc;
         }
@@ -2546,6 +2578,22 @@ osm_status osm_step_batch(osm_handle *h, osm_c64 *const *u_devs, osm_step_stats 
         HIPCHK(h, hipStreamSynchronize(h->st));
         if (err) return fail(h, OSM_EHIP, "batched solve: barrier wait timed out");
         if ((s = prof_collect(h)) != OSM_OK) return s;
+        if (o.algo == OSM_PRECOND) {
+            // instances whose GMRES did not finish within the replay's chunk
+            for (int b = 0; b < nb; ++b) {
+                if (c[b].r_done != 1 || c[b].k_done || c[b].bad) continue;
+                osm_handle *u = h->sub[b];
+                StepCtl cb;
+                GmresCtl gcb;
+                if ((s = read_ctl(u, &cb, &gcb)) != OSM_OK) return fail(h, s, u->err);
+                if (cb.r_done == 1 && !cb.k_done && !cb.bad &&
+                    (s = gmres_continue(u, gcb, cb)) != OSM_OK) {
+                    fill();
+                    return fail(h, s, "instance " + std::to_string(b) + ": " + u->err);
+                }
+                c[b] = cb;
+            }
+        }
         done = true;
         for (int b = 0; b < nb; ++b) {
             if (c[b].bad) {

@@ -427,6 +427,7 @@ struct InstDesc {
     double *line_part, *trace_part, *mass_part;
     double *scal;                   // [0] mass before, [1] mass after
     StepCtl *ctl;
+    GmresCtl *gctl;                 // preconditioned instances: reset with the iteration
     int *flag;                      // non-finite input
 };
 

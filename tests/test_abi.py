@@ -88,8 +88,15 @@ def test_batch_footprint_is_the_sum_of_its_instances():
 def test_batch_rejects_bad_arguments_on_the_host():
     from paper_1603_05110_amd import osm
     with pytest.raises(osm.OsmError) as e:
-        osm.osm_query_batch([_pb(), _pb()], algo="precond")
+        osm.osm_query_batch([_pb(beta=0.0), _pb(beta=0.0)], algo="interface")
     assert e.value.status == osm.OSM_EUNSUPPORTED
+    with pytest.raises(osm.OsmError) as e:
+        osm.osm_query_batch([_pb(), _pb()], algo="precond", krylov="bicgstab", gmres_restart=8)
+    assert e.value.status == osm.OSM_EINVAL
+    # preconditioned batches: every instance's L_h in the footprint
+    dc, _ = osm.osm_query_batch([_pb(), _pb()])
+    dp, _ = osm.osm_query_batch([_pb(), _pb()], algo="precond")
+    assert dp > dc
     with pytest.raises(osm.OsmError) as e:
         osm.osm_query_batch([_pb(), _pb(strip_cells=[10, 5])])
     assert e.value.status == osm.OSM_EINVAL

@@ -110,6 +110,60 @@ def test_batch_equals_instances_run_alone():
         assert rel(ud[i].cpu().numpy(), u1.cpu().numpy()) < 1e-11, i
 
 
+@pytest.mark.parametrize("prec", ["fp64", "c32"])
+def test_preconditioned_batch_matches_monolithic(prec):
+    """The preconditioned algorithm (eq. algo_pd) per instance of a batch:
+    every instance's L_h of its own strip classes, its GMRES on P x = y
+    inside the replayed chunk and, when a chunk is not enough, continued by
+    the host; two converged steps against the monolithic oracle."""
+    from paper_1603_05110_amd import osm
+    log(f"preconditioned batch {prec}")
+    pbs, us, Ws = mixed_batch()
+    steps = 2
+    refs = [run_monolithic(pb, u, W, steps, tol_q=1e-14) for pb, u, W in zip(pbs, us, Ws)]
+    b = osm.OsmBatch(pbs, DEV, algo="precond", prec=prec, tol_k=1e-12, tol_k_relative=True,
+                     tol_q=1e-14, max_k=200, tol_gmres=1e-2)
+    b.factor([to_dev(W) for W in Ws])
+    ud = [to_dev(u) for u in us]
+    for _ in range(steps):
+        st = b.step(ud)
+        log("  k " + " ".join(str(s["k"]) for s in st) + ", GMRES " +
+            " ".join(str(s["gmres_total"]) for s in st))
+    b.close()
+    for i in range(len(pbs)):
+        assert rel(ud[i].cpu().numpy(), refs[i]) < 1e-10, i
+        assert st[i]["gmres_total"] > 0
+
+
+def test_preconditioned_batch_equals_instances_run_alone():
+    """Each preconditioned instance of the batch takes the single-instance
+    path's iterations (within one) and reaches its answer; both take far
+    fewer Schwarz iterations than the classical batch."""
+    from paper_1603_05110_amd import osm
+    log("preconditioned batch vs single")
+    pbs, us, Ws = mixed_batch()
+    opts = dict(tol_k=1e-12, tol_k_relative=True, tol_q=1e-14, max_k=4000, tol_gmres=1e-2)
+    b = osm.OsmBatch(pbs, DEV, algo="precond", **opts)
+    b.factor([to_dev(W) for W in Ws])
+    ud = [to_dev(u) for u in us]
+    st = b.step(ud)
+    b.close()
+    bc = osm.OsmBatch(pbs, DEV, **opts)
+    bc.factor([to_dev(W) for W in Ws])
+    stc = bc.step([to_dev(u) for u in us])
+    bc.close()
+    for i, pb in enumerate(pbs):
+        s = osm.OsmSolver(pb, DEV, algo="precond", **opts)
+        s.factor(to_dev(Ws[i]))
+        u1 = to_dev(us[i])
+        s1 = s.step(u1)
+        s.close()
+        log(f"  instance {i}: batch k {st[i]['k']}, alone {s1['k']}, classical {stc[i]['k']}")
+        assert abs(s1["k"] - st[i]["k"]) <= 1
+        assert st[i]["k"] < stc[i]["k"]
+        assert rel(ud[i].cpu().numpy(), u1.cpu().numpy()) < 1e-10, i
+
+
 def _edge_term(pb, u_old, u_new):
     """v* M^Gamma_d v over the two physical x-edges, v = (u_n + u_{n-1})/2."""
     hy = pb.hy
