@@ -180,6 +180,21 @@ typedef struct {
                                      its work vectors share the GMRES basis);
                                      stats.gmres_total then counts BiCGStab
                                      iterations                                   */
+    int32_t strip_order;          /* unknown order of the strip factor (Section 2.2:
+                                     K_j is block tridiagonal in either order):
+                                     0 = node-line order, ny x ny blocks, dense
+                                     Schur complements inverted on the matrix
+                                     cores (as in prec); 1 = y-line order, nx x nx
+                                     blocks (nx = a strip's node-lines) along the
+                                     ny y-lines, factored and solved in FP64
+                                     whatever prec says (Robin only, every strip
+                                     at most 64 node-lines; EINVAL otherwise);
+                                     2 = the autotuner times one solve of each
+                                     order after the first factorisation and
+                                     keeps the faster (node-line order where the
+                                     y-line order is not available; both factors
+                                     are allocated).  osm_strip_order() tells
+                                     which is in use.                             */
 } osm_options;
 
 typedef struct {
@@ -268,6 +283,17 @@ osm_status osm_get_lh_blocks(osm_handle *h, osm_c64 *blocks_dev);
  * D_m - U_{m-1}^T S_{m-1}^{-1} U_{m-1} - U_m T_{m+1}^{-1} U_m^T. */
 osm_status osm_get_factor(osm_handle *h, void *dst_dev);
 
+/* Copy the stored y-line-order factor (osm_strip_order() == 1): strip by
+ * strip, y-line a = 0 .. ny-1, the dense inverse (nx_j x nx_j, row-major,
+ * complex128) of that y-line's Schur complement, sum_j ny nx_j^2 elements.
+ * With A_a the block of y-line a and B_a its coupling to y-line a+1, and
+ * middle y-line m = (ny-1)/2: y-lines a < m hold T_a^{-1} (T_0 = A_0, T_a =
+ * A_a - B_{a-1}^T T_{a-1}^{-1} B_{a-1}), y-lines a > m hold U_a^{-1} (U_{ny-1}
+ * = A_{ny-1}, U_a = A_a - B_a U_{a+1}^{-1} B_a^T), y-line m the inverse of
+ * A_m - B_{m-1}^T T_{m-1}^{-1} B_{m-1} - B_m U_{m+1}^{-1} B_m^T.  OSM_ESTATE
+ * when the handle keeps no y-line factor or has not factored. */
+osm_status osm_get_yfactor(osm_handle *h, osm_c64 *dst_dev);
+
 /* Kernel timing for measurement: enable = 1 resets the counters and brackets
  * every later launch of the strip-solve kernel with HIP events on the
  * handle's stream; enable = 0 stops.  Both return, in *solve_ms and
@@ -304,6 +330,11 @@ int32_t osm_solve_team(const osm_handle *h);
  * (waves per workgroup x rows kept in registers as for 0 .. 3).  0 for a
  * NULL handle. */
 int32_t osm_solve_shape(const osm_handle *h);
+
+/* Unknown order of the strip factor in use: 0 = node-line order, 1 = y-line
+ * order (osm_options.strip_order; with 2 the autotuner's choice, known after
+ * the first factorisation, node-line order before it).  0 for a NULL handle. */
+int32_t osm_strip_order(const osm_handle *h);
 
 /* ---------------------------------------------------------------- learned guess
  * A network predicts the next step's interface start from the history (the

@@ -1,0 +1,619 @@
+// Strip factor and solve in y-line order (the unknowns of a strip taken
+// y-line by y-line): the strip matrix K_j is block tridiagonal with
+// (nx x nx) blocks, nx = the strip's node-lines, ny blocks along y,
+//     K = tridiag(B_{a-1}^T, A_a, B_a),
+// A_a (within y-line a) and B_a (y-line a to a+1) both tridiagonal in x;
+// K_j is complex symmetric, so the block below the diagonal is B^T.  The
+// entries are those of the node-line coefficients (Dc(l, a, d) = K[(l, a),
+// (l, a + d - 1)], Uc(l, a, d) = K[(l, a), (l + 1, a + d - 1)]):
+//     A_a[l][l] = Dc(l, a, 1),  A_a[l][l+1] = A_a[l+1][l] = Uc(l, a, 1),
+//     B_a[l][l] = Dc(l, a, 2),  B_a[l][l+1] = Uc(l, a, 2),
+//     B_a[l+1][l] = K[(l+1, a), (l, a+1)] = Uc(l, a+1, 0).
+// The block Thomas algorithm runs twisted: y-lines below the middle line
+// m = (ny - 1) / 2 are eliminated from a = 0 up (T_a = A_a - B_{a-1}^T
+// T_{a-1}^{-1} B_{a-1}), those above from a = ny - 1 down (U_a = A_a - B_a
+// U_{a+1}^{-1} B_a^T), and the middle line takes both terms.  The stored
+// factor is the inverse of every complement (nx x nx, FP64), nx^2 per y-line
+// instead of the ny^2 per node-line of the node-line order.  The
+// complements are complex symmetric with a positive-definite imaginary part
+// (that of K_j, 2/dt M + c p M^Gamma, is; z^* S z for a Schur complement S
+// equals w^* K w for a w whose last block is z), so Gauss-Jordan needs no
+// pivoting; the stored inverses are symmetric up to rounding, and the solve
+// reads them by columns.
+//
+// The sweeps are sequential in y, so both the factor and the solve are
+// latency-bound chains, one per strip half: the factor keeps each
+// complement in registers (one barrier per pivot), the solve keeps the data
+// of the next few y-lines in flight in registers while it works on the
+// current one.
+#include "osm_internal.h"
+
+#include <algorithm>
+#include <utility>
+
+namespace {
+
+__device__ __forceinline__ double2 yz() { return cd(0.0, 0.0); }
+// the solve kernels return at once when the fixed point is done (as the
+// node-line solve does)
+__device__ __forceinline__ bool yidle(const StepCtl *c) {
+    return c && (c->q_conv || c->k_done || c->bad);
+}
+__device__ __forceinline__ double2 ymul(double2 a, double2 b) {
+    return cd(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 yfma(double2 a, double2 b, double2 c) {
+    return cd(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double2 yneg(double2 a) { return cd(-a.x, -a.y); }
+// c ? a : b, component-wise (a conditional on the struct itself selects
+// between addresses and keeps the values out of registers)
+__device__ __forceinline__ double2 ysel(bool c, double2 a, double2 b) {
+    return cd(c ? a.x : b.x, c ? a.y : b.y);
+}
+
+// ---------------------------------------------------------------- factor
+// A workgroup of 256 threads per strip half: thread (k = tid mod n, rg = tid
+// div n) owns column k of rows rg + ng r, r < R (ng = 256 div n row groups;
+// R >= ceil(n / ng), a template parameter); threads with rg >= ng idle.
+// Rows i >= n of a thread are computed on clamped data and never published
+// or stored.
+constexpr int YF_THREADS = 256;
+constexpr int YF_COLB = 64;    // pivot column buffer: rows < n <= 64
+
+// LDS of a factor workgroup: the pivot row (2 x 64) and column (2 x 64) of
+// the current and the next pivot, A's two diagonals and the coupling block's
+// three (5 n), the previous inverse and then the product H (n^2).
+struct YFactorLds {
+    double2 *cb, *gl, *rowb, *colb;
+};
+__device__ __forceinline__ YFactorLds yf_lds(double2 *base, int n) {
+    YFactorLds L;
+    L.rowb = base;                                // 2 x 64
+    L.colb = base + 128;                          // 2 x YF_COLB
+    L.cb = base + 128 + 2 * YF_COLB;              // 5 n
+    L.gl = base + 128 + 2 * YF_COLB + 5 * n;      // n^2
+    return L;
+}
+
+// Coefficients of y-line a: A's diagonal and off-diagonal (cb[0, 2n)) and,
+// when ab >= 0, the coupling block B_ab's diagonal, upper and lower entries
+// (cb[2n, 5n)), also written y-line-major to YB for the solve.
+__device__ void yf_coef(const YStrip &S, int ny, int a, int ab, const double2 *Dc,
+                        const double2 *Uc, double2 *cb, double2 *YB) {
+    const int n = S.nx;
+    for (int l = threadIdx.x; l < n; l += blockDim.x) {
+        const long r = ((long)(S.off + l) * ny + a) * 3;
+        cb[l] = Dc[r + 1];
+        cb[n + l] = l + 1 < n ? Uc[r + 1] : yz();
+        if (ab >= 0) {
+            const long rb = ((long)(S.off + l) * ny + ab) * 3;
+            const double2 d = Dc[rb + 2];
+            const double2 up = l + 1 < n ? Uc[rb + 2] : yz();
+            const double2 lo = l + 1 < n ? Uc[((long)(S.off + l) * ny + ab + 1) * 3 + 0] : yz();
+            cb[2 * n + l] = d;
+            cb[3 * n + l] = up;
+            cb[4 * n + l] = lo;
+            double2 *yb = YB + S.boff + (long)ab * 3 * n;
+            yb[l] = d;
+            yb[n + l] = up;
+            yb[2 * n + l] = lo;
+        }
+    }
+}
+
+// The entries index j contributes to the tridiagonal products, for its
+// neighbours j - 1, j, j + 1: lower (tr = 0) B[j-1][j], B[j][j], B[j+1][j];
+// upper (tr = 1) B[j][j-1], B[j][j], B[j][j+1]; zero outside [0, n).
+struct Tri { double2 m1, z0, p1; };
+__device__ __forceinline__ Tri yf_tri(const double2 *cb, int n, int j, int tr) {
+    Tri t;
+    const double2 *up = cb + 3 * n, *lo = cb + 4 * n;
+    const int jm = max(j - 1, 0);
+    t.z0 = cb[2 * n + j];
+    t.m1 = ysel(j > 0, ysel(tr, lo[jm], up[jm]), yz());
+    t.p1 = ysel(j + 1 < n, ysel(tr, up[j], lo[j]), yz());
+    return t;
+}
+
+// c[r] -= (X G Y)[i_r][k] with G in L.gl (n x n): lower C -= B^T G B, upper
+// C -= B G B^T, as H = G Y (3 terms) then X H (3 terms); reads clamped into
+// the block (their coefficient is zero where clamping changed the index).
+// Ends with L.gl free.
+template <int R>
+__device__ __forceinline__ void yf_sandwich(double2 (&c)[R], const YFactorLds &L, int n, int k, int rg, int ng,
+                            bool act, int tr) {
+    double2 h[R];
+    const Tri tk = yf_tri(L.cb, n, k, tr);
+    const int km = max(k - 1, 0), kp = min(k + 1, n - 1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double2 *gi = L.gl + min(rg + ng * r, n - 1) * n;
+        h[r] = yfma(gi[kp], tk.p1, yfma(gi[km], tk.m1, ymul(gi[k], tk.z0)));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = rg + ng * r;
+        if (act && i < n) L.gl[i * n + k] = h[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = min(rg + ng * r, n - 1);
+        const Tri ti = yf_tri(L.cb, n, i, tr);
+        const double2 s = yfma(ti.p1, L.gl[min(i + 1, n - 1) * n + k],
+                               yfma(ti.m1, L.gl[max(i - 1, 0) * n + k],
+                                    ymul(ti.z0, L.gl[i * n + k])));
+        c[r].x -= s.x;
+        c[r].y -= s.y;
+    }
+    __syncthreads();
+}
+
+// In-place Gauss-Jordan inversion of the complement held in registers,
+// without pivoting.  Pivot p reads row p and column p of the current matrix
+// from LDS (buffer p & 1) and publishes row and column p + 1 after its
+// update into the other buffer: one barrier per pivot.  The pivots run in
+// blocks RB of ng (a compile-time block index, so that the register holding
+// row p + 1, row group (p + 1) mod ng, slot (p + 1) div ng, is static).
+template <int R, int RB>
+__device__ __forceinline__ void yf_pivot_block(double2 (&c)[R], const YFactorLds &L, int n,
+                                               int k, int rg, int ng, bool act) {
+    for (int s = 0; s < ng; ++s) {
+        const int p = RB * ng + s;
+        if (p >= n) return;
+        const int b = p & 1, nb = b ^ 1;
+        const double2 *rowp = L.rowb + 64 * b, *colp = L.colb + YF_COLB * b;
+        const double2 piv = rowp[p];
+        const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
+        const double2 d = cd(piv.x * inv, -piv.y * inv);   // 1 / C[p][p]
+        const double2 rkd = ymul(rowp[k], d);              // C[p][k] / C[p][p]
+        const double2 nd = yneg(d);
+        const bool kpiv = k == p;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double2 v = c[r];
+            const double2 f = colp[min(rg + ng * r, n - 1)];
+            const double2 upd = cd(v.x - (f.x * rkd.x - f.y * rkd.y),
+                                   v.y - (f.x * rkd.y + f.y * rkd.x));
+            const double2 colv = ymul(v, nd);
+            const double2 rowv = ysel(kpiv, d, rkd);
+            const double2 nv = ysel(kpiv, colv, upd);
+            c[r] = ysel(rg + ng * r == p, rowv, nv);
+        }
+        if (p + 1 < n && act) {
+            // row p + 1: row group s + 1 (slot RB), or row group 0 (slot
+            // RB + 1) when s + 1 == ng
+            const bool wrap = s + 1 == ng;
+            constexpr int RN = RB + 1 < R ? RB + 1 : RB;
+            if (rg == (wrap ? 0 : s + 1)) L.rowb[64 * nb + k] = ysel(wrap, c[RN], c[RB]);
+            if (k == p + 1) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (rg + ng * r < n) L.colb[YF_COLB * nb + rg + ng * r] = c[r];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int R, int... RBs>
+__device__ __forceinline__ void yf_pivot_blocks(double2 (&c)[R], const YFactorLds &L, int n,
+                                                int k, int rg, int ng, bool act,
+                                                std::integer_sequence<int, RBs...>) {
+    (yf_pivot_block<R, RBs>(c, L, n, k, rg, ng, act), ...);
+}
+
+template <int R>
+__device__ __forceinline__ void yf_invert(double2 (&c)[R], const YFactorLds &L, int n, int k, int rg, int ng,
+                          bool act) {
+    if (act && rg == 0) L.rowb[k] = c[0];
+    if (act && k == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (rg + ng * r < n) L.colb[rg + ng * r] = c[r];
+    }
+    __syncthreads();
+    yf_pivot_blocks(c, L, n, k, rg, ng, act, std::make_integer_sequence<int, R>());
+}
+
+// A_a[i][k] from cb
+__device__ __forceinline__ double2 yf_a(const double2 *cb, int n, int i, int k) {
+    const int mn = min(min(i, k), n - 1);
+    const double2 dg = cb[min(i, n - 1)], od = cb[n + mn];
+    return ysel(i == k, dg, ysel(k == i + 1 || i == k + 1, od, yz()));
+}
+
+template <int R>
+__device__ __forceinline__ void yf_store(const double2 (&c)[R], double2 *out, int n, int k,
+                                         int rg, int ng, bool act) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = rg + ng * r;
+        if (act && i < n) out[i * n + k] = c[r];
+    }
+}
+
+// The two halves of every strip: blockIdx.x = 2 j + half.
+template <int R>
+__global__ __launch_bounds__(YF_THREADS) void yfactor_half_kernel(const YStrip *ys, int ny,
+                                                                  const double2 *Dc,
+                                                                  const double2 *Uc, double2 *YF,
+                                                                  double2 *YB) {
+    const int j = blockIdx.x >> 1, half = blockIdx.x & 1;
+    const YStrip S = ys[j];
+    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    extern __shared__ double2 ylds[];
+    const YFactorLds L = yf_lds(ylds, n);
+    const int ng = YF_THREADS / n, k = threadIdx.x % n, rg = threadIdx.x / n;
+    const bool act = rg < ng;
+    double2 c[R];
+    const int a0 = half == 0 ? 0 : ny - 1, a1 = m, da = half == 0 ? 1 : -1;
+    for (int a = a0; a != a1; a += da) {
+        const bool first = a == a0;
+        // coupling block: lower B_{a-1}, upper B_a
+        const int ab = first ? -1 : (half == 0 ? a - 1 : a);
+        if (!first) yf_store(c, L.gl, n, k, rg, ng, act);   // the previous inverse
+        yf_coef(S, ny, a, ab, Dc, Uc, L.cb, YB);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) c[r] = yf_a(L.cb, n, rg + ng * r, k);
+        if (!first) yf_sandwich(c, L, n, k, rg, ng, act, half);
+        yf_invert(c, L, n, k, rg, ng, act);
+        yf_store(c, YF + S.yoff + (long)a * nn, n, k, rg, ng, act);
+    }
+}
+
+// The middle line of every strip: C = A_m - B_{m-1}^T T_{m-1}^{-1} B_{m-1}
+// - B_m U_{m+1}^{-1} B_m^T (the terms present), inverted.
+template <int R>
+__global__ __launch_bounds__(YF_THREADS) void yfactor_mid_kernel(const YStrip *ys, int ny,
+                                                                 const double2 *Dc,
+                                                                 const double2 *Uc, double2 *YF,
+                                                                 double2 *YB) {
+    const YStrip S = ys[blockIdx.x];
+    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    extern __shared__ double2 ylds[];
+    const YFactorLds L = yf_lds(ylds, n);
+    const int ng = YF_THREADS / n, k = threadIdx.x % n, rg = threadIdx.x / n;
+    const bool act = rg < ng;
+    double2 c[R];
+    yf_coef(S, ny, m, -1, Dc, Uc, L.cb, YB);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) c[r] = yf_a(L.cb, n, rg + ng * r, k);
+    __syncthreads();
+    for (int side = 0; side < 2; ++side) {
+        const int ab = side == 0 ? m - 1 : m;           // coupling block index
+        const int ag = side == 0 ? m - 1 : m + 1;       // neighbouring complement
+        if (ag < 0 || ag >= ny) continue;
+        yf_coef(S, ny, m, ab, Dc, Uc, L.cb, YB);
+        const double2 *src = YF + S.yoff + (long)ag * nn;
+        for (int e = threadIdx.x; e < nn; e += blockDim.x) L.gl[e] = src[e];
+        __syncthreads();
+        yf_sandwich(c, L, n, k, rg, ng, act, side);
+    }
+    yf_invert(c, L, n, k, rg, ng, act);
+    yf_store(c, YF + S.yoff + (long)m * nn, n, k, rg, ng, act);
+}
+
+// Rows per thread the factor needs for strips of at most max_nx node-lines
+// (the largest ceil(n / (256 div n)) over n <= max_nx).
+int yf_rows(int max_nx) {
+    int r = 1;
+    for (int n = 1; n <= max_nx; ++n) {
+        const int ng = YF_THREADS / n;
+        r = std::max(r, (n + ng - 1) / ng);
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------- solve
+// One workgroup of 8 waves per strip half.  Thread (i = lane, w = wave)
+// holds the entries G[q][i], q = w + 8 r, of the inverse a step multiplies
+// by (G is symmetric, so these are row i's terms, read coalesced); wave 0
+// (i < n) also holds row i's coupling coefficients and right-hand side.
+// The data of the next YS_DEPTH - 1 steps are loaded while the current one
+// computes.
+constexpr int YS_THREADS = 512;
+constexpr int YS_NR = 8;
+constexpr int YS_DEPTH = 4;
+
+struct YStage {
+    double2 g[YS_NR];
+    double2 cd, cu, cl;     // B[i][i], B[i][i+1], B[i+1][i] of the step's coupling block
+    double2 rhs;
+};
+
+// Loads of one step, all unconditional (a load under a branch would make the
+// compiler wait for every load in flight before using any): G's entries
+// G[q][i] (indices clamped into the block; the clamped q >= n meet v[q] = 0,
+// rows i >= n are never read back), the coupling block's coefficients (yb,
+// y-line-major) and the right-hand side at y-line a (src, packed lines from
+// line off) of row min(i, n - 1).
+__device__ __forceinline__ void ys_load(YStage &s, const double2 *G, const double2 *yb,
+                                        const double2 *src, long off, int ny, int a, int n, int i,
+                                        int w) {
+    const int ic = min(i, n - 1);
+#pragma unroll
+    for (int r = 0; r < YS_NR; ++r) s.g[r] = G[min(w + 8 * r, n - 1) * n + ic];
+    s.cd = yb[ic];
+    s.cu = yb[n + ic];
+    s.cl = yb[2 * n + ic];
+    s.rhs = src[(off + ic) * ny + a];
+}
+
+// Partial product of the step: sum over this thread's q of G[q][i] v[q].
+__device__ __forceinline__ double2 ys_partial(const YStage &s, const double2 *v, int w) {
+    double2 acc = yz();
+#pragma unroll
+    for (int r = 0; r < YS_NR; ++r) acc = yfma(s.g[r], v[w + 8 * r], acc);
+    return acc;
+}
+
+// Sum of the 8 waves' partials of row j (0 outside [0, n)).
+__device__ __forceinline__ double2 ys_row(const double2 *part, int j, int n) {
+    double2 s = yz();
+    if (j < 0 || j >= n) return s;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+        const double2 p = part[w * 64 + j];
+        s.x += p.x;
+        s.y += p.y;
+    }
+    return s;
+}
+
+__device__ __forceinline__ double2 shfl_up1(double2 v) {
+    return cd(__shfl_up(v.x, 1), __shfl_up(v.y, 1));
+}
+
+// Row i (wave 0, every lane) of the coupling product with t = (t_{i-1},
+// t_i, t_{i+1}):
+// tr = 0: (B^T t)_i = B[i-1][i] t_{i-1} + B[i][i] t_i + B[i+1][i] t_{i+1}
+// tr = 1: (B t)_i   = B[i][i-1] t_{i-1} + B[i][i] t_i + B[i][i+1] t_{i+1}
+// (row i - 1's coefficients from the lane below).
+__device__ __forceinline__ double2 ys_couple(const YStage &s, int i, double2 tm, double2 t0,
+                                            double2 tp, int tr) {
+    const double2 um = shfl_up1(s.cu), lm = shfl_up1(s.cl);
+    double2 acc = ymul(s.cd, t0);
+    acc = yfma(ysel(tr, s.cu, s.cl), tp, acc);
+    if (i > 0) acc = yfma(ysel(tr, lm, um), tm, acc);
+    return acc;
+}
+
+// Forward sweeps, blockIdx.x = 2 j + half: lower w_a = b_a - B_{a-1}^T
+// T_{a-1}^{-1} w_{a-1} for a = 0 .. m - 1, upper v_a = b_a - B_a U_{a+1}^{-1}
+// v_{a+1} for a = ny - 1 .. m + 1; w and v are written over x.  Step k
+// (a = a0 + k da) multiplies by the inverse of y-line a - da and coupling
+// block a - 1 (lower) or a (upper).
+__global__ __launch_bounds__(YS_THREADS) void ysolve_fwd_kernel(const YStrip *ys, int ny,
+                                                                const double2 *YF,
+                                                                const double2 *YB,
+                                                                const double2 *b, double2 *x,
+                                                                const StepCtl *c, int *ran) {
+    if (yidle(c)) return;
+    if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
+    const int j = blockIdx.x >> 1, half = blockIdx.x & 1;
+    const YStrip S = ys[j];
+    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ double2 v[64], part[8 * 64];
+    const int a0 = half == 0 ? 0 : ny - 1, da = half == 0 ? 1 : -1;
+    const int steps = half == 0 ? m : ny - 1 - m;
+    if (threadIdx.x < 64) v[threadIdx.x] = yz();
+    // step k's data; steps past the end reload the last one (unused), step
+    // 0 has no product and points G and yb at y-line 0's (unused)
+    auto load = [&](YStage &st, int k) {
+        k = min(k, steps - 1);
+        const int a = a0 + k * da;
+        const int ag = k > 0 ? a - da : 0, ab = k > 0 ? (half == 0 ? a - 1 : a) : 0;
+        ys_load(st, YF + S.yoff + (long)ag * nn, YB + S.boff + (long)ab * 3 * n, b, S.off, ny,
+                a, n, i, w);
+    };
+    auto step = [&](const YStage &st, int k) {
+        const int a = a0 + k * da;
+        double2 val = st.rhs;
+        if (k > 0) {
+            part[w * 64 + i] = ys_partial(st, v, w);
+            __syncthreads();
+            if (w == 0) {
+                const double2 s = ys_couple(st, i, ys_row(part, i - 1, n), ys_row(part, i, n),
+                                            ys_row(part, i + 1, n), half);
+                val.x -= s.x;
+                val.y -= s.y;
+            }
+        }
+        if (w == 0 && i < n) {
+            v[i] = val;
+            x[(long)(S.off + i) * ny + a] = val;
+        }
+        __syncthreads();
+    };
+    YStage s0, s1, s2, s3;
+    load(s0, 0);
+    load(s1, 1);
+    load(s2, 2);
+    __syncthreads();
+    for (int k = 0; k < steps; k += YS_DEPTH) {
+        load(s3, k + 3);
+        step(s0, k);
+        if (k + 1 >= steps) break;
+        load(s0, k + 4);
+        step(s1, k + 1);
+        if (k + 2 >= steps) break;
+        load(s1, k + 5);
+        step(s2, k + 2);
+        if (k + 3 >= steps) break;
+        load(s2, k + 6);
+        step(s3, k + 3);
+    }
+}
+
+// Backward sweeps: lower x_a = T_a^{-1}(w_a - B_a x_{a+1}) for a = m - 1
+// down to 0, upper x_a = U_a^{-1}(v_a - B_{a-1}^T x_{a-1}) for a = m + 1 up.
+// Step k (a = a0 + k da) multiplies by the inverse of y-line a, coupling
+// block a (lower) or a - 1 (upper), and reads w_a / v_a from x.
+__global__ __launch_bounds__(YS_THREADS) void ysolve_bwd_kernel(const YStrip *ys, int ny,
+                                                                const double2 *YF,
+                                                                const double2 *YB, double2 *x,
+                                                                const StepCtl *c) {
+    if (yidle(c)) return;
+    const int j = blockIdx.x >> 1, half = blockIdx.x & 1;
+    const YStrip S = ys[j];
+    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ double2 v[64], part[8 * 64];
+    const int a0 = half == 0 ? m - 1 : m + 1, da = half == 0 ? -1 : 1;
+    const int steps = half == 0 ? m : ny - 1 - m;
+    if (threadIdx.x < 64) v[threadIdx.x] = yz();
+    // x_m, the start of both sweeps (rows i - 1, i, i + 1 in wave 0)
+    double2 tm = yz(), t0 = yz(), tp = yz();
+    if (w == 0) {
+        const double2 *xm = x + (long)S.off * ny + m;
+        if (i > 0 && i - 1 < n) tm = xm[(long)(i - 1) * ny];
+        if (i < n) t0 = xm[(long)i * ny];
+        if (i + 1 < n) tp = xm[(long)(i + 1) * ny];
+    }
+    auto load = [&](YStage &st, int k) {
+        k = min(k, steps - 1);   // past the end: the last step's data again (unused)
+        const int a = a0 + k * da;
+        const int ab = half == 0 ? a : a - 1;
+        ys_load(st, YF + S.yoff + (long)a * nn, YB + S.boff + (long)ab * 3 * n, x, S.off, ny, a,
+                n, i, w);
+    };
+    auto step = [&](const YStage &st, int k) {
+        const int a = a0 + k * da;
+        if (w == 0) {
+            const double2 s = ys_couple(st, i, tm, t0, tp, half == 0 ? 1 : 0);
+            if (i < n) v[i] = cd(st.rhs.x - s.x, st.rhs.y - s.y);
+        }
+        __syncthreads();
+        part[w * 64 + i] = ys_partial(st, v, w);
+        __syncthreads();
+        if (w == 0) {
+            tm = ys_row(part, i - 1, n);
+            t0 = ys_row(part, i, n);
+            tp = ys_row(part, i + 1, n);
+            if (i < n) x[(long)(S.off + i) * ny + a] = t0;
+        }
+    };
+    YStage s0, s1, s2, s3;
+    load(s0, 0);
+    load(s1, 1);
+    load(s2, 2);
+    for (int k = 0; k < steps; k += YS_DEPTH) {
+        load(s3, k + 3);
+        step(s0, k);
+        if (k + 1 >= steps) break;
+        load(s0, k + 4);
+        step(s1, k + 1);
+        if (k + 2 >= steps) break;
+        load(s1, k + 5);
+        step(s2, k + 2);
+        if (k + 3 >= steps) break;
+        load(s2, k + 6);
+        step(s3, k + 3);
+    }
+}
+
+// Middle line: x_m = M_m^{-1}(b_m - B_{m-1}^T T_{m-1}^{-1} w_{m-1} - B_m
+// U_{m+1}^{-1} v_{m+1}), the terms present; three products of one step
+// each, all their data loaded up front.
+__global__ __launch_bounds__(YS_THREADS) void ysolve_mid_kernel(const YStrip *ys, int ny,
+                                                                const double2 *YF,
+                                                                const double2 *YB,
+                                                                const double2 *b, double2 *x,
+                                                                const StepCtl *c) {
+    if (yidle(c)) return;
+    const YStrip S = ys[blockIdx.x];
+    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ double2 v[64], part[8 * 64];
+    if (threadIdx.x < 64) v[threadIdx.x] = yz();   // entries q >= n meet clamped G values
+    const bool lo = m - 1 >= 0, hi = m + 1 < ny;
+    YStage sl, sh, sm;
+    // lower side: inverse of m - 1, coupling block m - 1, w_{m-1} from x;
+    // upper side: inverse of m + 1, coupling block m, v_{m+1} from x (a
+    // missing side points at y-line m's data, unused); the middle product
+    // has no coupling block (coefficients of block 0 loaded, unused)
+    const int al = lo ? m - 1 : m, ah = hi ? m + 1 : m, bl = lo ? m - 1 : 0, bh = hi ? m : 0;
+    ys_load(sl, YF + S.yoff + (long)al * nn, YB + S.boff + (long)bl * 3 * n, x, S.off, ny, al,
+            n, i, w);
+    ys_load(sh, YF + S.yoff + (long)ah * nn, YB + S.boff + (long)bh * 3 * n, x, S.off, ny, ah,
+            n, i, w);
+    ys_load(sm, YF + S.yoff + (long)m * nn, YB + S.boff, b, S.off, ny, m, n, i, w);
+    double2 r = sm.rhs;
+    auto side = [&](const YStage &st, int tr) {
+        if (w == 0 && i < n) v[i] = st.rhs;
+        __syncthreads();
+        part[w * 64 + i] = ys_partial(st, v, w);
+        __syncthreads();
+        if (w == 0) {
+            const double2 s = ys_couple(st, i, ys_row(part, i - 1, n), ys_row(part, i, n),
+                                        ys_row(part, i + 1, n), tr);
+            r.x -= s.x;
+            r.y -= s.y;
+        }
+        __syncthreads();
+    };
+    if (lo) side(sl, 0);
+    if (hi) side(sh, 1);
+    if (w == 0 && i < n) v[i] = r;
+    __syncthreads();
+    part[w * 64 + i] = ys_partial(sm, v, w);
+    __syncthreads();
+    if (w == 0 && i < n) x[(long)(S.off + i) * ny + m] = ys_row(part, i, n);
+}
+
+}  // namespace
+
+size_t yorder_factor_lds(int max_nx) {
+    return sizeof(double2) *
+           (128 + 2 * (size_t)YF_COLB + 5 * (size_t)max_nx + (size_t)max_nx * max_nx);
+}
+
+// Per y-line: the inversion (n^3 complex multiply-adds) and the two
+// products with the tridiagonal coupling block (6 n^2), 8 real flops each.
+double yorder_factor_flops(int ny, int nx) {
+    const double n = nx;
+    return (double)ny * 8.0 * (n * n * n + 6.0 * n * n);
+}
+
+hipError_t launch_yfactor(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
+                          const double2 *Dc, const double2 *Uc, double2 *YF, double2 *YB,
+                          hipEvent_t ev0, hipEvent_t ev1) {
+    hipError_t e;
+    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
+    const size_t lds = yorder_factor_lds(max_nx);
+    const int rows = yf_rows(max_nx);
+    auto go = [&](auto half, auto mid) {
+        hipLaunchKernelGGL(half, dim3(2 * nstrips), dim3(YF_THREADS), lds, st, ys, ny, Dc, Uc, YF,
+                           YB);
+        hipLaunchKernelGGL(mid, dim3(nstrips), dim3(YF_THREADS), lds, st, ys, ny, Dc, Uc, YF, YB);
+    };
+    if (rows <= 4) go(yfactor_half_kernel<4>, yfactor_mid_kernel<4>);
+    else if (rows <= 8) go(yfactor_half_kernel<8>, yfactor_mid_kernel<8>);
+    else if (rows <= 16) go(yfactor_half_kernel<16>, yfactor_mid_kernel<16>);
+    else return hipErrorInvalidValue;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev1) e = hipEventRecord(ev1, st);
+    return e;
+}
+
+hipError_t launch_ysolve(hipStream_t st, const YStrip *ys, int nstrips, int ny, const double2 *YF,
+                         const double2 *YB, const double2 *b, double2 *x, const StepCtl *c,
+                         int *ran, hipEvent_t ev0, hipEvent_t ev1) {
+    hipError_t e;
+    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(ysolve_fwd_kernel, dim3(2 * nstrips), dim3(YS_THREADS), 0, st, ys, ny, YF,
+                       YB, b, x, c, ran);
+    hipLaunchKernelGGL(ysolve_mid_kernel, dim3(nstrips), dim3(YS_THREADS), 0, st, ys, ny, YF, YB,
+                       b, x, c);
+    hipLaunchKernelGGL(ysolve_bwd_kernel, dim3(2 * nstrips), dim3(YS_THREADS), 0, st, ys, ny, YF,
+                       YB, x, c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev1) e = hipEventRecord(ev1, st);
+    return e;
+}

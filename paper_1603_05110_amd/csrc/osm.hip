@@ -45,6 +45,13 @@ struct osm_handle {
     void *Rbuf = nullptr, *Cbuf = nullptr, *Pbuf = nullptr;
     bool sym = false;                // factor holds upper triangles only
     void *spart = nullptr;           // half-storage solve: members' partials
+    // factor in y-line order (osm_options.strip_order): the inverses of the
+    // y-lines' Schur complements, strip by strip
+    int order = 0;                   // in use: 0 = node-line order (F), 1 = y-line order (YF)
+    bool order_tuned = true;         // false until the autotuner has chosen
+    double2 *YF = nullptr, *YB = nullptr;
+    YStrip *ys_d = nullptr;
+    double order_ms[2] = {0.0, 0.0}; // autotuner: one solve in each order (ms)
     // strip vectors
     double2 *zeta = nullptr, *res = nullptr, *delta = nullptr;
     // interface vectors
@@ -217,6 +224,8 @@ std::string validate(const osm_problem *p, const osm_options *o) {
     if (o->solve_shape < 0 || o->solve_shape > 8) return "solve_shape must be 0 (tuned) or 1..8";
     if (o->q_estimate < 0 || o->q_estimate > 1) return "q_estimate must be 0 or 1";
     if (o->g1_init < 0 || o->g1_init > 1) return "g1_init must be 0 (zero) or 1 (seeded random)";
+    if (o->strip_order < 0 || o->strip_order > 2)
+        return "strip_order must be 0 (node-line), 1 (y-line) or 2 (tuned)";
     if (!isfinite(p->beta)) return "beta not finite";
     std::vector<int> c = strip_cells_of(p);
     if ((int)c.size() != p->nsub) return "strip_cells NULL but ncx not divisible by nsub";
@@ -226,6 +235,15 @@ std::string validate(const osm_problem *p, const osm_options *o) {
         sum += v;
     }
     if (sum != p->ncx) return "strip_cells do not sum to ncx";
+    if (o->strip_order == 1) {
+        if (p->tc != OSM_TC_ROBIN)
+            return "strip_order 1 (y-line order) needs the Robin condition: S_pade^m couples "
+                   "a strip edge's y-lines densely";
+        for (int v : c)
+            if (v + 1 > YORDER_MAX_NX)
+                return "strip_order 1 (y-line order) needs every strip within " +
+                       std::to_string(YORDER_MAX_NX) + " node-lines";
+    }
     if (o->algo != OSM_CLASSICAL && o->algo != OSM_PRECOND && o->algo != OSM_INTERFACE_KRYLOV)
         return "bad algo";
     if (o->algo == OSM_INTERFACE_KRYLOV && p->beta != 0.0)
@@ -251,7 +269,19 @@ struct Sizes {
     int lh;     // L_h and its kernels are built (OSM_PRECOND)
     int fp32;
     int sym;    // the upper-triangle solve kernels are available (partials buffer)
+    int yo;     // factors kept: 0 = node-line order, 1 = y-line order, 2 = both
+    long ysum;  // elements of the y-line-order factor: ny * sum_j nx_j^2
+    long ybsum; // its coupling coefficients: 3 ny * sum_j nx_j
 };
+
+// The y-line order is available for Robin problems whose strips all have at
+// most YORDER_MAX_NX node-lines.
+static bool yorder_ok(const osm_problem *p, const std::vector<int> &cells) {
+    if (p->tc != OSM_TC_ROBIN) return false;
+    for (int v : cells)
+        if (v + 1 > YORDER_MAX_NX) return false;
+    return true;
+}
 
 // Column counts the upper-triangle solve has kernels for (33 chunks of 64 in
 // c32, 17 in FP64); the setup also checks the device's LDS.
@@ -279,14 +309,29 @@ Sizes sizes_of(const osm_problem *p, const osm_options *o) {
     // dense edge blocks in batches of at most 256 MB (at least one edge)
     s.peb = s.pm ? std::max(1L, std::min(2 * s.N, (256L << 20) / (s.n * s.n * 16))) : 0;
     s.fp32 = o->prec == OSM_C32_REFINE;
-    s.sym = sym_eligible(s.n, s.fp32);
+    s.yo = 0;
+    s.ysum = 0;
+    s.ybsum = 0;
+    if (o->strip_order == 1) s.yo = 1;
+    else if (o->strip_order == 2 && yorder_ok(p, c)) s.yo = 2;
+    if (s.yo) {
+        for (int v : c) {
+            s.ysum += (long)(v + 1) * (v + 1);
+            s.ybsum += v + 1;
+        }
+        s.ysum *= s.n;
+        s.ybsum *= 3 * s.n;
+    }
+    if (s.yo == 1) s.fp32 = 0;   // the y-line order is FP64 throughout
+    s.sym = s.yo != 1 && sym_eligible(s.n, s.fp32);
     return s;
 }
 
 uint64_t device_bytes(const Sizes &s) {
     uint64_t fe = s.fp32 ? 8 : 16;
     uint64_t b = 0;
-    b += (uint64_t)s.Lt * s.n * s.n * fe;               // factor
+    if (s.yo != 1) b += (uint64_t)s.Lt * s.n * s.n * fe;                     // factor
+    if (s.yo) b += (uint64_t)(s.ysum + s.ybsum) * 16 + (uint64_t)s.N * sizeof(YStrip);  // y-line factor
     b += 2ull * s.Lt * s.n * 3 * 16;                    // Dc, Uc
     b += (uint64_t)s.nglob * s.n * 8;                   // W
     b += 3ull * s.Lt * s.n * 16;                        // zeta, res, delta
@@ -417,6 +462,21 @@ osm_status do_factor(osm_handle *h) {
     if (h->pm)   // LU of every edge operator D_{e,s}(W_n)
         HIPCHK(h, launch_pade_lu(h->st, h->P, h->strips_d, h->W_d, 2 * h->N, 0, h->pm, h->pad,
                                  h->psub, h->pcp, h->pinv));
+    if (h->YF && (h->order == 1 || !h->order_tuned)) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (h->prof && h->order == 1) {
+            double fl = 0.0;
+            for (const StripMeta &sm : h->strips_h) fl += yorder_factor_flops(h->n, sm.nx);
+            osm_status s = fslot(h, fl, &e0, &e1);
+            if (s != OSM_OK) return s;
+        }
+        HIPCHK(h, launch_yfactor(h->st, h->ys_d, h->N, h->n, h->maxnx, h->Dc, h->Uc, h->YF, h->YB,
+                                 e0, e1));
+        if (h->order == 1) {
+            h->factored = true;
+            return OSM_OK;
+        }
+    }
     osm_status s;
     int depth = (int)h->step_batch.size();
     const int pmode = h->pm ? 1 : 0;
@@ -439,6 +499,13 @@ osm_status do_factor(osm_handle *h) {
 // inverse read in the forward and the backward sweep (the last line of a
 // strip once), plus b, x and the coupling coefficients once.
 double single_solve_bytes(const osm_handle *h) {
+    if (h->order == 1) {
+        // y-line order: 2 ny - 1 inverses of nx_j^2 FP64 values per strip
+        double b = 0.0;
+        for (const StripMeta &sm : h->strips_h)
+            b += (2.0 * h->n - 1.0) * (double)sm.nx * sm.nx * 16.0;
+        return b + (double)h->Lt * h->n * 80.0;
+    }
     double es = h->fp32 ? 8.0 : 16.0;
     double per = solve_shape_is_sym(h->shape) ? 0.5 * (double)h->n * (h->n + 1)
                                               : (double)h->n * h->n;
@@ -467,7 +534,34 @@ osm_status prof_collect(osm_handle *h) {
 
 // x = K^{-1} b on every strip (packed layout); skipped on the device when
 // ctl says the fixed point is done.
+// Event pair and work flag of the next timed solve launch.
+osm_status solve_slot(osm_handle *h, hipEvent_t *e0, hipEvent_t *e1, int **ran) {
+    if (h->prof_used == PROF_SLOTS) {
+        HIPCHK(h, hipStreamSynchronize(h->st));
+        osm_status s = prof_collect(h);
+        if (s != OSM_OK) return s;
+    }
+    int slot = h->prof_used++;
+    if ((int)h->evs.size() < 2 * (slot + 1))
+        return fail(h, OSM_ESTATE, "timing events not created (osm_kernel_timing)");
+    *e0 = h->evs[2 * slot];
+    *e1 = h->evs[2 * slot + 1];
+    *ran = h->ran_d + slot;
+    return OSM_OK;
+}
+
 osm_status do_solve(osm_handle *h, const double2 *b, double2 *x, const StepCtl *ctl = nullptr) {
+    if (h->order == 1) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int *ran = nullptr;
+        if (h->prof) {
+            osm_status s = solve_slot(h, &e0, &e1, &ran);
+            if (s != OSM_OK) return s;
+        }
+        HIPCHK(h, launch_ysolve(h->st, h->ys_d, h->N, h->n, h->YF, h->YB, b, x, ctl, ran, e0,
+                                e1));
+        return OSM_OK;
+    }
     SolveArgs a;
     a.n = h->n;
     a.team = h->team;
@@ -490,17 +584,8 @@ osm_status do_solve(osm_handle *h, const double2 *b, double2 *x, const StepCtl *
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->prof) {
-        if (h->prof_used == PROF_SLOTS) {
-            HIPCHK(h, hipStreamSynchronize(h->st));
-            osm_status s = prof_collect(h);
-            if (s != OSM_OK) return s;
-        }
-        int slot = h->prof_used++;
-        if ((int)h->evs.size() < 2 * (slot + 1))
-            return fail(h, OSM_ESTATE, "timing events not created (osm_kernel_timing)");
-        e0 = h->evs[2 * slot];
-        e1 = h->evs[2 * slot + 1];
-        a.ran = h->ran_d + slot;
+        osm_status s = solve_slot(h, &e0, &e1, &a.ran);
+        if (s != OSM_OK) return s;
     }
     HIPCHK(h, launch_strip_solve(h->st, a, h->fp32, e0, e1));
     return OSM_OK;
@@ -1154,7 +1239,7 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
                             osm_handle **out, bool allow_sym) {
     Sizes sz = sizes_of(prob, opt);
     sz.sym = allow_sym && sz.sym && solve_sym_supported((int)sz.n, sz.fp32);
-    {
+    if (sz.yo != 1) {
         // the strip solve keeps both products of a step (2 ny complex values)
         // in one workgroup's LDS
         int dev = 0, lim = 0;
@@ -1282,10 +1367,31 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         SALLOC(h->step_first_d, int, first_all.size());
         SALLOC(h->ff_lines_d, int, h->maxnx);
         SALLOC(h->ff_first_d, int, h->maxnx);
+        if (sz.yo) {
+            // y-line order: strip j's inverses start at yoff_j, ny nx_j^2 each
+            std::vector<YStrip> ys(h->N);
+            long yo = 0, bo = 0;
+            for (int j = 0; j < h->N; ++j) {
+                ys[j].off = h->strips_h[j].off;
+                ys[j].nx = h->strips_h[j].nx;
+                ys[j].yoff = yo;
+                ys[j].boff = bo;
+                yo += (long)h->n * ys[j].nx * ys[j].nx;
+                bo += 3L * h->n * ys[j].nx;
+            }
+            SALLOC(h->YF, double2, yo);
+            SALLOC(h->YB, double2, bo);
+            SALLOC(h->ys_d, YStrip, h->N);
+            HIPCHK(h, hipMemcpy(h->ys_d, ys.data(), sizeof(YStrip) * h->N, hipMemcpyHostToDevice));
+            h->order = sz.yo == 1 ? 1 : 0;
+            h->order_tuned = sz.yo != 2;
+        }
         {
             hipError_t e;
-            h->F = dalloc<char>(h, fe * (size_t)h->Lt * nn, &e);
-            if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for the factor");
+            if (sz.yo != 1) {
+                h->F = dalloc<char>(h, fe * (size_t)h->Lt * nn, &e);
+                if (e != hipSuccess) return fail(h, OSM_ENOMEM, "hipMalloc failed for the factor");
+            }
             // panels for a batch of 2 lines per strip in the factor precision,
             // and for one strip in FP64 (the free factor built for L_h)
             size_t lb = std::max(fe * 2 * (size_t)h->N, sizeof(double2));
@@ -1411,6 +1517,11 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             HIPCHK(h, hipMemcpy(h->gctl, &c0, sizeof(c0), hipMemcpyHostToDevice));
         }
         // workgroups per strip in the solve: fill the resident capacity
+        if (sz.yo == 1) {
+            h->team_tuned = true;   // no node-line solve
+            if (h->opt.algo == OSM_PRECOND) return build_lh(h);
+            return OSM_OK;
+        }
         if (h->opt.solve_shape > 0) h->shape = h->opt.solve_shape - 1;
         if (solve_shape_is_sym(h->shape) && !h->spart)
             return fail(h, OSM_EINVAL, "solve_shape: no upper-triangle kernel for this ny and precision");
@@ -1519,6 +1630,52 @@ static osm_status autotune_team(osm_handle *h) {
     return OSM_OK;
 }
 
+// With strip_order 2: after the first factorisation (both orders factored)
+// time three solves in each order, the node-line one with its tuned kernel,
+// and keep the faster; the y-line order then runs in FP64 only.
+static osm_status autotune_order(osm_handle *h) {
+    if (h->order_tuned) return OSM_OK;
+    osm_status se = create_timing_events(h);
+    if (se != OSM_OK) return se;
+    bool prof = h->prof;
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    osm_status s0 = prof_collect(h);
+    if (s0 != OSM_OK) return s0;
+    double keep_ms = h->solve_ms;
+    long long keep_n = h->solve_launches;
+    double keep_b = h->solve_bytes;
+    HIPCHK(h, hipMemsetAsync(h->res, 0, sizeof(double2) * (size_t)h->Lt * h->n, h->st));
+    HIPCHK(h, launch_clear_flag(h->st, h->err_d));
+    for (int o = 0; o < 2; ++o) {
+        h->order = o;
+        h->prof = false;
+        osm_status s = do_solve(h, h->res, h->delta);
+        if (s == OSM_OK) s = check_solve_error(h);
+        h->prof = true;
+        h->solve_ms = 0.0;
+        h->solve_launches = 0;
+        for (int r = 0; r < 3 && s == OSM_OK; ++r) {
+            s = do_solve(h, h->res, h->delta);
+            if (s == OSM_OK) s = check_solve_error(h);
+        }
+        if (s != OSM_OK) { h->prof = prof; h->order = 0; return s; }
+        h->order_ms[o] = h->solve_ms / 3.0;
+    }
+    h->order = h->order_ms[1] < h->order_ms[0] ? 1 : 0;
+    if (h->order == 1) h->fp32 = 0;
+    h->prof = prof;
+    h->solve_ms = keep_ms;
+    h->solve_launches = keep_n;
+    h->solve_bytes = keep_b;
+    h->order_tuned = true;
+    return OSM_OK;
+}
+
+static osm_status autotune(osm_handle *h) {
+    osm_status s = autotune_team(h);
+    return s == OSM_OK ? autotune_order(h) : s;
+}
+
 osm_status osm_factor(osm_handle *h, const double *W_dev) {
     if (!h) return OSM_EINVAL;
     SINGLE_ONLY(h);
@@ -1527,7 +1684,7 @@ osm_status osm_factor(osm_handle *h, const double *W_dev) {
                              hipMemcpyDeviceToDevice, h->st));
     osm_status s = do_factor(h);
     if (s != OSM_OK) return s;
-    s = autotune_team(h);
+    s = autotune(h);
     if (s != OSM_OK) return s;
     HIPCHK(h, hipStreamSynchronize(h->st));
     return OSM_OK;
@@ -1542,7 +1699,7 @@ osm_status osm_factor_rotating(osm_handle *h, int32_t n) {
                                 h->prob.vyy, t1, t0, h->W_d));
     osm_status s = do_factor(h);
     if (s != OSM_OK) return s;
-    s = autotune_team(h);
+    s = autotune(h);
     if (s != OSM_OK) return s;
     HIPCHK(h, hipStreamSynchronize(h->st));
     return OSM_OK;
@@ -1762,12 +1919,31 @@ osm_status osm_get_factor(osm_handle *h, void *dst_dev) {
     SINGLE_ONLY(h);
     if (!dst_dev) return fail(h, OSM_EINVAL, "dst_dev is NULL");
     if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called first");
+    if (!h->F || h->order == 1)
+        return fail(h, OSM_ESTATE, "the strip factor is kept in y-line order (osm_get_yfactor)");
     size_t fe = h->fp32 ? sizeof(float2) : sizeof(double2);
     HIPCHK(h, hipMemcpyAsync(dst_dev, h->F, fe * (size_t)h->Lt * h->n * h->n,
                              hipMemcpyDeviceToDevice, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
     return OSM_OK;
 }
+
+osm_status osm_get_yfactor(osm_handle *h, osm_c64 *dst_dev) {
+    if (!h) return OSM_EINVAL;
+    SINGLE_ONLY(h);
+    if (!dst_dev) return fail(h, OSM_EINVAL, "dst_dev is NULL");
+    if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called first");
+    if (!h->YF || h->order != 1)
+        return fail(h, OSM_ESTATE, "the strip factor is not kept in y-line order");
+    long cnt = 0;
+    for (const StripMeta &sm : h->strips_h) cnt += (long)h->n * sm.nx * sm.nx;
+    HIPCHK(h, hipMemcpyAsync(dst_dev, h->YF, sizeof(double2) * (size_t)cnt,
+                             hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return OSM_OK;
+}
+
+int32_t osm_strip_order(const osm_handle *h) { return h ? h->order : 0; }
 
 // Every event pair a timed launch may use, created once (when timing is
 // switched on, and by the solve autotuner), so that timed steps allocate
@@ -2087,6 +2263,8 @@ static std::string validate_batch(const osm_problem *probs, int32_t nb, const os
         return "batched instances run the classical or the preconditioned algorithm";
     if (opt->algo == OSM_PRECOND && opt->krylov != 0)
         return "preconditioned batched instances solve P x = y by GMRES (krylov = 0)";
+    if (opt->strip_order != 0)
+        return "batched instances factor their strips in node-line order (strip_order = 0)";
     for (int b = 0; b < nb; ++b)
         if (probs[b].tc != OSM_TC_ROBIN)
             return "instance " + std::to_string(b) + ": batched instances use the Robin condition";

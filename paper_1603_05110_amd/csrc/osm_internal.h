@@ -225,6 +225,31 @@ int solve_shape_is_sym(int shape);
 int solve_sym_supported(int n, int fp32);
 size_t solve_pf_smem(int n, int fp32);
 
+// kernels_yorder.hip: the strip factor and solve in y-line order (the
+// strip's unknowns taken y-line by y-line: blocks of its nx node-lines,
+// block tridiagonal along the ny y-lines), twisted, FP64; Robin only.
+#define YORDER_MAX_NX 64
+struct YStrip {
+    int off;     // first packed line of the strip
+    int nx;      // node-lines of the strip (<= YORDER_MAX_NX)
+    long yoff;   // first element of its inverses in the factor: ny x nx x nx
+    long boff;   // first element of its coupling coefficients: (ny - 1) x 3 x nx
+                 // (per y-line a: B_a's diagonal, upper and lower entries)
+};
+size_t yorder_factor_lds(int max_nx);
+// algorithmic flops of factoring one strip (ny y-lines of nx unknowns)
+double yorder_factor_flops(int ny, int nx);
+// Dc, Uc: coefficients of every packed line (launch_coef layout); writes the
+// inverses (YF) and the coupling coefficients in y-line order (YB)
+hipError_t launch_yfactor(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
+                          const double2 *Dc, const double2 *Uc, double2 *YF, double2 *YB,
+                          hipEvent_t ev0, hipEvent_t ev1);
+// x = K^{-1} b on every strip; skipped when c says the fixed point is done
+// (ran, when given, set to 1 otherwise); ev0/ev1 bracket the three kernels
+hipError_t launch_ysolve(hipStream_t st, const YStrip *ys, int nstrips, int ny, const double2 *YF,
+                         const double2 *YB, const double2 *b, double2 *x, const StepCtl *c,
+                         int *ran, hipEvent_t ev0, hipEvent_t ev1);
+
 // kernels_control.hip
 // Step configuration and device-side state of one time step.
 struct StepCfg {

@@ -51,7 +51,8 @@ class osm_options(ctypes.Structure):
                 ("team", ctypes.c_int32), ("mem_cap", ctypes.c_uint64),
                 ("eta_q", ctypes.c_double), ("solve_shape", ctypes.c_int32),
                 ("q_estimate", ctypes.c_int32), ("g1_init", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("krylov", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("krylov", ctypes.c_int32),
+                ("strip_order", ctypes.c_int32)]
 
 
 class osm_step_stats(ctypes.Structure):
@@ -72,6 +73,7 @@ class osm_footprint(ctypes.Structure):
 EXPORTS = ["osm_query", "osm_setup", "osm_factor", "osm_factor_rotating", "osm_step",
            "osm_interface_apply", "osm_set_interface_guess", "osm_get_interface",
            "osm_strip_solve", "osm_get_strip_solution", "osm_get_lh_blocks", "osm_get_factor",
+           "osm_get_yfactor", "osm_strip_order",
            "osm_kernel_timing", "osm_kernel_work", "osm_solve_team", "osm_solve_shape",
            "osm_net_nparams", "osm_net_create", "osm_net_set_params", "osm_net_get_params",
            "osm_net_forward", "osm_net_loss_grad", "osm_net_loss_grad_noalloc",
@@ -103,6 +105,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "osm_get_strip_solution": ([H, P], st),
         "osm_get_lh_blocks": ([H, P], st),
         "osm_get_factor": ([H, P], st),
+        "osm_get_yfactor": ([H, P], st),
+        "osm_strip_order": ([H], ctypes.c_int32),
         "osm_solve_team": ([H], ctypes.c_int32),
         "osm_solve_shape": ([H], ctypes.c_int32),
         "osm_kernel_timing": ([H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -181,14 +185,15 @@ def make_options(algo="classical", prec="fp64", tol_k=1e-10, tol_k_relative=Fals
                  max_k=2000, tol_q=1e-13, max_q=100, fixed_k=0, fixed_q=0,
                  warm_start=True, tol_gmres=1e-12, gmres_restart=50, max_gmres=1000,
                  guess=0, team=0, mem_cap=0, eta_q=0.0, solve_shape=0, q_estimate=0,
-                 g1_init=0, seed=0, krylov="gmres"):
+                 g1_init=0, seed=0, krylov="gmres", strip_order="node"):
     return osm_options({"classical": OSM_CLASSICAL, "precond": OSM_PRECOND,
                         "interface": OSM_INTERFACE_KRYLOV}[algo],
                        {"fp64": OSM_FP64, "c32": OSM_C32_REFINE}[prec],
                        tol_k, int(tol_k_relative), max_k, tol_q, max_q, fixed_k, fixed_q,
                        int(warm_start), tol_gmres, gmres_restart, max_gmres, guess, team,
                        mem_cap, eta_q, solve_shape, int(q_estimate), int(g1_init),
-                       int(seed) & 0xFFFFFFFFFFFFFFFF, {"gmres": 0, "bicgstab": 1}[krylov])
+                       int(seed) & 0xFFFFFFFFFFFFFFFF, {"gmres": 0, "bicgstab": 1}[krylov],
+                       {"node": 0, "y": 1, "tuned": 2}[strip_order])
 
 
 def osm_query(pb, **opts):
@@ -274,6 +279,21 @@ class OsmSolver:
         f = torch.empty((self.lt, self.ny, self.ny), dtype=dt, device=self.device)
         self._c(_lib.osm_get_factor(self.h, _ptr(f)))
         return f
+
+    def get_yfactor(self):
+        """The y-line-order factor, one (ny, nx_j, nx_j) tensor per strip."""
+        nx = [int(c) + 1 for c in self.pb.strip_cells]
+        f = torch.empty(sum(self.ny * k * k for k in nx), dtype=torch.complex128,
+                        device=self.device)
+        self._c(_lib.osm_get_yfactor(self.h, _ptr(f)))
+        out, o = [], 0
+        for k in nx:
+            out.append(f[o:o + self.ny * k * k].view(self.ny, k, k))
+            o += self.ny * k * k
+        return out
+
+    def strip_order(self):
+        return "y" if int(_lib.osm_strip_order(self.h)) == 1 else "node"
 
     def solve_team(self):
         return int(_lib.osm_solve_team(self.h))

@@ -165,7 +165,8 @@ def test_interface_krylov_is_accepted_for_the_linear_problem():
 
 
 def test_options_struct_matches_the_header():
-    """The ctypes mirror of osm_options ends with g1_init, seed and krylov, laid out
+    """The ctypes mirror of osm_options ends with g1_init, seed, krylov and
+    strip_order, laid out
     as the C compiler lays out include/osm.h (checked with the C compiler
     of the build)."""
     import ctypes
@@ -181,6 +182,7 @@ def test_options_struct_matches_the_header():
         'int main(void) { printf("%zu %zu %zu %zu %zu\\n", sizeof(osm_options), '
         'offsetof(osm_options, g1_init), offsetof(osm_options, seed), '
         'offsetof(osm_options, krylov), sizeof(osm_problem)); '
+        'printf("%zu\\n", offsetof(osm_options, strip_order)); '
         'printf("%zu %zu\\n", sizeof(osm_step_stats), offsetof(osm_step_stats, guess_ratio)); '
         'return 0; }\n')
     with tempfile.TemporaryDirectory() as d:
@@ -189,7 +191,8 @@ def test_options_struct_matches_the_header():
         open(c, "w").write(src)
         subprocess.run([cc, "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
-    size, off_g1, off_seed, off_kr, psize, ssize, off_gr = map(int, out)
+    size, off_g1, off_seed, off_kr, psize, off_so, ssize, off_gr = map(int, out)
+    assert off_so == osm.osm_options.strip_order.offset
     assert ssize == ctypes.sizeof(osm.osm_step_stats)
     assert off_gr == osm.osm_step_stats.guess_ratio.offset
     assert size == ctypes.sizeof(osm.osm_options)
@@ -197,3 +200,42 @@ def test_options_struct_matches_the_header():
     assert off_seed == osm.osm_options.seed.offset
     assert off_kr == osm.osm_options.krylov.offset
     assert psize == ctypes.sizeof(osm.osm_problem)
+
+
+def test_strip_order_footprint_and_checks():
+    """y-line order keeps ny nx_j^2 FP64 values per strip instead of the
+    node-line order's ny^2 per packed line; the tuned order keeps both where
+    the y-line order is available, and only the node-line factor where it is
+    not (S_pade^m).  The y-line order needs the Robin condition and strips of
+    at most 64 node-lines, and batches use the node-line order."""
+    from paper_1603_05110_amd import osm
+    pb = _pb(ncy=256)
+    dn, _ = osm.osm_query(pb)
+    dy, _ = osm.osm_query(pb, strip_order="y")
+    dt, _ = osm.osm_query(pb, strip_order="tuned")
+    ny, lt = 257, 18
+    node_factor = lt * ny * ny * 16
+    y_factor = 2 * 9 * 9 * ny * 16
+    assert dy < dn - node_factor + y_factor + 64 * 1024
+    assert dt >= dn + y_factor
+    # prec is ignored in y-line order: the factor is FP64 either way
+    assert osm.osm_query(pb, strip_order="y", prec="c32")[0] == dy
+    pade = _pb(ncy=32, tc="pade", pade_m=4, p=0.0, p_bc=0.0)
+    assert osm.osm_query(pade, strip_order="tuned")[0] == osm.osm_query(pade)[0]
+    for bad in [dict(pb=pade), dict(pb=_pb(ncx=200, strip_cells=[100, 100]))]:
+        with pytest.raises(osm.OsmError) as e:
+            osm.osm_query(bad["pb"], strip_order="y")
+        assert e.value.status == osm.OSM_EINVAL
+    # a strip wider than 64 node-lines: the tuned order falls back to node-line
+    wide = _pb(ncx=200, strip_cells=[100, 100])
+    assert osm.osm_query(wide, strip_order="tuned")[0] == osm.osm_query(wide)[0]
+    with pytest.raises(osm.OsmError) as e:
+        osm.osm_query_batch([_pb(), _pb()], strip_order="y")
+    assert e.value.status == osm.OSM_EINVAL
+    import ctypes
+    prob, keep = osm.make_problem(pb)
+    opt = osm.make_options()
+    opt.strip_order = 3
+    fp = osm.osm_footprint()
+    assert osm._lib.osm_query(ctypes.byref(prob), ctypes.byref(opt),
+                              ctypes.byref(fp)) == osm.OSM_EINVAL

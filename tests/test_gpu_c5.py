@@ -60,13 +60,15 @@ def _edge_term(pb, u_old, u_new):
     return tot
 
 
-def test_c5_full_size_step_satisfies_the_discrete_equation():
+@pytest.mark.parametrize("order", ["node", "y"])
+def test_c5_full_size_step_satisfies_the_discrete_equation(order):
     from paper_1603_05110_amd import osm
     wl = c5(steps=1)
     pb, u0 = wl.problems[0], wl.u0[0]
-    log(f"C5 full size: {pb.name}, ny={pb.ncy + 1}, strips={pb.nsub}, c32 precond")
+    log(f"C5 full size: {pb.name}, ny={pb.ncy + 1}, strips={pb.nsub}, c32 precond, "
+        f"{order} order")
     s = osm.OsmSolver(pb, DEV, algo="precond", prec="c32", tol_k=1e-12, tol_k_relative=True,
-                      tol_q=1e-14, max_k=500)
+                      tol_q=1e-14, max_k=500, strip_order=order)
     s.factor_rotating(1)
     ud = torch.from_numpy(np.ascontiguousarray(u0)).to(DEV)
     st = s.step(ud)
@@ -84,3 +86,49 @@ def test_c5_full_size_step_satisfies_the_discrete_equation():
     d_mass = st["mass_after"] - st["mass_before"]
     rhs = -2.0 * pb.lap_coef * pb.p_bc * pb.dt * _edge_term(pb, u0, u1)
     assert abs(d_mass - rhs) < 1e-11 * st["mass_before"]
+
+
+def test_c5_full_size_strip_solves_match_oracle():
+    """Both strip orders at full size (2049 nodes per line, strips of 24 to
+    42 node-lines): the solve of a random right-hand side on the first, a
+    middle, the widest and the last strip against the oracle's sparse LU of
+    that strip (the other strips are solved too, unchecked)."""
+    from oracle.schwarz import SchwarzOracle
+    from paper_1603_05110_amd import osm
+    wl = c5(steps=1)
+    pb = wl.problems[0]
+    W = step_potential(pb, 1)
+    cells = list(pb.strip_cells)
+    wide = int(np.argmax(cells))
+    check = sorted({0, pb.nsub // 2, wide, pb.nsub - 1})
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal((pb.ncx + pb.nsub, pb.ncy + 1)) + 1j * rng.standard_normal(
+        (pb.ncx + pb.nsub, pb.ncy + 1))
+    offs = np.concatenate([[0], np.cumsum([c + 1 for c in cells])])
+    from oracle.fem import StripMatrices
+    import scipy.sparse.linalg as spla
+    want = {}
+    for j in check:
+        st = int(np.sum(cells[:j]))
+        mats = StripMatrices(cells[j], pb.ncy, pb.hx, pb.hy)
+        pl = pb.p_bc if j == 0 else pb.p
+        pr = pb.p_bc if j == pb.nsub - 1 else pb.p
+        K = mats.operator(W[st:st + cells[j] + 1], pb.dt, pb.lap_coef, pl, pr)
+        want[j] = spla.splu(K.tocsc()).solve(b[offs[j]:offs[j + 1]].ravel()).reshape(
+            cells[j] + 1, pb.ncy + 1)
+    for order in ("node", "y"):
+        for prec, tol in (("fp64", 1e-12), ("c32", 2e-6)):
+            if order == "y" and prec == "c32":
+                continue    # the y-line order is FP64 whatever prec says
+            log(f"  C5 strip solve, {order} order, {prec}")
+            s = osm.OsmSolver(pb, DEV, algo="classical", prec=prec, strip_order=order)
+            s.factor(torch.from_numpy(W).to(DEV))
+            x = s.strip_solve(torch.from_numpy(b).to(DEV)).cpu().numpy()
+            s.close()
+            torch.cuda.empty_cache()
+            for j in check:
+                got = x[offs[j]:offs[j + 1]]
+                r = float(np.linalg.norm(got - want[j]) / np.linalg.norm(want[j]))
+                mx = float(np.max(np.abs(got - want[j])) / np.max(np.abs(want[j])))
+                log(f"    strip {j} ({cells[j]} cells): rel {r:.2e} max {mx:.2e}")
+                assert r < tol and mx < tol, (order, prec, j)

@@ -7,9 +7,9 @@
 * GPE 1024^2 cells, 32 strips (the learned-start workload's problem): two
   steps against the monolithic oracle.
 * Rotating GPE 2048^2 cells, 64 uneven strips: three steps of the
-  complex-FP32 path against the FP64 GPU path (the monolithic oracle does
-  not fit a test at 4.2 M nodes; its discrete equation is checked in
-  test_gpu_c5.py).
+  complex-FP32 path and of the y-line-order path against the FP64 GPU path
+  (the monolithic oracle does not fit a test at 4.2 M nodes; its discrete
+  equation and sampled strip solves are checked in test_gpu_c5.py).
 
 Solver settings are the benchmark's: relative Schwarz tolerance 1e-12,
 inexact inner solves with the error-estimate test, GMRES tolerance 3e-2.
@@ -34,10 +34,10 @@ def log(msg):
     sys.stdout.flush()
 
 
-def opts(prec):
+def opts(prec, **kw):
     return dict(algo="precond", prec=prec, tol_k=1e-12, tol_k_relative=True, max_k=500,
                 tol_q=1e-13, max_q=200, warm_start=True, tol_gmres=3e-2, gmres_restart=50,
-                max_gmres=2000, eta_q=3e-2, q_estimate=1)
+                max_gmres=2000, eta_q=3e-2, q_estimate=1, **kw)
 
 
 def rel(a, b):
@@ -123,9 +123,10 @@ def test_rotating_2048_c32_against_fp64():
     wl = c5(steps=3)
     pb, u0 = wl.problems[0], wl.u0[0]
     out = {}
-    for prec in ("c32", "fp64"):
+    for prec in ("c32", "fp64", "y"):
         log(f"rotating 2048^2 / 64 strips, {prec}, 3 steps")
-        s = osm.OsmSolver(pb, DEV, **opts(prec))
+        o = opts("fp64", strip_order="y") if prec == "y" else opts(prec)
+        s = osm.OsmSolver(pb, DEV, **o)
         u = torch.from_numpy(np.ascontiguousarray(u0)).to(DEV)
         for n in range(1, 4):
             s.factor_rotating(n)
@@ -136,3 +137,4 @@ def test_rotating_2048_c32_against_fp64():
         del u
         torch.cuda.empty_cache()
     check_against(out["c32"], out["fp64"], pb, 1e-10, "c32 vs FP64")
+    check_against(out["y"], out["fp64"], pb, 1e-10, "y-line order vs node-line FP64")
