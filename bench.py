@@ -40,6 +40,7 @@ METRIC = "dof-steps/s at 1e-10 rel L2 vs FP64 oracle; Schwarz/GMRES iters per st
 HBM_PEAK_GBS = 8000.0
 MFMA_FP32_PEAK_TFLOPS = 157.3
 MFMA_FP64_PEAK_TFLOPS = 78.6
+FP64_VALU_PEAK_TFLOPS = 78.6     # 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch), each scaled by the counter's reading for a 1 GiB device copy in
@@ -53,7 +54,8 @@ TRAFFIC = {
         "summary": "profiles/sweep_update_c32_rot2048_hbm_counters.md"},
 }
 
-TRAFFIC_SOURCES = {"strip_solve": "kernels_solve.hip", "sweep_update": "kernels_factor.hip"}
+TRAFFIC_SOURCES = {"strip_solve": "kernels_solve.hip", "sweep_update": "kernels_factor.hip",
+                   "ysolve": "kernels_yorder.hip", "yfactor": "kernels_yorder.hip"}
 
 
 def kernel_source_sha256(kernel):
@@ -92,11 +94,11 @@ def solver_opts(prec):
                 gmres_restart=50, max_gmres=2000, eta_q=3e-2, q_estimate=1)
 
 
-def run_gpu(pb, u0, V, prec, steps, warmup, dev, measure=True):
+def run_gpu(pb, u0, V, prec, steps, warmup, dev, measure=True, **extra):
     import torch
     from paper_1603_05110_amd import osm
     t = time.perf_counter()
-    s = osm.OsmSolver(pb, dev, **solver_opts(prec))
+    s = osm.OsmSolver(pb, dev, **solver_opts(prec), **extra)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t
     W = torch.from_numpy(V).to(dev)
@@ -505,45 +507,32 @@ def profile_factor(pb, args, dev):
                       "solve": solve, "copy_bytes": 2 * src.numel() * 8}), flush=True)
 
 
-def run_rotating(args, dev):
-    """Rotating GPE at full size (2048^2 cells, 64 uneven strips), solved in
-    the rotating frame: the step potential changes every step, so every step
-    refactors all 2112 strip lines (osm_factor_rotating) before its Schwarz
-    iterations.  A truncated horizon of --steps steps is timed (the full
-    1000-step horizon is the same work repeated).  Beside it: the plain FP64
-    GPU path over the first --fp64-steps steps (throughput, and the relative
-    L2 difference of the two after those steps), the first step checked
-    against the discrete equation the oracle solves, and the oracle's rate on
-    a bounded sample of the same workload."""
+def rot_leg(pb, u0, opts, steps, warmup, dev, ncmp=0, keep_first=False, label="main"):
+    """One timed run of the rotating workload: setup, first factorisation
+    (with the autotuners), --warmup untimed steps, then `steps` timed steps
+    of factor(W_n) + step, with HIP-event timing of the factor and solve
+    kernels.  Returns the rates, the kernel statistics and the states after
+    step 1 and step ncmp (when asked)."""
     import numpy as np
     import torch
 
     from paper_1603_05110_amd import osm
-    from workloads import c5
-
-    wl = c5(steps=args.steps)
-    pb, u0 = wl.problems[0], wl.u0[0]
     dof = (pb.ncx + 1) * (pb.ncy + 1)
-    if args.profile_factor > 0:
-        profile_factor(pb, args, dev)
-        return
-    print(f"bench: {pb.name} dof={dof} prec={args.prec} steps={args.steps}", file=sys.stderr,
-          flush=True)
-    opts = solver_opts(args.prec)
     t = time.perf_counter()
     s = osm.OsmSolver(pb, dev, **opts)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t
-    print(f"bench: setup (L_h built) {t_setup:.1f}s", file=sys.stderr, flush=True)
     u = torch.from_numpy(u0).to(dev)
     t = time.perf_counter()
     s.factor_rotating(1)
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t
-    print(f"bench: first factor + solve autotune {t_first:.1f}s", file=sys.stderr, flush=True)
-    if args.warmup > 0:
+    order = s.strip_order()
+    print(f"bench[{label}]: setup {t_setup:.1f}s, first factor + autotune {t_first:.1f}s, "
+          f"strip order {order}", file=sys.stderr, flush=True)
+    if warmup > 0:
         uw = u.clone()
-        for n in range(1, args.warmup + 1):
+        for n in range(1, warmup + 1):
             s.factor_rotating(n)
             s.step(uw)
         del uw
@@ -551,20 +540,19 @@ def run_rotating(args, dev):
     s.kernel_timing(True)
     stats, t_fac = [], 0.0
     u_first = u_cmp = None
-    ncmp = min(args.fp64_steps, args.steps) if args.fp64_steps > 0 else 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for n in range(1, args.steps + 1):
+    for n in range(1, steps + 1):
         ta = time.perf_counter()
         s.factor_rotating(n)
         torch.cuda.synchronize()
         t_fac += time.perf_counter() - ta
         stats.append(s.step(u))
-        if n == 1:
+        if n == 1 and keep_first:
             u_first = u.clone()
         if n == ncmp:
             u_cmp = u.clone()
-        print(f"bench: step {n}: k {stats[-1]['k']} gmres {stats[-1]['gmres_total']} "
+        print(f"bench[{label}]: step {n}: k {stats[-1]['k']} gmres {stats[-1]['gmres_total']} "
               f"q {stats[-1]['q_total']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
@@ -575,50 +563,110 @@ def run_rotating(args, dev):
     s.close()
     del u
     torch.cuda.empty_cache()
-    value = dof * args.steps / T
     avg_ms = kern[0] / max(kern[1], 1)
     nbytes = solve_work / max(kern[1], 1)
-    achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    upd_avg_ms = fac_ms / max(fac_n, 1)
-    upd_tflops = fac_fl / (fac_ms * 1e-3) / 1e12 if fac_ms > 0 else 0.0
-    print(f"bench: {T:.2f}s for {args.steps} steps ({t_fac:.2f}s factor), {value:.4g} dof-steps/s",
-          file=sys.stderr, flush=True)
+    out = {"order": order, "value": dof * steps / T, "T": T, "ms_per_step": 1e3 * T / steps,
+           "factor_s_per_step": t_fac / steps, "setup_s": t_setup, "first_s": t_first,
+           "stats": stats,
+           "solve": {"launches": kern[1], "avg_launch_ms": avg_ms, "bytes_per_launch": nbytes,
+                     "ms_per_step": kern[0] / steps,
+                     "achieved_GBs": nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0,
+                     "workgroups_per_strip": team, "tile_shape": shape},
+           "factor": {"launches": fac_n, "avg_launch_ms": fac_ms / max(fac_n, 1),
+                      "ms_per_step": fac_ms / steps, "flops_timed": fac_fl,
+                      "tflops": fac_fl / (fac_ms * 1e-3) / 1e12 if fac_ms > 0 else 0.0},
+           "u_first": u_first, "u_cmp": u_cmp}
+    print(f"bench[{label}]: {T:.2f}s for {steps} steps ({t_fac:.2f}s factor), "
+          f"{out['value']:.4g} dof-steps/s", file=sys.stderr, flush=True)
+    return out
 
-    # the plain FP64 GPU path over the first ncmp steps, from the same u0
+
+def iters_of(stats):
+    import numpy as np
+    return {"k_mean": float(np.mean([x["k"] for x in stats])),
+            "k_max": int(np.max([x["k"] for x in stats])),
+            "q_total": int(sum(x["q_total"] for x in stats)),
+            "gmres_total": int(sum(x["gmres_total"] for x in stats))}
+
+
+def run_rotating(args, dev):
+    """Rotating GPE at full size (2048^2 cells, 64 uneven strips), solved in
+    the rotating frame: the step potential changes every step, so every step
+    refactors every strip (osm_factor_rotating) before its Schwarz
+    iterations.  A truncated horizon of --steps steps is timed (the full
+    1000-step horizon is the same work repeated).  The strip order is the
+    autotuner's choice (--strip-order tuned): the y-line order's factor and
+    solve are FP64.  Beside it: the node-line order (ny x ny blocks, complex
+    FP32 + refinement) over --node-steps steps, the plain FP64 node-line
+    path over the first --fp64-steps steps (with the relative L2 difference
+    of the two), the first step checked against the discrete equation the
+    FP64 oracle solves, and the oracle's rate on a bounded sample of the same
+    workload."""
+    import numpy as np
+    import torch
+
+    from workloads import c5
+
+    wl = c5(steps=args.steps)
+    pb, u0 = wl.problems[0], wl.u0[0]
+    dof = (pb.ncx + 1) * (pb.ncy + 1)
+    if args.profile_factor > 0:
+        profile_factor(pb, args, dev)
+        return
+    print(f"bench: {pb.name} dof={dof} prec={args.prec} steps={args.steps} "
+          f"strip order {args.strip_order}", file=sys.stderr, flush=True)
+    ncmp = min(args.fp64_steps, args.steps) if args.fp64_steps > 0 else 0
+    opts = dict(solver_opts(args.prec), strip_order=args.strip_order,
+                lh_form=args.lh_form)
+    main = rot_leg(pb, u0, opts, args.steps, args.warmup, dev, ncmp=ncmp,
+                   keep_first=not args.no_cpu_baseline)
+    order = main["order"]
+
+    # the node-line order (ny x ny blocks on the matrix cores), the other
+    # choice of the strip order
+    node = None
+    if order != "node" and args.node_steps > 0:
+        nl = rot_leg(pb, u0, dict(solver_opts(args.prec), strip_order="node",
+                                  lh_form=args.lh_form), args.node_steps, 1, dev, label="node")
+        upd_t = nl["factor"]["tflops"]
+        node = {"value": nl["value"], "steps": args.node_steps, "ms_per_step": nl["ms_per_step"],
+                "factor_s_per_step": nl["factor_s_per_step"], "iters": iters_of(nl["stats"]),
+                "prec": args.prec,
+                "sweep_update": {"bound": "mfma", "achieved": upd_t, "unit": "TFLOP/s",
+                                 "peak": MFMA_FP32_PEAK_TFLOPS if args.prec == "c32"
+                                 else MFMA_FP64_PEAK_TFLOPS,
+                                 "avg_launch_ms": nl["factor"]["avg_launch_ms"],
+                                 "launches": nl["factor"]["launches"],
+                                 "traffic": measured_traffic("rot2048", args.prec,
+                                                             "sweep_update")},
+                "solve": dict(nl["solve"], bound="hbm", peak=HBM_PEAK_GBS,
+                              traffic=measured_traffic("rot2048", args.prec, "strip_solve",
+                                                       nl["solve"]["tile_shape"]))}
+
+    # the plain FP64 node-line path over the first ncmp steps, from the same u0
     fp64 = None
-    if ncmp > 0 and args.prec != "fp64":
-        ta = time.perf_counter()
-        s64 = osm.OsmSolver(pb, dev, **solver_opts("fp64"))
-        torch.cuda.synchronize()
-        t_setup64 = time.perf_counter() - ta
-        u64 = torch.from_numpy(u0).to(dev)
-        s64.factor_rotating(1)      # first factor, with the solve autotune
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        k64 = []
-        for n in range(1, ncmp + 1):
-            s64.factor_rotating(n)
-            k64.append(s64.step(u64)["k"])
-        torch.cuda.synchronize()
-        T64 = time.perf_counter() - ta
-        s64.close()
-        diff = float(torch.linalg.vector_norm(u_cmp - u64) / torch.linalg.vector_norm(u64))
-        fp64 = {"value": dof * ncmp / T64, "steps": ncmp, "ms_per_step": 1e3 * T64 / ncmp,
-                "setup_s": t_setup64, "k": k64,
-                "rel_l2_c32_vs_fp64": diff,
-                "note": "same steps from the same u0; factor(W_n) inside the timed steps"}
-        print(f"bench: fp64 {fp64['value']:.4g} dof-steps/s; c32 vs fp64 after {ncmp} steps "
-              f"{diff:.3e}", file=sys.stderr, flush=True)
-        del u64
-    del u_cmp
+    if ncmp > 0 and (args.prec != "fp64" or order != "node"):
+        lg = rot_leg(pb, u0, dict(solver_opts("fp64"), strip_order="node",
+                                  lh_form=args.lh_form), ncmp, 0, dev, ncmp=ncmp, label="fp64")
+        diff = float(torch.linalg.vector_norm(main["u_cmp"] - lg["u_cmp"]) /
+                     torch.linalg.vector_norm(lg["u_cmp"]))
+        fp64 = {"value": lg["value"], "steps": ncmp, "ms_per_step": lg["ms_per_step"],
+                "setup_s": lg["setup_s"], "k": [x["k"] for x in lg["stats"]],
+                "rel_l2_vs_main": diff,
+                "note": "node-line order, FP64 factor and solve; same steps from the same u0; "
+                        "factor(W_n) inside the timed steps"}
+        print(f"bench: fp64 node-line {fp64['value']:.4g} dof-steps/s; main vs fp64 after "
+              f"{ncmp} steps {diff:.3e}", file=sys.stderr, flush=True)
+        del lg
+    main["u_cmp"] = None
     torch.cuda.empty_cache()
 
     check, cpu = None, None
     if not args.no_cpu_baseline:
         from oracle.fem import StripMatrices, weighted_mass_2d
         from oracle.rotating import step_potential
-        u1 = u_first.cpu().numpy()
-        del u_first
+        u1 = main["u_first"].cpu().numpy()
+        main["u_first"] = None
         W1 = step_potential(pb, 1)
         mats = StripMatrices(pb.ncx, pb.ncy, pb.hx, pb.hy)
         K = mats.operator(W1, pb.dt, pb.lap_coef, pb.p_bc, pb.p_bc)
@@ -631,54 +679,82 @@ def run_rotating(args, dev):
         del K, r, v, F, mats
         print(f"bench: step-1 residual {check['rel_residual_discrete_equation']:.3e}",
               file=sys.stderr, flush=True)
-        kps = float(np.mean([x["k"] for x in stats]))
+        kps = float(np.mean([x["k"] for x in main["stats"]]))
         cpu = cpu_sample_rotating(pb, W1, u0, kps)
         print(f"bench: oracle {cpu['value']:.4g} dof-steps/s ({cpu['seconds']:.1f}s sampled)",
               file=sys.stderr, flush=True)
+
+    sv, fc = main["solve"], main["factor"]
+    if order == "y":
+        # the y-line order: FP64 factor (ALU, latency-bound chains) and solve
+        solve_obj = {"kernel": "ysolve (forward, middle, backward)", "bound": "hbm",
+                     "achieved": sv["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": sv["achieved_GBs"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("rot2048", "y", "ysolve"),
+                     "bytes_per_launch": sv["bytes_per_launch"],
+                     "avg_launch_ms": sv["avg_launch_ms"], "launches": sv["launches"],
+                     "ms_per_step": sv["ms_per_step"]}
+        factor_obj = {"kernel": "yfactor (halves, middle)", "bound": "alu",
+                      "achieved": fc["tflops"], "peak": FP64_VALU_PEAK_TFLOPS,
+                      "unit": "TFLOP/s", "frac": fc["tflops"] / FP64_VALU_PEAK_TFLOPS,
+                      "traffic": measured_traffic("rot2048", "y", "yfactor"),
+                      "flops_timed": fc["flops_timed"], "avg_launch_ms": fc["avg_launch_ms"],
+                      "launches": fc["launches"], "ms_per_step": fc["ms_per_step"],
+                      "note": "algorithmic flops: per y-line 8 (n^3 + 6 n^2) for the "
+                              "inversion and the two coupling products"}
+        dominant = solve_obj if sv["ms_per_step"] >= fc["ms_per_step"] else factor_obj
+        other = factor_obj if dominant is solve_obj else solve_obj
+        roofline = dominant
+        dtype = "f64"
+    else:
+        roofline = {"kernel": "sweep_update", "bound": "mfma", "achieved": fc["tflops"],
+                    "peak": MFMA_FP32_PEAK_TFLOPS if args.prec == "c32" else MFMA_FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s",
+                    "frac": fc["tflops"] / (MFMA_FP32_PEAK_TFLOPS if args.prec == "c32"
+                                            else MFMA_FP64_PEAK_TFLOPS),
+                    "traffic": measured_traffic("rot2048", args.prec, "sweep_update"),
+                    "flops_timed": fc["flops_timed"], "avg_launch_ms": fc["avg_launch_ms"],
+                    "launches": fc["launches"],
+                    "note": ("algorithmic flops: 8 real flops per complex multiply-add over "
+                             "the upper 64x64 tiles each pass updates; the kernel issues 6 "
+                             "(three real products)")}
+        other = {"kernel": "strip_solve", "bound": "hbm", "achieved": sv["achieved_GBs"],
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sv["achieved_GBs"] / HBM_PEAK_GBS,
+                 "traffic": measured_traffic("rot2048", args.prec, "strip_solve",
+                                             sv["tile_shape"]),
+                 "bytes_per_launch": sv["bytes_per_launch"], "avg_launch_ms": sv["avg_launch_ms"],
+                 "launches": sv["launches"], "workgroups_per_strip": sv["workgroups_per_strip"],
+                 "tile_shape": sv["tile_shape"]}
+        dtype = "c64+f64-refine" if args.prec == "c32" else "c128"
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": main["value"],
         "unit": "dof-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * T / args.steps,
+        "ms_per_step": main["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64+f64-refine" if args.prec == "c32" else "c128",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": "rotating GPE in the rotating frame, Omega_r=0.7, "
                                "V=-(x^2+1.2y^2)/2, f=-500|u|^2, (-16,16)^2, 2048^2 cells, "
                                "64 uneven strips, p=5, dt=5e-4, vortex Gaussian, preconditioned, "
                                "refactor every step",
                    "dof": dof, "strips": pb.nsub, "algo": "precond", "prec": args.prec,
+                   "strip_order": order, "strip_order_option": args.strip_order,
+                   "lh_form": args.lh_form,
                    "timed": "per step: factor(W_n) + Schwarz/GMRES",
                    "horizon": f"{args.steps} of 1000 steps"},
-        "iters": {"k_mean": float(np.mean([x["k"] for x in stats])),
-                  "k_max": int(np.max([x["k"] for x in stats])),
-                  "q_total": int(sum(x["q_total"] for x in stats)),
-                  "gmres_total": int(sum(x["gmres_total"] for x in stats))},
-        "roofline": {"kernel": "sweep_update", "bound": "mfma", "achieved": upd_tflops,
-                     "peak": MFMA_FP32_PEAK_TFLOPS if args.prec == "c32" else MFMA_FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s",
-                     "frac": upd_tflops / MFMA_FP32_PEAK_TFLOPS if args.prec == "c32"
-                     else upd_tflops / MFMA_FP64_PEAK_TFLOPS,
-                     "traffic": measured_traffic("rot2048", args.prec, "sweep_update"),
-                     "flops_timed": fac_fl,
-                     "avg_launch_ms": upd_avg_ms, "launches": fac_n,
-                     "note": ("algorithmic flops: 8 real flops per complex multiply-add over "
-                              "the upper 64x64 tiles each pass updates; the kernel issues 6 "
-                              "(three real products)")},
-        "solve": {"kernel": "strip_solve", "bound": "hbm", "achieved": achieved,
-                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                  "traffic": measured_traffic("rot2048", args.prec, "strip_solve", shape),
-                  "bytes_per_launch": nbytes, "avg_launch_ms": avg_ms, "launches": kern[1],
-                  "workgroups_per_strip": team, "tile_shape": shape},
-        "factor": {"s_per_step": t_fac / args.steps,
-                   "update_ms_per_step": fac_ms / args.steps},
-        "setup_s": t_setup,
-        "first_factor_and_autotune_s": t_first,
+        "iters": iters_of(main["stats"]),
+        "roofline": roofline,
+        "other_kernel": other,
+        "factor": {"s_per_step": main["factor_s_per_step"]},
+        "setup_s": main["setup_s"],
+        "first_factor_and_autotune_s": main["first_s"],
+        "node_line_order": node,
         "fp64_gpu": fp64,
         "check": check,
         "cpu_baseline": cpu,
@@ -853,6 +929,15 @@ def main():
     ap.add_argument("--profile-solves", type=int, default=5)
     ap.add_argument("--team", type=int, default=0,
                     help="profiler modes: workgroups per strip in the solve (0 = autotune)")
+    ap.add_argument("--strip-order", default="tuned", choices=["node", "y", "tuned"],
+                    help="rot2048: unknown order of the strip factor (tuned: the autotuner "
+                         "times both after the first factorisation)")
+    ap.add_argument("--node-steps", type=int, default=5,
+                    help="rot2048: steps of the node-line order timed beside a y-line main run "
+                         "(0 = skip)")
+    ap.add_argument("--lh-form", default="auto", choices=["auto", "dense", "modal"],
+                    help="L_h as dense blocks per strip class or in the modal form (auto: "
+                         "modal where ny > 1088)")
     ap.add_argument("--solve-shape", type=int, default=0,
                     help="profiler modes: strip-solve tile shape + 1 (0 = autotune)")
     args = ap.parse_args()
@@ -896,7 +981,8 @@ def main():
         profile_solve(pb, V, args.prec, args.profile_solve, dev, args.team, args.solve_shape)
         return
 
-    main_run = run_gpu(pb, u0, V, args.prec, args.steps, args.warmup, dev)
+    main_run = run_gpu(pb, u0, V, args.prec, args.steps, args.warmup, dev,
+                       lh_form=args.lh_form)
     T = main_run["seconds"]
     st = main_run["stats"]
     value = dof * args.steps / T

@@ -195,6 +195,18 @@ typedef struct {
                                      y-line order is not available; both factors
                                      are allocated).  osm_strip_order() tells
                                      which is in use.                             */
+    int32_t lh_form;              /* OSM_PRECOND, how L_h is kept and applied:
+                                     1 = dense ny x ny blocks per strip class,
+                                     built at setup by 2 ny strip solves each
+                                     (the form S_pade^m always uses); 2 = for
+                                     the Robin condition, in the cosine
+                                     eigenbasis of the y-direction (exact for
+                                     W = 0 on the uniform mesh: two dense real
+                                     ny x ny transforms of all traces on the
+                                     matrix cores around a 2 x 2 combination per
+                                     mode); 0 = 2 where the dense blocks' fused
+                                     product kernel does not apply (ny > 1088),
+                                     else 1                                      */
 } osm_options;
 
 typedef struct {
@@ -270,7 +282,8 @@ osm_status osm_get_strip_solution(osm_handle *h, osm_c64 *v_dev);
 
 /* Copy the dense blocks X^{j,1..4} of L_h (Proposition 3.1) of every strip:
  * nsub x 4 x ny x ny complex, row-major blocks; blocks a strip does not have
- * (X^{1,1..3}, X^{N,2..4}) are zero. */
+ * (X^{1,1..3}, X^{N,2..4}) are zero.  In the modal form (osm_options.lh_form)
+ * the blocks are formed from it, O(ny^3) work per block. */
 osm_status osm_get_lh_blocks(osm_handle *h, osm_c64 *blocks_dev);
 
 /* Copy the stored block-Thomas factor: for every line of the packed strip

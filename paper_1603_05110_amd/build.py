@@ -13,7 +13,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libosm.so")
 SOURCES = ["osm.hip", "kernels_assemble.hip", "kernels_factor.hip", "kernels_solve.hip",
            "kernels_control.hip", "kernels_batch.hip", "kernels_net.hip",
-           "kernels_gmres.hip", "kernels_krylov.hip", "kernels_pade.hip", "kernels_yorder.hip"]
+           "kernels_gmres.hip", "kernels_krylov.hip", "kernels_pade.hip", "kernels_yorder.hip",
+           "kernels_lhmodal.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -simplifycfg-sink-common=false: the IR-level sinking of identical

@@ -748,6 +748,10 @@ static hipError_t lh_apply(hipStream_t st, const Phys &P, const StripMeta *strip
                            const LhPlan &pl, const double2 *LH, const double2 *x, double2 *y,
                            int mode_p, const GmresCtl *ctl, const double2 *V = nullptr,
                            long ng = 0, int nv = 0, double2 *part = nullptr, int ld = 0) {
+    if (pl.md.phi) {
+        if (part) return hipErrorInvalidValue;
+        return launch_lh_modal(st, P, strips, pl.md, x, y, mode_p, ctl);
+    }
     int nch = (P.ny + 63) / 64;
     const bool reg = nch <= 17 && pl.blocks > 0 && pl.tab && pl.list &&
                      pl.tiles == (P.ny + 1) / 2;

@@ -59,9 +59,10 @@ __device__ __forceinline__ double2 ysel(bool c, double2 a, double2 b) {
 // Rows i >= n of a thread are computed on clamped data and never published
 // or stored.
 constexpr int YF_THREADS = 256;
-constexpr int YF_COLB = 64;    // pivot column buffer: rows < n <= 64
+constexpr int YF_COLB = 65;    // pivot column buffer: rows < n <= 64, and a slot that
+                               // takes the writes of rows >= n (never read)
 
-// LDS of a factor workgroup: the pivot row (2 x 64) and column (2 x 64) of
+// LDS of a factor workgroup: the pivot row (2 x 64) and column (2 x 65) of
 // the current and the next pivot, A's two diagonals and the coupling block's
 // three (5 n), the previous inverse and then the product H (n^2).
 struct YFactorLds {
@@ -99,6 +100,43 @@ __device__ void yf_coef(const YStrip &S, int ny, int a, int ab, const double2 *D
             yb[n + l] = up;
             yb[2 * n + l] = lo;
         }
+    }
+}
+
+// The coefficients one thread (row l = min(tid, n - 1)) contributes to
+// y-line a's LDS copy: A's diagonal and off-diagonal, and B_ab's diagonal,
+// upper and lower entries.  Loaded unconditionally (ab clamped to 0 when
+// there is no coupling block) so that the next y-line's loads can be in
+// flight while the current one is inverted; put() applies the masks.
+struct YCoef { double2 ad, ao, bd, bu, bl; };
+__device__ __forceinline__ YCoef yf_coef_load(const YStrip &S, int ny, int a, int ab,
+                                              const double2 *Dc, const double2 *Uc) {
+    YCoef q;
+    const int l = min((int)threadIdx.x, S.nx - 1), abc = max(ab, 0);
+    const long r = ((long)(S.off + l) * ny + a) * 3, rb = ((long)(S.off + l) * ny + abc) * 3;
+    q.ad = Dc[r + 1];
+    q.ao = Uc[r + 1];
+    q.bd = Dc[rb + 2];
+    q.bu = Uc[rb + 2];
+    q.bl = Uc[rb + 3];    // Uc(l, ab + 1, 0)
+    return q;
+}
+__device__ __forceinline__ void yf_coef_put(const YCoef &q, const YStrip &S, int ab, double2 *cb,
+                                            double2 *YB) {
+    const int n = S.nx, l = threadIdx.x;
+    if (l >= n) return;
+    const bool in = l + 1 < n;
+    cb[l] = q.ad;
+    cb[n + l] = ysel(in, q.ao, yz());
+    if (ab >= 0) {
+        const double2 up = ysel(in, q.bu, yz()), lo = ysel(in, q.bl, yz());
+        cb[2 * n + l] = q.bd;
+        cb[3 * n + l] = up;
+        cb[4 * n + l] = lo;
+        double2 *yb = YB + S.boff + (long)ab * 3 * n;
+        yb[l] = q.bd;
+        yb[n + l] = up;
+        yb[2 * n + l] = lo;
     }
 }
 
@@ -168,19 +206,20 @@ __device__ __forceinline__ void yf_pivot_block(double2 (&c)[R], const YFactorLds
         const double2 piv = rowp[p];
         const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
         const double2 d = cd(piv.x * inv, -piv.y * inv);   // 1 / C[p][p]
-        const double2 rkd = ymul(rowp[k], d);              // C[p][k] / C[p][p]
-        const double2 nd = yneg(d);
+        // every entry becomes s v - C[i][p] mu and row p becomes mu, with
+        // mu = C[p][k] / C[p][p], s = 1 off column p, and mu = 1 / C[p][p],
+        // s = 0 on it (where C[i][p] is v itself)
         const bool kpiv = k == p;
+        const double2 mu = ysel(kpiv, d, ymul(rowp[k], d));
+        const double sv = kpiv ? 0.0 : 1.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const double2 v = c[r];
             const double2 f = colp[min(rg + ng * r, n - 1)];
-            const double2 upd = cd(v.x - (f.x * rkd.x - f.y * rkd.y),
-                                   v.y - (f.x * rkd.y + f.y * rkd.x));
-            const double2 colv = ymul(v, nd);
-            const double2 rowv = ysel(kpiv, d, rkd);
-            const double2 nv = ysel(kpiv, colv, upd);
-            c[r] = ysel(rg + ng * r == p, rowv, nv);
+            const double2 nv = cd(fma(sv, v.x, fma(f.y, mu.y, -f.x * mu.x)),
+                                  fma(sv, v.y, -fma(f.x, mu.y, f.y * mu.x)));
+            // row p = RB ng + s is slot RB of row group s
+            c[r] = r == RB ? ysel(rg == s, mu, nv) : nv;
         }
         if (p + 1 < n && act) {
             // row p + 1: row group s + 1 (slot RB), or row group 0 (slot
@@ -190,8 +229,10 @@ __device__ __forceinline__ void yf_pivot_block(double2 (&c)[R], const YFactorLds
             if (rg == (wrap ? 0 : s + 1)) L.rowb[64 * nb + k] = ysel(wrap, c[RN], c[RB]);
             if (k == p + 1) {
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    if (rg + ng * r < n) L.colb[YF_COLB * nb + rg + ng * r] = c[r];
+                for (int r = 0; r < R; ++r) {
+                    const int i = rg + ng * r;
+                    L.colb[YF_COLB * nb + (i < n ? i : YF_COLB - 1)] = c[r];
+                }
             }
         }
         __syncthreads();
@@ -250,12 +291,18 @@ __global__ __launch_bounds__(YF_THREADS) void yfactor_half_kernel(const YStrip *
     const bool act = rg < ng;
     double2 c[R];
     const int a0 = half == 0 ? 0 : ny - 1, a1 = m, da = half == 0 ? 1 : -1;
+    // coupling block of y-line a: lower B_{a-1}, upper B_a (none for a0)
+    auto ab_of = [&](int a) { return a == a0 ? -1 : (half == 0 ? a - 1 : a); };
+    YCoef nxt = yf_coef_load(S, ny, a0, -1, Dc, Uc);
     for (int a = a0; a != a1; a += da) {
         const bool first = a == a0;
-        // coupling block: lower B_{a-1}, upper B_a
-        const int ab = first ? -1 : (half == 0 ? a - 1 : a);
+        const int ab = ab_of(a);
         if (!first) yf_store(c, L.gl, n, k, rg, ng, act);   // the previous inverse
-        yf_coef(S, ny, a, ab, Dc, Uc, L.cb, YB);
+        const YCoef cur = nxt;
+        // the next y-line's coefficients (the last one loads its own again)
+        const int an = a + da != a1 ? a + da : a;
+        nxt = yf_coef_load(S, ny, an, ab_of(an), Dc, Uc);
+        yf_coef_put(cur, S, ab, L.cb, YB);
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < R; ++r) c[r] = yf_a(L.cb, n, rg + ng * r, k);

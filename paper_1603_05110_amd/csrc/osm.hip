@@ -88,6 +88,7 @@ struct osm_handle {
     BicgState *bstate = nullptr;   // BiCGStab scalars (osm_options.krylov = 1)
     double *bpart = nullptr;       // BiCGStab dot-product partials
     int gmv_blocks = 0;            // workgroups gmv holds partials for
+    bool lhm = false;              // L_h in the modal form (lhp.md)
     LhClass *lh_tab_d = nullptr;   // work plan of the register-resident L_h kernel
     int *lh_list_d = nullptr;
     LhPlan lhp;
@@ -226,6 +227,7 @@ std::string validate(const osm_problem *p, const osm_options *o) {
     if (o->g1_init < 0 || o->g1_init > 1) return "g1_init must be 0 (zero) or 1 (seeded random)";
     if (o->strip_order < 0 || o->strip_order > 2)
         return "strip_order must be 0 (node-line), 1 (y-line) or 2 (tuned)";
+    if (o->lh_form < 0 || o->lh_form > 2) return "lh_form must be 0 (auto), 1 (dense) or 2 (modal)";
     if (!isfinite(p->beta)) return "beta not finite";
     std::vector<int> c = strip_cells_of(p);
     if ((int)c.size() != p->nsub) return "strip_cells NULL but ncx not divisible by nsub";
@@ -267,6 +269,7 @@ struct Sizes {
     long pm;    // S_pade^m terms (0 for Robin)
     long peb;   // S_pade^m edges per batch of the dense edge blocks
     int lh;     // L_h and its kernels are built (OSM_PRECOND)
+    int lhm;    // ... in the modal form (Robin; lh_form 2, or 0 where ny > 1088)
     int fp32;
     int sym;    // the upper-triangle solve kernels are available (partials buffer)
     int yo;     // factors kept: 0 = node-line order, 1 = y-line order, 2 = both
@@ -306,6 +309,7 @@ Sizes sizes_of(const osm_problem *p, const osm_options *o) {
     s.m = o->algo != OSM_CLASSICAL ? o->gmres_restart : 0;
     s.lh = o->algo == OSM_PRECOND;
     s.pm = p->tc == OSM_TC_PADE ? p->pade_m : 0;
+    s.lhm = s.lh && !s.pm && (o->lh_form == 2 || (o->lh_form == 0 && s.n > 17 * 64));
     // dense edge blocks in batches of at most 256 MB (at least one edge)
     s.peb = s.pm ? std::max(1L, std::min(2 * s.N, (256L << 20) / (s.n * s.n * 16))) : 0;
     s.fp32 = o->prec == OSM_C32_REFINE;
@@ -356,7 +360,11 @@ uint64_t device_bytes(const Sizes &s) {
         b += 2ull * s.peb * s.n * s.n * 16;             // dense edge blocks, scratch
         if (s.lh) b += 2ull * s.n * s.n * 16;           // free edge blocks (L_h)
     }
-    if (s.lh) {
+    if (s.lhm) {
+        b += 2ull * s.n * s.n * 8;                      // Phi, Phi^{-1}
+        b += 4ull * s.ncls * s.n * 16;                  // modal diagonals
+        b += 2ull * s.ng * 16;                          // transformed traces, combination
+    } else if (s.lh) {
         b += 4ull * s.ncls * s.n * s.n * 16;            // L_h blocks
         b += (uint64_t)lh_fused_blocks_bound((int)s.n, (int)s.N, (int)s.ncls) * (s.m + 1) * 16;
         b += (uint64_t)s.ncls * sizeof(LhClass) + (uint64_t)s.N * 4;   // L_h kernel plan
@@ -1069,6 +1077,90 @@ osm_status interface_step(osm_handle *h, const double2 *u, osm_step_stats *S) {
 }
 
 // ---------------------------------------------------------------- L_h build
+// L_h in the cosine eigenbasis of the y-direction (Robin, W = 0): Phi,
+// Phi^{-1} = Phi^T M_y and per strip class the four modal diagonals, from the
+// corner entries of T_mu^{-1}, T_mu = A_x - c lambda_mu M_x (A_x = 2i/dt M_x
+// - c S_x + i c (pl e_0 e_0^T + pr e_n e_n^T); Section 2.2's 1-D Q1 mass and
+// stiffness), by two tridiagonal solves per mode.
+static osm_status build_lh_modal(osm_handle *h, const std::vector<int> &rep) {
+    const int n = h->n, per = 2 * (n - 1);
+    const double hy = h->P.hy, hx = h->P.hx, c = h->prob.lap_coef, dt = h->prob.dt;
+    const double p = h->prob.p;
+    // cos(pi q / (n - 1)), q < 2 (n - 1): the argument mu j pi / (n - 1)
+    // reduced exactly to q = mu j mod 2 (n - 1)
+    std::vector<double> ctab(per), alpha(n), mth(n), lam(n);
+    for (int q = 0; q < per; ++q) ctab[q] = cos(M_PI * q / (n - 1));
+    for (int mu = 0; mu < n; ++mu) {
+        const double cs = ctab[mu], sh = sin(0.5 * M_PI * mu / (n - 1));
+        const double sum = (mu == 0 || mu == n - 1) ? n - 1.0 : 0.5 * (n - 1.0);
+        mth[mu] = hy * (2.0 + cs) / 3.0;             // M_y phi = mth D phi
+        alpha[mu] = 1.0 / sqrt(mth[mu] * sum);      // phi^T M_y phi = 1
+        lam[mu] = 12.0 * sh * sh / (hy * hy * (2.0 + cs));
+    }
+    std::vector<double> phi((size_t)n * n), phinv((size_t)n * n);
+    for (int j = 0; j < n; ++j) {
+        const double dj = (j == 0 || j == n - 1) ? 0.5 : 1.0;
+        for (int mu = 0; mu < n; ++mu) {
+            const double cq = ctab[(size_t)((long)mu * j % per)];
+            phi[(size_t)j * n + mu] = alpha[mu] * cq;
+            phinv[(size_t)mu * n + j] = mth[mu] * dj * alpha[mu] * cq;
+        }
+    }
+    std::vector<double2> dm((size_t)h->ncls * 4 * n);
+    const zc I(0.0, 1.0);
+    for (int cl = 0; cl < h->ncls; ++cl) {
+        const StripMeta &sm = h->strips_h[rep[cl]];
+        const int nx = sm.nx;
+        std::vector<zc> a(nx), cp(nx), z(nx);
+        for (int mu = 0; mu < n; ++mu) {
+            const zc w = 2.0 * I / dt - c * lam[mu];       // coefficient of M_x
+            const zc b = w * (hx / 6.0) + c / hx;          // off-diagonal
+            for (int i = 0; i < nx; ++i)
+                a[i] = (i == 0 || i == nx - 1) ? w * (hx / 3.0) - c / hx : w * (2.0 * hx / 3.0) - 2.0 * c / hx;
+            a[0] += I * c * sm.pl;
+            a[nx - 1] += I * c * sm.pr;
+            // T z = e_s by the Thomas algorithm (no pivoting: Im T is
+            // positive definite); returns (z_0, z_{nx-1})
+            auto solve = [&](int s, zc *z0, zc *zn) {
+                zc m = a[0];
+                cp[0] = b / m;
+                z[0] = (s == 0 ? 1.0 : 0.0) / m;
+                for (int i = 1; i < nx; ++i) {
+                    m = a[i] - b * cp[i - 1];
+                    cp[i] = b / m;
+                    z[i] = ((i == s ? 1.0 : 0.0) - b * z[i - 1]) / m;
+                }
+                for (int i = nx - 2; i >= 0; --i) z[i] -= cp[i] * z[i + 1];
+                *z0 = z[0];
+                *zn = z[nx - 1];
+            };
+            zc t00, tn0, t0n, tnn;
+            solve(0, &t00, &tn0);
+            solve(nx - 1, &t0n, &tnn);
+            const zc f = 2.0 * I * p * c;
+            const zc v[4] = {f * t00 - 1.0, f * t0n, f * tn0, f * tnn - 1.0};
+            for (int bk = 0; bk < 4; ++bk)
+                dm[((size_t)cl * 4 + bk) * n + mu] = cd(v[bk].real(), v[bk].imag());
+        }
+    }
+    double *phi_d, *phinv_d;
+    double2 *dm_d, *xh_d;
+    ALLOC(h, phi_d, double, (long)n * n);
+    ALLOC(h, phinv_d, double, (long)n * n);
+    ALLOC(h, dm_d, double2, (long)h->ncls * 4 * n);
+    ALLOC(h, xh_d, double2, 2L * h->ng);
+    HIPCHK(h, hipMemcpy(phi_d, phi.data(), sizeof(double) * phi.size(), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(phinv_d, phinv.data(), sizeof(double) * phinv.size(),
+                        hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(dm_d, dm.data(), sizeof(double2) * dm.size(), hipMemcpyHostToDevice));
+    h->lhp = LhPlan();
+    h->lhp.md.phi = phi_d;
+    h->lhp.md.phinv = phinv_d;
+    h->lhp.md.dm = dm_d;
+    h->lhp.md.xh = xh_d;
+    return OSM_OK;
+}
+
 osm_status build_lh(osm_handle *h) {
     int n = h->n;
     long nn = (long)n * n;
@@ -1091,6 +1183,7 @@ osm_status build_lh(osm_handle *h) {
     h->ncls = (int)rep.size();
     HIPCHK(h, hipMemcpy(h->strips_d, h->strips_h.data(), sizeof(StripMeta) * h->N,
                         hipMemcpyHostToDevice));
+    if (h->lhm) return build_lh_modal(h, rep);
     // work plan of the register-resident L_h kernel (within the buffers
     // sized at setup; without one the unfused kernels are used)
     h->lhp = LhPlan();
@@ -1263,6 +1356,7 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
     hipGetDevice(&h->device);
     h->n = (int)sz.n; h->N = (int)sz.N; h->Lt = (int)sz.Lt; h->nglob = (int)sz.nglob;
     h->ng = (int)sz.ng; h->maxnx = (int)sz.maxnx; h->fp32 = sz.fp32; h->m = (int)sz.m;
+    h->lhm = sz.lhm != 0;
     Phys &P = h->P;
     P.hx = (prob->xr - prob->xl) / prob->ncx;
     P.hy = (prob->yu - prob->yb) / prob->ncy;
@@ -1487,7 +1581,7 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             SALLOC(h->bstate, BicgState, 1);
             SALLOC(h->bpart, double, bicg_partials());
             // the plan itself is built with the strip classes (build_lh)
-            int nb1 = sz.lh ? lh_fused_blocks_bound(h->n, h->N, (int)sz.ncls) : 0;
+            int nb1 = sz.lh && !sz.lhm ? lh_fused_blocks_bound(h->n, h->N, (int)sz.ncls) : 0;
             if (nb1 > 0) {
                 SALLOC(h->gmv, double2, (long)nb1 * (h->m + 1));
                 SALLOC(h->lh_tab_d, LhClass, sz.ncls);
@@ -1906,6 +2000,11 @@ osm_status osm_get_lh_blocks(osm_handle *h, osm_c64 *blocks_dev) {
         for (int b = 0; b < 4; ++b) {
             bool has = (j >= 1 || b == 3) && (j <= h->N - 2 || b == 0);
             if (!has) continue;
+            if (h->lhm) {
+                HIPCHK(h, launch_lh_modal_dense(h->st, h->n, h->lhp.md, c, b,
+                                                out + (long)(4 * j + b) * nn));
+                continue;
+            }
             HIPCHK(h, hipMemcpyAsync(out + (long)(4 * j + b) * nn, h->LH + (long)(4 * c + b) * nn,
                                      sizeof(double2) * nn, hipMemcpyDeviceToDevice, h->st));
         }

@@ -345,12 +345,30 @@ int gmres_chunks(long n);
 struct LhClass {
     int cls, list_off, count, groups, block_off;
 };
+// L_h in the eigenbasis of the y-direction (kernels_lhmodal.hip): used
+// instead of the dense blocks when phi is set.
+struct LhModal {
+    const double *phi = nullptr;     // n x n, Phi[j][mu]
+    const double *phinv = nullptr;   // n x n, Phi^{-1}[mu][j]
+    const double2 *dm = nullptr;     // ncls x 4 x n: the modal diagonals of X^1 .. X^4
+    double2 *xh = nullptr;           // 2 x 2 (N - 1) x n work vectors (transformed traces,
+                                     // then their per-mode combination)
+};
 struct LhPlan {
     const LhClass *tab = nullptr;   // device, ncls entries
     const int *list = nullptr;      // device, nsub entries
     int ncls = 0, tiles = 0;
     int blocks = 0;                 // 0: the register-resident kernel is not used
+    LhModal md;
 };
+// kernels_lhmodal.hip: y = L_h x, or x - L_h x when mode_p (x, y distinct,
+// interface layout); skipped when ctl says the GMRES cycle is done
+hipError_t launch_lh_modal(hipStream_t st, const Phys &P, const StripMeta *strips,
+                           const LhModal &md, const double2 *x, double2 *y, int mode_p,
+                           const GmresCtl *ctl);
+// the dense n x n block X^{blk} of strip class cls from the modal form
+hipError_t launch_lh_modal_dense(hipStream_t st, int n, const LhModal &md, int cls, int blk,
+                                 double2 *out);
 // Host side of the plan: strip_cls[j] is strip j's class.  Fills tab and
 // list and returns the workgroup count (0 when ny needs more than 17 column
 // chunks).

@@ -52,7 +52,7 @@ class osm_options(ctypes.Structure):
                 ("eta_q", ctypes.c_double), ("solve_shape", ctypes.c_int32),
                 ("q_estimate", ctypes.c_int32), ("g1_init", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("krylov", ctypes.c_int32),
-                ("strip_order", ctypes.c_int32)]
+                ("strip_order", ctypes.c_int32), ("lh_form", ctypes.c_int32)]
 
 
 class osm_step_stats(ctypes.Structure):
@@ -185,7 +185,7 @@ def make_options(algo="classical", prec="fp64", tol_k=1e-10, tol_k_relative=Fals
                  max_k=2000, tol_q=1e-13, max_q=100, fixed_k=0, fixed_q=0,
                  warm_start=True, tol_gmres=1e-12, gmres_restart=50, max_gmres=1000,
                  guess=0, team=0, mem_cap=0, eta_q=0.0, solve_shape=0, q_estimate=0,
-                 g1_init=0, seed=0, krylov="gmres", strip_order="node"):
+                 g1_init=0, seed=0, krylov="gmres", strip_order="node", lh_form="auto"):
     return osm_options({"classical": OSM_CLASSICAL, "precond": OSM_PRECOND,
                         "interface": OSM_INTERFACE_KRYLOV}[algo],
                        {"fp64": OSM_FP64, "c32": OSM_C32_REFINE}[prec],
@@ -193,7 +193,8 @@ def make_options(algo="classical", prec="fp64", tol_k=1e-10, tol_k_relative=Fals
                        int(warm_start), tol_gmres, gmres_restart, max_gmres, guess, team,
                        mem_cap, eta_q, solve_shape, int(q_estimate), int(g1_init),
                        int(seed) & 0xFFFFFFFFFFFFFFFF, {"gmres": 0, "bicgstab": 1}[krylov],
-                       {"node": 0, "y": 1, "tuned": 2}[strip_order])
+                       {"node": 0, "y": 1, "tuned": 2}[strip_order],
+                       {"auto": 0, "dense": 1, "modal": 2}[lh_form])
 
 
 def osm_query(pb, **opts):

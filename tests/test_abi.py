@@ -182,7 +182,7 @@ def test_options_struct_matches_the_header():
         'int main(void) { printf("%zu %zu %zu %zu %zu\\n", sizeof(osm_options), '
         'offsetof(osm_options, g1_init), offsetof(osm_options, seed), '
         'offsetof(osm_options, krylov), sizeof(osm_problem)); '
-        'printf("%zu\\n", offsetof(osm_options, strip_order)); '
+        'printf("%zu %zu\\n", offsetof(osm_options, strip_order), offsetof(osm_options, lh_form)); '
         'printf("%zu %zu\\n", sizeof(osm_step_stats), offsetof(osm_step_stats, guess_ratio)); '
         'return 0; }\n')
     with tempfile.TemporaryDirectory() as d:
@@ -191,8 +191,9 @@ def test_options_struct_matches_the_header():
         open(c, "w").write(src)
         subprocess.run([cc, "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
-    size, off_g1, off_seed, off_kr, psize, off_so, ssize, off_gr = map(int, out)
+    size, off_g1, off_seed, off_kr, psize, off_so, off_ld, ssize, off_gr = map(int, out)
     assert off_so == osm.osm_options.strip_order.offset
+    assert off_ld == osm.osm_options.lh_form.offset
     assert ssize == ctypes.sizeof(osm.osm_step_stats)
     assert off_gr == osm.osm_step_stats.guess_ratio.offset
     assert size == ctypes.sizeof(osm.osm_options)
