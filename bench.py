@@ -469,7 +469,7 @@ def profile_factor(pb, args, dev):
     import torch
     from paper_1603_05110_amd import osm
     opts = dict(solver_opts(args.prec), algo="classical", team=args.team,
-                solve_shape=args.solve_shape)
+                solve_shape=args.solve_shape, strip_order=args.strip_order)
     s = osm.OsmSolver(pb, dev, **opts)
     s.factor_rotating(1)
     torch.cuda.synchronize()
@@ -479,6 +479,7 @@ def profile_factor(pb, args, dev):
     torch.cuda.synchronize()
     s.kernel_timing(False)
     ms, n, fl = s.factor_timing()
+    order = s.strip_order()
     solve = None
     if args.profile_solves > 0:
         gen = torch.Generator(device="cpu").manual_seed(1603)
@@ -494,16 +495,20 @@ def profile_factor(pb, args, dev):
         solve = {"launches": sn, "avg_launch_ms": savg, "bytes_per_launch": nbytes,
                  "achieved_GBs": nbytes / (savg * 1e-3) / 1e9 if savg > 0 else 0.0,
                  "workgroups_per_strip": s.solve_team(), "tile_shape": s.solve_shape(),
-                 "source_sha256": kernel_source_sha256("strip_solve")}
+                 "source_sha256": kernel_source_sha256("ysolve" if order == "y"
+                                                       else "strip_solve")}
     s.close()
     src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "profile-factor", "prec": args.prec, "factors": args.profile_factor,
+                      "strip_order": order,
                       "update_launches": n, "update_avg_ms": ms / max(n, 1),
                       "update_tflops": fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0,
-                      "update_flops": fl, "update_source_sha256": kernel_source_sha256("sweep_update"),
+                      "update_flops": fl,
+                      "update_source_sha256": kernel_source_sha256("yfactor" if order == "y"
+                                                                   else "sweep_update"),
                       "solve": solve, "copy_bytes": 2 * src.numel() * 8}), flush=True)
 
 

@@ -357,128 +357,236 @@ int yf_rows(int max_nx) {
 }
 
 // ---------------------------------------------------------------- solve
-// One workgroup of 8 waves per strip half.  Thread (i = lane, w = wave)
-// holds the entries G[q][i], q = w + 8 r, of the inverse a step multiplies
-// by (G is symmetric, so these are row i's terms, read coalesced); wave 0
-// (i < n) also holds row i's coupling coefficients and right-hand side.
-// The data of the next YS_DEPTH - 1 steps are loaded while the current one
-// computes.
-constexpr int YS_THREADS = 512;
-constexpr int YS_NR = 8;
+// One workgroup of NR waves per strip half, NR = ceil(max nx / 8) (4, 6 or
+// 8, a template parameter).  Wave w owns rows i = 8 w +
+// (lane >> 3) of the strip's y-line vectors; the 8 lanes of a row (slice
+// qs = lane & 7) hold the entries G[q][i], q = qs + 8 r, r < NR, of the inverse a
+// step multiplies by (G is symmetric, so these are row i's terms), and one
+// more value of row i each: qs 1 the coupling block's diagonal, qs 2 its
+// entry towards row i + 1, qs 3 the one towards row i - 1 (for the
+// product with B^T or with B), qs 6 the right-hand side.  A row's sums are
+// formed within its 8 lanes by DPP; rows meet in LDS.  The data of the next
+// YS_DEPTH - 1 steps are loaded while the current one computes.
 constexpr int YS_DEPTH = 4;
 
+template <int NR>
 struct YStage {
-    double2 g[YS_NR];
-    double2 cd, cu, cl;     // B[i][i], B[i][i+1], B[i+1][i] of the step's coupling block
-    double2 rhs;
+    double2 g[NR];
+    double2 ex;     // this lane's coefficient or right-hand-side value
 };
 
-// Loads of one step, all unconditional (a load under a branch would make the
-// compiler wait for every load in flight before using any): G's entries
-// G[q][i] (indices clamped into the block; the clamped q >= n meet v[q] = 0,
-// rows i >= n are never read back), the coupling block's coefficients (yb,
-// y-line-major) and the right-hand side at y-line a (src, packed lines from
-// line off) of row min(i, n - 1).
-__device__ __forceinline__ void ys_load(YStage &s, const double2 *G, const double2 *yb,
+// Sum over the 8 lanes of a row group (quad swaps, then the half-row
+// mirror), in every lane of the group.  Every lane of the wave must be active.
+__device__ __forceinline__ double ys_gsum(double v) {
+    v += dpp_f64<0xB1>(v);     // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);     // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);    // row_half_mirror
+    return v;
+}
+__device__ __forceinline__ double2 ys_gsum2(double2 v) { return cd(ys_gsum(v.x), ys_gsum(v.y)); }
+
+// Buffer resource over one inverse (n^2 complex values): a lane whose
+// offset lies past it reads zeros without a memory request.  The base and
+// size are the same in every lane (scalar registers).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t ys_block(const double2 *G, int nn) {
+    const unsigned long long b = reinterpret_cast<unsigned long long>(G);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    void *p = reinterpret_cast<void *>(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0,
+                                             __builtin_amdgcn_readfirstlane(nn * 16), 0x00020000);
+}
+
+// Loads of one step, all unconditional (a load under a branch would make
+// the compiler wait for every load in flight): G[q][i] through the block's
+// resource, lanes with q >= n or i >= n reading zeros; the lane's extra
+// value from an index clamped into its array (rows i >= n are never
+// stored).  yb: the step's coupling block (y-line-major), tr = 1 for the
+// product with B, 0 for B^T; src: the right-hand side's packed lines.
+template <int NR>
+__device__ __forceinline__ void ys_load(YStage<NR> &s, const double2 *G, const double2 *yb,
                                         const double2 *src, long off, int ny, int a, int n, int i,
-                                        int w) {
-    const int ic = min(i, n - 1);
+                                        int qs, int tr) {
+    const int ic = min(i, n - 1), im = max(ic - 1, 0);
+    const __amdgpu_buffer_rsrc_t rs = ys_block(G, n * n);
 #pragma unroll
-    for (int r = 0; r < YS_NR; ++r) s.g[r] = G[min(w + 8 * r, n - 1) * n + ic];
-    s.cd = yb[ic];
-    s.cu = yb[n + ic];
-    s.cl = yb[2 * n + ic];
-    s.rhs = src[(off + ic) * ny + a];
-}
-
-// Partial product of the step: sum over this thread's q of G[q][i] v[q].
-__device__ __forceinline__ double2 ys_partial(const YStage &s, const double2 *v, int w) {
-    double2 acc = yz();
-#pragma unroll
-    for (int r = 0; r < YS_NR; ++r) acc = yfma(s.g[r], v[w + 8 * r], acc);
-    return acc;
-}
-
-// Sum of the 8 waves' partials of row j (0 outside [0, n)).
-__device__ __forceinline__ double2 ys_row(const double2 *part, int j, int n) {
-    double2 s = yz();
-    if (j < 0 || j >= n) return s;
-#pragma unroll
-    for (int w = 0; w < 8; ++w) {
-        const double2 p = part[w * 64 + j];
-        s.x += p.x;
-        s.y += p.y;
+    for (int r = 0; r < NR; ++r) {
+        const int q = qs + 8 * r;
+        const unsigned bo = (q < n && i < n) ? (unsigned)(q * n + i) * 16u : 0xFFFFFFF0u;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, bo, 0, 0);
+        __builtin_memcpy(&s.g[r], &v, sizeof(double2));
     }
-    return s;
+    // (B t)_i = B[i][i] t_i + B[i][i+1] t_{i+1} + B[i][i-1] t_{i-1} and
+    // (B^T t)_i = B[i][i] t_i + B[i+1][i] t_{i+1} + B[i-1][i] t_{i-1}, with
+    // B[l][l+1] at yb[n + l] and B[l+1][l] at yb[2n + l]
+    const int ci = qs == 2 ? (tr ? n : 2 * n) + ic : (qs == 3 ? (tr ? 2 * n : n) + im : ic);
+    const double2 *p = qs == 6 ? src + (off + ic) * ny + a : yb + ci;
+    s.ex = *p;
 }
 
-__device__ __forceinline__ double2 shfl_up1(double2 v) {
-    return cd(__shfl_up(v.x, 1), __shfl_up(v.y, 1));
+// This lane's product over its q slice: sum_r G[q][i] v[q].
+template <int NR>
+__device__ __forceinline__ double2 ys_partial(const YStage<NR> &s, const double2 *v, int qs) {
+    double2 a0 = yz(), a1 = yz();
+#pragma unroll
+    for (int r = 0; r < NR; r += 2) {
+        a0 = yfma(s.g[r], v[qs + 8 * r], a0);
+        a1 = yfma(s.g[r + 1], v[qs + 8 * (r + 1)], a1);
+    }
+    return cd(a0.x + a1.x, a0.y + a1.y);
 }
 
-// Row i (wave 0, every lane) of the coupling product with t = (t_{i-1},
-// t_i, t_{i+1}):
-// tr = 0: (B^T t)_i = B[i-1][i] t_{i-1} + B[i][i] t_i + B[i+1][i] t_{i+1}
-// tr = 1: (B t)_i   = B[i][i-1] t_{i-1} + B[i][i] t_i + B[i][i+1] t_{i+1}
-// (row i - 1's coefficients from the lane below).
-__device__ __forceinline__ double2 ys_couple(const YStage &s, int i, double2 tm, double2 t0,
-                                            double2 tp, int tr) {
-    const double2 um = shfl_up1(s.cu), lm = shfl_up1(s.cl);
-    double2 acc = ymul(s.cd, t0);
-    acc = yfma(ysel(tr, s.cu, s.cl), tp, acc);
-    if (i > 0) acc = yfma(ysel(tr, lm, um), tm, acc);
-    return acc;
+// rhs - (coupling product)_i from the row's lanes; tl holds the product's
+// input vector at tl[1 + j] (tl[0] = 0 for j = -1).  with_rhs = 0 leaves
+// the right-hand side out.
+template <int NR>
+__device__ __forceinline__ double2 ys_couple(const YStage<NR> &s, const double2 *tl, int i, int qs,
+                                            bool with_rhs) {
+    const int j = qs == 2 ? i + 1 : (qs == 3 ? i - 1 : i);
+    const double2 t = tl[1 + min(j, 63)];
+    const bool c = qs == 1 || qs == 2 || (qs == 3 && i > 0);
+    const double2 m = ymul(ysel(c, s.ex, yz()), t);
+    const double2 own = ysel(qs == 6 && with_rhs, s.ex, yz());
+    return ys_gsum2(cd(own.x - m.x, own.y - m.y));
+}
+
+// L2 prefetch.  A chain's y-lines are read once, in order, from HBM, and
+// only half the CUs run chains, so each chain is bound by the loads one CU
+// keeps in flight.  Every chain therefore has a helper workgroup on the
+// same XCD (workgroups are dealt to the XCDs round-robin, so helper
+// h0 + c of chain c, h0 a multiple of 8, shares its L2) that reads the
+// inverses and coupling coefficients of the chain's next YP_LEAD steps into
+// L2, paced by the chain's progress word: (epoch << 20) + steps done,
+// written by every lane of the chain after each step.  Wave 0 of the helper
+// only paces (a bounded wait of YP_SPINS sleeps; after one that runs out
+// the helper stops pacing for the sweep, which costs cache space, not
+// correctness) and releases the
+// others at a barrier; waves 1..7 only load, into a ring of 4 steps whose
+// values are summed 2 steps later, so neither waits on the other's memory
+// operations.
+constexpr int YP_LEAD = 8;
+constexpr unsigned YP_SPINS = 1u << 14;
+
+// loads per loading thread and step: the (8 NR)^2 entries of an inverse over
+// the 64 (NR - 1) loading threads, and one coupling coefficient
+constexpr int yp_q(int nr) { return (nr * nr + nr - 2) / (nr - 1) + 1; }
+
+template <bool FWD, int NR>
+__device__ void ys_helper(const YStrip &S, int ny, int half, const double2 *YF,
+                          const double2 *YB, unsigned long long *prog, unsigned long long base) {
+    constexpr int YP_Q = yp_q(NR), NL = 64 * (NR - 1);
+    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    const int a0 = FWD ? (half == 0 ? 0 : ny - 1) : (half == 0 ? m - 1 : m + 1);
+    const int da = FWD ? (half == 0 ? 1 : -1) : (half == 0 ? -1 : 1);
+    const int steps = half == 0 ? m : ny - 1 - m;
+    const int wave = threadIdx.x >> 6, lt = (int)threadIdx.x - 64;   // loader index
+    double acc = 0.0;
+    double ring[4][YP_Q];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < YP_Q; ++q) ring[u][q] = 0.0;
+    auto touch = [&](double (&r)[YP_Q], int k) {
+        const int a = a0 + min(k, steps - 1) * da;
+        const int ag = FWD ? (k > 0 ? a - da : a) : a;
+        const int ab = max(FWD ? (half == 0 ? a - 1 : a) : (half == 0 ? a : a - 1), 0);
+        const double2 *G = YF + S.yoff + (long)ag * nn;
+#pragma unroll
+        for (int q = 0; q < YP_Q - 1; ++q) r[q] = G[min(lt + NL * q, nn - 1)].x;
+        r[YP_Q - 1] = YB[S.boff + (long)ab * 3 * n + min(lt, 3 * n - 1)].x;
+    };
+    auto fold = [&](const double (&r)[YP_Q]) {
+#pragma unroll
+        for (int q = 0; q < YP_Q; ++q) acc += r[q];
+    };
+    // the pacer and the loaders pass one barrier per step each
+    if (wave == 0) {
+        bool pace = true;   // off for the rest of the sweep after one timed-out wait
+        for (int k = 0; k < steps; ++k) {
+            if (threadIdx.x == 0 && pace && k >= YP_LEAD) {
+                unsigned spins = 0;
+                while (__hip_atomic_load(prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                       base + (unsigned long long)(k - YP_LEAD)) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++spins >= YP_SPINS) {
+                        pace = false;
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    for (int k0 = 0; k0 < steps; k0 += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u;
+            if (k >= steps) break;
+            touch(ring[u], k);
+            __syncthreads();
+            fold(ring[(u + 2) & 3]);   // the step 2 back, summed after this step's loads
+        }
+    }
+    // keeps the loads: the sum is never this value
+    if (acc == -1.0e300) prog[0] = 0;
 }
 
 // Forward sweeps, blockIdx.x = 2 j + half: lower w_a = b_a - B_{a-1}^T
 // T_{a-1}^{-1} w_{a-1} for a = 0 .. m - 1, upper v_a = b_a - B_a U_{a+1}^{-1}
 // v_{a+1} for a = ny - 1 .. m + 1; w and v are written over x.  Step k
 // (a = a0 + k da) multiplies by the inverse of y-line a - da and coupling
-// block a - 1 (lower) or a (upper).
-__global__ __launch_bounds__(YS_THREADS) void ysolve_fwd_kernel(const YStrip *ys, int ny,
-                                                                const double2 *YF,
-                                                                const double2 *YB,
-                                                                const double2 *b, double2 *x,
-                                                                const StepCtl *c, int *ran) {
+// block a - 1 (lower, B^T) or a (upper, B).
+template <int NR>
+__global__ __launch_bounds__(64 * NR) void ysolve_fwd_kernel(
+    const YStrip *ys, int ny, const double2 *YF, const double2 *YB, const double2 *b, double2 *x,
+    const StepCtl *c, int *ran, int nchain, unsigned long long *prog, unsigned long long epoch) {
     if (yidle(c)) return;
+    const int h0 = (nchain + 7) & ~7;
+    const unsigned long long base = epoch << 20;
+    if ((int)blockIdx.x >= nchain) {
+        const int ch = (int)blockIdx.x - h0;
+        if (ch >= 0 && ch < nchain)
+            ys_helper<true, NR>(ys[ch >> 1], ny, ch & 1, YF, YB, prog + ch, base);
+        return;
+    }
     if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
+    unsigned long long *my = prog + blockIdx.x;
     const int j = blockIdx.x >> 1, half = blockIdx.x & 1;
     const YStrip S = ys[j];
     const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
-    const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __shared__ double2 v[64], part[8 * 64];
+    const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * 8 + (lane >> 3), qs = lane & 7;
+    __shared__ double2 v[64], tl[66];
     const int a0 = half == 0 ? 0 : ny - 1, da = half == 0 ? 1 : -1;
     const int steps = half == 0 ? m : ny - 1 - m;
+    const int tr = half;
     if (threadIdx.x < 64) v[threadIdx.x] = yz();
+    if (threadIdx.x < 66) tl[threadIdx.x] = yz();
     // step k's data; steps past the end reload the last one (unused), step
     // 0 has no product and points G and yb at y-line 0's (unused)
-    auto load = [&](YStage &st, int k) {
+    auto load = [&](YStage<NR> &st, int k) {
         k = min(k, steps - 1);
         const int a = a0 + k * da;
         const int ag = k > 0 ? a - da : 0, ab = k > 0 ? (half == 0 ? a - 1 : a) : 0;
         ys_load(st, YF + S.yoff + (long)ag * nn, YB + S.boff + (long)ab * 3 * n, b, S.off, ny,
-                a, n, i, w);
+                a, n, i, qs, tr);
     };
-    auto step = [&](const YStage &st, int k) {
+    auto step = [&](const YStage<NR> &st, int k) {
         const int a = a0 + k * da;
-        double2 val = st.rhs;
         if (k > 0) {
-            part[w * 64 + i] = ys_partial(st, v, w);
+            const double2 t = ys_gsum2(ys_partial(st, v, qs));
+            if (qs == 0 && i < n) tl[1 + i] = t;
             __syncthreads();
-            if (w == 0) {
-                const double2 s = ys_couple(st, i, ys_row(part, i - 1, n), ys_row(part, i, n),
-                                            ys_row(part, i + 1, n), half);
-                val.x -= s.x;
-                val.y -= s.y;
-            }
         }
-        if (w == 0 && i < n) {
+        const double2 val = ys_couple(st, tl, i, qs, true);
+        if (qs == 0 && i < n) {
             v[i] = val;
             x[(long)(S.off + i) * ny + a] = val;
         }
+        *my = base + (unsigned long long)(k + 1);   // progress, for the helper
         __syncthreads();
     };
-    YStage s0, s1, s2, s3;
+    YStage<NR> s0, s1, s2, s3;
     load(s0, 0);
     load(s1, 1);
     load(s2, 2);
@@ -501,52 +609,56 @@ __global__ __launch_bounds__(YS_THREADS) void ysolve_fwd_kernel(const YStrip *ys
 // Backward sweeps: lower x_a = T_a^{-1}(w_a - B_a x_{a+1}) for a = m - 1
 // down to 0, upper x_a = U_a^{-1}(v_a - B_{a-1}^T x_{a-1}) for a = m + 1 up.
 // Step k (a = a0 + k da) multiplies by the inverse of y-line a, coupling
-// block a (lower) or a - 1 (upper), and reads w_a / v_a from x.
-__global__ __launch_bounds__(YS_THREADS) void ysolve_bwd_kernel(const YStrip *ys, int ny,
-                                                                const double2 *YF,
-                                                                const double2 *YB, double2 *x,
-                                                                const StepCtl *c) {
+// block a (lower, B) or a - 1 (upper, B^T), and reads w_a / v_a from x.
+template <int NR>
+__global__ __launch_bounds__(64 * NR) void ysolve_bwd_kernel(
+    const YStrip *ys, int ny, const double2 *YF, const double2 *YB, double2 *x, const StepCtl *c,
+    int nchain, unsigned long long *prog, unsigned long long epoch) {
     if (yidle(c)) return;
+    const int h0 = (nchain + 7) & ~7;
+    const unsigned long long base = epoch << 20;
+    if ((int)blockIdx.x >= nchain) {
+        const int ch = (int)blockIdx.x - h0;
+        if (ch >= 0 && ch < nchain)
+            ys_helper<false, NR>(ys[ch >> 1], ny, ch & 1, YF, YB, prog + ch, base);
+        return;
+    }
+    unsigned long long *my = prog + blockIdx.x;
     const int j = blockIdx.x >> 1, half = blockIdx.x & 1;
     const YStrip S = ys[j];
     const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
-    const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __shared__ double2 v[64], part[8 * 64];
+    const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * 8 + (lane >> 3), qs = lane & 7;
+    __shared__ double2 v[64], tl[66];
     const int a0 = half == 0 ? m - 1 : m + 1, da = half == 0 ? -1 : 1;
     const int steps = half == 0 ? m : ny - 1 - m;
+    const int tr = half == 0 ? 1 : 0;
     if (threadIdx.x < 64) v[threadIdx.x] = yz();
-    // x_m, the start of both sweeps (rows i - 1, i, i + 1 in wave 0)
-    double2 tm = yz(), t0 = yz(), tp = yz();
-    if (w == 0) {
-        const double2 *xm = x + (long)S.off * ny + m;
-        if (i > 0 && i - 1 < n) tm = xm[(long)(i - 1) * ny];
-        if (i < n) t0 = xm[(long)i * ny];
-        if (i + 1 < n) tp = xm[(long)(i + 1) * ny];
-    }
-    auto load = [&](YStage &st, int k) {
+    if (threadIdx.x < 66) tl[threadIdx.x] = yz();
+    __syncthreads();
+    // x_m, the start of both sweeps
+    if (qs == 0 && i < n) tl[1 + i] = x[(long)(S.off + i) * ny + m];
+    __syncthreads();
+    auto load = [&](YStage<NR> &st, int k) {
         k = min(k, steps - 1);   // past the end: the last step's data again (unused)
         const int a = a0 + k * da;
         const int ab = half == 0 ? a : a - 1;
         ys_load(st, YF + S.yoff + (long)a * nn, YB + S.boff + (long)ab * 3 * n, x, S.off, ny, a,
-                n, i, w);
+                n, i, qs, tr);
     };
-    auto step = [&](const YStage &st, int k) {
+    auto step = [&](const YStage<NR> &st, int k) {
         const int a = a0 + k * da;
-        if (w == 0) {
-            const double2 s = ys_couple(st, i, tm, t0, tp, half == 0 ? 1 : 0);
-            if (i < n) v[i] = cd(st.rhs.x - s.x, st.rhs.y - s.y);
-        }
+        const double2 r = ys_couple(st, tl, i, qs, true);
+        if (qs == 0 && i < n) v[i] = r;
         __syncthreads();
-        part[w * 64 + i] = ys_partial(st, v, w);
-        __syncthreads();
-        if (w == 0) {
-            tm = ys_row(part, i - 1, n);
-            t0 = ys_row(part, i, n);
-            tp = ys_row(part, i + 1, n);
-            if (i < n) x[(long)(S.off + i) * ny + a] = t0;
+        const double2 t = ys_gsum2(ys_partial(st, v, qs));
+        if (qs == 0 && i < n) {
+            tl[1 + i] = t;
+            x[(long)(S.off + i) * ny + a] = t;
         }
+        *my = base + (unsigned long long)(k + 1);   // progress, for the helper
+        __syncthreads();
     };
-    YStage s0, s1, s2, s3;
+    YStage<NR> s0, s1, s2, s3;
     load(s0, 0);
     load(s1, 1);
     load(s2, 2);
@@ -568,7 +680,8 @@ __global__ __launch_bounds__(YS_THREADS) void ysolve_bwd_kernel(const YStrip *ys
 // Middle line: x_m = M_m^{-1}(b_m - B_{m-1}^T T_{m-1}^{-1} w_{m-1} - B_m
 // U_{m+1}^{-1} v_{m+1}), the terms present; three products of one step
 // each, all their data loaded up front.
-__global__ __launch_bounds__(YS_THREADS) void ysolve_mid_kernel(const YStrip *ys, int ny,
+template <int NR>
+__global__ __launch_bounds__(64 * NR) void ysolve_mid_kernel(const YStrip *ys, int ny,
                                                                 const double2 *YF,
                                                                 const double2 *YB,
                                                                 const double2 *b, double2 *x,
@@ -576,42 +689,44 @@ __global__ __launch_bounds__(YS_THREADS) void ysolve_mid_kernel(const YStrip *ys
     if (yidle(c)) return;
     const YStrip S = ys[blockIdx.x];
     const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
-    const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __shared__ double2 v[64], part[8 * 64];
+    const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * 8 + (lane >> 3), qs = lane & 7;
+    __shared__ double2 v[64], tl[66];
     if (threadIdx.x < 64) v[threadIdx.x] = yz();   // entries q >= n meet clamped G values
+    if (threadIdx.x < 66) tl[threadIdx.x] = yz();
     const bool lo = m - 1 >= 0, hi = m + 1 < ny;
-    YStage sl, sh, sm;
-    // lower side: inverse of m - 1, coupling block m - 1, w_{m-1} from x;
-    // upper side: inverse of m + 1, coupling block m, v_{m+1} from x (a
-    // missing side points at y-line m's data, unused); the middle product
-    // has no coupling block (coefficients of block 0 loaded, unused)
+    YStage<NR> sl, sh, sm;
+    // lower side: inverse of m - 1, coupling block m - 1 (B^T), w_{m-1} from
+    // x; upper side: inverse of m + 1, coupling block m (B), v_{m+1} from x
+    // (a missing side points at y-line m's data, unused); the middle
+    // product: inverse of m, b_m (coupling entries of block 0, unused)
     const int al = lo ? m - 1 : m, ah = hi ? m + 1 : m, bl = lo ? m - 1 : 0, bh = hi ? m : 0;
     ys_load(sl, YF + S.yoff + (long)al * nn, YB + S.boff + (long)bl * 3 * n, x, S.off, ny, al,
-            n, i, w);
+            n, i, qs, 0);
     ys_load(sh, YF + S.yoff + (long)ah * nn, YB + S.boff + (long)bh * 3 * n, x, S.off, ny, ah,
-            n, i, w);
-    ys_load(sm, YF + S.yoff + (long)m * nn, YB + S.boff, b, S.off, ny, m, n, i, w);
-    double2 r = sm.rhs;
-    auto side = [&](const YStage &st, int tr) {
-        if (w == 0 && i < n) v[i] = st.rhs;
+            n, i, qs, 1);
+    ys_load(sm, YF + S.yoff + (long)m * nn, YB + S.boff, b, S.off, ny, m, n, i, qs, 0);
+    __syncthreads();
+    double2 acc = yz();
+    auto side = [&](const YStage<NR> &st) {
+        // the side's vector (the right-hand-side slot of its stage) into v
+        if (qs == 6 && i < n) v[i] = st.ex;
         __syncthreads();
-        part[w * 64 + i] = ys_partial(st, v, w);
+        const double2 t = ys_gsum2(ys_partial(st, v, qs));
+        if (qs == 0 && i < n) tl[1 + i] = t;
         __syncthreads();
-        if (w == 0) {
-            const double2 s = ys_couple(st, i, ys_row(part, i - 1, n), ys_row(part, i, n),
-                                        ys_row(part, i + 1, n), tr);
-            r.x -= s.x;
-            r.y -= s.y;
-        }
+        const double2 cpl = ys_couple(st, tl, i, qs, false);   // -(coupling product)_i
+        acc.x += cpl.x;
+        acc.y += cpl.y;
         __syncthreads();
     };
-    if (lo) side(sl, 0);
-    if (hi) side(sh, 1);
-    if (w == 0 && i < n) v[i] = r;
+    if (lo) side(sl);
+    if (hi) side(sh);
+    // b_m from the middle stage's right-hand-side lane, to the whole row
+    const double2 rb = ys_gsum2(ysel(qs == 6, sm.ex, yz()));
+    if (qs == 0 && i < n) v[i] = cd(rb.x + acc.x, rb.y + acc.y);
     __syncthreads();
-    part[w * 64 + i] = ys_partial(sm, v, w);
-    __syncthreads();
-    if (w == 0 && i < n) x[(long)(S.off + i) * ny + m] = ys_row(part, i, n);
+    const double2 t = ys_gsum2(ys_partial(sm, v, qs));
+    if (qs == 0 && i < n) x[(long)(S.off + i) * ny + m] = t;
 }
 
 }  // namespace
@@ -649,17 +764,30 @@ hipError_t launch_yfactor(hipStream_t st, const YStrip *ys, int nstrips, int ny,
     return e;
 }
 
-hipError_t launch_ysolve(hipStream_t st, const YStrip *ys, int nstrips, int ny, const double2 *YF,
-                         const double2 *YB, const double2 *b, double2 *x, const StepCtl *c,
-                         int *ran, hipEvent_t ev0, hipEvent_t ev1) {
+hipError_t launch_ysolve(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
+                         const double2 *YF, const double2 *YB, const double2 *b, double2 *x,
+                         const StepCtl *c, int *ran, unsigned long long *prog,
+                         unsigned long long *epoch, hipEvent_t ev0, hipEvent_t ev1) {
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(ysolve_fwd_kernel, dim3(2 * nstrips), dim3(YS_THREADS), 0, st, ys, ny, YF,
-                       YB, b, x, c, ran);
-    hipLaunchKernelGGL(ysolve_mid_kernel, dim3(nstrips), dim3(YS_THREADS), 0, st, ys, ny, YF, YB,
-                       b, x, c);
-    hipLaunchKernelGGL(ysolve_bwd_kernel, dim3(2 * nstrips), dim3(YS_THREADS), 0, st, ys, ny, YF,
-                       YB, x, c);
+    // chains 0 .. 2N-1, then (from the next multiple of 8) their helpers
+    const int nchain = 2 * nstrips, grid = ((nchain + 7) & ~7) + nchain;
+    const unsigned long long ef = ++*epoch, eb = ++*epoch;
+    auto go = [&](auto fwd, auto mid, auto bwd, int nr) {
+        hipLaunchKernelGGL(fwd, dim3(grid), dim3(64 * nr), 0, st, ys, ny, YF, YB, b, x, c, ran,
+                           nchain, prog, ef);
+        hipLaunchKernelGGL(mid, dim3(nstrips), dim3(64 * nr), 0, st, ys, ny, YF, YB, b, x, c);
+        hipLaunchKernelGGL(bwd, dim3(grid), dim3(64 * nr), 0, st, ys, ny, YF, YB, x, c, nchain,
+                           prog, eb);
+    };
+    if (max_nx <= 32)
+        go(ysolve_fwd_kernel<4>, ysolve_mid_kernel<4>, ysolve_bwd_kernel<4>, 4);
+    else if (max_nx <= 48)
+        go(ysolve_fwd_kernel<6>, ysolve_mid_kernel<6>, ysolve_bwd_kernel<6>, 6);
+    else if (max_nx <= 64)
+        go(ysolve_fwd_kernel<8>, ysolve_mid_kernel<8>, ysolve_bwd_kernel<8>, 8);
+    else
+        return hipErrorInvalidValue;
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev1) e = hipEventRecord(ev1, st);
     return e;

@@ -51,6 +51,8 @@ struct osm_handle {
     bool order_tuned = true;         // false until the autotuner has chosen
     double2 *YF = nullptr, *YB = nullptr;
     YStrip *ys_d = nullptr;
+    unsigned long long *yprog = nullptr;   // progress words of the solve's chains
+    unsigned long long yepoch = 0;
     double order_ms[2] = {0.0, 0.0}; // autotuner: one solve in each order (ms)
     // strip vectors
     double2 *zeta = nullptr, *res = nullptr, *delta = nullptr;
@@ -335,7 +337,7 @@ uint64_t device_bytes(const Sizes &s) {
     uint64_t fe = s.fp32 ? 8 : 16;
     uint64_t b = 0;
     if (s.yo != 1) b += (uint64_t)s.Lt * s.n * s.n * fe;                     // factor
-    if (s.yo) b += (uint64_t)(s.ysum + s.ybsum) * 16 + (uint64_t)s.N * sizeof(YStrip);  // y-line factor
+    if (s.yo) b += (uint64_t)(s.ysum + s.ybsum) * 16 + (uint64_t)s.N * (sizeof(YStrip) + 16);  // y-line factor
     b += 2ull * s.Lt * s.n * 3 * 16;                    // Dc, Uc
     b += (uint64_t)s.nglob * s.n * 8;                   // W
     b += 3ull * s.Lt * s.n * 16;                        // zeta, res, delta
@@ -566,8 +568,8 @@ osm_status do_solve(osm_handle *h, const double2 *b, double2 *x, const StepCtl *
             osm_status s = solve_slot(h, &e0, &e1, &ran);
             if (s != OSM_OK) return s;
         }
-        HIPCHK(h, launch_ysolve(h->st, h->ys_d, h->N, h->n, h->YF, h->YB, b, x, ctl, ran, e0,
-                                e1));
+        HIPCHK(h, launch_ysolve(h->st, h->ys_d, h->N, h->n, h->maxnx, h->YF, h->YB, b, x, ctl,
+                                ran, h->yprog, &h->yepoch, e0, e1));
         return OSM_OK;
     }
     SolveArgs a;
@@ -1475,6 +1477,8 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
             }
             SALLOC(h->YF, double2, yo);
             SALLOC(h->YB, double2, bo);
+            SALLOC(h->yprog, unsigned long long, 2 * h->N);
+            HIPCHK(h, hipMemset(h->yprog, 0, sizeof(unsigned long long) * 2 * h->N));
             SALLOC(h->ys_d, YStrip, h->N);
             HIPCHK(h, hipMemcpy(h->ys_d, ys.data(), sizeof(YStrip) * h->N, hipMemcpyHostToDevice));
             h->order = sz.yo == 1 ? 1 : 0;

@@ -245,10 +245,14 @@ hipError_t launch_yfactor(hipStream_t st, const YStrip *ys, int nstrips, int ny,
                           const double2 *Dc, const double2 *Uc, double2 *YF, double2 *YB,
                           hipEvent_t ev0, hipEvent_t ev1);
 // x = K^{-1} b on every strip; skipped when c says the fixed point is done
-// (ran, when given, set to 1 otherwise); ev0/ev1 bracket the three kernels
-hipError_t launch_ysolve(hipStream_t st, const YStrip *ys, int nstrips, int ny, const double2 *YF,
-                         const double2 *YB, const double2 *b, double2 *x, const StepCtl *c,
-                         int *ran, hipEvent_t ev0, hipEvent_t ev1);
+// (ran, when given, set to 1 otherwise); ev0/ev1 bracket the three kernels.
+// prog: 2 nstrips progress words (zeroed once; the sweeps' L2 prefetch
+// helpers poll them), epoch: the host's launch counter for them (advanced
+// by two per call, below 2^44)
+hipError_t launch_ysolve(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
+                         const double2 *YF, const double2 *YB, const double2 *b, double2 *x,
+                         const StepCtl *c, int *ran, unsigned long long *prog,
+                         unsigned long long *epoch, hipEvent_t ev0, hipEvent_t ev1);
 
 // kernels_control.hip
 // Step configuration and device-side state of one time step.
