@@ -53,61 +53,45 @@ __device__ __forceinline__ double2 ysel(bool c, double2 a, double2 b) {
 }
 
 // ---------------------------------------------------------------- factor
-// A workgroup of 256 threads per strip half: thread (k = tid mod n, rg = tid
-// div n) owns column k of rows rg + ng r, r < R (ng = 256 div n row groups;
-// R >= ceil(n / ng), a template parameter); threads with rg >= ng idle.
-// Rows i >= n of a thread are computed on clamped data and never published
-// or stored.
+// A workgroup of 256 threads per strip half works on the complement padded
+// with the identity to NP = 16 T >= nx (T = 2, 3 or 4, a template
+// parameter).  Thread (tr, tc) = (tid >> 4, tid & 15) owns the entries
+// (tr + 16 a, tc + 16 c), a, c < T, in registers.  The padding keeps the
+// identity through the coupling products (its coefficients are zero) and
+// through the inversion (it is decoupled).
 constexpr int YF_THREADS = 256;
-constexpr int YF_COLB = 65;    // pivot column buffer: rows < n <= 64, and a slot that
-                               // takes the writes of rows >= n (never read)
 
-// LDS of a factor workgroup: the pivot row (2 x 64) and column (2 x 65) of
-// the current and the next pivot, A's two diagonals and the coupling block's
-// three (5 n), the previous inverse and then the product H (n^2).
-struct YFactorLds {
-    double2 *cb, *gl, *rowb, *colb;
+template <int T>
+struct YFLds {
+    static constexpr int NP = 16 * T;
+    double2 *cb;      // 5 NP: A's diagonal and off-diagonal, B's diagonal, upper, lower
+                      // (zero past n)
+    double2 *gl;      // NP x NP: the previous inverse, then the product H
+    double2 *rowsP;   // 2 x 8 x NP: the block step's pivot rows (by step parity)
+    double2 *colsP;   // 2 x NP x 8: its pivot columns
+    double2 *zs;      // 2 x 8 x NP: Z = D C_PR, and D on the pivot columns
+    double2 *ds;      // 4 x 64: each wave's copy of D
 };
-__device__ __forceinline__ YFactorLds yf_lds(double2 *base, int n) {
-    YFactorLds L;
-    L.rowb = base;                                // 2 x 64
-    L.colb = base + 128;                          // 2 x YF_COLB
-    L.cb = base + 128 + 2 * YF_COLB;              // 5 n
-    L.gl = base + 128 + 2 * YF_COLB + 5 * n;      // n^2
+template <int T>
+__device__ __forceinline__ YFLds<T> yf_lds(double2 *base) {
+    constexpr int NP = 16 * T;
+    YFLds<T> L;
+    L.cb = base;
+    L.gl = L.cb + 5 * NP;
+    L.rowsP = L.gl + NP * NP;
+    L.colsP = L.rowsP + 16 * NP;
+    L.zs = L.colsP + 16 * NP;
+    L.ds = L.zs + 16 * NP;
     return L;
 }
-
-// Coefficients of y-line a: A's diagonal and off-diagonal (cb[0, 2n)) and,
-// when ab >= 0, the coupling block B_ab's diagonal, upper and lower entries
-// (cb[2n, 5n)), also written y-line-major to YB for the solve.
-__device__ void yf_coef(const YStrip &S, int ny, int a, int ab, const double2 *Dc,
-                        const double2 *Uc, double2 *cb, double2 *YB) {
-    const int n = S.nx;
-    for (int l = threadIdx.x; l < n; l += blockDim.x) {
-        const long r = ((long)(S.off + l) * ny + a) * 3;
-        cb[l] = Dc[r + 1];
-        cb[n + l] = l + 1 < n ? Uc[r + 1] : yz();
-        if (ab >= 0) {
-            const long rb = ((long)(S.off + l) * ny + ab) * 3;
-            const double2 d = Dc[rb + 2];
-            const double2 up = l + 1 < n ? Uc[rb + 2] : yz();
-            const double2 lo = l + 1 < n ? Uc[((long)(S.off + l) * ny + ab + 1) * 3 + 0] : yz();
-            cb[2 * n + l] = d;
-            cb[3 * n + l] = up;
-            cb[4 * n + l] = lo;
-            double2 *yb = YB + S.boff + (long)ab * 3 * n;
-            yb[l] = d;
-            yb[n + l] = up;
-            yb[2 * n + l] = lo;
-        }
-    }
-}
+__host__ __device__ constexpr int yf_lds_count(int np) { return np * np + 53 * np + 256; }
 
 // The coefficients one thread (row l = min(tid, n - 1)) contributes to
 // y-line a's LDS copy: A's diagonal and off-diagonal, and B_ab's diagonal,
 // upper and lower entries.  Loaded unconditionally (ab clamped to 0 when
 // there is no coupling block) so that the next y-line's loads can be in
-// flight while the current one is inverted; put() applies the masks.
+// flight while the current one is inverted; put() applies the masks and
+// also writes B_ab y-line-major to YB for the solve.
 struct YCoef { double2 ad, ao, bd, bu, bl; };
 __device__ __forceinline__ YCoef yf_coef_load(const YStrip &S, int ny, int a, int ab,
                                               const double2 *Dc, const double2 *Uc) {
@@ -121,18 +105,18 @@ __device__ __forceinline__ YCoef yf_coef_load(const YStrip &S, int ny, int a, in
     q.bl = Uc[rb + 3];    // Uc(l, ab + 1, 0)
     return q;
 }
-__device__ __forceinline__ void yf_coef_put(const YCoef &q, const YStrip &S, int ab, double2 *cb,
-                                            double2 *YB) {
+__device__ __forceinline__ void yf_coef_put(const YCoef &q, const YStrip &S, int ab, int np,
+                                            double2 *cb, double2 *YB) {
     const int n = S.nx, l = threadIdx.x;
     if (l >= n) return;
     const bool in = l + 1 < n;
     cb[l] = q.ad;
-    cb[n + l] = ysel(in, q.ao, yz());
+    cb[np + l] = ysel(in, q.ao, yz());
     if (ab >= 0) {
         const double2 up = ysel(in, q.bu, yz()), lo = ysel(in, q.bl, yz());
-        cb[2 * n + l] = q.bd;
-        cb[3 * n + l] = up;
-        cb[4 * n + l] = lo;
+        cb[2 * np + l] = q.bd;
+        cb[3 * np + l] = up;
+        cb[4 * np + l] = lo;
         double2 *yb = YB + S.boff + (long)ab * 3 * n;
         yb[l] = q.bd;
         yb[n + l] = up;
@@ -144,217 +128,303 @@ __device__ __forceinline__ void yf_coef_put(const YCoef &q, const YStrip &S, int
 // neighbours j - 1, j, j + 1: lower (tr = 0) B[j-1][j], B[j][j], B[j+1][j];
 // upper (tr = 1) B[j][j-1], B[j][j], B[j][j+1]; zero outside [0, n).
 struct Tri { double2 m1, z0, p1; };
-__device__ __forceinline__ Tri yf_tri(const double2 *cb, int n, int j, int tr) {
+__device__ __forceinline__ Tri yf_tri(const double2 *cb, int np, int j, int tr) {
     Tri t;
-    const double2 *up = cb + 3 * n, *lo = cb + 4 * n;
-    const int jm = max(j - 1, 0);
-    t.z0 = cb[2 * n + j];
+    const double2 *up = cb + 3 * np, *lo = cb + 4 * np;
+    const int jm = max(j - 1, 0), jp = min(j, np - 1);
+    t.z0 = cb[2 * np + j];
     t.m1 = ysel(j > 0, ysel(tr, lo[jm], up[jm]), yz());
-    t.p1 = ysel(j + 1 < n, ysel(tr, up[j], lo[j]), yz());
+    t.p1 = ysel(j + 1 < np, ysel(tr, up[jp], lo[jp]), yz());
     return t;
 }
 
-// c[r] -= (X G Y)[i_r][k] with G in L.gl (n x n): lower C -= B^T G B, upper
-// C -= B G B^T, as H = G Y (3 terms) then X H (3 terms); reads clamped into
-// the block (their coefficient is zero where clamping changed the index).
-// Ends with L.gl free.
-template <int R>
-__device__ __forceinline__ void yf_sandwich(double2 (&c)[R], const YFactorLds &L, int n, int k, int rg, int ng,
-                            bool act, int tr) {
-    double2 h[R];
-    const Tri tk = yf_tri(L.cb, n, k, tr);
-    const int km = max(k - 1, 0), kp = min(k + 1, n - 1);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const double2 *gi = L.gl + min(rg + ng * r, n - 1) * n;
-        h[r] = yfma(gi[kp], tk.p1, yfma(gi[km], tk.m1, ymul(gi[k], tk.z0)));
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = rg + ng * r;
-        if (act && i < n) L.gl[i * n + k] = h[r];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = min(rg + ng * r, n - 1);
-        const Tri ti = yf_tri(L.cb, n, i, tr);
-        const double2 s = yfma(ti.p1, L.gl[min(i + 1, n - 1) * n + k],
-                               yfma(ti.m1, L.gl[max(i - 1, 0) * n + k],
-                                    ymul(ti.z0, L.gl[i * n + k])));
-        c[r].x -= s.x;
-        c[r].y -= s.y;
-    }
-    __syncthreads();
-}
-
-// In-place Gauss-Jordan inversion of the complement held in registers,
-// without pivoting.  Pivot p reads row p and column p of the current matrix
-// from LDS (buffer p & 1) and publishes row and column p + 1 after its
-// update into the other buffer: one barrier per pivot.  The pivots run in
-// blocks RB of ng (a compile-time block index, so that the register holding
-// row p + 1, row group (p + 1) mod ng, slot (p + 1) div ng, is static).
-template <int R, int RB>
-__device__ __forceinline__ void yf_pivot_block(double2 (&c)[R], const YFactorLds &L, int n,
-                                               int k, int rg, int ng, bool act) {
-    for (int s = 0; s < ng; ++s) {
-        const int p = RB * ng + s;
-        if (p >= n) return;
-        const int b = p & 1, nb = b ^ 1;
-        const double2 *rowp = L.rowb + 64 * b, *colp = L.colb + YF_COLB * b;
-        const double2 piv = rowp[p];
-        const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
-        const double2 d = cd(piv.x * inv, -piv.y * inv);   // 1 / C[p][p]
-        // every entry becomes s v - C[i][p] mu and row p becomes mu, with
-        // mu = C[p][k] / C[p][p], s = 1 off column p, and mu = 1 / C[p][p],
-        // s = 0 on it (where C[i][p] is v itself)
-        const bool kpiv = k == p;
-        const double2 mu = ysel(kpiv, d, ymul(rowp[k], d));
-        const double sv = kpiv ? 0.0 : 1.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const double2 v = c[r];
-            const double2 f = colp[min(rg + ng * r, n - 1)];
-            const double2 nv = cd(fma(sv, v.x, fma(f.y, mu.y, -f.x * mu.x)),
-                                  fma(sv, v.y, -fma(f.x, mu.y, f.y * mu.x)));
-            // row p = RB ng + s is slot RB of row group s
-            c[r] = r == RB ? ysel(rg == s, mu, nv) : nv;
-        }
-        if (p + 1 < n && act) {
-            // row p + 1: row group s + 1 (slot RB), or row group 0 (slot
-            // RB + 1) when s + 1 == ng
-            const bool wrap = s + 1 == ng;
-            constexpr int RN = RB + 1 < R ? RB + 1 : RB;
-            if (rg == (wrap ? 0 : s + 1)) L.rowb[64 * nb + k] = ysel(wrap, c[RN], c[RB]);
-            if (k == p + 1) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int i = rg + ng * r;
-                    L.colb[YF_COLB * nb + (i < n ? i : YF_COLB - 1)] = c[r];
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
-
-template <int R, int... RBs>
-__device__ __forceinline__ void yf_pivot_blocks(double2 (&c)[R], const YFactorLds &L, int n,
-                                                int k, int rg, int ng, bool act,
-                                                std::integer_sequence<int, RBs...>) {
-    (yf_pivot_block<R, RBs>(c, L, n, k, rg, ng, act), ...);
-}
-
-template <int R>
-__device__ __forceinline__ void yf_invert(double2 (&c)[R], const YFactorLds &L, int n, int k, int rg, int ng,
-                          bool act) {
-    if (act && rg == 0) L.rowb[k] = c[0];
-    if (act && k == 0) {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (rg + ng * r < n) L.colb[rg + ng * r] = c[r];
-    }
-    __syncthreads();
-    yf_pivot_blocks(c, L, n, k, rg, ng, act, std::make_integer_sequence<int, R>());
-}
-
-// A_a[i][k] from cb
-__device__ __forceinline__ double2 yf_a(const double2 *cb, int n, int i, int k) {
-    const int mn = min(min(i, k), n - 1);
-    const double2 dg = cb[min(i, n - 1)], od = cb[n + mn];
+// A_a (padded with the identity) at (i, k) from cb
+__device__ __forceinline__ double2 yf_a(const double2 *cb, int np, int n, int i, int k) {
+    if (i >= n || k >= n) return cd(i == k ? 1.0 : 0.0, 0.0);
+    const double2 dg = cb[i], od = cb[np + min(i, k)];
     return ysel(i == k, dg, ysel(k == i + 1 || i == k + 1, od, yz()));
 }
 
-template <int R>
-__device__ __forceinline__ void yf_store(const double2 (&c)[R], double2 *out, int n, int k,
-                                         int rg, int ng, bool act) {
+// c -= (X G Y) with G in L.gl: lower C -= B^T G B, upper C -= B G B^T, as
+// H = G Y (3 terms) then X H (3 terms); the coefficients past the padding
+// edge are zero, so the reads are clamped.  Ends with L.gl free.
+template <int T>
+__device__ __forceinline__ void yf_sandwich(double2 (&c)[T][T], const YFLds<T> &L, int tr,
+                                            int tc, int side) {
+    constexpr int NP = 16 * T;
+    double2 h[T][T];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = rg + ng * r;
-        if (act && i < n) out[i * n + k] = c[r];
+    for (int cc = 0; cc < T; ++cc) {
+        const int k = tc + 16 * cc;
+        const Tri tk = yf_tri(L.cb, NP, k, side);
+        const int km = max(k - 1, 0), kp = min(k + 1, NP - 1);
+#pragma unroll
+        for (int a = 0; a < T; ++a) {
+            const double2 *gi = L.gl + (tr + 16 * a) * NP;
+            h[a][cc] = yfma(gi[kp], tk.p1, yfma(gi[km], tk.m1, ymul(gi[k], tk.z0)));
+        }
     }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int cc = 0; cc < T; ++cc) L.gl[(tr + 16 * a) * NP + tc + 16 * cc] = h[a][cc];
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+        const int i = tr + 16 * a;
+        const Tri ti = yf_tri(L.cb, NP, i, side);
+        const int im = max(i - 1, 0), ip = min(i + 1, NP - 1);
+#pragma unroll
+        for (int cc = 0; cc < T; ++cc) {
+            const int k = tc + 16 * cc;
+            const double2 s = yfma(ti.p1, L.gl[ip * NP + k],
+                                   yfma(ti.m1, L.gl[im * NP + k], ymul(ti.z0, L.gl[i * NP + k])));
+            c[a][cc].x -= s.x;
+            c[a][cc].y -= s.y;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double2 yshfl(double2 v, int src) {
+    return cd(__shfl(v.x, src), __shfl(v.y, src));
+}
+
+// One block step S of the in-place Gauss-Jordan inversion (no pivoting):
+// pivot block P = rows and columns 8 S .. 8 S + 7 (row group half S & 1,
+// register slot S >> 1, known at compile time).  With D = C_PP^{-1}:
+//     C_PP <- D,  C_PR <- D C_PR,  C_RP <- -C_RP D,  C_RR <- C_RR - C_RP D C_PR.
+// The block's rows and columns go to LDS (buffers of the step's parity, so
+// the next step needs no barrier before publishing); every wave inverts the
+// 8 x 8 pivot block in its own lanes (lane 8 a + c holds D[a][c]; scalar
+// Gauss-Jordan with lane shuffles, no pivoting); Z = D C_PR (D itself on
+// the pivot columns) goes to LDS; each entry then takes 8 complex
+// multiply-adds.  Two barriers per block step.
+// The in-place Gauss-Jordan inversion (no pivoting) in block steps s =
+// 0 .. 2T-1 of 8 pivots: P = rows and columns 8 s .. 8 s + 7.  With
+// D = C_PP^{-1}:
+//     C_PP <- D,  C_PR <- D C_PR,  C_RP <- -C_RP D,  C_RR <- C_RR - C_RP D C_PR.
+// The register tile is rotated by one slot in rows and columns after every
+// second step, so the pivot block always sits in slot 0 (row group half
+// s & 1): slot a holds rows tr + 16 ((a + s/2) mod T), likewise the columns,
+// and T rotations over the 2T steps restore the order.  Each step puts its
+// pivot rows and columns in LDS (buffers of the step's parity, so the next
+// step needs no barrier before publishing); every wave inverts the 8 x 8
+// pivot block in its own lanes (lane 8 a + c holds D[a][c]; scalar
+// Gauss-Jordan with lane shuffles); Z = D C_PR (D itself on the pivot
+// columns) goes to LDS; each entry then takes 8 complex multiply-adds, as
+// two rank-4 halves.  Two barriers per step.
+template <int T>
+__device__ __forceinline__ void yf_invert(double2 (&c)[T][T], const YFLds<T> &L, int tr, int tc) {
+    constexpr int NP = 16 * T;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ar = lane >> 3, ac = lane & 7;
+    double2 *dsw = L.ds + wave * 64;
+#pragma unroll 1
+    for (int s = 0; s < 2 * T; ++s) {
+        const int hf = s & 1, p0 = 8 * s, rot = s >> 1;
+        double2 *rowsP = L.rowsP + hf * 8 * NP, *colsP = L.colsP + hf * NP * 8;
+        double2 *zs = L.zs + hf * 8 * NP;
+        auto row_of = [&](int a) { return tr + 16 * ((a + rot) % T); };
+        auto col_of = [&](int cc) { return tc + 16 * ((cc + rot) % T); };
+        const bool prow = (tr >> 3) == hf, pcol = (tc >> 3) == hf;
+        if (prow) {
+#pragma unroll
+            for (int cc = 0; cc < T; ++cc) rowsP[(tr & 7) * NP + col_of(cc)] = c[0][cc];
+        }
+        if (pcol) {
+#pragma unroll
+            for (int a = 0; a < T; ++a) colsP[row_of(a) * 8 + (tc & 7)] = c[a][0];
+        }
+        __syncthreads();
+        // D = C_PP^{-1}, every wave on its own
+        double2 D = rowsP[ar * NP + p0 + ac];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const double2 pq = cd(lane_f64(D.x, 9 * q), lane_f64(D.y, 9 * q));
+            const double inv = 1.0 / (pq.x * pq.x + pq.y * pq.y);
+            const double2 d = cd(pq.x * inv, -pq.y * inv);
+            const double2 rq = yshfl(D, 8 * q + ac), cq = yshfl(D, 8 * ar + q);
+            const bool kq = ac == q;
+            const double2 mu = ysel(kq, d, ymul(rq, d));
+            const double sv = kq ? 0.0 : 1.0;
+            const double2 nv = cd(fma(sv, D.x, fma(cq.y, mu.y, -cq.x * mu.x)),
+                                  fma(sv, D.y, -fma(cq.x, mu.y, cq.y * mu.x)));
+            D = ysel(ar == q, mu, nv);
+        }
+        dsw[lane] = D;
+        // Z = D C_PR over all NP columns (D on the pivot columns)
+#pragma unroll
+        for (int w = 0; w < (8 * NP + 255) / 256; ++w) {
+            const int v = (int)threadIdx.x + 256 * w;
+            if (v < 8 * NP) {
+                const int m = v / NP, k = v % NP;
+                double2 z = yz();
+#pragma unroll
+                for (int l = 0; l < 8; ++l) z = yfma(dsw[m * 8 + l], rowsP[l * NP + k], z);
+                const bool kp = k >= p0 && k < p0 + 8;
+                zs[m * NP + k] = ysel(kp, dsw[m * 8 + min(max(k - p0, 0), 7)], z);
+            }
+        }
+        __syncthreads();
+        double2 acc[T][T];
+#pragma unroll
+        for (int a = 0; a < T; ++a)
+#pragma unroll
+            for (int cc = 0; cc < T; ++cc) acc[a][cc] = yz();
+#pragma unroll
+        for (int mh = 0; mh < 8; mh += 4) {
+            double2 zk[T][4], cp[T][4];
+#pragma unroll
+            for (int cc = 0; cc < T; ++cc)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) zk[cc][m] = zs[(mh + m) * NP + col_of(cc)];
+#pragma unroll
+            for (int a = 0; a < T; ++a)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) cp[a][m] = colsP[row_of(a) * 8 + mh + m];
+#pragma unroll
+            for (int a = 0; a < T; ++a)
+#pragma unroll
+                for (int cc = 0; cc < T; ++cc)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        acc[a][cc] = yfma(cp[a][m], zk[cc][m], acc[a][cc]);
+        }
+#pragma unroll
+        for (int a = 0; a < T; ++a) {
+#pragma unroll
+            for (int cc = 0; cc < T; ++cc) {
+                // the pivot columns start from zero (C_RP <- -C_RP D)
+                const double2 base = cc == 0 ? ysel(pcol, yz(), c[a][cc]) : c[a][cc];
+                const double2 nv = cd(base.x - acc[a][cc].x, base.y - acc[a][cc].y);
+                // the pivot rows take Z (D C_PR, and D on the pivot columns)
+                c[a][cc] = a == 0 ? ysel(prow, zs[(tr & 7) * NP + col_of(cc)], nv) : nv;
+            }
+        }
+        if (hf == 1) {   // the next block's rows and columns into slot 0
+            double2 t[T][T];
+#pragma unroll
+            for (int a = 0; a < T; ++a)
+#pragma unroll
+                for (int cc = 0; cc < T; ++cc) t[a][cc] = c[(a + 1) % T][(cc + 1) % T];
+#pragma unroll
+            for (int a = 0; a < T; ++a)
+#pragma unroll
+                for (int cc = 0; cc < T; ++cc) c[a][cc] = t[a][cc];
+        }
+    }
+    __syncthreads();
+}
+
+template <int T>
+__device__ __forceinline__ void yf_store(const double2 (&c)[T][T], double2 *out, int n, int tr,
+                                         int tc) {
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int cc = 0; cc < T; ++cc) {
+            const int i = tr + 16 * a, k = tc + 16 * cc;
+            if (i < n && k < n) out[i * n + k] = c[a][cc];
+        }
+}
+
+template <int T>
+__device__ __forceinline__ void yf_init(const YFLds<T> &L) {
+    constexpr int NP = 16 * T;
+    for (int e = threadIdx.x; e < 5 * NP; e += blockDim.x) L.cb[e] = yz();
 }
 
 // The two halves of every strip: blockIdx.x = 2 j + half.
-template <int R>
+template <int T>
 __global__ __launch_bounds__(YF_THREADS) void yfactor_half_kernel(const YStrip *ys, int ny,
                                                                   const double2 *Dc,
                                                                   const double2 *Uc, double2 *YF,
                                                                   double2 *YB) {
+    constexpr int NP = 16 * T;
     const int j = blockIdx.x >> 1, half = blockIdx.x & 1;
     const YStrip S = ys[j];
     const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
     extern __shared__ double2 ylds[];
-    const YFactorLds L = yf_lds(ylds, n);
-    const int ng = YF_THREADS / n, k = threadIdx.x % n, rg = threadIdx.x / n;
-    const bool act = rg < ng;
-    double2 c[R];
+    const YFLds<T> L = yf_lds<T>(ylds);
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+    yf_init(L);
+    double2 c[T][T];
     const int a0 = half == 0 ? 0 : ny - 1, a1 = m, da = half == 0 ? 1 : -1;
     // coupling block of y-line a: lower B_{a-1}, upper B_a (none for a0)
     auto ab_of = [&](int a) { return a == a0 ? -1 : (half == 0 ? a - 1 : a); };
     YCoef nxt = yf_coef_load(S, ny, a0, -1, Dc, Uc);
+    __syncthreads();
     for (int a = a0; a != a1; a += da) {
         const bool first = a == a0;
         const int ab = ab_of(a);
-        if (!first) yf_store(c, L.gl, n, k, rg, ng, act);   // the previous inverse
+        if (!first) {   // the previous inverse, for the product
+#pragma unroll
+            for (int aa = 0; aa < T; ++aa)
+#pragma unroll
+                for (int cc = 0; cc < T; ++cc)
+                    L.gl[(tr + 16 * aa) * NP + tc + 16 * cc] = c[aa][cc];
+        }
         const YCoef cur = nxt;
         // the next y-line's coefficients (the last one loads its own again)
         const int an = a + da != a1 ? a + da : a;
         nxt = yf_coef_load(S, ny, an, ab_of(an), Dc, Uc);
-        yf_coef_put(cur, S, ab, L.cb, YB);
+        yf_coef_put(cur, S, ab, NP, L.cb, YB);
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < R; ++r) c[r] = yf_a(L.cb, n, rg + ng * r, k);
-        if (!first) yf_sandwich(c, L, n, k, rg, ng, act, half);
-        yf_invert(c, L, n, k, rg, ng, act);
-        yf_store(c, YF + S.yoff + (long)a * nn, n, k, rg, ng, act);
+        for (int aa = 0; aa < T; ++aa)
+#pragma unroll
+            for (int cc = 0; cc < T; ++cc) c[aa][cc] = yf_a(L.cb, NP, n, tr + 16 * aa, tc + 16 * cc);
+        if (!first) yf_sandwich(c, L, tr, tc, half);
+        yf_invert(c, L, tr, tc);
+        yf_store(c, YF + S.yoff + (long)a * nn, n, tr, tc);
     }
 }
 
 // The middle line of every strip: C = A_m - B_{m-1}^T T_{m-1}^{-1} B_{m-1}
 // - B_m U_{m+1}^{-1} B_m^T (the terms present), inverted.
-template <int R>
+template <int T>
 __global__ __launch_bounds__(YF_THREADS) void yfactor_mid_kernel(const YStrip *ys, int ny,
                                                                  const double2 *Dc,
                                                                  const double2 *Uc, double2 *YF,
                                                                  double2 *YB) {
+    constexpr int NP = 16 * T;
     const YStrip S = ys[blockIdx.x];
     const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
     extern __shared__ double2 ylds[];
-    const YFactorLds L = yf_lds(ylds, n);
-    const int ng = YF_THREADS / n, k = threadIdx.x % n, rg = threadIdx.x / n;
-    const bool act = rg < ng;
-    double2 c[R];
-    yf_coef(S, ny, m, -1, Dc, Uc, L.cb, YB);
+    const YFLds<T> L = yf_lds<T>(ylds);
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+    yf_init(L);
+    __syncthreads();
+    double2 c[T][T];
+    yf_coef_put(yf_coef_load(S, ny, m, -1, Dc, Uc), S, -1, NP, L.cb, YB);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < R; ++r) c[r] = yf_a(L.cb, n, rg + ng * r, k);
+    for (int aa = 0; aa < T; ++aa)
+#pragma unroll
+        for (int cc = 0; cc < T; ++cc) c[aa][cc] = yf_a(L.cb, NP, n, tr + 16 * aa, tc + 16 * cc);
     __syncthreads();
     for (int side = 0; side < 2; ++side) {
         const int ab = side == 0 ? m - 1 : m;           // coupling block index
         const int ag = side == 0 ? m - 1 : m + 1;       // neighbouring complement
         if (ag < 0 || ag >= ny) continue;
-        yf_coef(S, ny, m, ab, Dc, Uc, L.cb, YB);
+        yf_coef_put(yf_coef_load(S, ny, m, ab, Dc, Uc), S, ab, NP, L.cb, YB);
         const double2 *src = YF + S.yoff + (long)ag * nn;
-        for (int e = threadIdx.x; e < nn; e += blockDim.x) L.gl[e] = src[e];
+        for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {
+            const int i = e / NP, k = e % NP;
+            L.gl[e] = (i < n && k < n) ? src[i * n + k] : cd(i == k ? 1.0 : 0.0, 0.0);
+        }
         __syncthreads();
-        yf_sandwich(c, L, n, k, rg, ng, act, side);
+        yf_sandwich(c, L, tr, tc, side);
     }
-    yf_invert(c, L, n, k, rg, ng, act);
-    yf_store(c, YF + S.yoff + (long)m * nn, n, k, rg, ng, act);
+    yf_invert(c, L, tr, tc);
+    yf_store(c, YF + S.yoff + (long)m * nn, n, tr, tc);
 }
 
-// Rows per thread the factor needs for strips of at most max_nx node-lines
-// (the largest ceil(n / (256 div n)) over n <= max_nx).
-int yf_rows(int max_nx) {
-    int r = 1;
-    for (int n = 1; n <= max_nx; ++n) {
-        const int ng = YF_THREADS / n;
-        r = std::max(r, (n + ng - 1) / ng);
-    }
-    return r;
-}
+// Registers of the factor for strips of at most max_nx node-lines: the
+// padded order NP = 16 T >= max_nx.
+int yf_t(int max_nx) { return max_nx <= 32 ? 2 : (max_nx <= 48 ? 3 : 4); }
 
 // ---------------------------------------------------------------- solve
 // One workgroup of NR waves per strip half, NR = ceil(max nx / 8) (4, 6 or
@@ -732,8 +802,7 @@ __global__ __launch_bounds__(64 * NR) void ysolve_mid_kernel(const YStrip *ys, i
 }  // namespace
 
 size_t yorder_factor_lds(int max_nx) {
-    return sizeof(double2) *
-           (128 + 2 * (size_t)YF_COLB + 5 * (size_t)max_nx + (size_t)max_nx * max_nx);
+    return sizeof(double2) * (size_t)yf_lds_count(16 * yf_t(max_nx));
 }
 
 // Per y-line: the inversion (n^3 complex multiply-adds) and the two
@@ -749,15 +818,14 @@ hipError_t launch_yfactor(hipStream_t st, const YStrip *ys, int nstrips, int ny,
     hipError_t e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     const size_t lds = yorder_factor_lds(max_nx);
-    const int rows = yf_rows(max_nx);
     auto go = [&](auto half, auto mid) {
         hipLaunchKernelGGL(half, dim3(2 * nstrips), dim3(YF_THREADS), lds, st, ys, ny, Dc, Uc, YF,
                            YB);
         hipLaunchKernelGGL(mid, dim3(nstrips), dim3(YF_THREADS), lds, st, ys, ny, Dc, Uc, YF, YB);
     };
-    if (rows <= 4) go(yfactor_half_kernel<4>, yfactor_mid_kernel<4>);
-    else if (rows <= 8) go(yfactor_half_kernel<8>, yfactor_mid_kernel<8>);
-    else if (rows <= 16) go(yfactor_half_kernel<16>, yfactor_mid_kernel<16>);
+    if (max_nx <= 32) go(yfactor_half_kernel<2>, yfactor_mid_kernel<2>);
+    else if (max_nx <= 48) go(yfactor_half_kernel<3>, yfactor_mid_kernel<3>);
+    else if (max_nx <= 64) go(yfactor_half_kernel<4>, yfactor_mid_kernel<4>);
     else return hipErrorInvalidValue;
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev1) e = hipEventRecord(ev1, st);
