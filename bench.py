@@ -52,6 +52,14 @@ TRAFFIC = {
         "bytes": 4.0256e+09,
         "source_sha256": "0188a515ae068128f803335738cdd412be490495c3eb45af7f1614408e1640bd",
         "summary": "profiles/sweep_update_c32_rot2048_hbm_counters.md"},
+    ("rot2048", "y", "ysolve"): {
+        "bytes": 6.0943e+09,
+        "source_sha256": "b49ab4d7ccd290432cfe7567166bf92676287ca187817c53b55f4af7c3c0cc67",
+        "summary": "profiles/ysolve_yfactor_f64_rot2048_hbm_counters.md"},
+    ("rot2048", "y", "yfactor"): {
+        "bytes": 2.9691e+09,
+        "source_sha256": "b49ab4d7ccd290432cfe7567166bf92676287ca187817c53b55f4af7c3c0cc67",
+        "summary": "profiles/ysolve_yfactor_f64_rot2048_hbm_counters.md"},
 }
 
 TRAFFIC_SOURCES = {"strip_solve": "kernels_solve.hip", "sweep_update": "kernels_factor.hip",
@@ -123,9 +131,11 @@ def run_gpu(pb, u0, V, prec, steps, warmup, dev, measure=True, **extra):
     work = s.kernel_work() if measure else 0.0
     team = s.solve_team()
     shape = s.solve_shape()
+    order = s.strip_order()
     s.close()
     return dict(seconds=t1 - t0, factor_s=t_fac, setup_s=t_setup, stats=stats, u=u,
-                solve_ms=kern[0], solve_launches=kern[1], solve_work=work, team=team, shape=shape)
+                solve_ms=kern[0], solve_launches=kern[1], solve_work=work, team=team, shape=shape,
+                order=order)
 
 
 def profile_solve(pb, V, prec, launches, dev, team=0, solve_shape=0):
@@ -325,7 +335,7 @@ def run_learned(args, dev):
     from paper_1603_05110_amd import learned, osm
     from workloads import c4, c4_family, net_init, rng_for
 
-    opts = dict(solver_opts("c32"))
+    opts = dict(solver_opts("c32"), strip_order=args.strip_order, lh_form=args.lh_form)
     t0 = time.perf_counter()
     Xs, Ts = [], []
     rng = rng_for(4, salt=1)
@@ -858,9 +868,11 @@ def run_paper_e6(args, dev):
             dof = (pb.ncx + 1) * (pb.ncy + 1)
             opts = dict(algo=algo, prec=args.prec, tol_k=1e-10, tol_k_relative=False,
                         max_k=5000, tol_q=1e-13, max_q=200, warm_start=True,
-                        tol_gmres=3e-2, gmres_restart=50, max_gmres=4000)
+                        tol_gmres=3e-2, gmres_restart=50, max_gmres=4000,
+                        strip_order=args.strip_order, lh_form=args.lh_form)
             s = osm.OsmSolver(pb, dev, **opts)
             s.factor_rotating(1)
+            order = s.strip_order()
             u = torch.from_numpy(u0).to(dev)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -872,24 +884,29 @@ def run_paper_e6(args, dev):
             T = time.perf_counter() - t0
             s.close()
             hours = PAPER_E6_HOURS[algo][N]
-            runs.append({"algo": algo, "N": N, "value": dof * args.steps / T,
+            runs.append({"algo": algo, "N": N, "strip_order": order,
+                         "value": dof * args.steps / T,
                          "ms_per_step": 1e3 * T / args.steps, "k_mean": float(np.mean(ks)),
                          "k_max": int(np.max(ks)),
                          "paper_hours_T0.1": hours,
                          "paper_dof_steps_per_s": dof * 1000 / (hours * 3600.0)})
-            print(f"bench: {algo} N={N}: {runs[-1]['value']:.4g} dof-steps/s, k mean "
+            print(f"bench: {algo} N={N} ({order}): {runs[-1]['value']:.4g} dof-steps/s, k mean "
                   f"{runs[-1]['k_mean']:.1f} (paper {runs[-1]['paper_dof_steps_per_s']:.3g})",
                   file=sys.stderr, flush=True)
     best = max(runs, key=lambda r: r["value"])
     out = {"metric": METRIC, "value": best["value"], "unit": "dof-steps/s", "n_gpus": 1,
            "steps": args.steps, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "c64+f64-refine" if args.prec == "c32" else "c128",
+           "vs_baseline": None,
+           "dtype": ("f64" if best["strip_order"] == "y" else
+                     "c64+f64-refine" if args.prec == "c32" else "c128"),
            "data": "synthetic",
            "config": {"workload": "paper Section 5.2.2: rotating GPE, (-16,16)^2, 1024^2 cells, "
                                   "omega=0.4, beta=10.15, dt=1e-4, Robin p=180, refactor every "
                                   "step", "dof": 1025 * 1025,
-                      "horizon": f"{args.steps} of 1000 steps", "best": {"algo": best["algo"],
-                                                                          "N": best["N"]}},
+                      "strip_order_option": args.strip_order,
+                      "horizon": f"{args.steps} of 1000 steps",
+                      "best": {"algo": best["algo"], "N": best["N"],
+                               "strip_order": best["strip_order"]}},
            "runs": runs}
     print(json.dumps(out), flush=True)
 
@@ -935,14 +952,15 @@ def main():
     ap.add_argument("--team", type=int, default=0,
                     help="profiler modes: workgroups per strip in the solve (0 = autotune)")
     ap.add_argument("--strip-order", default="tuned", choices=["node", "y", "tuned"],
-                    help="rot2048: unknown order of the strip factor (tuned: the autotuner "
-                         "times both after the first factorisation)")
+                    help="rot2048, gpe512, learned1024, paper-e6: unknown order of the strip "
+                         "factor (tuned: the autotuner times both after the first "
+                         "factorisation)")
     ap.add_argument("--node-steps", type=int, default=5,
                     help="rot2048: steps of the node-line order timed beside a y-line main run "
                          "(0 = skip)")
     ap.add_argument("--lh-form", default="auto", choices=["auto", "dense", "modal"],
                     help="L_h as dense blocks per strip class or in the modal form (auto: "
-                         "modal where ny > 1088)")
+                         "modal where ny > 1088, or ny >= 1025 with ny - 1 a power of two: by FFT)")
     ap.add_argument("--solve-shape", type=int, default=0,
                     help="profiler modes: strip-solve tile shape + 1 (0 = autotune)")
     args = ap.parse_args()
@@ -987,7 +1005,7 @@ def main():
         return
 
     main_run = run_gpu(pb, u0, V, args.prec, args.steps, args.warmup, dev,
-                       lh_form=args.lh_form)
+                       lh_form=args.lh_form, strip_order=args.strip_order)
     T = main_run["seconds"]
     st = main_run["stats"]
     value = dof * args.steps / T
@@ -999,8 +1017,15 @@ def main():
 
     avg_ms = main_run["solve_ms"] / max(main_run["solve_launches"], 1)
     nbytes = main_run["solve_work"] / max(main_run["solve_launches"], 1)
-    # tile shapes 0-3: full-row kernel, 4-7: upper-triangle kernel
-    solve_kernel = "strip_solve_pf_kernel" if main_run["shape"] < 4 else "strip_solve_sym_kernel"
+    order = main_run["order"]
+    if order == "y":
+        solve_kernel = "ysolve (forward, middle, backward)"
+        traffic = measured_traffic("gpe512", "y", "ysolve")
+    else:
+        # tile shapes 0-3: full-row kernel, 4-7: upper-triangle kernel
+        solve_kernel = ("strip_solve_pf_kernel" if main_run["shape"] < 4
+                        else "strip_solve_sym_kernel")
+        traffic = measured_traffic("gpe512", args.prec, "strip_solve", main_run["shape"])
     achieved = nbytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
 
     fp64 = None
@@ -1050,19 +1075,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64+f64-refine" if args.prec == "c32" else "c128",
+        "dtype": ("f64" if order == "y" else
+                  "c64+f64-refine" if args.prec == "c32" else "c128"),
         "data": "synthetic",
         "config": {"workload": "GPE trap V=-(x^2+y^2)/2, f=-50|u|^2, (-8,8)^2, 512x512 cells, "
                                "16 equal strips, Robin p=5, dt=1e-3, preconditioned GMRES",
                    "dof": dof, "strips": pb.nsub, "algo": "precond", "prec": args.prec,
-                   "timed": "factor(W) + steps"},
+                   "strip_order": order, "strip_order_option": args.strip_order,
+                   "lh_form": args.lh_form, "timed": "factor(W) + steps"},
         "iters": {"k_mean": float(np.mean(ks)), "k_max": int(np.max(ks)),
                   "q_total": int(np.sum(qs)), "gmres_total": int(np.sum(gm)),
                   "gmres_per_step": float(np.mean(gm))},
         "roofline": {"kernel": solve_kernel, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("gpe512", args.prec, "strip_solve",
-                                                 main_run["shape"]),
+                     "traffic": traffic,
                      "bytes_per_launch": nbytes,
                      "avg_launch_ms": avg_ms,
                      "launches": main_run["solve_launches"],

@@ -201,12 +201,16 @@ typedef struct {
                                      (the form S_pade^m always uses); 2 = for
                                      the Robin condition, in the cosine
                                      eigenbasis of the y-direction (exact for
-                                     W = 0 on the uniform mesh: two dense real
-                                     ny x ny transforms of all traces on the
-                                     matrix cores around a 2 x 2 combination per
-                                     mode); 0 = 2 where the dense blocks' fused
-                                     product kernel does not apply (ny > 1088),
-                                     else 1                                      */
+                                     W = 0 on the uniform mesh: a discrete
+                                     cosine transform of every trace, a 2 x 2
+                                     combination per mode, the transform back;
+                                     by FFT of length 2 (ny - 1) when ny - 1 is
+                                     a power of two up to 2048, else as dense
+                                     real ny x ny products on the matrix
+                                     cores); 0 = 2 where ny - 1 is such a power
+                                     of two at least 1024 or where the dense
+                                     blocks' fused product kernel does not
+                                     apply (ny > 1088), else 1                   */
 } osm_options;
 
 typedef struct {
@@ -348,6 +352,11 @@ int32_t osm_solve_shape(const osm_handle *h);
  * order (osm_options.strip_order; with 2 the autotuner's choice, known after
  * the first factorisation, node-line order before it).  0 for a NULL handle. */
 int32_t osm_strip_order(const osm_handle *h);
+
+/* How L_h is applied (osm_options.lh_form, Section 4.2): 0 = not built
+ * (classical algorithm), 1 = dense blocks per strip class, 2 = modal form by
+ * dense real transforms, 3 = modal form by FFT.  0 for a NULL handle. */
+int32_t osm_lh_form(const osm_handle *h);
 
 /* ---------------------------------------------------------------- learned guess
  * A network predicts the next step's interface start from the history (the

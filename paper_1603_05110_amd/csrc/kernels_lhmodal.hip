@@ -173,6 +173,148 @@ __global__ __launch_bounds__(256) void lhm_combine_kernel(int n, int nsub, const
     yh[(long)t * n + mu] = v;
 }
 
+// ---------------------------------------------------------------- by FFT
+// When n - 1 = N is a power of two the transforms are discrete cosine
+// transforms of the first kind.  With z the even extension of a trace v to
+// L = 2N points (z_j = v_j for j <= N, z_{L-j} = v_j), the DFT
+// F(z)_mu = sum_j z_j exp(-2 pi i j mu / L) is even in mu and its first N + 1
+// entries are sum_j c_j v_j cos(pi j mu / N) with c_j = 1 at the ends and 2
+// inside.  The normalisation of Phi and the mass matrix cancel in the product
+// Phi diag(d) Phi^{-1} = Phi diag(d) diag(mth) Phi^T D (M_y phi_mu =
+// mth_mu D phi_mu, D = diag(1/2, 1, ..., 1, 1/2)): with alpha_mu^2 mth_mu
+// times the end weights equal to 2/L, one block application is
+//     X v = F(ext(d . F(ext v))) / L   on the entries 0..N,
+// so L_h x needs one FFT of every trace and one of every output, with no
+// matrix at all.  The FFT is Stockham's self-sorting radix-4 form (a radix-2
+// pass first when log2 L is odd), in place in LDS: each pass reads its
+// butterflies' inputs into registers, synchronises, then writes them to the
+// sorted positions.
+constexpr int FT_THREADS = 512;
+
+// exp(-2 pi i m / L) for m < L from the quarter table tq[r], r < L/4
+// (exp(-2 pi i q / 4) = (-i)^q for the quarter q of m).
+__device__ __forceinline__ double2 ft_tw(const double2 *tq, int m, int lg) {
+    const int q = m >> (lg - 2), r = m & ((1 << (lg - 2)) - 1);
+    const double2 t = tq[r];
+    if (q == 0) return t;
+    if (q == 1) return cd(t.y, -t.x);
+    if (q == 2) return cd(-t.x, -t.y);
+    return cd(-t.y, t.x);
+}
+
+__device__ __forceinline__ void ft_table(double2 *tq, int lg) {
+    const int q4 = 1 << (lg - 2);
+    for (int r = threadIdx.x; r < q4; r += FT_THREADS) {
+        double sn, cs;
+        sincospi(ldexp((double)r, 1 - lg), &sn, &cs);     // angle 2 pi r / L
+        tq[r] = cd(cs, -sn);
+    }
+}
+
+// In-place DFT of buf[0..L), L = 2^lg, 3 <= lg <= 12.  Every pass has at
+// most L/4 radix-4 (or, first, L/2 <= 1024 radix-2) butterflies: two per
+// thread at most.
+__device__ __forceinline__ void ft_fft(double2 *buf, const double2 *tq, int lg) {
+    const int L = 1 << lg, tid = threadIdx.x;
+    int ns = 1, lns = 0;
+    for (int done = 0; done < lg;) {
+        const bool r4 = ((lg - done) & 1) == 0;
+        const int lr = r4 ? 2 : 1, B = L >> lr;
+        double2 v[2][4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int j = tid + q * FT_THREADS;
+            if (j < B) {
+                const int k = j & (ns - 1), step = lg - lns - lr;   // L / (ns R) = 2^step
+                v[q][0] = buf[j];
+                v[q][1] = cmul(buf[j + B], ft_tw(tq, k << step, lg));
+                if (r4) {
+                    v[q][2] = cmul(buf[j + 2 * B], ft_tw(tq, (2 * k) << step, lg));
+                    v[q][3] = cmul(buf[j + 3 * B], ft_tw(tq, (3 * k) << step, lg));
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int j = tid + q * FT_THREADS;
+            if (j < B) {
+                const int k = j & (ns - 1), o = ((j - k) << lr) + k;
+                if (r4) {
+                    const double2 a0 = cadd(v[q][0], v[q][2]), a1 = csub(v[q][0], v[q][2]);
+                    const double2 a2 = cadd(v[q][1], v[q][3]), d = csub(v[q][1], v[q][3]);
+                    const double2 a3 = cd(d.y, -d.x);          // (v1 - v3) (-i)
+                    buf[o] = cadd(a0, a2);
+                    buf[o + ns] = cadd(a1, a3);
+                    buf[o + 2 * ns] = csub(a0, a2);
+                    buf[o + 3 * ns] = csub(a1, a3);
+                } else {
+                    buf[o] = cadd(v[q][0], v[q][1]);
+                    buf[o + ns] = csub(v[q][0], v[q][1]);
+                }
+            }
+        }
+        __syncthreads();
+        ns <<= lr;
+        lns += lr;
+        done += lr;
+    }
+}
+
+// xh[t][mu] = F(ext x_t)_mu, mu <= N, for trace t = blockIdx.x.
+__global__ __launch_bounds__(FT_THREADS) void lhf_forward_kernel(int n, int lg,
+                                                                 const double2 *x, double2 *xh,
+                                                                 const GmresCtl *ctl) {
+    if (ctl && ctl->done) return;
+    extern __shared__ double2 flds[];
+    const int L = 1 << lg, N = n - 1, t = blockIdx.x;
+    double2 *buf = flds, *tq = flds + L;
+    ft_table(tq, lg);
+    const double2 *xt = x + (long)t * n;
+    for (int j = threadIdx.x; j <= N; j += FT_THREADS) {
+        const double2 v = xt[j];
+        buf[j] = v;
+        if (j > 0 && j < N) buf[L - j] = v;
+    }
+    __syncthreads();
+    ft_fft(buf, tq, lg);
+    double2 *o = xh + (long)t * n;
+    for (int mu = threadIdx.x; mu <= N; mu += FT_THREADS) o[mu] = buf[mu];
+}
+
+// Output trace t = blockIdx.x: its strip's per-mode combination of the
+// transformed inputs, transformed back; out = base + sign y (base may be
+// null; it may alias out).
+__global__ __launch_bounds__(FT_THREADS) void lhf_inverse_kernel(
+    int n, int lg, int nsub, const double2 *xh, const StripMeta *strips, const double2 *dm,
+    const double2 *base, double sign, double2 *out, const GmresCtl *ctl) {
+    if (ctl && ctl->done) return;
+    extern __shared__ double2 flds[];
+    const int L = 1 << lg, N = n - 1, t = blockIdx.x;
+    double2 *buf = flds, *tq = flds + L;
+    ft_table(tq, lg);
+    const LhmSrc s = lhm_src(t, nsub);
+    const double2 *d = dm + (long)strips[s.strip].cls * 4 * n;
+    const double inv = ldexp(1.0, -lg);
+    for (int mu = threadIdx.x; mu <= N; mu += FT_THREADS) {
+        double2 v = cd(0.0, 0.0);
+        if (s.sl >= 0) v = cadd(v, cmul(d[(long)s.bl * n + mu], xh[(long)s.sl * n + mu]));
+        if (s.sr >= 0) v = cadd(v, cmul(d[(long)s.br * n + mu], xh[(long)s.sr * n + mu]));
+        v = cd(v.x * inv, v.y * inv);
+        buf[mu] = v;
+        if (mu > 0 && mu < N) buf[L - mu] = v;
+    }
+    __syncthreads();
+    ft_fft(buf, tq, lg);
+    for (int j = threadIdx.x; j <= N; j += FT_THREADS) {
+        const long idx = (long)t * n + j;
+        const double2 y = buf[j];
+        double2 o = cd(sign * y.x, sign * y.y);
+        if (base) o = cadd(base[idx], o);
+        out[idx] = o;
+    }
+}
+
 // Dense block X^b of strip class cls: out[r][c] = sum_mu Phi[r][mu] d(mu)
 // Phi^{-1}[mu][c] (for inspection; O(n^3)).
 __global__ void lhm_dense_kernel(int n, const double *phi, const double *phinv,
@@ -195,6 +337,15 @@ hipError_t launch_lh_modal(hipStream_t st, const Phys &P, const StripMeta *strip
                            const LhModal &md, const double2 *x, double2 *y, int mode_p,
                            const GmresCtl *ctl) {
     const int n = P.ny, ntr = 2 * (P.nsub - 1);
+    if (md.lg > 0) {
+        const size_t lds = lh_fft_lds(md.lg);
+        hipLaunchKernelGGL(lhf_forward_kernel, dim3((unsigned)ntr), dim3(FT_THREADS), lds, st,
+                           n, md.lg, x, md.xh, ctl);
+        hipLaunchKernelGGL(lhf_inverse_kernel, dim3((unsigned)ntr), dim3(FT_THREADS), lds, st,
+                           n, md.lg, P.nsub, (const double2 *)md.xh, strips, md.dm,
+                           mode_p ? x : (const double2 *)nullptr, mode_p ? -1.0 : 1.0, y, ctl);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((n + TM_N - 1) / TM_N), (unsigned)((ntr + TM_T - 1) / TM_T));
     double2 *yh = md.xh + (long)ntr * n;
     // x^ = Phi^{-1} x for every trace
@@ -217,4 +368,14 @@ hipError_t launch_lh_modal_dense(hipStream_t st, int n, const LhModal &md, int c
                        dim3(256), 0, st, n, md.phi, md.phinv, md.dm + ((long)cls * 4 + blk) * n,
                        out);
     return hipGetLastError();
+}
+
+size_t lh_fft_lds(int lg) { return ((size_t)5 << (lg - 2)) * sizeof(double2); }
+
+int lh_fft_log2(int n) {
+    const int N = n - 1;
+    if (N < 4 || (N & (N - 1)) != 0) return 0;
+    int lg = 1;
+    while ((1 << (lg - 1)) < N) ++lg;          // L = 2N = 2^lg
+    return lg <= 12 ? lg : 0;
 }

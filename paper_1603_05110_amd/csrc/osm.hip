@@ -271,7 +271,8 @@ struct Sizes {
     long pm;    // S_pade^m terms (0 for Robin)
     long peb;   // S_pade^m edges per batch of the dense edge blocks
     int lh;     // L_h and its kernels are built (OSM_PRECOND)
-    int lhm;    // ... in the modal form (Robin; lh_form 2, or 0 where ny > 1088)
+    int lhm;    // ... in the modal form (Robin; lh_form 2, or 0 where ny > 1024 and either
+                // the FFT form applies or ny > 1088)
     int fp32;
     int sym;    // the upper-triangle solve kernels are available (partials buffer)
     int yo;     // factors kept: 0 = node-line order, 1 = y-line order, 2 = both
@@ -311,7 +312,9 @@ Sizes sizes_of(const osm_problem *p, const osm_options *o) {
     s.m = o->algo != OSM_CLASSICAL ? o->gmres_restart : 0;
     s.lh = o->algo == OSM_PRECOND;
     s.pm = p->tc == OSM_TC_PADE ? p->pade_m : 0;
-    s.lhm = s.lh && !s.pm && (o->lh_form == 2 || (o->lh_form == 0 && s.n > 17 * 64));
+    s.lhm = s.lh && !s.pm &&
+            (o->lh_form == 2 ||
+             (o->lh_form == 0 && (s.n > 17 * 64 || (s.n > 1024 && lh_fft_log2((int)s.n) > 0))));
     // dense edge blocks in batches of at most 256 MB (at least one edge)
     s.peb = s.pm ? std::max(1L, std::min(2 * s.N, (256L << 20) / (s.n * s.n * 16))) : 0;
     s.fp32 = o->prec == OSM_C32_REFINE;
@@ -1160,6 +1163,14 @@ static osm_status build_lh_modal(osm_handle *h, const std::vector<int> &rep) {
     h->lhp.md.phinv = phinv_d;
     h->lhp.md.dm = dm_d;
     h->lhp.md.xh = xh_d;
+    // the transforms by FFT where ny - 1 is a power of two and the LDS fits
+    const int lg = lh_fft_log2(n);
+    int dev = 0, lim = 0;
+    if (lg > 0 && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+            hipSuccess &&
+        lh_fft_lds(lg) <= (size_t)lim)
+        h->lhp.md.lg = lg;
     return OSM_OK;
 }
 
@@ -2047,6 +2058,12 @@ osm_status osm_get_yfactor(osm_handle *h, osm_c64 *dst_dev) {
 }
 
 int32_t osm_strip_order(const osm_handle *h) { return h ? h->order : 0; }
+
+int32_t osm_lh_form(const osm_handle *h) {
+    if (!h || h->opt.algo != OSM_PRECOND) return 0;
+    if (!h->lhm) return 1;
+    return h->lhp.md.lg > 0 ? 3 : 2;
+}
 
 // Every event pair a timed launch may use, created once (when timing is
 // switched on, and by the solve autotuner), so that timed steps allocate

@@ -357,6 +357,7 @@ struct LhModal {
     const double2 *dm = nullptr;     // ncls x 4 x n: the modal diagonals of X^1 .. X^4
     double2 *xh = nullptr;           // 2 x 2 (N - 1) x n work vectors (transformed traces,
                                      // then their per-mode combination)
+    int lg = 0;                      // > 0: the transforms by FFT of length 2^lg = 2 (n - 1)
 };
 struct LhPlan {
     const LhClass *tab = nullptr;   // device, ncls entries
@@ -370,6 +371,10 @@ struct LhPlan {
 hipError_t launch_lh_modal(hipStream_t st, const Phys &P, const StripMeta *strips,
                            const LhModal &md, const double2 *x, double2 *y, int mode_p,
                            const GmresCtl *ctl);
+// log2 of the FFT length 2 (n - 1) when n - 1 is a power of two in [4, 2048],
+// else 0; the dynamic LDS of the FFT kernels at that length
+int lh_fft_log2(int n);
+size_t lh_fft_lds(int lg);
 // the dense n x n block X^{blk} of strip class cls from the modal form
 hipError_t launch_lh_modal_dense(hipStream_t st, int n, const LhModal &md, int cls, int blk,
                                  double2 *out);

@@ -73,7 +73,7 @@ class osm_footprint(ctypes.Structure):
 EXPORTS = ["osm_query", "osm_setup", "osm_factor", "osm_factor_rotating", "osm_step",
            "osm_interface_apply", "osm_set_interface_guess", "osm_get_interface",
            "osm_strip_solve", "osm_get_strip_solution", "osm_get_lh_blocks", "osm_get_factor",
-           "osm_get_yfactor", "osm_strip_order",
+           "osm_get_yfactor", "osm_strip_order", "osm_lh_form",
            "osm_kernel_timing", "osm_kernel_work", "osm_solve_team", "osm_solve_shape",
            "osm_net_nparams", "osm_net_create", "osm_net_set_params", "osm_net_get_params",
            "osm_net_forward", "osm_net_loss_grad", "osm_net_loss_grad_noalloc",
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "osm_get_factor": ([H, P], st),
         "osm_get_yfactor": ([H, P], st),
         "osm_strip_order": ([H], ctypes.c_int32),
+        "osm_lh_form": ([H], ctypes.c_int32),
         "osm_solve_team": ([H], ctypes.c_int32),
         "osm_solve_shape": ([H], ctypes.c_int32),
         "osm_kernel_timing": ([H, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -295,6 +296,11 @@ class OsmSolver:
 
     def strip_order(self):
         return "y" if int(_lib.osm_strip_order(self.h)) == 1 else "node"
+
+    def lh_form(self):
+        """How L_h is applied: None (not built), "dense", "modal" (dense real
+        transforms) or "fft" (the modal form by FFT)."""
+        return (None, "dense", "modal", "fft")[int(_lib.osm_lh_form(self.h))]
 
     def solve_team(self):
         return int(_lib.osm_solve_team(self.h))

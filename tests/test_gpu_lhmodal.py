@@ -5,7 +5,9 @@ against the FP64 oracle and against the dense-block form.
 * L_h x on a problem with uneven strips, both Robin values and ny = 130
   (three 64-wide column tiles, ragged) and 20 traces (two 16-trace tiles,
   ragged): against the oracle's dense blocks, and against the GPU's dense
-  form (lh_form).
+  form (lh_form).  The same at ny = 9, 65, 129 and 257, where ny - 1 is a
+  power of two and the transforms run by FFT (lengths 16 to 512, with and
+  without the radix-2 pass).
 * The dense blocks formed from the modal form against the dense build.
 * Full size (2048^2 cells, 64 uneven strips): L_h x on sampled strips
   against the oracle's free strip solve of that strip's inputs (the two
@@ -73,10 +75,12 @@ def free_response(orc, j, x):
     return out
 
 
-def test_modal_lh_matvec_matches_oracle_and_dense_form():
+@pytest.mark.parametrize("ncy,form", [(129, "modal"), (8, "fft"), (64, "fft"), (128, "fft"),
+                                      (256, "fft")])
+def test_modal_lh_matvec_matches_oracle_and_dense_form(ncy, form):
     osm = _osm()
-    pb = problem()
-    log(f"modal L_h x: ny={pb.ncy + 1}, {pb.nsub} strips")
+    pb = problem(ncy)
+    log(f"modal L_h x: ny={pb.ncy + 1}, {pb.nsub} strips, expect {form}")
     orc = SchwarzOracle(pb, np.zeros((pb.ncx + 1, pb.ncy + 1)))
     orc.build_Lh()
     rng = np.random.default_rng(3)
@@ -86,6 +90,7 @@ def test_modal_lh_matvec_matches_oracle_and_dense_form():
     got = {}
     for dense in (False, True):
         s = osm.OsmSolver(pb, DEV, algo="precond", lh_form="dense" if dense else "modal")
+        assert s.lh_form() == ("dense" if dense else form)
         got[dense] = s.interface_apply(osm.OSM_IFACE_LH, None, to_dev(x)).cpu().numpy()
         s.close()
     for dense in (False, True):
@@ -99,9 +104,10 @@ def test_modal_lh_matvec_matches_oracle_and_dense_form():
             assert rel(got[False][t], v) < 1e-12, (j, t)
 
 
-def test_modal_dense_blocks_equal_the_dense_build():
+@pytest.mark.parametrize("ncy", [70, 64])
+def test_modal_dense_blocks_equal_the_dense_build(ncy):
     osm = _osm()
-    pb = problem(ncy=70)
+    pb = problem(ncy=ncy)
     blk = {}
     for dense in (False, True):
         s = osm.OsmSolver(pb, DEV, algo="precond", lh_form="dense" if dense else "modal")
@@ -110,11 +116,13 @@ def test_modal_dense_blocks_equal_the_dense_build():
     assert np.max(np.abs(blk[False] - blk[True])) < 1e-12 * np.max(np.abs(blk[True]))
 
 
-def test_pinv_by_gmres_in_both_forms():
+@pytest.mark.parametrize("ncy", [99, 128])
+def test_pinv_by_gmres_in_both_forms(ncy):
     """(I - L_h)^{-1} y by GMRES: (I - L_h) applied to the result gives y
-    back (oracle's blocks), in the modal and the dense form."""
+    back (oracle's blocks), in the modal (dense transforms at ny = 100, FFT
+    at ny = 129) and the dense form."""
     osm = _osm()
-    pb = problem(ncy=99)
+    pb = problem(ncy=ncy)
     orc = SchwarzOracle(pb, np.zeros((pb.ncx + 1, pb.ncy + 1)))
     orc.build_Lh()
     rng = np.random.default_rng(5)
@@ -132,7 +140,7 @@ def test_pinv_by_gmres_in_both_forms():
 def test_full_size_modal_lh_on_sampled_strips():
     """2048^2 cells, 64 uneven strips (ny = 2049: 33 column tiles, 126
     traces): L_h x on the first, a middle, the widest and the last strip
-    against the oracle's free strip solves."""
+    against the oracle's free strip solves (the FFT of length 4096)."""
     from workloads import c5
     osm = _osm()
     pb = c5(steps=1).problems[0]
@@ -141,6 +149,7 @@ def test_full_size_modal_lh_on_sampled_strips():
     ntr = 2 * (pb.nsub - 1)
     x = rng.standard_normal((ntr, pb.ncy + 1)) + 1j * rng.standard_normal((ntr, pb.ncy + 1))
     s = osm.OsmSolver(pb, DEV, algo="precond")      # ny = 2049: the modal form by default
+    assert s.lh_form() == "fft"
     got = s.interface_apply(osm.OSM_IFACE_LH, None, to_dev(x)).cpu().numpy()
     s.close()
     orc = SchwarzOracle.__new__(SchwarzOracle)
