@@ -52,11 +52,11 @@ TRAFFIC = {
         "bytes": 4.0256e+09,
         "source_sha256": "0188a515ae068128f803335738cdd412be490495c3eb45af7f1614408e1640bd",
         "summary": "profiles/sweep_update_c32_rot2048_hbm_counters.md"},
-    ("rot2048", "y", "ysolve"): {
+    ("rot2048", "fp64", "ysolve"): {
         "bytes": 6.0943e+09,
         "source_sha256": "b49ab4d7ccd290432cfe7567166bf92676287ca187817c53b55f4af7c3c0cc67",
         "summary": "profiles/ysolve_yfactor_f64_rot2048_hbm_counters.md"},
-    ("rot2048", "y", "yfactor"): {
+    ("rot2048", "fp64", "yfactor"): {
         "bytes": 2.9691e+09,
         "source_sha256": "b49ab4d7ccd290432cfe7567166bf92676287ca187817c53b55f4af7c3c0cc67",
         "summary": "profiles/ysolve_yfactor_f64_rot2048_hbm_counters.md"},
@@ -701,18 +701,19 @@ def run_rotating(args, dev):
 
     sv, fc = main["solve"], main["factor"]
     if order == "y":
-        # the y-line order: FP64 factor (ALU, latency-bound chains) and solve
+        # the y-line order: FP64 factor (ALU, latency-bound chains), inverses
+        # stored as prec says, solve in FP64
         solve_obj = {"kernel": "ysolve (forward, middle, backward)", "bound": "hbm",
                      "achieved": sv["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": sv["achieved_GBs"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("rot2048", "y", "ysolve"),
+                     "traffic": measured_traffic("rot2048", args.prec, "ysolve"),
                      "bytes_per_launch": sv["bytes_per_launch"],
                      "avg_launch_ms": sv["avg_launch_ms"], "launches": sv["launches"],
                      "ms_per_step": sv["ms_per_step"]}
         factor_obj = {"kernel": "yfactor (halves, middle)", "bound": "alu",
                       "achieved": fc["tflops"], "peak": FP64_VALU_PEAK_TFLOPS,
                       "unit": "TFLOP/s", "frac": fc["tflops"] / FP64_VALU_PEAK_TFLOPS,
-                      "traffic": measured_traffic("rot2048", "y", "yfactor"),
+                      "traffic": measured_traffic("rot2048", args.prec, "yfactor"),
                       "flops_timed": fc["flops_timed"], "avg_launch_ms": fc["avg_launch_ms"],
                       "launches": fc["launches"], "ms_per_step": fc["ms_per_step"],
                       "note": "algorithmic flops: per y-line 8 (n^3 + 6 n^2) for the "
@@ -720,7 +721,6 @@ def run_rotating(args, dev):
         dominant = solve_obj if sv["ms_per_step"] >= fc["ms_per_step"] else factor_obj
         other = factor_obj if dominant is solve_obj else solve_obj
         roofline = dominant
-        dtype = "f64"
     else:
         roofline = {"kernel": "sweep_update", "bound": "mfma", "achieved": fc["tflops"],
                     "peak": MFMA_FP32_PEAK_TFLOPS if args.prec == "c32" else MFMA_FP64_PEAK_TFLOPS,
@@ -740,7 +740,7 @@ def run_rotating(args, dev):
                  "bytes_per_launch": sv["bytes_per_launch"], "avg_launch_ms": sv["avg_launch_ms"],
                  "launches": sv["launches"], "workgroups_per_strip": sv["workgroups_per_strip"],
                  "tile_shape": sv["tile_shape"]}
-        dtype = "c64+f64-refine" if args.prec == "c32" else "c128"
+    dtype = "c64+f64-refine" if args.prec == "c32" else "c128"
     out = {
         "metric": METRIC,
         "value": main["value"],
@@ -897,8 +897,7 @@ def run_paper_e6(args, dev):
     out = {"metric": METRIC, "value": best["value"], "unit": "dof-steps/s", "n_gpus": 1,
            "steps": args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None,
-           "dtype": ("f64" if best["strip_order"] == "y" else
-                     "c64+f64-refine" if args.prec == "c32" else "c128"),
+           "dtype": "c64+f64-refine" if args.prec == "c32" else "c128",
            "data": "synthetic",
            "config": {"workload": "paper Section 5.2.2: rotating GPE, (-16,16)^2, 1024^2 cells, "
                                   "omega=0.4, beta=10.15, dt=1e-4, Robin p=180, refactor every "
@@ -1020,7 +1019,7 @@ def main():
     order = main_run["order"]
     if order == "y":
         solve_kernel = "ysolve (forward, middle, backward)"
-        traffic = measured_traffic("gpe512", "y", "ysolve")
+        traffic = measured_traffic("gpe512", args.prec, "ysolve")
     else:
         # tile shapes 0-3: full-row kernel, 4-7: upper-triangle kernel
         solve_kernel = ("strip_solve_pf_kernel" if main_run["shape"] < 4
@@ -1075,8 +1074,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f64" if order == "y" else
-                  "c64+f64-refine" if args.prec == "c32" else "c128"),
+        "dtype": "c64+f64-refine" if args.prec == "c32" else "c128",
         "data": "synthetic",
         "config": {"workload": "GPE trap V=-(x^2+y^2)/2, f=-50|u|^2, (-8,8)^2, 512x512 cells, "
                                "16 equal strips, Robin p=5, dt=1e-3, preconditioned GMRES",

@@ -186,9 +186,11 @@ typedef struct {
                                      Schur complements inverted on the matrix
                                      cores (as in prec); 1 = y-line order, nx x nx
                                      blocks (nx = a strip's node-lines) along the
-                                     ny y-lines, factored and solved in FP64
-                                     whatever prec says (Robin only, every strip
-                                     at most 64 node-lines; EINVAL otherwise);
+                                     ny y-lines, complements formed and inverted
+                                     in FP64, the inverses stored as prec says
+                                     (complex FP32 in OSM_C32_REFINE) and applied
+                                     in FP64 (Robin only, every strip at most 64
+                                     node-lines; EINVAL otherwise);
                                      2 = the autotuner times one solve of each
                                      order after the first factorisation and
                                      keeps the faster (node-line order where the
@@ -301,15 +303,18 @@ osm_status osm_get_lh_blocks(osm_handle *h, osm_c64 *blocks_dev);
 osm_status osm_get_factor(osm_handle *h, void *dst_dev);
 
 /* Copy the stored y-line-order factor (osm_strip_order() == 1): strip by
- * strip, y-line a = 0 .. ny-1, the dense inverse (nx_j x nx_j, row-major,
- * complex128) of that y-line's Schur complement, sum_j ny nx_j^2 elements.
+ * strip, y-line a = 0 .. ny-1, the dense inverse (nx_j x nx_j, row-major;
+ * complex128 in OSM_FP64, complex64 in OSM_C32_REFINE: the complements are
+ * formed and inverted in FP64 either way, the inverses rounded to FP32 for
+ * storage in the latter) of that y-line's Schur complement, sum_j ny nx_j^2
+ * elements.
  * With A_a the block of y-line a and B_a its coupling to y-line a+1, and
  * middle y-line m = (ny-1)/2: y-lines a < m hold T_a^{-1} (T_0 = A_0, T_a =
  * A_a - B_{a-1}^T T_{a-1}^{-1} B_{a-1}), y-lines a > m hold U_a^{-1} (U_{ny-1}
  * = A_{ny-1}, U_a = A_a - B_a U_{a+1}^{-1} B_a^T), y-line m the inverse of
  * A_m - B_{m-1}^T T_{m-1}^{-1} B_{m-1} - B_m U_{m+1}^{-1} B_m^T.  OSM_ESTATE
  * when the handle keeps no y-line factor or has not factored. */
-osm_status osm_get_yfactor(osm_handle *h, osm_c64 *dst_dev);
+osm_status osm_get_yfactor(osm_handle *h, void *dst_dev);
 
 /* Kernel timing for measurement: enable = 1 resets the counters and brackets
  * every later launch of the strip-solve kernel with HIP events on the

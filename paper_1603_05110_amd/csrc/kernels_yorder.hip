@@ -13,8 +13,12 @@
 // m = (ny - 1) / 2 are eliminated from a = 0 up (T_a = A_a - B_{a-1}^T
 // T_{a-1}^{-1} B_{a-1}), those above from a = ny - 1 down (U_a = A_a - B_a
 // U_{a+1}^{-1} B_a^T), and the middle line takes both terms.  The stored
-// factor is the inverse of every complement (nx x nx, FP64), nx^2 per y-line
-// instead of the ny^2 per node-line of the node-line order.  The
+// factor is the inverse of every complement (nx x nx), nx^2 per y-line
+// instead of the ny^2 per node-line of the node-line order.  The complements
+// are formed and inverted in FP64; the inverses are stored in FP64, or in
+// complex FP32 for the complex-FP32-with-refinement precision (the solve
+// then multiplies in FP64 by rounded inverses, and the FP64 residual of the
+// fixed point refines, as with the node-line order's FP32 factors).  The
 // complements are complex symmetric with a positive-definite imaginary part
 // (that of K_j, 2/dt M + c p M^Gamma, is; z^* S z for a Schur complement S
 // equals w^* K w for a w whose last block is z), so Gauss-Jordan needs no
@@ -29,6 +33,7 @@
 #include "osm_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 namespace {
@@ -46,6 +51,17 @@ __device__ __forceinline__ double2 yfma(double2 a, double2 b, double2 c) {
     return cd(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
 }
 __device__ __forceinline__ double2 yneg(double2 a) { return cd(-a.x, -a.y); }
+// stored inverse entries: FP64 or complex FP32, used in FP64.  A complex
+// FP32 block keeps its rows at an even stride (the last column of an odd
+// order padded with zero) so that the solve reads whole 16-byte pairs.
+template <typename E>
+__host__ __device__ constexpr int yld(int n) { return sizeof(E) == 8 ? (n + 1) & ~1 : n; }
+__device__ __forceinline__ double2 y2d(double2 v) { return v; }
+__device__ __forceinline__ double2 y2d(float2 v) { return cd((double)v.x, (double)v.y); }
+__device__ __forceinline__ void yput(double2 *p, double2 v) { *p = v; }
+__device__ __forceinline__ void yput(float2 *p, double2 v) {
+    *p = make_float2((float)v.x, (float)v.y);
+}
 // c ? a : b, component-wise (a conditional on the struct itself selects
 // between addresses and keeps the values out of registers)
 __device__ __forceinline__ double2 ysel(bool c, double2 a, double2 b) {
@@ -318,15 +334,16 @@ __device__ __forceinline__ void yf_invert(double2 (&c)[T][T], const YFLds<T> &L,
     __syncthreads();
 }
 
-template <int T>
-__device__ __forceinline__ void yf_store(const double2 (&c)[T][T], double2 *out, int n, int tr,
+template <int T, typename E>
+__device__ __forceinline__ void yf_store(const double2 (&c)[T][T], E *out, int n, int tr,
                                          int tc) {
+    const int ld = yld<E>(n);   // ld <= NP: an odd n is below NP
 #pragma unroll
     for (int a = 0; a < T; ++a)
 #pragma unroll
         for (int cc = 0; cc < T; ++cc) {
             const int i = tr + 16 * a, k = tc + 16 * cc;
-            if (i < n && k < n) out[i * n + k] = c[a][cc];
+            if (i < n && k < ld) yput(out + i * ld + k, k < n ? c[a][cc] : yz());
         }
 }
 
@@ -337,15 +354,15 @@ __device__ __forceinline__ void yf_init(const YFLds<T> &L) {
 }
 
 // The two halves of every strip: blockIdx.x = 2 j + half.
-template <int T>
+template <int T, typename E>
 __global__ __launch_bounds__(YF_THREADS) void yfactor_half_kernel(const YStrip *ys, int ny,
                                                                   const double2 *Dc,
-                                                                  const double2 *Uc, double2 *YF,
+                                                                  const double2 *Uc, E *YF,
                                                                   double2 *YB) {
     constexpr int NP = 16 * T;
     const int j = blockIdx.x >> 1, half = blockIdx.x & 1;
     const YStrip S = ys[j];
-    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    const int n = S.nx, nn = n * yld<E>(n), m = (ny - 1) / 2;
     extern __shared__ double2 ylds[];
     const YFLds<T> L = yf_lds<T>(ylds);
     const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
@@ -384,14 +401,14 @@ __global__ __launch_bounds__(YF_THREADS) void yfactor_half_kernel(const YStrip *
 
 // The middle line of every strip: C = A_m - B_{m-1}^T T_{m-1}^{-1} B_{m-1}
 // - B_m U_{m+1}^{-1} B_m^T (the terms present), inverted.
-template <int T>
+template <int T, typename E>
 __global__ __launch_bounds__(YF_THREADS) void yfactor_mid_kernel(const YStrip *ys, int ny,
                                                                  const double2 *Dc,
-                                                                 const double2 *Uc, double2 *YF,
+                                                                 const double2 *Uc, E *YF,
                                                                  double2 *YB) {
     constexpr int NP = 16 * T;
     const YStrip S = ys[blockIdx.x];
-    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    const int n = S.nx, ld = yld<E>(n), nn = n * ld, m = (ny - 1) / 2;
     extern __shared__ double2 ylds[];
     const YFLds<T> L = yf_lds<T>(ylds);
     const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
@@ -410,10 +427,10 @@ __global__ __launch_bounds__(YF_THREADS) void yfactor_mid_kernel(const YStrip *y
         const int ag = side == 0 ? m - 1 : m + 1;       // neighbouring complement
         if (ag < 0 || ag >= ny) continue;
         yf_coef_put(yf_coef_load(S, ny, m, ab, Dc, Uc), S, ab, NP, L.cb, YB);
-        const double2 *src = YF + S.yoff + (long)ag * nn;
+        const E *src = YF + S.yoff + (long)ag * nn;
         for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {
             const int i = e / NP, k = e % NP;
-            L.gl[e] = (i < n && k < n) ? src[i * n + k] : cd(i == k ? 1.0 : 0.0, 0.0);
+            L.gl[e] = (i < n && k < n) ? y2d(src[i * ld + k]) : cd(i == k ? 1.0 : 0.0, 0.0);
         }
         __syncthreads();
         yf_sandwich(c, L, tr, tc, side);
@@ -439,9 +456,13 @@ int yf_t(int max_nx) { return max_nx <= 32 ? 2 : (max_nx <= 48 ? 3 : 4); }
 // YS_DEPTH - 1 steps are loaded while the current one computes.
 constexpr int YS_DEPTH = 4;
 
-template <int NR>
+// FP64 storage: g[r] = G[q][i], q = qs + 8 r, r < NR.  Complex FP32
+// storage: g[r] = (G[i][q], G[i][q + 1]), q = 2 qs + 16 r, r < NR / 2 (row
+// i read along its row: the inverse is symmetric), half the loads.
+template <int NR, typename E>
 struct YStage {
-    double2 g[NR];
+    static constexpr int NL = sizeof(E) == 16 ? NR : NR / 2;
+    typename std::conditional<sizeof(E) == 16, double2, float4>::type g[NL];
     double2 ex;     // this lane's coefficient or right-hand-side value
 };
 
@@ -458,13 +479,15 @@ __device__ __forceinline__ double2 ys_gsum2(double2 v) { return cd(ys_gsum(v.x),
 // Buffer resource over one inverse (n^2 complex values): a lane whose
 // offset lies past it reads zeros without a memory request.  The base and
 // size are the same in every lane (scalar registers).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t ys_block(const double2 *G, int nn) {
+template <typename E>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t ys_block(const E *G, int nn) {
     const unsigned long long b = reinterpret_cast<unsigned long long>(G);
     const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
     const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
     void *p = reinterpret_cast<void *>(((unsigned long long)hi << 32) | lo);
     return __builtin_amdgcn_make_buffer_rsrc(p, (short)0,
-                                             __builtin_amdgcn_readfirstlane(nn * 16), 0x00020000);
+                                             __builtin_amdgcn_readfirstlane(nn * (int)sizeof(E)),
+                                             0x00020000);
 }
 
 // Loads of one step, all unconditional (a load under a branch would make
@@ -473,18 +496,25 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t ys_block(const double2 *G, int
 // value from an index clamped into its array (rows i >= n are never
 // stored).  yb: the step's coupling block (y-line-major), tr = 1 for the
 // product with B, 0 for B^T; src: the right-hand side's packed lines.
-template <int NR>
-__device__ __forceinline__ void ys_load(YStage<NR> &s, const double2 *G, const double2 *yb,
+template <int NR, typename E>
+__device__ __forceinline__ void ys_load(YStage<NR, E> &s, const E *G, const double2 *yb,
                                         const double2 *src, long off, int ny, int a, int n, int i,
                                         int qs, int tr) {
     const int ic = min(i, n - 1), im = max(ic - 1, 0);
-    const __amdgpu_buffer_rsrc_t rs = ys_block(G, n * n);
+    const int ld = yld<E>(n);
+    const __amdgpu_buffer_rsrc_t rs = ys_block(G, n * ld);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int q = qs + 8 * r;
-        const unsigned bo = (q < n && i < n) ? (unsigned)(q * n + i) * 16u : 0xFFFFFFF0u;
+    for (int r = 0; r < YStage<NR, E>::NL; ++r) {
+        unsigned bo;
+        if constexpr (sizeof(E) == 16) {
+            const int q = qs + 8 * r;
+            bo = (q < n && i < n) ? (unsigned)(q * n + i) * 16u : 0xFFFFFFF0u;
+        } else {   // q even and ld even: the pair lies within row i
+            const int q = 2 * qs + 16 * r;
+            bo = (q < ld && i < n) ? (unsigned)(i * ld + q) * 8u : 0xFFFFFFF0u;
+        }
         const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, bo, 0, 0);
-        __builtin_memcpy(&s.g[r], &v, sizeof(double2));
+        __builtin_memcpy(&s.g[r], &v, 16);
     }
     // (B t)_i = B[i][i] t_i + B[i][i+1] t_{i+1} + B[i][i-1] t_{i-1} and
     // (B^T t)_i = B[i][i] t_i + B[i+1][i] t_{i+1} + B[i-1][i] t_{i-1}, with
@@ -495,13 +525,22 @@ __device__ __forceinline__ void ys_load(YStage<NR> &s, const double2 *G, const d
 }
 
 // This lane's product over its q slice: sum_r G[q][i] v[q].
-template <int NR>
-__device__ __forceinline__ double2 ys_partial(const YStage<NR> &s, const double2 *v, int qs) {
+template <int NR, typename E>
+__device__ __forceinline__ double2 ys_partial(const YStage<NR, E> &s, const double2 *v, int qs) {
     double2 a0 = yz(), a1 = yz();
+    if constexpr (sizeof(E) == 16) {
 #pragma unroll
-    for (int r = 0; r < NR; r += 2) {
-        a0 = yfma(s.g[r], v[qs + 8 * r], a0);
-        a1 = yfma(s.g[r + 1], v[qs + 8 * (r + 1)], a1);
+        for (int r = 0; r < NR; r += 2) {
+            a0 = yfma(s.g[r], v[qs + 8 * r], a0);
+            a1 = yfma(s.g[r + 1], v[qs + 8 * (r + 1)], a1);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR / 2; ++r) {
+            const int q = 2 * qs + 16 * r;
+            a0 = yfma(cd((double)s.g[r].x, (double)s.g[r].y), v[q], a0);
+            a1 = yfma(cd((double)s.g[r].z, (double)s.g[r].w), v[q + 1], a1);
+        }
     }
     return cd(a0.x + a1.x, a0.y + a1.y);
 }
@@ -509,8 +548,8 @@ __device__ __forceinline__ double2 ys_partial(const YStage<NR> &s, const double2
 // rhs - (coupling product)_i from the row's lanes; tl holds the product's
 // input vector at tl[1 + j] (tl[0] = 0 for j = -1).  with_rhs = 0 leaves
 // the right-hand side out.
-template <int NR>
-__device__ __forceinline__ double2 ys_couple(const YStage<NR> &s, const double2 *tl, int i, int qs,
+template <int NR, typename E>
+__device__ __forceinline__ double2 ys_couple(const YStage<NR, E> &s, const double2 *tl, int i, int qs,
                                             bool with_rhs) {
     const int j = qs == 2 ? i + 1 : (qs == 3 ? i - 1 : i);
     const double2 t = tl[1 + min(j, 63)];
@@ -541,11 +580,11 @@ constexpr unsigned YP_SPINS = 1u << 14;
 // the 64 (NR - 1) loading threads, and one coupling coefficient
 constexpr int yp_q(int nr) { return (nr * nr + nr - 2) / (nr - 1) + 1; }
 
-template <bool FWD, int NR>
-__device__ void ys_helper(const YStrip &S, int ny, int half, const double2 *YF,
+template <bool FWD, int NR, typename E>
+__device__ void ys_helper(const YStrip &S, int ny, int half, const E *YF,
                           const double2 *YB, unsigned long long *prog, unsigned long long base) {
     constexpr int YP_Q = yp_q(NR), NL = 64 * (NR - 1);
-    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    const int n = S.nx, nn = n * yld<E>(n), m = (ny - 1) / 2;
     const int a0 = FWD ? (half == 0 ? 0 : ny - 1) : (half == 0 ? m - 1 : m + 1);
     const int da = FWD ? (half == 0 ? 1 : -1) : (half == 0 ? -1 : 1);
     const int steps = half == 0 ? m : ny - 1 - m;
@@ -560,9 +599,9 @@ __device__ void ys_helper(const YStrip &S, int ny, int half, const double2 *YF,
         const int a = a0 + min(k, steps - 1) * da;
         const int ag = FWD ? (k > 0 ? a - da : a) : a;
         const int ab = max(FWD ? (half == 0 ? a - 1 : a) : (half == 0 ? a : a - 1), 0);
-        const double2 *G = YF + S.yoff + (long)ag * nn;
+        const E *G = YF + S.yoff + (long)ag * nn;
 #pragma unroll
-        for (int q = 0; q < YP_Q - 1; ++q) r[q] = G[min(lt + NL * q, nn - 1)].x;
+        for (int q = 0; q < YP_Q - 1; ++q) r[q] = (double)G[min(lt + NL * q, nn - 1)].x;
         r[YP_Q - 1] = YB[S.boff + (long)ab * 3 * n + min(lt, 3 * n - 1)].x;
     };
     auto fold = [&](const double (&r)[YP_Q]) {
@@ -607,9 +646,9 @@ __device__ void ys_helper(const YStrip &S, int ny, int half, const double2 *YF,
 // v_{a+1} for a = ny - 1 .. m + 1; w and v are written over x.  Step k
 // (a = a0 + k da) multiplies by the inverse of y-line a - da and coupling
 // block a - 1 (lower, B^T) or a (upper, B).
-template <int NR>
+template <int NR, typename E>
 __global__ __launch_bounds__(64 * NR) void ysolve_fwd_kernel(
-    const YStrip *ys, int ny, const double2 *YF, const double2 *YB, const double2 *b, double2 *x,
+    const YStrip *ys, int ny, const E *YF, const double2 *YB, const double2 *b, double2 *x,
     const StepCtl *c, int *ran, int nchain, unsigned long long *prog, unsigned long long epoch) {
     if (yidle(c)) return;
     const int h0 = (nchain + 7) & ~7;
@@ -617,14 +656,14 @@ __global__ __launch_bounds__(64 * NR) void ysolve_fwd_kernel(
     if ((int)blockIdx.x >= nchain) {
         const int ch = (int)blockIdx.x - h0;
         if (ch >= 0 && ch < nchain)
-            ys_helper<true, NR>(ys[ch >> 1], ny, ch & 1, YF, YB, prog + ch, base);
+            ys_helper<true, NR, E>(ys[ch >> 1], ny, ch & 1, YF, YB, prog + ch, base);
         return;
     }
     if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
     unsigned long long *my = prog + blockIdx.x;
     const int j = blockIdx.x >> 1, half = blockIdx.x & 1;
     const YStrip S = ys[j];
-    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    const int n = S.nx, nn = n * yld<E>(n), m = (ny - 1) / 2;
     const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * 8 + (lane >> 3), qs = lane & 7;
     __shared__ double2 v[64], tl[66];
     const int a0 = half == 0 ? 0 : ny - 1, da = half == 0 ? 1 : -1;
@@ -634,14 +673,14 @@ __global__ __launch_bounds__(64 * NR) void ysolve_fwd_kernel(
     if (threadIdx.x < 66) tl[threadIdx.x] = yz();
     // step k's data; steps past the end reload the last one (unused), step
     // 0 has no product and points G and yb at y-line 0's (unused)
-    auto load = [&](YStage<NR> &st, int k) {
+    auto load = [&](YStage<NR, E> &st, int k) {
         k = min(k, steps - 1);
         const int a = a0 + k * da;
         const int ag = k > 0 ? a - da : 0, ab = k > 0 ? (half == 0 ? a - 1 : a) : 0;
         ys_load(st, YF + S.yoff + (long)ag * nn, YB + S.boff + (long)ab * 3 * n, b, S.off, ny,
                 a, n, i, qs, tr);
     };
-    auto step = [&](const YStage<NR> &st, int k) {
+    auto step = [&](const YStage<NR, E> &st, int k) {
         const int a = a0 + k * da;
         if (k > 0) {
             const double2 t = ys_gsum2(ys_partial(st, v, qs));
@@ -656,7 +695,7 @@ __global__ __launch_bounds__(64 * NR) void ysolve_fwd_kernel(
         *my = base + (unsigned long long)(k + 1);   // progress, for the helper
         __syncthreads();
     };
-    YStage<NR> s0, s1, s2, s3;
+    YStage<NR, E> s0, s1, s2, s3;
     load(s0, 0);
     load(s1, 1);
     load(s2, 2);
@@ -680,9 +719,9 @@ __global__ __launch_bounds__(64 * NR) void ysolve_fwd_kernel(
 // down to 0, upper x_a = U_a^{-1}(v_a - B_{a-1}^T x_{a-1}) for a = m + 1 up.
 // Step k (a = a0 + k da) multiplies by the inverse of y-line a, coupling
 // block a (lower, B) or a - 1 (upper, B^T), and reads w_a / v_a from x.
-template <int NR>
+template <int NR, typename E>
 __global__ __launch_bounds__(64 * NR) void ysolve_bwd_kernel(
-    const YStrip *ys, int ny, const double2 *YF, const double2 *YB, double2 *x, const StepCtl *c,
+    const YStrip *ys, int ny, const E *YF, const double2 *YB, double2 *x, const StepCtl *c,
     int nchain, unsigned long long *prog, unsigned long long epoch) {
     if (yidle(c)) return;
     const int h0 = (nchain + 7) & ~7;
@@ -690,13 +729,13 @@ __global__ __launch_bounds__(64 * NR) void ysolve_bwd_kernel(
     if ((int)blockIdx.x >= nchain) {
         const int ch = (int)blockIdx.x - h0;
         if (ch >= 0 && ch < nchain)
-            ys_helper<false, NR>(ys[ch >> 1], ny, ch & 1, YF, YB, prog + ch, base);
+            ys_helper<false, NR, E>(ys[ch >> 1], ny, ch & 1, YF, YB, prog + ch, base);
         return;
     }
     unsigned long long *my = prog + blockIdx.x;
     const int j = blockIdx.x >> 1, half = blockIdx.x & 1;
     const YStrip S = ys[j];
-    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    const int n = S.nx, nn = n * yld<E>(n), m = (ny - 1) / 2;
     const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * 8 + (lane >> 3), qs = lane & 7;
     __shared__ double2 v[64], tl[66];
     const int a0 = half == 0 ? m - 1 : m + 1, da = half == 0 ? -1 : 1;
@@ -708,14 +747,14 @@ __global__ __launch_bounds__(64 * NR) void ysolve_bwd_kernel(
     // x_m, the start of both sweeps
     if (qs == 0 && i < n) tl[1 + i] = x[(long)(S.off + i) * ny + m];
     __syncthreads();
-    auto load = [&](YStage<NR> &st, int k) {
+    auto load = [&](YStage<NR, E> &st, int k) {
         k = min(k, steps - 1);   // past the end: the last step's data again (unused)
         const int a = a0 + k * da;
         const int ab = half == 0 ? a : a - 1;
         ys_load(st, YF + S.yoff + (long)a * nn, YB + S.boff + (long)ab * 3 * n, x, S.off, ny, a,
                 n, i, qs, tr);
     };
-    auto step = [&](const YStage<NR> &st, int k) {
+    auto step = [&](const YStage<NR, E> &st, int k) {
         const int a = a0 + k * da;
         const double2 r = ys_couple(st, tl, i, qs, true);
         if (qs == 0 && i < n) v[i] = r;
@@ -728,7 +767,7 @@ __global__ __launch_bounds__(64 * NR) void ysolve_bwd_kernel(
         *my = base + (unsigned long long)(k + 1);   // progress, for the helper
         __syncthreads();
     };
-    YStage<NR> s0, s1, s2, s3;
+    YStage<NR, E> s0, s1, s2, s3;
     load(s0, 0);
     load(s1, 1);
     load(s2, 2);
@@ -750,21 +789,21 @@ __global__ __launch_bounds__(64 * NR) void ysolve_bwd_kernel(
 // Middle line: x_m = M_m^{-1}(b_m - B_{m-1}^T T_{m-1}^{-1} w_{m-1} - B_m
 // U_{m+1}^{-1} v_{m+1}), the terms present; three products of one step
 // each, all their data loaded up front.
-template <int NR>
+template <int NR, typename E>
 __global__ __launch_bounds__(64 * NR) void ysolve_mid_kernel(const YStrip *ys, int ny,
-                                                                const double2 *YF,
+                                                                const E *YF,
                                                                 const double2 *YB,
                                                                 const double2 *b, double2 *x,
                                                                 const StepCtl *c) {
     if (yidle(c)) return;
     const YStrip S = ys[blockIdx.x];
-    const int n = S.nx, nn = n * n, m = (ny - 1) / 2;
+    const int n = S.nx, nn = n * yld<E>(n), m = (ny - 1) / 2;
     const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * 8 + (lane >> 3), qs = lane & 7;
     __shared__ double2 v[64], tl[66];
     if (threadIdx.x < 64) v[threadIdx.x] = yz();   // entries q >= n meet clamped G values
     if (threadIdx.x < 66) tl[threadIdx.x] = yz();
     const bool lo = m - 1 >= 0, hi = m + 1 < ny;
-    YStage<NR> sl, sh, sm;
+    YStage<NR, E> sl, sh, sm;
     // lower side: inverse of m - 1, coupling block m - 1 (B^T), w_{m-1} from
     // x; upper side: inverse of m + 1, coupling block m (B), v_{m+1} from x
     // (a missing side points at y-line m's data, unused); the middle
@@ -777,7 +816,7 @@ __global__ __launch_bounds__(64 * NR) void ysolve_mid_kernel(const YStrip *ys, i
     ys_load(sm, YF + S.yoff + (long)m * nn, YB + S.boff, b, S.off, ny, m, n, i, qs, 0);
     __syncthreads();
     double2 acc = yz();
-    auto side = [&](const YStage<NR> &st) {
+    auto side = [&](const YStage<NR, E> &st) {
         // the side's vector (the right-hand-side slot of its stage) into v
         if (qs == 6 && i < n) v[i] = st.ex;
         __syncthreads();
@@ -812,35 +851,41 @@ double yorder_factor_flops(int ny, int nx) {
     return (double)ny * 8.0 * (n * n * n + 6.0 * n * n);
 }
 
-hipError_t launch_yfactor(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
-                          const double2 *Dc, const double2 *Uc, double2 *YF, double2 *YB,
-                          hipEvent_t ev0, hipEvent_t ev1) {
-    hipError_t e;
-    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
+template <typename E>
+static hipError_t yfactor_typed(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
+                                const double2 *Dc, const double2 *Uc, E *YF, double2 *YB) {
     const size_t lds = yorder_factor_lds(max_nx);
     auto go = [&](auto half, auto mid) {
         hipLaunchKernelGGL(half, dim3(2 * nstrips), dim3(YF_THREADS), lds, st, ys, ny, Dc, Uc, YF,
                            YB);
         hipLaunchKernelGGL(mid, dim3(nstrips), dim3(YF_THREADS), lds, st, ys, ny, Dc, Uc, YF, YB);
     };
-    if (max_nx <= 32) go(yfactor_half_kernel<2>, yfactor_mid_kernel<2>);
-    else if (max_nx <= 48) go(yfactor_half_kernel<3>, yfactor_mid_kernel<3>);
-    else if (max_nx <= 64) go(yfactor_half_kernel<4>, yfactor_mid_kernel<4>);
+    if (max_nx <= 32) go(yfactor_half_kernel<2, E>, yfactor_mid_kernel<2, E>);
+    else if (max_nx <= 48) go(yfactor_half_kernel<3, E>, yfactor_mid_kernel<3, E>);
+    else if (max_nx <= 64) go(yfactor_half_kernel<4, E>, yfactor_mid_kernel<4, E>);
     else return hipErrorInvalidValue;
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_yfactor(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
+                          const double2 *Dc, const double2 *Uc, void *YF, int fp32, double2 *YB,
+                          hipEvent_t ev0, hipEvent_t ev1) {
+    hipError_t e;
+    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
+    e = fp32 ? yfactor_typed(st, ys, nstrips, ny, max_nx, Dc, Uc, (float2 *)YF, YB)
+             : yfactor_typed(st, ys, nstrips, ny, max_nx, Dc, Uc, (double2 *)YF, YB);
+    if (e != hipSuccess) return e;
     if (ev1) e = hipEventRecord(ev1, st);
     return e;
 }
 
-hipError_t launch_ysolve(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
-                         const double2 *YF, const double2 *YB, const double2 *b, double2 *x,
-                         const StepCtl *c, int *ran, unsigned long long *prog,
-                         unsigned long long *epoch, hipEvent_t ev0, hipEvent_t ev1) {
-    hipError_t e;
-    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
+template <typename E>
+static hipError_t ysolve_typed(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
+                               const E *YF, const double2 *YB, const double2 *b, double2 *x,
+                               const StepCtl *c, int *ran, unsigned long long *prog,
+                               unsigned long long ef, unsigned long long eb) {
     // chains 0 .. 2N-1, then (from the next multiple of 8) their helpers
     const int nchain = 2 * nstrips, grid = ((nchain + 7) & ~7) + nchain;
-    const unsigned long long ef = ++*epoch, eb = ++*epoch;
     auto go = [&](auto fwd, auto mid, auto bwd, int nr) {
         hipLaunchKernelGGL(fwd, dim3(grid), dim3(64 * nr), 0, st, ys, ny, YF, YB, b, x, c, ran,
                            nchain, prog, ef);
@@ -849,14 +894,28 @@ hipError_t launch_ysolve(hipStream_t st, const YStrip *ys, int nstrips, int ny, 
                            prog, eb);
     };
     if (max_nx <= 32)
-        go(ysolve_fwd_kernel<4>, ysolve_mid_kernel<4>, ysolve_bwd_kernel<4>, 4);
+        go(ysolve_fwd_kernel<4, E>, ysolve_mid_kernel<4, E>, ysolve_bwd_kernel<4, E>, 4);
     else if (max_nx <= 48)
-        go(ysolve_fwd_kernel<6>, ysolve_mid_kernel<6>, ysolve_bwd_kernel<6>, 6);
+        go(ysolve_fwd_kernel<6, E>, ysolve_mid_kernel<6, E>, ysolve_bwd_kernel<6, E>, 6);
     else if (max_nx <= 64)
-        go(ysolve_fwd_kernel<8>, ysolve_mid_kernel<8>, ysolve_bwd_kernel<8>, 8);
+        go(ysolve_fwd_kernel<8, E>, ysolve_mid_kernel<8, E>, ysolve_bwd_kernel<8, E>, 8);
     else
         return hipErrorInvalidValue;
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_ysolve(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
+                         const void *YF, int fp32, const double2 *YB, const double2 *b,
+                         double2 *x, const StepCtl *c, int *ran, unsigned long long *prog,
+                         unsigned long long *epoch, hipEvent_t ev0, hipEvent_t ev1) {
+    hipError_t e;
+    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
+    const unsigned long long ef = ++*epoch, eb = ++*epoch;
+    e = fp32 ? ysolve_typed(st, ys, nstrips, ny, max_nx, (const float2 *)YF, YB, b, x, c, ran,
+                            prog, ef, eb)
+             : ysolve_typed(st, ys, nstrips, ny, max_nx, (const double2 *)YF, YB, b, x, c, ran,
+                            prog, ef, eb);
+    if (e != hipSuccess) return e;
     if (ev1) e = hipEventRecord(ev1, st);
     return e;
 }

@@ -49,7 +49,8 @@ struct osm_handle {
     // y-lines' Schur complements, strip by strip
     int order = 0;                   // in use: 0 = node-line order (F), 1 = y-line order (YF)
     bool order_tuned = true;         // false until the autotuner has chosen
-    double2 *YF = nullptr, *YB = nullptr;
+    void *YF = nullptr;              // y-line inverses: double2, or float2 when fp32
+    double2 *YB = nullptr;
     YStrip *ys_d = nullptr;
     unsigned long long *yprog = nullptr;   // progress words of the solve's chains
     unsigned long long yepoch = 0;
@@ -276,7 +277,8 @@ struct Sizes {
     int fp32;
     int sym;    // the upper-triangle solve kernels are available (partials buffer)
     int yo;     // factors kept: 0 = node-line order, 1 = y-line order, 2 = both
-    long ysum;  // elements of the y-line-order factor: ny * sum_j nx_j^2
+    long ysum;  // elements of the y-line-order factor: ny * sum_j nx_j ld_j (ld_j = nx_j, or
+                // nx_j rounded up to even for complex FP32 storage)
     long ybsum; // its coupling coefficients: 3 ny * sum_j nx_j
 };
 
@@ -325,13 +327,12 @@ Sizes sizes_of(const osm_problem *p, const osm_options *o) {
     else if (o->strip_order == 2 && yorder_ok(p, c)) s.yo = 2;
     if (s.yo) {
         for (int v : c) {
-            s.ysum += (long)(v + 1) * (v + 1);
+            s.ysum += (long)(v + 1) * (s.fp32 ? (v + 2) & ~1 : v + 1);
             s.ybsum += v + 1;
         }
         s.ysum *= s.n;
         s.ybsum *= 3 * s.n;
     }
-    if (s.yo == 1) s.fp32 = 0;   // the y-line order is FP64 throughout
     s.sym = s.yo != 1 && sym_eligible(s.n, s.fp32);
     return s;
 }
@@ -340,7 +341,8 @@ uint64_t device_bytes(const Sizes &s) {
     uint64_t fe = s.fp32 ? 8 : 16;
     uint64_t b = 0;
     if (s.yo != 1) b += (uint64_t)s.Lt * s.n * s.n * fe;                     // factor
-    if (s.yo) b += (uint64_t)(s.ysum + s.ybsum) * 16 + (uint64_t)s.N * (sizeof(YStrip) + 16);  // y-line factor
+    if (s.yo) b += (uint64_t)s.ysum * fe + (uint64_t)s.ybsum * 16 +
+                   (uint64_t)s.N * (sizeof(YStrip) + 16);   // y-line factor
     b += 2ull * s.Lt * s.n * 3 * 16;                    // Dc, Uc
     b += (uint64_t)s.nglob * s.n * 8;                   // W
     b += 3ull * s.Lt * s.n * 16;                        // zeta, res, delta
@@ -483,8 +485,8 @@ osm_status do_factor(osm_handle *h) {
             osm_status s = fslot(h, fl, &e0, &e1);
             if (s != OSM_OK) return s;
         }
-        HIPCHK(h, launch_yfactor(h->st, h->ys_d, h->N, h->n, h->maxnx, h->Dc, h->Uc, h->YF, h->YB,
-                                 e0, e1));
+        HIPCHK(h, launch_yfactor(h->st, h->ys_d, h->N, h->n, h->maxnx, h->Dc, h->Uc, h->YF,
+                                 h->fp32, h->YB, e0, e1));
         if (h->order == 1) {
             h->factored = true;
             return OSM_OK;
@@ -513,10 +515,11 @@ osm_status do_factor(osm_handle *h) {
 // strip once), plus b, x and the coupling coefficients once.
 double single_solve_bytes(const osm_handle *h) {
     if (h->order == 1) {
-        // y-line order: 2 ny - 1 inverses of nx_j^2 FP64 values per strip
+        // y-line order: 2 ny - 1 inverses of nx_j^2 values per strip
+        const double ye = h->fp32 ? 8.0 : 16.0;
         double b = 0.0;
         for (const StripMeta &sm : h->strips_h)
-            b += (2.0 * h->n - 1.0) * (double)sm.nx * sm.nx * 16.0;
+            b += (2.0 * h->n - 1.0) * (double)sm.nx * sm.nx * ye;
         return b + (double)h->Lt * h->n * 80.0;
     }
     double es = h->fp32 ? 8.0 : 16.0;
@@ -571,8 +574,8 @@ osm_status do_solve(osm_handle *h, const double2 *b, double2 *x, const StepCtl *
             osm_status s = solve_slot(h, &e0, &e1, &ran);
             if (s != OSM_OK) return s;
         }
-        HIPCHK(h, launch_ysolve(h->st, h->ys_d, h->N, h->n, h->maxnx, h->YF, h->YB, b, x, ctl,
-                                ran, h->yprog, &h->yepoch, e0, e1));
+        HIPCHK(h, launch_ysolve(h->st, h->ys_d, h->N, h->n, h->maxnx, h->YF, h->fp32, h->YB, b,
+                                x, ctl, ran, h->yprog, &h->yepoch, e0, e1));
         return OSM_OK;
     }
     SolveArgs a;
@@ -1475,7 +1478,8 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
         SALLOC(h->ff_lines_d, int, h->maxnx);
         SALLOC(h->ff_first_d, int, h->maxnx);
         if (sz.yo) {
-            // y-line order: strip j's inverses start at yoff_j, ny nx_j^2 each
+            // y-line order: strip j's inverses start at yoff_j, ny nx_j ld_j each
+            // (rows at stride ld_j: nx_j, or nx_j rounded up to even in FP32)
             std::vector<YStrip> ys(h->N);
             long yo = 0, bo = 0;
             for (int j = 0; j < h->N; ++j) {
@@ -1483,10 +1487,11 @@ static osm_status setup_one(const osm_problem *prob, const osm_options *opt, hip
                 ys[j].nx = h->strips_h[j].nx;
                 ys[j].yoff = yo;
                 ys[j].boff = bo;
-                yo += (long)h->n * ys[j].nx * ys[j].nx;
+                yo += (long)h->n * ys[j].nx * (h->fp32 ? (ys[j].nx + 1) & ~1 : ys[j].nx);
                 bo += 3L * h->n * ys[j].nx;
             }
-            SALLOC(h->YF, double2, yo);
+            if (h->fp32) SALLOC(h->YF, float2, yo);
+            else SALLOC(h->YF, double2, yo);
             SALLOC(h->YB, double2, bo);
             SALLOC(h->yprog, unsigned long long, 2 * h->N);
             HIPCHK(h, hipMemset(h->yprog, 0, sizeof(unsigned long long) * 2 * h->N));
@@ -1771,7 +1776,6 @@ static osm_status autotune_order(osm_handle *h) {
         h->order_ms[o] = h->solve_ms / 3.0;
     }
     h->order = h->order_ms[1] < h->order_ms[0] ? 1 : 0;
-    if (h->order == 1) h->fp32 = 0;
     h->prof = prof;
     h->solve_ms = keep_ms;
     h->solve_launches = keep_n;
@@ -2042,17 +2046,24 @@ osm_status osm_get_factor(osm_handle *h, void *dst_dev) {
     return OSM_OK;
 }
 
-osm_status osm_get_yfactor(osm_handle *h, osm_c64 *dst_dev) {
+osm_status osm_get_yfactor(osm_handle *h, void *dst_dev) {
     if (!h) return OSM_EINVAL;
     SINGLE_ONLY(h);
     if (!dst_dev) return fail(h, OSM_EINVAL, "dst_dev is NULL");
     if (!h->factored) return fail(h, OSM_ESTATE, "osm_factor must be called first");
     if (!h->YF || h->order != 1)
         return fail(h, OSM_ESTATE, "the strip factor is not kept in y-line order");
-    long cnt = 0;
-    for (const StripMeta &sm : h->strips_h) cnt += (long)h->n * sm.nx * sm.nx;
-    HIPCHK(h, hipMemcpyAsync(dst_dev, h->YF, sizeof(double2) * (size_t)cnt,
-                             hipMemcpyDeviceToDevice, h->st));
+    // unpacked to nx_j x nx_j blocks (the stored rows may be padded)
+    const size_t fe = h->fp32 ? sizeof(float2) : sizeof(double2);
+    char *dst = (char *)dst_dev;
+    const char *src = (const char *)h->YF;
+    for (const StripMeta &sm : h->strips_h) {
+        const size_t nx = (size_t)sm.nx, ld = h->fp32 ? (nx + 1) & ~(size_t)1 : nx;
+        HIPCHK(h, hipMemcpy2DAsync(dst, nx * fe, src, ld * fe, nx * fe, (size_t)h->n * nx,
+                                   hipMemcpyDeviceToDevice, h->st));
+        dst += (size_t)h->n * nx * nx * fe;
+        src += (size_t)h->n * nx * ld * fe;
+    }
     HIPCHK(h, hipStreamSynchronize(h->st));
     return OSM_OK;
 }

@@ -227,7 +227,8 @@ size_t solve_pf_smem(int n, int fp32);
 
 // kernels_yorder.hip: the strip factor and solve in y-line order (the
 // strip's unknowns taken y-line by y-line: blocks of its nx node-lines,
-// block tridiagonal along the ny y-lines), twisted, FP64; Robin only.
+// block tridiagonal along the ny y-lines), twisted, formed in FP64; the
+// inverses stored in FP64 or (fp32) complex FP32; Robin only.
 #define YORDER_MAX_NX 64
 struct YStrip {
     int off;     // first packed line of the strip
@@ -240,9 +241,10 @@ size_t yorder_factor_lds(int max_nx);
 // algorithmic flops of factoring one strip (ny y-lines of nx unknowns)
 double yorder_factor_flops(int ny, int nx);
 // Dc, Uc: coefficients of every packed line (launch_coef layout); writes the
-// inverses (YF) and the coupling coefficients in y-line order (YB)
+// inverses (YF: double2, or float2 when fp32) and the coupling coefficients
+// in y-line order (YB)
 hipError_t launch_yfactor(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
-                          const double2 *Dc, const double2 *Uc, double2 *YF, double2 *YB,
+                          const double2 *Dc, const double2 *Uc, void *YF, int fp32, double2 *YB,
                           hipEvent_t ev0, hipEvent_t ev1);
 // x = K^{-1} b on every strip; skipped when c says the fixed point is done
 // (ran, when given, set to 1 otherwise); ev0/ev1 bracket the three kernels.
@@ -250,8 +252,8 @@ hipError_t launch_yfactor(hipStream_t st, const YStrip *ys, int nstrips, int ny,
 // helpers poll them), epoch: the host's launch counter for them (advanced
 // by two per call, below 2^44)
 hipError_t launch_ysolve(hipStream_t st, const YStrip *ys, int nstrips, int ny, int max_nx,
-                         const double2 *YF, const double2 *YB, const double2 *b, double2 *x,
-                         const StepCtl *c, int *ran, unsigned long long *prog,
+                         const void *YF, int fp32, const double2 *YB, const double2 *b,
+                         double2 *x, const StepCtl *c, int *ran, unsigned long long *prog,
                          unsigned long long *epoch, hipEvent_t ev0, hipEvent_t ev1);
 
 // kernels_control.hip

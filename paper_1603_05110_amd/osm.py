@@ -285,8 +285,8 @@ class OsmSolver:
     def get_yfactor(self):
         """The y-line-order factor, one (ny, nx_j, nx_j) tensor per strip."""
         nx = [int(c) + 1 for c in self.pb.strip_cells]
-        f = torch.empty(sum(self.ny * k * k for k in nx), dtype=torch.complex128,
-                        device=self.device)
+        dt = torch.complex64 if self._opt.prec == OSM_C32_REFINE else torch.complex128
+        f = torch.empty(sum(self.ny * k * k for k in nx), dtype=dt, device=self.device)
         self._c(_lib.osm_get_yfactor(self.h, _ptr(f)))
         out, o = [], 0
         for k in nx:

@@ -118,8 +118,6 @@ def test_c5_full_size_strip_solves_match_oracle():
             cells[j] + 1, pb.ncy + 1)
     for order in ("node", "y"):
         for prec, tol in (("fp64", 1e-12), ("c32", 2e-6)):
-            if order == "y" and prec == "c32":
-                continue    # the y-line order is FP64 whatever prec says
             log(f"  C5 strip solve, {order} order, {prec}")
             s = osm.OsmSolver(pb, DEV, algo="classical", prec=prec, strip_order=order)
             s.factor(torch.from_numpy(W).to(DEV))

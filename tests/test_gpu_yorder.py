@@ -12,6 +12,11 @@ along the ny y-lines) against the FP64 oracle.
   strips of 3 and of 64 node-lines (the limit) and uneven strips.
 * Converged steps (classical and preconditioned) against the monolithic
   oracle, the rotating-frame refactor, and the autotuned order.
+* Complex FP32 storage of the inverses (prec c32): the half-chain y-lines'
+  stored blocks are exactly the FP64 blocks rounded (the complements are
+  formed in FP64 either way), the middle line's within FP32 rounding; the
+  strip solve within FP32 accuracy; converged steps to the FP64 bar, the
+  fixed point's FP64 residual refining.
 """
 import sys
 
@@ -65,18 +70,33 @@ def strip_matrix_y(orc, j):
     return K[np.ix_(perm, perm)], nx
 
 
-@pytest.mark.parametrize("ncy,cells", [(9, (3, 5, 4)), (10, (4, 2, 6)), (2, (3, 3))])
-def test_factor_blocks_are_inverses_of_schur_complements(ncy, cells):
-    log(f"y-order factor blocks ny={ncy + 1} cells={cells}")
+def _yfactor(pb, W, prec):
     osm = _osm()
-    pb = problem(sum(cells), ncy, cells)
-    W = potential(pb, 3)
-    orc = SchwarzOracle(pb, W)
-    s = osm.OsmSolver(pb, DEV, strip_order="y")
+    s = osm.OsmSolver(pb, DEV, strip_order="y", prec=prec)
     s.factor(to_dev(W))
     assert s.strip_order() == "y"
     got = [f.cpu().numpy() for f in s.get_yfactor()]
     s.close()
+    return got
+
+
+@pytest.mark.parametrize("prec", ["fp64", "c32"])
+@pytest.mark.parametrize("ncy,cells", [(9, (3, 5, 4)), (10, (4, 2, 6)), (2, (3, 3))])
+def test_factor_blocks_are_inverses_of_schur_complements(ncy, cells, prec):
+    log(f"y-order factor blocks ny={ncy + 1} cells={cells} {prec}")
+    pb = problem(sum(cells), ncy, cells)
+    W = potential(pb, 3)
+    orc = SchwarzOracle(pb, W)
+    got = _yfactor(pb, W, prec)
+    if prec == "c32":
+        assert got[0].dtype == np.complex64
+        g64 = _yfactor(pb, W, "fp64")
+        m = pb.ncy // 2
+        for j in range(pb.nsub):
+            for a in range(pb.ncy + 1):
+                if a != m:   # the chains never read their stored blocks back
+                    assert np.array_equal(got[j][a], g64[j][a].astype(np.complex64)), (j, a)
+    tol = 1e-12 if prec == "fp64" else 1e-6
     ny, m = pb.ncy + 1, pb.ncy // 2
     for j in range(pb.nsub):
         Ky, nx = strip_matrix_y(orc, j)
@@ -89,14 +109,16 @@ def test_factor_blocks_are_inverses_of_schur_complements(ncy, cells):
                 want = sub[:nx, :nx]
             else:
                 want = np.linalg.inv(Ky)[a * nx:(a + 1) * nx, a * nx:(a + 1) * nx]
-            assert rel(got[j][a], want) < 1e-12, (j, a)
+            assert rel(got[j][a], want) < tol, (j, a)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "c32"])
 @pytest.mark.parametrize("ncx,ncy,cells", [(30, 99, (9, 12, 9)), (20, 128, (10, 10)),
                                            (24, 64, (5, 7, 6, 6)), (6, 2, (2, 2, 2)),
                                            (70, 40, (63, 7))])
-def test_strip_solve_matches_oracle(ncx, ncy, cells):
-    log(f"y-order strip solve {ncx}x{ncy} {cells}")
+def test_strip_solve_matches_oracle(ncx, ncy, cells, prec):
+    log(f"y-order strip solve {ncx}x{ncy} {cells} {prec}")
+    tol = 1e-12 if prec == "fp64" else 1e-5
     osm = _osm()
     pb = problem(ncx, ncy, cells)
     W = potential(pb, 1)
@@ -106,17 +128,18 @@ def test_strip_solve_matches_oracle(ncx, ncy, cells):
           for c in cells]
     ref = [orc._lu[j].solve(bs[j].ravel()).reshape(bs[j].shape) for j in range(len(cells))]
     want = np.concatenate(ref)
-    s = osm.OsmSolver(pb, DEV, strip_order="y")
+    s = osm.OsmSolver(pb, DEV, strip_order="y", prec=prec)
     s.factor(to_dev(W))
     x = s.strip_solve(to_dev(np.concatenate(bs))).cpu().numpy()
     s.close()
     assert np.all(np.isfinite(x))
-    assert rel(x, want) < 1e-12
+    log(f"  rel {rel(x, want):.2e}")
+    assert rel(x, want) < tol
     o = 0
     for j, c in enumerate(cells):
-        assert rel(x[o:o + c + 1], ref[j]) < 1e-12, j
+        assert rel(x[o:o + c + 1], ref[j]) < tol, j
         o += c + 1
-    assert np.max(np.abs(x - want)) < 1e-12 * np.max(np.abs(want))
+    assert np.max(np.abs(x - want)) < tol * np.max(np.abs(want))
 
 
 def smooth_problem():
@@ -130,14 +153,15 @@ def smooth_problem():
     return pb, u, 0.5 * np.sin(X) * np.cos(Y)
 
 
-@pytest.mark.parametrize("algo,order", [("classical", "y"), ("precond", "y"),
-                                        ("precond", "tuned")])
-def test_converged_steps_match_monolithic(algo, order):
-    log(f"y-order converged steps {algo} {order}")
+@pytest.mark.parametrize("algo,order,prec", [("classical", "y", "c32"), ("precond", "y", "c32"),
+                                             ("precond", "tuned", "c32"),
+                                             ("precond", "y", "fp64")])
+def test_converged_steps_match_monolithic(algo, order, prec):
+    log(f"y-order converged steps {algo} {order} {prec}")
     osm = _osm()
     pb, u, W = smooth_problem()
     ref = run_monolithic(pb, u, W, 3, tol_q=1e-14)
-    s = osm.OsmSolver(pb, DEV, algo=algo, prec="c32", tol_k=1e-12, tol_k_relative=True,
+    s = osm.OsmSolver(pb, DEV, algo=algo, prec=prec, tol_k=1e-12, tol_k_relative=True,
                       tol_q=1e-14, max_k=4000, strip_order=order)
     s.factor(to_dev(W))
     log(f"  order in use: {s.strip_order()}")
@@ -145,14 +169,15 @@ def test_converged_steps_match_monolithic(algo, order):
     for _ in range(3):
         st = s.step(ud)
         log(f"  k={st['k']} q={st['q_total']} gmres={st['gmres_total']}")
-        if s.strip_order() == "y":
-            assert st["refine_total"] == 0      # FP64 solves: nothing to refine
+        # the fixed point refines the FP32-stored factors; nothing with FP64
+        assert st["refine_total"] == (st["q_total"] if prec == "c32" else 0)
     s.close()
     assert rel(ud.cpu().numpy(), ref) < 1e-10
 
 
-def test_rotating_frame_refactor_every_step_matches_oracle():
-    log("y-order rotating frame")
+@pytest.mark.parametrize("prec", ["fp64", "c32"])
+def test_rotating_frame_refactor_every_step_matches_oracle(prec):
+    log(f"y-order rotating frame {prec}")
     from oracle.rotating import step_potential
     from workloads import gaussian_boost
     osm = _osm()
@@ -162,7 +187,7 @@ def test_rotating_frame_refactor_every_step_matches_oracle():
     steps = 4
     ref = run_monolithic(pb, u0, lambda n: step_potential(pb, n), steps, tol_q=1e-14)
     s = osm.OsmSolver(pb, DEV, algo="precond", tol_k=1e-12, tol_k_relative=True, tol_q=1e-14,
-                      strip_order="y")
+                      strip_order="y", prec=prec)
     ud = to_dev(u0)
     for n in range(1, steps + 1):
         s.factor_rotating(n)
