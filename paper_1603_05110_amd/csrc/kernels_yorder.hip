@@ -444,37 +444,59 @@ __global__ __launch_bounds__(YF_THREADS) void yfactor_mid_kernel(const YStrip *y
 int yf_t(int max_nx) { return max_nx <= 32 ? 2 : (max_nx <= 48 ? 3 : 4); }
 
 // ---------------------------------------------------------------- solve
-// One workgroup of NR waves per strip half, NR = ceil(max nx / 8) (4, 6 or
-// 8, a template parameter).  Wave w owns rows i = 8 w +
-// (lane >> 3) of the strip's y-line vectors; the 8 lanes of a row (slice
-// qs = lane & 7) hold the entries G[q][i], q = qs + 8 r, r < NR, of the inverse a
-// step multiplies by (G is symmetric, so these are row i's terms), and one
-// more value of row i each: qs 1 the coupling block's diagonal, qs 2 its
-// entry towards row i + 1, qs 3 the one towards row i - 1 (for the
-// product with B^T or with B), qs 6 the right-hand side.  A row's sums are
-// formed within its 8 lanes by DPP; rows meet in LDS.  The data of the next
-// YS_DEPTH - 1 steps are loaded while the current one computes.
+// One workgroup per strip half covers 8 NR rows, NR = ceil(max nx / 8) (4,
+// 6 or 8, a template parameter).  LPR lanes serve a row: 8 with FP64
+// storage, 4 with complex FP32 storage (16-byte loads carry two entries
+// there), so a wave owns 64 / LPR rows and the workgroup has NR LPR / 8
+// waves.  Lane slice qs = lane % LPR of row i holds the entries of the
+// inverse G the step multiplies by: FP64, G[q][i] for q = qs + 8 r (G is
+// symmetric, so these are row i's terms); FP32, the pairs (G[i][q],
+// G[i][q+1]) for q = 2 qs + 8 r; r < NR either way.  It also holds one more
+// value of row i: qs 1 the coupling block's diagonal, qs 2 its entry towards
+// row i + 1, qs 3 the one towards row i - 1 (for the product with B^T or
+// with B), qs YQ_RHS the right-hand side.  A row's sums are formed within
+// its lanes by DPP; rows meet in LDS.  The data of the next YS_DEPTH - 1
+// steps are loaded while the current one computes.  Halving the waves with
+// FP32 storage halves the instructions the busiest SIMD issues per step (a
+// step is a few hundred instructions of dependent arithmetic, group sums and
+// LDS traffic between two barriers).
 constexpr int YS_DEPTH = 4;
+template <typename E>
+__host__ __device__ constexpr int ylpr() { return sizeof(E) == 8 ? 4 : 8; }
+template <typename E>
+__host__ __device__ constexpr int yq_rhs() { return sizeof(E) == 8 ? 0 : 6; }
+template <int NR, typename E>
+__host__ __device__ constexpr int ywaves() { return NR * ylpr<E>() / 8; }
 
-// FP64 storage: g[r] = G[q][i], q = qs + 8 r, r < NR.  Complex FP32
-// storage: g[r] = (G[i][q], G[i][q + 1]), q = 2 qs + 16 r, r < NR / 2 (row
-// i read along its row: the inverse is symmetric), half the loads.
 template <int NR, typename E>
 struct YStage {
-    static constexpr int NL = sizeof(E) == 16 ? NR : NR / 2;
-    typename std::conditional<sizeof(E) == 16, double2, float4>::type g[NL];
+    typename std::conditional<sizeof(E) == 16, double2, float4>::type g[NR];
     double2 ex;     // this lane's coefficient or right-hand-side value
 };
 
-// Sum over the 8 lanes of a row group (quad swaps, then the half-row
-// mirror), in every lane of the group.  Every lane of the wave must be active.
+// Sum over the LPR lanes of a row group (quad swaps, then for 8 lanes the
+// half-row mirror), in every lane of the group.  Every lane of the wave must
+// be active.
+// (Every source lane of these patterns is valid, so the moves need no old
+// value: no register is zeroed before each.)
+template <int CTRL>
+__device__ __forceinline__ double ydpp(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int LPR>
 __device__ __forceinline__ double ys_gsum(double v) {
-    v += dpp_f64<0xB1>(v);     // quad_perm [1,0,3,2]
-    v += dpp_f64<0x4E>(v);     // quad_perm [2,3,0,1]
-    v += dpp_f64<0x141>(v);    // row_half_mirror
+    v += ydpp<0xB1>(v);     // quad_perm [1,0,3,2]
+    v += ydpp<0x4E>(v);     // quad_perm [2,3,0,1]
+    if constexpr (LPR == 8) v += ydpp<0x141>(v);    // row_half_mirror
     return v;
 }
-__device__ __forceinline__ double2 ys_gsum2(double2 v) { return cd(ys_gsum(v.x), ys_gsum(v.y)); }
+template <int LPR>
+__device__ __forceinline__ double2 ys_gsum2(double2 v) {
+    return cd(ys_gsum<LPR>(v.x), ys_gsum<LPR>(v.y));
+}
 
 // Buffer resource over one inverse (n^2 complex values): a lane whose
 // offset lies past it reads zeros without a memory request.  The base and
@@ -504,13 +526,13 @@ __device__ __forceinline__ void ys_load(YStage<NR, E> &s, const E *G, const doub
     const int ld = yld<E>(n);
     const __amdgpu_buffer_rsrc_t rs = ys_block(G, n * ld);
 #pragma unroll
-    for (int r = 0; r < YStage<NR, E>::NL; ++r) {
+    for (int r = 0; r < NR; ++r) {
         unsigned bo;
         if constexpr (sizeof(E) == 16) {
             const int q = qs + 8 * r;
             bo = (q < n && i < n) ? (unsigned)(q * n + i) * 16u : 0xFFFFFFF0u;
         } else {   // q even and ld even: the pair lies within row i
-            const int q = 2 * qs + 16 * r;
+            const int q = 2 * qs + 8 * r;
             bo = (q < ld && i < n) ? (unsigned)(i * ld + q) * 8u : 0xFFFFFFF0u;
         }
         const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, bo, 0, 0);
@@ -520,7 +542,7 @@ __device__ __forceinline__ void ys_load(YStage<NR, E> &s, const E *G, const doub
     // (B^T t)_i = B[i][i] t_i + B[i+1][i] t_{i+1} + B[i-1][i] t_{i-1}, with
     // B[l][l+1] at yb[n + l] and B[l+1][l] at yb[2n + l]
     const int ci = qs == 2 ? (tr ? n : 2 * n) + ic : (qs == 3 ? (tr ? 2 * n : n) + im : ic);
-    const double2 *p = qs == 6 ? src + (off + ic) * ny + a : yb + ci;
+    const double2 *p = qs == yq_rhs<E>() ? src + (off + ic) * ny + a : yb + ci;
     s.ex = *p;
 }
 
@@ -536,8 +558,8 @@ __device__ __forceinline__ double2 ys_partial(const YStage<NR, E> &s, const doub
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < NR / 2; ++r) {
-            const int q = 2 * qs + 16 * r;
+        for (int r = 0; r < NR; ++r) {
+            const int q = 2 * qs + 8 * r;
             a0 = yfma(cd((double)s.g[r].x, (double)s.g[r].y), v[q], a0);
             a1 = yfma(cd((double)s.g[r].z, (double)s.g[r].w), v[q + 1], a1);
         }
@@ -555,8 +577,8 @@ __device__ __forceinline__ double2 ys_couple(const YStage<NR, E> &s, const doubl
     const double2 t = tl[1 + min(j, 63)];
     const bool c = qs == 1 || qs == 2 || (qs == 3 && i > 0);
     const double2 m = ymul(ysel(c, s.ex, yz()), t);
-    const double2 own = ysel(qs == 6 && with_rhs, s.ex, yz());
-    return ys_gsum2(cd(own.x - m.x, own.y - m.y));
+    const double2 own = ysel(qs == yq_rhs<E>() && with_rhs, s.ex, yz());
+    return ys_gsum2<ylpr<E>()>(cd(own.x - m.x, own.y - m.y));
 }
 
 // L2 prefetch.  A chain's y-lines are read once, in order, from HBM, and
@@ -576,14 +598,18 @@ __device__ __forceinline__ double2 ys_couple(const YStage<NR, E> &s, const doubl
 constexpr int YP_LEAD = 8;
 constexpr unsigned YP_SPINS = 1u << 14;
 
-// loads per loading thread and step: the (8 NR)^2 entries of an inverse over
-// the 64 (NR - 1) loading threads, and one coupling coefficient
-constexpr int yp_q(int nr) { return (nr * nr + nr - 2) / (nr - 1) + 1; }
+// loads per loading thread and step: one per 128-byte line of an inverse
+// ((8 NR)^2 entries of es bytes) over the 64 (nw - 1) loading threads, and
+// one coupling coefficient
+constexpr int yp_q(int nr, int nw, int es) {
+    return ((64 * nr * nr * es + 127) / 128 + 64 * (nw - 1) - 1) / (64 * (nw - 1)) + 1;
+}
 
 template <bool FWD, int NR, typename E>
 __device__ void ys_helper(const YStrip &S, int ny, int half, const E *YF,
                           const double2 *YB, unsigned long long *prog, unsigned long long base) {
-    constexpr int YP_Q = yp_q(NR), NL = 64 * (NR - 1);
+    constexpr int NW = ywaves<NR, E>(), YP_Q = yp_q(NR, NW, (int)sizeof(E)), NL = 64 * (NW - 1);
+    constexpr int EPL = 128 / (int)sizeof(E);   // entries per line
     const int n = S.nx, nn = n * yld<E>(n), m = (ny - 1) / 2;
     const int a0 = FWD ? (half == 0 ? 0 : ny - 1) : (half == 0 ? m - 1 : m + 1);
     const int da = FWD ? (half == 0 ? 1 : -1) : (half == 0 ? -1 : 1);
@@ -601,8 +627,8 @@ __device__ void ys_helper(const YStrip &S, int ny, int half, const E *YF,
         const int ab = max(FWD ? (half == 0 ? a - 1 : a) : (half == 0 ? a : a - 1), 0);
         const E *G = YF + S.yoff + (long)ag * nn;
 #pragma unroll
-        for (int q = 0; q < YP_Q - 1; ++q) r[q] = (double)G[min(lt + NL * q, nn - 1)].x;
-        r[YP_Q - 1] = YB[S.boff + (long)ab * 3 * n + min(lt, 3 * n - 1)].x;
+        for (int q = 0; q < YP_Q - 1; ++q) r[q] = (double)G[min((lt + NL * q) * EPL, nn - 1)].x;
+        r[YP_Q - 1] = YB[S.boff + (long)ab * 3 * n + min(lt * 8, 3 * n - 1)].x;
     };
     auto fold = [&](const double (&r)[YP_Q]) {
 #pragma unroll
@@ -647,7 +673,7 @@ __device__ void ys_helper(const YStrip &S, int ny, int half, const E *YF,
 // (a = a0 + k da) multiplies by the inverse of y-line a - da and coupling
 // block a - 1 (lower, B^T) or a (upper, B).
 template <int NR, typename E>
-__global__ __launch_bounds__(64 * NR) void ysolve_fwd_kernel(
+__global__ __launch_bounds__((64 * ywaves<NR, E>())) void ysolve_fwd_kernel(
     const YStrip *ys, int ny, const E *YF, const double2 *YB, const double2 *b, double2 *x,
     const StepCtl *c, int *ran, int nchain, unsigned long long *prog, unsigned long long epoch) {
     if (yidle(c)) return;
@@ -664,7 +690,9 @@ __global__ __launch_bounds__(64 * NR) void ysolve_fwd_kernel(
     const int j = blockIdx.x >> 1, half = blockIdx.x & 1;
     const YStrip S = ys[j];
     const int n = S.nx, nn = n * yld<E>(n), m = (ny - 1) / 2;
-    const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * 8 + (lane >> 3), qs = lane & 7;
+    constexpr int LPR = ylpr<E>();
+    const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * (64 / LPR) + lane / LPR;
+    const int qs = lane % LPR;
     __shared__ double2 v[64], tl[66];
     const int a0 = half == 0 ? 0 : ny - 1, da = half == 0 ? 1 : -1;
     const int steps = half == 0 ? m : ny - 1 - m;
@@ -683,7 +711,7 @@ __global__ __launch_bounds__(64 * NR) void ysolve_fwd_kernel(
     auto step = [&](const YStage<NR, E> &st, int k) {
         const int a = a0 + k * da;
         if (k > 0) {
-            const double2 t = ys_gsum2(ys_partial(st, v, qs));
+            const double2 t = ys_gsum2<LPR>(ys_partial(st, v, qs));
             if (qs == 0 && i < n) tl[1 + i] = t;
             __syncthreads();
         }
@@ -720,7 +748,7 @@ __global__ __launch_bounds__(64 * NR) void ysolve_fwd_kernel(
 // Step k (a = a0 + k da) multiplies by the inverse of y-line a, coupling
 // block a (lower, B) or a - 1 (upper, B^T), and reads w_a / v_a from x.
 template <int NR, typename E>
-__global__ __launch_bounds__(64 * NR) void ysolve_bwd_kernel(
+__global__ __launch_bounds__((64 * ywaves<NR, E>())) void ysolve_bwd_kernel(
     const YStrip *ys, int ny, const E *YF, const double2 *YB, double2 *x, const StepCtl *c,
     int nchain, unsigned long long *prog, unsigned long long epoch) {
     if (yidle(c)) return;
@@ -736,7 +764,9 @@ __global__ __launch_bounds__(64 * NR) void ysolve_bwd_kernel(
     const int j = blockIdx.x >> 1, half = blockIdx.x & 1;
     const YStrip S = ys[j];
     const int n = S.nx, nn = n * yld<E>(n), m = (ny - 1) / 2;
-    const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * 8 + (lane >> 3), qs = lane & 7;
+    constexpr int LPR = ylpr<E>();
+    const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * (64 / LPR) + lane / LPR;
+    const int qs = lane % LPR;
     __shared__ double2 v[64], tl[66];
     const int a0 = half == 0 ? m - 1 : m + 1, da = half == 0 ? -1 : 1;
     const int steps = half == 0 ? m : ny - 1 - m;
@@ -759,7 +789,7 @@ __global__ __launch_bounds__(64 * NR) void ysolve_bwd_kernel(
         const double2 r = ys_couple(st, tl, i, qs, true);
         if (qs == 0 && i < n) v[i] = r;
         __syncthreads();
-        const double2 t = ys_gsum2(ys_partial(st, v, qs));
+        const double2 t = ys_gsum2<LPR>(ys_partial(st, v, qs));
         if (qs == 0 && i < n) {
             tl[1 + i] = t;
             x[(long)(S.off + i) * ny + a] = t;
@@ -790,7 +820,7 @@ __global__ __launch_bounds__(64 * NR) void ysolve_bwd_kernel(
 // U_{m+1}^{-1} v_{m+1}), the terms present; three products of one step
 // each, all their data loaded up front.
 template <int NR, typename E>
-__global__ __launch_bounds__(64 * NR) void ysolve_mid_kernel(const YStrip *ys, int ny,
+__global__ __launch_bounds__((64 * ywaves<NR, E>())) void ysolve_mid_kernel(const YStrip *ys, int ny,
                                                                 const E *YF,
                                                                 const double2 *YB,
                                                                 const double2 *b, double2 *x,
@@ -798,7 +828,9 @@ __global__ __launch_bounds__(64 * NR) void ysolve_mid_kernel(const YStrip *ys, i
     if (yidle(c)) return;
     const YStrip S = ys[blockIdx.x];
     const int n = S.nx, nn = n * yld<E>(n), m = (ny - 1) / 2;
-    const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * 8 + (lane >> 3), qs = lane & 7;
+    constexpr int LPR = ylpr<E>();
+    const int lane = threadIdx.x & 63, i = (threadIdx.x >> 6) * (64 / LPR) + lane / LPR;
+    const int qs = lane % LPR;
     __shared__ double2 v[64], tl[66];
     if (threadIdx.x < 64) v[threadIdx.x] = yz();   // entries q >= n meet clamped G values
     if (threadIdx.x < 66) tl[threadIdx.x] = yz();
@@ -818,9 +850,9 @@ __global__ __launch_bounds__(64 * NR) void ysolve_mid_kernel(const YStrip *ys, i
     double2 acc = yz();
     auto side = [&](const YStage<NR, E> &st) {
         // the side's vector (the right-hand-side slot of its stage) into v
-        if (qs == 6 && i < n) v[i] = st.ex;
+        if (qs == yq_rhs<E>() && i < n) v[i] = st.ex;
         __syncthreads();
-        const double2 t = ys_gsum2(ys_partial(st, v, qs));
+        const double2 t = ys_gsum2<LPR>(ys_partial(st, v, qs));
         if (qs == 0 && i < n) tl[1 + i] = t;
         __syncthreads();
         const double2 cpl = ys_couple(st, tl, i, qs, false);   // -(coupling product)_i
@@ -831,10 +863,10 @@ __global__ __launch_bounds__(64 * NR) void ysolve_mid_kernel(const YStrip *ys, i
     if (lo) side(sl);
     if (hi) side(sh);
     // b_m from the middle stage's right-hand-side lane, to the whole row
-    const double2 rb = ys_gsum2(ysel(qs == 6, sm.ex, yz()));
+    const double2 rb = ys_gsum2<LPR>(ysel(qs == yq_rhs<E>(), sm.ex, yz()));
     if (qs == 0 && i < n) v[i] = cd(rb.x + acc.x, rb.y + acc.y);
     __syncthreads();
-    const double2 t = ys_gsum2(ys_partial(sm, v, qs));
+    const double2 t = ys_gsum2<LPR>(ys_partial(sm, v, qs));
     if (qs == 0 && i < n) x[(long)(S.off + i) * ny + m] = t;
 }
 
@@ -887,11 +919,12 @@ static hipError_t ysolve_typed(hipStream_t st, const YStrip *ys, int nstrips, in
     // chains 0 .. 2N-1, then (from the next multiple of 8) their helpers
     const int nchain = 2 * nstrips, grid = ((nchain + 7) & ~7) + nchain;
     auto go = [&](auto fwd, auto mid, auto bwd, int nr) {
-        hipLaunchKernelGGL(fwd, dim3(grid), dim3(64 * nr), 0, st, ys, ny, YF, YB, b, x, c, ran,
-                           nchain, prog, ef);
-        hipLaunchKernelGGL(mid, dim3(nstrips), dim3(64 * nr), 0, st, ys, ny, YF, YB, b, x, c);
-        hipLaunchKernelGGL(bwd, dim3(grid), dim3(64 * nr), 0, st, ys, ny, YF, YB, x, c, nchain,
-                           prog, eb);
+        const dim3 block((unsigned)(8 * nr * ylpr<E>()));   // 64 NR LPR / 8 threads
+        hipLaunchKernelGGL(fwd, dim3(grid), block, 0, st, ys, ny, YF, YB, b, x, c, ran, nchain,
+                           prog, ef);
+        hipLaunchKernelGGL(mid, dim3(nstrips), block, 0, st, ys, ny, YF, YB, b, x, c);
+        hipLaunchKernelGGL(bwd, dim3(grid), block, 0, st, ys, ny, YF, YB, x, c, nchain, prog,
+                           eb);
     };
     if (max_nx <= 32)
         go(ysolve_fwd_kernel<4, E>, ysolve_mid_kernel<4, E>, ysolve_bwd_kernel<4, E>, 4);
