@@ -52,14 +52,14 @@ TRAFFIC = {
         "bytes": 4.0256e+09,
         "source_sha256": "0188a515ae068128f803335738cdd412be490495c3eb45af7f1614408e1640bd",
         "summary": "profiles/sweep_update_c32_rot2048_hbm_counters.md"},
-    ("rot2048", "fp64", "ysolve"): {
-        "bytes": 6.0943e+09,
-        "source_sha256": "b49ab4d7ccd290432cfe7567166bf92676287ca187817c53b55f4af7c3c0cc67",
-        "summary": "profiles/ysolve_yfactor_f64_rot2048_hbm_counters.md"},
-    ("rot2048", "fp64", "yfactor"): {
-        "bytes": 2.9691e+09,
-        "source_sha256": "b49ab4d7ccd290432cfe7567166bf92676287ca187817c53b55f4af7c3c0cc67",
-        "summary": "profiles/ysolve_yfactor_f64_rot2048_hbm_counters.md"},
+    ("rot2048", "c32", "ysolve"): {
+        "bytes": 3.0766e+09,
+        "source_sha256": "714329e0631c309012d2a5008703b3df51364cde2008881c307a75fbfab17483",
+        "summary": "profiles/ysolve_yfactor_c32_rot2048_hbm_counters.md"},
+    ("rot2048", "c32", "yfactor"): {
+        "bytes": 1.8161e+09,
+        "source_sha256": "714329e0631c309012d2a5008703b3df51364cde2008881c307a75fbfab17483",
+        "summary": "profiles/ysolve_yfactor_c32_rot2048_hbm_counters.md"},
 }
 
 TRAFFIC_SOURCES = {"strip_solve": "kernels_solve.hip", "sweep_update": "kernels_factor.hip",

@@ -203,6 +203,15 @@ __device__ __forceinline__ void yf_sandwich(double2 (&c)[T][T], const YFLds<T> &
     __syncthreads();
 }
 
+// 1 / x for the pivots' squared moduli (positive, far from overflow and
+// underflow): the hardware reciprocal refined by two Newton steps, a shorter
+// dependent chain than the IEEE division with its scaling and fix-up steps.
+__device__ __forceinline__ double yrcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+}
+
 __device__ __forceinline__ double2 yshfl(double2 v, int src) {
     return cd(__shfl(v.x, src), __shfl(v.y, src));
 }
@@ -259,7 +268,7 @@ __device__ __forceinline__ void yf_invert(double2 (&c)[T][T], const YFLds<T> &L,
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const double2 pq = cd(lane_f64(D.x, 9 * q), lane_f64(D.y, 9 * q));
-            const double inv = 1.0 / (pq.x * pq.x + pq.y * pq.y);
+            const double inv = yrcp(pq.x * pq.x + pq.y * pq.y);
             const double2 d = cd(pq.x * inv, -pq.y * inv);
             const double2 rq = yshfl(D, 8 * q + ac), cq = yshfl(D, 8 * ar + q);
             const bool kq = ac == q;
